@@ -1,0 +1,177 @@
+"""Benchmark: fully implicit Newton iterations per second on the 1.1M-cell
+two-phase dead-oil five-spot (60x220x85, 2x2 BSR), one MI355X.
+
+A step is one FIM time step (dt = 10 days) through the C ABI: properties,
+TPFA assembly, block-Jacobi GMRES, Newton updates and cuts, all in the HIP
+library.  Inputs are seeded synthetic data resident in HBM before timing.
+
+Prints one JSON line with the throughput, the roofline of the dominant
+kernel (BSR SpMV, timed with HIP events on the library's stream inside the
+timed steps) and the FP64 oracle's throughput on the host as a baseline.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "Newton iters/s & BSR-SpMV GB/s (% HBM peak) at 1.1M cells; adjoint/forward time"
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def tolerances(mode):
+    from paper_2406_10862_amd import reservoirs as rv
+    if mode == "parity":
+        return rv.Options(max_lin=400, restart=30)
+    # the paper's scalability setting: nonlinear and linear residuals 1e-3
+    return rv.Options(tol_cnv=1e-3, tol_mb=1e-7, tol_dp=1e30, tol_ds=1e30, tol_well=1e-2,
+                      lin_rtol=1e-3, max_lin=400, restart=30)
+
+
+def spmv_bytes(nnzb, nrows, nb):
+    """Algorithmic bytes of one FP64 BSR SpMV: values, column indices, row
+    pointers, x read once, y written once."""
+    return nnzb * nb * nb * 8 + nnzb * 4 + (nrows + 1) * 4 + 2 * nrows * nb * 8
+
+
+def cpu_baseline(res):
+    """The oracle as it is, one Newton iteration of the first step of the same
+    workload on the host's cores: property evaluation, residual and Jacobian,
+    and its BILU(0)-GMRES(50) linear solve capped at 60 iterations."""
+    from oracle.fimref import OracleModel
+    t0 = time.perf_counter()
+    m = OracleModel(res)
+    setup = time.perf_counter() - t0
+    opt = m.options(max_newton=1, max_cuts=0, max_lin=60)
+    t0 = time.perf_counter()
+    st, rep = m.step(res.schedule[0], opt)
+    t = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {
+        "value": rep.newton_iters / t if t > 0 else None,
+        "unit": "Newton iters/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": (f"one Newton iteration of the first 10-day step of the same 1,122,000-cell "
+                   f"workload (assembly + BILU0-GMRES(50) capped at 60 iterations, "
+                   f"{rep.linear_iters} done) plus one residual evaluation; "
+                   f"{t:.1f} s wall, setup {setup:.1f} s not counted"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--tol", choices=["parity", "paper"], default="parity")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "spmv_c2_traffic.json"))
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2406_10862_amd import fim, reservoirs as rv
+
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    res = rv.config_c2()
+    opts = tolerances(args.tol)
+    g = fim.Fim(res, options=opts, profile=True)
+    g.set_initial_state()
+    torch.cuda.synchronize()
+    log(f"setup {time.perf_counter() - t0:.1f}s: {res.name} cells={g.n} nnzb={g.nnzb}")
+
+    sched = res.schedule
+    k = 0
+    for _ in range(args.warmup):
+        rc, rep = g.fim_step(sched[k % len(sched)])
+        k += 1
+        log(f"warmup step: rc={rc} newton={rep.newton_iters} linear={rep.linear_iters} "
+            f"cuts={rep.cuts}")
+    torch.cuda.synchronize()
+    newton = linear = cuts = calls = 0
+    spmv_ms = 0.0
+    phases = [0.0, 0.0, 0.0]
+    t_start = time.perf_counter()
+    for s in range(args.steps):
+        rc, rep = g.fim_step(sched[k % len(sched)])
+        k += 1
+        newton += rep.newton_iters
+        linear += rep.linear_iters
+        cuts += rep.cuts
+        calls += rep.spmv_calls
+        spmv_ms += rep.spmv_ms
+        phases[0] += rep.t_assemble
+        phases[1] += rep.t_linear
+        phases[2] += rep.t_update
+        log(f"step {s}: rc={rc} newton={rep.newton_iters} linear={rep.linear_iters} "
+            f"cuts={rep.cuts} cnv={max(rep.cnv):.2e}")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+
+    nbytes = spmv_bytes(g.nnzb, g.nrows, g.nb)
+    avg_ms = spmv_ms / calls if calls else float("nan")
+    achieved = nbytes / (avg_ms * 1e-3) / 1e9 if calls else None
+    traffic = None
+    if os.path.exists(args.traffic):
+        try:
+            traffic = json.load(open(args.traffic)).get("bytes_per_launch")
+        except Exception:
+            traffic = None
+    out = {
+        "metric": METRIC,
+        "value": newton / wall,
+        "unit": "Newton iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "two-phase dead-oil FIM five-spot 60x220x85 = 1,122,000 cells, "
+                        "seeded log-normal perm (sigma 2), 2x2 BSR, dt 10 days",
+            "cells": g.n, "block_rows": g.nrows, "nnzb": g.nnzb, "nb": g.nb,
+            "tolerances": args.tol, "precond": "block-Jacobi", "gmres_restart": opts.restart,
+            "newton_iters": newton, "linear_iters": linear, "cuts": cuts,
+            "linear_per_newton": linear / newton if newton else None,
+            "phase_ms": {"assemble": phases[0], "linear": phases[1], "update": phases[2]},
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_spmv<2,8> (BSR SpMV inside GMRES)",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS if achieved else None,
+            "traffic": traffic,
+            "bytes_per_launch": nbytes,
+            "avg_launch_us": avg_ms * 1e3,
+            "launches": calls,
+        },
+    }
+    if not args.no_cpu:
+        log("timing the oracle on the host (bounded sample)")
+        out["cpu_baseline"] = cpu_baseline(res)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

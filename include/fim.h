@@ -1,0 +1,234 @@
+/*
+ * fim.h - C ABI of libfim.so, the MI355X (gfx950) fully implicit black-oil
+ * step: per-cell black-oil properties, two-point-flux upwinded face fluxes
+ * assembled into a residual and a 2x2 / 3x3 block-sparse (BSR) Jacobian,
+ * and right-preconditioned GMRES on that Jacobian, driven by Newton with
+ * time-step cuts.  Every numeric step runs in HIP kernels on the device of
+ * the stream passed to fim_create.
+ *
+ * Paper (OpenCAEPoro, arXiv 2406.10862):
+ *   Sec. 2.1, eq. (1)   component mass conservation (diffusion term zero);
+ *   Sec. 2.1, eq. (2)   Darcy velocity with gravity;
+ *   Sec. 2.1            constraints N_i = phi sum_j S_j xi_j x_ij,
+ *                       sum_j S_j = 1, and the black-oil closure (phase
+ *                       quantities explicit in P from tables);
+ *   Sec. 3.2.3          Bulk (PVT, SAT, ROCK, ACCU), BulkConn (connection
+ *                       fluxes) and AllWells (perforation flux, well rows);
+ *   Sec. 3.2.4          one FIM Newton iteration = assemble, solve and
+ *                       update, property update, convergence check;
+ *   Sec. 3.3.1-3.3.2    Setup / InitReservoir / GoOneStep, time stepping
+ *                       with conditional returns to earlier stages;
+ *   Sec. 3.3.3          the linear system returns the solution and the
+ *                       iteration count;
+ *   Sec. 5.1            FGMRES with block-Jacobi ILU(0) smoothing.
+ *
+ * Conventions
+ *   Units: FIELD (ft, mD, psi, days, rb, stb, Mscf, cP; gas density lb/Mscf).
+ *   Cells: c = i + nx*(j + ny*k), 0-based, k = 0 is the top layer.  Depth
+ *     of a cell centre = top + (thickness of the layers above) + dz_k/2.
+ *   Unknowns per cell: (P, Sw) for model 2 (dead oil / water) and
+ *     (P, Sw, X) for model 3 (black oil), X = Sg when flag = FIM_SAT and
+ *     X = Rs (Mscf/stb) when flag = FIM_UNSAT.  Equations per cell: water,
+ *     oil[, gas], in surface units per day.
+ *   Wells: one extra block row per well after the cells; slot 0 holds the
+ *     bottom-hole pressure, other slots are identity rows with value 0.
+ *   Vectors (residual, Newton update, GMRES vectors) are interleaved:
+ *     entry (row, slot) at row*nb + slot.  BSR blocks are row-major,
+ *     val[(q*nb + equation)*nb + unknown]; columns ascend within a row.
+ *   Ownership: inputs are copied at the call; outputs go to caller-owned
+ *     buffers of the documented size.  "_dev" arguments are device pointers
+ *     valid on the context's device; everything else is host memory.
+ *   Errors: a negative return is an error (the message is available from
+ *     fim_last_error() on the same thread); FIM_E_HIP leaves the context
+ *     unusable.  A positive return is a status, the context stays valid.
+ *     After FIM_NOT_CONVERGED the state is the state at the start of the
+ *     step.  No exception crosses the ABI.  Use one context per thread.
+ */
+#ifndef FIM_H
+#define FIM_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    FIM_OK = 0,
+    FIM_NOT_CONVERGED = 1,
+    FIM_E_ARG = -1,
+    FIM_E_NOMEM = -2,
+    FIM_E_HIP = -3,
+    FIM_E_STATE = -4
+};
+
+enum { FIM_DEADOIL_OW = 2, FIM_BLACKOIL_3P = 3 };          /* model id == block size */
+enum { FIM_PROD = 0, FIM_INJ_WATER = 1, FIM_INJ_GAS = 2 };  /* well kind */
+enum { FIM_BHP = 0, FIM_RATE = 1 };                         /* well control */
+enum { FIM_UNSAT = 0, FIM_SAT = 1 };                        /* phase-state flag */
+enum { FIM_PREC_BJ = 0 };                                   /* preconditioner */
+enum { FIM_FP64 = 0 };                                      /* precision mode */
+
+/* Cartesian grid: dx[nx], dy[ny], dz[nz] in ft, top = depth of the top face. */
+typedef struct {
+    int32_t nx, ny, nz;
+    const double *dx, *dy, *dz;
+    double top;
+} fim_grid;
+
+/* Rock: per-cell permeabilities (mD; kz is used on vertical faces) and
+ * reference porosity; phi(P) = poro*(1 + cr*(P - pref)). */
+typedef struct {
+    const double *kx, *ky, *kz, *poro;
+    double cr, pref;
+} fim_rock;
+
+/* Fluid.  PVT table columns over nrows pressures p (strictly increasing):
+ * saturated oil Bo (rb/stb), Rs (Mscf/stb), muo (cP), gas Bg (rb/Mscf),
+ * mug (cP).  Values between rows are linear in P, the end intervals
+ * extrapolate, and a pressure on a row uses the interval starting there.
+ * Model 2 uses p, bo, muo only.  Undersaturated oil (model 3, flag UNSAT):
+ * Pb from inverse interpolation of the Rs column, Bo = Bo_sat(Pb)*(1 -
+ * co_us*(P - Pb)), muo = muo_sat(Pb)*(1 + cmu_us*(P - Pb)).  Water:
+ * Bw = bw_ref*exp(-cw*(P - pw_ref)), constant muw.  Densities at stock tank:
+ * rho_sc = {water lb/ft3, oil lb/ft3, gas lb/Mscf}.  Relative
+ * permeabilities are Corey: krw = krw_max*<(Sw-swc)/(1-swc-sor)>^nw,
+ * kro = kro_max*<(So-sor)/D>^no, krg = krg_max*<(Sg-sgc)/D>^ng with
+ * D = 1-swc-sor-sgc (sgc ignored by model 2) and <.> clamped to [0,1].
+ * Capillary pressure is zero. */
+typedef struct {
+    int32_t model, nrows;
+    const double *p, *bo, *rs, *muo, *bg, *mug;
+    double co_us, cmu_us;
+    double bw_ref, cw, muw, pw_ref;
+    double rho_sc[3];
+    double swc, sor, sgc, nw, no, ng, krw_max, kro_max, krg_max;
+} fim_fluid;
+
+/* Well with nperf perforations in distinct cells.  Producers take BHP
+ * control; injectors (pure water or free gas) take BHP or a surface RATE
+ * target (> 0).  wi[nperf] may be NULL: then Peaceman's well index with
+ * wellbore radius rw (ft) and skin is used.  The BHP acts at every
+ * perforation (no wellbore head).  Producer perforation rate of component
+ * i: WI*Lam_i*(P - Pbhp), Lam_i = kr_i b_i/mu_i (gas adds Rs*Lam_o);
+ * injector: -WI*(sum_j kr_j/mu_j)*b_inj*(Pbhp - P). */
+typedef struct {
+    int32_t kind, control;
+    double target;
+    int32_t nperf;
+    const int32_t *cells;
+    const double *wi;
+    double rw, skin;
+} fim_well;
+
+/* Solver controls (the OCPControl role).  Convergence of a Newton
+ * iteration requires, per component i, CNV_i = dt*max_c|R_ic|/(PV_c b_ic)
+ * <= tol_cnv and MB_i = dt*|sum_c R_ic|/sum_c PV_c b_ic <= tol_mb, every
+ * well residual divided by its derivative w.r.t. the BHP <= tol_well
+ * (psi), and a last Newton update with max|dP| <= tol_dp (psi, cells and
+ * wells) and max|dS| <= tol_ds.  Updates are chopped per cell to
+ * max|dS| <= ds_max and |dP| <= dp_max.  A failed Newton solve halves dt,
+ * at most max_cuts times per step.  GMRES(restart) runs to relative
+ * residual lin_rtol or max_lin iterations per Newton iteration (restart
+ * in [1, 40]); an unconverged solve is still used when it reduced the
+ * residual.  profile != 0 brackets every SpMV launch of fim_step with HIP
+ * events and reports their summed duration in fim_step_report. */
+typedef struct {
+    double tol_cnv, tol_mb, tol_dp, tol_ds, tol_well;
+    double ds_max, dp_max, lin_rtol;
+    int32_t max_newton, max_lin, restart, max_cuts;
+    int32_t precond, precision, profile, reserved;
+} fim_options;
+
+#define FIM_MAX_SUB 256
+typedef struct {
+    int32_t newton_iters, linear_iters, cuts, converged, nsub, spmv_calls;
+    double dt_done, cnv[3], mb[3];
+    double t_assemble, t_linear, t_update;   /* device ms per phase */
+    double spmv_ms;                          /* summed SpMV kernel ms (HIP events) */
+    double dt_sub[FIM_MAX_SUB];              /* accepted sub-step sizes (days) */
+} fim_step_report;
+
+typedef struct fim_ctx fim_ctx;
+
+/* Setup (the paper's Setup + static part of InitReservoir).  hip_stream
+ * is a hipStream_t (NULL = the default stream); all work of the context is
+ * queued on it.  Validates sizes, table monotonicity, the positive total
+ * compressibility of saturated rows (Bg*dRs/dP > dBo/dP), perforation
+ * ranges and controls; returns FIM_E_ARG with a message on bad input. */
+int fim_create(const fim_grid *grid, const fim_rock *rock, const fim_fluid *fluid,
+               int32_t nwells, const fim_well *wells, const fim_options *opt,
+               void *hip_stream, fim_ctx **out);
+void fim_destroy(fim_ctx *ctx);
+const char *fim_last_error(void);
+
+int fim_sizes(const fim_ctx *ctx, int32_t *ncells, int32_t *nb, int32_t *nwells,
+              int32_t *nnzb, int32_t *nprops);
+int fim_set_options(fim_ctx *ctx, const fim_options *opt);
+
+/* State (the non-equilibrium InitReservoir: one state per cell).  p, sw,
+ * x3 (ignored by model 2), flag: [ncells]; bhp: [nwells] or NULL, which
+ * selects the target for BHP wells and the mean perforated-cell pressure
+ * for rate wells.  Also records the state as the start of the next step. */
+int fim_set_state(fim_ctx *ctx, const double *p, const double *sw, const double *x3,
+                  const int8_t *flag, const double *bhp);
+int fim_set_state_dev(fim_ctx *ctx, const double *p_dev, const double *sw_dev,
+                      const double *x3_dev, const int8_t *flag_dev, const double *bhp);
+int fim_get_state(fim_ctx *ctx, double *p, double *sw, double *x3, int8_t *flag, double *bhp);
+
+/* One time step of dt_days (GoOneStep): Newton iterations on the
+ * backward-Euler system, halving the step on failure.  Advances the state
+ * in place; fills rep (may be NULL).  Returns FIM_OK or FIM_NOT_CONVERGED. */
+int fim_step(fim_ctx *ctx, double dt_days, fim_step_report *rep);
+
+/* Surface rates q[w*3 + i] (component i = water, oil, gas; production
+ * positive, injection negative) and bottom-hole pressures at the state. */
+int fim_get_well_rates(fim_ctx *ctx, double *q_surf, double *bhp);
+
+/* ---- testing hooks ------------------------------------------------------ */
+
+/* Static data (cell volume ft3, centre depth ft, reference pore volume rb,
+ * transmissibility to the +x/+y/+z neighbour, 0 on the boundary, and the
+ * per-perforation well index in input order).  Any pointer may be NULL. */
+int fim_static(fim_ctx *ctx, double *vol, double *depth, double *pvref, double *tx,
+               double *ty, double *tz, double *wi);
+
+/* Set the Newton iterate without changing the step-start accumulation. */
+int fim_set_iterate(fim_ctx *ctx, const double *p, const double *sw, const double *x3,
+                    const int8_t *flag, const double *bhp);
+
+/* Property record at the current iterate, out[q*ncells + c], q in
+ * [0, nprops): with np = nb phases (water, oil[, gas]) and a group = one
+ * value followed by its derivatives w.r.t. (P, Sw[, X]):
+ *   np groups Lam_j = kr_j b_j/mu_j;  (nb==3) 1 group Lam_og = Rs*Lam_o;
+ *   1 group lam_t = sum_j kr_j/mu_j;  np groups gam_j = rho_j/144 (psi/ft);
+ *   nb groups A_i (accumulation of component i);  np values b_j = 1/B_j;
+ *   1 value PV (rb at P). */
+int fim_props(fim_ctx *ctx, double *out);
+
+/* Residual R[(ncells+nwells)*nb] and Jacobian at the current iterate for a
+ * step of dt days; rowptr[ncells+nwells+1], colind[nnzb],
+ * val[nnzb*nb*nb].  Any output pointer may be NULL. */
+int fim_assemble(fim_ctx *ctx, double dt, double *R, int32_t *rowptr, int32_t *colind,
+                 double *val);
+
+/* y = M^-1 x with the block-Jacobi preconditioner of the last assembled
+ * Jacobian; x, y: [(ncells+nwells)*nb]. */
+int fim_precond_apply(fim_ctx *ctx, const double *x, double *y);
+
+/* Solve J x = b with the last assembled Jacobian by the configured
+ * preconditioned GMRES; b, x: [(ncells+nwells)*nb] (x is the output, the
+ * initial guess is zero).  iters and relres (true ||b - J x||/||b||) may
+ * be NULL.  Returns FIM_OK or FIM_NOT_CONVERGED. */
+int fim_linear_solve(fim_ctx *ctx, const double *b, double *x, int32_t *iters,
+                     double *relres);
+
+/* y = A x for a canonical BSR matrix of nrows block rows with nb in {2,3};
+ * every pointer is a device pointer; queued on hip_stream, no sync. */
+int fim_bsr_spmv(int32_t nrows, int32_t nb, const int32_t *rowptr_dev,
+                 const int32_t *colind_dev, const double *val_dev, const double *x_dev,
+                 double *y_dev, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,1058 @@
+// fim_api.cpp - host runtime behind the C ABI (include/fim.h): context and
+// device memory, static pattern, the Newton driver (paper Sec. 3.2.4), the
+// time-step driver with conditional returns (Sec. 3.3.2) and the GMRES
+// driver (Sec. 5.1, Sec. 3.3.3).  The host only orders launches, reads a
+// few scalars per iteration and solves the small Hessenberg least-squares
+// problem of GMRES; every vector and matrix operation is a HIP kernel.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "fim.h"
+#include "fim_internal.h"
+
+using namespace fim;
+
+namespace {
+
+thread_local std::string g_err;
+
+struct ArgError {};
+struct HipError {};
+struct StateError {};
+
+void set_err(const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+}
+
+#define HIPCHECK(call)                                                                    \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess) {                                                           \
+            set_err("HIP error '%s' in %s (%s:%d)", hipGetErrorString(e_), #call, __FILE__, \
+                    __LINE__);                                                            \
+            throw HipError();                                                             \
+        }                                                                                 \
+    } while (0)
+
+#define REQUIRE(cond, ...)        \
+    do {                          \
+        if (!(cond)) {            \
+            set_err(__VA_ARGS__); \
+            throw ArgError();     \
+        }                         \
+    } while (0)
+
+template <typename F>
+int guarded(F &&f) {
+    try {
+        return f();
+    } catch (const ArgError &) {
+        return FIM_E_ARG;
+    } catch (const StateError &) {
+        return FIM_E_STATE;
+    } catch (const HipError &) {
+        return FIM_E_HIP;
+    } catch (const std::bad_alloc &) {
+        set_err("host out of memory");
+        return FIM_E_NOMEM;
+    } catch (...) {
+        set_err("unexpected internal error");
+        return FIM_E_HIP;
+    }
+}
+
+// scalar slots in the device/pinned scalar area
+enum { S_CONV = 0, S_UPD = 16, S_NORM = 20, S_RES = 24, S_COUNT = 32 };
+
+}  // namespace
+
+struct fim_ctx {
+    hipStream_t s = nullptr;
+    int dev = 0;
+    fim_options opt{};
+    Grid g{};
+    int n = 0, nb = 0, nw = 0, nperf = 0, nrows = 0, nnzb = 0, m = 0;
+    long nvec = 0;
+    Phys phys{};
+    std::vector<int> wkind, wctrl, wps, perf_src;   // perf_src: sorted -> input index
+    std::vector<double> wtarget;
+    std::vector<void *> owned;
+    // device
+    double *dx = nullptr, *dy = nullptr, *dz = nullptr, *kx = nullptr, *ky = nullptr,
+           *kz = nullptr, *poro = nullptr, *tab = nullptr;
+    double *vol = nullptr, *depth = nullptr, *pvref = nullptr, *tx = nullptr, *ty = nullptr,
+           *tz = nullptr;
+    int *dwkind = nullptr, *dwctrl = nullptr, *dwps = nullptr, *pcell = nullptr,
+        *pwell = nullptr, *cps = nullptr, *cperf = nullptr;
+    double *dwtarget = nullptr, *wi = nullptr, *wrw = nullptr, *wskin = nullptr;
+    double *P = nullptr, *Sw = nullptr, *X = nullptr, *pbhp = nullptr;
+    int8_t *flag = nullptr;
+    double *sP[2] = {}, *sSw[2] = {}, *sX[2] = {}, *spb[2] = {};
+    int8_t *sflag[2] = {};
+    double *rec = nullptr, *aold = nullptr, *wmeas = nullptr;
+    int *rowptr = nullptr, *colind = nullptr, *diagpos = nullptr;
+    double *val = nullptr, *R = nullptr, *dinv = nullptr;
+    int *bad = nullptr;
+    double *V = nullptr, *w = nullptr, *z = nullptr, *x = nullptr, *r = nullptr, *t = nullptr,
+           *b = nullptr, *H = nullptr, *tmp = nullptr, *ydev = nullptr;
+    int *reorth = nullptr;
+    double *partials = nullptr, *scal = nullptr;
+    unsigned *counter = nullptr;
+    double *pin = nullptr;        // pinned host: scalars, H columns, y
+    size_t pin_len = 0;
+    bool state_set = false, jac_ready = false, prec_ready = false;
+    hipEvent_t ev[4] = {};
+    hipEvent_t colev[kMaxRestart] = {};
+    std::vector<hipEvent_t> spmv_ev;
+    int spmv_used = 0;
+    double spmv_ms = 0.0;
+    int spmv_calls = 0;
+
+    Wells wells() const {
+        Wells W;
+        W.nw = nw;
+        W.kind = dwkind;
+        W.ctrl = dwctrl;
+        W.target = dwtarget;
+        W.wps = dwps;
+        W.pcell = pcell;
+        W.pwell = pwell;
+        W.wi = wi;
+        W.cps = cps;
+        W.cperf = cperf;
+        return W;
+    }
+    Sys sys() const { return Sys{rowptr, colind, diagpos, val, R}; }
+
+    template <typename T>
+    T *alloc(size_t count) {
+        void *p = nullptr;
+        if (count == 0) count = 1;
+        hipError_t e = hipMalloc(&p, count * sizeof(T));
+        if (e != hipSuccess) {
+            set_err("hipMalloc of %zu bytes failed: %s", count * sizeof(T), hipGetErrorString(e));
+            throw std::bad_alloc();
+        }
+        owned.push_back(p);
+        return static_cast<T *>(p);
+    }
+    template <typename T>
+    T *upload(const T *src, size_t count) {
+        T *d = alloc<T>(count);
+        if (src && count) HIPCHECK(hipMemcpyAsync(d, src, count * sizeof(T), hipMemcpyHostToDevice, s));
+        return d;
+    }
+    void sync() { HIPCHECK(hipStreamSynchronize(s)); }
+    void release(void *p) {
+        if (!p) return;
+        auto it = std::find(owned.begin(), owned.end(), p);
+        if (it != owned.end()) owned.erase(it);
+        (void)hipFree(p);
+    }
+
+    ~fim_ctx() {
+        if (s) (void)hipStreamSynchronize(s);
+        for (void *p : owned) (void)hipFree(p);
+        if (pin) (void)hipHostFree(pin);
+        for (auto &e : ev)
+            if (e) (void)hipEventDestroy(e);
+        for (auto &e : colev)
+            if (e) (void)hipEventDestroy(e);
+        for (auto &e : spmv_ev) (void)hipEventDestroy(e);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// validation and setup
+
+static void check_options(const fim_options *o) {
+    REQUIRE(o, "options pointer is NULL");
+    REQUIRE(o->restart >= 1 && o->restart <= kMaxRestart, "restart must be in [1, %d]",
+            kMaxRestart);
+    REQUIRE(o->max_lin >= 1 && o->max_newton >= 1 && o->max_cuts >= 0,
+            "max_lin, max_newton >= 1 and max_cuts >= 0 required");
+    REQUIRE(o->ds_max > 0 && o->dp_max > 0 && o->lin_rtol > 0 && o->lin_rtol < 1,
+            "ds_max, dp_max > 0 and 0 < lin_rtol < 1 required");
+    REQUIRE(o->precond == FIM_PREC_BJ, "unknown preconditioner %d", o->precond);
+    REQUIRE(o->precision == FIM_FP64, "unknown precision mode %d", o->precision);
+}
+
+static void build_pattern(fim_ctx *c, std::vector<int> &rp, std::vector<int> &ci,
+                          std::vector<int> &dp, const std::vector<std::vector<int>> &cell_wells,
+                          const std::vector<int> &sorted_cells) {
+    const int n = c->n, nx = c->g.nx, ny = c->g.ny, nz = c->g.nz, nxy = nx * ny;
+    rp.assign(c->nrows + 1, 0);
+    ci.clear();
+    dp.assign(c->nrows, -1);
+    for (int cell = 0; cell < n; ++cell) {
+        const int i = cell % nx, j = (cell / nx) % ny, k = cell / nxy;
+        // ascending columns: -z, -y, -x, diagonal, +x, +y, +z, well columns
+        if (k > 0) ci.push_back(cell - nxy);
+        if (j > 0) ci.push_back(cell - nx);
+        if (i > 0) ci.push_back(cell - 1);
+        dp[cell] = (int)ci.size();
+        ci.push_back(cell);
+        if (i + 1 < nx) ci.push_back(cell + 1);
+        if (j + 1 < ny) ci.push_back(cell + nx);
+        if (k + 1 < nz) ci.push_back(cell + nxy);
+        for (int wl : cell_wells[cell]) ci.push_back(n + wl);
+        rp[cell + 1] = (int)ci.size();
+    }
+    for (int wl = 0; wl < c->nw; ++wl) {
+        for (int p = c->wps[wl]; p < c->wps[wl + 1]; ++p) ci.push_back(sorted_cells[p]);
+        dp[n + wl] = (int)ci.size();
+        ci.push_back(n + wl);
+        rp[n + wl + 1] = (int)ci.size();
+    }
+}
+
+static void alloc_krylov(fim_ctx *c, int m) {
+    c->release(c->V);
+    c->release(c->H);
+    c->V = nullptr;
+    c->H = nullptr;
+    c->m = m;
+    c->V = c->alloc<double>((size_t)(m + 1) * c->nvec);
+    c->H = c->alloc<double>((size_t)(m + 1) * (kMaxRestart + 2));
+}
+
+static int create_impl(const fim_grid *grid, const fim_rock *rock, const fim_fluid *fl,
+                       int32_t nwells, const fim_well *wells, const fim_options *opt,
+                       void *stream, fim_ctx **out) {
+    REQUIRE(out, "out pointer is NULL");
+    *out = nullptr;
+    REQUIRE(grid && rock && fl, "grid, rock and fluid are required");
+    REQUIRE(grid->nx >= 1 && grid->ny >= 1 && grid->nz >= 1, "grid dimensions must be >= 1");
+    const long nl = (long)grid->nx * grid->ny * grid->nz;
+    REQUIRE(nl < (1L << 28), "grid too large (%ld cells)", nl);
+    REQUIRE(grid->dx && grid->dy && grid->dz, "dx, dy, dz are required");
+    for (int i = 0; i < grid->nx; ++i) REQUIRE(grid->dx[i] > 0, "dx must be > 0");
+    for (int i = 0; i < grid->ny; ++i) REQUIRE(grid->dy[i] > 0, "dy must be > 0");
+    for (int i = 0; i < grid->nz; ++i) REQUIRE(grid->dz[i] > 0, "dz must be > 0");
+    REQUIRE(rock->kx && rock->ky && rock->kz && rock->poro, "rock arrays are required");
+    for (long c = 0; c < nl; ++c) {
+        REQUIRE(rock->kx[c] >= 0 && rock->ky[c] >= 0 && rock->kz[c] >= 0,
+                "permeability must be >= 0 (cell %ld)", c);
+        REQUIRE(rock->poro[c] > 0 && rock->poro[c] <= 1, "porosity must be in (0, 1] (cell %ld)", c);
+    }
+    REQUIRE(fl->model == FIM_DEADOIL_OW || fl->model == FIM_BLACKOIL_3P, "model must be 2 or 3");
+    REQUIRE(fl->nrows >= 2 && fl->nrows <= kMaxTableRows, "PVT rows must be in [2, %d]",
+            kMaxTableRows);
+    REQUIRE(fl->p && fl->bo && fl->muo, "PVT columns p, bo, muo are required");
+    const bool bo3 = fl->model == FIM_BLACKOIL_3P;
+    if (bo3) REQUIRE(fl->rs && fl->bg && fl->mug, "model 3 needs rs, bg, mug columns");
+    for (int r = 0; r < fl->nrows; ++r) {
+        REQUIRE(fl->bo[r] > 0 && fl->muo[r] > 0, "Bo and muo must be > 0");
+        if (bo3) REQUIRE(fl->bg[r] > 0 && fl->mug[r] > 0, "Bg and mug must be > 0");
+        if (r + 1 < fl->nrows) {
+            REQUIRE(fl->p[r + 1] > fl->p[r], "table pressures must increase");
+            if (bo3) {
+                REQUIRE(fl->rs[r + 1] > fl->rs[r], "Rs column must increase");
+                const double dp = fl->p[r + 1] - fl->p[r];
+                const double dRs = (fl->rs[r + 1] - fl->rs[r]) / dp;
+                const double dBo = (fl->bo[r + 1] - fl->bo[r]) / dp;
+                REQUIRE(fl->bg[r] * dRs > dBo,
+                        "saturated row %d has negative total compressibility (Bg dRs/dP <= dBo/dP)", r);
+            }
+        }
+    }
+    REQUIRE(fl->bw_ref > 0 && fl->muw > 0, "water Bw_ref and muw must be > 0");
+    REQUIRE(fl->swc >= 0 && fl->sor >= 0 && fl->sgc >= 0 &&
+                fl->swc + fl->sor + (bo3 ? fl->sgc : 0.0) < 1,
+            "end points must satisfy swc + sor (+ sgc) < 1");
+    REQUIRE(nwells >= 0 && (nwells == 0 || wells), "wells pointer required");
+    check_options(opt);
+
+    auto *c = new fim_ctx();
+    try {
+        c->s = static_cast<hipStream_t>(stream);
+        c->opt = *opt;
+        c->g = Grid{grid->nx, grid->ny, grid->nz, (int)nl};
+        c->n = (int)nl;
+        c->nb = fl->model;
+        c->nw = nwells;
+
+        // wells: perforations sorted by cell within each well
+        std::vector<int> sorted_cells;
+        std::vector<double> wi_sorted, rw(nwells), skin(nwells);
+        c->wps.assign(nwells + 1, 0);
+        std::vector<int> pwell_h;
+        int src_base = 0;
+        for (int wl = 0; wl < nwells; ++wl) {
+            const fim_well &W = wells[wl];
+            REQUIRE(W.kind >= FIM_PROD && W.kind <= FIM_INJ_GAS, "well %d: bad kind", wl);
+            REQUIRE(W.control == FIM_BHP || W.control == FIM_RATE, "well %d: bad control", wl);
+            REQUIRE(!(W.kind == FIM_PROD && W.control == FIM_RATE),
+                    "well %d: rate-controlled producers are not supported", wl);
+            REQUIRE(!(W.kind == FIM_INJ_GAS && !bo3), "well %d: gas injection needs model 3", wl);
+            REQUIRE(W.control == FIM_BHP || W.target > 0, "well %d: rate target must be > 0", wl);
+            REQUIRE(W.nperf >= 1 && W.cells, "well %d: needs perforations", wl);
+            REQUIRE(W.wi || W.rw > 0, "well %d: rw must be > 0 without explicit WI", wl);
+            std::vector<int> idx(W.nperf);
+            std::iota(idx.begin(), idx.end(), 0);
+            std::stable_sort(idx.begin(), idx.end(),
+                             [&](int a, int b2) { return W.cells[a] < W.cells[b2]; });
+            for (int q = 0; q < W.nperf; ++q) {
+                const int cell = W.cells[idx[q]];
+                REQUIRE(cell >= 0 && cell < c->n, "well %d: perforation cell %d out of range", wl,
+                        cell);
+                REQUIRE(q == 0 || W.cells[idx[q - 1]] != cell, "well %d: duplicate cell %d", wl,
+                        cell);
+                sorted_cells.push_back(cell);
+                pwell_h.push_back(wl);
+                c->perf_src.push_back(src_base + idx[q]);
+                wi_sorted.push_back(W.wi ? W.wi[idx[q]] : 0.0);
+                if (W.wi) REQUIRE(W.wi[idx[q]] > 0, "well %d: explicit WI must be > 0", wl);
+            }
+            src_base += W.nperf;
+            c->wps[wl + 1] = c->wps[wl] + W.nperf;
+            c->wkind.push_back(W.kind);
+            c->wctrl.push_back(W.control);
+            c->wtarget.push_back(W.target);
+            rw[wl] = W.rw;
+            skin[wl] = W.skin;
+        }
+        c->nperf = c->wps[nwells];
+        c->nrows = c->n + nwells;
+        c->nvec = (long)c->nrows * c->nb;
+
+        // perforations of each cell in ascending well order
+        std::vector<std::vector<int>> cell_wells(c->n);
+        std::vector<int> cps(c->n + 1, 0), cperf;
+        {
+            std::vector<std::vector<int>> cell_perfs(c->n);
+            for (int p = 0; p < c->nperf; ++p) {
+                cell_wells[sorted_cells[p]].push_back(pwell_h[p]);
+                cell_perfs[sorted_cells[p]].push_back(p);
+            }
+            for (int cell = 0; cell < c->n; ++cell) {
+                cps[cell + 1] = cps[cell] + (int)cell_perfs[cell].size();
+                for (int p : cell_perfs[cell]) cperf.push_back(p);
+            }
+        }
+        std::vector<int> rp, ci, dp;
+        build_pattern(c, rp, ci, dp, cell_wells, sorted_cells);
+        c->nnzb = (int)ci.size();
+
+        // fluid and rock scalars
+        Phys &f = c->phys;
+        f.model = fl->model;
+        f.nrows = fl->nrows;
+        f.co_us = fl->co_us;
+        f.cmu_us = fl->cmu_us;
+        f.bw_ref = fl->bw_ref;
+        f.cw = fl->cw;
+        f.muw = fl->muw;
+        f.pw_ref = fl->pw_ref;
+        f.rho_w = fl->rho_sc[0];
+        f.rho_o = fl->rho_sc[1];
+        f.rho_g = fl->rho_sc[2];
+        f.swc = fl->swc;
+        f.sor = fl->sor;
+        f.sgc = fl->sgc;
+        f.nw = fl->nw;
+        f.no = fl->no;
+        f.ng = fl->ng;
+        f.krw_max = fl->krw_max;
+        f.kro_max = fl->kro_max;
+        f.krg_max = fl->krg_max;
+        f.cr = rock->cr;
+        f.pref = rock->pref;
+        std::vector<double> tab(6 * fl->nrows, 1.0);
+        for (int r = 0; r < fl->nrows; ++r) {
+            tab[r] = fl->p[r];
+            tab[fl->nrows + r] = fl->bo[r];
+            tab[2 * fl->nrows + r] = bo3 ? fl->rs[r] : 0.0;
+            tab[3 * fl->nrows + r] = fl->muo[r];
+            tab[4 * fl->nrows + r] = bo3 ? fl->bg[r] : 1.0;
+            tab[5 * fl->nrows + r] = bo3 ? fl->mug[r] : 1.0;
+        }
+
+        // device memory (everything above validated the input without the device)
+        HIPCHECK(hipGetDevice(&c->dev));
+        const int n = c->n;
+        c->dx = c->upload(grid->dx, grid->nx);
+        c->dy = c->upload(grid->dy, grid->ny);
+        c->dz = c->upload(grid->dz, grid->nz);
+        c->kx = c->upload(rock->kx, n);
+        c->ky = c->upload(rock->ky, n);
+        c->kz = c->upload(rock->kz, n);
+        c->poro = c->upload(rock->poro, n);
+        c->tab = c->upload(tab.data(), tab.size());
+        f.tab = c->tab;
+        c->vol = c->alloc<double>(n);
+        c->depth = c->alloc<double>(n);
+        c->pvref = c->alloc<double>(n);
+        c->tx = c->alloc<double>(n);
+        c->ty = c->alloc<double>(n);
+        c->tz = c->alloc<double>(n);
+        c->dwkind = c->upload(c->wkind.data(), nwells);
+        c->dwctrl = c->upload(c->wctrl.data(), nwells);
+        c->dwtarget = c->upload(c->wtarget.data(), nwells);
+        c->dwps = c->upload(c->wps.data(), nwells + 1);
+        c->pcell = c->upload(sorted_cells.data(), c->nperf);
+        c->pwell = c->upload(pwell_h.data(), c->nperf);
+        c->wi = c->upload(wi_sorted.data(), c->nperf);
+        c->wrw = c->upload(rw.data(), nwells);
+        c->wskin = c->upload(skin.data(), nwells);
+        c->cps = c->upload(cps.data(), n + 1);
+        c->cperf = c->upload(cperf.data(), cperf.size());
+        c->P = c->alloc<double>(n);
+        c->Sw = c->alloc<double>(n);
+        c->X = c->alloc<double>(n);
+        c->flag = c->alloc<int8_t>(n);
+        c->pbhp = c->alloc<double>(std::max(nwells, 1));
+        for (int k = 0; k < 2; ++k) {
+            c->sP[k] = c->alloc<double>(n);
+            c->sSw[k] = c->alloc<double>(n);
+            c->sX[k] = c->alloc<double>(n);
+            c->sflag[k] = c->alloc<int8_t>(n);
+            c->spb[k] = c->alloc<double>(std::max(nwells, 1));
+        }
+        const int nrec = (c->nb == 2) ? Rec<2>::NREC : Rec<3>::NREC;
+        c->rec = c->alloc<double>((size_t)nrec * n);
+        c->aold = c->alloc<double>((size_t)c->nb * n);
+        c->wmeas = c->alloc<double>(std::max(nwells, 1));
+        c->rowptr = c->upload(rp.data(), rp.size());
+        c->colind = c->upload(ci.data(), ci.size());
+        c->diagpos = c->upload(dp.data(), dp.size());
+        c->val = c->alloc<double>((size_t)c->nnzb * c->nb * c->nb);
+        c->R = c->alloc<double>(c->nvec);
+        c->dinv = c->alloc<double>((size_t)c->nrows * c->nb * c->nb);
+        c->bad = c->alloc<int>(1);
+        c->w = c->alloc<double>(c->nvec);
+        c->z = c->alloc<double>(c->nvec);
+        c->x = c->alloc<double>(c->nvec);
+        c->r = c->alloc<double>(c->nvec);
+        c->t = c->alloc<double>(c->nvec);
+        c->b = c->alloc<double>(c->nvec);
+        c->tmp = c->alloc<double>(kMaxRestart + 2);
+        c->ydev = c->alloc<double>(kMaxRestart + 2);
+        c->reorth = c->alloc<int>(1);
+        alloc_krylov(c, opt->restart);
+        const size_t np = (size_t)(kMaxRestart + 1) * 1024 + (size_t)2048 * 16;
+        c->partials = c->alloc<double>(np);
+        c->scal = c->alloc<double>(S_COUNT);
+        c->counter = c->alloc<unsigned>(1);
+        HIPCHECK(hipMemsetAsync(c->counter, 0, sizeof(unsigned), c->s));
+        HIPCHECK(hipMemsetAsync(c->reorth, 0, sizeof(int), c->s));
+        c->pin_len = S_COUNT + (size_t)(kMaxRestart + 1) * (kMaxRestart + 2) + kMaxRestart + 2;
+        HIPCHECK(hipHostMalloc((void **)&c->pin, c->pin_len * sizeof(double), hipHostMallocDefault));
+        for (auto &e : c->ev) HIPCHECK(hipEventCreate(&e));
+        for (auto &e : c->colev) HIPCHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+
+        // static precompute (PreProcess / ROCK / AllWells setup)
+        launch_static(c->s, c->g, c->dx, c->dy, c->dz, grid->top, c->kx, c->ky, c->kz, c->poro,
+                      c->vol, c->depth, c->pvref, c->tx, c->ty, c->tz);
+        launch_peaceman(c->s, c->g, c->nperf, c->pcell, c->pwell, c->dx, c->dy, c->dz, c->kx,
+                        c->ky, c->wrw, c->wskin, c->wi);
+        HIPCHECK(hipGetLastError());
+        c->sync();
+    } catch (...) {
+        delete c;
+        throw;
+    }
+    *out = c;
+    return FIM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// small device helpers
+
+static void props(fim_ctx *c, bool with_aold) {
+    launch_props(c->s, c->nb, c->phys, c->n, c->pvref, c->P, c->Sw, c->X, c->flag, c->rec,
+                 with_aold ? c->aold : nullptr);
+}
+
+static void assemble(fim_ctx *c, double dt) {
+    launch_assemble(c->s, c->nb, c->g, c->phys, c->wells(), c->sys(), c->depth, c->tx, c->ty,
+                    c->tz, c->P, c->pbhp, c->rec, c->aold, dt, c->wmeas);
+    c->jac_ready = true;
+    c->prec_ready = false;
+}
+
+static void d2h_scalars(fim_ctx *c, int first, int count) {
+    HIPCHECK(hipMemcpyAsync(c->pin + first, c->scal + first, count * sizeof(double),
+                            hipMemcpyDeviceToHost, c->s));
+}
+
+static void save_state(fim_ctx *c, int slot) {
+    const size_t n = c->n;
+    HIPCHECK(hipMemcpyAsync(c->sP[slot], c->P, n * 8, hipMemcpyDeviceToDevice, c->s));
+    HIPCHECK(hipMemcpyAsync(c->sSw[slot], c->Sw, n * 8, hipMemcpyDeviceToDevice, c->s));
+    HIPCHECK(hipMemcpyAsync(c->sX[slot], c->X, n * 8, hipMemcpyDeviceToDevice, c->s));
+    HIPCHECK(hipMemcpyAsync(c->sflag[slot], c->flag, n, hipMemcpyDeviceToDevice, c->s));
+    if (c->nw)
+        HIPCHECK(hipMemcpyAsync(c->spb[slot], c->pbhp, c->nw * 8, hipMemcpyDeviceToDevice, c->s));
+}
+
+static void restore_state(fim_ctx *c, int slot) {
+    const size_t n = c->n;
+    HIPCHECK(hipMemcpyAsync(c->P, c->sP[slot], n * 8, hipMemcpyDeviceToDevice, c->s));
+    HIPCHECK(hipMemcpyAsync(c->Sw, c->sSw[slot], n * 8, hipMemcpyDeviceToDevice, c->s));
+    HIPCHECK(hipMemcpyAsync(c->X, c->sX[slot], n * 8, hipMemcpyDeviceToDevice, c->s));
+    HIPCHECK(hipMemcpyAsync(c->flag, c->sflag[slot], n, hipMemcpyDeviceToDevice, c->s));
+    if (c->nw)
+        HIPCHECK(hipMemcpyAsync(c->pbhp, c->spb[slot], c->nw * 8, hipMemcpyDeviceToDevice, c->s));
+}
+
+static void prec_setup(fim_ctx *c) {
+    launch_bj_setup(c->s, c->nb, c->nrows, c->diagpos, c->val, c->dinv, c->bad);
+    c->prec_ready = true;
+}
+
+// SpMV inside the solver, optionally bracketed by events
+static void solver_spmv(fim_ctx *c, const double *xin, double *yout, bool profile) {
+    if (profile) {
+        if (c->spmv_used + 2 > (int)c->spmv_ev.size()) {
+            // pool full: drain it
+            HIPCHECK(hipEventSynchronize(c->spmv_ev[c->spmv_used - 1]));
+            for (int k = 0; k < c->spmv_used; k += 2) {
+                float ms = 0;
+                HIPCHECK(hipEventElapsedTime(&ms, c->spmv_ev[k], c->spmv_ev[k + 1]));
+                c->spmv_ms += ms;
+            }
+            c->spmv_used = 0;
+        }
+        HIPCHECK(hipEventRecord(c->spmv_ev[c->spmv_used], c->s));
+        launch_spmv(c->s, c->nb, c->nrows, c->rowptr, c->colind, c->val, xin, yout);
+        HIPCHECK(hipEventRecord(c->spmv_ev[c->spmv_used + 1], c->s));
+        c->spmv_used += 2;
+        c->spmv_calls += 1;
+    } else {
+        launch_spmv(c->s, c->nb, c->nrows, c->rowptr, c->colind, c->val, xin, yout);
+    }
+}
+
+static void drain_spmv_events(fim_ctx *c) {
+    if (!c->spmv_used) return;
+    HIPCHECK(hipEventSynchronize(c->spmv_ev[c->spmv_used - 1]));
+    for (int k = 0; k < c->spmv_used; k += 2) {
+        float ms = 0;
+        HIPCHECK(hipEventElapsedTime(&ms, c->spmv_ev[k], c->spmv_ev[k + 1]));
+        c->spmv_ms += ms;
+    }
+    c->spmv_used = 0;
+}
+
+// ---------------------------------------------------------------------------
+// right-preconditioned restarted GMRES with classical Gram-Schmidt and a
+// DGKS-triggered second pass.  Solves J x = b (b, x device vectors of the
+// context), initial guess zero.  The host stays one Arnoldi step behind the
+// device: step j+1 is queued before the Hessenberg column of step j is read.
+
+static int gmres(fim_ctx *c, const double *bvec, double *xvec, int max_it, double rtol,
+                 bool profile, int *iters_out, double *relres_out) {
+    const int m = c->m, nb = c->nb, nrows = c->nrows;
+    const long nv = c->nvec;
+    const int LD = kMaxRestart + 2;          // stride of a Hessenberg column
+    double *pinH = c->pin + S_COUNT;          // pinned copies of the columns
+    double *piny = pinH + (size_t)(kMaxRestart + 1) * LD;
+    launch_scale_copy(c->s, nv, nullptr, 0.0, xvec);
+    launch_norm2(c->s, nv, bvec, c->partials, c->counter, c->scal + S_NORM);
+    d2h_scalars(c, S_NORM, 2);
+    c->sync();
+    const double bnorm = c->pin[S_NORM + 1];
+    *iters_out = 0;
+    if (!(bnorm > 0.0)) {
+        *relres_out = (bnorm == 0.0) ? 0.0 : NAN;
+        return bnorm == 0.0 ? 0 : -1;
+    }
+    std::vector<double> Hh((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+    hipEvent_t *colev = c->colev;
+    const double *rvec = bvec;
+    const double *beta_dev = c->scal + S_NORM + 1;
+    double beta = bnorm;
+    int total = 0, status = 1;
+    double relres = 1.0;
+
+    auto enqueue = [&](int j) {
+        double *col = c->H + (size_t)j * LD;
+        double *vj1 = c->V + (size_t)(j + 1) * nv;
+        solver_spmv(c, c->z, c->w, profile);
+        launch_multidot(c->s, nv, j + 1, c->V, c->w, c->partials, c->counter, col, nullptr);
+        launch_update_norm(c->s, nv, j + 1, c->V, col, c->w, c->partials, c->counter, col + j + 1,
+                           nullptr, c->reorth, nullptr);
+        launch_multidot(c->s, nv, j + 1, c->V, c->w, c->partials, c->counter, c->tmp, c->reorth);
+        launch_update_norm(c->s, nv, j + 1, c->V, c->tmp, c->w, c->partials, c->counter,
+                           col + j + 1, c->reorth, nullptr, col);
+        launch_normalize_precond(c->s, nb, nrows, c->w, col + j + 1, vj1, c->z, c->dinv);
+        HIPCHECK(hipMemcpyAsync(pinH + (size_t)j * LD, col, (j + 2) * sizeof(double),
+                                hipMemcpyDeviceToHost, c->s));
+        HIPCHECK(hipEventRecord(colev[j], c->s));
+    };
+
+    {
+        for (;;) {
+            launch_normalize_precond(c->s, nb, nrows, rvec, beta_dev, c->V, c->z, c->dinv);
+            std::fill(g.begin(), g.end(), 0.0);
+            g[0] = beta;
+            int k = 0;
+            enqueue(0);
+            for (int j = 0;; ++j) {
+                if (j + 1 < m && total + j + 1 < max_it) enqueue(j + 1);
+                HIPCHECK(hipEventSynchronize(colev[j]));
+                const double *h = pinH + (size_t)j * LD;
+                for (int i = 0; i <= j + 1; ++i) Hh[(size_t)i * m + j] = h[i];
+                for (int i = 0; i < j; ++i) {
+                    const double a = Hh[(size_t)i * m + j], bq = Hh[(size_t)(i + 1) * m + j];
+                    Hh[(size_t)i * m + j] = cs[i] * a + sn[i] * bq;
+                    Hh[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * bq;
+                }
+                const double a = Hh[(size_t)j * m + j], bq = Hh[(size_t)(j + 1) * m + j];
+                const double den = std::hypot(a, bq);
+                cs[j] = den > 0 ? a / den : 1.0;
+                sn[j] = den > 0 ? bq / den : 0.0;
+                Hh[(size_t)j * m + j] = den;
+                Hh[(size_t)(j + 1) * m + j] = 0.0;
+                g[j + 1] = -sn[j] * g[j];
+                g[j] = cs[j] * g[j];
+                k = j + 1;
+                const bool breakdown = !(h[j + 1] > 0.0) || !std::isfinite(h[j + 1]);
+                if (std::fabs(g[j + 1]) <= rtol * bnorm || k == m || total + k >= max_it ||
+                    breakdown || !std::isfinite(g[j + 1]))
+                    break;
+            }
+            total += k;
+            // least squares: back substitution on the rotated Hessenberg matrix
+            for (int i = k - 1; i >= 0; --i) {
+                double sacc = g[i];
+                for (int jj = i + 1; jj < k; ++jj) sacc -= Hh[(size_t)i * m + jj] * y[jj];
+                y[i] = sacc / Hh[(size_t)i * m + i];
+            }
+            for (int i = 0; i < k; ++i) piny[i] = y[i];
+            HIPCHECK(hipMemcpyAsync(c->ydev, piny, k * sizeof(double), hipMemcpyHostToDevice, c->s));
+            launch_final_update(c->s, nb, nrows, k, c->V, c->ydev, c->dinv, xvec);
+            solver_spmv(c, xvec, c->t, profile);
+            launch_residual(c->s, nv, bvec, c->t, c->r, c->partials, c->counter, c->scal + S_RES);
+            d2h_scalars(c, S_RES, 2);
+            c->sync();
+            beta = c->pin[S_RES + 1];
+            relres = beta / bnorm;
+            if (relres <= rtol) {
+                status = 0;
+                break;
+            }
+            if (total >= max_it || !std::isfinite(relres)) break;
+            rvec = c->r;
+            beta_dev = c->scal + S_RES + 1;
+        }
+    }
+    *iters_out = total;
+    *relres_out = relres;
+    return status;
+}
+
+// ---------------------------------------------------------------------------
+// Newton iterations for one sub-step (Sec. 3.2.4): 1 when converged.
+
+struct NewtonStats {
+    int newton = 0, linear = 0;
+    double cnv[3] = {0, 0, 0}, mb[3] = {0, 0, 0};
+    double t_asm = 0, t_lin = 0, t_upd = 0;
+};
+
+static float elapsed(hipEvent_t a, hipEvent_t b) {
+    float ms = 0;
+    HIPCHECK(hipEventElapsedTime(&ms, a, b));
+    return ms;
+}
+
+static bool newton(fim_ctx *c, double dt, NewtonStats &st) {
+    const fim_options &o = c->opt;
+    const int nb = c->nb;
+    double last_dp = INFINITY, last_ds = INFINITY;
+    bool pending_update = false;
+    for (int it = 0;; ++it) {
+        HIPCHECK(hipEventRecord(c->ev[0], c->s));
+        props(c, it == 0);
+        assemble(c, dt);
+        launch_conv(c->s, nb, c->n, c->nw, c->rec, c->R, c->wmeas, dt, c->partials,
+                    conv_blocks(c->n), c->counter, c->scal + S_CONV);
+        HIPCHECK(hipEventRecord(c->ev[1], c->s));
+        d2h_scalars(c, S_CONV, S_NORM - S_CONV);
+        c->sync();
+        if (pending_update) st.t_upd += elapsed(c->ev[2], c->ev[3]);
+        st.t_asm += elapsed(c->ev[0], c->ev[1]);
+        const double *sc = c->pin + S_CONV;
+        if (it > 0) {
+            last_dp = c->pin[S_UPD];
+            last_ds = c->pin[S_UPD + 1];
+        }
+        bool finite = std::isfinite(last_dp) || it == 0;
+        bool conv = it > 0;
+        for (int i = 0; i < nb; ++i) {
+            st.cnv[i] = sc[i];
+            st.mb[i] = dt * std::fabs(sc[nb + i]) / sc[2 * nb + i];
+            finite = finite && std::isfinite(st.cnv[i]) && std::isfinite(st.mb[i]);
+            conv = conv && st.cnv[i] <= o.tol_cnv && st.mb[i] <= o.tol_mb;
+        }
+        const double wmax = sc[3 * nb];
+        finite = finite && std::isfinite(wmax);
+        if (!finite) return false;
+        conv = conv && wmax <= o.tol_well && last_dp <= o.tol_dp && last_ds <= o.tol_ds;
+        if (conv) return true;
+        if (it >= o.max_newton) return false;
+
+        prec_setup(c);
+        int li = 0;
+        double rr = 0;
+        const int gs = gmres(c, c->R, c->x, o.max_lin, o.lin_rtol, o.profile != 0, &li, &rr);
+        HIPCHECK(hipEventRecord(c->ev[2], c->s));
+        HIPCHECK(hipEventSynchronize(c->ev[2]));
+        st.t_lin += elapsed(c->ev[1], c->ev[2]);
+        st.linear += li;
+        st.newton += 1;
+        if (gs != 0 && !(std::isfinite(rr) && rr < 1.0)) return false;
+        launch_newton_update(c->s, nb, c->phys, c->n, c->nw, c->x, o.ds_max, o.dp_max, c->P,
+                             c->Sw, c->X, c->flag, c->pbhp, c->partials, update_blocks(c->n),
+                             c->counter, c->scal + S_UPD);
+        HIPCHECK(hipEventRecord(c->ev[3], c->s));
+        pending_update = true;
+    }
+}
+
+static int step_impl(fim_ctx *c, double dt, fim_step_report *rep) {
+    REQUIRE(dt > 0 && std::isfinite(dt), "dt must be > 0");
+    if (!c->state_set) {
+        set_err("state not set (call fim_set_state first)");
+        throw StateError();
+    }
+    fim_step_report r{};
+    c->spmv_ms = 0;
+    c->spmv_calls = 0;
+    c->spmv_used = 0;
+    if (c->opt.profile && c->spmv_ev.empty()) {
+        c->spmv_ev.resize(2048);
+        for (auto &e : c->spmv_ev) HIPCHECK(hipEventCreate(&e));
+    }
+    save_state(c, 0);
+    double remaining = dt, h = dt;
+    int status = FIM_OK;
+    NewtonStats st;
+    while (remaining > 1e-12 * dt) {
+        const double tdt = std::min(h, remaining);
+        save_state(c, 1);
+        if (newton(c, tdt, st)) {
+            remaining -= tdt;
+            if (r.nsub < FIM_MAX_SUB) r.dt_sub[r.nsub] = tdt;
+            r.nsub++;
+        } else {
+            restore_state(c, 1);
+            r.cuts++;
+            if (r.cuts > c->opt.max_cuts) {
+                restore_state(c, 0);
+                status = FIM_NOT_CONVERGED;
+                break;
+            }
+            h = 0.5 * tdt;
+        }
+    }
+    // step-start accumulation of the next step
+    props(c, true);
+    drain_spmv_events(c);
+    c->sync();
+    c->jac_ready = false;
+    r.newton_iters = st.newton;
+    r.linear_iters = st.linear;
+    r.converged = status == FIM_OK;
+    r.dt_done = status == FIM_OK ? dt : 0.0;
+    for (int i = 0; i < 3; ++i) {
+        r.cnv[i] = st.cnv[i];
+        r.mb[i] = st.mb[i];
+    }
+    r.t_assemble = st.t_asm;
+    r.t_linear = st.t_lin;
+    r.t_update = st.t_upd;
+    r.spmv_ms = c->spmv_ms;
+    r.spmv_calls = c->spmv_calls;
+    if (rep) *rep = r;
+    return status;
+}
+
+// ---------------------------------------------------------------------------
+// state transfer
+
+static void put_state(fim_ctx *c, const double *p, const double *sw, const double *x3,
+                      const int8_t *flag, const double *bhp, bool dev, bool reset_start) {
+    REQUIRE(p && sw, "p and sw are required");
+    const size_t n = c->n;
+    const hipMemcpyKind kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    HIPCHECK(hipMemcpyAsync(c->P, p, n * 8, kind, c->s));
+    HIPCHECK(hipMemcpyAsync(c->Sw, sw, n * 8, kind, c->s));
+    if (x3 && c->nb == 3) HIPCHECK(hipMemcpyAsync(c->X, x3, n * 8, kind, c->s));
+    else launch_scale_copy(c->s, (long)n, nullptr, 0.0, c->X);
+    if (flag && c->nb == 3) HIPCHECK(hipMemcpyAsync(c->flag, flag, n, kind, c->s));
+    else HIPCHECK(hipMemsetAsync(c->flag, 0, n, c->s));
+    std::vector<double> pb(c->nw);
+    if (bhp) {
+        for (int wl = 0; wl < c->nw; ++wl) pb[wl] = bhp[wl];
+    } else if (c->nw) {
+        // BHP wells start at their target, rate wells at the mean pressure of
+        // their perforated cells
+        std::vector<double> ph(n);
+        if (dev) {
+            HIPCHECK(hipMemcpyAsync(ph.data(), p, n * 8, hipMemcpyDeviceToHost, c->s));
+            c->sync();
+        } else {
+            std::memcpy(ph.data(), p, n * 8);
+        }
+        std::vector<int> cells(c->nperf);
+        HIPCHECK(hipMemcpy(cells.data(), c->pcell, c->nperf * sizeof(int), hipMemcpyDeviceToHost));
+        for (int wl = 0; wl < c->nw; ++wl) {
+            if (c->wctrl[wl] == FIM_BHP) {
+                pb[wl] = c->wtarget[wl];
+            } else {
+                double sacc = 0;
+                for (int q = c->wps[wl]; q < c->wps[wl + 1]; ++q) sacc += ph[cells[q]];
+                pb[wl] = sacc / (c->wps[wl + 1] - c->wps[wl]);
+            }
+        }
+    }
+    if (c->nw) {
+        HIPCHECK(hipMemcpyAsync(c->pbhp, pb.data(), c->nw * 8, hipMemcpyHostToDevice, c->s));
+    }
+    if (reset_start) props(c, true);
+    c->sync();
+    c->state_set = true;
+    c->jac_ready = false;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+
+extern "C" {
+
+const char *fim_last_error(void) { return g_err.c_str(); }
+
+int fim_create(const fim_grid *grid, const fim_rock *rock, const fim_fluid *fluid,
+               int32_t nwells, const fim_well *wells, const fim_options *opt, void *hip_stream,
+               fim_ctx **out) {
+    return guarded([&] { return create_impl(grid, rock, fluid, nwells, wells, opt, hip_stream, out); });
+}
+
+void fim_destroy(fim_ctx *ctx) { delete ctx; }
+
+int fim_sizes(const fim_ctx *c, int32_t *ncells, int32_t *nb, int32_t *nwells, int32_t *nnzb,
+              int32_t *nprops) {
+    return guarded([&] {
+        REQUIRE(c, "context is NULL");
+        if (ncells) *ncells = c->n;
+        if (nb) *nb = c->nb;
+        if (nwells) *nwells = c->nw;
+        if (nnzb) *nnzb = c->nnzb;
+        if (nprops) *nprops = (c->nb == 2) ? Rec<2>::N : Rec<3>::N;
+        return FIM_OK;
+    });
+}
+
+int fim_set_options(fim_ctx *c, const fim_options *opt) {
+    return guarded([&] {
+        REQUIRE(c, "context is NULL");
+        check_options(opt);
+        if (opt->restart > c->m) {
+            c->sync();
+            alloc_krylov(c, opt->restart);
+        } else {
+            c->m = opt->restart;
+        }
+        c->opt = *opt;
+        return FIM_OK;
+    });
+}
+
+int fim_set_state(fim_ctx *c, const double *p, const double *sw, const double *x3,
+                  const int8_t *flag, const double *bhp) {
+    return guarded([&] {
+        REQUIRE(c, "context is NULL");
+        put_state(c, p, sw, x3, flag, bhp, false, true);
+        return FIM_OK;
+    });
+}
+
+int fim_set_state_dev(fim_ctx *c, const double *p, const double *sw, const double *x3,
+                      const int8_t *flag, const double *bhp) {
+    return guarded([&] {
+        REQUIRE(c, "context is NULL");
+        put_state(c, p, sw, x3, flag, bhp, true, true);
+        return FIM_OK;
+    });
+}
+
+int fim_set_iterate(fim_ctx *c, const double *p, const double *sw, const double *x3,
+                    const int8_t *flag, const double *bhp) {
+    return guarded([&] {
+        REQUIRE(c, "context is NULL");
+        if (!c->state_set) {
+            set_err("state not set (call fim_set_state first)");
+            throw StateError();
+        }
+        put_state(c, p, sw, x3, flag, bhp, false, false);
+        return FIM_OK;
+    });
+}
+
+int fim_get_state(fim_ctx *c, double *p, double *sw, double *x3, int8_t *flag, double *bhp) {
+    return guarded([&] {
+        REQUIRE(c, "context is NULL");
+        const size_t n = c->n;
+        if (p) HIPCHECK(hipMemcpyAsync(p, c->P, n * 8, hipMemcpyDeviceToHost, c->s));
+        if (sw) HIPCHECK(hipMemcpyAsync(sw, c->Sw, n * 8, hipMemcpyDeviceToHost, c->s));
+        if (x3) HIPCHECK(hipMemcpyAsync(x3, c->X, n * 8, hipMemcpyDeviceToHost, c->s));
+        if (flag) HIPCHECK(hipMemcpyAsync(flag, c->flag, n, hipMemcpyDeviceToHost, c->s));
+        if (bhp && c->nw)
+            HIPCHECK(hipMemcpyAsync(bhp, c->pbhp, c->nw * 8, hipMemcpyDeviceToHost, c->s));
+        c->sync();
+        return FIM_OK;
+    });
+}
+
+int fim_step(fim_ctx *c, double dt_days, fim_step_report *rep) {
+    return guarded([&] {
+        REQUIRE(c, "context is NULL");
+        return step_impl(c, dt_days, rep);
+    });
+}
+
+int fim_get_well_rates(fim_ctx *c, double *q_surf, double *bhp) {
+    return guarded([&] {
+        REQUIRE(c, "context is NULL");
+        if (!c->state_set) {
+            set_err("state not set");
+            throw StateError();
+        }
+        if (c->nw == 0) return FIM_OK;
+        props(c, false);
+        double *dq = c->partials;   // scratch, >= 3 * nwells doubles
+        launch_well_rates(c->s, c->nb, c->wells(), c->P, c->pbhp, c->rec, c->n, dq);
+        if (q_surf) HIPCHECK(hipMemcpyAsync(q_surf, dq, c->nw * 3 * 8, hipMemcpyDeviceToHost, c->s));
+        if (bhp) HIPCHECK(hipMemcpyAsync(bhp, c->pbhp, c->nw * 8, hipMemcpyDeviceToHost, c->s));
+        c->sync();
+        return FIM_OK;
+    });
+}
+
+int fim_static(fim_ctx *c, double *vol, double *depth, double *pvref, double *tx, double *ty,
+               double *tz, double *wi_out) {
+    return guarded([&] {
+        REQUIRE(c, "context is NULL");
+        const size_t b = (size_t)c->n * 8;
+        if (vol) HIPCHECK(hipMemcpyAsync(vol, c->vol, b, hipMemcpyDeviceToHost, c->s));
+        if (depth) HIPCHECK(hipMemcpyAsync(depth, c->depth, b, hipMemcpyDeviceToHost, c->s));
+        if (pvref) HIPCHECK(hipMemcpyAsync(pvref, c->pvref, b, hipMemcpyDeviceToHost, c->s));
+        if (tx) HIPCHECK(hipMemcpyAsync(tx, c->tx, b, hipMemcpyDeviceToHost, c->s));
+        if (ty) HIPCHECK(hipMemcpyAsync(ty, c->ty, b, hipMemcpyDeviceToHost, c->s));
+        if (tz) HIPCHECK(hipMemcpyAsync(tz, c->tz, b, hipMemcpyDeviceToHost, c->s));
+        std::vector<double> ws(c->nperf);
+        if (wi_out && c->nperf)
+            HIPCHECK(hipMemcpyAsync(ws.data(), c->wi, c->nperf * 8, hipMemcpyDeviceToHost, c->s));
+        c->sync();
+        if (wi_out)
+            for (int q = 0; q < c->nperf; ++q) wi_out[c->perf_src[q]] = ws[q];
+        return FIM_OK;
+    });
+}
+
+int fim_props(fim_ctx *c, double *out) {
+    return guarded([&] {
+        REQUIRE(c && out, "context and out are required");
+        if (!c->state_set) {
+            set_err("state not set");
+            throw StateError();
+        }
+        props(c, false);
+        const int N = (c->nb == 2) ? Rec<2>::N : Rec<3>::N;
+        HIPCHECK(hipMemcpyAsync(out, c->rec, (size_t)N * c->n * 8, hipMemcpyDeviceToHost, c->s));
+        c->sync();
+        return FIM_OK;
+    });
+}
+
+int fim_assemble(fim_ctx *c, double dt, double *Rout, int32_t *rowptr, int32_t *colind,
+                 double *valout) {
+    return guarded([&] {
+        REQUIRE(c, "context is NULL");
+        REQUIRE(dt > 0, "dt must be > 0");
+        if (!c->state_set) {
+            set_err("state not set");
+            throw StateError();
+        }
+        props(c, false);
+        assemble(c, dt);
+        HIPCHECK(hipGetLastError());
+        if (Rout) HIPCHECK(hipMemcpyAsync(Rout, c->R, c->nvec * 8, hipMemcpyDeviceToHost, c->s));
+        if (rowptr)
+            HIPCHECK(hipMemcpyAsync(rowptr, c->rowptr, (c->nrows + 1) * 4, hipMemcpyDeviceToHost, c->s));
+        if (colind)
+            HIPCHECK(hipMemcpyAsync(colind, c->colind, (size_t)c->nnzb * 4, hipMemcpyDeviceToHost, c->s));
+        if (valout)
+            HIPCHECK(hipMemcpyAsync(valout, c->val, (size_t)c->nnzb * c->nb * c->nb * 8,
+                                    hipMemcpyDeviceToHost, c->s));
+        c->sync();
+        return FIM_OK;
+    });
+}
+
+int fim_precond_apply(fim_ctx *c, const double *xh, double *yh) {
+    return guarded([&] {
+        REQUIRE(c && xh && yh, "context, x and y are required");
+        if (!c->jac_ready) {
+            set_err("no assembled Jacobian (call fim_assemble first)");
+            throw StateError();
+        }
+        prec_setup(c);
+        HIPCHECK(hipMemcpyAsync(c->b, xh, c->nvec * 8, hipMemcpyHostToDevice, c->s));
+        launch_bj_apply(c->s, c->nb, c->nrows, c->dinv, c->b, c->t);
+        HIPCHECK(hipMemcpyAsync(yh, c->t, c->nvec * 8, hipMemcpyDeviceToHost, c->s));
+        c->sync();
+        return FIM_OK;
+    });
+}
+
+int fim_linear_solve(fim_ctx *c, const double *bh, double *xh, int32_t *iters, double *relres) {
+    return guarded([&] {
+        REQUIRE(c && bh && xh, "context, b and x are required");
+        if (!c->jac_ready) {
+            set_err("no assembled Jacobian (call fim_assemble first)");
+            throw StateError();
+        }
+        prec_setup(c);
+        HIPCHECK(hipMemcpyAsync(c->b, bh, c->nvec * 8, hipMemcpyHostToDevice, c->s));
+        int it = 0;
+        double rr = 0;
+        const int st = gmres(c, c->b, c->x, c->opt.max_lin, c->opt.lin_rtol, false, &it, &rr);
+        HIPCHECK(hipMemcpyAsync(xh, c->x, c->nvec * 8, hipMemcpyDeviceToHost, c->s));
+        c->sync();
+        if (iters) *iters = it;
+        if (relres) *relres = rr;
+        return st == 0 ? FIM_OK : FIM_NOT_CONVERGED;
+    });
+}
+
+int fim_bsr_spmv(int32_t nrows, int32_t nb, const int32_t *rowptr, const int32_t *colind,
+                 const double *val, const double *x, double *y, void *hip_stream) {
+    return guarded([&] {
+        REQUIRE(nb == 2 || nb == 3, "nb must be 2 or 3");
+        REQUIRE(nrows >= 0, "nrows must be >= 0");
+        if (nrows == 0) return FIM_OK;
+        REQUIRE(rowptr && colind && val && x && y, "device pointers are required");
+        launch_spmv(static_cast<hipStream_t>(hip_stream), nb, nrows, rowptr, colind, val, x, y);
+        HIPCHECK(hipGetLastError());
+        return FIM_OK;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,122 @@
+// fim_internal.h - device data layout and kernel launchers of libfim.so.
+//
+// Layout in HBM (one context):
+//   state        P, Sw, X [n] fp64, flag [n] int8, pbhp [nw]  (structure of arrays)
+//   static       depth, pvref, tx, ty, tz [n]                 (cell-owned + faces)
+//   properties   rec [NREC][n]: the exported property record followed by
+//                d(b_j)/dP for each phase (used by injector perforations)
+//   system       R [(n+nw)*nb] interleaved; BSR rowptr [n+nw+1], colind [nnzb],
+//                val [nnzb][nb][nb] row-major blocks; diagpos [n+nw]
+//   Krylov       V [(m+1)][(n+nw)*nb], w, z, x, b, r [(n+nw)*nb]; dinv [n+nw][nb][nb]
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fim {
+
+constexpr int kMaxTableRows = 64;
+constexpr int kBlock = 256;          // threads per block of the cell/vector kernels
+constexpr int kMaxRestart = 40;       // GMRES restart length cap (registers of multidot)
+
+enum { kProd = 0, kInjWater = 1, kInjGas = 2 };
+enum { kBhp = 0, kRate = 1 };
+enum { kUnsat = 0, kSat = 1 };
+
+// Index map of the property record for block size NB (NB phases).
+template <int NB>
+struct Rec {
+    static constexpr int G = NB + 1;                   // value + NB derivatives
+    static constexpr int LAM = 0;                      // NB groups: kr_j b_j / mu_j
+    static constexpr int LAMOG = NB * G;               // NB == 3: Rs * Lam_o
+    static constexpr int LT = LAMOG + (NB == 3 ? G : 0);   // total mobility
+    static constexpr int GAM = LT + G;                 // NB groups: rho_j / 144
+    static constexpr int ACC = GAM + NB * G;           // NB groups: accumulations
+    static constexpr int B = ACC + NB * G;             // NB values: 1/B_j
+    static constexpr int PV = B + NB;                  // pore volume
+    static constexpr int N = PV + 1;                   // exported record length
+    static constexpr int DBP = N;                      // NB values: d(1/B_j)/dP
+    static constexpr int NREC = N + NB;                // stored record length
+};
+
+struct Phys {                       // fluid + rock scalars, passed by value
+    int model, nrows;
+    double co_us, cmu_us, bw_ref, cw, muw, pw_ref;
+    double rho_w, rho_o, rho_g;
+    double swc, sor, sgc, nw, no, ng, krw_max, kro_max, krg_max;
+    double cr, pref;
+    const double *tab;              // device [6][nrows]: p, bo, rs, muo, bg, mug
+};
+
+struct Grid {
+    int nx, ny, nz, n;
+};
+
+struct Wells {                      // perforations sorted by cell within each well
+    int nw;
+    const int *kind, *ctrl;         // [nw]
+    const double *target;           // [nw]
+    const int *wps;                 // [nw+1] perforation ranges
+    const int *pcell;               // [nperf] perforated cell
+    const int *pwell;               // [nperf] owning well
+    const double *wi;               // [nperf]
+    const int *cps;                 // [n+1] per-cell ranges into cperf
+    const int *cperf;               // perforations of each cell, ascending well
+};
+
+struct Sys {
+    const int *rowptr, *colind, *diagpos;
+    double *val, *R;
+};
+
+// ---- physics kernels (fim_phys.hip) ---------------------------------------
+void launch_static(hipStream_t s, Grid g, const double *dx, const double *dy, const double *dz,
+                   double top, const double *kx, const double *ky, const double *kz,
+                   const double *poro, double *vol, double *depth, double *pvref, double *tx,
+                   double *ty, double *tz);
+void launch_peaceman(hipStream_t s, Grid g, int nperf, const int *pcell, const int *pwell,
+                     const double *dx, const double *dy, const double *dz, const double *kx,
+                     const double *ky, const double *rw, const double *skin, double *wi);
+void launch_props(hipStream_t s, int nb, Phys f, int n, const double *pvref, const double *P,
+                  const double *Sw, const double *X, const int8_t *flag, double *rec,
+                  double *aold);
+void launch_assemble(hipStream_t s, int nb, Grid g, Phys f, Wells w, Sys sys,
+                     const double *depth, const double *tx, const double *ty, const double *tz,
+                     const double *P, const double *pbhp, const double *rec, const double *aold,
+                     double dt, double *wmeas);
+void launch_conv(hipStream_t s, int nb, int n, int nw, const double *rec, const double *R,
+                 const double *wmeas, double dt, double *partials, int nparts_blocks,
+                 unsigned *counter, double *out);
+void launch_newton_update(hipStream_t s, int nb, Phys f, int n, int nw, const double *y,
+                          double ds_max, double dp_max, double *P, double *Sw, double *X,
+                          int8_t *flag, double *pbhp, double *partials, int nblocks,
+                          unsigned *counter, double *out);
+void launch_well_rates(hipStream_t s, int nb, Wells w, const double *P, const double *pbhp,
+                       const double *rec, int n, double *q);
+int conv_blocks(int n);
+int update_blocks(int n);
+
+// ---- linear algebra kernels (fim_linalg.hip) --------------------------------
+void launch_spmv(hipStream_t s, int nb, int nrows, const int *rowptr, const int *colind,
+                 const double *val, const double *x, double *y);
+void launch_bj_setup(hipStream_t s, int nb, int nrows, const int *diagpos, const double *val,
+                     double *dinv, int *bad);
+void launch_bj_apply(hipStream_t s, int nb, int nrows, const double *dinv, const double *x,
+                     double *y);
+// partial-sum helpers shared by the Krylov kernels
+int vec_blocks(long nvec);
+void launch_norm2(hipStream_t s, long nvec, const double *x, double *partials,
+                  unsigned *counter, double *out);
+void launch_normalize_precond(hipStream_t s, int nb, int nrows, const double *w,
+                              const double *hptr, double *v, double *z, const double *dinv);
+void launch_multidot(hipStream_t s, long nvec, int nv, const double *V, const double *w,
+                     double *partials, unsigned *counter, double *dst, const int *gate);
+void launch_update_norm(hipStream_t s, long nvec, int nv, const double *V, const double *coef,
+                        double *w, double *partials, unsigned *counter, double *hnext,
+                        const int *gate, int *reorth, double *hacc);
+void launch_final_update(hipStream_t s, int nb, int nrows, int k, const double *V,
+                         const double *y, const double *dinv, double *x);
+void launch_residual(hipStream_t s, long nvec, const double *b, const double *Ax, double *r,
+                     double *partials, unsigned *counter, double *out);
+void launch_scale_copy(hipStream_t s, long nvec, const double *x, double a, double *y);
+
+}  // namespace fim

@@ -1,0 +1,473 @@
+// fim_linalg.hip - BSR SpMV, block-Jacobi preconditioner and the vector
+// kernels of right-preconditioned GMRES (paper Sec. 5.1: FGMRES with
+// block-Jacobi smoothing; Sec. 3.3.3: the solve returns the solution and
+// the iteration count).
+//
+// Everything here streams HBM: SpMV assigns a group of G lanes to one block
+// row so consecutive lanes read consecutive blocks (coalesced) while the
+// matrix values and indices, read once, bypass the caches (non-temporal)
+// and the gathered vector stays cached.  The orthogonalisation kernels read
+// each basis vector once per pass with all dot products of a pass
+// accumulated in registers.
+#include <math.h>
+
+#include "fim_internal.h"
+#include "fim_reduce.h"
+
+namespace fim {
+
+typedef double d2 __attribute__((ext_vector_type(2)));
+
+constexpr int kMaxDots = kMaxRestart + 1;   // basis vectors + the vector itself
+
+// ---------------------------------------------------------------------------
+// y = A x, canonical BSR
+
+template <int NB, int G>
+__global__ __launch_bounds__(kBlock) void k_spmv(int nrows, const int *__restrict__ rowptr,
+                                                 const int *__restrict__ colind,
+                                                 const double *__restrict__ val,
+                                                 const double *__restrict__ x,
+                                                 double *__restrict__ y) {
+    const int lg = threadIdx.x & (G - 1);
+    const int row = (int)(((long)blockIdx.x * blockDim.x + threadIdx.x) / G);
+    double acc[NB];
+#pragma unroll
+    for (int e = 0; e < NB; ++e) acc[e] = 0.0;
+    if (row < nrows) {
+        const int b = __builtin_nontemporal_load(rowptr + row);
+        const int e = __builtin_nontemporal_load(rowptr + row + 1);
+        for (int q = b + lg; q < e; q += G) {
+            const int col = __builtin_nontemporal_load(colind + q);
+            if constexpr (NB == 2) {
+                const d2 *blk = reinterpret_cast<const d2 *>(val + (size_t)q * 4);
+                const d2 r0 = __builtin_nontemporal_load(blk);
+                const d2 r1 = __builtin_nontemporal_load(blk + 1);
+                const d2 xv = *reinterpret_cast<const d2 *>(x + (size_t)col * 2);
+                acc[0] += r0.x * xv.x + r0.y * xv.y;
+                acc[1] += r1.x * xv.x + r1.y * xv.y;
+            } else {
+                const double *blk = val + (size_t)q * NB * NB;
+                double a[NB * NB], xv[NB];
+#pragma unroll
+                for (int t = 0; t < NB * NB; ++t) a[t] = __builtin_nontemporal_load(blk + t);
+#pragma unroll
+                for (int u = 0; u < NB; ++u) xv[u] = x[(size_t)col * NB + u];
+#pragma unroll
+                for (int r = 0; r < NB; ++r)
+#pragma unroll
+                    for (int u = 0; u < NB; ++u) acc[r] += a[r * NB + u] * xv[u];
+            }
+        }
+    }
+#pragma unroll
+    for (int off = G / 2; off >= 1; off >>= 1)
+#pragma unroll
+        for (int e = 0; e < NB; ++e) acc[e] += __shfl_xor(acc[e], off, 64);
+    if (row < nrows && lg == 0) {
+        if constexpr (NB == 2) {
+            d2 o;
+            o.x = acc[0];
+            o.y = acc[1];
+            *reinterpret_cast<d2 *>(y + (size_t)row * 2) = o;
+        } else {
+#pragma unroll
+            for (int e = 0; e < NB; ++e) y[(size_t)row * NB + e] = acc[e];
+        }
+    }
+}
+
+void launch_spmv(hipStream_t s, int nb, int nrows, const int *rowptr, const int *colind,
+                 const double *val, const double *x, double *y) {
+    constexpr int G = 8;
+    const long threads = (long)nrows * G;
+    dim3 grid((unsigned)((threads + kBlock - 1) / kBlock)), block(kBlock);
+    if (nb == 2)
+        hipLaunchKernelGGL((k_spmv<2, G>), grid, block, 0, s, nrows, rowptr, colind, val, x, y);
+    else
+        hipLaunchKernelGGL((k_spmv<3, G>), grid, block, 0, s, nrows, rowptr, colind, val, x, y);
+}
+
+// ---------------------------------------------------------------------------
+// block Jacobi: inverse of each diagonal block
+
+template <int NB>
+__device__ inline bool invert_block(const double *a, double *inv) {
+    if constexpr (NB == 2) {
+        const double det = a[0] * a[3] - a[1] * a[2];
+        if (!(det != 0.0) || !isfinite(det)) return false;
+        const double r = 1.0 / det;
+        inv[0] = a[3] * r;
+        inv[1] = -a[1] * r;
+        inv[2] = -a[2] * r;
+        inv[3] = a[0] * r;
+        return true;
+    } else {
+        // Gauss-Jordan elimination with row pivoting on [A | I]
+        double m[NB][2 * NB];
+#pragma unroll
+        for (int r = 0; r < NB; ++r)
+#pragma unroll
+            for (int c = 0; c < 2 * NB; ++c) m[r][c] = c < NB ? a[r * NB + c] : (c - NB == r);
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+            // pivot search and row swap with compile-time row indices only
+            int p = c;
+            double best = fabs(m[c][c]);
+#pragma unroll
+            for (int r = c + 1; r < NB; ++r)
+                if (fabs(m[r][c]) > best) {
+                    best = fabs(m[r][c]);
+                    p = r;
+                }
+            if (!(best != 0.0)) return false;
+#pragma unroll
+            for (int r = c + 1; r < NB; ++r)
+                if (r == p)
+#pragma unroll
+                    for (int k = 0; k < 2 * NB; ++k) {
+                        const double t = m[c][k];
+                        m[c][k] = m[r][k];
+                        m[r][k] = t;
+                    }
+            const double d = 1.0 / m[c][c];
+#pragma unroll
+            for (int k = 0; k < 2 * NB; ++k) m[c][k] *= d;
+#pragma unroll
+            for (int r = 0; r < NB; ++r) {
+                if (r == c) continue;
+                const double f = m[r][c];
+#pragma unroll
+                for (int k = 0; k < 2 * NB; ++k) m[r][k] -= f * m[c][k];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < NB; ++r)
+#pragma unroll
+            for (int c = 0; c < NB; ++c) inv[r * NB + c] = m[r][NB + c];
+        return true;
+    }
+}
+
+template <int NB>
+__global__ __launch_bounds__(kBlock) void k_bj_setup(int nrows, const int *__restrict__ diagpos,
+                                                     const double *__restrict__ val,
+                                                     double *__restrict__ dinv, int *bad) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrows) return;
+    double a[NB * NB], inv[NB * NB];
+    const double *src = val + (size_t)diagpos[r] * NB * NB;
+#pragma unroll
+    for (int t = 0; t < NB * NB; ++t) a[t] = src[t];
+    if (!invert_block<NB>(a, inv)) {
+        atomicOr(bad, 1);
+#pragma unroll
+        for (int t = 0; t < NB * NB; ++t) inv[t] = (t % (NB + 1) == 0) ? 1.0 : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < NB * NB; ++t) dinv[(size_t)r * NB * NB + t] = inv[t];
+}
+
+template <int NB>
+__device__ inline void apply_block(const double *__restrict__ dinv, int r, const double (&v)[NB],
+                                   double (&z)[NB]) {
+    const double *m = dinv + (size_t)r * NB * NB;
+#pragma unroll
+    for (int e = 0; e < NB; ++e) {
+        double s = 0.0;
+#pragma unroll
+        for (int u = 0; u < NB; ++u) s += m[e * NB + u] * v[u];
+        z[e] = s;
+    }
+}
+
+template <int NB>
+__global__ __launch_bounds__(kBlock) void k_bj_apply(int nrows, const double *__restrict__ dinv,
+                                                     const double *__restrict__ x,
+                                                     double *__restrict__ y) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrows) return;
+    double v[NB], z[NB];
+#pragma unroll
+    for (int e = 0; e < NB; ++e) v[e] = x[(size_t)r * NB + e];
+    apply_block<NB>(dinv, r, v, z);
+#pragma unroll
+    for (int e = 0; e < NB; ++e) y[(size_t)r * NB + e] = z[e];
+}
+
+void launch_bj_setup(hipStream_t s, int nb, int nrows, const int *diagpos, const double *val,
+                     double *dinv, int *bad) {
+    dim3 grid((nrows + kBlock - 1) / kBlock), block(kBlock);
+    if (nb == 2) hipLaunchKernelGGL(k_bj_setup<2>, grid, block, 0, s, nrows, diagpos, val, dinv, bad);
+    else hipLaunchKernelGGL(k_bj_setup<3>, grid, block, 0, s, nrows, diagpos, val, dinv, bad);
+}
+
+void launch_bj_apply(hipStream_t s, int nb, int nrows, const double *dinv, const double *x,
+                     double *y) {
+    dim3 grid((nrows + kBlock - 1) / kBlock), block(kBlock);
+    if (nb == 2) hipLaunchKernelGGL(k_bj_apply<2>, grid, block, 0, s, nrows, dinv, x, y);
+    else hipLaunchKernelGGL(k_bj_apply<3>, grid, block, 0, s, nrows, dinv, x, y);
+}
+
+// ---------------------------------------------------------------------------
+// Krylov vector kernels.  Grids are capped so the last-block reductions stay
+// short; every thread walks the vector with a grid stride.
+
+int vec_blocks(long nvec) {
+    long b = (nvec + kBlock - 1) / kBlock;
+    return (int)(b < 1024 ? (b > 0 ? b : 1) : 1024);
+}
+
+// out[0] = ||x||^2, out[1] = ||x||
+__global__ __launch_bounds__(kBlock) void k_norm2(long nvec, const double *__restrict__ x,
+                                                  double *partials, unsigned *counter,
+                                                  double *out) {
+    double v[1] = {0.0};
+    const bool mx[1] = {false};
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < nvec;
+         i += (long)gridDim.x * blockDim.x) {
+        const double a = x[i];
+        v[0] += a * a;
+    }
+    if (grid_reduce<1>(v, mx, partials, counter, out) && threadIdx.x == 0) out[1] = sqrt(out[0]);
+}
+
+void launch_norm2(hipStream_t s, long nvec, const double *x, double *partials, unsigned *counter,
+                  double *out) {
+    hipLaunchKernelGGL(k_norm2, dim3(vec_blocks(nvec)), dim3(kBlock), 0, s, nvec, x, partials,
+                       counter, out);
+}
+
+// v = w / h and z = M^-1 v (block Jacobi), one block row per thread.  h is
+// read from device memory (h <= 0 or non-finite: zero vectors, the happy
+// breakdown of the Arnoldi process).
+template <int NB>
+__global__ __launch_bounds__(kBlock) void k_normalize_precond(int nrows,
+                                                              const double *__restrict__ w,
+                                                              const double *__restrict__ hptr,
+                                                              double *__restrict__ v,
+                                                              double *__restrict__ z,
+                                                              const double *__restrict__ dinv) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrows) return;
+    const double h = *hptr;
+    const bool ok = h > 0.0 && isfinite(h);
+    double a[NB], b[NB];
+#pragma unroll
+    for (int e = 0; e < NB; ++e) a[e] = ok ? w[(size_t)r * NB + e] / h : 0.0;
+    apply_block<NB>(dinv, r, a, b);
+#pragma unroll
+    for (int e = 0; e < NB; ++e) {
+        v[(size_t)r * NB + e] = a[e];
+        z[(size_t)r * NB + e] = b[e];
+    }
+}
+
+void launch_normalize_precond(hipStream_t s, int nb, int nrows, const double *w,
+                              const double *hptr, double *v, double *z, const double *dinv) {
+    dim3 grid((nrows + kBlock - 1) / kBlock), block(kBlock);
+    if (nb == 2)
+        hipLaunchKernelGGL(k_normalize_precond<2>, grid, block, 0, s, nrows, w, hptr, v, z, dinv);
+    else
+        hipLaunchKernelGGL(k_normalize_precond<3>, grid, block, 0, s, nrows, w, hptr, v, z, dinv);
+}
+
+// Reductions of several sums at once.  Slots i < k and the last slot
+// (kMaxDots-1) are active; loops are fully unrolled with guards so the
+// per-thread values stay in registers.  Result in thread 0.
+__device__ inline bool slot_on(int i, int k) { return i < k || i == kMaxDots - 1; }
+
+__device__ inline void block_reduce_many(double (&v)[kMaxDots], int k,
+                                         double (&sh)[kMaxDots][kWaves]) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < kMaxDots; ++i) {
+        if (!slot_on(i, k)) continue;
+        double a = v[i];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) a += __shfl_xor(a, off, 64);
+        if (lane == 0) sh[i][wid] = a;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < kMaxDots; ++i) {
+            if (!slot_on(i, k)) continue;
+            double a = sh[i][0];
+            for (int w = 1; w < kWaves; ++w) a += sh[i][w];
+            v[i] = a;
+        }
+    }
+    __syncthreads();
+}
+
+// Grid reduction; partials laid out [slot][block] so the last block reads
+// them with all its threads.  out[i] for i < k, out[k] = last slot.  True
+// in the last block.
+__device__ inline bool grid_reduce_many(double (&v)[kMaxDots], int k, double *partials,
+                                        unsigned *counter, double *out) {
+    __shared__ double sh[kMaxDots][kWaves];
+    __shared__ int is_last;
+    block_reduce_many(v, k, sh);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < kMaxDots; ++i)
+            if (slot_on(i, k)) partials[(size_t)i * gridDim.x + blockIdx.x] = v[i];
+        __threadfence();
+        is_last = (atomicAdd(counter, 1u) == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!is_last) return false;
+    __threadfence();
+#pragma unroll
+    for (int i = 0; i < kMaxDots; ++i) {
+        v[i] = 0.0;
+        if (slot_on(i, k))
+            for (unsigned b = threadIdx.x; b < gridDim.x; b += blockDim.x)
+                v[i] += partials[(size_t)i * gridDim.x + b];
+    }
+    block_reduce_many(v, k, sh);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < kMaxDots - 1; ++i)
+            if (i < k) out[i] = v[i];
+        out[k] = v[kMaxDots - 1];
+        atomicExch(counter, 0u);
+    }
+    return true;
+}
+
+// dst[i] = <V_i, w> for i < nv, dst[nv] = <w, w>.  Skipped when *gate == 0.
+__global__ __launch_bounds__(kBlock) void k_multidot(long nvec, int nv, const double *__restrict__ V,
+                                                     const double *__restrict__ w,
+                                                     double *partials, unsigned *counter,
+                                                     double *dst, const int *gate) {
+    if (gate && *gate == 0) return;
+    double acc[kMaxDots];
+#pragma unroll
+    for (int i = 0; i < kMaxDots; ++i) acc[i] = 0.0;
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < nvec;
+         e += (long)gridDim.x * blockDim.x) {
+        const double we = w[e];
+#pragma unroll
+        for (int i = 0; i < kMaxDots - 1; ++i)
+            if (i < nv) acc[i] += __builtin_nontemporal_load(V + (size_t)i * nvec + e) * we;
+        acc[kMaxDots - 1] += we * we;
+    }
+    grid_reduce_many(acc, nv, partials, counter, dst);
+}
+
+void launch_multidot(hipStream_t s, long nvec, int nv, const double *V, const double *w,
+                     double *partials, unsigned *counter, double *dst, const int *gate) {
+    hipLaunchKernelGGL(k_multidot, dim3(vec_blocks(nvec)), dim3(kBlock), 0, s, nvec, nv, V, w,
+                       partials, counter, dst, gate);
+}
+
+// w -= sum_{i<nv} coef[i] V_i, then ||w||.  In the last block: when hacc is
+// set (second Gram-Schmidt pass) hacc[i] += coef[i]; hnext = ||w||; when
+// reorth is set (first pass) it becomes 1 if the norm dropped below
+// ||w_before|| / sqrt(2) = sqrt(coef[nv] / 2) (the DGKS test).
+__global__ __launch_bounds__(kBlock) void k_update_norm(long nvec, int nv,
+                                                        const double *__restrict__ V,
+                                                        const double *coef, double *w,
+                                                        double *partials, unsigned *counter,
+                                                        double *hnext, const int *gate,
+                                                        int *reorth, double *hacc) {
+    if (gate && *gate == 0) return;
+    __shared__ double c[kMaxDots];
+    for (int i = threadIdx.x; i <= nv; i += blockDim.x) c[i] = coef[i];
+    __syncthreads();
+    double v[1] = {0.0};
+    const bool mx[1] = {false};
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < nvec;
+         e += (long)gridDim.x * blockDim.x) {
+        double a = w[e];
+#pragma unroll 4
+        for (int i = 0; i < nv; ++i) a -= c[i] * __builtin_nontemporal_load(V + (size_t)i * nvec + e);
+        w[e] = a;
+        v[0] += a * a;
+    }
+    double out[1];
+    if (grid_reduce<1>(v, mx, partials, counter, out) && threadIdx.x == 0) {
+        const double before = c[nv];
+        if (hacc)
+            for (int i = 0; i < nv; ++i) hacc[i] += c[i];
+        if (reorth) *reorth = (out[0] < 0.5 * before) ? 1 : 0;
+        *hnext = sqrt(out[0]);
+    }
+}
+
+void launch_update_norm(hipStream_t s, long nvec, int nv, const double *V, const double *coef,
+                        double *w, double *partials, unsigned *counter, double *hnext,
+                        const int *gate, int *reorth, double *hacc) {
+    hipLaunchKernelGGL(k_update_norm, dim3(vec_blocks(nvec)), dim3(kBlock), 0, s, nvec, nv, V,
+                       coef, w, partials, counter, hnext, gate, reorth, hacc);
+}
+
+// x += M^-1 (sum_{i<k} y_i V_i)
+template <int NB>
+__global__ __launch_bounds__(kBlock) void k_final_update(int nrows, int k,
+                                                         const double *__restrict__ V,
+                                                         const double *__restrict__ y,
+                                                         const double *__restrict__ dinv,
+                                                         double *__restrict__ x) {
+    __shared__ double ys[kMaxRestart];
+    for (int i = threadIdx.x; i < k; i += blockDim.x) ys[i] = y[i];
+    __syncthreads();
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrows) return;
+    const size_t nvec = (size_t)nrows * NB;
+    double u[NB], z[NB];
+#pragma unroll
+    for (int e = 0; e < NB; ++e) u[e] = 0.0;
+    for (int i = 0; i < k; ++i)
+#pragma unroll
+        for (int e = 0; e < NB; ++e) u[e] += ys[i] * V[i * nvec + (size_t)r * NB + e];
+    apply_block<NB>(dinv, r, u, z);
+#pragma unroll
+    for (int e = 0; e < NB; ++e) x[(size_t)r * NB + e] += z[e];
+}
+
+void launch_final_update(hipStream_t s, int nb, int nrows, int k, const double *V,
+                         const double *y, const double *dinv, double *x) {
+    dim3 grid((nrows + kBlock - 1) / kBlock), block(kBlock);
+    if (nb == 2) hipLaunchKernelGGL(k_final_update<2>, grid, block, 0, s, nrows, k, V, y, dinv, x);
+    else hipLaunchKernelGGL(k_final_update<3>, grid, block, 0, s, nrows, k, V, y, dinv, x);
+}
+
+// r = b - Ax; out[0] = ||r||^2, out[1] = ||r||
+__global__ __launch_bounds__(kBlock) void k_residual(long nvec, const double *__restrict__ b,
+                                                     const double *__restrict__ Ax,
+                                                     double *__restrict__ r, double *partials,
+                                                     unsigned *counter, double *out) {
+    double v[1] = {0.0};
+    const bool mx[1] = {false};
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < nvec;
+         i += (long)gridDim.x * blockDim.x) {
+        const double a = b[i] - Ax[i];
+        r[i] = a;
+        v[0] += a * a;
+    }
+    if (grid_reduce<1>(v, mx, partials, counter, out) && threadIdx.x == 0) out[1] = sqrt(out[0]);
+}
+
+void launch_residual(hipStream_t s, long nvec, const double *b, const double *Ax, double *r,
+                     double *partials, unsigned *counter, double *out) {
+    hipLaunchKernelGGL(k_residual, dim3(vec_blocks(nvec)), dim3(kBlock), 0, s, nvec, b, Ax, r,
+                       partials, counter, out);
+}
+
+__global__ __launch_bounds__(kBlock) void k_scale_copy(long nvec, const double *__restrict__ x,
+                                                       double a, double *__restrict__ y) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < nvec;
+         i += (long)gridDim.x * blockDim.x)
+        y[i] = x ? a * x[i] : a;
+}
+
+// y = a*x, or y = a everywhere when x is null (a fill kernel, so nothing here
+// records a memset node into a captured graph)
+void launch_scale_copy(hipStream_t s, long nvec, const double *x, double a, double *y) {
+    hipLaunchKernelGGL(k_scale_copy, dim3(vec_blocks(nvec)), dim3(kBlock), 0, s, nvec, x, a, y);
+}
+
+}  // namespace fim

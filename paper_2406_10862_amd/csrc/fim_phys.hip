@@ -1,0 +1,768 @@
+// fim_phys.hip - cell, face and well kernels of the FIM black-oil step.
+//
+// Paper anchors: Sec. 2.1 eqs. (1)-(2) and the constraints below them
+// (component conservation, Darcy flux with gravity, N_i = phi sum S_j xi_j
+// x_ij, sum S_j = 1, black-oil closure); Sec. 3.2.3 (Bulk PVT/SAT/ROCK/ACCU,
+// BulkConn, AllWells); Sec. 3.2.4 (one Newton iteration: assemble, solve
+// and update, update properties, check convergence).
+//
+// All kernels are bound by HBM traffic: one thread owns one cell, state and
+// property arrays are structure-of-arrays so a wave touches contiguous
+// memory, and the PVT table is staged in LDS for the interval searches.
+#include <math.h>
+
+#include "fim_internal.h"
+#include "fim_reduce.h"
+
+namespace fim {
+
+constexpr double kDarcy = 0.001127;     // mD*ft^2/(ft*cP) * psi -> rb/day
+constexpr double kBbl = 5.615;          // ft3 per bbl
+constexpr double kPsiFt = 144.0;        // (lb/ft3)*ft -> psi
+
+// ---------------------------------------------------------------------------
+// static precompute: volumes, centre depths, pore volumes, TPFA transmissibilities
+
+__device__ inline double harmonic_T(double k1, double h1, double k2, double h2, double area) {
+    // conductances k*A/h of the two half cells in series
+    double g1 = k1 * area / h1, g2 = k2 * area / h2;
+    if (!(g1 > 0.0) || !(g2 > 0.0)) return 0.0;
+    return kDarcy * (g1 * g2) / (g1 + g2);
+}
+
+__global__ __launch_bounds__(kBlock) void k_static(Grid g, const double *dx, const double *dy,
+                                                   const double *dz, double top,
+                                                   const double *kx, const double *ky,
+                                                   const double *kz, const double *poro,
+                                                   double *vol, double *depth, double *pvref,
+                                                   double *tx, double *ty, double *tz) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.n) return;
+    int i = c % g.nx, j = (c / g.nx) % g.ny, k = c / (g.nx * g.ny);
+    double above = 0.0;
+    for (int kk = 0; kk < k; ++kk) above += dz[kk];
+    double v = dx[i] * dy[j] * dz[k];
+    vol[c] = v;
+    depth[c] = top + above + 0.5 * dz[k];
+    pvref[c] = v * poro[c] / kBbl;
+    int nxy = g.nx * g.ny;
+    tx[c] = (i + 1 < g.nx)
+                ? harmonic_T(kx[c], 0.5 * dx[i], kx[c + 1], 0.5 * dx[i + 1], dy[j] * dz[k])
+                : 0.0;
+    ty[c] = (j + 1 < g.ny) ? harmonic_T(ky[c], 0.5 * dy[j], ky[c + g.nx], 0.5 * dy[j + 1],
+                                        dx[i] * dz[k])
+                           : 0.0;
+    tz[c] = (k + 1 < g.nz)
+                ? harmonic_T(kz[c], 0.5 * dz[k], kz[c + nxy], 0.5 * dz[k + 1], dx[i] * dy[j])
+                : 0.0;
+}
+
+// Peaceman well index with the anisotropic equivalent radius
+__global__ void k_peaceman(Grid g, int nperf, const int *pcell, const int *pwell,
+                           const double *dx, const double *dy, const double *dz,
+                           const double *kx, const double *ky, const double *rw,
+                           const double *skin, double *wi) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nperf || wi[p] > 0.0) return;
+    int c = pcell[p], w = pwell[p];
+    int i = c % g.nx, j = (c / g.nx) % g.ny, k = c / (g.nx * g.ny);
+    double a = ky[c] / kx[c];                          // anisotropy ratio
+    double num = sqrt(sqrt(a) * dx[i] * dx[i] + sqrt(1.0 / a) * dy[j] * dy[j]);
+    double ro = 0.28 * num / (pow(a, 0.25) + pow(1.0 / a, 0.25));
+    wi[p] = 2.0 * M_PI * kDarcy * sqrt(kx[c] * ky[c]) * dz[k] / (log(ro / rw[w]) + skin[w]);
+}
+
+// ---------------------------------------------------------------------------
+// per-cell black-oil properties with derivatives
+
+struct TabL {                       // PVT columns in LDS
+    const double *p, *bo, *rs, *muo, *bg, *mug;
+    int n;
+};
+
+__device__ inline void stage_table(const Phys &f, double *sm, TabL &t) {
+    for (int e = threadIdx.x; e < 6 * f.nrows; e += blockDim.x) sm[e] = f.tab[e];
+    t.n = f.nrows;
+    t.p = sm;
+    t.bo = sm + f.nrows;
+    t.rs = sm + 2 * f.nrows;
+    t.muo = sm + 3 * f.nrows;
+    t.bg = sm + 4 * f.nrows;
+    t.mug = sm + 5 * f.nrows;
+    __syncthreads();
+}
+
+// largest i in [0, n-2] with t[i] <= v (0 when v is below the table)
+__device__ inline int interval(const double *t, int n, double v) {
+    int lo = 0, hi = n - 2;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (t[mid] <= v) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ inline double lin(const double *t, const double *y, int i, double v, double &slope) {
+    slope = (y[i + 1] - y[i]) / (t[i + 1] - t[i]);
+    return y[i] + slope * (v - t[i]);
+}
+
+__device__ inline void corey(double num, double den, double kmax, double ex, double &kr,
+                             double &dkr) {
+    double s = num / den;
+    if (s <= 0.0) {
+        kr = 0.0;
+        dkr = 0.0;
+    } else if (s >= 1.0) {
+        kr = kmax;
+        dkr = 0.0;
+    } else {
+        double sp = pow(s, ex - 1.0);
+        kr = kmax * sp * s;
+        dkr = kmax * ex * sp / den;
+    }
+}
+
+__device__ inline double rs_sat(const TabL &t, double P) {
+    double s;
+    return lin(t.p, t.rs, interval(t.p, t.n, P), P, s);
+}
+
+template <int NB>
+__device__ void cell_props(const Phys &f, const TabL &t, double pvref, double P, double Sw,
+                           double X, int flag, double (&r)[Rec<NB>::NREC]) {
+    using RI = Rec<NB>;
+    constexpr int G = RI::G;
+#pragma unroll
+    for (int q = 0; q < RI::NREC; ++q) r[q] = 0.0;
+
+    const double bw = exp(f.cw * (P - f.pw_ref)) / f.bw_ref;
+    const double dbw = f.cw * bw;
+    double Rs = 0, dRsP = 0, dRsX = 0, Bo, dBoP, dBoX = 0, muo, dmuoP, dmuoX = 0;
+    double Sg = 0, dSgX = 0, Bg = 1, dBgP = 0, mug = 1, dmugP = 0;
+    const int ip = interval(t.p, t.n, P);
+    if constexpr (NB == 2) {
+        Bo = lin(t.p, t.bo, ip, P, dBoP);
+        muo = lin(t.p, t.muo, ip, P, dmuoP);
+    } else {
+        Bg = lin(t.p, t.bg, ip, P, dBgP);
+        mug = lin(t.p, t.mug, ip, P, dmugP);
+        if (flag == kSat) {
+            Rs = lin(t.p, t.rs, ip, P, dRsP);
+            Bo = lin(t.p, t.bo, ip, P, dBoP);
+            muo = lin(t.p, t.muo, ip, P, dmuoP);
+            Sg = X;
+            dSgX = 1.0;
+        } else {
+            // undersaturated: bubble point on the Rs column, saturated data at
+            // Pb on the same interval, linear extension in P - Pb
+            Rs = X;
+            dRsX = 1.0;
+            const int ir = interval(t.rs, t.n, Rs);
+            const double dPb = (t.p[ir + 1] - t.p[ir]) / (t.rs[ir + 1] - t.rs[ir]);
+            const double Pb = t.p[ir] + (Rs - t.rs[ir]) * dPb;
+            double sB, sM;
+            const double Bb = lin(t.p, t.bo, ir, Pb, sB);
+            const double Mb = lin(t.p, t.muo, ir, Pb, sM);
+            const double d = P - Pb;
+            Bo = Bb * (1.0 - f.co_us * d);
+            dBoP = -Bb * f.co_us;
+            dBoX = (sB * (1.0 - f.co_us * d) + Bb * f.co_us) * dPb;
+            muo = Mb * (1.0 + f.cmu_us * d);
+            dmuoP = Mb * f.cmu_us;
+            dmuoX = (sM * (1.0 + f.cmu_us * d) - Mb * f.cmu_us) * dPb;
+        }
+    }
+    const double bo = 1.0 / Bo, dboP = -dBoP * bo * bo, dboX = -dBoX * bo * bo;
+    const double bg = 1.0 / Bg, dbgP = -dBgP * bg * bg;
+
+    // gravity gradients rho_j / 144
+    const double mo = kBbl * f.rho_o + Rs * f.rho_g;        // lb per stb of oil + gas
+    r[RI::GAM + 0 * G + 0] = f.rho_w * bw / kPsiFt;
+    r[RI::GAM + 0 * G + 1] = f.rho_w * dbw / kPsiFt;
+    r[RI::GAM + 1 * G + 0] = mo * bo / (kBbl * kPsiFt);
+    r[RI::GAM + 1 * G + 1] = (dRsP * f.rho_g * bo + mo * dboP) / (kBbl * kPsiFt);
+    if constexpr (NB == 3) {
+        r[RI::GAM + 1 * G + 3] = (dRsX * f.rho_g * bo + mo * dboX) / (kBbl * kPsiFt);
+        r[RI::GAM + 2 * G + 0] = f.rho_g * bg / (kBbl * kPsiFt);
+        r[RI::GAM + 2 * G + 1] = f.rho_g * dbgP / (kBbl * kPsiFt);
+    }
+
+    // relative permeabilities
+    const double So = 1.0 - Sw - Sg;
+    const double Dgo = 1.0 - f.swc - f.sor - (NB == 3 ? f.sgc : 0.0);
+    double krw, dkrw, kro, dkro, krg = 0, dkrg = 0;
+    corey(Sw - f.swc, 1.0 - f.swc - f.sor, f.krw_max, f.nw, krw, dkrw);
+    corey(So - f.sor, Dgo, f.kro_max, f.no, kro, dkro);
+    if constexpr (NB == 3) corey(Sg - f.sgc, Dgo, f.krg_max, f.ng, krg, dkrg);
+    const double dkroSw = -dkro, dkroX = -dkro * dSgX, dkrgX = dkrg * dSgX;
+
+    // Lam_j = kr_j b_j / mu_j
+    r[RI::LAM + 0] = krw * bw / f.muw;
+    r[RI::LAM + 1] = krw * dbw / f.muw;
+    r[RI::LAM + 2] = dkrw * bw / f.muw;
+    const double bmo = bo / muo;
+    const double dbmoP = (dboP - bmo * dmuoP) / muo;
+    const double dbmoX = (dboX - bmo * dmuoX) / muo;
+    const double lo = kro * bmo;
+    r[RI::LAM + G + 0] = lo;
+    r[RI::LAM + G + 1] = kro * dbmoP;
+    r[RI::LAM + G + 2] = dkroSw * bmo;
+    if constexpr (NB == 3) {
+        const double dloX = dkroX * bmo + kro * dbmoX;
+        r[RI::LAM + G + 3] = dloX;
+        const double bmg = bg / mug;
+        r[RI::LAM + 2 * G + 0] = krg * bmg;
+        r[RI::LAM + 2 * G + 1] = krg * (dbgP - bmg * dmugP) / mug;
+        r[RI::LAM + 2 * G + 3] = dkrgX * bmg;
+        r[RI::LAMOG + 0] = Rs * lo;
+        r[RI::LAMOG + 1] = dRsP * lo + Rs * r[RI::LAM + G + 1];
+        r[RI::LAMOG + 2] = Rs * r[RI::LAM + G + 2];
+        r[RI::LAMOG + 3] = dRsX * lo + Rs * dloX;
+    }
+    // total mobility sum_j kr_j / mu_j
+    r[RI::LT + 0] = krw / f.muw + kro / muo + (NB == 3 ? krg / mug : 0.0);
+    r[RI::LT + 1] = -kro * dmuoP / (muo * muo) - (NB == 3 ? krg * dmugP / (mug * mug) : 0.0);
+    r[RI::LT + 2] = dkrw / f.muw + dkroSw / muo;
+    if constexpr (NB == 3) r[RI::LT + 3] = dkroX / muo - kro * dmuoX / (muo * muo) + dkrgX / mug;
+
+    // pore volume and accumulation N_i = PV sum_j S_j b_j x_ij
+    const double pv = pvref * (1.0 + f.cr * (P - f.pref));
+    const double dpv = pvref * f.cr;
+    r[RI::PV] = pv;
+    r[RI::B + 0] = bw;
+    r[RI::B + 1] = bo;
+    r[RI::DBP + 0] = dbw;
+    r[RI::DBP + 1] = dboP;
+    r[RI::ACC + 0] = pv * bw * Sw;
+    r[RI::ACC + 1] = (dpv * bw + pv * dbw) * Sw;
+    r[RI::ACC + 2] = pv * bw;
+    r[RI::ACC + G + 0] = pv * bo * So;
+    r[RI::ACC + G + 1] = (dpv * bo + pv * dboP) * So;
+    r[RI::ACC + G + 2] = -pv * bo;
+    if constexpr (NB == 3) {
+        r[RI::B + 2] = bg;
+        r[RI::DBP + 2] = dbgP;
+        r[RI::ACC + G + 3] = pv * (dboX * So - bo * dSgX);
+        const double gas = bg * Sg + Rs * bo * So;
+        const double gP = dbgP * Sg + (dRsP * bo + Rs * dboP) * So;
+        const double gX = bg * dSgX + (dRsX * bo + Rs * dboX) * So - Rs * bo * dSgX;
+        r[RI::ACC + 2 * G + 0] = pv * gas;
+        r[RI::ACC + 2 * G + 1] = dpv * gas + pv * gP;
+        r[RI::ACC + 2 * G + 2] = -pv * Rs * bo;
+        r[RI::ACC + 2 * G + 3] = pv * gX;
+    }
+}
+
+template <int NB>
+__global__ __launch_bounds__(kBlock) void k_props(Phys f, int n, const double *__restrict__ pvref,
+                                                  const double *__restrict__ P,
+                                                  const double *__restrict__ Sw,
+                                                  const double *__restrict__ X,
+                                                  const int8_t *__restrict__ flag,
+                                                  double *__restrict__ rec,
+                                                  double *__restrict__ aold) {
+    __shared__ double sm[6 * kMaxTableRows];
+    TabL t;
+    stage_table(f, sm, t);
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    using RI = Rec<NB>;
+    double r[RI::NREC];
+    cell_props<NB>(f, t, pvref[c], P[c], Sw[c], NB == 3 ? X[c] : 0.0, NB == 3 ? flag[c] : 0, r);
+#pragma unroll
+    for (int q = 0; q < RI::NREC; ++q) rec[(size_t)q * n + c] = r[q];
+    if (aold)
+#pragma unroll
+        for (int i = 0; i < NB; ++i) aold[(size_t)i * n + c] = r[RI::ACC + i * RI::G];
+}
+
+// ---------------------------------------------------------------------------
+// face fluxes and cell-centric assembly
+
+template <int NB>
+struct Side {                       // what a face needs from one cell
+    double P, z;
+    double lam[NB][NB + 1];
+    double lamog[NB + 1];
+    double gam[NB][NB + 1];
+};
+
+template <int NB>
+__device__ inline void load_side(const double *__restrict__ rec, int n, int c,
+                                 const double *__restrict__ P, const double *__restrict__ depth,
+                                 Side<NB> &s) {
+    using RI = Rec<NB>;
+    s.P = P[c];
+    s.z = depth[c];
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+        for (int u = 0; u <= NB; ++u) {
+            s.lam[j][u] = rec[(size_t)(RI::LAM + j * RI::G + u) * n + c];
+            s.gam[j][u] = rec[(size_t)(RI::GAM + j * RI::G + u) * n + c];
+        }
+#pragma unroll
+    for (int u = 0; u <= NB; ++u)
+        s.lamog[u] = (NB == 3) ? rec[(size_t)(RI::LAMOG + u) * n + c] : 0.0;
+}
+
+// Flux of every component from K to L across a face of transmissibility T
+// (phase-potential upstream weighting, arithmetic mean face density) and
+// its derivatives w.r.t. the unknowns of K and of L.  Both cells of a face
+// evaluate it with the same (K, L) order, so F_LK = -F_KL exactly.
+template <int NB>
+__device__ inline void face_flux(double T, const Side<NB> &K, const Side<NB> &L, double (&F)[NB],
+                                 double (&dK)[NB][NB], double (&dL)[NB][NB]) {
+    const double dz = K.z - L.z;
+    double dphi[NB], gK[NB][NB], gL[NB][NB];
+    bool up[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        dphi[j] = (K.P - L.P) - 0.5 * (K.gam[j][0] + L.gam[j][0]) * dz;
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            gK[j][u] = (u == 0 ? 1.0 : 0.0) - 0.5 * K.gam[j][1 + u] * dz;
+            gL[j][u] = (u == 0 ? -1.0 : 0.0) - 0.5 * L.gam[j][1 + u] * dz;
+        }
+        up[j] = dphi[j] >= 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const double c = up[i] ? K.lam[i][0] : L.lam[i][0];
+        F[i] = T * c * dphi[i];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const double dcK = up[i] ? K.lam[i][1 + u] : 0.0;
+            const double dcL = up[i] ? 0.0 : L.lam[i][1 + u];
+            dK[i][u] = T * (dcK * dphi[i] + c * gK[i][u]);
+            dL[i][u] = T * (dcL * dphi[i] + c * gL[i][u]);
+        }
+    }
+    if constexpr (NB == 3) {        // gas dissolved in the oil phase
+        const double c = up[1] ? K.lamog[0] : L.lamog[0];
+        F[2] += T * c * dphi[1];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const double dcK = up[1] ? K.lamog[1 + u] : 0.0;
+            const double dcL = up[1] ? 0.0 : L.lamog[1 + u];
+            dK[2][u] += T * (dcK * dphi[1] + c * gK[1][u]);
+            dL[2][u] += T * (dcL * dphi[1] + c * gL[1][u]);
+        }
+    }
+}
+
+template <int NB>
+__device__ inline void store_block(double *__restrict__ val, int q, const double (&b)[NB][NB]) {
+    double *dst = val + (size_t)q * NB * NB;
+    if constexpr (NB == 2) {
+        reinterpret_cast<double2 *>(dst)[0] = make_double2(b[0][0], b[0][1]);
+        reinterpret_cast<double2 *>(dst)[1] = make_double2(b[1][0], b[1][1]);
+    } else {
+#pragma unroll
+        for (int e = 0; e < NB; ++e)
+#pragma unroll
+            for (int u = 0; u < NB; ++u) dst[e * NB + u] = b[e][u];
+    }
+}
+
+// Perforation rate of every component and its derivatives (production
+// positive): producers WI*Lam_i*(P - Pbhp); injectors of pure water or free
+// gas -WI*lam_t*b_inj*(Pbhp - P).
+template <int NB>
+__device__ inline void perf_rate(int kind, double wi, double P, double pbhp,
+                                 const double *__restrict__ rec, int n, int c, double (&q)[NB],
+                                 double (&dq)[NB][NB], double (&dqb)[NB]) {
+    using RI = Rec<NB>;
+    auto R = [&](int k) { return rec[(size_t)k * n + c]; };
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        q[i] = 0.0;
+        dqb[i] = 0.0;
+#pragma unroll
+        for (int u = 0; u < NB; ++u) dq[i][u] = 0.0;
+    }
+    if (kind == kProd) {
+        const double d = P - pbhp;
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            double lam = R(RI::LAM + i * RI::G);
+            if (NB == 3 && i == 2) lam += R(RI::LAMOG);
+            q[i] = wi * lam * d;
+            dqb[i] = -wi * lam;
+#pragma unroll
+            for (int u = 0; u < NB; ++u) {
+                double dl = R(RI::LAM + i * RI::G + 1 + u);
+                if (NB == 3 && i == 2) dl += R(RI::LAMOG + 1 + u);
+                dq[i][u] = wi * (dl * d + (u == 0 ? lam : 0.0));
+            }
+        }
+    } else {
+        const int i = (kind == kInjWater) ? 0 : 2;
+        if (i >= NB) return;
+        const double lt = R(RI::LT), b = R(RI::B + i), db = R(RI::DBP + i);
+        const double d = pbhp - P;
+        q[i] = -wi * lt * b * d;
+        dqb[i] = -wi * lt * b;
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const double dlt = R(RI::LT + 1 + u);
+            dq[i][u] = -wi * ((dlt * b + (u == 0 ? lt * db : 0.0)) * d - (u == 0 ? lt * b : 0.0));
+        }
+    }
+}
+
+template <int NB>
+__global__ __launch_bounds__(kBlock) void k_assemble_cells(
+    Grid g, Wells w, Sys sys, const double *__restrict__ depth, const double *__restrict__ tx,
+    const double *__restrict__ ty, const double *__restrict__ tz, const double *__restrict__ P,
+    const double *__restrict__ pbhp, const double *__restrict__ rec,
+    const double *__restrict__ aold, double dt) {
+    using RI = Rec<NB>;
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = g.n;
+    if (c >= n) return;
+    const int nx = g.nx, nxy = g.nx * g.ny;
+    const int i = c % nx, j = (c / nx) % g.ny, k = c / nxy;
+
+    double R[NB], D[NB][NB];
+    const double rdt = 1.0 / dt;
+#pragma unroll
+    for (int e = 0; e < NB; ++e) {
+        R[e] = (rec[(size_t)(RI::ACC + e * RI::G) * n + c] - aold[(size_t)e * n + c]) * rdt;
+#pragma unroll
+        for (int u = 0; u < NB; ++u) D[e][u] = rec[(size_t)(RI::ACC + e * RI::G + 1 + u) * n + c] * rdt;
+    }
+    Side<NB> me, nbr;
+    load_side<NB>(rec, n, c, P, depth, me);
+    int q = sys.rowptr[c];
+    double F[NB], dK[NB][NB], dL[NB][NB], off[NB][NB];
+
+    // neighbour below in index order: it is the K side of the face
+    auto lower = [&](int cn, double T) {
+        load_side<NB>(rec, n, cn, P, depth, nbr);
+        face_flux<NB>(T, nbr, me, F, dK, dL);
+#pragma unroll
+        for (int e = 0; e < NB; ++e) {
+            R[e] -= F[e];
+#pragma unroll
+            for (int u = 0; u < NB; ++u) {
+                D[e][u] -= dL[e][u];
+                off[e][u] = -dK[e][u];
+            }
+        }
+        store_block<NB>(sys.val, q++, off);
+    };
+    // neighbour above in index order: this cell is the K side
+    auto upper = [&](int cn, double T) {
+        load_side<NB>(rec, n, cn, P, depth, nbr);
+        face_flux<NB>(T, me, nbr, F, dK, dL);
+#pragma unroll
+        for (int e = 0; e < NB; ++e) {
+            R[e] += F[e];
+#pragma unroll
+            for (int u = 0; u < NB; ++u) {
+                D[e][u] += dK[e][u];
+                off[e][u] = dL[e][u];
+            }
+        }
+        store_block<NB>(sys.val, q++, off);
+    };
+    if (k > 0) lower(c - nxy, tz[c - nxy]);
+    if (j > 0) lower(c - nx, ty[c - nx]);
+    if (i > 0) lower(c - 1, tx[c - 1]);
+    const int qd = q++;
+    if (i + 1 < nx) upper(c + 1, tx[c]);
+    if (j + 1 < g.ny) upper(c + nx, ty[c]);
+    if (k + 1 < g.nz) upper(c + nxy, tz[c]);
+
+    // perforations of this cell, in ascending well order (well columns)
+    for (int pp = w.cps[c]; pp < w.cps[c + 1]; ++pp) {
+        const int p = w.cperf[pp];
+        const int wl = w.pwell[p];
+        double qr[NB], dq[NB][NB], dqb[NB];
+        perf_rate<NB>(w.kind[wl], w.wi[p], me.P, pbhp[wl], rec, n, c, qr, dq, dqb);
+#pragma unroll
+        for (int e = 0; e < NB; ++e) {
+            R[e] += qr[e];
+#pragma unroll
+            for (int u = 0; u < NB; ++u) {
+                D[e][u] += dq[e][u];
+                off[e][u] = (u == 0) ? dqb[e] : 0.0;
+            }
+        }
+        store_block<NB>(sys.val, q++, off);
+    }
+    store_block<NB>(sys.val, qd, D);
+#pragma unroll
+    for (int e = 0; e < NB; ++e) sys.R[(size_t)c * NB + e] = R[e];
+}
+
+// Well rows: one wave per well.  Rate rows sum the injected component over
+// the perforations; BHP rows pin the bottom-hole pressure.  Slots >= 1 of a
+// well row are identity rows.  wmeas[w] = |R_w| / |dR_w/dPbhp| (psi).
+template <int NB>
+__global__ __launch_bounds__(64) void k_assemble_wells(Wells w, Sys sys, int n,
+                                                       const double *__restrict__ P,
+                                                       const double *__restrict__ pbhp,
+                                                       const double *__restrict__ rec,
+                                                       double *__restrict__ wmeas) {
+    const int wl = blockIdx.x, lane = threadIdx.x;
+    const int row = n + wl, base = sys.rowptr[row];
+    const int p0 = w.wps[wl], np = w.wps[wl + 1] - p0;
+    const bool rate = w.ctrl[wl] == kRate;
+    const int kind = w.kind[wl];
+    const int ii = (kind == kInjGas) ? 2 : 0;
+    double s[2] = {0.0, 0.0};
+    for (int p = lane; p < np; p += 64) {
+        const int pid = p0 + p, c = w.pcell[pid];
+        double blk[NB][NB];
+#pragma unroll
+        for (int e = 0; e < NB; ++e)
+#pragma unroll
+            for (int u = 0; u < NB; ++u) blk[e][u] = 0.0;
+        if (rate && ii < NB) {
+            double qr[NB], dq[NB][NB], dqb[NB];
+            perf_rate<NB>(kind, w.wi[pid], P[c], pbhp[wl], rec, n, c, qr, dq, dqb);
+            s[0] += qr[ii];
+            s[1] += dqb[ii];
+#pragma unroll
+            for (int u = 0; u < NB; ++u) blk[0][u] = -dq[ii][u];
+        }
+        store_block<NB>(sys.val, base + p, blk);
+    }
+    const bool mx[2] = {false, false};
+    wave_reduce<2>(s, mx);
+    if (lane == 0) {
+        double d[NB][NB];
+#pragma unroll
+        for (int e = 0; e < NB; ++e)
+#pragma unroll
+            for (int u = 0; u < NB; ++u) d[e][u] = (e == u && e > 0) ? 1.0 : 0.0;
+        double r0;
+        if (rate) {
+            d[0][0] = -s[1];
+            r0 = -s[0] - w.target[wl];
+        } else {
+            d[0][0] = 1.0;
+            r0 = pbhp[wl] - w.target[wl];
+        }
+        store_block<NB>(sys.val, base + np, d);
+        sys.R[(size_t)row * NB] = r0;
+#pragma unroll
+        for (int e = 1; e < NB; ++e) sys.R[(size_t)row * NB + e] = 0.0;
+        wmeas[wl] = fabs(r0) / (d[0][0] != 0.0 ? fabs(d[0][0]) : 1.0);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// convergence measures: out = [max_c dt|R_ic|/(PV b_i)], [sum_c R_ic],
+// [sum_c PV b_i], max well measure
+
+template <int NB>
+__global__ __launch_bounds__(kBlock) void k_conv(int n, int nw, const double *__restrict__ rec,
+                                                 const double *__restrict__ R,
+                                                 const double *__restrict__ wmeas, double dt,
+                                                 double *partials, unsigned *counter,
+                                                 double *out) {
+    using RI = Rec<NB>;
+    constexpr int K = 3 * NB + 1;
+    double v[K];
+    bool mx[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        v[k] = 0.0;
+        mx[k] = (k < NB) || (k == 3 * NB);
+    }
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
+        const double pv = rec[(size_t)RI::PV * n + c];
+#pragma unroll
+        for (int e = 0; e < NB; ++e) {
+            const double r = R[(size_t)c * NB + e];
+            const double scale = pv * rec[(size_t)(RI::B + e) * n + c];
+            v[e] = rop(v[e], dt * fabs(r) / scale, true);
+            v[NB + e] += r;
+            v[2 * NB + e] += scale;
+        }
+    }
+    if (blockIdx.x == 0)
+        for (int wl = threadIdx.x; wl < nw; wl += blockDim.x) v[3 * NB] = rop(v[3 * NB], wmeas[wl], true);
+    grid_reduce<K>(v, mx, partials, counter, out);
+}
+
+// ---------------------------------------------------------------------------
+// Newton update: delta = -y; per-cell saturation chop and pressure clip,
+// three-phase variable switching; out = [max|dP| (cells and wells), max|dS|]
+
+template <int NB>
+__global__ __launch_bounds__(kBlock) void k_newton_update(Phys f, int n, int nw,
+                                                          const double *__restrict__ y,
+                                                          double ds_max, double dp_max,
+                                                          double *__restrict__ P,
+                                                          double *__restrict__ Sw,
+                                                          double *__restrict__ X,
+                                                          int8_t *__restrict__ flag,
+                                                          double *__restrict__ pbhp,
+                                                          double *partials, unsigned *counter,
+                                                          double *out) {
+    __shared__ double sm[6 * kMaxTableRows];
+    TabL t;
+    stage_table(f, sm, t);
+    double v[2] = {0.0, 0.0};
+    const bool mx[2] = {true, true};
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
+        double dP = -y[(size_t)c * NB];
+        dP = fmin(fmax(dP, -dp_max), dp_max);
+        double dS = -y[(size_t)c * NB + 1];
+        double dX = (NB == 3) ? -y[(size_t)c * NB + 2] : 0.0;
+        const bool sat = (NB == 3) && flag[c] == kSat;
+        double m = fabs(dS);
+        if (sat) m = fmax(m, fabs(dX));
+        if (m > ds_max) {
+            const double a = ds_max / m;
+            dS *= a;
+            if (sat) dX *= a;
+        }
+        const double p = P[c] + dP;
+        P[c] = p;
+        Sw[c] += dS;
+        v[0] = rop(v[0], fabs(dP), true);
+        v[1] = rop(v[1], fabs(dS), true);
+        if constexpr (NB == 3) {
+            if (sat) v[1] = rop(v[1], fabs(dX), true);
+            const double x = X[c] + dX;
+            if (sat && x < 0.0) {
+                flag[c] = kUnsat;
+                X[c] = rs_sat(t, p);
+            } else if (!sat && x > rs_sat(t, p)) {
+                flag[c] = kSat;
+                X[c] = 0.0;
+            } else {
+                X[c] = x;
+            }
+        }
+        if (dP != dP || dS != dS || dX != dX) v[0] = NAN;
+    }
+    if (grid_reduce<2>(v, mx, partials, counter, out) && threadIdx.x == 0) {
+        double m = out[0];
+        for (int wl = 0; wl < nw; ++wl) {
+            double d = -y[(size_t)(n + wl) * NB];
+            d = fmin(fmax(d, -dp_max), dp_max);
+            pbhp[wl] += d;
+            m = rop(m, fabs(d), true);
+            if (d != d) m = NAN;
+        }
+        out[0] = m;
+    }
+}
+
+// Surface rates per well: q[w*3 + i], production positive.
+template <int NB>
+__global__ __launch_bounds__(64) void k_well_rates(Wells w, const double *__restrict__ P,
+                                                   const double *__restrict__ pbhp,
+                                                   const double *__restrict__ rec, int n,
+                                                   double *__restrict__ qout) {
+    const int wl = blockIdx.x, lane = threadIdx.x;
+    const int p0 = w.wps[wl], np = w.wps[wl + 1] - p0;
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int p = lane; p < np; p += 64) {
+        const int pid = p0 + p, c = w.pcell[pid];
+        double qr[NB], dq[NB][NB], dqb[NB];
+        perf_rate<NB>(w.kind[wl], w.wi[pid], P[c], pbhp[wl], rec, n, c, qr, dq, dqb);
+#pragma unroll
+        for (int e = 0; e < NB; ++e) s[e] += qr[e];
+    }
+    const bool mx[3] = {false, false, false};
+    wave_reduce<3>(s, mx);
+    if (lane == 0)
+        for (int e = 0; e < 3; ++e) qout[wl * 3 + e] = s[e];
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+
+static inline int blocks_for(long n, int bs) { return (int)((n + bs - 1) / bs); }
+int conv_blocks(int n) { return min(blocks_for(n, kBlock), 2048); }
+int update_blocks(int n) { return min(blocks_for(n, kBlock), 2048); }
+
+void launch_static(hipStream_t s, Grid g, const double *dx, const double *dy, const double *dz,
+                   double top, const double *kx, const double *ky, const double *kz,
+                   const double *poro, double *vol, double *depth, double *pvref, double *tx,
+                   double *ty, double *tz) {
+    hipLaunchKernelGGL(k_static, dim3(blocks_for(g.n, kBlock)), dim3(kBlock), 0, s, g, dx, dy,
+                       dz, top, kx, ky, kz, poro, vol, depth, pvref, tx, ty, tz);
+}
+
+void launch_peaceman(hipStream_t s, Grid g, int nperf, const int *pcell, const int *pwell,
+                     const double *dx, const double *dy, const double *dz, const double *kx,
+                     const double *ky, const double *rw, const double *skin, double *wi) {
+    if (nperf == 0) return;
+    hipLaunchKernelGGL(k_peaceman, dim3(blocks_for(nperf, 64)), dim3(64), 0, s, g, nperf, pcell,
+                       pwell, dx, dy, dz, kx, ky, rw, skin, wi);
+}
+
+void launch_props(hipStream_t s, int nb, Phys f, int n, const double *pvref, const double *P,
+                  const double *Sw, const double *X, const int8_t *flag, double *rec,
+                  double *aold) {
+    dim3 grid(blocks_for(n, kBlock)), block(kBlock);
+    if (nb == 2)
+        hipLaunchKernelGGL(k_props<2>, grid, block, 0, s, f, n, pvref, P, Sw, X, flag, rec, aold);
+    else
+        hipLaunchKernelGGL(k_props<3>, grid, block, 0, s, f, n, pvref, P, Sw, X, flag, rec, aold);
+}
+
+void launch_assemble(hipStream_t s, int nb, Grid g, Phys f, Wells w, Sys sys,
+                     const double *depth, const double *tx, const double *ty, const double *tz,
+                     const double *P, const double *pbhp, const double *rec, const double *aold,
+                     double dt, double *wmeas) {
+    (void)f;
+    dim3 grid(blocks_for(g.n, kBlock)), block(kBlock);
+    if (nb == 2) {
+        hipLaunchKernelGGL(k_assemble_cells<2>, grid, block, 0, s, g, w, sys, depth, tx, ty, tz,
+                           P, pbhp, rec, aold, dt);
+        if (w.nw)
+            hipLaunchKernelGGL(k_assemble_wells<2>, dim3(w.nw), dim3(64), 0, s, w, sys, g.n, P,
+                               pbhp, rec, wmeas);
+    } else {
+        hipLaunchKernelGGL(k_assemble_cells<3>, grid, block, 0, s, g, w, sys, depth, tx, ty, tz,
+                           P, pbhp, rec, aold, dt);
+        if (w.nw)
+            hipLaunchKernelGGL(k_assemble_wells<3>, dim3(w.nw), dim3(64), 0, s, w, sys, g.n, P,
+                               pbhp, rec, wmeas);
+    }
+}
+
+void launch_conv(hipStream_t s, int nb, int n, int nw, const double *rec, const double *R,
+                 const double *wmeas, double dt, double *partials, int nblocks,
+                 unsigned *counter, double *out) {
+    if (nb == 2)
+        hipLaunchKernelGGL(k_conv<2>, dim3(nblocks), dim3(kBlock), 0, s, n, nw, rec, R, wmeas, dt,
+                           partials, counter, out);
+    else
+        hipLaunchKernelGGL(k_conv<3>, dim3(nblocks), dim3(kBlock), 0, s, n, nw, rec, R, wmeas, dt,
+                           partials, counter, out);
+}
+
+void launch_newton_update(hipStream_t s, int nb, Phys f, int n, int nw, const double *y,
+                          double ds_max, double dp_max, double *P, double *Sw, double *X,
+                          int8_t *flag, double *pbhp, double *partials, int nblocks,
+                          unsigned *counter, double *out) {
+    if (nb == 2)
+        hipLaunchKernelGGL(k_newton_update<2>, dim3(nblocks), dim3(kBlock), 0, s, f, n, nw, y,
+                           ds_max, dp_max, P, Sw, X, flag, pbhp, partials, counter, out);
+    else
+        hipLaunchKernelGGL(k_newton_update<3>, dim3(nblocks), dim3(kBlock), 0, s, f, n, nw, y,
+                           ds_max, dp_max, P, Sw, X, flag, pbhp, partials, counter, out);
+}
+
+void launch_well_rates(hipStream_t s, int nb, Wells w, const double *P, const double *pbhp,
+                       const double *rec, int n, double *q) {
+    if (!w.nw) return;
+    if (nb == 2)
+        hipLaunchKernelGGL(k_well_rates<2>, dim3(w.nw), dim3(64), 0, s, w, P, pbhp, rec, n, q);
+    else
+        hipLaunchKernelGGL(k_well_rates<3>, dim3(w.nw), dim3(64), 0, s, w, P, pbhp, rec, n, q);
+}
+
+}  // namespace fim

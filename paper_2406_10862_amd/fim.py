@@ -1,0 +1,324 @@
+"""ctypes binding of libfim.so (include/fim.h).  Argument marshalling only:
+every numeric step runs in the library's HIP kernels.
+
+The library must have been built (``python -m paper_2406_10862_amd.build``
+or ``__graft_entry__.build()``); importing this module never falls back to
+anything else, it raises when the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import reservoirs as rv
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfim.so")
+
+FIM_OK, FIM_NOT_CONVERGED = 0, 1
+FIM_E_ARG, FIM_E_NOMEM, FIM_E_HIP, FIM_E_STATE = -1, -2, -3, -4
+FIM_MAX_SUB = 256
+
+i32p = C.POINTER(C.c_int32)
+f64p = C.POINTER(C.c_double)
+i8p = C.POINTER(C.c_int8)
+
+
+class FimGrid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("dx", f64p), ("dy", f64p), ("dz", f64p), ("top", C.c_double)]
+
+
+class FimRock(C.Structure):
+    _fields_ = [("kx", f64p), ("ky", f64p), ("kz", f64p), ("poro", f64p),
+                ("cr", C.c_double), ("pref", C.c_double)]
+
+
+class FimFluid(C.Structure):
+    _fields_ = [("model", C.c_int32), ("nrows", C.c_int32),
+                ("p", f64p), ("bo", f64p), ("rs", f64p), ("muo", f64p), ("bg", f64p),
+                ("mug", f64p), ("co_us", C.c_double), ("cmu_us", C.c_double),
+                ("bw_ref", C.c_double), ("cw", C.c_double), ("muw", C.c_double),
+                ("pw_ref", C.c_double), ("rho_sc", C.c_double * 3),
+                ("swc", C.c_double), ("sor", C.c_double), ("sgc", C.c_double),
+                ("nw", C.c_double), ("no", C.c_double), ("ng", C.c_double),
+                ("krw_max", C.c_double), ("kro_max", C.c_double), ("krg_max", C.c_double)]
+
+
+class FimWell(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("control", C.c_int32), ("target", C.c_double),
+                ("nperf", C.c_int32), ("cells", i32p), ("wi", f64p),
+                ("rw", C.c_double), ("skin", C.c_double)]
+
+
+class FimOptions(C.Structure):
+    _fields_ = [("tol_cnv", C.c_double), ("tol_mb", C.c_double), ("tol_dp", C.c_double),
+                ("tol_ds", C.c_double), ("tol_well", C.c_double), ("ds_max", C.c_double),
+                ("dp_max", C.c_double), ("lin_rtol", C.c_double),
+                ("max_newton", C.c_int32), ("max_lin", C.c_int32), ("restart", C.c_int32),
+                ("max_cuts", C.c_int32), ("precond", C.c_int32), ("precision", C.c_int32),
+                ("profile", C.c_int32), ("reserved", C.c_int32)]
+
+
+class FimStepReport(C.Structure):
+    _fields_ = [("newton_iters", C.c_int32), ("linear_iters", C.c_int32),
+                ("cuts", C.c_int32), ("converged", C.c_int32), ("nsub", C.c_int32),
+                ("spmv_calls", C.c_int32), ("dt_done", C.c_double),
+                ("cnv", C.c_double * 3), ("mb", C.c_double * 3),
+                ("t_assemble", C.c_double), ("t_linear", C.c_double),
+                ("t_update", C.c_double), ("spmv_ms", C.c_double),
+                ("dt_sub", C.c_double * FIM_MAX_SUB)]
+
+
+EXPORTS = ["fim_create", "fim_destroy", "fim_last_error", "fim_sizes", "fim_set_options",
+           "fim_set_state", "fim_set_state_dev", "fim_get_state", "fim_step",
+           "fim_get_well_rates", "fim_static", "fim_set_iterate", "fim_props",
+           "fim_assemble", "fim_precond_apply", "fim_linear_solve", "fim_bsr_spmv"]
+
+_LIB = None
+
+
+class FimError(RuntimeError):
+    pass
+
+
+def lib():
+    """Load libfim.so; raises when it has not been built."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise FimError(f"{LIB_PATH} is missing: build it with "
+                       "`python -m paper_2406_10862_amd.build` (no fallback path exists)")
+    # torch bundles its own HIP runtime under the same soname as the system
+    # one; it must be the first one loaded so that the library binds to the
+    # runtime that owns the device and the streams torch hands out
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    L = C.CDLL(LIB_PATH)
+    vp = C.c_void_p
+    L.fim_create.argtypes = [C.POINTER(FimGrid), C.POINTER(FimRock), C.POINTER(FimFluid),
+                             C.c_int32, C.POINTER(FimWell), C.POINTER(FimOptions), vp,
+                             C.POINTER(vp)]
+    L.fim_destroy.argtypes = [vp]
+    L.fim_destroy.restype = None
+    L.fim_last_error.restype = C.c_char_p
+    L.fim_sizes.argtypes = [vp, i32p, i32p, i32p, i32p, i32p]
+    L.fim_set_options.argtypes = [vp, C.POINTER(FimOptions)]
+    for f in ("fim_set_state", "fim_set_iterate"):
+        getattr(L, f).argtypes = [vp, f64p, f64p, f64p, i8p, f64p]
+    L.fim_set_state_dev.argtypes = [vp, vp, vp, vp, vp, f64p]
+    L.fim_get_state.argtypes = [vp, f64p, f64p, f64p, i8p, f64p]
+    L.fim_step.argtypes = [vp, C.c_double, C.POINTER(FimStepReport)]
+    L.fim_get_well_rates.argtypes = [vp, f64p, f64p]
+    L.fim_static.argtypes = [vp] + [f64p] * 7
+    L.fim_props.argtypes = [vp, f64p]
+    L.fim_assemble.argtypes = [vp, C.c_double, f64p, i32p, i32p, f64p]
+    L.fim_precond_apply.argtypes = [vp, f64p, f64p]
+    L.fim_linear_solve.argtypes = [vp, f64p, f64p, i32p, f64p]
+    L.fim_bsr_spmv.argtypes = [C.c_int32, C.c_int32, vp, vp, vp, vp, vp, vp]
+    for f in EXPORTS:
+        if f not in ("fim_destroy", "fim_last_error"):
+            getattr(L, f).restype = C.c_int32
+    _LIB = L
+    return L
+
+
+def _check(rc, what):
+    if rc < 0:
+        raise FimError(f"{what} failed ({rc}): {lib().fim_last_error().decode()}")
+    return rc
+
+
+def _p(a, t):
+    return None if a is None else a.ctypes.data_as(t)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def current_stream():
+    """hipStream_t of torch's current stream, or NULL without torch/GPU."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except Exception:
+        pass
+    return C.c_void_p(0)
+
+
+def options_struct(o: rv.Options, profile=False) -> FimOptions:
+    return FimOptions(tol_cnv=o.tol_cnv, tol_mb=o.tol_mb, tol_dp=o.tol_dp, tol_ds=o.tol_ds,
+                      tol_well=o.tol_well, ds_max=o.ds_max, dp_max=o.dp_max,
+                      lin_rtol=o.lin_rtol, max_newton=o.max_newton, max_lin=o.max_lin,
+                      restart=o.restart, max_cuts=o.max_cuts, precond=o.precond,
+                      precision=o.precision, profile=1 if profile else 0, reserved=0)
+
+
+class Fim:
+    """One fim_ctx built from a seeded reservoir description."""
+
+    def __init__(self, res: rv.Reservoir, options: rv.Options | None = None, stream=None,
+                 profile=False):
+        L = lib()
+        self.res = res
+        fl = res.fluid
+        self._keep = []
+
+        def d(a):
+            a = _f64(a)
+            self._keep.append(a)
+            return _p(a, f64p)
+
+        grid = FimGrid(res.nx, res.ny, res.nz, d(res.dx), d(res.dy), d(res.dz), res.top)
+        rock = FimRock(d(res.kx), d(res.ky), d(res.kz), d(res.poro), res.cr, res.pref)
+        fluid = FimFluid(model=fl.model, nrows=len(fl.p), p=d(fl.p), bo=d(fl.bo), rs=d(fl.rs),
+                         muo=d(fl.muo), bg=d(fl.bg), mug=d(fl.mug), co_us=fl.co_us,
+                         cmu_us=fl.cmu_us, bw_ref=fl.bw_ref, cw=fl.cw, muw=fl.muw,
+                         pw_ref=fl.pw_ref, rho_sc=(C.c_double * 3)(*fl.rho_sc), swc=fl.swc,
+                         sor=fl.sor, sgc=fl.sgc, nw=fl.nw, no=fl.no, ng=fl.ng,
+                         krw_max=fl.krw_max, kro_max=fl.kro_max, krg_max=fl.krg_max)
+        wells = (FimWell * max(len(res.wells), 1))()
+        for k, w in enumerate(res.wells):
+            cells = np.ascontiguousarray(w.cells, dtype=np.int32)
+            self._keep.append(cells)
+            wi = d(w.wi) if w.wi is not None else None
+            wells[k] = FimWell(kind=w.kind, control=w.control, target=w.target,
+                               nperf=len(cells), cells=_p(cells, i32p), wi=wi, rw=w.rw,
+                               skin=w.skin)
+        self.options = options if options is not None else res.options
+        opt = options_struct(self.options, profile)
+        self.stream = current_stream() if stream is None else stream
+        h = C.c_void_p()
+        _check(L.fim_create(C.byref(grid), C.byref(rock), C.byref(fluid), len(res.wells),
+                            wells, C.byref(opt), self.stream, C.byref(h)), "fim_create")
+        self.h = h
+        n, nb, nw, nnzb, npr = (C.c_int32() for _ in range(5))
+        _check(L.fim_sizes(self.h, C.byref(n), C.byref(nb), C.byref(nw), C.byref(nnzb),
+                           C.byref(npr)), "fim_sizes")
+        self.n, self.nb, self.nw, self.nnzb, self.nprops = (n.value, nb.value, nw.value,
+                                                            nnzb.value, npr.value)
+        self.nrows = self.n + self.nw
+        self._keep_static = []
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().fim_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- options / state ---------------------------------------------------------
+    def fim_set_options(self, options: rv.Options, profile=False):
+        self.options = options
+        _check(lib().fim_set_options(self.h, C.byref(options_struct(options, profile))),
+               "fim_set_options")
+
+    def fim_set_state(self, P, Sw, X=None, flag=None, bhp=None):
+        P, Sw = _f64(P), _f64(Sw)
+        X = _f64(X) if X is not None else None
+        flag = np.ascontiguousarray(flag, np.int8) if flag is not None else None
+        bhp = _f64(bhp) if bhp is not None and len(bhp) else None
+        _check(lib().fim_set_state(self.h, _p(P, f64p), _p(Sw, f64p), _p(X, f64p),
+                                   _p(flag, i8p), _p(bhp, f64p)), "fim_set_state")
+
+    def fim_set_state_dev(self, P, Sw, X=None, flag=None, bhp=None):
+        """Device tensors (torch) on the context's device and stream."""
+        ptr = lambda t: C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+        bhp = _f64(bhp) if bhp is not None and len(bhp) else None
+        _check(lib().fim_set_state_dev(self.h, ptr(P), ptr(Sw), ptr(X), ptr(flag),
+                                       _p(bhp, f64p)), "fim_set_state_dev")
+
+    def fim_set_iterate(self, P, Sw, X=None, flag=None, bhp=None):
+        P, Sw = _f64(P), _f64(Sw)
+        X = _f64(X) if X is not None else None
+        flag = np.ascontiguousarray(flag, np.int8) if flag is not None else None
+        bhp = _f64(bhp) if bhp is not None and len(bhp) else None
+        _check(lib().fim_set_iterate(self.h, _p(P, f64p), _p(Sw, f64p), _p(X, f64p),
+                                     _p(flag, i8p), _p(bhp, f64p)), "fim_set_iterate")
+
+    def set_initial_state(self):
+        r = self.res
+        bhp = None
+        self.fim_set_state(r.p0, r.sw0, r.x0, r.flag0, bhp)
+
+    def fim_get_state(self):
+        n = self.n
+        P, Sw, X = np.zeros(n), np.zeros(n), np.zeros(n)
+        flag = np.zeros(n, np.int8)
+        bhp = np.zeros(max(self.nw, 1))
+        _check(lib().fim_get_state(self.h, _p(P, f64p), _p(Sw, f64p), _p(X, f64p),
+                                   _p(flag, i8p), _p(bhp, f64p)), "fim_get_state")
+        return dict(P=P, Sw=Sw, X=X, flag=flag, pbhp=bhp[: self.nw])
+
+    def fim_step(self, dt):
+        rep = FimStepReport()
+        rc = _check(lib().fim_step(self.h, float(dt), C.byref(rep)), "fim_step")
+        return rc, rep
+
+    def fim_get_well_rates(self):
+        q = np.zeros(max(self.nw, 1) * 3)
+        bhp = np.zeros(max(self.nw, 1))
+        _check(lib().fim_get_well_rates(self.h, _p(q, f64p), _p(bhp, f64p)),
+               "fim_get_well_rates")
+        return q[: self.nw * 3].reshape(self.nw, 3), bhp[: self.nw]
+
+    # -- testing hooks ---------------------------------------------------------------
+    def fim_static(self):
+        n = self.n
+        out = [np.zeros(n) for _ in range(6)]
+        nperf = sum(len(w.cells) for w in self.res.wells)
+        wi = np.zeros(max(nperf, 1))
+        _check(lib().fim_static(self.h, *[_p(a, f64p) for a in out], _p(wi, f64p)),
+               "fim_static")
+        keys = ["vol", "depth", "pvref", "tx", "ty", "tz"]
+        d = dict(zip(keys, out))
+        d["wi"] = wi[:nperf]
+        return d
+
+    def fim_props(self):
+        out = np.zeros(self.nprops * self.n)
+        _check(lib().fim_props(self.h, _p(out, f64p)), "fim_props")
+        return out.reshape(self.nprops, self.n)
+
+    def fim_assemble(self, dt, jacobian=True):
+        R = np.zeros(self.nrows * self.nb)
+        rowptr = np.zeros(self.nrows + 1, np.int32)
+        colind = np.zeros(self.nnzb, np.int32)
+        val = np.zeros(self.nnzb * self.nb * self.nb) if jacobian else None
+        _check(lib().fim_assemble(self.h, float(dt), _p(R, f64p), _p(rowptr, i32p),
+                                  _p(colind, i32p), _p(val, f64p)), "fim_assemble")
+        return R, rowptr, colind, val
+
+    def fim_precond_apply(self, x):
+        x = _f64(x)
+        y = np.zeros_like(x)
+        _check(lib().fim_precond_apply(self.h, _p(x, f64p), _p(y, f64p)), "fim_precond_apply")
+        return y
+
+    def fim_linear_solve(self, b):
+        b = _f64(b)
+        x = np.zeros_like(b)
+        it = C.c_int32(0)
+        rr = C.c_double(0)
+        rc = _check(lib().fim_linear_solve(self.h, _p(b, f64p), _p(x, f64p), C.byref(it),
+                                           C.byref(rr)), "fim_linear_solve")
+        return x, rc, it.value, rr.value
+
+
+def fim_bsr_spmv(nrows, nb, rowptr, colind, val, x, y, stream=None):
+    """y = A x on torch device tensors (canonical BSR, interleaved vectors)."""
+    s = current_stream() if stream is None else stream
+    ptr = lambda t: C.c_void_p(t.data_ptr())
+    _check(lib().fim_bsr_spmv(int(nrows), int(nb), ptr(rowptr), ptr(colind), ptr(val), ptr(x),
+                              ptr(y), s), "fim_bsr_spmv")

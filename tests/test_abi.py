@@ -1,0 +1,106 @@
+"""CPU checks of the C ABI: the library loads, exports every symbol the
+header declares, its structs have the header's layout, and argument
+validation rejects bad input before any device work."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2406_10862_amd import fim, reservoirs as rv
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fim.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fim_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = fim.lib()
+    names = declared_functions()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(L, name), name
+    assert sorted(fim.EXPORTS) == names
+
+
+def test_struct_layout_matches_header(tmp_path):
+    src = tmp_path / "sz.c"
+    src.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "fim.h"\n'
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu\\n\","
+        "sizeof(fim_grid),sizeof(fim_rock),sizeof(fim_fluid),sizeof(fim_well),"
+        "sizeof(fim_options),sizeof(fim_step_report),offsetof(fim_step_report,dt_sub),"
+        "offsetof(fim_options,max_newton));return 0;}\n")
+    exe = tmp_path / "sz"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    want = [C.sizeof(fim.FimGrid), C.sizeof(fim.FimRock), C.sizeof(fim.FimFluid),
+            C.sizeof(fim.FimWell), C.sizeof(fim.FimOptions), C.sizeof(fim.FimStepReport),
+            fim.FimStepReport.dt_sub.offset, fim.FimOptions.max_newton.offset]
+    assert got == want
+
+
+def _create(res, **opt_over):
+    o = rv.Options()
+    for k, v in opt_over.items():
+        setattr(o, k, v)
+    return fim.Fim(res, options=o, stream=C.c_void_p(0))
+
+
+def _expect_arg_error(res, match, **opt_over):
+    with pytest.raises(fim.FimError, match=match) as ei:
+        _create(res, **opt_over)
+    assert "(-1)" in str(ei.value)
+
+
+def test_validation_rejects_bad_input_without_a_device():
+    base = rv.config_c2_small(4, 4, 2)
+    r = base.copy()
+    r.fluid.p = r.fluid.p[::-1].copy()
+    _expect_arg_error(r, "table pressures must increase")
+    r = base.copy()
+    r.wells[1].cells = np.array([0, 0], np.int32)
+    _expect_arg_error(r, "duplicate cell")
+    r = base.copy()
+    r.wells[0].cells = np.array([10 ** 6], np.int32)
+    _expect_arg_error(r, "out of range")
+    r = base.copy()
+    r.wells[1].control = rv.RATE
+    _expect_arg_error(r, "rate-controlled producers")
+    r = base.copy()
+    r.poro[3] = 0.0
+    _expect_arg_error(r, "porosity")
+    _expect_arg_error(base, "restart", restart=0)
+    _expect_arg_error(base, "restart", restart=41)
+    r = base.copy()
+    r.wells.append(rv.Well(rv.INJ_GAS, rv.RATE, 10.0, np.array([5], np.int32)))
+    _expect_arg_error(r, "gas injection needs model 3")
+    bad = rv.blackoil_fluid()
+    bad.bg = bad.bg * 1e-4        # makes the total compressibility negative
+    r = rv.config_c1()
+    r.fluid = bad
+    _expect_arg_error(r, "negative total compressibility")
+
+
+def test_spmv_rejects_bad_block_size_without_a_device():
+    L = fim.lib()
+    assert L.fim_bsr_spmv(4, 4, None, None, None, None, None, None) == fim.FIM_E_ARG
+    assert b"nb must be 2 or 3" in L.fim_last_error()
+    # an empty matrix is a no-op
+    assert L.fim_bsr_spmv(0, 2, None, None, None, None, None, None) == fim.FIM_OK
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    monkeypatch.setattr(fim, "_LIB", None)
+    monkeypatch.setattr(fim, "LIB_PATH", str(tmp_path / "libfim.so"))
+    with pytest.raises(fim.FimError, match="no fallback"):
+        fim.lib()

@@ -1,0 +1,353 @@
+"""GPU parity: every stage of the HIP path against the FP64 oracle, through
+the C ABI, on seeded inputs that span several tiles and ragged tails."""
+import numpy as np
+import pytest
+
+from paper_2406_10862_amd import fim, reservoirs as rv
+from oracle import fimref as fr
+from tests.gpu_cases import (STATE_TOL, oracle_state, pair, run_parity_steps, state_errors)
+from tests.helpers import box, ramp_state, blackoil_mixed_state
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    print(f"\n[gpu case] {request.node.nodeid}", flush=True)
+    yield
+
+
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "these tests need the GPU"
+    return torch
+
+
+# ---------------------------------------------------------------------------
+# static precompute
+
+@pytest.mark.parametrize("cfg", ["c1", "c2s"])
+def test_static_matches_oracle(cfg):
+    res = rv.config_c1() if cfg == "c1" else rv.config_c2_small(13, 17, 5)
+    g, o = pair(res)
+    a, b = g.fim_static(), o.static()
+    for k in ["vol", "depth", "pvref", "tx", "ty", "tz", "wi"]:
+        np.testing.assert_allclose(a[k], b[k], rtol=1e-14, atol=0, err_msg=k)
+
+
+# ---------------------------------------------------------------------------
+# properties
+
+def _props_err(a, b):
+    scale = np.maximum(np.abs(b).max(axis=1, keepdims=True), 1e-300)
+    return (np.abs(a - b) / scale).max()
+
+
+def test_props_match_oracle_two_phase():
+    res = rv.config_c2_small(13, 17, 5)
+    rng = np.random.default_rng(21)
+    P = 300.0 + 10000.0 * rng.uniform(size=res.n)        # spans and leaves the table
+    Sw = rng.uniform(-0.05, 1.05, size=res.n)            # includes both Corey clamps
+    g, o = pair(res)
+    g.fim_set_iterate(P, Sw, np.zeros(res.n), np.zeros(res.n, np.int8), o.pbhp)
+    e = _props_err(g.fim_props(), o.props(P=P, Sw=Sw))
+    assert e <= 1e-13, e
+
+
+def test_props_match_oracle_three_phase_mixed_flags():
+    res = rv.config_c1()
+    rng = np.random.default_rng(22)
+    P, Sw, X, flag = blackoil_mixed_state(res, rng)
+    P = P + rng.uniform(-2500, 4500, size=res.n)       # many table intervals
+    g, o = pair(res)
+    g.fim_set_iterate(P, Sw, X, flag, o.pbhp)
+    e = _props_err(g.fim_props(), o.props(P=P, Sw=Sw, X=X, flag=flag))
+    assert e <= 1e-13, e
+
+
+def test_props_on_exact_table_nodes():
+    res = rv.config_c1()
+    fl = res.fluid
+    P = np.resize(fl.p, res.n).astype(float)            # every row, exactly
+    Sw = np.full(res.n, 0.3)
+    flag = np.resize(np.array([0, 1], np.int8), res.n)
+    X = np.where(flag == 1, 0.1, np.resize(fl.rs, res.n))
+    g, o = pair(res)
+    g.fim_set_iterate(P, Sw, X, flag, o.pbhp)
+    e = _props_err(g.fim_props(), o.props(P=P, Sw=Sw, X=X, flag=flag))
+    assert e <= 1e-13, e
+
+
+# ---------------------------------------------------------------------------
+# residual and Jacobian
+
+def _assemble_pair(res, state, dt=7.0):
+    g, o = pair(res)
+    P, Sw, X, flag, pbhp = state
+    g.fim_set_iterate(P, Sw, X, flag, pbhp)
+    R_g, rp_g, ci_g, val_g = g.fim_assemble(dt)
+    R_o, val_o = o.assemble(dt, Aold=o.accum(), P=P, Sw=Sw, X=X, flag=flag, pbhp=pbhp)
+    rp_o, ci_o = o.pattern()
+    return (R_g, rp_g, ci_g, val_g), (R_o, rp_o, ci_o, val_o), o
+
+
+def _check_assembly(a, b, nb):
+    R_g, rp_g, ci_g, val_g = a
+    R_o, rp_o, ci_o, val_o = b
+    assert np.array_equal(rp_g, rp_o) and np.array_equal(ci_g, ci_o)
+    nrows = len(rp_o) - 1
+    # residual: relative to the largest term that enters the row, bounded
+    # below by the row's own size
+    vb = np.abs(val_o).reshape(-1, nb * nb)
+    row_of_blk = np.repeat(np.arange(nrows), np.diff(rp_o))
+    jscale = np.zeros(nrows)
+    np.maximum.at(jscale, row_of_blk, vb.max(axis=1))
+    rscale = np.maximum(np.abs(R_o).reshape(-1, nb).max(axis=1), 1e-300)
+    eR = (np.abs(R_g - R_o).reshape(-1, nb).max(axis=1) / rscale).max()
+    eJ = (np.abs(val_g - val_o).reshape(-1, nb * nb).max(axis=1) / jscale[row_of_blk]).max()
+    return eR, eJ
+
+
+def test_assembly_matches_oracle_two_phase():
+    res = rv.config_c2_small(13, 17, 5)
+    rng = np.random.default_rng(31)
+    P = ramp_state(res, rng) + rng.normal(0, 40, res.n)
+    Sw = rng.uniform(0.15, 0.85, res.n)
+    pbhp = np.array([5100.0, 4000.0, 4000.0, 4000.0, 4000.0])
+    st = (P, Sw, np.zeros(res.n), np.zeros(res.n, np.int8), pbhp)
+    a, b, _ = _assemble_pair(res, st)
+    eR, eJ = _check_assembly(a, b, 2)
+    assert eR <= 1e-12 and eJ <= 1e-12, (eR, eJ)
+
+
+def test_assembly_matches_oracle_three_phase():
+    res = rv.config_c1()
+    rng = np.random.default_rng(32)
+    P, Sw, X, flag = blackoil_mixed_state(res, rng)
+    st = (P, Sw, X, flag, np.array([6100.0, 1000.0]))
+    a, b, _ = _assemble_pair(res, st)
+    eR, eJ = _check_assembly(a, b, 3)
+    assert eR <= 1e-12 and eJ <= 1e-12, (eR, eJ)
+
+
+def test_assembled_fluxes_cancel_on_the_gpu():
+    # closed box: the sum over cells of the flux part of R vanishes
+    res = rv.config_c2_small(9, 11, 4)
+    res.wells = []
+    rng = np.random.default_rng(33)
+    g = fim.Fim(res)
+    P = ramp_state(res, rng) + rng.normal(0, 30, res.n)
+    Sw = rng.uniform(0.2, 0.8, res.n)
+    g.fim_set_state(P, Sw, None, None, None)
+    R, *_ = g.fim_assemble(1.0, jacobian=False)
+    R = R.reshape(-1, 2)
+    for i in range(2):
+        assert abs(R[:, i].sum()) <= 1e-12 * np.abs(R[:, i]).sum()
+
+
+# ---------------------------------------------------------------------------
+# BSR SpMV
+
+def _random_bsr(nrows, nb, rng, max_len=9, long_rows=()):
+    lens = rng.integers(0, max_len + 1, size=nrows)
+    for r, L in long_rows:
+        lens[r] = L
+    rowptr = np.zeros(nrows + 1, np.int32)
+    rowptr[1:] = np.cumsum(lens)
+    colind = np.concatenate([np.sort(rng.choice(nrows, size=min(L, nrows), replace=False))
+                             for L in lens]).astype(np.int32) if nrows else np.zeros(0, np.int32)
+    rowptr[1:] = np.cumsum([min(L, nrows) for L in lens])
+    val = rng.normal(size=len(colind) * nb * nb)
+    return rowptr, colind, val
+
+
+def _gpu_spmv(rowptr, colind, val, x, nb):
+    torch = torch_dev()
+    d = torch.device("cuda")
+    nrows = len(rowptr) - 1
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(d)
+    y = torch.full((max(nrows * nb, 1),), np.nan, dtype=torch.float64, device=d)
+    xs = t(x) if len(x) else torch.zeros(1, dtype=torch.float64, device=d)
+    fim.fim_bsr_spmv(nrows, nb, t(rowptr), t(colind) if len(colind) else t(np.zeros(1, np.int32)),
+                     t(val) if len(val) else t(np.zeros(1)), xs, y)
+    torch.cuda.synchronize()
+    return y.cpu().numpy()[: nrows * nb]
+
+
+@pytest.mark.parametrize("nb", [2, 3])
+@pytest.mark.parametrize("nrows", [1, 7, 64, 1000, 4099])
+def test_spmv_matches_oracle_random_patterns(nb, nrows):
+    rng = np.random.default_rng(nrows * 10 + nb)
+    long_rows = [(0, min(nrows, 300))] if nrows > 100 else ()
+    rowptr, colind, val = _random_bsr(nrows, nb, rng, long_rows=long_rows)
+    x = rng.normal(size=nrows * nb)
+    y = _gpu_spmv(rowptr, colind, val, x, nb)
+    yo = fr.bsr_spmv(rowptr, colind, val, x, nb)
+    scale = fr.bsr_spmv(rowptr, colind, np.abs(val), np.abs(x), nb)
+    assert np.all(np.abs(y - yo) <= 1e-14 * scale + 1e-300)
+
+
+def test_spmv_on_the_fim_jacobian():
+    res = rv.config_c2_small(13, 17, 5)
+    rng = np.random.default_rng(41)
+    g, o = pair(res)
+    R, rowptr, colind, val = g.fim_assemble(10.0)
+    x = rng.normal(size=len(R))
+    y = _gpu_spmv(rowptr, colind, val, x, 2)
+    yo = fr.bsr_spmv(rowptr, colind, val, x, 2)
+    scale = fr.bsr_spmv(rowptr, colind, np.abs(val), np.abs(x), 2)
+    assert np.all(np.abs(y - yo) <= 1e-14 * scale)
+
+
+# ---------------------------------------------------------------------------
+# preconditioner and linear solve
+
+@pytest.mark.parametrize("cfg", ["c1", "c2s"])
+def test_block_jacobi_apply_matches_oracle(cfg):
+    res = rv.config_c1() if cfg == "c1" else rv.config_c2_small(13, 17, 5)
+    g, o = pair(res)
+    R, rowptr, colind, val = g.fim_assemble(10.0)
+    x = np.random.default_rng(51).normal(size=len(R))
+    y = g.fim_precond_apply(x)
+    yo = fr.bj_apply(fr.bj_setup(rowptr, colind, val, g.nb), x, g.nb)
+    np.testing.assert_allclose(y, yo, rtol=1e-12, atol=1e-12 * np.abs(yo).max())
+
+
+@pytest.mark.parametrize("cfg", ["c1", "c2s"])
+def test_linear_solve_matches_dense_solution(cfg):
+    res = rv.config_c1() if cfg == "c1" else rv.config_c2_small(7, 9, 3)
+    g, o = pair(res)
+    opts = rv.Options(lin_rtol=1e-12, max_lin=2000, restart=40)
+    g.fim_set_options(opts)
+    R, rowptr, colind, val = g.fim_assemble(10.0)
+    A = fr.bsr_to_dense(rowptr, colind, val, g.nb)
+    xd = np.linalg.solve(A, R)
+    x, rc, it, rr = g.fim_linear_solve(R)
+    assert rc == fim.FIM_OK and rr <= 1e-12, (rc, it, rr)
+    assert np.abs(x - xd).max() <= 1e-8 * np.abs(xd).max()
+    assert np.linalg.norm(A @ x - R) <= 1e-11 * np.linalg.norm(R)
+
+
+def test_linear_solve_zero_rhs():
+    g, o = pair(rv.config_c2_small(5, 5, 2))
+    R, *_ = g.fim_assemble(10.0)
+    x, rc, it, rr = g.fim_linear_solve(np.zeros_like(R))
+    assert rc == fim.FIM_OK and it == 0 and np.all(x == 0)
+
+
+# ---------------------------------------------------------------------------
+# full time steps
+
+def test_steps_match_oracle_three_phase_c1():
+    res = rv.config_c1()
+    g, o, errs = run_parity_steps(res, 10)
+    worst = {k: max(e[k] for e in errs) for k in errs[0]}
+    print("c1 parity per quantity:", worst)
+    assert all(v <= STATE_TOL for v in worst.values()), worst
+    assert (o.flag == rv.SAT).any()
+
+
+def test_steps_match_oracle_two_phase_heterogeneous():
+    res = rv.config_c2_small(13, 17, 5, nsteps=3)
+    g, o, errs = run_parity_steps(res, 3)
+    worst = {k: max(e[k] for e in errs) for k in errs[0]}
+    print("c2-like parity per quantity:", worst)
+    assert all(v <= STATE_TOL for v in worst.values()), worst
+
+
+@pytest.mark.parametrize("dims", [(1, 1, 1), (1, 9, 1), (7, 1, 3), (1, 1, 6)])
+def test_steps_match_oracle_degenerate_grids(dims):
+    nx, ny, nz = dims
+    n = nx * ny * nz
+    wells = [rv.Well(rv.INJ_WATER, rv.RATE, 2.0, np.array([0], np.int32)),
+             rv.Well(rv.PROD, rv.BHP, 4000.0, np.array([n - 1], np.int32))] if n > 1 else \
+        [rv.Well(rv.PROD, rv.BHP, 4000.0, np.array([0], np.int32))]
+    rng = np.random.default_rng(n)
+    res = box(nx, ny, nz, dx=30.0, dy=20.0, dz=4.0, k=rng.uniform(20, 400, n), wells=wells,
+              p0=4700.0, sw0=0.25)
+    res.schedule = [5.0, 5.0]
+    g, o, errs = run_parity_steps(res, 2)
+    worst = {k: max(e[k] for e in errs) for k in errs[0]}
+    assert all(v <= STATE_TOL for v in worst.values()), worst
+
+
+def test_closed_box_without_wells_relaxes_under_gravity():
+    res = box(4, 3, 5, dz=8.0, k=300.0, kv=30.0, sw0=np.linspace(0.25, 0.7, 60))
+    res.schedule = [20.0, 20.0]
+    g, o, errs = run_parity_steps(res, 2)
+    worst = {k: max(e[k] for e in errs) for k in errs[0]}
+    assert all(v <= STATE_TOL for v in worst.values()), worst
+
+
+def test_gpu_mass_balance():
+    res = rv.config_c2_small(13, 17, 5, nsteps=2)
+    g = fim.Fim(res)
+    g.set_initial_state()
+    ix = fr.prop_index(2)
+    for dt in res.schedule:
+        A0 = g.fim_props()[[ix["A_w"], ix["A_o"]]].sum(axis=1)
+        rc, rep = g.fim_step(dt)
+        assert rc == fim.FIM_OK and rep.nsub == 1
+        A1 = g.fim_props()[[ix["A_w"], ix["A_o"]]].sum(axis=1)
+        q, _ = g.fim_get_well_rates()
+        err = np.abs(A1 - A0 + dt * q.sum(axis=0)[:2]) / np.abs(A1)
+        assert err.max() <= 1e-12, err
+
+
+def test_gpu_is_deterministic_and_restartable():
+    res = rv.config_c2_small(10, 12, 4, nsteps=4)
+    a = fim.Fim(res)
+    a.set_initial_state()
+    for dt in res.schedule:
+        assert a.fim_step(dt)[0] == fim.FIM_OK
+    b = fim.Fim(res)
+    b.set_initial_state()
+    for dt in res.schedule[:2]:
+        assert b.fim_step(dt)[0] == fim.FIM_OK
+    saved = b.fim_get_state()
+    c = fim.Fim(res)
+    c.fim_set_state(saved["P"], saved["Sw"], saved["X"], saved["flag"], saved["pbhp"])
+    for dt in res.schedule[2:]:
+        assert c.fim_step(dt)[0] == fim.FIM_OK
+    sa, sc = a.fim_get_state(), c.fim_get_state()
+    for k in ["P", "Sw", "X", "flag", "pbhp"]:
+        assert np.array_equal(sa[k], sc[k]), k
+
+
+def test_gpu_cuts_follow_the_oracle_policy():
+    res = rv.config_c2_small(6, 6, 3)
+    opts = rv.Options(max_newton=6)
+    g, o = pair(res, options=opts)
+    rc, rep = g.fim_step(10.0)
+    st, orep = o.step(10.0, o.options(max_newton=6))
+    assert rc == fim.FIM_OK and st == 0
+    assert rep.cuts >= 1 and abs(sum(rep.dt_sub[: rep.nsub]) - 10.0) < 1e-12
+    e = state_errors(g.fim_get_state(), oracle_state(o), res.fluid, 2)
+    assert all(v <= STATE_TOL for v in e.values()), e
+
+
+def test_gpu_failure_restores_the_step_start_state():
+    res = rv.config_c2_small(6, 6, 3)
+    g = fim.Fim(res, options=rv.Options(max_newton=1, max_cuts=2))
+    g.set_initial_state()
+    before = g.fim_get_state()
+    rc, rep = g.fim_step(10.0)
+    assert rc == fim.FIM_NOT_CONVERGED and rep.cuts == 3 and rep.converged == 0
+    after = g.fim_get_state()
+    for k in before:
+        assert np.array_equal(before[k], after[k]), k
+
+
+def test_well_rates_match_oracle():
+    res = rv.config_c1()
+    g, o = pair(res)
+    for _ in range(2):
+        st, rep = o.step(30.0)
+        for h in rep.dt_sub[: rep.nsub]:
+            assert g.fim_step(h)[0] == fim.FIM_OK
+    q, bhp = g.fim_get_well_rates()
+    qo = o.well_rates()
+    np.testing.assert_allclose(q, qo, rtol=1e-8, atol=1e-8 * np.abs(qo).max())
+    np.testing.assert_allclose(bhp, o.pbhp, rtol=1e-9)
+    # the rate-controlled gas injector meets its target
+    assert q[0, 2] == pytest.approx(-res.wells[0].target, rel=1e-9)
