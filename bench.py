@@ -30,10 +30,10 @@ def log(msg):
 def tolerances(mode):
     from paper_2406_10862_amd import reservoirs as rv
     if mode == "parity":
-        return rv.Options(max_lin=400, restart=30)
+        return rv.Options(max_lin=400, restart=40, max_newton=30)
     # the paper's scalability setting: nonlinear and linear residuals 1e-3
     return rv.Options(tol_cnv=1e-3, tol_mb=1e-7, tol_dp=1e30, tol_ds=1e30, tol_well=1e-2,
-                      lin_rtol=1e-3, max_lin=400, restart=30)
+                      lin_rtol=1e-3, max_lin=400, restart=40, max_newton=30, forcing=0)
 
 
 def spmv_bytes(nnzb, nrows, nb):
@@ -74,6 +74,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--tol", choices=["parity", "paper"], default="parity")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cycle", type=int, default=2, choices=[1, 2], help="AMG cycle: 1 V, 2 W")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "spmv_c2_traffic.json"))
     args = ap.parse_args()
     if args.gpus != 1:
@@ -90,6 +91,7 @@ def main():
     t0 = time.perf_counter()
     res = rv.config_c2()
     opts = tolerances(args.tol)
+    opts.amg_cycle = args.cycle
     g = fim.Fim(res, options=opts, profile=True)
     g.set_initial_state()
     torch.cuda.synchronize()
@@ -101,7 +103,8 @@ def main():
         rc, rep = g.fim_step(sched[k % len(sched)])
         k += 1
         log(f"warmup step: rc={rc} newton={rep.newton_iters} linear={rep.linear_iters} "
-            f"cuts={rep.cuts}")
+            f"cuts={rep.cuts} cnv={max(rep.cnv):.2e} mb={max(rep.mb):.2e} "
+            f"dp={rep.last_dp:.2e} ds={rep.last_ds:.2e} well={rep.well_res:.2e}")
     torch.cuda.synchronize()
     newton = linear = cuts = calls = 0
     spmv_ms = 0.0
@@ -119,7 +122,8 @@ def main():
         phases[1] += rep.t_linear
         phases[2] += rep.t_update
         log(f"step {s}: rc={rc} newton={rep.newton_iters} linear={rep.linear_iters} "
-            f"cuts={rep.cuts} cnv={max(rep.cnv):.2e}")
+            f"cuts={rep.cuts} cnv={max(rep.cnv):.2e} mb={max(rep.mb):.2e} "
+            f"dp={rep.last_dp:.2e} ds={rep.last_ds:.2e} well={rep.well_res:.2e}")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
 
@@ -149,7 +153,9 @@ def main():
             "workload": "two-phase dead-oil FIM five-spot 60x220x85 = 1,122,000 cells, "
                         "seeded log-normal perm (sigma 2), 2x2 BSR, dt 10 days",
             "cells": g.n, "block_rows": g.nrows, "nnzb": g.nnzb, "nb": g.nb,
-            "tolerances": args.tol, "precond": "block-Jacobi", "gmres_restart": opts.restart,
+            "tolerances": args.tol,
+            "precond": {0: "block-Jacobi", 2: "CPR (quasi-IMPES + aggregation AMG) + block-Jacobi"}[opts.precond],
+            "amg_cycle": {1: "V", 2: "W"}.get(opts.amg_cycle), "gmres_restart": opts.restart,
             "newton_iters": newton, "linear_iters": linear, "cuts": cuts,
             "linear_per_newton": linear / newton if newton else None,
             "phase_ms": {"assemble": phases[0], "linear": phases[1], "update": phases[2]},

@@ -65,7 +65,7 @@ enum { FIM_DEADOIL_OW = 2, FIM_BLACKOIL_3P = 3 };          /* model id == block 
 enum { FIM_PROD = 0, FIM_INJ_WATER = 1, FIM_INJ_GAS = 2 };  /* well kind */
 enum { FIM_BHP = 0, FIM_RATE = 1 };                         /* well control */
 enum { FIM_UNSAT = 0, FIM_SAT = 1 };                        /* phase-state flag */
-enum { FIM_PREC_BJ = 0 };                                   /* preconditioner */
+enum { FIM_PREC_BJ = 0, FIM_PREC_CPR = 2 };                /* preconditioner */
 enum { FIM_FP64 = 0 };                                      /* precision mode */
 
 /* Cartesian grid: dx[nx], dy[ny], dz[nz] in ft, top = depth of the top face. */
@@ -130,13 +130,21 @@ typedef struct {
  * at most max_cuts times per step.  GMRES(restart) runs to relative
  * residual lin_rtol or max_lin iterations per Newton iteration (restart
  * in [1, 40]); an unconverged solve is still used when it reduced the
- * residual.  profile != 0 brackets every SpMV launch of fim_step with HIP
- * events and reports their summed duration in fim_step_report. */
+ * residual.  The solver is flexible GMRES, right-preconditioned by block
+ * Jacobi (FIM_PREC_BJ) or by CPR (FIM_PREC_CPR): a quasi-IMPES pressure
+ * stage solved by one aggregation-AMG cycle (amg_cycle 1 = V, 2 = W, 0 =
+ * default W; amg_sweeps red-black Gauss-Seidel sweeps before and after the
+ * coarse correction, 0 = default 1) followed by block Jacobi on the
+ * remaining residual.  forcing != 0 replaces the fixed lin_rtol by the
+ * Eisenstat-Walker forcing term (choice 2, gamma 0.9, alpha 2) between 1e-2
+ * and lin_rtol.  graphs != 0 replays each Arnoldi step after its SpMV as a
+ * captured HIP graph.  profile != 0 brackets every SpMV launch of fim_step
+ * with HIP events and reports their summed duration in fim_step_report. */
 typedef struct {
     double tol_cnv, tol_mb, tol_dp, tol_ds, tol_well;
     double ds_max, dp_max, lin_rtol;
     int32_t max_newton, max_lin, restart, max_cuts;
-    int32_t precond, precision, profile, reserved;
+    int32_t precond, precision, profile, amg_cycle, amg_sweeps, graphs, forcing, reserved;
 } fim_options;
 
 #define FIM_MAX_SUB 256
@@ -145,14 +153,16 @@ typedef struct {
     double dt_done, cnv[3], mb[3];
     double t_assemble, t_linear, t_update;   /* device ms per phase */
     double spmv_ms;                          /* summed SpMV kernel ms (HIP events) */
+    double last_dp, last_ds, well_res;       /* last Newton check: update sizes, well measure */
     double dt_sub[FIM_MAX_SUB];              /* accepted sub-step sizes (days) */
 } fim_step_report;
 
 typedef struct fim_ctx fim_ctx;
 
 /* Setup (the paper's Setup + static part of InitReservoir).  hip_stream
- * is a hipStream_t (NULL = the default stream); all work of the context is
- * queued on it.  Validates sizes, table monotonicity, the positive total
+ * is a hipStream_t (NULL = the default stream) that the context orders its
+ * work after; the context runs on a stream of its own on the current
+ * device.  Validates sizes, table monotonicity, the positive total
  * compressibility of saturated rows (Bg*dRs/dP > dBo/dP), perforation
  * ranges and controls; returns FIM_E_ARG with a message on bad input. */
 int fim_create(const fim_grid *grid, const fim_rock *rock, const fim_fluid *fluid,
@@ -211,8 +221,8 @@ int fim_props(fim_ctx *ctx, double *out);
 int fim_assemble(fim_ctx *ctx, double dt, double *R, int32_t *rowptr, int32_t *colind,
                  double *val);
 
-/* y = M^-1 x with the block-Jacobi preconditioner of the last assembled
- * Jacobian; x, y: [(ncells+nwells)*nb]. */
+/* y = M^-1 x with the configured preconditioner (block Jacobi or CPR) of
+ * the last assembled Jacobian; x, y: [(ncells+nwells)*nb]. */
 int fim_precond_apply(fim_ctx *ctx, const double *x, double *y);
 
 /* Solve J x = b with the last assembled Jacobian by the configured

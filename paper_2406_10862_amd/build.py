@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfim.so")
-SOURCES = ["fim_phys.hip", "fim_linalg.hip", "fim_api.cpp"]
+SOURCES = ["fim_phys.hip", "fim_linalg.hip", "fim_amg.hip", "fim_api.cpp"]
 ARCH = os.environ.get("FIM_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
@@ -41,7 +41,8 @@ def build(verbose=False) -> str:
     with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
         objs = list(ex.map(lambda s: _compile(s, obj_dir, verbose), SOURCES))
     tmp = LIB + ".tmp"
-    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-Wl,--no-undefined", "-o", tmp,
+           *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -1,0 +1,589 @@
+// fim_amg.hip - CPR two-stage preconditioner with an aggregation AMG on the
+// pressure block (paper Sec. 5.1: CPR with AMG on pressure and block-Jacobi
+// smoothing, inside FGMRES).
+//
+// Stage 1: quasi-IMPES decoupling.  For each cell the weights w_c solve
+// D_c^T w_c = e_P (D_c the diagonal block), normalised by max|w_c|; the
+// pressure matrix is A_p[c][d] = w_c^T A_cd e_P (well rows keep their BHP
+// equation).  A_p is solved approximately by one V- or W-cycle.
+// Stage 2: block Jacobi on the residual of the full system.
+//
+// The hierarchy exploits the Cartesian grid: aggregates are 2x2x2 boxes, so
+// with piecewise-constant interpolation every Galerkin coarse operator is
+// again a 7-point stencil (plus the well rows and columns, each well staying
+// its own aggregate).  The smoother is red-black Gauss-Seidel.  Level data
+// is stored colour-split (all red cells, then all black cells, the x
+// dimension padded to even) so a colour sweep reads its coefficients
+// contiguously; padded cells have a unit diagonal and no couplings.  The
+// coarsest level is inverted densely once per setup.
+#include <math.h>
+
+#include "fim_internal.h"
+#include "fim_reduce.h"
+
+namespace fim {
+
+// stencil slots: 0 diagonal, 1 -x, 2 +x, 3 -y, 4 +y, 5 -z, 6 +z
+__device__ inline int split_of(const AmgLevel &L, int i, int j, int k) {
+    const int c = i + L.nxp * (j + L.ny * k);
+    return (((i + j + k) & 1) ? L.half : 0) + (c >> 1);
+}
+
+__device__ inline void cell_of(const AmgLevel &L, int s, int &i, int &j, int &k) {
+    const int color = s >= L.half;
+    const int c0 = 2 * (s - color * L.half);
+    const int row = c0 / L.nxp;
+    j = row % L.ny;
+    k = row / L.ny;
+    const int i0 = c0 - row * L.nxp;
+    i = i0 + (((j + k) & 1) ^ color);
+}
+
+__device__ inline bool neighbour(const AmgLevel &L, int d, int i, int j, int k, int &ni, int &nj,
+                                 int &nk) {
+    ni = i;
+    nj = j;
+    nk = k;
+    switch (d) {
+        case 1: ni = i - 1; break;
+        case 2: ni = i + 1; break;
+        case 3: nj = j - 1; break;
+        case 4: nj = j + 1; break;
+        case 5: nk = k - 1; break;
+        default: nk = k + 1; break;
+    }
+    return ni >= 0 && ni < L.nx && nj >= 0 && nj < L.ny && nk >= 0 && nk < L.nz;
+}
+
+// ---------------------------------------------------------------------------
+// setup: pressure matrix from the Jacobian
+
+template <int NB>
+__device__ inline void qi_weights(const double *__restrict__ d, double (&w)[NB]) {
+    // first row of D^-1 (adjugate row over the determinant), then scaled
+    if constexpr (NB == 2) {
+        const double det = d[0] * d[3] - d[1] * d[2];
+        w[0] = d[3] / det;
+        w[1] = -d[1] / det;
+    } else {
+        const double c0 = d[4] * d[8] - d[5] * d[7];
+        const double c1 = -(d[1] * d[8] - d[2] * d[7]);
+        const double c2 = d[1] * d[5] - d[2] * d[4];
+        const double det = d[0] * c0 + d[3] * c1 + d[6] * c2;
+        w[0] = c0 / det;
+        w[1] = c1 / det;
+        w[2] = c2 / det;
+    }
+    double m = 0.0;
+#pragma unroll
+    for (int e = 0; e < NB; ++e) m = fmax(m, fabs(w[e]));
+    if (!(m > 0.0) || !isfinite(m)) {
+#pragma unroll
+        for (int e = 0; e < NB; ++e) w[e] = (e == 0) ? 1.0 : 0.0;
+        return;
+    }
+#pragma unroll
+    for (int e = 0; e < NB; ++e) w[e] /= m;
+}
+
+template <int NB>
+__device__ inline double pcoef(const double *__restrict__ val, int q, const double (&w)[NB]) {
+    double s = 0.0;
+#pragma unroll
+    for (int e = 0; e < NB; ++e) s += w[e] * val[(size_t)q * NB * NB + e * NB];
+    return s;
+}
+
+template <int NB>
+__global__ __launch_bounds__(kBlock) void k_amg_extract(AmgLevel L, Grid g, Wells wl, Sys sys,
+                                                        double *__restrict__ wq) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = g.n;
+    const int stride = 2 * L.half;
+    if (t < n) {
+        const int c = t, nx = g.nx, ny = g.ny, nxy = nx * ny;
+        const int i = c % nx, j = (c / nx) % ny, k = c / nxy;
+        double w[NB];
+        qi_weights<NB>(sys.val + (size_t)sys.diagpos[c] * NB * NB, w);
+#pragma unroll
+        for (int e = 0; e < NB; ++e) wq[(size_t)c * NB + e] = w[e];
+        const int s = split_of(L, i, j, k);
+        int q = sys.rowptr[c];
+        double a[7];
+        a[5] = (k > 0) ? pcoef<NB>(sys.val, q++, w) : 0.0;
+        a[3] = (j > 0) ? pcoef<NB>(sys.val, q++, w) : 0.0;
+        a[1] = (i > 0) ? pcoef<NB>(sys.val, q++, w) : 0.0;
+        a[0] = pcoef<NB>(sys.val, q++, w);
+        a[2] = (i + 1 < nx) ? pcoef<NB>(sys.val, q++, w) : 0.0;
+        a[4] = (j + 1 < ny) ? pcoef<NB>(sys.val, q++, w) : 0.0;
+        a[6] = (k + 1 < g.nz) ? pcoef<NB>(sys.val, q++, w) : 0.0;
+#pragma unroll
+        for (int d = 0; d < 7; ++d) L.a[(size_t)d * stride + s] = a[d];
+        for (int pp = wl.cps[c]; pp < wl.cps[c + 1]; ++pp) L.acw[wl.cperf[pp]] = pcoef<NB>(sys.val, q++, w);
+    } else if (t < n + L.nw) {
+        const int wi = t - n;
+        const int base = sys.rowptr[n + wi];
+        const int p0 = L.sps[wi], np = L.sps[wi + 1] - p0;
+        for (int p = 0; p < np; ++p) L.awc[p0 + p] = sys.val[(size_t)(base + p) * NB * NB];
+        L.aww[wi] = sys.val[(size_t)(base + np) * NB * NB];
+    }
+}
+
+// Galerkin coarsening with piecewise-constant aggregates: couplings inside an
+// aggregate move to the coarse diagonal, couplings across an aggregate face
+// add up on the coarse stencil slot of that face.
+__global__ __launch_bounds__(kBlock) void k_amg_coarsen(AmgLevel F, AmgLevel C,
+                                                        const int *__restrict__ cfs_ptr,
+                                                        const int *__restrict__ cfs_idx) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int ncs = 2 * C.half;
+    const int fstride = 2 * F.half;
+    if (t < ncs) {
+        int I, J, K;
+        cell_of(C, t, I, J, K);
+        if (I >= C.nx) return;                     // padded coarse cell: fixed at creation
+        double a[7] = {0, 0, 0, 0, 0, 0, 0};
+        for (int dk = 0; dk < 2; ++dk)
+            for (int dj = 0; dj < 2; ++dj)
+                for (int di = 0; di < 2; ++di) {
+                    const int i = 2 * I + di, j = 2 * J + dj, k = 2 * K + dk;
+                    if (i >= F.nx || j >= F.ny || k >= F.nz) continue;
+                    const int s = split_of(F, i, j, k);
+                    a[0] += F.a[s];
+#pragma unroll
+                    for (int d = 1; d < 7; ++d) {
+                        int ni, nj, nk;
+                        if (!neighbour(F, d, i, j, k, ni, nj, nk)) continue;
+                        const double v = F.a[(size_t)d * fstride + s];
+                        if ((ni >> 1) == I && (nj >> 1) == J && (nk >> 1) == K) a[0] += v;
+                        else a[d] += v;
+                    }
+                }
+#pragma unroll
+        for (int d = 0; d < 7; ++d) C.a[(size_t)d * ncs + t] = a[d];
+    } else {
+        const int cs = t - ncs;                     // coarse well slot
+        if (cs < C.nslot) {
+            double acw = 0.0, awc = 0.0;
+            for (int q = cfs_ptr[cs]; q < cfs_ptr[cs + 1]; ++q) {
+                acw += F.acw[cfs_idx[q]];
+                awc += F.awc[cfs_idx[q]];
+            }
+            C.acw[cs] = acw;
+            C.awc[cs] = awc;
+        } else if (cs < C.nslot + C.nw) {
+            C.aww[cs - C.nslot] = F.aww[cs - C.nslot];
+        }
+    }
+}
+
+// dense matrix of the coarsest level: rows/cols are split indices, then wells
+__global__ void k_amg_dense(AmgLevel L, double *__restrict__ M) {
+    const int n = 2 * L.half + L.nw;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    double *row = M + (size_t)t * n;
+    for (int c = 0; c < n; ++c) row[c] = 0.0;
+    if (t < 2 * L.half) {
+        int i, j, k;
+        cell_of(L, t, i, j, k);
+        if (i >= L.nx) {
+            row[t] = 1.0;
+            return;
+        }
+        row[t] = L.a[t];
+        for (int d = 1; d < 7; ++d) {
+            int ni, nj, nk;
+            if (neighbour(L, d, i, j, k, ni, nj, nk))
+                row[split_of(L, ni, nj, nk)] += L.a[(size_t)d * 2 * L.half + t];
+        }
+        for (int q = L.cps[t]; q < L.cps[t + 1]; ++q) {
+            const int sl = L.cslot[q];
+            row[2 * L.half + L.swell[sl]] += L.acw[sl];
+        }
+    } else {
+        const int w = t - 2 * L.half;
+        row[t] = L.aww[w];
+        for (int q = L.sps[w]; q < L.sps[w + 1]; ++q) row[L.scell[q]] += L.awc[q];
+    }
+}
+
+// Gauss-Jordan inverse with partial pivoting by one workgroup; A is
+// overwritten, Ainv receives the inverse, *bad is set on a zero pivot.
+__global__ __launch_bounds__(1024) void k_dense_invert(int n, double *__restrict__ A,
+                                                       double *__restrict__ Ainv,
+                                                       double *__restrict__ colk, int *bad) {
+    __shared__ double bv[1024];
+    __shared__ int bi[1024];
+    __shared__ int piv;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int e = tid; e < n * n; e += nt) Ainv[e] = ((e / n) == (e % n)) ? 1.0 : 0.0;
+    __syncthreads();
+    for (int k = 0; k < n; ++k) {
+        double best = -1.0;
+        int bidx = k;
+        for (int r = k + tid; r < n; r += nt) {
+            const double v = fabs(A[(size_t)r * n + k]);
+            if (v > best) {
+                best = v;
+                bidx = r;
+            }
+        }
+        bv[tid] = best;
+        bi[tid] = bidx;
+        __syncthreads();
+        for (int off = nt / 2; off > 0; off >>= 1) {
+            if (tid < off) {
+                const double o = bv[tid + off];
+                const int oi = bi[tid + off];
+                if (o > bv[tid] || (o == bv[tid] && oi < bi[tid])) {
+                    bv[tid] = o;
+                    bi[tid] = oi;
+                }
+            }
+            __syncthreads();
+        }
+        if (tid == 0) {
+            piv = bi[0];
+            if (!(bv[0] > 0.0)) *bad = 1;
+        }
+        __syncthreads();
+        const int p = piv;
+        if (p != k)
+            for (int c = tid; c < n; c += nt) {
+                double t1 = A[(size_t)k * n + c];
+                A[(size_t)k * n + c] = A[(size_t)p * n + c];
+                A[(size_t)p * n + c] = t1;
+                t1 = Ainv[(size_t)k * n + c];
+                Ainv[(size_t)k * n + c] = Ainv[(size_t)p * n + c];
+                Ainv[(size_t)p * n + c] = t1;
+            }
+        __syncthreads();
+        const double dk = A[(size_t)k * n + k];
+        const double rdk = (dk != 0.0) ? 1.0 / dk : 0.0;
+        for (int c = tid; c < n; c += nt) {
+            A[(size_t)k * n + c] *= rdk;
+            Ainv[(size_t)k * n + c] *= rdk;
+        }
+        for (int r = tid; r < n; r += nt) colk[r] = A[(size_t)r * n + k];
+        __syncthreads();
+        for (int e = tid; e < n * n; e += nt) {
+            const int r = e / n, c = e % n;
+            if (r == k) continue;
+            const double f = colk[r];
+            if (f == 0.0) continue;
+            A[e] -= f * A[(size_t)k * n + c];
+            Ainv[e] -= f * Ainv[(size_t)k * n + c];
+        }
+        __syncthreads();
+    }
+}
+
+// x = Minv b, one wave per row
+__global__ __launch_bounds__(256) void k_dense_gemv(int n, const double *__restrict__ M,
+                                                    const double *__restrict__ b,
+                                                    double *__restrict__ x) {
+    const int row = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (row >= n) return;
+    double s = 0.0;
+    for (int c = lane; c < n; c += 64) s += M[(size_t)row * n + c] * b[c];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) x[row] = s;
+}
+
+// ---------------------------------------------------------------------------
+// cycle kernels
+
+__device__ inline double read_cell(const AmgLevel &L, const AmgLevel &C, int mode, int ni, int nj,
+                                   int nk) {
+    if (mode & kCellsZero) return 0.0;
+    double v = L.x[split_of(L, ni, nj, nk)];
+    if (mode & kCellsCorr) v += C.x[split_of(C, ni >> 1, nj >> 1, nk >> 1)];
+    return v;
+}
+
+__device__ inline double read_well(const AmgLevel &L, const AmgLevel &C, int mode, int w) {
+    if (mode & kWellsZero) return 0.0;
+    double v = L.x[2 * L.half + w];
+    if (mode & kWellsCorr) v += C.x[2 * C.half + w];
+    return v;
+}
+
+// Gauss-Seidel update of every cell of one colour (cells of one colour are
+// not coupled to each other, so the sweep is exact and order-free).
+__global__ __launch_bounds__(kBlock) void k_amg_sweep(AmgLevel L, AmgLevel C, int color,
+                                                      int mode) {
+    const int h = blockIdx.x * blockDim.x + threadIdx.x;
+    if (h >= L.half) return;
+    const int s = color * L.half + h;
+    int i, j, k;
+    cell_of(L, s, i, j, k);
+    if (i >= L.nx) {
+        L.x[s] = 0.0;
+        return;
+    }
+    const int stride = 2 * L.half;
+    double acc = L.b[s];
+#pragma unroll
+    for (int d = 1; d < 7; ++d) {
+        int ni, nj, nk;
+        if (neighbour(L, d, i, j, k, ni, nj, nk))
+            acc -= L.a[(size_t)d * stride + s] * read_cell(L, C, mode, ni, nj, nk);
+    }
+    for (int q = L.cps[s]; q < L.cps[s + 1]; ++q) {
+        const int sl = L.cslot[q];
+        acc -= L.acw[sl] * read_well(L, C, mode, L.swell[sl]);
+    }
+    L.x[s] = acc / L.a[s];
+}
+
+// wells: one wave per well, lanes stride over its slots
+__device__ inline double well_row_sum(const AmgLevel &L, int w, int lane) {
+    double acc = 0.0;
+    for (int q = L.sps[w] + lane; q < L.sps[w + 1]; q += 64) acc += L.awc[q] * L.x[L.scell[q]];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    return acc;
+}
+
+__global__ __launch_bounds__(kBlock) void k_amg_well_sweep(AmgLevel L) {
+    const int w = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, lane = threadIdx.x & 63;
+    if (w >= L.nw) return;
+    const double sum = well_row_sum(L, w, lane);
+    if (lane == 0) L.x[2 * L.half + w] = (L.b[2 * L.half + w] - sum) / L.aww[w];
+}
+
+__device__ inline double cell_residual(const AmgLevel &L, int s, int i, int j, int k) {
+    const int stride = 2 * L.half;
+    double r = L.b[s] - L.a[s] * L.x[s];
+#pragma unroll
+    for (int d = 1; d < 7; ++d) {
+        int ni, nj, nk;
+        if (neighbour(L, d, i, j, k, ni, nj, nk))
+            r -= L.a[(size_t)d * stride + s] * L.x[split_of(L, ni, nj, nk)];
+    }
+    for (int q = L.cps[s]; q < L.cps[s + 1]; ++q) {
+        const int sl = L.cslot[q];
+        r -= L.acw[sl] * L.x[2 * L.half + L.swell[sl]];
+    }
+    return r;
+}
+
+// fine residual r = b - A x of every cell (one thread per cell, coalesced
+// over the colour-split index) and of every well (one wave per well)
+__global__ __launch_bounds__(kBlock) void k_amg_residual(AmgLevel F) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int ncs = 2 * F.half;
+    const int cell_blocks = (ncs + kBlock - 1) / kBlock;
+    if ((int)blockIdx.x < cell_blocks) {
+        if (t >= ncs) return;
+        int i, j, k;
+        cell_of(F, t, i, j, k);
+        F.r[t] = (i >= F.nx) ? 0.0 : cell_residual(F, t, i, j, k);
+    } else {
+        const int w = (((int)blockIdx.x - cell_blocks) * kBlock + threadIdx.x) >> 6;
+        const int lane = threadIdx.x & 63;
+        if (w >= F.nw) return;
+        const double sum = well_row_sum(F, w, lane);
+        if (lane == 0)
+            F.r[ncs + w] = F.b[ncs + w] - F.aww[w] * F.x[ncs + w] - sum;
+    }
+}
+
+// coarse right-hand side = aggregate sums of the fine residual (R = P^T)
+__global__ __launch_bounds__(kBlock) void k_amg_aggregate(AmgLevel F, AmgLevel C) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int ncs = 2 * C.half;
+    if (t < ncs) {
+        int I, J, K;
+        cell_of(C, t, I, J, K);
+        if (I >= C.nx) return;
+        double sum = 0.0;
+        for (int dk = 0; dk < 2; ++dk)
+            for (int dj = 0; dj < 2; ++dj)
+                for (int di = 0; di < 2; ++di) {
+                    const int i = 2 * I + di, j = 2 * J + dj, k = 2 * K + dk;
+                    if (i >= F.nx || j >= F.ny || k >= F.nz) continue;
+                    sum += F.r[split_of(F, i, j, k)];
+                }
+        C.b[t] = sum;
+    } else if (t < ncs + C.nw) {
+        C.b[t] = F.r[2 * F.half + (t - ncs)];
+    }
+}
+
+// x_fine += P x_coarse
+__global__ __launch_bounds__(kBlock) void k_amg_correct(AmgLevel F, AmgLevel C) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < 2 * F.half) {
+        int i, j, k;
+        cell_of(F, t, i, j, k);
+        if (i >= F.nx) return;
+        F.x[t] += C.x[split_of(C, i >> 1, j >> 1, k >> 1)];
+    } else if (t < 2 * F.half + F.nw) {
+        const int w = t - 2 * F.half;
+        F.x[t] += C.x[2 * C.half + w];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// CPR stage kernels
+
+// v = w / h (the new Arnoldi vector) and the pressure right-hand side
+// b_p = W^T v of the first level.
+template <int NB>
+__global__ __launch_bounds__(kBlock) void k_cpr_restrict(int n, int nw, AmgLevel L,
+                                                         const int *__restrict__ split0,
+                                                         const double *__restrict__ w,
+                                                         const double *__restrict__ hptr,
+                                                         double *__restrict__ v,
+                                                         const double *__restrict__ wq) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n + nw) return;
+    bool zero = false;
+    double h = 1.0;
+    if (hptr) {
+        h = *hptr;
+        zero = !(h > 0.0 && isfinite(h));
+    }
+    double a[NB];
+#pragma unroll
+    for (int e = 0; e < NB; ++e) {
+        const double we = w[(size_t)r * NB + e];
+        a[e] = zero ? 0.0 : (hptr ? we / h : we);
+        if (hptr) v[(size_t)r * NB + e] = a[e];
+    }
+    if (r < n) {
+        double s = 0.0;
+#pragma unroll
+        for (int e = 0; e < NB; ++e) s += wq[(size_t)r * NB + e] * a[e];
+        L.b[split0[r]] = s;
+    } else {
+        L.b[2 * L.half + (r - n)] = a[0];
+    }
+}
+
+// z = x1 + D^-1 (v - A x1), x1 = the pressure correction in the pressure
+// slot of every row.  A x1 needs only the pressure column of each block; a
+// group of G lanes walks one block row as in the SpMV.
+template <int NB, int G>
+__global__ __launch_bounds__(kBlock) void k_cpr_finish(int n, int nw, AmgLevel L,
+                                                       const int *__restrict__ split0, Sys sys,
+                                                       const double *__restrict__ v,
+                                                       const double *__restrict__ dinv,
+                                                       double *__restrict__ z) {
+    const int lg = threadIdx.x & (G - 1);
+    const int r = (int)(((long)blockIdx.x * blockDim.x + threadIdx.x) / G);
+    const int nrows = n + nw;
+    auto xp = [&](int col) -> double {
+        return col < n ? L.x[split0[col]] : L.x[2 * L.half + (col - n)];
+    };
+    double t[NB];
+#pragma unroll
+    for (int e = 0; e < NB; ++e) t[e] = 0.0;
+    if (r < nrows) {
+        const int b = sys.rowptr[r], e = sys.rowptr[r + 1];
+        for (int q = b + lg; q < e; q += G) {
+            const double p = xp(__builtin_nontemporal_load(sys.colind + q));
+            const double *blk = sys.val + (size_t)q * NB * NB;
+#pragma unroll
+            for (int u = 0; u < NB; ++u) t[u] += __builtin_nontemporal_load(blk + u * NB) * p;
+        }
+    }
+#pragma unroll
+    for (int off = G / 2; off >= 1; off >>= 1)
+#pragma unroll
+        for (int u = 0; u < NB; ++u) t[u] += __shfl_xor(t[u], off, 64);
+    if (r >= nrows || lg != 0) return;
+    double res[NB];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) res[u] = v[(size_t)r * NB + u] - t[u];
+    const double *m = dinv + (size_t)r * NB * NB;
+    const double pr = xp(r);
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+        double s = (u == 0) ? pr : 0.0;
+#pragma unroll
+        for (int e2 = 0; e2 < NB; ++e2) s += m[u * NB + e2] * res[e2];
+        z[(size_t)r * NB + u] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+
+static inline dim3 grid_for(long n, int bs) { return dim3((unsigned)((n + bs - 1) / bs)); }
+
+void launch_amg_extract(hipStream_t s, int nb, const AmgLevel &L, Grid g, Wells w, Sys sys,
+                        double *wq) {
+    const long n = (long)g.n + L.nw;
+    if (nb == 2) hipLaunchKernelGGL(k_amg_extract<2>, grid_for(n, kBlock), dim3(kBlock), 0, s, L, g, w, sys, wq);
+    else hipLaunchKernelGGL(k_amg_extract<3>, grid_for(n, kBlock), dim3(kBlock), 0, s, L, g, w, sys, wq);
+}
+
+void launch_amg_coarsen(hipStream_t s, const AmgLevel &F, const AmgLevel &C, const int *cfs_ptr,
+                        const int *cfs_idx) {
+    const long n = 2L * C.half + C.nslot + C.nw;
+    hipLaunchKernelGGL(k_amg_coarsen, grid_for(n, kBlock), dim3(kBlock), 0, s, F, C, cfs_ptr, cfs_idx);
+}
+
+void launch_amg_coarsest_setup(hipStream_t s, const AmgLevel &L, double *M, double *Minv,
+                               double *colk, int *bad) {
+    const int n = 2 * L.half + L.nw;
+    hipLaunchKernelGGL(k_amg_dense, grid_for(n, 64), dim3(64), 0, s, L, M);
+    hipLaunchKernelGGL(k_dense_invert, dim3(1), dim3(1024), 0, s, n, M, Minv, colk, bad);
+}
+
+void launch_amg_coarsest_solve(hipStream_t s, const AmgLevel &L, const double *Minv) {
+    const int n = 2 * L.half + L.nw;
+    hipLaunchKernelGGL(k_dense_gemv, grid_for((long)n * 64, 256), dim3(256), 0, s, n, Minv, L.b, L.x);
+}
+
+void launch_amg_sweep(hipStream_t s, const AmgLevel &L, const AmgLevel &C, int color, int mode) {
+    hipLaunchKernelGGL(k_amg_sweep, grid_for(L.half, kBlock), dim3(kBlock), 0, s, L, C, color, mode);
+}
+
+void launch_amg_well_sweep(hipStream_t s, const AmgLevel &L) {
+    if (L.nw) hipLaunchKernelGGL(k_amg_well_sweep, grid_for(64L * L.nw, kBlock), dim3(kBlock), 0, s, L);
+}
+
+void launch_amg_restrict(hipStream_t s, const AmgLevel &F, const AmgLevel &C) {
+    const long cell_blocks = (2L * F.half + kBlock - 1) / kBlock;
+    const long well_blocks = (64L * F.nw + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_amg_residual, dim3((unsigned)(cell_blocks + well_blocks)), dim3(kBlock), 0,
+                       s, F);
+    hipLaunchKernelGGL(k_amg_aggregate, grid_for(2L * C.half + C.nw, kBlock), dim3(kBlock), 0, s, F, C);
+}
+
+void launch_amg_correct(hipStream_t s, const AmgLevel &F, const AmgLevel &C) {
+    hipLaunchKernelGGL(k_amg_correct, grid_for(2L * F.half + F.nw, kBlock), dim3(kBlock), 0, s, F, C);
+}
+
+void launch_cpr_restrict(hipStream_t s, int nb, int n, int nw, const AmgLevel &L,
+                         const int *split0, const double *w, const double *hptr, double *v,
+                         const double *wq) {
+    const long rows = (long)n + nw;
+    if (nb == 2)
+        hipLaunchKernelGGL(k_cpr_restrict<2>, grid_for(rows, kBlock), dim3(kBlock), 0, s, n, nw, L,
+                           split0, w, hptr, v, wq);
+    else
+        hipLaunchKernelGGL(k_cpr_restrict<3>, grid_for(rows, kBlock), dim3(kBlock), 0, s, n, nw, L,
+                           split0, w, hptr, v, wq);
+}
+
+void launch_cpr_finish(hipStream_t s, int nb, int n, int nw, const AmgLevel &L,
+                       const int *split0, Sys sys, const double *v, const double *dinv,
+                       double *z) {
+    constexpr int G = 8;
+    const long threads = ((long)n + nw) * G;
+    if (nb == 2)
+        hipLaunchKernelGGL((k_cpr_finish<2, G>), grid_for(threads, kBlock), dim3(kBlock), 0, s, n,
+                           nw, L, split0, sys, v, dinv, z);
+    else
+        hipLaunchKernelGGL((k_cpr_finish<3, G>), grid_for(threads, kBlock), dim3(kBlock), 0, s, n,
+                           nw, L, split0, sys, v, dinv, z);
+}
+
+}  // namespace fim

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <limits>
 #include <new>
@@ -80,7 +81,10 @@ enum { S_CONV = 0, S_UPD = 16, S_NORM = 20, S_RES = 24, S_COUNT = 32 };
 }  // namespace
 
 struct fim_ctx {
-    hipStream_t s = nullptr;
+    hipStream_t s = nullptr;          // the context's own stream
+    hipStream_t user_s = nullptr;     // the caller's stream the work is ordered after
+    hipEvent_t ev_user = nullptr;
+    hipGraphExec_t step_exec[kMaxRestart] = {};   // Arnoldi step j after its SpMV
     int dev = 0;
     fim_options opt{};
     Grid g{};
@@ -106,8 +110,14 @@ struct fim_ctx {
     int *rowptr = nullptr, *colind = nullptr, *diagpos = nullptr;
     double *val = nullptr, *R = nullptr, *dinv = nullptr;
     int *bad = nullptr;
-    double *V = nullptr, *w = nullptr, *z = nullptr, *x = nullptr, *r = nullptr, *t = nullptr,
-           *b = nullptr, *H = nullptr, *tmp = nullptr, *ydev = nullptr;
+    double *V = nullptr, *Z = nullptr, *w = nullptr, *z = nullptr, *x = nullptr, *r = nullptr,
+           *t = nullptr, *b = nullptr, *H = nullptr, *tmp = nullptr, *ydev = nullptr;
+    // pressure AMG of the CPR preconditioner
+    std::vector<AmgLevel> lv;
+    std::vector<const int *> cfs_ptr, cfs_idx;     // coarse slot -> fine slots, per level
+    double *Mden = nullptr, *Minv = nullptr, *colk = nullptr, *wq = nullptr;
+    int *amg_bad = nullptr;
+    int *split0 = nullptr;                          // natural cell -> level-0 split index
     int *reorth = nullptr;
     double *partials = nullptr, *scal = nullptr;
     unsigned *counter = nullptr;
@@ -163,8 +173,17 @@ struct fim_ctx {
         (void)hipFree(p);
     }
 
+    void drop_graphs() {
+        for (auto &g : step_exec)
+            if (g) {
+                (void)hipGraphExecDestroy(g);
+                g = nullptr;
+            }
+    }
+
     ~fim_ctx() {
         if (s) (void)hipStreamSynchronize(s);
+        drop_graphs();
         for (void *p : owned) (void)hipFree(p);
         if (pin) (void)hipHostFree(pin);
         for (auto &e : ev)
@@ -172,6 +191,8 @@ struct fim_ctx {
         for (auto &e : colev)
             if (e) (void)hipEventDestroy(e);
         for (auto &e : spmv_ev) (void)hipEventDestroy(e);
+        if (ev_user) (void)hipEventDestroy(ev_user);
+        if (s) (void)hipStreamDestroy(s);
     }
 };
 
@@ -186,7 +207,12 @@ static void check_options(const fim_options *o) {
             "max_lin, max_newton >= 1 and max_cuts >= 0 required");
     REQUIRE(o->ds_max > 0 && o->dp_max > 0 && o->lin_rtol > 0 && o->lin_rtol < 1,
             "ds_max, dp_max > 0 and 0 < lin_rtol < 1 required");
-    REQUIRE(o->precond == FIM_PREC_BJ, "unknown preconditioner %d", o->precond);
+    REQUIRE(o->precond == FIM_PREC_BJ || o->precond == FIM_PREC_CPR, "unknown preconditioner %d",
+            o->precond);
+    REQUIRE(o->amg_cycle >= 0 && o->amg_cycle <= 2, "amg_cycle must be 0, 1 or 2");
+    REQUIRE(o->amg_sweeps >= 0 && o->amg_sweeps <= 8, "amg_sweeps must be in [0, 8]");
+    REQUIRE(o->graphs == 0 || o->graphs == 1, "graphs must be 0 or 1");
+    REQUIRE(o->forcing == 0 || o->forcing == 1, "forcing must be 0 or 1");
     REQUIRE(o->precision == FIM_FP64, "unknown precision mode %d", o->precision);
 }
 
@@ -221,12 +247,122 @@ static void build_pattern(fim_ctx *c, std::vector<int> &rp, std::vector<int> &ci
 
 static void alloc_krylov(fim_ctx *c, int m) {
     c->release(c->V);
+    c->release(c->Z);
     c->release(c->H);
-    c->V = nullptr;
-    c->H = nullptr;
+    c->V = c->Z = c->H = nullptr;
     c->m = m;
     c->V = c->alloc<double>((size_t)(m + 1) * c->nvec);
+    c->Z = c->alloc<double>((size_t)(m + 1) * c->nvec);
     c->H = c->alloc<double>((size_t)(m + 1) * (kMaxRestart + 2));
+}
+
+// Structured aggregation hierarchy of the pressure AMG (built once): level
+// dimensions halve (rounding up) until a level has at most kCoarseMax cells;
+// each well keeps one slot per distinct perforated cell of every level.
+static void build_amg(fim_ctx *c, const std::vector<int> &sorted_cells,
+                      const std::vector<int> &pwell_h) {
+    int nx = c->g.nx, ny = c->g.ny, nz = c->g.nz;
+    const int nw = c->nw;
+    std::vector<int> slot_cell = sorted_cells, slot_well = pwell_h, sps = c->wps;
+    c->cfs_ptr.push_back(nullptr);
+    c->cfs_idx.push_back(nullptr);
+    for (;;) {
+        AmgLevel L{};
+        L.nx = nx;
+        L.ny = ny;
+        L.nz = nz;
+        L.nxp = nx + (nx & 1);
+        L.half = L.nxp * ny * nz / 2;
+        L.nw = nw;
+        L.nslot = (int)slot_cell.size();
+        const int ncs = 2 * L.half;
+        auto split = [&](int cn) {
+            const int i = cn % nx, j = (cn / nx) % ny, k = cn / (nx * ny);
+            const int cc = i + L.nxp * (j + ny * k);
+            return (((i + j + k) & 1) ? L.half : 0) + (cc >> 1);
+        };
+        std::vector<int> scell(L.nslot), cps(ncs + 1, 0), cslot(L.nslot);
+        for (int q = 0; q < L.nslot; ++q) {
+            scell[q] = split(slot_cell[q]);
+            cps[scell[q] + 1]++;
+        }
+        for (int q = 0; q < ncs; ++q) cps[q + 1] += cps[q];
+        {
+            std::vector<int> fill(cps.begin(), cps.end() - 1);
+            for (int q = 0; q < L.nslot; ++q) cslot[fill[scell[q]]++] = q;
+        }
+        L.a = c->alloc<double>((size_t)7 * ncs);
+        launch_scale_copy(c->s, ncs, nullptr, 1.0, L.a);
+        launch_scale_copy(c->s, 6L * ncs, nullptr, 0.0, L.a + ncs);
+        L.aww = c->alloc<double>(std::max(nw, 1));
+        L.acw = c->alloc<double>(std::max(L.nslot, 1));
+        L.awc = c->alloc<double>(std::max(L.nslot, 1));
+        L.x = c->alloc<double>(ncs + nw);
+        L.b = c->alloc<double>(ncs + nw);
+        L.r = c->alloc<double>(ncs + nw);
+        launch_scale_copy(c->s, ncs + nw, nullptr, 0.0, L.x);
+        launch_scale_copy(c->s, ncs + nw, nullptr, 0.0, L.b);
+        launch_scale_copy(c->s, ncs + nw, nullptr, 0.0, L.r);
+        if (c->lv.empty()) {
+            std::vector<int> sp(c->n);
+            for (int cn = 0; cn < c->n; ++cn) sp[cn] = split(cn);
+            c->split0 = c->upload(sp.data(), sp.size());
+        }
+        L.sps = c->upload(sps.data(), sps.size());
+        L.scell = c->upload(scell.data(), scell.size());
+        L.swell = c->upload(slot_well.data(), slot_well.size());
+        L.cps = c->upload(cps.data(), cps.size());
+        L.cslot = c->upload(cslot.data(), cslot.size());
+        c->sync();                  // the host vectors above are temporaries
+        c->lv.push_back(L);
+        if ((long)nx * ny * nz <= kCoarseMax || (nx == 1 && ny == 1 && nz == 1)) break;
+        // next level: coarse dimensions and the well slots they keep
+        const int cnx = (nx + 1) / 2, cny = (ny + 1) / 2, cnz = (nz + 1) / 2;
+        std::vector<int> ncell, nwell, nsps(nw + 1, 0), fine_to_coarse(L.nslot);
+        for (int w = 0; w < nw; ++w) {
+            std::vector<int> cc;
+            for (int q = sps[w]; q < sps[w + 1]; ++q) {
+                const int cn = slot_cell[q];
+                const int i = cn % nx, j = (cn / nx) % ny, k = cn / (nx * ny);
+                cc.push_back(i / 2 + cnx * (j / 2 + cny * (k / 2)));
+            }
+            std::vector<int> uniq = cc;
+            std::sort(uniq.begin(), uniq.end());
+            uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
+            const int base = (int)ncell.size();
+            for (int u : uniq) {
+                ncell.push_back(u);
+                nwell.push_back(w);
+            }
+            for (int q = sps[w]; q < sps[w + 1]; ++q)
+                fine_to_coarse[q] = base + (int)(std::lower_bound(uniq.begin(), uniq.end(),
+                                                                  cc[q - sps[w]]) - uniq.begin());
+            nsps[w + 1] = (int)ncell.size();
+        }
+        std::vector<int> fptr(ncell.size() + 1, 0), fidx(L.nslot);
+        for (int q = 0; q < L.nslot; ++q) fptr[fine_to_coarse[q] + 1]++;
+        for (size_t q = 0; q < ncell.size(); ++q) fptr[q + 1] += fptr[q];
+        {
+            std::vector<int> fill(fptr.begin(), fptr.end() - 1);
+            for (int q = 0; q < L.nslot; ++q) fidx[fill[fine_to_coarse[q]]++] = q;
+        }
+        c->cfs_ptr.push_back(c->upload(fptr.data(), fptr.size()));
+        c->cfs_idx.push_back(c->upload(fidx.data(), std::max<size_t>(fidx.size(), 1)));
+        c->sync();
+        nx = cnx;
+        ny = cny;
+        nz = cnz;
+        slot_cell.swap(ncell);
+        slot_well.swap(nwell);
+        sps.swap(nsps);
+    }
+    const AmgLevel &Lc = c->lv.back();
+    const size_t n = 2 * (size_t)Lc.half + Lc.nw;
+    c->Mden = c->alloc<double>(n * n);
+    c->Minv = c->alloc<double>(n * n);
+    c->colk = c->alloc<double>(n);
+    c->amg_bad = c->alloc<int>(1);
+    c->wq = c->alloc<double>((size_t)c->n * c->nb);
 }
 
 static int create_impl(const fim_grid *grid, const fim_rock *rock, const fim_fluid *fl,
@@ -278,7 +414,7 @@ static int create_impl(const fim_grid *grid, const fim_rock *rock, const fim_flu
 
     auto *c = new fim_ctx();
     try {
-        c->s = static_cast<hipStream_t>(stream);
+        c->user_s = static_cast<hipStream_t>(stream);
         c->opt = *opt;
         c->g = Grid{grid->nx, grid->ny, grid->nz, (int)nl};
         c->n = (int)nl;
@@ -383,6 +519,10 @@ static int create_impl(const fim_grid *grid, const fim_rock *rock, const fim_flu
 
         // device memory (everything above validated the input without the device)
         HIPCHECK(hipGetDevice(&c->dev));
+        HIPCHECK(hipStreamCreateWithFlags(&c->s, hipStreamNonBlocking));
+        HIPCHECK(hipEventCreateWithFlags(&c->ev_user, hipEventDisableTiming));
+        HIPCHECK(hipEventRecord(c->ev_user, c->user_s));
+        HIPCHECK(hipStreamWaitEvent(c->s, c->ev_user, 0));
         const int n = c->n;
         c->dx = c->upload(grid->dx, grid->nx);
         c->dy = c->upload(grid->dy, grid->ny);
@@ -443,7 +583,8 @@ static int create_impl(const fim_grid *grid, const fim_rock *rock, const fim_flu
         c->ydev = c->alloc<double>(kMaxRestart + 2);
         c->reorth = c->alloc<int>(1);
         alloc_krylov(c, opt->restart);
-        const size_t np = (size_t)(kMaxRestart + 1) * 1024 + (size_t)2048 * 16;
+        build_amg(c, sorted_cells, pwell_h);
+        const size_t np = (size_t)(kMaxRestart + 2) * 2048 + (size_t)2048 * 16;
         c->partials = c->alloc<double>(np);
         c->scal = c->alloc<double>(S_COUNT);
         c->counter = c->alloc<unsigned>(1);
@@ -509,9 +650,61 @@ static void restore_state(fim_ctx *c, int slot) {
         HIPCHECK(hipMemcpyAsync(c->pbhp, c->spb[slot], c->nw * 8, hipMemcpyDeviceToDevice, c->s));
 }
 
+// One cycle of the pressure AMG on level l (right-hand side in lv[l].b,
+// result in lv[l].x): red-black Gauss-Seidel with zero initial guess,
+// coarse-grid correction(s), then smoothing that applies the pending
+// correction while it reads.
+static void amg_cycle(fim_ctx *c, int l) {
+    const int L = (int)c->lv.size();
+    if (l == L - 1) {
+        launch_amg_coarsest_solve(c->s, c->lv[l], c->Minv);
+        return;
+    }
+    const AmgLevel &F = c->lv[l], &C = c->lv[l + 1];
+    const int nu = c->opt.amg_sweeps > 0 ? c->opt.amg_sweeps : 1;
+    int gamma = (c->opt.amg_cycle == 1) ? 1 : 2;
+    if (l + 1 == L - 1) gamma = 1;             // the coarsest level is solved exactly
+    for (int sw = 0; sw < nu; ++sw) {
+        launch_amg_sweep(c->s, F, C, 0, sw == 0 ? (kCellsZero | kWellsZero) : 0);
+        launch_amg_sweep(c->s, F, C, 1, sw == 0 ? kWellsZero : 0);
+        launch_amg_well_sweep(c->s, F);
+    }
+    for (int gv = 0; gv < gamma; ++gv) {
+        if (gv > 0) launch_amg_correct(c->s, F, C);
+        launch_amg_restrict(c->s, F, C);
+        amg_cycle(c, l + 1);
+    }
+    for (int sw = 0; sw < nu; ++sw) {
+        launch_amg_sweep(c->s, F, C, 0, sw == 0 ? (kCellsCorr | kWellsCorr) : 0);
+        launch_amg_sweep(c->s, F, C, 1, sw == 0 ? kWellsCorr : 0);
+        launch_amg_well_sweep(c->s, F);
+    }
+}
+
 static void prec_setup(fim_ctx *c) {
     launch_bj_setup(c->s, c->nb, c->nrows, c->diagpos, c->val, c->dinv, c->bad);
+    if (c->opt.precond == FIM_PREC_CPR) {
+        launch_amg_extract(c->s, c->nb, c->lv[0], c->g, c->wells(), c->sys(), c->wq);
+        for (size_t l = 1; l < c->lv.size(); ++l)
+            launch_amg_coarsen(c->s, c->lv[l - 1], c->lv[l], c->cfs_ptr[l], c->cfs_idx[l]);
+        launch_amg_coarsest_setup(c->s, c->lv.back(), c->Mden, c->Minv, c->colk, c->amg_bad);
+    }
     c->prec_ready = true;
+}
+
+// z = M^-1 v.  With hptr set, v = w / *hptr is formed (and stored) first,
+// as for a new Arnoldi vector; without it v = w.
+static void precondition(fim_ctx *c, const double *w, const double *hptr, double *v, double *z) {
+    if (c->opt.precond == FIM_PREC_CPR) {
+        launch_cpr_restrict(c->s, c->nb, c->n, c->nw, c->lv[0], c->split0, w, hptr, v, c->wq);
+        amg_cycle(c, 0);
+        launch_cpr_finish(c->s, c->nb, c->n, c->nw, c->lv[0], c->split0, c->sys(), hptr ? v : w,
+                          c->dinv, z);
+    } else if (hptr) {
+        launch_normalize_precond(c->s, c->nb, c->nrows, w, hptr, v, z, c->dinv);
+    } else {
+        launch_bj_apply(c->s, c->nb, c->nrows, c->dinv, w, z);
+    }
 }
 
 // SpMV inside the solver, optionally bracketed by events
@@ -549,18 +742,78 @@ static void drain_spmv_events(fim_ctx *c) {
 }
 
 // ---------------------------------------------------------------------------
-// right-preconditioned restarted GMRES with classical Gram-Schmidt and a
-// DGKS-triggered second pass.  Solves J x = b (b, x device vectors of the
-// context), initial guess zero.  The host stays one Arnoldi step behind the
-// device: step j+1 is queued before the Hessenberg column of step j is read.
+// Flexible GMRES (right preconditioning, the preconditioned vectors Z kept)
+// with classical Gram-Schmidt and a DGKS-triggered second pass.  Solves
+// J x = b (b, x device vectors of the context), initial guess zero.  The host
+// stays one Arnoldi step behind the device: step j+1 is queued before the
+// Hessenberg column of step j is read.
+
+// Arnoldi step j after its SpMV (w = J z_j): two Gram-Schmidt passes (the
+// second gated on the device), the new basis vector and its preconditioned
+// image, and the copy of the Hessenberg column to pinned host memory.
+static void arnoldi_rest(fim_ctx *c, int j) {
+    const long nv = c->nvec;
+    const int LD = kMaxRestart + 2;
+    double *col = c->H + (size_t)j * LD;
+    double *pinH = c->pin + S_COUNT;
+    launch_multidot(c->s, nv, j + 1, c->V, c->w, c->partials, c->counter, col, nullptr);
+    launch_update_norm(c->s, nv, j + 1, c->V, col, c->w, c->partials, c->counter, col + j + 1,
+                       nullptr, c->reorth, nullptr);
+    launch_multidot(c->s, nv, j + 1, c->V, c->w, c->partials, c->counter, c->tmp, c->reorth);
+    launch_update_norm(c->s, nv, j + 1, c->V, c->tmp, c->w, c->partials, c->counter, col + j + 1,
+                       c->reorth, nullptr, col);
+    precondition(c, c->w, col + j + 1, c->V + (size_t)(j + 1) * nv, c->Z + (size_t)(j + 1) * nv);
+    HIPCHECK(hipMemcpyAsync(pinH + (size_t)j * LD, col, (j + 2) * sizeof(double),
+                            hipMemcpyDeviceToHost, c->s));
+}
+
+static void arnoldi_rest_graph(fim_ctx *c, int j) {
+    if (!c->step_exec[j]) {
+        hipGraph_t graph = nullptr;
+        HIPCHECK(hipStreamBeginCapture(c->s, hipStreamCaptureModeThreadLocal));
+        try {
+            arnoldi_rest(c, j);
+        } catch (...) {
+            (void)hipStreamEndCapture(c->s, &graph);
+            if (graph) (void)hipGraphDestroy(graph);
+            throw;
+        }
+        HIPCHECK(hipStreamEndCapture(c->s, &graph));
+        hipError_t e = hipGraphInstantiate(&c->step_exec[j], graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        HIPCHECK(e);
+    }
+    HIPCHECK(hipGraphLaunch(c->step_exec[j], c->s));
+}
+
+// Linear tolerance of a Newton iteration: the fixed lin_rtol, or the
+// Eisenstat-Walker choice 2 (gamma 0.9, alpha 2) kept in [lin_rtol, 1e-2]
+// with its safeguard against dropping too fast.
+struct Forcing {
+    double rn_prev = -1.0, eta_prev = 1e-2;
+    double next(const fim_options &o, double rn) {
+        const double eta_max = 1e-2;
+        double eta = eta_max;
+        if (o.forcing && rn_prev > 0.0) {
+            eta = 0.9 * (rn / rn_prev) * (rn / rn_prev);
+            const double guard = 0.9 * eta_prev * eta_prev;
+            if (guard > 0.1) eta = std::max(eta, guard);
+        }
+        if (!o.forcing) eta = o.lin_rtol;
+        eta = std::min(std::max(eta, o.lin_rtol), std::max(eta_max, o.lin_rtol));
+        rn_prev = rn;
+        eta_prev = eta;
+        return eta;
+    }
+};
 
 static int gmres(fim_ctx *c, const double *bvec, double *xvec, int max_it, double rtol,
-                 bool profile, int *iters_out, double *relres_out) {
-    const int m = c->m, nb = c->nb, nrows = c->nrows;
+                 bool profile, int *iters_out, double *relres_out, Forcing *forcing = nullptr) {
+    const int m = c->m;
     const long nv = c->nvec;
     const int LD = kMaxRestart + 2;          // stride of a Hessenberg column
-    double *pinH = c->pin + S_COUNT;          // pinned copies of the columns
-    double *piny = pinH + (size_t)(kMaxRestart + 1) * LD;
+    const double *pinH = c->pin + S_COUNT;    // pinned copies of the columns
+    double *piny = c->pin + S_COUNT + (size_t)(kMaxRestart + 1) * LD;
     launch_scale_copy(c->s, nv, nullptr, 0.0, xvec);
     launch_norm2(c->s, nv, bvec, c->partials, c->counter, c->scal + S_NORM);
     d2h_scalars(c, S_NORM, 2);
@@ -571,6 +824,7 @@ static int gmres(fim_ctx *c, const double *bvec, double *xvec, int max_it, doubl
         *relres_out = (bnorm == 0.0) ? 0.0 : NAN;
         return bnorm == 0.0 ? 0 : -1;
     }
+    if (forcing) rtol = forcing->next(c->opt, bnorm);
     std::vector<double> Hh((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
     hipEvent_t *colev = c->colev;
     const double *rvec = bvec;
@@ -580,24 +834,15 @@ static int gmres(fim_ctx *c, const double *bvec, double *xvec, int max_it, doubl
     double relres = 1.0;
 
     auto enqueue = [&](int j) {
-        double *col = c->H + (size_t)j * LD;
-        double *vj1 = c->V + (size_t)(j + 1) * nv;
-        solver_spmv(c, c->z, c->w, profile);
-        launch_multidot(c->s, nv, j + 1, c->V, c->w, c->partials, c->counter, col, nullptr);
-        launch_update_norm(c->s, nv, j + 1, c->V, col, c->w, c->partials, c->counter, col + j + 1,
-                           nullptr, c->reorth, nullptr);
-        launch_multidot(c->s, nv, j + 1, c->V, c->w, c->partials, c->counter, c->tmp, c->reorth);
-        launch_update_norm(c->s, nv, j + 1, c->V, c->tmp, c->w, c->partials, c->counter,
-                           col + j + 1, c->reorth, nullptr, col);
-        launch_normalize_precond(c->s, nb, nrows, c->w, col + j + 1, vj1, c->z, c->dinv);
-        HIPCHECK(hipMemcpyAsync(pinH + (size_t)j * LD, col, (j + 2) * sizeof(double),
-                                hipMemcpyDeviceToHost, c->s));
+        solver_spmv(c, c->Z + (size_t)j * nv, c->w, profile);
+        if (c->opt.graphs) arnoldi_rest_graph(c, j);
+        else arnoldi_rest(c, j);
         HIPCHECK(hipEventRecord(colev[j], c->s));
     };
 
     {
         for (;;) {
-            launch_normalize_precond(c->s, nb, nrows, rvec, beta_dev, c->V, c->z, c->dinv);
+            precondition(c, rvec, beta_dev, c->V, c->Z);
             std::fill(g.begin(), g.end(), 0.0);
             g[0] = beta;
             int k = 0;
@@ -635,7 +880,7 @@ static int gmres(fim_ctx *c, const double *bvec, double *xvec, int max_it, doubl
             }
             for (int i = 0; i < k; ++i) piny[i] = y[i];
             HIPCHECK(hipMemcpyAsync(c->ydev, piny, k * sizeof(double), hipMemcpyHostToDevice, c->s));
-            launch_final_update(c->s, nb, nrows, k, c->V, c->ydev, c->dinv, xvec);
+            launch_axpy_multi(c->s, nv, k, c->Z, c->ydev, xvec);
             solver_spmv(c, xvec, c->t, profile);
             launch_residual(c->s, nv, bvec, c->t, c->r, c->partials, c->counter, c->scal + S_RES);
             d2h_scalars(c, S_RES, 2);
@@ -662,6 +907,7 @@ static int gmres(fim_ctx *c, const double *bvec, double *xvec, int max_it, doubl
 struct NewtonStats {
     int newton = 0, linear = 0;
     double cnv[3] = {0, 0, 0}, mb[3] = {0, 0, 0};
+    double last_dp = 0, last_ds = 0, well_res = 0;
     double t_asm = 0, t_lin = 0, t_upd = 0;
 };
 
@@ -671,11 +917,21 @@ static float elapsed(hipEvent_t a, hipEvent_t b) {
     return ms;
 }
 
+// FIM_DEBUG=1 in the environment prints one line per Newton iteration
+static bool debug_on() {
+    static const int on = [] {
+        const char *e = std::getenv("FIM_DEBUG");
+        return (e && *e && *e != '0') ? 1 : 0;
+    }();
+    return on != 0;
+}
+
 static bool newton(fim_ctx *c, double dt, NewtonStats &st) {
     const fim_options &o = c->opt;
     const int nb = c->nb;
     double last_dp = INFINITY, last_ds = INFINITY;
     bool pending_update = false;
+    Forcing forcing;
     for (int it = 0;; ++it) {
         HIPCHECK(hipEventRecord(c->ev[0], c->s));
         props(c, it == 0);
@@ -701,21 +957,31 @@ static bool newton(fim_ctx *c, double dt, NewtonStats &st) {
             conv = conv && st.cnv[i] <= o.tol_cnv && st.mb[i] <= o.tol_mb;
         }
         const double wmax = sc[3 * nb];
+        st.last_dp = last_dp;
+        st.last_ds = last_ds;
+        st.well_res = wmax;
         finite = finite && std::isfinite(wmax);
         if (!finite) return false;
         conv = conv && wmax <= o.tol_well && last_dp <= o.tol_dp && last_ds <= o.tol_ds;
+        if (debug_on())
+            std::fprintf(stderr,
+                         "[fim] dt %.4g it %d cnv %.2e %.2e mb %.2e %.2e well %.2e dp %.2e ds %.2e%s\n",
+                         dt, it, st.cnv[0], st.cnv[1], st.mb[0], st.mb[1], wmax, last_dp, last_ds,
+                         conv ? " converged" : "");
         if (conv) return true;
         if (it >= o.max_newton) return false;
 
         prec_setup(c);
         int li = 0;
         double rr = 0;
-        const int gs = gmres(c, c->R, c->x, o.max_lin, o.lin_rtol, o.profile != 0, &li, &rr);
+        const int gs = gmres(c, c->R, c->x, o.max_lin, o.lin_rtol, o.profile != 0, &li, &rr,
+                             &forcing);
         HIPCHECK(hipEventRecord(c->ev[2], c->s));
         HIPCHECK(hipEventSynchronize(c->ev[2]));
         st.t_lin += elapsed(c->ev[1], c->ev[2]);
         st.linear += li;
         st.newton += 1;
+        if (debug_on()) std::fprintf(stderr, "[fim]   linear %d iterations relres %.2e\n", li, rr);
         if (gs != 0 && !(std::isfinite(rr) && rr < 1.0)) return false;
         launch_newton_update(c->s, nb, c->phys, c->n, c->nw, c->x, o.ds_max, o.dp_max, c->P,
                              c->Sw, c->X, c->flag, c->pbhp, c->partials, update_blocks(c->n),
@@ -779,6 +1045,9 @@ static int step_impl(fim_ctx *c, double dt, fim_step_report *rep) {
     r.t_update = st.t_upd;
     r.spmv_ms = c->spmv_ms;
     r.spmv_calls = c->spmv_calls;
+    r.last_dp = st.last_dp;
+    r.last_ds = st.last_ds;
+    r.well_res = st.well_res;
     if (rep) *rep = r;
     return status;
 }
@@ -863,6 +1132,8 @@ int fim_set_options(fim_ctx *c, const fim_options *opt) {
     return guarded([&] {
         REQUIRE(c, "context is NULL");
         check_options(opt);
+        c->sync();
+        c->drop_graphs();        // captured steps depend on the options and buffers
         if (opt->restart > c->m) {
             c->sync();
             alloc_krylov(c, opt->restart);
@@ -887,6 +1158,8 @@ int fim_set_state_dev(fim_ctx *c, const double *p, const double *sw, const doubl
                       const int8_t *flag, const double *bhp) {
     return guarded([&] {
         REQUIRE(c, "context is NULL");
+        HIPCHECK(hipEventRecord(c->ev_user, c->user_s));
+        HIPCHECK(hipStreamWaitEvent(c->s, c->ev_user, 0));
         put_state(c, p, sw, x3, flag, bhp, true, true);
         return FIM_OK;
     });
@@ -1015,7 +1288,7 @@ int fim_precond_apply(fim_ctx *c, const double *xh, double *yh) {
         }
         prec_setup(c);
         HIPCHECK(hipMemcpyAsync(c->b, xh, c->nvec * 8, hipMemcpyHostToDevice, c->s));
-        launch_bj_apply(c->s, c->nb, c->nrows, c->dinv, c->b, c->t);
+        precondition(c, c->b, nullptr, nullptr, c->t);
         HIPCHECK(hipMemcpyAsync(yh, c->t, c->nvec * 8, hipMemcpyDeviceToHost, c->s));
         c->sync();
         return FIM_OK;

@@ -68,6 +68,23 @@ struct Sys {
     double *val, *R;
 };
 
+// One level of the pressure AMG hierarchy (structured aggregation).  Cells
+// are stored colour-split: split index = colour * half + (c >> 1) with
+// c = i + nxp*(j + ny*k) and nxp = nx rounded up to even; wells follow the
+// 2*half cell entries in x and b.
+struct AmgLevel {
+    int nx, ny, nz, nxp, half, nw, nslot;
+    double *a;              // [7][2*half]: diagonal, -x, +x, -y, +y, -z, +z
+    double *aww;            // [nw] well diagonal
+    const int *sps;         // [nw+1] well -> slot range
+    const int *scell;       // [nslot] split index of the slot's cell
+    const int *swell;       // [nslot] well of the slot
+    double *acw, *awc;      // [nslot] cell->well and well->cell couplings
+    const int *cps;         // [2*half+1] split cell -> range in cslot
+    const int *cslot;       // slot ids of each cell
+    double *x, *b, *r;      // [2*half + nw]: iterate, right-hand side, residual
+};
+
 // ---- physics kernels (fim_phys.hip) ---------------------------------------
 void launch_static(hipStream_t s, Grid g, const double *dx, const double *dy, const double *dz,
                    double top, const double *kx, const double *ky, const double *kz,
@@ -118,5 +135,28 @@ void launch_final_update(hipStream_t s, int nb, int nrows, int k, const double *
 void launch_residual(hipStream_t s, long nvec, const double *b, const double *Ax, double *r,
                      double *partials, unsigned *counter, double *out);
 void launch_scale_copy(hipStream_t s, long nvec, const double *x, double a, double *y);
+void launch_axpy_multi(hipStream_t s, long nvec, int k, const double *Z, const double *y,
+                       double *x);
+
+// ---- CPR / pressure AMG kernels (fim_amg.hip) -----------------------------------
+constexpr int kCoarseMax = 64;       // cells of the level that is inverted densely
+void launch_amg_extract(hipStream_t s, int nb, const AmgLevel &L, Grid g, Wells w, Sys sys,
+                        double *wq);
+void launch_amg_coarsen(hipStream_t s, const AmgLevel &F, const AmgLevel &C, const int *cfs_ptr,
+                        const int *cfs_idx);
+void launch_amg_coarsest_setup(hipStream_t s, const AmgLevel &L, double *M, double *Minv,
+                               double *colk, int *bad);
+void launch_amg_coarsest_solve(hipStream_t s, const AmgLevel &L, const double *Minv);
+void launch_amg_sweep(hipStream_t s, const AmgLevel &L, const AmgLevel &C, int color, int mode);
+void launch_amg_well_sweep(hipStream_t s, const AmgLevel &L);
+void launch_amg_restrict(hipStream_t s, const AmgLevel &F, const AmgLevel &C);
+void launch_amg_correct(hipStream_t s, const AmgLevel &F, const AmgLevel &C);
+void launch_cpr_restrict(hipStream_t s, int nb, int n, int nw, const AmgLevel &L,
+                         const int *split0, const double *w, const double *hptr, double *v,
+                         const double *wq);
+void launch_cpr_finish(hipStream_t s, int nb, int n, int nw, const AmgLevel &L,
+                       const int *split0, Sys sys, const double *v, const double *dinv,
+                       double *z);
+enum { kCellsZero = 1, kCellsCorr = 2, kWellsZero = 4, kWellsCorr = 8 };
 
 }  // namespace fim

@@ -215,7 +215,7 @@ void launch_bj_apply(hipStream_t s, int nb, int nrows, const double *dinv, const
 
 int vec_blocks(long nvec) {
     long b = (nvec + kBlock - 1) / kBlock;
-    return (int)(b < 1024 ? (b > 0 ? b : 1) : 1024);
+    return (int)(b < 2048 ? (b > 0 ? b : 1) : 2048);
 }
 
 // out[0] = ||x||^2, out[1] = ||x||
@@ -346,8 +346,21 @@ __global__ __launch_bounds__(kBlock) void k_multidot(long nvec, int nv, const do
     double acc[kMaxDots];
 #pragma unroll
     for (int i = 0; i < kMaxDots; ++i) acc[i] = 0.0;
-    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < nvec;
-         e += (long)gridDim.x * blockDim.x) {
+    // two independent elements per step keep twice the loads in flight
+    const long gs = (long)gridDim.x * blockDim.x;
+    long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; e + gs < nvec; e += 2 * gs) {
+        const double w0 = w[e], w1 = w[e + gs];
+#pragma unroll
+        for (int i = 0; i < kMaxDots - 1; ++i)
+            if (i < nv) {
+                const double *vi = V + (size_t)i * nvec;
+                acc[i] += __builtin_nontemporal_load(vi + e) * w0 +
+                          __builtin_nontemporal_load(vi + e + gs) * w1;
+            }
+        acc[kMaxDots - 1] += w0 * w0 + w1 * w1;
+    }
+    if (e < nvec) {
         const double we = w[e];
 #pragma unroll
         for (int i = 0; i < kMaxDots - 1; ++i)
@@ -379,10 +392,22 @@ __global__ __launch_bounds__(kBlock) void k_update_norm(long nvec, int nv,
     __syncthreads();
     double v[1] = {0.0};
     const bool mx[1] = {false};
-    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < nvec;
-         e += (long)gridDim.x * blockDim.x) {
-        double a = w[e];
+    const long gs = (long)gridDim.x * blockDim.x;
+    long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; e + gs < nvec; e += 2 * gs) {
+        double a0 = w[e], a1 = w[e + gs];
 #pragma unroll 4
+        for (int i = 0; i < nv; ++i) {
+            const double *vi = V + (size_t)i * nvec;
+            a0 -= c[i] * __builtin_nontemporal_load(vi + e);
+            a1 -= c[i] * __builtin_nontemporal_load(vi + e + gs);
+        }
+        w[e] = a0;
+        w[e + gs] = a1;
+        v[0] += a0 * a0 + a1 * a1;
+    }
+    if (e < nvec) {
+        double a = w[e];
         for (int i = 0; i < nv; ++i) a -= c[i] * __builtin_nontemporal_load(V + (size_t)i * nvec + e);
         w[e] = a;
         v[0] += a * a;
@@ -455,6 +480,28 @@ void launch_residual(hipStream_t s, long nvec, const double *b, const double *Ax
                      double *partials, unsigned *counter, double *out) {
     hipLaunchKernelGGL(k_residual, dim3(vec_blocks(nvec)), dim3(kBlock), 0, s, nvec, b, Ax, r,
                        partials, counter, out);
+}
+
+// x += sum_{i<k} y_i Z_i (the flexible-GMRES update with stored
+// preconditioned vectors)
+__global__ __launch_bounds__(kBlock) void k_axpy_multi(long nvec, int k,
+                                                       const double *__restrict__ Z,
+                                                       const double *__restrict__ y,
+                                                       double *__restrict__ x) {
+    __shared__ double ys[kMaxRestart + 1];
+    for (int i = threadIdx.x; i < k; i += blockDim.x) ys[i] = y[i];
+    __syncthreads();
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < nvec;
+         e += (long)gridDim.x * blockDim.x) {
+        double a = x[e];
+        for (int i = 0; i < k; ++i) a += ys[i] * Z[(size_t)i * nvec + e];
+        x[e] = a;
+    }
+}
+
+void launch_axpy_multi(hipStream_t s, long nvec, int k, const double *Z, const double *y,
+                       double *x) {
+    hipLaunchKernelGGL(k_axpy_multi, dim3(vec_blocks(nvec)), dim3(kBlock), 0, s, nvec, k, Z, y, x);
 }
 
 __global__ __launch_bounds__(kBlock) void k_scale_copy(long nvec, const double *__restrict__ x,

@@ -59,7 +59,8 @@ class FimOptions(C.Structure):
                 ("dp_max", C.c_double), ("lin_rtol", C.c_double),
                 ("max_newton", C.c_int32), ("max_lin", C.c_int32), ("restart", C.c_int32),
                 ("max_cuts", C.c_int32), ("precond", C.c_int32), ("precision", C.c_int32),
-                ("profile", C.c_int32), ("reserved", C.c_int32)]
+                ("profile", C.c_int32), ("amg_cycle", C.c_int32), ("amg_sweeps", C.c_int32),
+                ("graphs", C.c_int32), ("forcing", C.c_int32), ("reserved", C.c_int32)]
 
 
 class FimStepReport(C.Structure):
@@ -69,6 +70,7 @@ class FimStepReport(C.Structure):
                 ("cnv", C.c_double * 3), ("mb", C.c_double * 3),
                 ("t_assemble", C.c_double), ("t_linear", C.c_double),
                 ("t_update", C.c_double), ("spmv_ms", C.c_double),
+                ("last_dp", C.c_double), ("last_ds", C.c_double), ("well_res", C.c_double),
                 ("dt_sub", C.c_double * FIM_MAX_SUB)]
 
 
@@ -158,7 +160,9 @@ def options_struct(o: rv.Options, profile=False) -> FimOptions:
                       tol_well=o.tol_well, ds_max=o.ds_max, dp_max=o.dp_max,
                       lin_rtol=o.lin_rtol, max_newton=o.max_newton, max_lin=o.max_lin,
                       restart=o.restart, max_cuts=o.max_cuts, precond=o.precond,
-                      precision=o.precision, profile=1 if profile else 0, reserved=0)
+                      precision=o.precision, profile=1 if profile else 0,
+                      amg_cycle=o.amg_cycle, amg_sweeps=o.amg_sweeps, graphs=o.graphs,
+                      forcing=o.forcing, reserved=0)
 
 
 class Fim:

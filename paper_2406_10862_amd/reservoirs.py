@@ -78,7 +78,7 @@ class Well:
 
 @dataclass
 class Options:
-    tol_cnv: float = 1e-9
+    tol_cnv: float = 1e-6
     tol_mb: float = 1e-12
     tol_dp: float = 1e-7
     tol_ds: float = 1e-10
@@ -90,8 +90,12 @@ class Options:
     max_lin: int = 400
     restart: int = 30
     max_cuts: int = 8
-    precond: int = PREC_BJ
+    precond: int = PREC_CPR
     precision: int = FP64
+    amg_cycle: int = 2          # 1 = V-cycle, 2 = W-cycle
+    amg_sweeps: int = 1
+    graphs: int = 1             # replay Arnoldi steps as HIP graphs
+    forcing: int = 1            # Eisenstat-Walker forcing term (lin_rtol is the floor)
 
 
 @dataclass
