@@ -67,6 +67,46 @@ def cpu_baseline(res):
     }
 
 
+def spmv_only(reps):
+    """The dominant kernel alone on the 1.1M-cell Jacobian, next to a plain
+    device copy of known size (reads 160 MiB, writes 160 MiB) used to scale the
+    HBM counters of a profiler run."""
+    import torch
+
+    from paper_2406_10862_amd import fim, reservoirs as rv
+
+    torch.cuda.set_device(0)
+    res = rv.config_c2()
+    g = fim.Fim(res)
+    g.set_initial_state()
+    R, rowptr, colind, val = g.fim_assemble(10.0)
+    d = torch.device("cuda")
+    trp, tci, tv = (torch.from_numpy(a).to(d) for a in (rowptr, colind, val))
+    x = torch.randn(len(R), dtype=torch.float64, device=d)
+    y = torch.empty_like(x)
+    copy_bytes = 160 * 2 ** 20
+    src = torch.ones(copy_bytes // 8, dtype=torch.float64, device=d)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    t_spmv = t_copy = 0.0
+    for _ in range(reps):
+        ev[0].record(stream)
+        fim.fim_bsr_spmv(g.nrows, g.nb, trp, tci, tv, x, y)
+        ev[1].record(stream)
+        dst.copy_(src)
+        ev[2].record(stream)
+        torch.cuda.synchronize()
+        t_spmv += ev[0].elapsed_time(ev[1])
+        t_copy += ev[1].elapsed_time(ev[2])
+    nbytes = spmv_bytes(g.nnzb, g.nrows, g.nb)
+    print(json.dumps({"spmv_avg_us": 1e3 * t_spmv / reps, "spmv_bytes": nbytes,
+                      "spmv_GBs": nbytes / (t_spmv / reps * 1e-3) / 1e9,
+                      "copy_avg_us": 1e3 * t_copy / reps, "copy_bytes_read": copy_bytes,
+                      "copy_bytes_written": copy_bytes, "reps": reps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,11 +116,16 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cycle", type=int, default=2, choices=[1, 2], help="AMG cycle: 1 V, 2 W")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "spmv_c2_traffic.json"))
+    ap.add_argument("--spmv-only", type=int, default=0, metavar="REPS",
+                    help="time only the SpMV of the 1.1M-cell Jacobian (profiler counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(the sharding design is described in DESIGN.md)", file=sys.stderr)
         sys.exit(2)
+    if args.spmv_only:
+        spmv_only(args.spmv_only)
+        return
 
     import torch
 
