@@ -138,13 +138,17 @@ typedef struct {
  * remaining residual.  forcing != 0 replaces the fixed lin_rtol by the
  * Eisenstat-Walker forcing term (choice 2, gamma 0.9, alpha 2) between 1e-2
  * and lin_rtol.  graphs != 0 replays each Arnoldi step after its SpMV as a
- * captured HIP graph.  profile != 0 brackets every SpMV launch of fim_step
- * with HIP events and reports their summed duration in fim_step_report. */
+ * captured HIP graph.  amg_fused: the coarse part of the AMG cycle, from
+ * the first level with at most amg_fused cells and wells down, runs as a
+ * single-workgroup launch (0 = default 4096, negative = every phase
+ * launched separately; the result is the same bit for bit).  profile != 0
+ * brackets every SpMV launch of fim_step with HIP events and reports their
+ * summed duration in fim_step_report. */
 typedef struct {
     double tol_cnv, tol_mb, tol_dp, tol_ds, tol_well;
     double ds_max, dp_max, lin_rtol;
     int32_t max_newton, max_lin, restart, max_cuts;
-    int32_t precond, precision, profile, amg_cycle, amg_sweeps, graphs, forcing, reserved;
+    int32_t precond, precision, profile, amg_cycle, amg_sweeps, graphs, forcing, amg_fused;
 } fim_options;
 
 #define FIM_MAX_SUB 256

@@ -279,18 +279,23 @@ __global__ __launch_bounds__(1024) void k_dense_invert(int n, double *__restrict
     }
 }
 
-// x = Minv b, one wave per row
-__global__ __launch_bounds__(256) void k_dense_gemv(int n, const double *__restrict__ M,
-                                                    const double *__restrict__ b,
-                                                    double *__restrict__ x) {
-    const int row = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int lane = threadIdx.x & 63;
-    if (row >= n) return;
+// x[row] = (Minv b)[row] by the 64 lanes of one wave
+__device__ inline void dense_row(int n, const double *__restrict__ M, const double *b, double *x,
+                                 int row, int lane) {
     double s = 0.0;
     for (int c = lane; c < n; c += 64) s += M[(size_t)row * n + c] * b[c];
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
     if (lane == 0) x[row] = s;
+}
+
+// x = Minv b, one wave per row
+__global__ __launch_bounds__(256) void k_dense_gemv(int n, const double *__restrict__ M,
+                                                    const double *__restrict__ b,
+                                                    double *__restrict__ x) {
+    const int row = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (row >= n) return;
+    dense_row(n, M, b, x, row, threadIdx.x & 63);
 }
 
 // ---------------------------------------------------------------------------
@@ -311,19 +316,15 @@ __device__ inline double read_well(const AmgLevel &L, const AmgLevel &C, int mod
     return v;
 }
 
-// Gauss-Seidel update of every cell of one colour (cells of one colour are
-// not coupled to each other, so the sweep is exact and order-free).
-__global__ __launch_bounds__(kBlock) void k_amg_sweep(AmgLevel L, AmgLevel C, int color,
-                                                      int mode) {
-    const int h = blockIdx.x * blockDim.x + threadIdx.x;
-    if (h >= L.half) return;
+// Gauss-Seidel value of cell h of one colour (cells of one colour are not
+// coupled to each other, so a colour sweep is exact and order-free);
+// padded cells get 0.
+__device__ inline double sweep_value(const AmgLevel &L, const AmgLevel &C, int color, int mode,
+                                     int h) {
     const int s = color * L.half + h;
     int i, j, k;
     cell_of(L, s, i, j, k);
-    if (i >= L.nx) {
-        L.x[s] = 0.0;
-        return;
-    }
+    if (i >= L.nx) return 0.0;
     const int stride = 2 * L.half;
     double acc = L.b[s];
 #pragma unroll
@@ -336,7 +337,18 @@ __global__ __launch_bounds__(kBlock) void k_amg_sweep(AmgLevel L, AmgLevel C, in
         const int sl = L.cslot[q];
         acc -= L.acw[sl] * read_well(L, C, mode, L.swell[sl]);
     }
-    L.x[s] = acc / L.a[s];
+    return acc / L.a[s];
+}
+
+__device__ inline void sweep_item(const AmgLevel &L, const AmgLevel &C, int color, int mode,
+                                  int h) {
+    L.x[color * L.half + h] = sweep_value(L, C, color, mode, h);
+}
+
+__global__ __launch_bounds__(kBlock) void k_amg_sweep(AmgLevel L, AmgLevel C, int color,
+                                                      int mode) {
+    const int h = blockIdx.x * blockDim.x + threadIdx.x;
+    if (h < L.half) sweep_item(L, C, color, mode, h);
 }
 
 // wells: one wave per well, lanes stride over its slots
@@ -348,11 +360,14 @@ __device__ inline double well_row_sum(const AmgLevel &L, int w, int lane) {
     return acc;
 }
 
-__global__ __launch_bounds__(kBlock) void k_amg_well_sweep(AmgLevel L) {
-    const int w = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, lane = threadIdx.x & 63;
-    if (w >= L.nw) return;
+__device__ inline void well_sweep_item(const AmgLevel &L, int w, int lane) {
     const double sum = well_row_sum(L, w, lane);
     if (lane == 0) L.x[2 * L.half + w] = (L.b[2 * L.half + w] - sum) / L.aww[w];
+}
+
+__global__ __launch_bounds__(kBlock) void k_amg_well_sweep(AmgLevel L) {
+    const int w = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (w < L.nw) well_sweep_item(L, w, threadIdx.x & 63);
 }
 
 __device__ inline double cell_residual(const AmgLevel &L, int s, int i, int j, int k) {
@@ -371,52 +386,58 @@ __device__ inline double cell_residual(const AmgLevel &L, int s, int i, int j, i
     return r;
 }
 
-// fine residual r = b - A x of every cell (one thread per cell, coalesced
-// over the colour-split index) and of every well (one wave per well)
-__global__ __launch_bounds__(kBlock) void k_amg_residual(AmgLevel F) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    const int ncs = 2 * F.half;
-    const int cell_blocks = (ncs + kBlock - 1) / kBlock;
+// Restriction (R = P^T): the coarse right-hand side of a coarse cell is
+// the sum of the fine residuals r = b - A x over its 2x2x2 aggregate.  A
+// group of 8 lanes takes one coarse cell (natural index t): lane q computes
+// the residual of child (q & 1, (q >> 1) & 1, q >> 2) and the group's first
+// lane adds the existing children in that (k, j, i) order.  Every lane of
+// the wave must call it (shuffles); on = false marks lanes past the end.
+__device__ inline void restrict_group(const AmgLevel &F, const AmgLevel &C, int t, int q,
+                                      bool on) {
+    double r = 0.0;
+    int have = 0, I = 0, J = 0, K = 0;
+    if (on) {
+        I = t % C.nx;
+        J = (t / C.nx) % C.ny;
+        K = t / (C.nx * C.ny);
+        const int i = 2 * I + (q & 1), j = 2 * J + ((q >> 1) & 1), k = 2 * K + (q >> 2);
+        if (i < F.nx && j < F.ny && k < F.nz) {
+            r = cell_residual(F, split_of(F, i, j, k), i, j, k);
+            have = 1;
+        }
+    }
+    const int first = (threadIdx.x & 63) & ~7;
+    double sum = 0.0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const double rc = __shfl(r, first + c, 64);
+        if (__shfl(have, first + c, 64)) sum += rc;
+    }
+    if (on && q == 0) C.b[split_of(C, I, J, K)] = sum;
+}
+
+// a well is its own aggregate: its coarse right-hand side is its residual
+__device__ inline void restrict_well(const AmgLevel &F, const AmgLevel &C, int w, int lane) {
+    const int f = 2 * F.half + w;
+    const double sum = well_row_sum(F, w, lane);
+    if (lane == 0) C.b[2 * C.half + w] = F.b[f] - F.aww[w] * F.x[f] - sum;
+}
+
+// coarse cells (8 lanes each) then wells (one wave each)
+__global__ __launch_bounds__(kBlock) void k_amg_restrict(AmgLevel F, AmgLevel C) {
+    const long t8 = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long n8 = 8L * C.nx * C.ny * C.nz;
+    const int cell_blocks = (int)((n8 + kBlock - 1) / kBlock);
     if ((int)blockIdx.x < cell_blocks) {
-        if (t >= ncs) return;
-        int i, j, k;
-        cell_of(F, t, i, j, k);
-        F.r[t] = (i >= F.nx) ? 0.0 : cell_residual(F, t, i, j, k);
+        restrict_group(F, C, (int)(t8 >> 3), (int)(t8 & 7), t8 < n8);
     } else {
         const int w = (((int)blockIdx.x - cell_blocks) * kBlock + threadIdx.x) >> 6;
-        const int lane = threadIdx.x & 63;
-        if (w >= F.nw) return;
-        const double sum = well_row_sum(F, w, lane);
-        if (lane == 0)
-            F.r[ncs + w] = F.b[ncs + w] - F.aww[w] * F.x[ncs + w] - sum;
+        if (w < F.nw) restrict_well(F, C, w, threadIdx.x & 63);
     }
 }
 
-// coarse right-hand side = aggregate sums of the fine residual (R = P^T)
-__global__ __launch_bounds__(kBlock) void k_amg_aggregate(AmgLevel F, AmgLevel C) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    const int ncs = 2 * C.half;
-    if (t < ncs) {
-        int I, J, K;
-        cell_of(C, t, I, J, K);
-        if (I >= C.nx) return;
-        double sum = 0.0;
-        for (int dk = 0; dk < 2; ++dk)
-            for (int dj = 0; dj < 2; ++dj)
-                for (int di = 0; di < 2; ++di) {
-                    const int i = 2 * I + di, j = 2 * J + dj, k = 2 * K + dk;
-                    if (i >= F.nx || j >= F.ny || k >= F.nz) continue;
-                    sum += F.r[split_of(F, i, j, k)];
-                }
-        C.b[t] = sum;
-    } else if (t < ncs + C.nw) {
-        C.b[t] = F.r[2 * F.half + (t - ncs)];
-    }
-}
-
-// x_fine += P x_coarse
-__global__ __launch_bounds__(kBlock) void k_amg_correct(AmgLevel F, AmgLevel C) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+// x_fine += P x_coarse at fine entry t
+__device__ inline void correct_item(const AmgLevel &F, const AmgLevel &C, int t) {
     if (t < 2 * F.half) {
         int i, j, k;
         cell_of(F, t, i, j, k);
@@ -426,6 +447,99 @@ __global__ __launch_bounds__(kBlock) void k_amg_correct(AmgLevel F, AmgLevel C) 
         const int w = t - 2 * F.half;
         F.x[t] += C.x[2 * C.half + w];
     }
+}
+
+__global__ __launch_bounds__(kBlock) void k_amg_correct(AmgLevel F, AmgLevel C) {
+    correct_item(F, C, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// The coarse part of a cycle in one workgroup.  Below a few thousand cells
+// a level's kernels are pure launch latency, and a W-cycle visits the
+// coarse levels many times; here one workgroup walks the phase list the
+// host recorded for the sub-cycle rooted at P.lv[0] (the same phases, in
+// the same order, as the per-level launches, and the same per-entry
+// arithmetic, so the result is bitwise that of the launched cycle).
+// Iterates, right-hand sides and the well-slot structure of all its levels
+// live in LDS (offsets from the host, per level; the phase list last); the
+// root's right-hand side comes in from and its iterate goes back to HBM.
+// The stencil coefficients stay in HBM and the L2.  Phases are separated
+// by workgroup barriers.
+template <class T>
+__device__ inline void lds_copy(T *dst, const T *src, int n) {
+    for (int e = threadIdx.x; e < n; e += blockDim.x) dst[e] = src[e];
+}
+
+__global__ __launch_bounds__(kSubThreads) void k_amg_subcycle(AmgSub P) {
+    extern __shared__ double lds[];
+    int *ldi = reinterpret_cast<int *>(lds + P.ldoubles);
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int wave = tid >> 6, lane = tid & 63, nwaves = nt >> 6;
+    // padded entries of the coarse right-hand sides are never restricted
+    // to but are read by the dense solve: start from zeros as in HBM
+    for (int k = 0; k < P.nlev; ++k) {
+        const AmgLevel &L = P.lv[k];
+        const int n = 2 * L.half + L.nw;
+        for (int e = tid; e < n; e += nt) lds[P.off[k][kSubB] + e] = (k == 0) ? L.b[e] : 0.0;
+        lds_copy(lds + P.off[k][kSubAcw], L.acw, L.nslot);
+        lds_copy(lds + P.off[k][kSubAwc], L.awc, L.nslot);
+        lds_copy(ldi + P.off[k][kSubCps], L.cps, 2 * L.half + 1);
+        lds_copy(ldi + P.off[k][kSubCslot], L.cslot, L.nslot);
+        lds_copy(ldi + P.off[k][kSubSwell], L.swell, L.nslot);
+        lds_copy(ldi + P.off[k][kSubScell], L.scell, L.nslot);
+        lds_copy(ldi + P.off[k][kSubSps], L.sps, L.nw + 1);
+    }
+    int *ops = ldi + P.opsoff;
+    lds_copy(ops, P.ops, P.nops);
+    __syncthreads();
+    auto level = [&](int k) {
+        AmgLevel L = P.lv[k];
+        L.x = lds + P.off[k][kSubX];
+        L.b = lds + P.off[k][kSubB];
+        L.acw = lds + P.off[k][kSubAcw];
+        L.awc = lds + P.off[k][kSubAwc];
+        L.cps = ldi + P.off[k][kSubCps];
+        L.cslot = ldi + P.off[k][kSubCslot];
+        L.swell = ldi + P.off[k][kSubSwell];
+        L.scell = ldi + P.off[k][kSubScell];
+        L.sps = ldi + P.off[k][kSubSps];
+        return L;
+    };
+    for (int o = 0; o < P.nops; ++o) {
+        const int op = __builtin_amdgcn_readfirstlane(ops[o]);
+        const int kind = op & 15, l = (op >> 4) & 15;
+        const AmgLevel F = level(l);
+        if (kind == kOpSweep) {
+            const AmgLevel C = level(l + 1);
+            const int color = (op >> 8) & 1, mode = (op >> 12) & 15;
+            // two entries per thread at a time so their loads overlap
+            for (int h = tid; h < F.half; h += 2 * nt) {
+                const int h2 = h + nt;
+                const double v1 = sweep_value(F, C, color, mode, h);
+                const double v2 = (h2 < F.half) ? sweep_value(F, C, color, mode, h2) : 0.0;
+                F.x[color * F.half + h] = v1;
+                if (h2 < F.half) F.x[color * F.half + h2] = v2;
+            }
+        } else if (kind == kOpWells) {
+            for (int w = wave; w < F.nw; w += nwaves) well_sweep_item(F, w, lane);
+        } else if (kind == kOpRestrict) {
+            const AmgLevel C = level(l + 1);
+            const int n8 = 8 * C.nx * C.ny * C.nz;
+            for (int base = 0; base < n8; base += nt) {
+                const int t8 = base + tid;
+                restrict_group(F, C, t8 >> 3, t8 & 7, t8 < n8);
+            }
+            for (int w = wave; w < F.nw; w += nwaves) restrict_well(F, C, w, lane);
+        } else if (kind == kOpCorrect) {
+            const AmgLevel C = level(l + 1);
+            for (int t = tid; t < 2 * F.half + F.nw; t += nt) correct_item(F, C, t);
+        } else {
+            const int n = 2 * F.half + F.nw;
+            for (int row = wave; row < n; row += nwaves) dense_row(n, P.Minv, F.b, F.x, row, lane);
+        }
+        __syncthreads();
+    }
+    const AmgLevel &R = P.lv[0];
+    for (int e = tid; e < 2 * R.half + R.nw; e += nt) R.x[e] = lds[P.off[0][kSubX] + e];
 }
 
 // ---------------------------------------------------------------------------
@@ -550,11 +664,23 @@ void launch_amg_well_sweep(hipStream_t s, const AmgLevel &L) {
 }
 
 void launch_amg_restrict(hipStream_t s, const AmgLevel &F, const AmgLevel &C) {
-    const long cell_blocks = (2L * F.half + kBlock - 1) / kBlock;
+    const long cell_blocks = (8L * C.nx * C.ny * C.nz + kBlock - 1) / kBlock;
     const long well_blocks = (64L * F.nw + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL(k_amg_residual, dim3((unsigned)(cell_blocks + well_blocks)), dim3(kBlock), 0,
-                       s, F);
-    hipLaunchKernelGGL(k_amg_aggregate, grid_for(2L * C.half + C.nw, kBlock), dim3(kBlock), 0, s, F, C);
+    hipLaunchKernelGGL(k_amg_restrict, dim3((unsigned)(cell_blocks + well_blocks)), dim3(kBlock), 0,
+                       s, F, C);
+}
+
+size_t amg_subcycle_lds(const AmgSub &P) {
+    return (size_t)P.ldoubles * sizeof(double) + ((size_t)P.opsoff + P.nops) * sizeof(int);
+}
+
+hipError_t amg_subcycle_allow_lds(size_t bytes) {
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_amg_subcycle),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+void launch_amg_subcycle(hipStream_t s, const AmgSub &P) {
+    hipLaunchKernelGGL(k_amg_subcycle, dim3(1), dim3(kSubThreads), amg_subcycle_lds(P), s, P);
 }
 
 void launch_amg_correct(hipStream_t s, const AmgLevel &F, const AmgLevel &C) {

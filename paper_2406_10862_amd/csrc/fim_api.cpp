@@ -116,11 +116,13 @@ struct fim_ctx {
     std::vector<AmgLevel> lv;
     std::vector<const int *> cfs_ptr, cfs_idx;     // coarse slot -> fine slots, per level
     double *Mden = nullptr, *Minv = nullptr, *colk = nullptr, *wq = nullptr;
+    int sub_root = -1;                              // first level of the fused sub-cycle
+    int *sub_ops = nullptr;                         // [kSubOps] its phase list
+    AmgSub sub{};
     int *amg_bad = nullptr;
     int *split0 = nullptr;                          // natural cell -> level-0 split index
     int *reorth = nullptr;
     double *partials = nullptr, *scal = nullptr;
-    unsigned *counter = nullptr;
     double *pin = nullptr;        // pinned host: scalars, H columns, y
     size_t pin_len = 0;
     bool state_set = false, jac_ready = false, prec_ready = false;
@@ -214,6 +216,7 @@ static void check_options(const fim_options *o) {
     REQUIRE(o->graphs == 0 || o->graphs == 1, "graphs must be 0 or 1");
     REQUIRE(o->forcing == 0 || o->forcing == 1, "forcing must be 0 or 1");
     REQUIRE(o->precision == FIM_FP64, "unknown precision mode %d", o->precision);
+    REQUIRE(o->amg_fused <= (1 << 20), "amg_fused must be at most 2^20 cells");
 }
 
 static void build_pattern(fim_ctx *c, std::vector<int> &rp, std::vector<int> &ci,
@@ -299,10 +302,8 @@ static void build_amg(fim_ctx *c, const std::vector<int> &sorted_cells,
         L.awc = c->alloc<double>(std::max(L.nslot, 1));
         L.x = c->alloc<double>(ncs + nw);
         L.b = c->alloc<double>(ncs + nw);
-        L.r = c->alloc<double>(ncs + nw);
         launch_scale_copy(c->s, ncs + nw, nullptr, 0.0, L.x);
         launch_scale_copy(c->s, ncs + nw, nullptr, 0.0, L.b);
-        launch_scale_copy(c->s, ncs + nw, nullptr, 0.0, L.r);
         if (c->lv.empty()) {
             std::vector<int> sp(c->n);
             for (int cn = 0; cn < c->n; ++cn) sp[cn] = split(cn);
@@ -364,6 +365,8 @@ static void build_amg(fim_ctx *c, const std::vector<int> &sorted_cells,
     c->amg_bad = c->alloc<int>(1);
     c->wq = c->alloc<double>((size_t)c->n * c->nb);
 }
+
+static void build_subcycle(fim_ctx *c);
 
 static int create_impl(const fim_grid *grid, const fim_rock *rock, const fim_fluid *fl,
                        int32_t nwells, const fim_well *wells, const fim_options *opt,
@@ -584,11 +587,10 @@ static int create_impl(const fim_grid *grid, const fim_rock *rock, const fim_flu
         c->reorth = c->alloc<int>(1);
         alloc_krylov(c, opt->restart);
         build_amg(c, sorted_cells, pwell_h);
+        build_subcycle(c);
         const size_t np = (size_t)(kMaxRestart + 2) * 2048 + (size_t)2048 * 16;
         c->partials = c->alloc<double>(np);
         c->scal = c->alloc<double>(S_COUNT);
-        c->counter = c->alloc<unsigned>(1);
-        HIPCHECK(hipMemsetAsync(c->counter, 0, sizeof(unsigned), c->s));
         HIPCHECK(hipMemsetAsync(c->reorth, 0, sizeof(int), c->s));
         c->pin_len = S_COUNT + (size_t)(kMaxRestart + 1) * (kMaxRestart + 2) + kMaxRestart + 2;
         HIPCHECK(hipHostMalloc((void **)&c->pin, c->pin_len * sizeof(double), hipHostMallocDefault));
@@ -654,31 +656,115 @@ static void restore_state(fim_ctx *c, int slot) {
 // result in lv[l].x): red-black Gauss-Seidel with zero initial guess,
 // coarse-grid correction(s), then smoothing that applies the pending
 // correction while it reads.
-static void amg_cycle(fim_ctx *c, int l) {
+// One AMG cycle from level l down (paper Sec. 5.1: the pressure stage of
+// CPR).  With rec == nullptr the phases are launched, and the sub-cycle
+// rooted at c->sub_root runs as one fused launch; otherwise the phases are
+// recorded into *rec with levels relative to root.
+static void amg_cycle(fim_ctx *c, int l, std::vector<int> *rec = nullptr, int root = 0) {
     const int L = (int)c->lv.size();
+    if (!rec && l == c->sub_root) {
+        launch_amg_subcycle(c->s, c->sub);
+        HIPCHECK(hipGetLastError());           // e.g. an LDS request the device refuses
+        return;
+    }
+    const int rl = l - root;
     if (l == L - 1) {
-        launch_amg_coarsest_solve(c->s, c->lv[l], c->Minv);
+        if (rec) rec->push_back(amg_op(kOpCoarse, rl));
+        else launch_amg_coarsest_solve(c->s, c->lv[l], c->Minv);
         return;
     }
     const AmgLevel &F = c->lv[l], &C = c->lv[l + 1];
     const int nu = c->opt.amg_sweeps > 0 ? c->opt.amg_sweeps : 1;
     int gamma = (c->opt.amg_cycle == 1) ? 1 : 2;
     if (l + 1 == L - 1) gamma = 1;             // the coarsest level is solved exactly
+    auto sweep = [&](int color, int mode) {
+        if (rec) rec->push_back(amg_op(kOpSweep, rl, color, mode));
+        else launch_amg_sweep(c->s, F, C, color, mode);
+    };
+    auto wells = [&] {
+        if (F.nw == 0) return;
+        if (rec) rec->push_back(amg_op(kOpWells, rl));
+        else launch_amg_well_sweep(c->s, F);
+    };
     for (int sw = 0; sw < nu; ++sw) {
-        launch_amg_sweep(c->s, F, C, 0, sw == 0 ? (kCellsZero | kWellsZero) : 0);
-        launch_amg_sweep(c->s, F, C, 1, sw == 0 ? kWellsZero : 0);
-        launch_amg_well_sweep(c->s, F);
+        sweep(0, sw == 0 ? (kCellsZero | kWellsZero) : 0);
+        sweep(1, sw == 0 ? kWellsZero : 0);
+        wells();
     }
     for (int gv = 0; gv < gamma; ++gv) {
-        if (gv > 0) launch_amg_correct(c->s, F, C);
-        launch_amg_restrict(c->s, F, C);
-        amg_cycle(c, l + 1);
+        if (rec) {
+            if (gv > 0) rec->push_back(amg_op(kOpCorrect, rl));
+            rec->push_back(amg_op(kOpRestrict, rl));
+        } else {
+            if (gv > 0) launch_amg_correct(c->s, F, C);
+            launch_amg_restrict(c->s, F, C);
+        }
+        amg_cycle(c, l + 1, rec, root);
     }
     for (int sw = 0; sw < nu; ++sw) {
-        launch_amg_sweep(c->s, F, C, 0, sw == 0 ? (kCellsCorr | kWellsCorr) : 0);
-        launch_amg_sweep(c->s, F, C, 1, sw == 0 ? kWellsCorr : 0);
-        launch_amg_well_sweep(c->s, F);
+        sweep(0, sw == 0 ? (kCellsCorr | kWellsCorr) : 0);
+        sweep(1, sw == 0 ? kWellsCorr : 0);
+        wells();
     }
+}
+
+// Choose the root of the fused sub-cycle (the first level with at most
+// amg_fused cells and wells) and record its phase list; a sub-cycle whose
+// levels or phase list do not fit (kSubLevels, kSubOps, the LDS of one
+// workgroup) moves the root one level coarser.
+static void build_subcycle(fim_ctx *c) {
+    c->sub_root = -1;
+    const int L = (int)c->lv.size();
+    if (L == 0 || c->opt.amg_fused < 0) return;
+    const long limit = c->opt.amg_fused > 0 ? c->opt.amg_fused : kFusedCellsDefault;
+    int root = 0;
+    while (root < L && 2L * c->lv[root].half + c->lv[root].nw > limit) ++root;
+    int dev = 0, lds_max = 0;
+    HIPCHECK(hipGetDevice(&dev));
+    HIPCHECK(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    std::vector<int> ops;
+    AmgSub sub{};
+    for (; root < L; ++root) {
+        if (L - root > kSubLevels) continue;
+        ops.clear();
+        amg_cycle(c, root, &ops, root);
+        if ((int)ops.size() > kSubOps) continue;
+        sub = AmgSub{};
+        sub.nlev = L - root;
+        long nd = 0, ni = 0;
+        for (int k = 0; k <= sub.nlev; ++k) {
+            // the entry past the coarsest is never dereferenced
+            const AmgLevel &Lk = (k < sub.nlev) ? c->lv[root + k] : AmgLevel{};
+            if (k < sub.nlev) sub.lv[k] = Lk;
+            const long n = 2L * Lk.half + Lk.nw;
+            int *o = sub.off[k];
+            o[kSubX] = (int)nd;
+            o[kSubB] = (int)(nd + n);
+            o[kSubAcw] = (int)(nd + 2 * n);
+            o[kSubAwc] = (int)(nd + 2 * n + Lk.nslot);
+            nd += 2 * n + 2L * Lk.nslot;
+            o[kSubCps] = (int)ni;
+            o[kSubCslot] = (int)(ni + 2L * Lk.half + 1);
+            o[kSubSwell] = o[kSubCslot] + Lk.nslot;
+            o[kSubScell] = o[kSubSwell] + Lk.nslot;
+            o[kSubSps] = o[kSubScell] + Lk.nslot;
+            ni += 2L * Lk.half + 1 + 3L * Lk.nslot + Lk.nw + 1;
+        }
+        sub.ldoubles = (int)nd;
+        sub.opsoff = (int)ni;
+        sub.nops = (int)ops.size();
+        if (amg_subcycle_lds(sub) <= (size_t)lds_max) break;
+    }
+    if (root >= L) return;
+    if (!c->sub_ops) c->sub_ops = c->alloc<int>(kSubOps);
+    HIPCHECK(hipMemcpyAsync(c->sub_ops, ops.data(), ops.size() * sizeof(int),
+                            hipMemcpyHostToDevice, c->s));
+    c->sync();
+    HIPCHECK(amg_subcycle_allow_lds(amg_subcycle_lds(sub)));
+    sub.ops = c->sub_ops;
+    sub.Minv = c->Minv;
+    c->sub = sub;
+    c->sub_root = root;
 }
 
 static void prec_setup(fim_ctx *c) {
@@ -756,11 +842,11 @@ static void arnoldi_rest(fim_ctx *c, int j) {
     const int LD = kMaxRestart + 2;
     double *col = c->H + (size_t)j * LD;
     double *pinH = c->pin + S_COUNT;
-    launch_multidot(c->s, nv, j + 1, c->V, c->w, c->partials, c->counter, col, nullptr);
-    launch_update_norm(c->s, nv, j + 1, c->V, col, c->w, c->partials, c->counter, col + j + 1,
+    launch_multidot(c->s, nv, j + 1, c->V, c->w, c->partials, col, nullptr);
+    launch_update_norm(c->s, nv, j + 1, c->V, col, c->w, c->partials, col + j + 1,
                        nullptr, c->reorth, nullptr);
-    launch_multidot(c->s, nv, j + 1, c->V, c->w, c->partials, c->counter, c->tmp, c->reorth);
-    launch_update_norm(c->s, nv, j + 1, c->V, c->tmp, c->w, c->partials, c->counter, col + j + 1,
+    launch_multidot(c->s, nv, j + 1, c->V, c->w, c->partials, c->tmp, c->reorth);
+    launch_update_norm(c->s, nv, j + 1, c->V, c->tmp, c->w, c->partials, col + j + 1,
                        c->reorth, nullptr, col);
     precondition(c, c->w, col + j + 1, c->V + (size_t)(j + 1) * nv, c->Z + (size_t)(j + 1) * nv);
     HIPCHECK(hipMemcpyAsync(pinH + (size_t)j * LD, col, (j + 2) * sizeof(double),
@@ -815,7 +901,7 @@ static int gmres(fim_ctx *c, const double *bvec, double *xvec, int max_it, doubl
     const double *pinH = c->pin + S_COUNT;    // pinned copies of the columns
     double *piny = c->pin + S_COUNT + (size_t)(kMaxRestart + 1) * LD;
     launch_scale_copy(c->s, nv, nullptr, 0.0, xvec);
-    launch_norm2(c->s, nv, bvec, c->partials, c->counter, c->scal + S_NORM);
+    launch_norm2(c->s, nv, bvec, c->partials, c->scal + S_NORM);
     d2h_scalars(c, S_NORM, 2);
     c->sync();
     const double bnorm = c->pin[S_NORM + 1];
@@ -882,7 +968,7 @@ static int gmres(fim_ctx *c, const double *bvec, double *xvec, int max_it, doubl
             HIPCHECK(hipMemcpyAsync(c->ydev, piny, k * sizeof(double), hipMemcpyHostToDevice, c->s));
             launch_axpy_multi(c->s, nv, k, c->Z, c->ydev, xvec);
             solver_spmv(c, xvec, c->t, profile);
-            launch_residual(c->s, nv, bvec, c->t, c->r, c->partials, c->counter, c->scal + S_RES);
+            launch_residual(c->s, nv, bvec, c->t, c->r, c->partials, c->scal + S_RES);
             d2h_scalars(c, S_RES, 2);
             c->sync();
             beta = c->pin[S_RES + 1];
@@ -937,7 +1023,7 @@ static bool newton(fim_ctx *c, double dt, NewtonStats &st) {
         props(c, it == 0);
         assemble(c, dt);
         launch_conv(c->s, nb, c->n, c->nw, c->rec, c->R, c->wmeas, dt, c->partials,
-                    conv_blocks(c->n), c->counter, c->scal + S_CONV);
+                    conv_blocks(c->n), c->scal + S_CONV);
         HIPCHECK(hipEventRecord(c->ev[1], c->s));
         d2h_scalars(c, S_CONV, S_NORM - S_CONV);
         c->sync();
@@ -985,7 +1071,7 @@ static bool newton(fim_ctx *c, double dt, NewtonStats &st) {
         if (gs != 0 && !(std::isfinite(rr) && rr < 1.0)) return false;
         launch_newton_update(c->s, nb, c->phys, c->n, c->nw, c->x, o.ds_max, o.dp_max, c->P,
                              c->Sw, c->X, c->flag, c->pbhp, c->partials, update_blocks(c->n),
-                             c->counter, c->scal + S_UPD);
+                             c->scal + S_UPD);
         HIPCHECK(hipEventRecord(c->ev[3], c->s));
         pending_update = true;
     }
@@ -1141,6 +1227,7 @@ int fim_set_options(fim_ctx *c, const fim_options *opt) {
             c->m = opt->restart;
         }
         c->opt = *opt;
+        build_subcycle(c);
         return FIM_OK;
     });
 }

@@ -82,7 +82,7 @@ struct AmgLevel {
     double *acw, *awc;      // [nslot] cell->well and well->cell couplings
     const int *cps;         // [2*half+1] split cell -> range in cslot
     const int *cslot;       // slot ids of each cell
-    double *x, *b, *r;      // [2*half + nw]: iterate, right-hand side, residual
+    double *x, *b;          // [2*half + nw]: iterate, right-hand side
 };
 
 // ---- physics kernels (fim_phys.hip) ---------------------------------------
@@ -102,11 +102,11 @@ void launch_assemble(hipStream_t s, int nb, Grid g, Phys f, Wells w, Sys sys,
                      double dt, double *wmeas);
 void launch_conv(hipStream_t s, int nb, int n, int nw, const double *rec, const double *R,
                  const double *wmeas, double dt, double *partials, int nparts_blocks,
-                 unsigned *counter, double *out);
+                 double *out);
 void launch_newton_update(hipStream_t s, int nb, Phys f, int n, int nw, const double *y,
                           double ds_max, double dp_max, double *P, double *Sw, double *X,
                           int8_t *flag, double *pbhp, double *partials, int nblocks,
-                          unsigned *counter, double *out);
+                          double *out);
 void launch_well_rates(hipStream_t s, int nb, Wells w, const double *P, const double *pbhp,
                        const double *rec, int n, double *q);
 int conv_blocks(int n);
@@ -121,19 +121,16 @@ void launch_bj_apply(hipStream_t s, int nb, int nrows, const double *dinv, const
                      double *y);
 // partial-sum helpers shared by the Krylov kernels
 int vec_blocks(long nvec);
-void launch_norm2(hipStream_t s, long nvec, const double *x, double *partials,
-                  unsigned *counter, double *out);
+void launch_norm2(hipStream_t s, long nvec, const double *x, double *partials, double *out);
 void launch_normalize_precond(hipStream_t s, int nb, int nrows, const double *w,
                               const double *hptr, double *v, double *z, const double *dinv);
 void launch_multidot(hipStream_t s, long nvec, int nv, const double *V, const double *w,
-                     double *partials, unsigned *counter, double *dst, const int *gate);
+                     double *partials, double *dst, const int *gate);
 void launch_update_norm(hipStream_t s, long nvec, int nv, const double *V, const double *coef,
-                        double *w, double *partials, unsigned *counter, double *hnext,
-                        const int *gate, int *reorth, double *hacc);
-void launch_final_update(hipStream_t s, int nb, int nrows, int k, const double *V,
-                         const double *y, const double *dinv, double *x);
+                        double *w, double *partials, double *hnext, const int *gate,
+                        int *reorth, double *hacc);
 void launch_residual(hipStream_t s, long nvec, const double *b, const double *Ax, double *r,
-                     double *partials, unsigned *counter, double *out);
+                     double *partials, double *out);
 void launch_scale_copy(hipStream_t s, long nvec, const double *x, double a, double *y);
 void launch_axpy_multi(hipStream_t s, long nvec, int k, const double *Z, const double *y,
                        double *x);
@@ -158,5 +155,37 @@ void launch_cpr_finish(hipStream_t s, int nb, int n, int nw, const AmgLevel &L,
                        const int *split0, Sys sys, const double *v, const double *dinv,
                        double *z);
 enum { kCellsZero = 1, kCellsCorr = 2, kWellsZero = 4, kWellsCorr = 8 };
+
+// A cycle is a sequence of phases on levels: colour sweeps, well sweeps,
+// restrictions, corrections and the dense coarsest solve.  The
+// coarse part of it can run as one workgroup walking a recorded phase list
+// (op = kind | level << 4 | colour << 8 | mode << 12, levels relative to the
+// sub-cycle's root).
+enum { kOpSweep = 0, kOpWells = 1, kOpRestrict = 2, kOpCorrect = 3, kOpCoarse = 4 };
+constexpr int kSubLevels = 8;          // levels one sub-cycle can span
+constexpr int kSubOps = 4096;          // phase-list capacity
+constexpr int kSubThreads = 1024;
+constexpr int kFusedCellsDefault = 4096;
+inline int amg_op(int kind, int level, int color = 0, int mode = 0) {
+    return kind | level << 4 | color << 8 | mode << 12;
+}
+// LDS arrays of one sub-cycle level: doubles (x, b, acw, awc) are offsets
+// from the LDS base, ints (cps, cslot, swell, scell, sps) from the end of
+// the doubles.
+enum { kSubX, kSubB, kSubAcw, kSubAwc, kSubCps, kSubCslot, kSubSwell, kSubScell, kSubSps,
+       kSubArrays };
+struct AmgSub {
+    AmgLevel lv[kSubLevels + 1];       // root first; entries past the coarsest stay empty
+    int off[kSubLevels + 1][kSubArrays];
+    int nlev;                          // levels from the root to the coarsest
+    int ldoubles;                      // LDS doubles before the int arrays
+    int opsoff;                        // phase list offset among the ints
+    const int *ops;
+    int nops;
+    const double *Minv;                // dense inverse of the coarsest level
+};
+size_t amg_subcycle_lds(const AmgSub &P);          // dynamic LDS bytes of one launch
+hipError_t amg_subcycle_allow_lds(size_t bytes);
+void launch_amg_subcycle(hipStream_t s, const AmgSub &P);
 
 }  // namespace fim

@@ -210,18 +210,30 @@ void launch_bj_apply(hipStream_t s, int nb, int nrows, const double *dinv, const
 }
 
 // ---------------------------------------------------------------------------
-// Krylov vector kernels.  Grids are capped so the last-block reductions stay
-// short; every thread walks the vector with a grid stride.
+// Krylov vector kernels.  Grids are capped at 2048 blocks (8 per CU) so the
+// per-block partials of a reduction stay few; every thread walks the vector
+// with a grid stride.
 
 int vec_blocks(long nvec) {
     long b = (nvec + kBlock - 1) / kBlock;
     return (int)(b < 2048 ? (b > 0 ? b : 1) : 2048);
 }
 
+// out[0] = sum of the partials, out[1] = its square root (a norm finish)
+__global__ __launch_bounds__(kBlock) void k_finish_norm(int nparts, const double *partials,
+                                                        double *out) {
+    const bool mx[1] = {false};
+    double a[1];
+    finish_partials<1>(nparts, mx, partials, a);
+    if (threadIdx.x == 0) {
+        out[0] = a[0];
+        out[1] = sqrt(a[0]);
+    }
+}
+
 // out[0] = ||x||^2, out[1] = ||x||
 __global__ __launch_bounds__(kBlock) void k_norm2(long nvec, const double *__restrict__ x,
-                                                  double *partials, unsigned *counter,
-                                                  double *out) {
+                                                  double *partials) {
     double v[1] = {0.0};
     const bool mx[1] = {false};
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < nvec;
@@ -229,13 +241,13 @@ __global__ __launch_bounds__(kBlock) void k_norm2(long nvec, const double *__res
         const double a = x[i];
         v[0] += a * a;
     }
-    if (grid_reduce<1>(v, mx, partials, counter, out) && threadIdx.x == 0) out[1] = sqrt(out[0]);
+    block_partials<1>(v, mx, partials);
 }
 
-void launch_norm2(hipStream_t s, long nvec, const double *x, double *partials, unsigned *counter,
-                  double *out) {
-    hipLaunchKernelGGL(k_norm2, dim3(vec_blocks(nvec)), dim3(kBlock), 0, s, nvec, x, partials,
-                       counter, out);
+void launch_norm2(hipStream_t s, long nvec, const double *x, double *partials, double *out) {
+    const int nblk = vec_blocks(nvec);
+    hipLaunchKernelGGL(k_norm2, dim3(nblk), dim3(kBlock), 0, s, nvec, x, partials);
+    hipLaunchKernelGGL(k_finish_norm, dim3(1), dim3(kBlock), 0, s, nblk, partials, out);
 }
 
 // v = w / h and z = M^-1 v (block Jacobi), one block row per thread.  h is
@@ -272,199 +284,140 @@ void launch_normalize_precond(hipStream_t s, int nb, int nrows, const double *w,
         hipLaunchKernelGGL(k_normalize_precond<3>, grid, block, 0, s, nrows, w, hptr, v, z, dinv);
 }
 
-// Reductions of several sums at once.  Slots i < k and the last slot
-// (kMaxDots-1) are active; loops are fully unrolled with guards so the
-// per-thread values stay in registers.  Result in thread 0.
-__device__ inline bool slot_on(int i, int k) { return i < k || i == kMaxDots - 1; }
+// dst[i] = <V_i, w> for i < nv, dst[nv] = <w, w>, in two kernels.  The
+// first runs a (column-block x vector-group) grid: each block accumulates
+// kDotGroup dot products over its share of the rows (w is re-read once per
+// group from cache) and writes one partial per product; the second sums the
+// partials of each product in block order with one workgroup per product.
+// Both are skipped when *gate == 0.
+constexpr int kDotGroup = 8;
+constexpr int kDotCols = 2048;
 
-__device__ inline void block_reduce_many(double (&v)[kMaxDots], int k,
-                                         double (&sh)[kMaxDots][kWaves]) {
+__global__ __launch_bounds__(kBlock) void k_multidot_part(long nvec, int nv,
+                                                          const double *__restrict__ V,
+                                                          const double *__restrict__ w,
+                                                          double *__restrict__ partials,
+                                                          const int *gate) {
+    if (gate && *gate == 0) return;
+    const int g0 = blockIdx.y * kDotGroup;
+    double acc[kDotGroup + 1];
+#pragma unroll
+    for (int i = 0; i <= kDotGroup; ++i) acc[i] = 0.0;
+    const bool self = blockIdx.y == 0;            // the first group also forms <w, w>
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < nvec;
+         e += (long)gridDim.x * blockDim.x) {
+        const double we = w[e];
+#pragma unroll
+        for (int i = 0; i < kDotGroup; ++i)
+            if (g0 + i < nv) acc[i] += __builtin_nontemporal_load(V + (size_t)(g0 + i) * nvec + e) * we;
+        if (self) acc[kDotGroup] += we * we;
+    }
+    __shared__ double sh[kDotGroup + 1][kWaves];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
-    for (int i = 0; i < kMaxDots; ++i) {
-        if (!slot_on(i, k)) continue;
-        double a = v[i];
+    for (int i = 0; i <= kDotGroup; ++i) {
+        double a = acc[i];
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) a += __shfl_xor(a, off, 64);
         if (lane == 0) sh[i][wid] = a;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int i = 0; i < kMaxDots; ++i) {
-            if (!slot_on(i, k)) continue;
-            double a = sh[i][0];
-            for (int w = 1; w < kWaves; ++w) a += sh[i][w];
-            v[i] = a;
-        }
+    if (threadIdx.x <= kDotGroup) {
+        const int i = threadIdx.x;
+        double a = sh[i][0];
+        for (int w2 = 1; w2 < kWaves; ++w2) a += sh[i][w2];
+        const int slot = (i < kDotGroup) ? g0 + i : nv;
+        if ((i < kDotGroup && slot < nv) || (i == kDotGroup && self))
+            partials[(size_t)slot * gridDim.x + blockIdx.x] = a;
     }
-    __syncthreads();
 }
 
-// Grid reduction; partials laid out [slot][block] so the last block reads
-// them with all its threads.  out[i] for i < k, out[k] = last slot.  True
-// in the last block.
-__device__ inline bool grid_reduce_many(double (&v)[kMaxDots], int k, double *partials,
-                                        unsigned *counter, double *out) {
-    __shared__ double sh[kMaxDots][kWaves];
-    __shared__ int is_last;
-    block_reduce_many(v, k, sh);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int i = 0; i < kMaxDots; ++i)
-            if (slot_on(i, k)) partials[(size_t)i * gridDim.x + blockIdx.x] = v[i];
-        __threadfence();
-        is_last = (atomicAdd(counter, 1u) == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (!is_last) return false;
-    __threadfence();
-#pragma unroll
-    for (int i = 0; i < kMaxDots; ++i) {
-        v[i] = 0.0;
-        if (slot_on(i, k))
-            for (unsigned b = threadIdx.x; b < gridDim.x; b += blockDim.x)
-                v[i] += partials[(size_t)i * gridDim.x + b];
-    }
-    block_reduce_many(v, k, sh);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int i = 0; i < kMaxDots - 1; ++i)
-            if (i < k) out[i] = v[i];
-        out[k] = v[kMaxDots - 1];
-        atomicExch(counter, 0u);
-    }
-    return true;
-}
-
-// dst[i] = <V_i, w> for i < nv, dst[nv] = <w, w>.  Skipped when *gate == 0.
-__global__ __launch_bounds__(kBlock) void k_multidot(long nvec, int nv, const double *__restrict__ V,
-                                                     const double *__restrict__ w,
-                                                     double *partials, unsigned *counter,
-                                                     double *dst, const int *gate) {
+__global__ __launch_bounds__(kBlock) void k_multidot_sum(int ncols, const double *__restrict__ partials,
+                                                         double *__restrict__ dst, const int *gate) {
     if (gate && *gate == 0) return;
-    double acc[kMaxDots];
+    const int slot = blockIdx.x;
+    double a = 0.0;
+    for (int b = threadIdx.x; b < ncols; b += blockDim.x) a += partials[(size_t)slot * ncols + b];
+    __shared__ double sh[kWaves];
 #pragma unroll
-    for (int i = 0; i < kMaxDots; ++i) acc[i] = 0.0;
-    // two independent elements per step keep twice the loads in flight
-    const long gs = (long)gridDim.x * blockDim.x;
-    long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    for (; e + gs < nvec; e += 2 * gs) {
-        const double w0 = w[e], w1 = w[e + gs];
-#pragma unroll
-        for (int i = 0; i < kMaxDots - 1; ++i)
-            if (i < nv) {
-                const double *vi = V + (size_t)i * nvec;
-                acc[i] += __builtin_nontemporal_load(vi + e) * w0 +
-                          __builtin_nontemporal_load(vi + e + gs) * w1;
-            }
-        acc[kMaxDots - 1] += w0 * w0 + w1 * w1;
+    for (int off = 32; off >= 1; off >>= 1) a += __shfl_xor(a, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = sh[0];
+        for (int w2 = 1; w2 < kWaves; ++w2) t += sh[w2];
+        dst[slot] = t;
     }
-    if (e < nvec) {
-        const double we = w[e];
-#pragma unroll
-        for (int i = 0; i < kMaxDots - 1; ++i)
-            if (i < nv) acc[i] += __builtin_nontemporal_load(V + (size_t)i * nvec + e) * we;
-        acc[kMaxDots - 1] += we * we;
-    }
-    grid_reduce_many(acc, nv, partials, counter, dst);
 }
 
 void launch_multidot(hipStream_t s, long nvec, int nv, const double *V, const double *w,
-                     double *partials, unsigned *counter, double *dst, const int *gate) {
-    hipLaunchKernelGGL(k_multidot, dim3(vec_blocks(nvec)), dim3(kBlock), 0, s, nvec, nv, V, w,
-                       partials, counter, dst, gate);
+                     double *partials, double *dst, const int *gate) {
+    long cols = (nvec + kBlock - 1) / kBlock;
+    cols = cols < kDotCols ? (cols > 0 ? cols : 1) : kDotCols;
+    const int groups = (nv + kDotGroup - 1) / kDotGroup > 0 ? (nv + kDotGroup - 1) / kDotGroup : 1;
+    hipLaunchKernelGGL(k_multidot_part, dim3((unsigned)cols, groups), dim3(kBlock), 0, s, nvec, nv,
+                       V, w, partials, gate);
+    hipLaunchKernelGGL(k_multidot_sum, dim3(nv + 1), dim3(kBlock), 0, s, (int)cols, partials, dst,
+                       gate);
 }
 
-// w -= sum_{i<nv} coef[i] V_i, then ||w||.  In the last block: when hacc is
-// set (second Gram-Schmidt pass) hacc[i] += coef[i]; hnext = ||w||; when
-// reorth is set (first pass) it becomes 1 if the norm dropped below
-// ||w_before|| / sqrt(2) = sqrt(coef[nv] / 2) (the DGKS test).
+// w -= sum_{i<nv} coef[i] V_i and the partials of ||w||^2.  The finishing
+// kernel then sets hnext = ||w||; when hacc is set (second Gram-Schmidt
+// pass) hacc[i] += coef[i]; when reorth is set (first pass) it becomes 1 if
+// the norm dropped below a tenth of ||w_before|| = sqrt(coef[nv]) (a
+// DGKS-type test for severe cancellation).  Both are skipped when
+// *gate == 0.
 __global__ __launch_bounds__(kBlock) void k_update_norm(long nvec, int nv,
                                                         const double *__restrict__ V,
                                                         const double *coef, double *w,
-                                                        double *partials, unsigned *counter,
-                                                        double *hnext, const int *gate,
-                                                        int *reorth, double *hacc) {
+                                                        double *partials, const int *gate) {
     if (gate && *gate == 0) return;
     __shared__ double c[kMaxDots];
     for (int i = threadIdx.x; i <= nv; i += blockDim.x) c[i] = coef[i];
     __syncthreads();
     double v[1] = {0.0};
     const bool mx[1] = {false};
-    const long gs = (long)gridDim.x * blockDim.x;
-    long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    for (; e + gs < nvec; e += 2 * gs) {
-        double a0 = w[e], a1 = w[e + gs];
-#pragma unroll 4
-        for (int i = 0; i < nv; ++i) {
-            const double *vi = V + (size_t)i * nvec;
-            a0 -= c[i] * __builtin_nontemporal_load(vi + e);
-            a1 -= c[i] * __builtin_nontemporal_load(vi + e + gs);
-        }
-        w[e] = a0;
-        w[e + gs] = a1;
-        v[0] += a0 * a0 + a1 * a1;
-    }
-    if (e < nvec) {
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < nvec;
+         e += (long)gridDim.x * blockDim.x) {
         double a = w[e];
+#pragma unroll 8
         for (int i = 0; i < nv; ++i) a -= c[i] * __builtin_nontemporal_load(V + (size_t)i * nvec + e);
         w[e] = a;
         v[0] += a * a;
     }
-    double out[1];
-    if (grid_reduce<1>(v, mx, partials, counter, out) && threadIdx.x == 0) {
-        const double before = c[nv];
+    block_partials<1>(v, mx, partials);
+}
+
+__global__ __launch_bounds__(kBlock) void k_update_finish(int nparts, int nv, const double *coef,
+                                                          const double *partials, double *hnext,
+                                                          const int *gate, int *reorth,
+                                                          double *hacc) {
+    if (gate && *gate == 0) return;
+    const bool mx[1] = {false};
+    double a[1];
+    finish_partials<1>(nparts, mx, partials, a);
+    if (threadIdx.x == 0) {
         if (hacc)
-            for (int i = 0; i < nv; ++i) hacc[i] += c[i];
-        if (reorth) *reorth = (out[0] < 0.5 * before) ? 1 : 0;
-        *hnext = sqrt(out[0]);
+            for (int i = 0; i < nv; ++i) hacc[i] += coef[i];
+        if (reorth) *reorth = (a[0] < 1e-2 * coef[nv]) ? 1 : 0;
+        *hnext = sqrt(a[0]);
     }
 }
 
 void launch_update_norm(hipStream_t s, long nvec, int nv, const double *V, const double *coef,
-                        double *w, double *partials, unsigned *counter, double *hnext,
-                        const int *gate, int *reorth, double *hacc) {
-    hipLaunchKernelGGL(k_update_norm, dim3(vec_blocks(nvec)), dim3(kBlock), 0, s, nvec, nv, V,
-                       coef, w, partials, counter, hnext, gate, reorth, hacc);
-}
-
-// x += M^-1 (sum_{i<k} y_i V_i)
-template <int NB>
-__global__ __launch_bounds__(kBlock) void k_final_update(int nrows, int k,
-                                                         const double *__restrict__ V,
-                                                         const double *__restrict__ y,
-                                                         const double *__restrict__ dinv,
-                                                         double *__restrict__ x) {
-    __shared__ double ys[kMaxRestart];
-    for (int i = threadIdx.x; i < k; i += blockDim.x) ys[i] = y[i];
-    __syncthreads();
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nrows) return;
-    const size_t nvec = (size_t)nrows * NB;
-    double u[NB], z[NB];
-#pragma unroll
-    for (int e = 0; e < NB; ++e) u[e] = 0.0;
-    for (int i = 0; i < k; ++i)
-#pragma unroll
-        for (int e = 0; e < NB; ++e) u[e] += ys[i] * V[i * nvec + (size_t)r * NB + e];
-    apply_block<NB>(dinv, r, u, z);
-#pragma unroll
-    for (int e = 0; e < NB; ++e) x[(size_t)r * NB + e] += z[e];
-}
-
-void launch_final_update(hipStream_t s, int nb, int nrows, int k, const double *V,
-                         const double *y, const double *dinv, double *x) {
-    dim3 grid((nrows + kBlock - 1) / kBlock), block(kBlock);
-    if (nb == 2) hipLaunchKernelGGL(k_final_update<2>, grid, block, 0, s, nrows, k, V, y, dinv, x);
-    else hipLaunchKernelGGL(k_final_update<3>, grid, block, 0, s, nrows, k, V, y, dinv, x);
+                        double *w, double *partials, double *hnext, const int *gate, int *reorth,
+                        double *hacc) {
+    const int nblk = vec_blocks(nvec);
+    hipLaunchKernelGGL(k_update_norm, dim3(nblk), dim3(kBlock), 0, s, nvec, nv, V, coef, w,
+                       partials, gate);
+    hipLaunchKernelGGL(k_update_finish, dim3(1), dim3(kBlock), 0, s, nblk, nv, coef, partials,
+                       hnext, gate, reorth, hacc);
 }
 
 // r = b - Ax; out[0] = ||r||^2, out[1] = ||r||
 __global__ __launch_bounds__(kBlock) void k_residual(long nvec, const double *__restrict__ b,
                                                      const double *__restrict__ Ax,
-                                                     double *__restrict__ r, double *partials,
-                                                     unsigned *counter, double *out) {
+                                                     double *__restrict__ r, double *partials) {
     double v[1] = {0.0};
     const bool mx[1] = {false};
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < nvec;
@@ -473,13 +426,14 @@ __global__ __launch_bounds__(kBlock) void k_residual(long nvec, const double *__
         r[i] = a;
         v[0] += a * a;
     }
-    if (grid_reduce<1>(v, mx, partials, counter, out) && threadIdx.x == 0) out[1] = sqrt(out[0]);
+    block_partials<1>(v, mx, partials);
 }
 
 void launch_residual(hipStream_t s, long nvec, const double *b, const double *Ax, double *r,
-                     double *partials, unsigned *counter, double *out) {
-    hipLaunchKernelGGL(k_residual, dim3(vec_blocks(nvec)), dim3(kBlock), 0, s, nvec, b, Ax, r,
-                       partials, counter, out);
+                     double *partials, double *out) {
+    const int nblk = vec_blocks(nvec);
+    hipLaunchKernelGGL(k_residual, dim3(nblk), dim3(kBlock), 0, s, nvec, b, Ax, r, partials);
+    hipLaunchKernelGGL(k_finish_norm, dim3(1), dim3(kBlock), 0, s, nblk, partials, out);
 }
 
 // x += sum_{i<k} y_i Z_i (the flexible-GMRES update with stored

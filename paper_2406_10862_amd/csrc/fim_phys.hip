@@ -564,8 +564,7 @@ template <int NB>
 __global__ __launch_bounds__(kBlock) void k_conv(int n, int nw, const double *__restrict__ rec,
                                                  const double *__restrict__ R,
                                                  const double *__restrict__ wmeas, double dt,
-                                                 double *partials, unsigned *counter,
-                                                 double *out) {
+                                                 double *partials) {
     using RI = Rec<NB>;
     constexpr int K = 3 * NB + 1;
     double v[K];
@@ -588,7 +587,21 @@ __global__ __launch_bounds__(kBlock) void k_conv(int n, int nw, const double *__
     }
     if (blockIdx.x == 0)
         for (int wl = threadIdx.x; wl < nw; wl += blockDim.x) v[3 * NB] = rop(v[3 * NB], wmeas[wl], true);
-    grid_reduce<K>(v, mx, partials, counter, out);
+    block_partials<K>(v, mx, partials);
+}
+
+template <int NB>
+__global__ __launch_bounds__(kBlock) void k_conv_finish(int nparts, const double *partials,
+                                                        double *out) {
+    constexpr int K = 3 * NB + 1;
+    bool mx[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) mx[k] = (k < NB) || (k == 3 * NB);
+    double a[K];
+    finish_partials<K>(nparts, mx, partials, a);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < K; ++k) out[k] = a[k];
 }
 
 // ---------------------------------------------------------------------------
@@ -603,9 +616,7 @@ __global__ __launch_bounds__(kBlock) void k_newton_update(Phys f, int n, int nw,
                                                           double *__restrict__ Sw,
                                                           double *__restrict__ X,
                                                           int8_t *__restrict__ flag,
-                                                          double *__restrict__ pbhp,
-                                                          double *partials, unsigned *counter,
-                                                          double *out) {
+                                                          double *partials) {
     __shared__ double sm[6 * kMaxTableRows];
     TabL t;
     stage_table(f, sm, t);
@@ -644,8 +655,21 @@ __global__ __launch_bounds__(kBlock) void k_newton_update(Phys f, int n, int nw,
         }
         if (dP != dP || dS != dS || dX != dX) v[0] = NAN;
     }
-    if (grid_reduce<2>(v, mx, partials, counter, out) && threadIdx.x == 0) {
-        double m = out[0];
+    block_partials<2>(v, mx, partials);
+}
+
+// One block: combines the cell maxima and updates the well pressures (the
+// BHP unknowns follow the cells in y), clipped like the cell pressures.
+template <int NB>
+__global__ __launch_bounds__(kBlock) void k_newton_finish(int nparts, int n, int nw,
+                                                          const double *__restrict__ y,
+                                                          double dp_max, double *pbhp,
+                                                          const double *partials, double *out) {
+    const bool mx[2] = {true, true};
+    double a[2];
+    finish_partials<2>(nparts, mx, partials, a);
+    if (threadIdx.x == 0) {
+        double m = a[0];
         for (int wl = 0; wl < nw; ++wl) {
             double d = -y[(size_t)(n + wl) * NB];
             d = fmin(fmax(d, -dp_max), dp_max);
@@ -654,6 +678,7 @@ __global__ __launch_bounds__(kBlock) void k_newton_update(Phys f, int n, int nw,
             if (d != d) m = NAN;
         }
         out[0] = m;
+        out[1] = a[1];
     }
 }
 
@@ -734,26 +759,33 @@ void launch_assemble(hipStream_t s, int nb, Grid g, Phys f, Wells w, Sys sys,
 }
 
 void launch_conv(hipStream_t s, int nb, int n, int nw, const double *rec, const double *R,
-                 const double *wmeas, double dt, double *partials, int nblocks,
-                 unsigned *counter, double *out) {
-    if (nb == 2)
+                 const double *wmeas, double dt, double *partials, int nblocks, double *out) {
+    if (nb == 2) {
         hipLaunchKernelGGL(k_conv<2>, dim3(nblocks), dim3(kBlock), 0, s, n, nw, rec, R, wmeas, dt,
-                           partials, counter, out);
-    else
+                           partials);
+        hipLaunchKernelGGL(k_conv_finish<2>, dim3(1), dim3(kBlock), 0, s, nblocks, partials, out);
+    } else {
         hipLaunchKernelGGL(k_conv<3>, dim3(nblocks), dim3(kBlock), 0, s, n, nw, rec, R, wmeas, dt,
-                           partials, counter, out);
+                           partials);
+        hipLaunchKernelGGL(k_conv_finish<3>, dim3(1), dim3(kBlock), 0, s, nblocks, partials, out);
+    }
 }
 
 void launch_newton_update(hipStream_t s, int nb, Phys f, int n, int nw, const double *y,
                           double ds_max, double dp_max, double *P, double *Sw, double *X,
                           int8_t *flag, double *pbhp, double *partials, int nblocks,
-                          unsigned *counter, double *out) {
-    if (nb == 2)
+                          double *out) {
+    if (nb == 2) {
         hipLaunchKernelGGL(k_newton_update<2>, dim3(nblocks), dim3(kBlock), 0, s, f, n, nw, y,
-                           ds_max, dp_max, P, Sw, X, flag, pbhp, partials, counter, out);
-    else
+                           ds_max, dp_max, P, Sw, X, flag, partials);
+        hipLaunchKernelGGL(k_newton_finish<2>, dim3(1), dim3(kBlock), 0, s, nblocks, n, nw, y,
+                           dp_max, pbhp, partials, out);
+    } else {
         hipLaunchKernelGGL(k_newton_update<3>, dim3(nblocks), dim3(kBlock), 0, s, f, n, nw, y,
-                           ds_max, dp_max, P, Sw, X, flag, pbhp, partials, counter, out);
+                           ds_max, dp_max, P, Sw, X, flag, partials);
+        hipLaunchKernelGGL(k_newton_finish<3>, dim3(1), dim3(kBlock), 0, s, nblocks, n, nw, y,
+                           dp_max, pbhp, partials, out);
+    }
 }
 
 void launch_well_rates(hipStream_t s, int nb, Wells w, const double *P, const double *pbhp,

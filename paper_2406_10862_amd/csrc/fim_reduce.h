@@ -1,9 +1,8 @@
 // fim_reduce.h - deterministic block and grid reductions for wave64.
 //
-// A grid reduction writes one partial per block, then the last block to
-// arrive (ticket from a global counter) combines the partials in block order
-// and resets the counter, so the result does not depend on scheduling and
-// no second kernel launch is needed.
+// A grid reduction writes one partial per block; a one-block kernel then
+// combines the partials in block order, so the result does not depend on
+// scheduling.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -45,37 +44,31 @@ __device__ inline void block_reduce(double (&v)[K], const bool (&mx)[K], double 
     __syncthreads();
 }
 
-// Grid-wide reduction of K values per thread into out[K].  Returns true in
-// the threads of the block that finished the reduction (the last block).
+// First half of a grid reduction: the block's K results go to
+// partials[k * gridDim.x + blockIdx.x].  No fence or atomic: the kernel
+// boundary makes them visible to the finishing kernel (a device-scope fence
+// per block would write back the whole L2 of the block's XCD).
 template <int K>
-__device__ inline bool grid_reduce(double (&v)[K], const bool (&mx)[K], double *partials,
-                                   unsigned *counter, double *out) {
+__device__ inline void block_partials(double (&v)[K], const bool (&mx)[K], double *partials) {
     __shared__ double sh[K][kWaves];
-    __shared__ int is_last;
     block_reduce<K>(v, mx, sh);
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0)
 #pragma unroll
-        for (int k = 0; k < K; ++k) partials[(size_t)blockIdx.x * K + k] = v[k];
-        __threadfence();
-        unsigned t = atomicAdd(counter, 1u);
-        is_last = (t == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (!is_last) return false;
-    __threadfence();
-    double a[K];
+        for (int k = 0; k < K; ++k) partials[(size_t)k * gridDim.x + blockIdx.x] = v[k];
+}
+
+// Second half, run by a single block: combines nparts partials of each of
+// the K slots in block order.  Result valid in thread 0.
+template <int K>
+__device__ inline void finish_partials(int nparts, const bool (&mx)[K], const double *partials,
+                                       double (&a)[K]) {
+    __shared__ double sh[K][kWaves];
 #pragma unroll
     for (int k = 0; k < K; ++k) a[k] = 0.0;
-    for (unsigned b = threadIdx.x; b < gridDim.x; b += blockDim.x)
+    for (int b = threadIdx.x; b < nparts; b += blockDim.x)
 #pragma unroll
-        for (int k = 0; k < K; ++k) a[k] = rop(a[k], partials[(size_t)b * K + k], mx[k]);
+        for (int k = 0; k < K; ++k) a[k] = rop(a[k], partials[(size_t)k * nparts + b], mx[k]);
     block_reduce<K>(a, mx, sh);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) out[k] = a[k];
-        atomicExch(counter, 0u);
-    }
-    return true;
 }
 
 }  // namespace fim

@@ -96,6 +96,7 @@ class Options:
     amg_sweeps: int = 1
     graphs: int = 1             # replay Arnoldi steps as HIP graphs
     forcing: int = 1            # Eisenstat-Walker forcing term (lin_rtol is the floor)
+    amg_fused: int = 0          # cells below which the AMG cycle runs fused (0 default, <0 off)
 
 
 @dataclass

@@ -269,6 +269,41 @@ def test_cpr_apply_is_linear_and_deterministic():
     assert np.array_equal(g.fim_precond_apply(a), za)
 
 
+@pytest.mark.parametrize("cfg,cycle,sweeps", [("c2s", 2, 1), ("c2s", 1, 2), ("c1", 2, 1),
+                                              ("line", 2, 3), ("wells", 2, 1)])
+def test_fused_amg_cycle_equals_launched_cycle(cfg, cycle, sweeps):
+    # the single-workgroup sub-cycle runs the same phases with the same
+    # per-entry arithmetic as the per-level launches: bitwise equal, whatever
+    # level it starts at
+    res = {"c2s": lambda: rv.config_c2_small(24, 40, 12), "c1": rv.config_c1,
+           "line": lambda: rv.buckley_leverett_1d(300),
+           "wells": lambda: rv.config_c2_small(31, 29, 7)}[cfg]()
+    g = fim.Fim(res)
+    g.set_initial_state()
+    R, *_ = g.fim_assemble(10.0)
+    v = np.random.default_rng(71).normal(size=len(R))
+    outs = {}
+    for fused in (-1, 64, 300, 1500, 0, 1 << 20):
+        g.fim_set_options(rv.Options(amg_cycle=cycle, amg_sweeps=sweeps, amg_fused=fused))
+        g.fim_assemble(10.0, jacobian=True)
+        outs[fused] = g.fim_precond_apply(v)
+    for fused, z in outs.items():
+        assert np.array_equal(z, outs[-1]), fused
+
+
+def test_fused_amg_cycle_in_full_steps():
+    res = rv.config_c2_small(24, 40, 12, nsteps=2)
+    states = []
+    for fused in (-1, 0):
+        g = fim.Fim(res, options=rv.Options(amg_fused=fused))
+        g.set_initial_state()
+        for dt in res.schedule:
+            assert g.fim_step(dt)[0] == fim.FIM_OK
+        states.append(g.fim_get_state())
+    for k in states[0]:
+        assert np.array_equal(states[0][k], states[1][k]), k
+
+
 def test_linear_solve_zero_rhs():
     g, o = pair(rv.config_c2_small(5, 5, 2))
     R, *_ = g.fim_assemble(10.0)
