@@ -120,8 +120,8 @@ def main():
                     help="time only the SpMV of the 1.1M-cell Jacobian (profiler counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the FIM path has no multi-GPU "
+              "implementation (no halo exchange or distributed reductions)", file=sys.stderr)
         sys.exit(2)
     if args.spmv_only:
         spmv_only(args.spmv_only)

@@ -12,9 +12,9 @@
  *   Sec. 2.1            constraints N_i = phi sum_j S_j xi_j x_ij,
  *                       sum_j S_j = 1, and the black-oil closure (phase
  *                       quantities explicit in P from tables);
- *   Sec. 3.2.3          Bulk (PVT, SAT, ROCK, ACCU), BulkConn (connection
+ *   Sec. 3.2.3-3.2.4    Bulk (PVT, SAT, ROCK, ACCU), BulkConn (connection
  *                       fluxes) and AllWells (perforation flux, well rows);
- *   Sec. 3.2.4          one FIM Newton iteration = assemble, solve and
+ *   Sec. 3.2.5          one FIM Newton iteration = assemble, solve and
  *                       update, property update, convergence check;
  *   Sec. 3.3.1-3.3.2    Setup / InitReservoir / GoOneStep, time stepping
  *                       with conditional returns to earlier stages;

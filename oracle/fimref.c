@@ -11,8 +11,8 @@
  *   Sec. 2.1 eq. (2)  Darcy velocity with gravity;
  *   Sec. 2.1 constraints N_i = phi sum_j S_j xi_j x_ij and sum_j S_j = 1;
  *   Sec. 2.1 black-oil closure: phase data explicit in P (tables);
- *   Sec. 3.2.3 Bulk::PVT / SAT / ROCK / ACCU, BulkConn fluxes, AllWells;
- *   Sec. 3.2.4 the four parts of one FIM Newton iteration;
+ *   Sec. 3.2.3 Bulk::PVT / SAT / ROCK / ACCU; Sec. 3.2.4 BulkConn fluxes, AllWells;
+ *   Sec. 3.2.5 the four parts of one FIM Newton iteration;
  *   Sec. 3.3.2 time stepping with conditional returns (cuts);
  *   Sec. 5.1   FGMRES with block-Jacobi ILU(0) as the iterative solver.
  */
@@ -339,7 +339,7 @@ typedef struct {
 } cellprops;
 
 /* interval i in [0, nrows-2] with t[i] <= v < t[i+1]; clamped at both ends,
- * so values outside the table extrapolate the end intervals (Q6 reading) */
+ * so values outside the table extrapolate the end intervals (the paper gives no interpolation rule: this is a reading) */
 static int tab_interval(const double *t, int nrows, double v) {
     int i = 0;
     while (i < nrows - 2 && t[i + 1] <= v) ++i;
@@ -390,7 +390,7 @@ static void eval_cell(const fr_model *m, int c, double P, double Sw, double X, i
     } else {
         /* undersaturated: bubble point from the inverse of the Rs column,
          * saturated values at Pb on the same interval, linear extension in
-         * P - Pb (Q7 reading) */
+         * P - Pb (a reading: the paper leaves undersaturated oil open) */
         Rs = X; dRsX = 1.0;
         int i = tab_interval(m->trs, m->nrows, Rs);
         double dPb = (m->tp[i + 1] - m->tp[i]) / (m->trs[i + 1] - m->trs[i]);
@@ -431,7 +431,7 @@ static void eval_cell(const fr_model *m, int c, double P, double Sw, double X, i
         cp->dgam[2][0] = drhogP / PSI_PER_LBFT2;
     }
 
-    /* saturations and relative permeabilities (Q10 reading) */
+    /* saturations and relative permeabilities (simple Corey; the paper names no three-phase model) */
     double So = 1.0 - Sw - Sg, dSoX = -dSgX;
     double krw, dkrw, kro, dkro, krg = 0, dkrg = 0;
     corey(Sw - m->swc, 1.0 - m->swc - m->sor, m->krw_max, m->nw_, &krw, &dkrw);
@@ -557,7 +557,8 @@ static void jadd(const fr_model *m, double *val, int row, int col, int eq, int u
 }
 
 /* Flux across the face K -> L (K < L) with transmissibility T: single-point
- * phase-potential upstream weighting (Q4), average face gravity (Q5).  Adds
+ * phase-potential upstream weighting, K upwind on ties, and the arithmetic
+ * mean of the two cells' gravity densities (readings: the paper fixes neither).  Adds
  * +F to row K, -F to row L, and the derivatives to the four blocks. */
 static void add_face(const fr_model *m, const cellprops *cp, const double *P, int K, int L,
                      double T, double *R, double *val) {
@@ -600,7 +601,7 @@ static void add_face(const fr_model *m, const cellprops *cp, const double *P, in
     }
 }
 
-/* Perforation rates (Q12 reading).  q[i] production-positive surface rate
+/* Perforation rates (Peaceman index, no wellbore head: a reading).  q[i] production-positive surface rate
  * of component i, dq[i][u] its derivative w.r.t. the cell unknowns and
  * dqb[i] w.r.t. the well's bottom-hole pressure. */
 static void perf_rate(const fr_model *m, const cellprops *c, double Pc, int kind, double wi,
@@ -708,7 +709,7 @@ void fr_well_rates(const fr_model *m, const double *P, const double *Sw, const d
     free(cp);
 }
 
-/* Convergence measures (Q14 reading): CNV_i is the largest cell residual in
+/* Convergence measures (the paper defines no norm: a reading): CNV_i is the largest cell residual in
  * saturation units, MB_i the normalised global mass imbalance. */
 static void conv_with(const fr_model *m, const cellprops *cp, const double *R, double dt,
                       double *cnv, double *mb) {
@@ -1022,7 +1023,7 @@ done:
 }
 
 /* ------------------------------------------------------------------------ */
-/* Newton iteration and time step (Sec. 3.2.4 and Sec. 3.3.2). */
+/* Newton iteration and time step (Sec. 3.2.5 and Sec. 3.3.2). */
 
 static double tab_rs_sat(const fr_model *m, double P) {
     double v, s;
@@ -1054,7 +1055,7 @@ static state_t state_alloc(const fr_model *m) {
 static void state_free(state_t *s) { free(s->P); free(s->Sw); free(s->X); free(s->flag); free(s->pbhp); }
 
 /* Newton update with per-cell saturation chopping, pressure clipping and
- * three-phase variable switching (Q2, Q18 readings).  Returns the largest
+ * three-phase variable switching (readings: the paper states neither the chop nor the switch).  Returns the largest
  * applied pressure and saturation changes. */
 static void newton_update(const fr_model *m, state_t *s, const double *dx, const fr_options *o,
                           double *maxdp, double *maxds) {

@@ -7,14 +7,15 @@
  * table or constant with the GPU library.
  *
  * What it computes (paper: Sec. 2.1, eqs. (1), (2) and the constraints that
- * follow them, with the black-oil closure stated right after; Sec. 3.2.4 for
+ * follow them, with the black-oil closure stated right after; Sec. 3.2.5 for
  * the four-part Newton iteration; Sec. 3.3.2 for the time-step loop with
  * conditional returns):
  *   backward-Euler, two-point-flux, single-point-upstream residual
  *     R_i,c = (A_i,c(x) - A_i,c(x^n))/dt + sum_faces F_i + sum_perf q_i
  *   in surface units per day, its analytic Jacobian in canonical BSR, and
  *   the Newton/linear iteration that drives R to zero.
- * Readings where the paper is silent are listed in the design doc (Q1..Q24).
+ * Where the paper is silent, each function's comment states the reading
+ * taken.
  *
  * Units: FIELD (ft, mD, psi, days, rb, stb, Mscf, cP).  Cell id is
  * c = i + nx*(j + ny*k), k = 0 is the top layer.  Unknowns per cell are
@@ -126,7 +127,8 @@ void fr_assemble(const fr_model *m, const double *P, const double *Sw, const dou
 void fr_well_rates(const fr_model *m, const double *P, const double *Sw, const double *X,
                    const int8_t *flag, const double *pbhp, double *q);
 
-/* Convergence measures at a residual: cnv[3], mb[3] (Q14 reading). */
+/* Convergence measures at a residual: cnv[3], mb[3] (a reading: the paper
+ * defines no norm). */
 void fr_conv(const fr_model *m, const double *P, const double *Sw, const double *X,
              const int8_t *flag, const double *R, double dt, double *cnv, double *mb);
 

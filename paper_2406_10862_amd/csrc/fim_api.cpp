@@ -1,5 +1,5 @@
 // fim_api.cpp - host runtime behind the C ABI (include/fim.h): context and
-// device memory, static pattern, the Newton driver (paper Sec. 3.2.4), the
+// device memory, static pattern, the Newton driver (paper Sec. 3.2.5), the
 // time-step driver with conditional returns (Sec. 3.3.2) and the GMRES
 // driver (Sec. 5.1, Sec. 3.3.3).  The host only orders launches, reads a
 // few scalars per iteration and solves the small Hessenberg least-squares
@@ -988,7 +988,7 @@ static int gmres(fim_ctx *c, const double *bvec, double *xvec, int max_it, doubl
 }
 
 // ---------------------------------------------------------------------------
-// Newton iterations for one sub-step (Sec. 3.2.4): 1 when converged.
+// Newton iterations for one sub-step (Sec. 3.2.5): 1 when converged.
 
 struct NewtonStats {
     int newton = 0, linear = 0;

@@ -2,8 +2,8 @@
 //
 // Paper anchors: Sec. 2.1 eqs. (1)-(2) and the constraints below them
 // (component conservation, Darcy flux with gravity, N_i = phi sum S_j xi_j
-// x_ij, sum S_j = 1, black-oil closure); Sec. 3.2.3 (Bulk PVT/SAT/ROCK/ACCU,
-// BulkConn, AllWells); Sec. 3.2.4 (one Newton iteration: assemble, solve
+// x_ij, sum S_j = 1, black-oil closure); Secs. 3.2.3-3.2.4 (Bulk PVT/SAT/ROCK/ACCU,
+// BulkConn, AllWells); Sec. 3.2.5 (one Newton iteration: assemble, solve
 // and update, update properties, check convergence).
 //
 // All kernels are bound by HBM traffic: one thread owns one cell, state and

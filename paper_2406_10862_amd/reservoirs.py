@@ -6,7 +6,7 @@ It contains none of the simulation arithmetic: no properties, fluxes,
 transmissibilities or well indices are computed here.
 
 The paper states the problem as grid + rock + fluid tables + wells + initial
-state (Sec. 3.2.3, the PreProcess/Bulk/AllWells description), validated on
+state (Secs. 3.2.3-3.2.4, the Bulk and AllWells descriptions), validated on
 SPE-style black-oil cases (Sec. 5.2).  The SPE datasets themselves are not
 used; seeded stand-ins with the same shapes are generated instead.
 

@@ -1,4 +1,4 @@
-"""Pins of the oracle's Newton iteration and time step (Sec. 3.2.4, Sec.
+"""Pins of the oracle's Newton iteration and time step (Sec. 3.2.5, Sec.
 3.3.2): brute-force single-cell solution, the Buckley-Leverett closed form,
 global mass balance, mirror symmetry, solver-path independence, cuts and
 restart determinism."""
