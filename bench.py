@@ -114,7 +114,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--tol", choices=["parity", "paper"], default="parity")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cycle", type=int, default=2, choices=[1, 2], help="AMG cycle: 1 V, 2 W")
+    ap.add_argument("--cycle", type=int, default=0,
+                    help="AMG cycle: 0 V at the finest level and W below, 1 V, 2 W, >=16 W on "
+                         "levels of at most that many cells")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "spmv_c2_traffic.json"))
     ap.add_argument("--spmv-only", type=int, default=0, metavar="REPS",
                     help="time only the SpMV of the 1.1M-cell Jacobian (profiler counter runs)")
@@ -200,7 +202,9 @@ def main():
             "cells": g.n, "block_rows": g.nrows, "nnzb": g.nnzb, "nb": g.nb,
             "tolerances": args.tol,
             "precond": {0: "block-Jacobi", 2: "CPR (quasi-IMPES + aggregation AMG) + block-Jacobi"}[opts.precond],
-            "amg_cycle": {1: "V", 2: "W"}.get(opts.amg_cycle), "gmres_restart": opts.restart,
+            "amg_cycle": {0: "V at the finest level, W below", 1: "V", 2: "W"}.get(
+                opts.amg_cycle, f"W on levels <= {opts.amg_cycle} cells, V above"),
+            "gmres_restart": opts.restart,
             "newton_iters": newton, "linear_iters": linear, "cuts": cuts,
             "linear_per_newton": linear / newton if newton else None,
             "phase_ms": {"assemble": phases[0], "linear": phases[1], "update": phases[2]},

@@ -133,7 +133,8 @@ typedef struct {
  * residual.  The solver is flexible GMRES, right-preconditioned by block
  * Jacobi (FIM_PREC_BJ) or by CPR (FIM_PREC_CPR): a quasi-IMPES pressure
  * stage solved by one aggregation-AMG cycle (amg_cycle 1 = V, 2 = W, 0 =
- * default W; amg_sweeps red-black Gauss-Seidel sweeps before and after the
+ * default: V at the finest level and W below it, a value >= 16 = W on the
+ * levels with at most that many cells and wells and V above them; amg_sweeps red-black Gauss-Seidel sweeps before and after the
  * coarse correction, 0 = default 1) followed by block Jacobi on the
  * remaining residual.  forcing != 0 replaces the fixed lin_rtol by the
  * Eisenstat-Walker forcing term (choice 2, gamma 0.9, alpha 2) between 1e-2

@@ -589,7 +589,8 @@ __global__ __launch_bounds__(kBlock) void k_cpr_finish(int n, int nw, AmgLevel L
                                                        const double *__restrict__ dinv,
                                                        double *__restrict__ z) {
     const int lg = threadIdx.x & (G - 1);
-    const int r = (int)(((long)blockIdx.x * blockDim.x + threadIdx.x) / G);
+    const long blk = xcd_block(blockIdx.x, gridDim.x);
+    const int r = (int)((blk * blockDim.x + threadIdx.x) / G);
     const int nrows = n + nw;
     auto xp = [&](int col) -> double {
         return col < n ? L.x[split0[col]] : L.x[2 * L.half + (col - n)];

@@ -211,7 +211,8 @@ static void check_options(const fim_options *o) {
             "ds_max, dp_max > 0 and 0 < lin_rtol < 1 required");
     REQUIRE(o->precond == FIM_PREC_BJ || o->precond == FIM_PREC_CPR, "unknown preconditioner %d",
             o->precond);
-    REQUIRE(o->amg_cycle >= 0 && o->amg_cycle <= 2, "amg_cycle must be 0, 1 or 2");
+    REQUIRE(o->amg_cycle >= 0 && (o->amg_cycle <= 2 || o->amg_cycle >= 16),
+            "amg_cycle must be 0, 1, 2 or a level size >= 16");
     REQUIRE(o->amg_sweeps >= 0 && o->amg_sweeps <= 8, "amg_sweeps must be in [0, 8]");
     REQUIRE(o->graphs == 0 || o->graphs == 1, "graphs must be 0 or 1");
     REQUIRE(o->forcing == 0 || o->forcing == 1, "forcing must be 0 or 1");
@@ -675,7 +676,11 @@ static void amg_cycle(fim_ctx *c, int l, std::vector<int> *rec = nullptr, int ro
     }
     const AmgLevel &F = c->lv[l], &C = c->lv[l + 1];
     const int nu = c->opt.amg_sweeps > 0 ? c->opt.amg_sweeps : 1;
-    int gamma = (c->opt.amg_cycle == 1) ? 1 : 2;
+    // default: V at the finest level, W below (the finest level dominates the
+    // cost of a visit, the coarse ones the convergence)
+    const int cyc = c->opt.amg_cycle;
+    int gamma = (cyc == 1 || (cyc == 0 && l == 0)) ? 1 : 2;
+    if (cyc >= 16 && 2L * F.half + F.nw > cyc) gamma = 1;   // V above the size limit
     if (l + 1 == L - 1) gamma = 1;             // the coarsest level is solved exactly
     auto sweep = [&](int color, int mode) {
         if (rec) rec->push_back(amg_op(kOpSweep, rl, color, mode));

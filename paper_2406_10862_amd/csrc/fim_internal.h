@@ -18,6 +18,19 @@ constexpr int kMaxTableRows = 64;
 constexpr int kBlock = 256;          // threads per block of the cell/vector kernels
 constexpr int kMaxRestart = 40;       // GMRES restart length cap (registers of multidot)
 
+// Workgroups are handed to the eight XCDs round-robin (block b to XCD
+// b mod 8), and every XCD has its own L2.  xcd_block maps the hardware block
+// index to a logical one so that each XCD walks one contiguous run of
+// logical blocks in dispatch order: rows that share vector entries (stencil
+// neighbours) are then served by one L2 instead of being fetched into all
+// eight.  A bijection on [0, nblk) for any nblk.
+constexpr int kXcds = 8;
+__device__ inline int xcd_block(int b, int nblk) {
+    const int q = nblk / kXcds, r = nblk % kXcds;
+    const int x = b % kXcds, j = b / kXcds;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + j;
+}
+
 enum { kProd = 0, kInjWater = 1, kInjGas = 2 };
 enum { kBhp = 0, kRate = 1 };
 enum { kUnsat = 0, kSat = 1 };

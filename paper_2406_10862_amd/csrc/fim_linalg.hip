@@ -21,42 +21,76 @@ typedef double d2 __attribute__((ext_vector_type(2)));
 constexpr int kMaxDots = kMaxRestart + 1;   // basis vectors + the vector itself
 
 // ---------------------------------------------------------------------------
-// y = A x, canonical BSR
+// y = A x, canonical BSR.  A group of G lanes owns one block row; lane lg
+// takes the V consecutive blocks starting at rowptr[row] + lg*V (then
+// + G*V, ...), so the lanes of a wave read one contiguous run of the value
+// and index arrays.  NT selects non-temporal loads of the matrix (no
+// allocation in L2/MALL); REMAP walks the rows XCD by XCD.
+constexpr int kSpmvG = 8, kSpmvV = 1;
+constexpr bool kSpmvNT = true, kSpmvRemap = false;
 
-template <int NB, int G>
+template <bool NT, class T>
+__device__ inline T ldm(const T *p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
+template <int NB, int G, int V, bool NT, bool REMAP>
 __global__ __launch_bounds__(kBlock) void k_spmv(int nrows, const int *__restrict__ rowptr,
                                                  const int *__restrict__ colind,
                                                  const double *__restrict__ val,
                                                  const double *__restrict__ x,
                                                  double *__restrict__ y) {
     const int lg = threadIdx.x & (G - 1);
-    const int row = (int)(((long)blockIdx.x * blockDim.x + threadIdx.x) / G);
+    const long blk = REMAP ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
+    const int row = (int)((blk * blockDim.x + threadIdx.x) / G);
     double acc[NB];
 #pragma unroll
     for (int e = 0; e < NB; ++e) acc[e] = 0.0;
     if (row < nrows) {
         const int b = __builtin_nontemporal_load(rowptr + row);
         const int e = __builtin_nontemporal_load(rowptr + row + 1);
-        for (int q = b + lg; q < e; q += G) {
-            const int col = __builtin_nontemporal_load(colind + q);
-            if constexpr (NB == 2) {
-                const d2 *blk = reinterpret_cast<const d2 *>(val + (size_t)q * 4);
-                const d2 r0 = __builtin_nontemporal_load(blk);
-                const d2 r1 = __builtin_nontemporal_load(blk + 1);
-                const d2 xv = *reinterpret_cast<const d2 *>(x + (size_t)col * 2);
-                acc[0] += r0.x * xv.x + r0.y * xv.y;
-                acc[1] += r1.x * xv.x + r1.y * xv.y;
-            } else {
-                const double *blk = val + (size_t)q * NB * NB;
-                double a[NB * NB], xv[NB];
+        for (int q0 = b + lg * V; q0 < e; q0 += G * V) {
+            int col[V];
+            double a[V][NB * NB];
 #pragma unroll
-                for (int t = 0; t < NB * NB; ++t) a[t] = __builtin_nontemporal_load(blk + t);
+            for (int u = 0; u < V; ++u) {
+                const int q = q0 + u;
+                if (q < e) {
+                    col[u] = ldm<NT>(colind + q);
+                    if constexpr (NB == 2) {
+                        const d2 *blk2 = reinterpret_cast<const d2 *>(val + (size_t)q * 4);
+                        const d2 r0 = ldm<NT>(blk2), r1 = ldm<NT>(blk2 + 1);
+                        a[u][0] = r0.x;
+                        a[u][1] = r0.y;
+                        a[u][2] = r1.x;
+                        a[u][3] = r1.y;
+                    } else {
 #pragma unroll
-                for (int u = 0; u < NB; ++u) xv[u] = x[(size_t)col * NB + u];
+                        for (int t = 0; t < NB * NB; ++t) a[u][t] = ldm<NT>(val + (size_t)q * NB * NB + t);
+                    }
+                }
+            }
 #pragma unroll
-                for (int r = 0; r < NB; ++r)
+            for (int u = 0; u < V; ++u) {
+                if (q0 + u < e) {
+                    double xv[NB];
+                    if constexpr (NB == 2) {
+                        const d2 v2 = *reinterpret_cast<const d2 *>(x + (size_t)col[u] * 2);
+                        xv[0] = v2.x;
+                        xv[1] = v2.y;
+                    } else {
 #pragma unroll
-                    for (int u = 0; u < NB; ++u) acc[r] += a[r * NB + u] * xv[u];
+                        for (int t = 0; t < NB; ++t) xv[t] = x[(size_t)col[u] * NB + t];
+                    }
+#pragma unroll
+                    for (int r = 0; r < NB; ++r) {
+                        double sum = a[u][r * NB] * xv[0];
+#pragma unroll
+                        for (int t = 1; t < NB; ++t) sum += a[u][r * NB + t] * xv[t];
+                        acc[r] += sum;
+                    }
+                }
             }
         }
     }
@@ -79,13 +113,16 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int nrows, const int *__restric
 
 void launch_spmv(hipStream_t s, int nb, int nrows, const int *rowptr, const int *colind,
                  const double *val, const double *x, double *y) {
-    constexpr int G = 8;
+    constexpr int G = kSpmvG, V = kSpmvV;
+    constexpr bool NT = kSpmvNT, RM = kSpmvRemap;
     const long threads = (long)nrows * G;
     dim3 grid((unsigned)((threads + kBlock - 1) / kBlock)), block(kBlock);
     if (nb == 2)
-        hipLaunchKernelGGL((k_spmv<2, G>), grid, block, 0, s, nrows, rowptr, colind, val, x, y);
+        hipLaunchKernelGGL((k_spmv<2, G, V, NT, RM>), grid, block, 0, s, nrows, rowptr, colind, val,
+                           x, y);
     else
-        hipLaunchKernelGGL((k_spmv<3, G>), grid, block, 0, s, nrows, rowptr, colind, val, x, y);
+        hipLaunchKernelGGL((k_spmv<3, G, V, NT, RM>), grid, block, 0, s, nrows, rowptr, colind, val,
+                           x, y);
 }
 
 // ---------------------------------------------------------------------------

@@ -92,7 +92,7 @@ class Options:
     max_cuts: int = 8
     precond: int = PREC_CPR
     precision: int = FP64
-    amg_cycle: int = 2          # 1 = V-cycle, 2 = W-cycle
+    amg_cycle: int = 0          # 0 = V at the finest level, W below; 1 = V; 2 = W; >=16 by size
     amg_sweeps: int = 1
     graphs: int = 1             # replay Arnoldi steps as HIP graphs
     forcing: int = 1            # Eisenstat-Walker forcing term (lin_rtol is the floor)

@@ -235,7 +235,7 @@ def test_linear_solve_matches_dense_solution(cfg, precond):
     assert np.abs(x - xd).max() <= bound * np.abs(xd).max()
 
 
-@pytest.mark.parametrize("cycle", [1, 2])
+@pytest.mark.parametrize("cycle", [0, 1, 2, 500])
 def test_cpr_needs_far_fewer_iterations_than_block_jacobi(cycle):
     # heterogeneous five-spot: the pressure stage removes the elliptic part
     # that stalls block Jacobi
@@ -269,8 +269,9 @@ def test_cpr_apply_is_linear_and_deterministic():
     assert np.array_equal(g.fim_precond_apply(a), za)
 
 
-@pytest.mark.parametrize("cfg,cycle,sweeps", [("c2s", 2, 1), ("c2s", 1, 2), ("c1", 2, 1),
-                                              ("line", 2, 3), ("wells", 2, 1)])
+@pytest.mark.parametrize("cfg,cycle,sweeps", [("c2s", 2, 1), ("c2s", 1, 2), ("c2s", 0, 1),
+                                              ("c2s", 500, 2), ("c1", 2, 1), ("line", 2, 3),
+                                              ("wells", 0, 1)])
 def test_fused_amg_cycle_equals_launched_cycle(cfg, cycle, sweeps):
     # the single-workgroup sub-cycle runs the same phases with the same
     # per-entry arithmetic as the per-level launches: bitwise equal, whatever
