@@ -29,14 +29,75 @@ __device__ inline int split_of(const AmgLevel &L, int i, int j, int k) {
     return (((i + j + k) & 1) ? L.half : 0) + (c >> 1);
 }
 
-__device__ inline void cell_of(const AmgLevel &L, int s, int &i, int &j, int &k) {
-    const int color = s >= L.half;
-    const int c0 = 2 * (s - color * L.half);
-    const int row = c0 / L.nxp;
-    j = row % L.ny;
-    k = row / L.ny;
+// n / d for n * d < 2^40, with m = ceil(2^40 / d) from the host: the
+// rounding error of the product stays below 1/d, so the quotient is exact.
+__device__ inline int fdiv(int n, unsigned long long m) {
+    return (int)(((unsigned long long)(unsigned)n * m) >> 40);
+}
+
+// Grid position of split entry s: (i, j, k), padded natural index
+// c = i + nxp*(j + ny*k) and colour (i + j + k) & 1.
+struct Pos {
+    int i, j, k, c, color;
+};
+
+__device__ inline Pos pos_of(const AmgLevel &L, int s) {
+    Pos p;
+    p.color = s >= L.half;
+    const int c0 = 2 * (s - p.color * L.half);
+    const int row = fdiv(c0, L.mnxp);
+    p.k = fdiv(row, L.mny);
+    p.j = row - p.k * L.ny;
     const int i0 = c0 - row * L.nxp;
-    i = i0 + (((j + k) & 1) ^ color);
+    p.i = i0 + (((p.j + p.k) & 1) ^ p.color);
+    p.c = c0 + (p.i - i0);
+    return p;
+}
+
+// Position of the cell (i, j, k).
+__device__ inline Pos pos_at(const AmgLevel &L, int i, int j, int k) {
+    Pos p;
+    p.i = i;
+    p.j = j;
+    p.k = k;
+    p.c = i + L.nxp * (j + L.ny * k);
+    p.color = (i + j + k) & 1;
+    return p;
+}
+
+__device__ inline int split_pos(const AmgLevel &L, const Pos &p) {
+    return (p.color ? L.half : 0) + (p.c >> 1);
+}
+
+// Neighbour d (stencil slot) of p: false outside the grid; otherwise its
+// split index (the other colour) in ns.
+__device__ inline bool nbr(const AmgLevel &L, const Pos &p, int d, int &ns) {
+    int dc;
+    bool in;
+    switch (d) {
+        case 1: in = p.i > 0; dc = -1; break;
+        case 2: in = p.i + 1 < L.nx; dc = 1; break;
+        case 3: in = p.j > 0; dc = -L.nxp; break;
+        case 4: in = p.j + 1 < L.ny; dc = L.nxp; break;
+        case 5: in = p.k > 0; dc = -L.nxp * L.ny; break;
+        default: in = p.k + 1 < L.nz; dc = L.nxp * L.ny; break;
+    }
+    ns = (p.color ? 0 : L.half) + ((p.c + dc) >> 1);
+    return in;
+}
+
+// coordinates of neighbour d of p
+__device__ inline void nbr_ijk(const Pos &p, int d, int &ni, int &nj, int &nk) {
+    ni = p.i + (d == 2) - (d == 1);
+    nj = p.j + (d == 4) - (d == 3);
+    nk = p.k + (d == 6) - (d == 5);
+}
+
+__device__ inline void cell_of(const AmgLevel &L, int s, int &i, int &j, int &k) {
+    const Pos p = pos_of(L, s);
+    i = p.i;
+    j = p.j;
+    k = p.k;
 }
 
 __device__ inline bool neighbour(const AmgLevel &L, int d, int i, int j, int k, int &ni, int &nj,
@@ -94,12 +155,20 @@ __device__ inline double pcoef(const double *__restrict__ val, int q, const doub
     return s;
 }
 
+// Also copies the pressure column of every block of the row (rows of
+// cells and wells) into ap[q][NB], the only part of A that the second CPR
+// stage multiplies.
 template <int NB>
 __global__ __launch_bounds__(kBlock) void k_amg_extract(AmgLevel L, Grid g, Wells wl, Sys sys,
-                                                        double *__restrict__ wq) {
+                                                        double *__restrict__ wq,
+                                                        double *__restrict__ ap) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int n = g.n;
     const int stride = 2 * L.half;
+    if (t < n + L.nw)
+        for (int q = sys.rowptr[t]; q < sys.rowptr[t + 1]; ++q)
+#pragma unroll
+            for (int u = 0; u < NB; ++u) ap[(size_t)q * NB + u] = sys.val[(size_t)q * NB * NB + u * NB];
     if (t < n) {
         const int c = t, nx = g.nx, ny = g.ny, nxy = nx * ny;
         const int i = c % nx, j = (c / nx) % ny, k = c / nxy;
@@ -301,11 +370,15 @@ __global__ __launch_bounds__(256) void k_dense_gemv(int n, const double *__restr
 // ---------------------------------------------------------------------------
 // cycle kernels
 
-__device__ inline double read_cell(const AmgLevel &L, const AmgLevel &C, int mode, int ni, int nj,
-                                   int nk) {
+__device__ inline double read_cell(const AmgLevel &L, const AmgLevel &C, int mode, int ns,
+                                   const Pos &p, int d) {
     if (mode & kCellsZero) return 0.0;
-    double v = L.x[split_of(L, ni, nj, nk)];
-    if (mode & kCellsCorr) v += C.x[split_of(C, ni >> 1, nj >> 1, nk >> 1)];
+    double v = L.x[ns];
+    if (mode & kCellsCorr) {
+        int ni, nj, nk;
+        nbr_ijk(p, d, ni, nj, nk);
+        v += C.x[split_of(C, ni >> 1, nj >> 1, nk >> 1)];
+    }
     return v;
 }
 
@@ -322,16 +395,14 @@ __device__ inline double read_well(const AmgLevel &L, const AmgLevel &C, int mod
 __device__ inline double sweep_value(const AmgLevel &L, const AmgLevel &C, int color, int mode,
                                      int h) {
     const int s = color * L.half + h;
-    int i, j, k;
-    cell_of(L, s, i, j, k);
-    if (i >= L.nx) return 0.0;
+    const Pos p = pos_of(L, s);
+    if (p.i >= L.nx) return 0.0;
     const int stride = 2 * L.half;
     double acc = L.b[s];
 #pragma unroll
     for (int d = 1; d < 7; ++d) {
-        int ni, nj, nk;
-        if (neighbour(L, d, i, j, k, ni, nj, nk))
-            acc -= L.a[(size_t)d * stride + s] * read_cell(L, C, mode, ni, nj, nk);
+        int ns;
+        if (nbr(L, p, d, ns)) acc -= L.a[(size_t)d * stride + s] * read_cell(L, C, mode, ns, p, d);
     }
     for (int q = L.cps[s]; q < L.cps[s + 1]; ++q) {
         const int sl = L.cslot[q];
@@ -343,6 +414,35 @@ __device__ inline double sweep_value(const AmgLevel &L, const AmgLevel &C, int c
 __device__ inline void sweep_item(const AmgLevel &L, const AmgLevel &C, int color, int mode,
                                   int h) {
     L.x[color * L.half + h] = sweep_value(L, C, color, mode, h);
+}
+
+// The first pre-smoothing pair from a zero iterate (wells still zero) in
+// one pass: red cell h gets b/a_0 (all its neighbours are zero), black cell
+// h gets its Gauss-Seidel value from those red values, computed on the fly.
+__device__ inline double red_from_zero(const AmgLevel &L, int s) { return L.b[s] / L.a[s]; }
+
+__device__ inline void presmooth_item(const AmgLevel &L, int h) {
+    L.x[h] = (pos_of(L, h).i >= L.nx) ? 0.0 : red_from_zero(L, h);
+    const int s = L.half + h;
+    const Pos p = pos_of(L, s);
+    if (p.i >= L.nx) {
+        L.x[s] = 0.0;
+        return;
+    }
+    const int stride = 2 * L.half;
+    double acc = L.b[s];
+#pragma unroll
+    for (int d = 1; d < 7; ++d) {
+        int ns;
+        if (nbr(L, p, d, ns)) acc -= L.a[(size_t)d * stride + s] * red_from_zero(L, ns);
+    }
+    for (int q = L.cps[s]; q < L.cps[s + 1]; ++q) acc -= L.acw[L.cslot[q]] * 0.0;
+    L.x[s] = acc / L.a[s];
+}
+
+__global__ __launch_bounds__(kBlock) void k_amg_presmooth(AmgLevel L) {
+    const int h = blockIdx.x * blockDim.x + threadIdx.x;
+    if (h < L.half) presmooth_item(L, h);
 }
 
 __global__ __launch_bounds__(kBlock) void k_amg_sweep(AmgLevel L, AmgLevel C, int color,
@@ -370,14 +470,13 @@ __global__ __launch_bounds__(kBlock) void k_amg_well_sweep(AmgLevel L) {
     if (w < L.nw) well_sweep_item(L, w, threadIdx.x & 63);
 }
 
-__device__ inline double cell_residual(const AmgLevel &L, int s, int i, int j, int k) {
+__device__ inline double cell_residual(const AmgLevel &L, int s, const Pos &p) {
     const int stride = 2 * L.half;
     double r = L.b[s] - L.a[s] * L.x[s];
 #pragma unroll
     for (int d = 1; d < 7; ++d) {
-        int ni, nj, nk;
-        if (neighbour(L, d, i, j, k, ni, nj, nk))
-            r -= L.a[(size_t)d * stride + s] * L.x[split_of(L, ni, nj, nk)];
+        int ns;
+        if (nbr(L, p, d, ns)) r -= L.a[(size_t)d * stride + s] * L.x[ns];
     }
     for (int q = L.cps[s]; q < L.cps[s + 1]; ++q) {
         const int sl = L.cslot[q];
@@ -392,20 +491,21 @@ __device__ inline double cell_residual(const AmgLevel &L, int s, int i, int j, i
 // the residual of child (q & 1, (q >> 1) & 1, q >> 2) and the group's first
 // lane adds the existing children in that (k, j, i) order.  Every lane of
 // the wave must call it (shuffles); on = false marks lanes past the end.
-__device__ inline void restrict_group(const AmgLevel &F, const AmgLevel &C, int t, int q,
-                                      bool on) {
-    double r = 0.0;
-    int have = 0, I = 0, J = 0, K = 0;
-    if (on) {
-        I = t % C.nx;
-        J = (t / C.nx) % C.ny;
-        K = t / (C.nx * C.ny);
-        const int i = 2 * I + (q & 1), j = 2 * J + ((q >> 1) & 1), k = 2 * K + (q >> 2);
-        if (i < F.nx && j < F.ny && k < F.nz) {
-            r = cell_residual(F, split_of(F, i, j, k), i, j, k);
-            have = 1;
-        }
-    }
+__device__ inline double restrict_child(const AmgLevel &F, const AmgLevel &C, int t, int q,
+                                        bool on, int &have) {
+    have = 0;
+    if (!on) return 0.0;
+    const int JK = fdiv(t, C.mnx), I = t - JK * C.nx;
+    const int K = fdiv(JK, C.mny), J = JK - K * C.ny;
+    const int i = 2 * I + (q & 1), j = 2 * J + ((q >> 1) & 1), k = 2 * K + (q >> 2);
+    if (i >= F.nx || j >= F.ny || k >= F.nz) return 0.0;
+    have = 1;
+    const Pos p = pos_at(F, i, j, k);
+    return cell_residual(F, split_pos(F, p), p);
+}
+
+__device__ inline void restrict_sum(const AmgLevel &C, int t, int q, bool on, double r,
+                                    int have) {
     const int first = (threadIdx.x & 63) & ~7;
     double sum = 0.0;
 #pragma unroll
@@ -413,7 +513,18 @@ __device__ inline void restrict_group(const AmgLevel &F, const AmgLevel &C, int 
         const double rc = __shfl(r, first + c, 64);
         if (__shfl(have, first + c, 64)) sum += rc;
     }
-    if (on && q == 0) C.b[split_of(C, I, J, K)] = sum;
+    if (on && q == 0) {
+        const int JK = fdiv(t, C.mnx), I = t - JK * C.nx;
+        const int K = fdiv(JK, C.mny), J = JK - K * C.ny;
+        C.b[split_of(C, I, J, K)] = sum;
+    }
+}
+
+__device__ inline void restrict_group(const AmgLevel &F, const AmgLevel &C, int t, int q,
+                                      bool on) {
+    int have;
+    const double r = restrict_child(F, C, t, q, on, have);
+    restrict_sum(C, t, q, on, r, have);
 }
 
 // a well is its own aggregate: its coarse right-hand side is its residual
@@ -439,10 +550,9 @@ __global__ __launch_bounds__(kBlock) void k_amg_restrict(AmgLevel F, AmgLevel C)
 // x_fine += P x_coarse at fine entry t
 __device__ inline void correct_item(const AmgLevel &F, const AmgLevel &C, int t) {
     if (t < 2 * F.half) {
-        int i, j, k;
-        cell_of(F, t, i, j, k);
-        if (i >= F.nx) return;
-        F.x[t] += C.x[split_of(C, i >> 1, j >> 1, k >> 1)];
+        const Pos p = pos_of(F, t);
+        if (p.i >= F.nx) return;
+        F.x[t] += C.x[split_of(C, p.i >> 1, p.j >> 1, p.k >> 1)];
     } else if (t < 2 * F.half + F.nw) {
         const int w = t - 2 * F.half;
         F.x[t] += C.x[2 * C.half + w];
@@ -469,17 +579,60 @@ __device__ inline void lds_copy(T *dst, const T *src, int n) {
     for (int e = threadIdx.x; e < n; e += blockDim.x) dst[e] = src[e];
 }
 
+// One phase of the sub-cycle on level F (coarser neighbour C) by the whole
+// workgroup.  Inlined once with the coefficients of F in LDS and once with
+// them in HBM, so every access has a known address space.
+__device__ __forceinline__ void subcycle_phase(int op, const AmgLevel &F, const AmgLevel &C,
+                                               const double *Minv) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int wave = tid >> 6, lane = tid & 63, nwaves = nt >> 6;
+    const int kind = op & 15;
+    if (kind == kOpPresmooth) {
+        for (int h = tid; h < F.half; h += nt) presmooth_item(F, h);
+    } else if (kind == kOpSweep) {
+        const int color = (op >> 8) & 1, mode = (op >> 12) & 15;
+        // two entries per thread at a time so their loads overlap
+        for (int h = tid; h < F.half; h += 2 * nt) {
+            const int h2 = h + nt;
+            const double v1 = sweep_value(F, C, color, mode, h);
+            const double v2 = (h2 < F.half) ? sweep_value(F, C, color, mode, h2) : 0.0;
+            F.x[color * F.half + h] = v1;
+            if (h2 < F.half) F.x[color * F.half + h2] = v2;
+        }
+    } else if (kind == kOpWells) {
+        for (int w = wave; w < F.nw; w += nwaves) well_sweep_item(F, w, lane);
+    } else if (kind == kOpRestrict) {
+        // two rounds of children per pass so their loads overlap; the trip
+        // count is uniform over the workgroup (shuffles inside)
+        const int n8 = 8 * C.nx * C.ny * C.nz;
+        for (int base = 0; base < n8; base += 2 * nt) {
+            const int t1 = base + tid, t2 = t1 + nt;
+            int h1, h2;
+            const double r1 = restrict_child(F, C, t1 >> 3, t1 & 7, t1 < n8, h1);
+            const double r2 = restrict_child(F, C, t2 >> 3, t2 & 7, t2 < n8, h2);
+            restrict_sum(C, t1 >> 3, t1 & 7, t1 < n8, r1, h1);
+            restrict_sum(C, t2 >> 3, t2 & 7, t2 < n8, r2, h2);
+        }
+        for (int w = wave; w < F.nw; w += nwaves) restrict_well(F, C, w, lane);
+    } else if (kind == kOpCorrect) {
+        for (int t = tid; t < 2 * F.half + F.nw; t += nt) correct_item(F, C, t);
+    } else {
+        const int n = 2 * F.half + F.nw;
+        for (int row = wave; row < n; row += nwaves) dense_row(n, Minv, F.b, F.x, row, lane);
+    }
+}
+
 __global__ __launch_bounds__(kSubThreads) void k_amg_subcycle(AmgSub P) {
     extern __shared__ double lds[];
     int *ldi = reinterpret_cast<int *>(lds + P.ldoubles);
     const int tid = threadIdx.x, nt = blockDim.x;
-    const int wave = tid >> 6, lane = tid & 63, nwaves = nt >> 6;
     // padded entries of the coarse right-hand sides are never restricted
     // to but are read by the dense solve: start from zeros as in HBM
     for (int k = 0; k < P.nlev; ++k) {
         const AmgLevel &L = P.lv[k];
         const int n = 2 * L.half + L.nw;
         for (int e = tid; e < n; e += nt) lds[P.off[k][kSubB] + e] = (k == 0) ? L.b[e] : 0.0;
+        if (P.off[k][kSubA] >= 0) lds_copy(lds + P.off[k][kSubA], L.a, 14 * L.half);
         lds_copy(lds + P.off[k][kSubAcw], L.acw, L.nslot);
         lds_copy(lds + P.off[k][kSubAwc], L.awc, L.nslot);
         lds_copy(ldi + P.off[k][kSubCps], L.cps, 2 * L.half + 1);
@@ -487,6 +640,11 @@ __global__ __launch_bounds__(kSubThreads) void k_amg_subcycle(AmgSub P) {
         lds_copy(ldi + P.off[k][kSubSwell], L.swell, L.nslot);
         lds_copy(ldi + P.off[k][kSubScell], L.scell, L.nslot);
         lds_copy(ldi + P.off[k][kSubSps], L.sps, L.nw + 1);
+    }
+    if (P.minvoff >= 0) {
+        const AmgLevel &L = P.lv[P.nlev - 1];
+        const int n = 2 * L.half + L.nw;
+        lds_copy(lds + P.minvoff, P.Minv, n * n);
     }
     int *ops = ldi + P.opsoff;
     lds_copy(ops, P.ops, P.nops);
@@ -506,35 +664,18 @@ __global__ __launch_bounds__(kSubThreads) void k_amg_subcycle(AmgSub P) {
     };
     for (int o = 0; o < P.nops; ++o) {
         const int op = __builtin_amdgcn_readfirstlane(ops[o]);
-        const int kind = op & 15, l = (op >> 4) & 15;
-        const AmgLevel F = level(l);
-        if (kind == kOpSweep) {
-            const AmgLevel C = level(l + 1);
-            const int color = (op >> 8) & 1, mode = (op >> 12) & 15;
-            // two entries per thread at a time so their loads overlap
-            for (int h = tid; h < F.half; h += 2 * nt) {
-                const int h2 = h + nt;
-                const double v1 = sweep_value(F, C, color, mode, h);
-                const double v2 = (h2 < F.half) ? sweep_value(F, C, color, mode, h2) : 0.0;
-                F.x[color * F.half + h] = v1;
-                if (h2 < F.half) F.x[color * F.half + h2] = v2;
-            }
-        } else if (kind == kOpWells) {
-            for (int w = wave; w < F.nw; w += nwaves) well_sweep_item(F, w, lane);
-        } else if (kind == kOpRestrict) {
-            const AmgLevel C = level(l + 1);
-            const int n8 = 8 * C.nx * C.ny * C.nz;
-            for (int base = 0; base < n8; base += nt) {
-                const int t8 = base + tid;
-                restrict_group(F, C, t8 >> 3, t8 & 7, t8 < n8);
-            }
-            for (int w = wave; w < F.nw; w += nwaves) restrict_well(F, C, w, lane);
-        } else if (kind == kOpCorrect) {
-            const AmgLevel C = level(l + 1);
-            for (int t = tid; t < 2 * F.half + F.nw; t += nt) correct_item(F, C, t);
+        const int l = (op >> 4) & 15;
+        const AmgLevel C = level(l + 1);
+        if ((op & 15) == kOpCoarse) {
+            const AmgLevel F = level(l);
+            if (P.minvoff >= 0) subcycle_phase(op, F, C, lds + P.minvoff);
+            else subcycle_phase(op, F, C, P.Minv);
+        } else if (P.off[l][kSubA] >= 0) {
+            AmgLevel F = level(l);
+            F.a = lds + P.off[l][kSubA];
+            subcycle_phase(op, F, C, P.Minv);
         } else {
-            const int n = 2 * F.half + F.nw;
-            for (int row = wave; row < n; row += nwaves) dense_row(n, P.Minv, F.b, F.x, row, lane);
+            subcycle_phase(op, level(l), C, P.Minv);
         }
         __syncthreads();
     }
@@ -580,11 +721,15 @@ __global__ __launch_bounds__(kBlock) void k_cpr_restrict(int n, int nw, AmgLevel
 }
 
 // z = x1 + D^-1 (v - A x1), x1 = the pressure correction in the pressure
-// slot of every row.  A x1 needs only the pressure column of each block; a
-// group of G lanes walks one block row as in the SpMV.
+// slot of every row.  A x1 needs only the pressure column of each block,
+// read from its compact copy ap[q][NB], with the column indices mapped to
+// level-0 AMG entries (colsplit); a group of G lanes walks one block row as
+// in the SpMV.
 template <int NB, int G>
 __global__ __launch_bounds__(kBlock) void k_cpr_finish(int n, int nw, AmgLevel L,
-                                                       const int *__restrict__ split0, Sys sys,
+                                                       const int *__restrict__ split0,
+                                                       const int *__restrict__ colsplit, Sys sys,
+                                                       const double *__restrict__ ap,
                                                        const double *__restrict__ v,
                                                        const double *__restrict__ dinv,
                                                        double *__restrict__ z) {
@@ -601,10 +746,10 @@ __global__ __launch_bounds__(kBlock) void k_cpr_finish(int n, int nw, AmgLevel L
     if (r < nrows) {
         const int b = sys.rowptr[r], e = sys.rowptr[r + 1];
         for (int q = b + lg; q < e; q += G) {
-            const double p = xp(__builtin_nontemporal_load(sys.colind + q));
-            const double *blk = sys.val + (size_t)q * NB * NB;
+            const double p = L.x[__builtin_nontemporal_load(colsplit + q)];
+            const double *col = ap + (size_t)q * NB;
 #pragma unroll
-            for (int u = 0; u < NB; ++u) t[u] += __builtin_nontemporal_load(blk + u * NB) * p;
+            for (int u = 0; u < NB; ++u) t[u] += __builtin_nontemporal_load(col + u) * p;
         }
     }
 #pragma unroll
@@ -632,10 +777,10 @@ __global__ __launch_bounds__(kBlock) void k_cpr_finish(int n, int nw, AmgLevel L
 static inline dim3 grid_for(long n, int bs) { return dim3((unsigned)((n + bs - 1) / bs)); }
 
 void launch_amg_extract(hipStream_t s, int nb, const AmgLevel &L, Grid g, Wells w, Sys sys,
-                        double *wq) {
+                        double *wq, double *ap) {
     const long n = (long)g.n + L.nw;
-    if (nb == 2) hipLaunchKernelGGL(k_amg_extract<2>, grid_for(n, kBlock), dim3(kBlock), 0, s, L, g, w, sys, wq);
-    else hipLaunchKernelGGL(k_amg_extract<3>, grid_for(n, kBlock), dim3(kBlock), 0, s, L, g, w, sys, wq);
+    if (nb == 2) hipLaunchKernelGGL(k_amg_extract<2>, grid_for(n, kBlock), dim3(kBlock), 0, s, L, g, w, sys, wq, ap);
+    else hipLaunchKernelGGL(k_amg_extract<3>, grid_for(n, kBlock), dim3(kBlock), 0, s, L, g, w, sys, wq, ap);
 }
 
 void launch_amg_coarsen(hipStream_t s, const AmgLevel &F, const AmgLevel &C, const int *cfs_ptr,
@@ -658,6 +803,10 @@ void launch_amg_coarsest_solve(hipStream_t s, const AmgLevel &L, const double *M
 
 void launch_amg_sweep(hipStream_t s, const AmgLevel &L, const AmgLevel &C, int color, int mode) {
     hipLaunchKernelGGL(k_amg_sweep, grid_for(L.half, kBlock), dim3(kBlock), 0, s, L, C, color, mode);
+}
+
+void launch_amg_presmooth(hipStream_t s, const AmgLevel &L) {
+    hipLaunchKernelGGL(k_amg_presmooth, grid_for(L.half, kBlock), dim3(kBlock), 0, s, L);
 }
 
 void launch_amg_well_sweep(hipStream_t s, const AmgLevel &L) {
@@ -701,16 +850,16 @@ void launch_cpr_restrict(hipStream_t s, int nb, int n, int nw, const AmgLevel &L
 }
 
 void launch_cpr_finish(hipStream_t s, int nb, int n, int nw, const AmgLevel &L,
-                       const int *split0, Sys sys, const double *v, const double *dinv,
-                       double *z) {
+                       const int *split0, const int *colsplit, Sys sys, const double *ap,
+                       const double *v, const double *dinv, double *z) {
     constexpr int G = 8;
     const long threads = ((long)n + nw) * G;
     if (nb == 2)
         hipLaunchKernelGGL((k_cpr_finish<2, G>), grid_for(threads, kBlock), dim3(kBlock), 0, s, n,
-                           nw, L, split0, sys, v, dinv, z);
+                           nw, L, split0, colsplit, sys, ap, v, dinv, z);
     else
         hipLaunchKernelGGL((k_cpr_finish<3, G>), grid_for(threads, kBlock), dim3(kBlock), 0, s, n,
-                           nw, L, split0, sys, v, dinv, z);
+                           nw, L, split0, colsplit, sys, ap, v, dinv, z);
 }
 
 }  // namespace fim

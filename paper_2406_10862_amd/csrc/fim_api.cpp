@@ -116,11 +116,13 @@ struct fim_ctx {
     std::vector<AmgLevel> lv;
     std::vector<const int *> cfs_ptr, cfs_idx;     // coarse slot -> fine slots, per level
     double *Mden = nullptr, *Minv = nullptr, *colk = nullptr, *wq = nullptr;
+    double *ap = nullptr;                           // [nnzb][nb] pressure column of A
     int sub_root = -1;                              // first level of the fused sub-cycle
     int *sub_ops = nullptr;                         // [kSubOps] its phase list
     AmgSub sub{};
     int *amg_bad = nullptr;
     int *split0 = nullptr;                          // natural cell -> level-0 split index
+    int *colsplit = nullptr;                        // [nnzb] column -> level-0 entry
     int *reorth = nullptr;
     double *partials = nullptr, *scal = nullptr;
     double *pin = nullptr;        // pinned host: scalars, H columns, y
@@ -279,6 +281,16 @@ static void build_amg(fim_ctx *c, const std::vector<int> &sorted_cells,
         L.half = L.nxp * ny * nz / 2;
         L.nw = nw;
         L.nslot = (int)slot_cell.size();
+        auto magic = [](long d) { return (unsigned long long)(((1ULL << 40) + d - 1) / d); };
+        L.mnx = magic(nx);
+        L.mny = magic(ny);
+        L.mnxp = magic(L.nxp);
+        // the multiply-shift divisions of the cycle kernels are exact while
+        // numerator * divisor < 2^40
+        REQUIRE((double)L.nxp * ny * nz * L.nxp < 1099511627776.0 &&
+                    (double)ny * nz * ny < 1099511627776.0 &&
+                    (double)nx * ny * nz * nx < 1099511627776.0,
+                "grid %d x %d x %d too large for the AMG index arithmetic", nx, ny, nz);
         const int ncs = 2 * L.half;
         auto split = [&](int cn) {
             const int i = cn % nx, j = (cn / nx) % ny, k = cn / (nx * ny);
@@ -365,6 +377,7 @@ static void build_amg(fim_ctx *c, const std::vector<int> &sorted_cells,
     c->colk = c->alloc<double>(n);
     c->amg_bad = c->alloc<int>(1);
     c->wq = c->alloc<double>((size_t)c->n * c->nb);
+    c->ap = c->alloc<double>((size_t)c->nnzb * c->nb);
 }
 
 static void build_subcycle(fim_ctx *c);
@@ -588,6 +601,25 @@ static int create_impl(const fim_grid *grid, const fim_rock *rock, const fim_flu
         c->reorth = c->alloc<int>(1);
         alloc_krylov(c, opt->restart);
         build_amg(c, sorted_cells, pwell_h);
+        {
+            // the level-0 AMG entry of every column (colour-split cell or
+            // well), so the second CPR stage gathers without the split map
+            const AmgLevel &L0 = c->lv[0];
+            std::vector<int> cs(ci.size());
+            for (size_t q = 0; q < ci.size(); ++q) {
+                const int col = ci[q];
+                if (col >= c->n) {
+                    cs[q] = 2 * L0.half + (col - c->n);
+                    continue;
+                }
+                const int i = col % c->g.nx, j = (col / c->g.nx) % c->g.ny,
+                          k = col / (c->g.nx * c->g.ny);
+                const int cc = i + L0.nxp * (j + c->g.ny * k);
+                cs[q] = (((i + j + k) & 1) ? L0.half : 0) + (cc >> 1);
+            }
+            c->colsplit = c->upload(cs.data(), cs.size());
+            c->sync();
+        }
         build_subcycle(c);
         const size_t np = (size_t)(kMaxRestart + 2) * 2048 + (size_t)2048 * 16;
         c->partials = c->alloc<double>(np);
@@ -692,8 +724,13 @@ static void amg_cycle(fim_ctx *c, int l, std::vector<int> *rec = nullptr, int ro
         else launch_amg_well_sweep(c->s, F);
     };
     for (int sw = 0; sw < nu; ++sw) {
-        sweep(0, sw == 0 ? (kCellsZero | kWellsZero) : 0);
-        sweep(1, sw == 0 ? kWellsZero : 0);
+        if (sw == 0) {                          // both colours from a zero iterate
+            if (rec) rec->push_back(amg_op(kOpPresmooth, rl));
+            else launch_amg_presmooth(c->s, F);
+        } else {
+            sweep(0, 0);
+            sweep(1, 0);
+        }
         wells();
     }
     for (int gv = 0; gv < gamma; ++gv) {
@@ -758,7 +795,29 @@ static void build_subcycle(fim_ctx *c) {
         sub.ldoubles = (int)nd;
         sub.opsoff = (int)ni;
         sub.nops = (int)ops.size();
-        if (amg_subcycle_lds(sub) <= (size_t)lds_max) break;
+        sub.minvoff = -1;
+        for (int k = 0; k <= sub.nlev; ++k) sub.off[k][kSubA] = -1;
+        if (amg_subcycle_lds(sub) > (size_t)lds_max) continue;
+        // what still fits goes to LDS too: the dense coarsest inverse first,
+        // then stencil coefficients from the coarser levels up
+        auto try_add = [&](long ndoubles) {
+            AmgSub t = sub;
+            t.ldoubles = (int)(sub.ldoubles + ndoubles);
+            if (amg_subcycle_lds(t) > (size_t)lds_max) return -1;
+            const int at = sub.ldoubles;
+            sub.ldoubles = t.ldoubles;
+            return at;
+        };
+        {
+            const AmgLevel &Lc = sub.lv[sub.nlev - 1];
+            const long nc = 2L * Lc.half + Lc.nw;
+            sub.minvoff = try_add(nc * nc);
+        }
+        for (int k = sub.nlev - 2; k >= 0; --k) {
+            sub.off[k][kSubA] = try_add(14L * sub.lv[k].half);
+            if (sub.off[k][kSubA] < 0) break;
+        }
+        break;
     }
     if (root >= L) return;
     if (!c->sub_ops) c->sub_ops = c->alloc<int>(kSubOps);
@@ -775,7 +834,7 @@ static void build_subcycle(fim_ctx *c) {
 static void prec_setup(fim_ctx *c) {
     launch_bj_setup(c->s, c->nb, c->nrows, c->diagpos, c->val, c->dinv, c->bad);
     if (c->opt.precond == FIM_PREC_CPR) {
-        launch_amg_extract(c->s, c->nb, c->lv[0], c->g, c->wells(), c->sys(), c->wq);
+        launch_amg_extract(c->s, c->nb, c->lv[0], c->g, c->wells(), c->sys(), c->wq, c->ap);
         for (size_t l = 1; l < c->lv.size(); ++l)
             launch_amg_coarsen(c->s, c->lv[l - 1], c->lv[l], c->cfs_ptr[l], c->cfs_idx[l]);
         launch_amg_coarsest_setup(c->s, c->lv.back(), c->Mden, c->Minv, c->colk, c->amg_bad);
@@ -789,7 +848,7 @@ static void precondition(fim_ctx *c, const double *w, const double *hptr, double
     if (c->opt.precond == FIM_PREC_CPR) {
         launch_cpr_restrict(c->s, c->nb, c->n, c->nw, c->lv[0], c->split0, w, hptr, v, c->wq);
         amg_cycle(c, 0);
-        launch_cpr_finish(c->s, c->nb, c->n, c->nw, c->lv[0], c->split0, c->sys(), hptr ? v : w,
+        launch_cpr_finish(c->s, c->nb, c->n, c->nw, c->lv[0], c->split0, c->colsplit, c->sys(), c->ap, hptr ? v : w,
                           c->dinv, z);
     } else if (hptr) {
         launch_normalize_precond(c->s, c->nb, c->nrows, w, hptr, v, z, c->dinv);

@@ -87,6 +87,7 @@ struct Sys {
 // 2*half cell entries in x and b.
 struct AmgLevel {
     int nx, ny, nz, nxp, half, nw, nslot;
+    unsigned long long mnx, mny, mnxp;   // ceil(2^40 / d) for d = nx, ny, nxp (exact division)
     double *a;              // [7][2*half]: diagonal, -x, +x, -y, +y, -z, +z
     double *aww;            // [nw] well diagonal
     const int *sps;         // [nw+1] well -> slot range
@@ -151,7 +152,7 @@ void launch_axpy_multi(hipStream_t s, long nvec, int k, const double *Z, const d
 // ---- CPR / pressure AMG kernels (fim_amg.hip) -----------------------------------
 constexpr int kCoarseMax = 64;       // cells of the level that is inverted densely
 void launch_amg_extract(hipStream_t s, int nb, const AmgLevel &L, Grid g, Wells w, Sys sys,
-                        double *wq);
+                        double *wq, double *ap);
 void launch_amg_coarsen(hipStream_t s, const AmgLevel &F, const AmgLevel &C, const int *cfs_ptr,
                         const int *cfs_idx);
 void launch_amg_coarsest_setup(hipStream_t s, const AmgLevel &L, double *M, double *Minv,
@@ -159,14 +160,15 @@ void launch_amg_coarsest_setup(hipStream_t s, const AmgLevel &L, double *M, doub
 void launch_amg_coarsest_solve(hipStream_t s, const AmgLevel &L, const double *Minv);
 void launch_amg_sweep(hipStream_t s, const AmgLevel &L, const AmgLevel &C, int color, int mode);
 void launch_amg_well_sweep(hipStream_t s, const AmgLevel &L);
+void launch_amg_presmooth(hipStream_t s, const AmgLevel &L);
 void launch_amg_restrict(hipStream_t s, const AmgLevel &F, const AmgLevel &C);
 void launch_amg_correct(hipStream_t s, const AmgLevel &F, const AmgLevel &C);
 void launch_cpr_restrict(hipStream_t s, int nb, int n, int nw, const AmgLevel &L,
                          const int *split0, const double *w, const double *hptr, double *v,
                          const double *wq);
 void launch_cpr_finish(hipStream_t s, int nb, int n, int nw, const AmgLevel &L,
-                       const int *split0, Sys sys, const double *v, const double *dinv,
-                       double *z);
+                       const int *split0, const int *colsplit, Sys sys, const double *ap,
+                       const double *v, const double *dinv, double *z);
 enum { kCellsZero = 1, kCellsCorr = 2, kWellsZero = 4, kWellsCorr = 8 };
 
 // A cycle is a sequence of phases on levels: colour sweeps, well sweeps,
@@ -174,7 +176,8 @@ enum { kCellsZero = 1, kCellsCorr = 2, kWellsZero = 4, kWellsCorr = 8 };
 // coarse part of it can run as one workgroup walking a recorded phase list
 // (op = kind | level << 4 | colour << 8 | mode << 12, levels relative to the
 // sub-cycle's root).
-enum { kOpSweep = 0, kOpWells = 1, kOpRestrict = 2, kOpCorrect = 3, kOpCoarse = 4 };
+enum { kOpSweep = 0, kOpWells = 1, kOpRestrict = 2, kOpCorrect = 3, kOpCoarse = 4,
+       kOpPresmooth = 5 };
 constexpr int kSubLevels = 8;          // levels one sub-cycle can span
 constexpr int kSubOps = 4096;          // phase-list capacity
 constexpr int kSubThreads = 1024;
@@ -182,10 +185,11 @@ constexpr int kFusedCellsDefault = 4096;
 inline int amg_op(int kind, int level, int color = 0, int mode = 0) {
     return kind | level << 4 | color << 8 | mode << 12;
 }
-// LDS arrays of one sub-cycle level: doubles (x, b, acw, awc) are offsets
-// from the LDS base, ints (cps, cslot, swell, scell, sps) from the end of
-// the doubles.
-enum { kSubX, kSubB, kSubAcw, kSubAwc, kSubCps, kSubCslot, kSubSwell, kSubScell, kSubSps,
+// LDS arrays of one sub-cycle level: doubles (x, b, acw, awc and, when they
+// fit, the stencil coefficients a; -1 = left in HBM) are offsets from the
+// LDS base, ints (cps, cslot, swell, scell, sps) from the end of the
+// doubles.
+enum { kSubX, kSubB, kSubAcw, kSubAwc, kSubA, kSubCps, kSubCslot, kSubSwell, kSubScell, kSubSps,
        kSubArrays };
 struct AmgSub {
     AmgLevel lv[kSubLevels + 1];       // root first; entries past the coarsest stay empty
@@ -196,6 +200,7 @@ struct AmgSub {
     const int *ops;
     int nops;
     const double *Minv;                // dense inverse of the coarsest level
+    int minvoff;                       // its LDS offset (doubles), -1 = read from HBM
 };
 size_t amg_subcycle_lds(const AmgSub &P);          // dynamic LDS bytes of one launch
 hipError_t amg_subcycle_allow_lds(size_t bytes);
