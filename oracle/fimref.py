@@ -349,6 +349,39 @@ def bilu0_solve(rowptr, colind, lu, b, nb):
     return x
 
 
+def ilu_tiles(nx, ny, nz, tile, well_cells):
+    """Subdomains of block-Jacobi ILU(0) (Sec. 5.1: block Jacobi over
+    subdomains with ILU(0) inside each).  Cell (i, j, k) belongs to the box
+    (i // tx, j // ty, k // tz); a well row joins the box that holds all of
+    its perforated cells, otherwise it is a subdomain of its own.  Returns the
+    subdomain id of every row (cells, then wells)."""
+    tx, ty, tz = tile
+    ntx, nty = -(-nx // tx), -(-ny // ty)
+    c = np.arange(nx * ny * nz)
+    i, j, k = c % nx, (c // nx) % ny, c // (nx * ny)
+    cell_tile = (i // tx) + ntx * ((j // ty) + nty * (k // tz))
+    nt = int(cell_tile.max()) + 1 if len(c) else 0
+    wt = []
+    for w, cells in enumerate(well_cells):
+        ts = set(int(cell_tile[q]) for q in cells)
+        wt.append(ts.pop() if len(ts) == 1 else nt + w)
+    return np.concatenate([cell_tile, np.array(wt, dtype=np.int64)])
+
+
+def bilu0_tiled(rowptr, colind, val, nb, row_tile):
+    """ILU(0) inside each subdomain: the natural-order BILU(0) of A with every
+    block that couples two different subdomains set to zero.  A zero coupling
+    adds nothing to any update, so the factors of each subdomain are those of
+    its own diagonal part and every cross-subdomain block stays zero."""
+    rowptr = np.asarray(rowptr)
+    colind = np.asarray(colind)
+    rows = np.repeat(np.arange(len(rowptr) - 1), np.diff(rowptr))
+    keep = row_tile[rows] == row_tile[colind]
+    v = _f64(val).reshape(-1, nb * nb).copy()
+    v[~keep] = 0.0
+    return bilu0(rowptr, colind, v.reshape(-1), nb)
+
+
 def dense_solve(A, b):
     A = np.array(A, dtype=np.float64, order="C")
     b = np.array(b, dtype=np.float64)

@@ -112,3 +112,77 @@ def test_gmres_zero_rhs_returns_zero(jac_c2s):
     rowptr, colind, val, R, nb = jac_c2s
     x, st, it, rr = fr.gmres_bilu0(rowptr, colind, val, np.zeros_like(R), nb)
     assert st == 0 and it == 0 and np.all(x == 0)
+
+
+# ---------------------------------------------------------------------------
+# block-Jacobi ILU(0) over box subdomains (tiles)
+
+def _model_matrix(res):
+    m = fr.OracleModel(res)
+    R, val = m.assemble(dt=10.0)
+    rowptr, colind = m.pattern()
+    return m, rowptr, colind, val
+
+
+def test_tiled_ilu0_with_single_cell_tiles_is_block_jacobi():
+    # every well spans several layers, so each well row is a subdomain of
+    # its own: ILU(0) of 1x1 blocks is the inverse of the diagonal block
+    res = rv.config_c2_small(7, 9, 3)
+    m, rowptr, colind, val = _model_matrix(res)
+    tiles = fr.ilu_tiles(res.nx, res.ny, res.nz, (1, 1, 1), [w.cells for w in res.wells])
+    assert len(set(tiles.tolist())) == len(rowptr) - 1
+    lu = fr.bilu0_tiled(rowptr, colind, val, m.nb, tiles)
+    x = np.random.default_rng(11).normal(size=(len(rowptr) - 1) * m.nb)
+    y = fr.bilu0_solve(rowptr, colind, lu, x, m.nb)
+    np.testing.assert_allclose(y, fr.bj_apply(fr.bj_setup(rowptr, colind, val, m.nb), x, m.nb),
+                               rtol=1e-12, atol=1e-14 * np.abs(y).max())
+
+
+@pytest.mark.parametrize("tile", [(1, 1, 4), (1, 3, 1)])
+def test_tiled_ilu0_on_line_tiles_is_exact_per_tile(tile):
+    # without wells a line-shaped subdomain has a block tridiagonal matrix,
+    # where ILU(0) drops no fill: the tiled solve must equal the exact solve
+    # of the subdomain-diagonal part of A
+    res = rv.config_c2_small(5, 6, 4)
+    res.wells = []
+    m, rowptr, colind, val = _model_matrix(res)
+    tiles = fr.ilu_tiles(res.nx, res.ny, res.nz, tile, [])
+    lu = fr.bilu0_tiled(rowptr, colind, val, m.nb, tiles)
+    nb = m.nb
+    A = fr.bsr_to_dense(rowptr, colind, val, nb)
+    rt = np.repeat(tiles, nb)
+    Ablk = np.where(rt[:, None] == rt[None, :], A, 0.0)
+    b = np.random.default_rng(12).normal(size=A.shape[0])
+    x = fr.bilu0_solve(rowptr, colind, lu, b, nb)
+    np.testing.assert_allclose(x, np.linalg.solve(Ablk, b), rtol=1e-10, atol=1e-12 * np.abs(x).max())
+
+
+def test_tiled_ilu0_reproduces_the_tile_part_of_a():
+    # (L U)_ij = A_ij on the pattern inside each subdomain, 0 across them
+    res = rv.config_c2_small(6, 7, 4)
+    m, rowptr, colind, val = _model_matrix(res)
+    nb = m.nb
+    tiles = fr.ilu_tiles(res.nx, res.ny, res.nz, (3, 4, 2), [w.cells for w in res.wells])
+    lu = fr.bilu0_tiled(rowptr, colind, val, nb, tiles).reshape(-1, nb, nb)
+    nrows = len(rowptr) - 1
+    L = np.eye(nrows * nb)
+    U = np.zeros((nrows * nb, nrows * nb))
+    for r in range(nrows):
+        for q in range(rowptr[r], rowptr[r + 1]):
+            c = colind[q]
+            blk = lu[q]
+            if c < r:
+                L[r * nb:(r + 1) * nb, c * nb:(c + 1) * nb] = blk
+            elif c == r:
+                U[r * nb:(r + 1) * nb, c * nb:(c + 1) * nb] = np.linalg.inv(blk)
+            else:
+                U[r * nb:(r + 1) * nb, c * nb:(c + 1) * nb] = blk
+    LU = L @ U
+    A = fr.bsr_to_dense(rowptr, colind, val, nb)
+    rt = np.repeat(tiles, nb)
+    for r in range(nrows):
+        for q in range(rowptr[r], rowptr[r + 1]):
+            c = colind[q]
+            got = LU[r * nb:(r + 1) * nb, c * nb:(c + 1) * nb]
+            want = A[r * nb:(r + 1) * nb, c * nb:(c + 1) * nb] if tiles[r] == tiles[c] else 0.0
+            np.testing.assert_allclose(got, want, rtol=1e-10, atol=1e-9 * np.abs(A).max())
