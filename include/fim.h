@@ -65,7 +65,8 @@ enum { FIM_DEADOIL_OW = 2, FIM_BLACKOIL_3P = 3 };          /* model id == block 
 enum { FIM_PROD = 0, FIM_INJ_WATER = 1, FIM_INJ_GAS = 2 };  /* well kind */
 enum { FIM_BHP = 0, FIM_RATE = 1 };                         /* well control */
 enum { FIM_UNSAT = 0, FIM_SAT = 1 };                        /* phase-state flag */
-enum { FIM_PREC_BJ = 0, FIM_PREC_CPR = 2 };                /* preconditioner */
+enum { FIM_PREC_BJ = 0, FIM_PREC_ILU0 = 1, FIM_PREC_CPR = 2,  /* preconditioner */
+       FIM_PREC_CPR_ILU0 = 3 };
 enum { FIM_FP64 = 0 };                                      /* precision mode */
 
 /* Cartesian grid: dx[nx], dy[ny], dz[nz] in ft, top = depth of the top face. */
@@ -131,12 +132,19 @@ typedef struct {
  * residual lin_rtol or max_lin iterations per Newton iteration (restart
  * in [1, 40]); an unconverged solve is still used when it reduced the
  * residual.  The solver is flexible GMRES, right-preconditioned by block
- * Jacobi (FIM_PREC_BJ) or by CPR (FIM_PREC_CPR): a quasi-IMPES pressure
+ * Jacobi (FIM_PREC_BJ), by block-Jacobi ILU(0) over box subdomains
+ * (FIM_PREC_ILU0) or by CPR (FIM_PREC_CPR, FIM_PREC_CPR_ILU0): a quasi-IMPES pressure
  * stage solved by one aggregation-AMG cycle (amg_cycle 1 = V, 2 = W, 0 =
  * default: V at the finest level and W below it, a value >= 16 = W on the
  * levels with at most that many cells and wells and V above them; amg_sweeps red-black Gauss-Seidel sweeps before and after the
  * coarse correction, 0 = default 1) followed by block Jacobi on the
- * remaining residual.  forcing != 0 replaces the fixed lin_rtol by the
+ * remaining residual (FIM_PREC_CPR_ILU0: block-Jacobi ILU(0) on it).
+ * Block-Jacobi ILU(0) (paper Sec. 5.1): the subdomains are boxes of
+ * tile_nx x tile_ny x tile_nz cells (0 = 8; a size >= the grid takes the
+ * whole axis), each with the wells whose perforations all lie in it (other
+ * wells stand alone); inside a subdomain the factors are the natural-order
+ * block ILU(0) of its diagonal part of the Jacobian, so one box covering
+ * the grid gives the plain natural-order BILU(0).  forcing != 0 replaces the fixed lin_rtol by the
  * Eisenstat-Walker forcing term (choice 2, gamma 0.9, alpha 2) between 1e-2
  * and lin_rtol.  graphs != 0 replays each Arnoldi step after its SpMV as a
  * captured HIP graph.  amg_fused: the coarse part of the AMG cycle, from
@@ -150,6 +158,7 @@ typedef struct {
     double ds_max, dp_max, lin_rtol;
     int32_t max_newton, max_lin, restart, max_cuts;
     int32_t precond, precision, profile, amg_cycle, amg_sweeps, graphs, forcing, amg_fused;
+    int32_t tile_nx, tile_ny, tile_nz, reserved;
 } fim_options;
 
 #define FIM_MAX_SUB 256

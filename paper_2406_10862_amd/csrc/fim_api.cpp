@@ -117,6 +117,12 @@ struct fim_ctx {
     std::vector<const int *> cfs_ptr, cfs_idx;     // coarse slot -> fine slots, per level
     double *Mden = nullptr, *Minv = nullptr, *colk = nullptr, *wq = nullptr;
     double *ap = nullptr;                           // [nnzb][nb] pressure column of A
+    // block-Jacobi ILU(0): tiles, factors and the CPR second-stage scratch
+    IluTiles ilu{};
+    int ilu_dims[3] = {0, 0, 0};
+    std::vector<int> perf_cell_h;                   // perforated cell of each perforation
+    double *lu = nullptr, *cprt = nullptr, *zp = nullptr;
+    int *ilu_bad = nullptr;
     int sub_root = -1;                              // first level of the fused sub-cycle
     int *sub_ops = nullptr;                         // [kSubOps] its phase list
     AmgSub sub{};
@@ -211,8 +217,9 @@ static void check_options(const fim_options *o) {
             "max_lin, max_newton >= 1 and max_cuts >= 0 required");
     REQUIRE(o->ds_max > 0 && o->dp_max > 0 && o->lin_rtol > 0 && o->lin_rtol < 1,
             "ds_max, dp_max > 0 and 0 < lin_rtol < 1 required");
-    REQUIRE(o->precond == FIM_PREC_BJ || o->precond == FIM_PREC_CPR, "unknown preconditioner %d",
-            o->precond);
+    REQUIRE(o->precond >= FIM_PREC_BJ && o->precond <= FIM_PREC_CPR_ILU0,
+            "unknown preconditioner %d", o->precond);
+    REQUIRE(o->tile_nx >= 0 && o->tile_ny >= 0 && o->tile_nz >= 0, "tile sizes must be >= 0");
     REQUIRE(o->amg_cycle >= 0 && (o->amg_cycle <= 2 || o->amg_cycle >= 16),
             "amg_cycle must be 0, 1, 2 or a level size >= 16");
     REQUIRE(o->amg_sweeps >= 0 && o->amg_sweeps <= 8, "amg_sweeps must be in [0, 8]");
@@ -381,6 +388,7 @@ static void build_amg(fim_ctx *c, const std::vector<int> &sorted_cells,
 }
 
 static void build_subcycle(fim_ctx *c);
+static void build_ilu(fim_ctx *c);
 
 static int create_impl(const fim_grid *grid, const fim_rock *rock, const fim_fluid *fl,
                        int32_t nwells, const fim_well *wells, const fim_options *opt,
@@ -600,6 +608,7 @@ static int create_impl(const fim_grid *grid, const fim_rock *rock, const fim_flu
         c->ydev = c->alloc<double>(kMaxRestart + 2);
         c->reorth = c->alloc<int>(1);
         alloc_krylov(c, opt->restart);
+        c->perf_cell_h = sorted_cells;
         build_amg(c, sorted_cells, pwell_h);
         {
             // the level-0 AMG entry of every column (colour-split cell or
@@ -621,6 +630,7 @@ static int create_impl(const fim_grid *grid, const fim_rock *rock, const fim_flu
             c->sync();
         }
         build_subcycle(c);
+        build_ilu(c);
         const size_t np = (size_t)(kMaxRestart + 2) * 2048 + (size_t)2048 * 16;
         c->partials = c->alloc<double>(np);
         c->scal = c->alloc<double>(S_COUNT);
@@ -831,9 +841,86 @@ static void build_subcycle(fim_ctx *c) {
     c->sub_root = root;
 }
 
+static bool uses_ilu(const fim_options &o) {
+    return o.precond == FIM_PREC_ILU0 || o.precond == FIM_PREC_CPR_ILU0;
+}
+static bool uses_cpr(const fim_options &o) {
+    return o.precond == FIM_PREC_CPR || o.precond == FIM_PREC_CPR_ILU0;
+}
+
+// Subdomains of block-Jacobi ILU(0): boxes of the option's size, each with
+// the wells whose perforations all lie in it (the others stand alone).
+static void build_ilu(fim_ctx *c) {
+    if (!uses_ilu(c->opt)) return;
+    const int nx = c->g.nx, ny = c->g.ny, nz = c->g.nz, n = c->n, nw = c->nw;
+    int d[3] = {c->opt.tile_nx, c->opt.tile_ny, c->opt.tile_nz};
+    const int gd[3] = {nx, ny, nz};
+    for (int a = 0; a < 3; ++a) d[a] = std::min(d[a] > 0 ? d[a] : 8, gd[a]);
+    if (c->lu && d[0] == c->ilu_dims[0] && d[1] == c->ilu_dims[1] && d[2] == c->ilu_dims[2]) return;
+    IluTiles T{};
+    T.tx = d[0];
+    T.ty = d[1];
+    T.tz = d[2];
+    T.ntx = (nx + T.tx - 1) / T.tx;
+    T.nty = (ny + T.ty - 1) / T.ty;
+    T.ntz = (nz + T.tz - 1) / T.tz;
+    const int ntiles = T.ntx * T.nty * T.ntz;
+    std::vector<int> rtile(n + nw), twp(ntiles + 1, 0), tw, wlocal(nw, -1), single;
+    for (int cell = 0; cell < n; ++cell) {
+        const int i = cell % nx, j = (cell / nx) % ny, k = cell / (nx * ny);
+        rtile[cell] = i / T.tx + T.ntx * (j / T.ty + T.nty * (k / T.tz));
+    }
+    std::vector<std::vector<int>> joined(ntiles);
+    for (int w = 0; w < nw; ++w) {
+        int t = -1;
+        bool one = true;
+        for (int p = c->wps[w]; p < c->wps[w + 1]; ++p) {
+            const int tp = rtile[c->perf_cell_h[p]];
+            if (t < 0) t = tp;
+            else if (tp != t) one = false;
+        }
+        if (one && t >= 0) {
+            rtile[n + w] = t;
+            wlocal[w] = (int)joined[t].size();
+            joined[t].push_back(w);
+        } else {
+            rtile[n + w] = ntiles + w;
+            single.push_back(w);
+        }
+    }
+    for (int t = 0; t < ntiles; ++t) {
+        twp[t + 1] = twp[t] + (int)joined[t].size();
+        tw.insert(tw.end(), joined[t].begin(), joined[t].end());
+        T.maxwells = std::max(T.maxwells, (int)joined[t].size());
+    }
+    int dev = 0, lds_max = 0;
+    HIPCHECK(hipGetDevice(&dev));
+    HIPCHECK(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    REQUIRE(ilu_solve_lds(c->nb, T) <= (size_t)lds_max,
+            "ILU(0) tile %d x %d x %d needs %zu bytes of LDS (at most %d)", T.tx, T.ty, T.tz,
+            ilu_solve_lds(c->nb, T), lds_max);
+    T.rtile = c->upload(rtile.data(), rtile.size());
+    T.twp = c->upload(twp.data(), twp.size());
+    T.tw = c->upload(tw.data(), std::max<size_t>(tw.size(), 1));
+    T.wlocal = c->upload(wlocal.data(), std::max<size_t>(wlocal.size(), 1));
+    T.single = c->upload(single.data(), std::max<size_t>(single.size(), 1));
+    T.nsingle = (int)single.size();
+    c->sync();                                  // the host vectors above are temporaries
+    HIPCHECK(ilu_allow_lds(c->nb, ilu_solve_lds(c->nb, T)));
+    if (!c->lu) {
+        c->lu = c->alloc<double>((size_t)c->nnzb * c->nb * c->nb);
+        c->cprt = c->alloc<double>(c->nvec);
+        c->zp = c->alloc<double>(c->nrows);
+        c->ilu_bad = c->alloc<int>(1);
+    }
+    c->ilu = T;
+    for (int a = 0; a < 3; ++a) c->ilu_dims[a] = d[a];
+}
+
 static void prec_setup(fim_ctx *c) {
-    launch_bj_setup(c->s, c->nb, c->nrows, c->diagpos, c->val, c->dinv, c->bad);
-    if (c->opt.precond == FIM_PREC_CPR) {
+    if (!uses_ilu(c->opt)) launch_bj_setup(c->s, c->nb, c->nrows, c->diagpos, c->val, c->dinv, c->bad);
+    else launch_ilu_factor(c->s, c->nb, c->g, c->ilu, c->sys(), c->lu, c->ilu_bad);
+    if (uses_cpr(c->opt)) {
         launch_amg_extract(c->s, c->nb, c->lv[0], c->g, c->wells(), c->sys(), c->wq, c->ap);
         for (size_t l = 1; l < c->lv.size(); ++l)
             launch_amg_coarsen(c->s, c->lv[l - 1], c->lv[l], c->cfs_ptr[l], c->cfs_idx[l]);
@@ -845,7 +932,16 @@ static void prec_setup(fim_ctx *c) {
 // z = M^-1 v.  With hptr set, v = w / *hptr is formed (and stored) first,
 // as for a new Arnoldi vector; without it v = w.
 static void precondition(fim_ctx *c, const double *w, const double *hptr, double *v, double *z) {
-    if (c->opt.precond == FIM_PREC_CPR) {
+    if (c->opt.precond == FIM_PREC_CPR_ILU0) {
+        launch_cpr_restrict(c->s, c->nb, c->n, c->nw, c->lv[0], c->split0, w, hptr, v, c->wq);
+        amg_cycle(c, 0);
+        launch_cpr_resid(c->s, c->nb, c->n, c->nw, c->lv[0], c->split0, c->colsplit, c->sys(), c->ap,
+                         hptr ? v : w, c->cprt, c->zp);
+        launch_ilu_solve(c->s, c->nb, c->g, c->ilu, c->sys(), c->lu, c->cprt, c->zp, z);
+    } else if (c->opt.precond == FIM_PREC_ILU0) {
+        if (hptr) launch_normalize(c->s, c->nvec, w, hptr, v);
+        launch_ilu_solve(c->s, c->nb, c->g, c->ilu, c->sys(), c->lu, hptr ? v : w, nullptr, z);
+    } else if (c->opt.precond == FIM_PREC_CPR) {
         launch_cpr_restrict(c->s, c->nb, c->n, c->nw, c->lv[0], c->split0, w, hptr, v, c->wq);
         amg_cycle(c, 0);
         launch_cpr_finish(c->s, c->nb, c->n, c->nw, c->lv[0], c->split0, c->colsplit, c->sys(), c->ap, hptr ? v : w,
@@ -1292,6 +1388,7 @@ int fim_set_options(fim_ctx *c, const fim_options *opt) {
         }
         c->opt = *opt;
         build_subcycle(c);
+        build_ilu(c);
         return FIM_OK;
     });
 }

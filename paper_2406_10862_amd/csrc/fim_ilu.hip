@@ -1,0 +1,359 @@
+// fim_ilu.hip - block-Jacobi ILU(0) over box subdomains (paper Sec. 5.1:
+// block Jacobi over subdomains with ILU(0) inside each, used as the
+// smoother of CPR and on its own).
+//
+// A subdomain ("tile") is a box of tx x ty x tz cells plus every well whose
+// perforations all lie in it; other wells stand alone.  Inside a tile the
+// factorisation is the natural-order block ILU(0) of the tile's diagonal
+// part of A (couplings to other tiles dropped): L_ik = A_ik inv(U_kk), then
+// A_ij -= L_ik U_kj for the (i, j) of the pattern, the inverted pivot block
+// kept in the diagonal slot.  With one tile covering the grid it is the
+// plain natural-order BILU(0).
+//
+// On a 7-point stencil row i depends only on rows in the previous
+// hyperplane li + lj + lk - 1 of its tile (and a well row on all of its
+// cells), so one workgroup per tile walks the hyperplanes with a barrier
+// between them; tiles run in parallel.  The triangular solves walk a row's
+// blocks in the pattern's canonical order (-z, -y, -x, diagonal, +x, +y,
+// +z, then wells), so neighbours are found from the row's own position,
+// and keep the tile's vector in LDS.
+#include <math.h>
+
+#include "fim_block.h"
+#include "fim_internal.h"
+
+namespace fim {
+
+struct TileBox {
+    int i0, j0, k0, txe, tye, tze;   // origin and extents (clipped at the grid edge)
+};
+
+__device__ inline TileBox tile_box(const Grid &g, const IluTiles &T, int b) {
+    TileBox t;
+    const int bi = b % T.ntx, bj = (b / T.ntx) % T.nty, bk = b / (T.ntx * T.nty);
+    t.i0 = bi * T.tx;
+    t.j0 = bj * T.ty;
+    t.k0 = bk * T.tz;
+    t.txe = min(T.tx, g.nx - t.i0);
+    t.tye = min(T.ty, g.ny - t.j0);
+    t.tze = min(T.tz, g.nz - t.k0);
+    return t;
+}
+
+// ILU(0) of one row in place (lu holds A's values on entry for rows not yet
+// factored): IKJ form restricted to the row's tile.  The row's lower
+// neighbours in its tile are factored already.
+template <int NB>
+__device__ void factor_row(int row, const IluTiles &T, const Sys &sys, double *lu, int *bad) {
+    constexpr int B2 = NB * NB;
+    const int t = T.rtile[row];
+    const int b0 = sys.rowptr[row], b1 = sys.rowptr[row + 1];
+    for (int q = b0; q < b1; ++q)
+#pragma unroll
+        for (int e = 0; e < B2; ++e) lu[(size_t)q * B2 + e] = sys.val[(size_t)q * B2 + e];
+    for (int qk = b0; qk < b1; ++qk) {
+        const int k = sys.colind[qk];
+        if (k >= row) break;
+        if (T.rtile[k] != t) continue;
+        double a[B2], u[B2], l[B2];
+#pragma unroll
+        for (int e = 0; e < B2; ++e) {
+            a[e] = lu[(size_t)qk * B2 + e];
+            u[e] = lu[(size_t)sys.diagpos[k] * B2 + e];
+        }
+        block_mul<NB>(a, u, l);
+#pragma unroll
+        for (int e = 0; e < B2; ++e) lu[(size_t)qk * B2 + e] = l[e];
+        const int k0 = sys.rowptr[k], k1 = sys.rowptr[k + 1];
+        for (int qj = qk + 1; qj < b1; ++qj) {
+            const int j = sys.colind[qj];
+            if (T.rtile[j] != t) continue;
+            for (int qkj = k0; qkj < k1; ++qkj) {
+                if (sys.colind[qkj] != j) continue;
+                double ukj[B2], p[B2];
+#pragma unroll
+                for (int e = 0; e < B2; ++e) ukj[e] = lu[(size_t)qkj * B2 + e];
+                block_mul<NB>(l, ukj, p);
+#pragma unroll
+                for (int e = 0; e < B2; ++e) lu[(size_t)qj * B2 + e] -= p[e];
+            }
+        }
+    }
+    const int di = sys.diagpos[row];
+    double d[B2], inv[B2];
+#pragma unroll
+    for (int e = 0; e < B2; ++e) d[e] = lu[(size_t)di * B2 + e];
+    if (!invert_block<NB>(d, inv)) {
+        *bad = 1;
+#pragma unroll
+        for (int e = 0; e < B2; ++e) inv[e] = (e % (NB + 1) == 0) ? 1.0 : 0.0;
+    }
+#pragma unroll
+    for (int e = 0; e < B2; ++e) lu[(size_t)di * B2 + e] = inv[e];
+}
+
+// One workgroup per tile, then one for the wells that stand alone.
+template <int NB>
+__global__ void k_ilu_factor(Grid g, IluTiles T, Sys sys, double *lu, int *bad) {
+    const int b = blockIdx.x;
+    const int ntiles = T.ntx * T.nty * T.ntz;
+    if (b >= ntiles) {
+        for (int e = threadIdx.x; e < T.nsingle; e += blockDim.x)
+            factor_row<NB>(g.n + T.single[e], T, sys, lu, bad);
+        return;
+    }
+    const TileBox tb = tile_box(g, T, b);
+    const int nlev = tb.txe + tb.tye + tb.tze - 2;
+    for (int s = 0; s < nlev; ++s) {
+        for (int p = threadIdx.x; p < tb.txe * tb.tye; p += blockDim.x) {
+            const int li = p % tb.txe, lj = p / tb.txe, lk = s - li - lj;
+            if (lk < 0 || lk >= tb.tze) continue;
+            const int row = (tb.i0 + li) + g.nx * ((tb.j0 + lj) + g.ny * (tb.k0 + lk));
+            factor_row<NB>(row, T, sys, lu, bad);
+        }
+        __syncthreads();
+    }
+    for (int e = T.twp[b] + threadIdx.x; e < T.twp[b + 1]; e += blockDim.x)
+        factor_row<NB>(g.n + T.tw[e], T, sys, lu, bad);
+}
+
+// acc -= blk * v (block-vector product summed first, as a matrix-vector
+// product would)
+template <int NB>
+__device__ inline void sub_mv(double (&acc)[NB], const double *blk, const double *v) {
+#pragma unroll
+    for (int r = 0; r < NB; ++r) {
+        double t = blk[r * NB] * v[0];
+#pragma unroll
+        for (int c = 1; c < NB; ++c) t += blk[r * NB + c] * v[c];
+        acc[r] -= t;
+    }
+}
+
+// x = M^-1 b: forward (L y = b, L unit lower) and backward (U x = y) inside
+// every tile; zp, when given, is added to the first slot of every row of x
+// (the pressure correction of the CPR first stage).
+template <int NB>
+__global__ void k_ilu_solve(Grid g, IluTiles T, Sys sys, const double *__restrict__ lu,
+                            const double *__restrict__ b, const double *__restrict__ zp,
+                            double *__restrict__ x) {
+    constexpr int B2 = NB * NB;
+    extern __shared__ double y[];
+    const int blk = blockIdx.x;
+    const int ntiles = T.ntx * T.nty * T.ntz;
+    const int n = g.n;
+    if (blk >= ntiles) {
+        for (int e = threadIdx.x; e < T.nsingle; e += blockDim.x) {
+            const int r = n + T.single[e];
+            double acc[NB] = {};
+            sub_mv<NB>(acc, lu + (size_t)sys.diagpos[r] * B2, b + (size_t)r * NB);
+#pragma unroll
+            for (int u = 0; u < NB; ++u)
+                x[(size_t)r * NB + u] = -acc[u] + ((u == 0 && zp) ? zp[r] : 0.0);
+        }
+        return;
+    }
+    const TileBox tb = tile_box(g, T, blk);
+    const int sxy = tb.txe * tb.tye, ncell = sxy * tb.tze;
+    const int w0 = T.twp[blk], nwt = T.twp[blk + 1] - w0;
+    const int nlev = tb.txe + tb.tye + tb.tze - 2;
+    // forward over the hyperplanes
+    for (int s = 0; s < nlev; ++s) {
+        for (int p = threadIdx.x; p < sxy; p += blockDim.x) {
+            const int li = p % tb.txe, lj = p / tb.txe, lk = s - li - lj;
+            if (lk < 0 || lk >= tb.tze) continue;
+            const int i = tb.i0 + li, j = tb.j0 + lj, k = tb.k0 + lk;
+            const int r = i + g.nx * (j + g.ny * k), l = li + tb.txe * (lj + tb.tye * lk);
+            double acc[NB];
+#pragma unroll
+            for (int u = 0; u < NB; ++u) acc[u] = b[(size_t)r * NB + u];
+            int q = sys.rowptr[r];
+            if (k > 0) {
+                if (lk > 0) sub_mv<NB>(acc, lu + (size_t)q * B2, y + (size_t)(l - sxy) * NB);
+                ++q;
+            }
+            if (j > 0) {
+                if (lj > 0) sub_mv<NB>(acc, lu + (size_t)q * B2, y + (size_t)(l - tb.txe) * NB);
+                ++q;
+            }
+            if (i > 0 && li > 0) sub_mv<NB>(acc, lu + (size_t)q * B2, y + (size_t)(l - 1) * NB);
+#pragma unroll
+            for (int u = 0; u < NB; ++u) y[(size_t)l * NB + u] = acc[u];
+        }
+        __syncthreads();
+    }
+    // the tile's wells: lower part = their perforated cells, all in the tile
+    for (int e = threadIdx.x; e < nwt; e += blockDim.x) {
+        const int r = n + T.tw[w0 + e];
+        double acc[NB];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) acc[u] = b[(size_t)r * NB + u];
+        for (int q = sys.rowptr[r]; q < sys.rowptr[r + 1]; ++q) {
+            const int col = sys.colind[q];
+            if (col >= n) break;
+            const int ci = col % g.nx, cj = (col / g.nx) % g.ny, ck = col / (g.nx * g.ny);
+            const int lc = (ci - tb.i0) + tb.txe * ((cj - tb.j0) + tb.tye * (ck - tb.k0));
+            sub_mv<NB>(acc, lu + (size_t)q * B2, y + (size_t)lc * NB);
+        }
+        // well rows have no upper part: x = inv(U_ww) y
+        double xw[NB] = {};
+        sub_mv<NB>(xw, lu + (size_t)sys.diagpos[r] * B2, acc);
+#pragma unroll
+        for (int u = 0; u < NB; ++u) y[(size_t)(ncell + e) * NB + u] = -xw[u];
+    }
+    __syncthreads();
+    // backward over the hyperplanes
+    for (int s = nlev - 1; s >= 0; --s) {
+        for (int p = threadIdx.x; p < sxy; p += blockDim.x) {
+            const int li = p % tb.txe, lj = p / tb.txe, lk = s - li - lj;
+            if (lk < 0 || lk >= tb.tze) continue;
+            const int i = tb.i0 + li, j = tb.j0 + lj, k = tb.k0 + lk;
+            const int r = i + g.nx * (j + g.ny * k), l = li + tb.txe * (lj + tb.tye * lk);
+            double acc[NB];
+#pragma unroll
+            for (int u = 0; u < NB; ++u) acc[u] = y[(size_t)l * NB + u];
+            const int qd = sys.rowptr[r] + (k > 0) + (j > 0) + (i > 0);
+            int q = qd + 1;
+            if (i + 1 < g.nx) {
+                if (li + 1 < tb.txe) sub_mv<NB>(acc, lu + (size_t)q * B2, y + (size_t)(l + 1) * NB);
+                ++q;
+            }
+            if (j + 1 < g.ny) {
+                if (lj + 1 < tb.tye) sub_mv<NB>(acc, lu + (size_t)q * B2, y + (size_t)(l + tb.txe) * NB);
+                ++q;
+            }
+            if (k + 1 < g.nz) {
+                if (lk + 1 < tb.tze) sub_mv<NB>(acc, lu + (size_t)q * B2, y + (size_t)(l + sxy) * NB);
+                ++q;
+            }
+            for (; q < sys.rowptr[r + 1]; ++q) {
+                const int w = sys.colind[q] - n;
+                if (T.rtile[n + w] == blk)
+                    sub_mv<NB>(acc, lu + (size_t)q * B2, y + (size_t)(ncell + T.wlocal[w]) * NB);
+            }
+            double xr[NB] = {};
+            sub_mv<NB>(xr, lu + (size_t)qd * B2, acc);
+#pragma unroll
+            for (int u = 0; u < NB; ++u) y[(size_t)l * NB + u] = -xr[u];
+        }
+        __syncthreads();
+    }
+    for (int l = threadIdx.x; l < ncell + nwt; l += blockDim.x) {
+        int r;
+        if (l < ncell) {
+            const int li = l % tb.txe, lj = (l / tb.txe) % tb.tye, lk = l / sxy;
+            r = (tb.i0 + li) + g.nx * ((tb.j0 + lj) + g.ny * (tb.k0 + lk));
+        } else {
+            r = n + T.tw[w0 + (l - ncell)];
+        }
+#pragma unroll
+        for (int u = 0; u < NB; ++u)
+            x[(size_t)r * NB + u] = y[(size_t)l * NB + u] + ((u == 0 && zp) ? zp[r] : 0.0);
+    }
+}
+
+// v = w / h for a new Arnoldi vector (zero when h is not a positive number)
+__global__ __launch_bounds__(kBlock) void k_normalize(long nvec, const double *__restrict__ w,
+                                                      const double *__restrict__ hptr,
+                                                      double *__restrict__ v) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nvec) return;
+    const double h = *hptr;
+    v[e] = (h > 0.0 && isfinite(h)) ? w[e] / h : 0.0;
+}
+
+// Residual of the CPR first stage for the second: t = v - A x1, with x1 the
+// pressure correction in the pressure slot of every row (A x1 from the
+// compact pressure column ap); zp[r] = that correction.  G lanes per row.
+template <int NB, int G>
+__global__ __launch_bounds__(kBlock) void k_cpr_resid(int n, int nw, AmgLevel L,
+                                                      const int *__restrict__ split0,
+                                                      const int *__restrict__ colsplit, Sys sys,
+                                                      const double *__restrict__ ap,
+                                                      const double *__restrict__ v,
+                                                      double *__restrict__ t,
+                                                      double *__restrict__ zp) {
+    const int lg = threadIdx.x & (G - 1);
+    const long bk = xcd_block(blockIdx.x, gridDim.x);
+    const int r = (int)((bk * blockDim.x + threadIdx.x) / G);
+    const int nrows = n + nw;
+    double a[NB];
+#pragma unroll
+    for (int e = 0; e < NB; ++e) a[e] = 0.0;
+    if (r < nrows) {
+        const int b = sys.rowptr[r], e = sys.rowptr[r + 1];
+        for (int q = b + lg; q < e; q += G) {
+            const double p = L.x[__builtin_nontemporal_load(colsplit + q)];
+#pragma unroll
+            for (int u = 0; u < NB; ++u) a[u] += __builtin_nontemporal_load(ap + (size_t)q * NB + u) * p;
+        }
+    }
+#pragma unroll
+    for (int off = G / 2; off >= 1; off >>= 1)
+#pragma unroll
+        for (int u = 0; u < NB; ++u) a[u] += __shfl_xor(a[u], off, 64);
+    if (r >= nrows || lg != 0) return;
+#pragma unroll
+    for (int u = 0; u < NB; ++u) t[(size_t)r * NB + u] = v[(size_t)r * NB + u] - a[u];
+    zp[r] = r < n ? L.x[split0[r]] : L.x[2 * L.half + (r - n)];
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+
+void launch_ilu_factor(hipStream_t s, int nb, Grid g, const IluTiles &T, Sys sys, double *lu,
+                       int *bad) {
+    const int nblk = T.ntx * T.nty * T.ntz + (T.nsingle > 0 ? 1 : 0);
+    const int bs = ilu_threads(T);
+    if (nb == 2) hipLaunchKernelGGL(k_ilu_factor<2>, dim3(nblk), dim3(bs), 0, s, g, T, sys, lu, bad);
+    else hipLaunchKernelGGL(k_ilu_factor<3>, dim3(nblk), dim3(bs), 0, s, g, T, sys, lu, bad);
+}
+
+int ilu_threads(const IluTiles &T) {
+    const int pairs = T.tx * T.ty;
+    return pairs >= 256 ? 256 : ((pairs + 63) / 64) * 64;
+}
+
+size_t ilu_solve_lds(int nb, const IluTiles &T) {
+    return (size_t)(T.tx * T.ty * T.tz + T.maxwells) * nb * sizeof(double);
+}
+
+hipError_t ilu_allow_lds(int nb, size_t bytes) {
+    if (nb == 2)
+        return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ilu_solve<2>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ilu_solve<3>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+void launch_ilu_solve(hipStream_t s, int nb, Grid g, const IluTiles &T, Sys sys,
+                      const double *lu, const double *b, const double *zp, double *x) {
+    const int nblk = T.ntx * T.nty * T.ntz + (T.nsingle > 0 ? 1 : 0);
+    const int bs = ilu_threads(T);
+    const size_t lds = ilu_solve_lds(nb, T);
+    if (nb == 2)
+        hipLaunchKernelGGL(k_ilu_solve<2>, dim3(nblk), dim3(bs), lds, s, g, T, sys, lu, b, zp, x);
+    else
+        hipLaunchKernelGGL(k_ilu_solve<3>, dim3(nblk), dim3(bs), lds, s, g, T, sys, lu, b, zp, x);
+}
+
+void launch_normalize(hipStream_t s, long nvec, const double *w, const double *hptr, double *v) {
+    hipLaunchKernelGGL(k_normalize, dim3((unsigned)((nvec + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                       s, nvec, w, hptr, v);
+}
+
+void launch_cpr_resid(hipStream_t s, int nb, int n, int nw, const AmgLevel &L, const int *split0,
+                      const int *colsplit, Sys sys, const double *ap, const double *v, double *t,
+                      double *zp) {
+    constexpr int G = 8;
+    const long threads = ((long)n + nw) * G;
+    const dim3 grid((unsigned)((threads + kBlock - 1) / kBlock));
+    if (nb == 2)
+        hipLaunchKernelGGL((k_cpr_resid<2, G>), grid, dim3(kBlock), 0, s, n, nw, L, split0, colsplit,
+                           sys, ap, v, t, zp);
+    else
+        hipLaunchKernelGGL((k_cpr_resid<3, G>), grid, dim3(kBlock), 0, s, n, nw, L, split0, colsplit,
+                           sys, ap, v, t, zp);
+}
+
+}  // namespace fim

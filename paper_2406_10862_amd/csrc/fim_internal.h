@@ -171,6 +171,28 @@ void launch_cpr_finish(hipStream_t s, int nb, int n, int nw, const AmgLevel &L,
                        const double *v, const double *dinv, double *z);
 enum { kCellsZero = 1, kCellsCorr = 2, kWellsZero = 4, kWellsCorr = 8 };
 
+// ---- block-Jacobi ILU(0) over box subdomains (fim_ilu.hip) ------------------
+struct IluTiles {
+    int tx, ty, tz;             // tile extents (cells)
+    int ntx, nty, ntz;          // tiles per axis
+    const int *rtile;           // [n+nw] subdomain of each row (wells alone: ntiles + w)
+    const int *twp, *tw;        // [ntiles+1], wells joined to each tile (ascending)
+    const int *wlocal;          // [nw] slot of a joined well among its tile's wells
+    const int *single;          // [nsingle] wells that stand alone
+    int nsingle, maxwells;      // maxwells: most wells joined to one tile
+};
+int ilu_threads(const IluTiles &T);
+size_t ilu_solve_lds(int nb, const IluTiles &T);
+hipError_t ilu_allow_lds(int nb, size_t bytes);
+void launch_ilu_factor(hipStream_t s, int nb, Grid g, const IluTiles &T, Sys sys, double *lu,
+                       int *bad);
+void launch_ilu_solve(hipStream_t s, int nb, Grid g, const IluTiles &T, Sys sys,
+                      const double *lu, const double *b, const double *zp, double *x);
+void launch_normalize(hipStream_t s, long nvec, const double *w, const double *hptr, double *v);
+void launch_cpr_resid(hipStream_t s, int nb, int n, int nw, const AmgLevel &L, const int *split0,
+                      const int *colsplit, Sys sys, const double *ap, const double *v, double *t,
+                      double *zp);
+
 // A cycle is a sequence of phases on levels: colour sweeps, well sweeps,
 // restrictions, corrections and the dense coarsest solve.  The
 // coarse part of it can run as one workgroup walking a recorded phase list

@@ -60,7 +60,9 @@ class FimOptions(C.Structure):
                 ("max_newton", C.c_int32), ("max_lin", C.c_int32), ("restart", C.c_int32),
                 ("max_cuts", C.c_int32), ("precond", C.c_int32), ("precision", C.c_int32),
                 ("profile", C.c_int32), ("amg_cycle", C.c_int32), ("amg_sweeps", C.c_int32),
-                ("graphs", C.c_int32), ("forcing", C.c_int32), ("amg_fused", C.c_int32)]
+                ("graphs", C.c_int32), ("forcing", C.c_int32), ("amg_fused", C.c_int32),
+                ("tile_nx", C.c_int32), ("tile_ny", C.c_int32), ("tile_nz", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class FimStepReport(C.Structure):
@@ -162,7 +164,8 @@ def options_struct(o: rv.Options, profile=False) -> FimOptions:
                       restart=o.restart, max_cuts=o.max_cuts, precond=o.precond,
                       precision=o.precision, profile=1 if profile else 0,
                       amg_cycle=o.amg_cycle, amg_sweeps=o.amg_sweeps, graphs=o.graphs,
-                      forcing=o.forcing, amg_fused=o.amg_fused)
+                      forcing=o.forcing, amg_fused=o.amg_fused,
+                      tile_nx=o.tile[0], tile_ny=o.tile[1], tile_nz=o.tile[2], reserved=0)
 
 
 class Fim:

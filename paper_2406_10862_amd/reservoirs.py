@@ -30,7 +30,7 @@ PROD, INJ_WATER, INJ_GAS = 0, 1, 2
 BHP, RATE = 0, 1
 
 # preconditioners / precision modes (option values shared with the C ABIs)
-PREC_BJ, PREC_ILU0, PREC_CPR = 0, 1, 2
+PREC_BJ, PREC_ILU0, PREC_CPR, PREC_CPR_ILU0 = 0, 1, 2, 3
 FP64, MIXED = 0, 1
 
 # phase-state flags for the three-phase model
@@ -97,6 +97,7 @@ class Options:
     graphs: int = 1             # replay Arnoldi steps as HIP graphs
     forcing: int = 1            # Eisenstat-Walker forcing term (lin_rtol is the floor)
     amg_fused: int = 0          # cells below which the AMG cycle runs fused (0 default, <0 off)
+    tile: tuple = (0, 0, 0)     # block-Jacobi ILU(0) subdomain box (0 = 8 cells per axis)
 
 
 @dataclass

@@ -213,15 +213,45 @@ def test_block_jacobi_apply_matches_oracle(cfg):
     np.testing.assert_allclose(y, yo, rtol=1e-12, atol=1e-12 * np.abs(yo).max())
 
 
+@pytest.mark.parametrize("cfg,tile", [("c1", "grid"), ("c2s", "grid"), ("odd", (4, 5, 2)),
+                                      ("odd", (1, 1, 1)), ("odd", (13, 1, 5)), ("wells", (8, 8, 8)),
+                                      ("line", "grid"), ("line", (1, 7, 1))])
+def test_ilu0_apply_matches_oracle(cfg, tile):
+    # block-Jacobi ILU(0) over boxes (natural-order BILU(0) when one box
+    # covers the grid) on the GPU's own Jacobian against the oracle's
+    res = {"c1": rv.config_c1, "c2s": lambda: rv.config_c2_small(7, 9, 3),
+           "odd": lambda: rv.config_c2_small(13, 17, 5),
+           "wells": lambda: rv.config_c2_small(20, 18, 10),
+           "line": lambda: rv.buckley_leverett_1d(300)}[cfg]()
+    if tile == "grid":
+        tile = (res.nx, res.ny, res.nz)
+    g = fim.Fim(res, options=rv.Options(precond=rv.PREC_ILU0, tile=tile))
+    g.set_initial_state()
+    R, rowptr, colind, val = g.fim_assemble(10.0)
+    tiles = fr.ilu_tiles(res.nx, res.ny, res.nz, tuple(min(t, d) for t, d in
+                                                      zip(tile, (res.nx, res.ny, res.nz))),
+                         [w.cells for w in res.wells])
+    lu = fr.bilu0_tiled(rowptr, colind, val, g.nb, tiles)
+    for seed in (81, 82):
+        x = np.random.default_rng(seed).normal(size=len(R))
+        y = g.fim_precond_apply(x)
+        yo = fr.bilu0_solve(rowptr, colind, lu, x, g.nb)
+        err = np.abs(y - yo).max() / np.abs(yo).max()
+        assert err <= 1e-11, err
+
+
 @pytest.mark.parametrize("cfg,precond", [(c, p) for c in ("c1", "c2s", "odd", "line")
-                                         for p in (rv.PREC_BJ, rv.PREC_CPR)
-                                         if not (c == "line" and p == rv.PREC_BJ)])
+                                         for p in (rv.PREC_BJ, rv.PREC_CPR, rv.PREC_ILU0,
+                                                   rv.PREC_CPR_ILU0)
+                                         # the incompressible line is too ill conditioned
+                                         # for a preconditioner without a pressure stage
+                                         if not (c == "line" and p in (rv.PREC_BJ, rv.PREC_ILU0))])
 def test_linear_solve_matches_dense_solution(cfg, precond):
     res = {"c1": rv.config_c1, "c2s": lambda: rv.config_c2_small(7, 9, 3),
            "odd": lambda: rv.config_c2_small(13, 17, 5),
            "line": lambda: rv.buckley_leverett_1d(300)}[cfg]()
     g, o = pair(res)
-    opts = rv.Options(lin_rtol=1e-12, max_lin=3000, restart=40, precond=precond)
+    opts = rv.Options(lin_rtol=1e-12, max_lin=3000, restart=40, precond=precond, tile=(4, 4, 2))
     g.fim_set_options(opts)
     R, rowptr, colind, val = g.fim_assemble(10.0)
     A = fr.bsr_to_dense(rowptr, colind, val, g.nb)
@@ -233,6 +263,22 @@ def test_linear_solve_matches_dense_solution(cfg, precond):
     # LAPACK solution is then bounded by cond(A) * eps, not by the residual
     bound = 1e-8 if cfg != "line" else 1e-5
     assert np.abs(x - xd).max() <= bound * np.abs(xd).max()
+
+
+def test_ilu0_needs_fewer_iterations_than_block_jacobi():
+    res = rv.config_c2_small(24, 40, 12)
+    g, o = pair(res)
+    R, *_ = g.fim_assemble(10.0)
+    its = {}
+    for pc in (rv.PREC_BJ, rv.PREC_ILU0, rv.PREC_CPR, rv.PREC_CPR_ILU0):
+        g.fim_set_options(rv.Options(lin_rtol=1e-8, max_lin=1500, restart=40, precond=pc))
+        g.fim_assemble(10.0, jacobian=False)
+        x, rc, it, rr = g.fim_linear_solve(R)
+        its[pc] = (rc, it, rr)
+    print("iterations BJ, ILU0, CPR, CPR+ILU0:", its)
+    assert all(v[0] == fim.FIM_OK for v in its.values()), its
+    assert its[rv.PREC_ILU0][1] < its[rv.PREC_BJ][1]
+    assert its[rv.PREC_CPR_ILU0][1] <= its[rv.PREC_CPR][1]
 
 
 @pytest.mark.parametrize("cycle", [0, 1, 2, 500])
@@ -315,18 +361,20 @@ def test_linear_solve_zero_rhs():
 # ---------------------------------------------------------------------------
 # full time steps
 
-def test_steps_match_oracle_three_phase_c1():
+@pytest.mark.parametrize("precond", [rv.PREC_CPR, rv.PREC_CPR_ILU0])
+def test_steps_match_oracle_three_phase_c1(precond):
     res = rv.config_c1()
-    g, o, errs = run_parity_steps(res, 10)
+    g, o, errs = run_parity_steps(res, 10, options=rv.Options(precond=precond, tile=(5, 5, 3)))
     worst = {k: max(e[k] for e in errs) for k in errs[0]}
     print("c1 parity per quantity:", worst)
     assert all(v <= STATE_TOL for v in worst.values()), worst
     assert (o.flag == rv.SAT).any()
 
 
-def test_steps_match_oracle_two_phase_heterogeneous():
+@pytest.mark.parametrize("precond", [rv.PREC_CPR, rv.PREC_ILU0, rv.PREC_CPR_ILU0])
+def test_steps_match_oracle_two_phase_heterogeneous(precond):
     res = rv.config_c2_small(13, 17, 5, nsteps=3)
-    g, o, errs = run_parity_steps(res, 3)
+    g, o, errs = run_parity_steps(res, 3, options=rv.Options(precond=precond, tile=(5, 6, 3)))
     worst = {k: max(e[k] for e in errs) for k in errs[0]}
     print("c2-like parity per quantity:", worst)
     assert all(v <= STATE_TOL for v in worst.values()), worst
