@@ -2,8 +2,9 @@
 two-phase dead-oil five-spot (60x220x85, 2x2 BSR), one MI355X.
 
 A step is one FIM time step (dt = 10 days) through the C ABI: properties,
-TPFA assembly, block-Jacobi GMRES, Newton updates and cuts, all in the HIP
-library.  Inputs are seeded synthetic data resident in HBM before timing.
+TPFA assembly, FGMRES preconditioned by CPR (aggregation AMG on pressure,
+then block-Jacobi ILU(0) over 8x8x8 boxes), Newton updates and cuts, all in
+the HIP library.  Inputs are seeded synthetic data resident in HBM before timing.
 
 Prints one JSON line with the throughput, the roofline of the dominant
 kernel (BSR SpMV, timed with HIP events on the library's stream inside the
@@ -117,6 +118,8 @@ def main():
     ap.add_argument("--cycle", type=int, default=0,
                     help="AMG cycle: 0 V at the finest level and W below, 1 V, 2 W, >=16 W on "
                          "levels of at most that many cells")
+    ap.add_argument("--precond", default="cpr_ilu0", choices=["bj", "ilu0", "cpr", "cpr_ilu0"])
+    ap.add_argument("--tile", default="0,0,0", help="block-Jacobi ILU(0) box, e.g. 4,4,16")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "spmv_c2_traffic.json"))
     ap.add_argument("--spmv-only", type=int, default=0, metavar="REPS",
                     help="time only the SpMV of the 1.1M-cell Jacobian (profiler counter runs)")
@@ -139,6 +142,10 @@ def main():
     res = rv.config_c2()
     opts = tolerances(args.tol)
     opts.amg_cycle = args.cycle
+    opts.precond = {"bj": rv.PREC_BJ, "ilu0": rv.PREC_ILU0, "cpr": rv.PREC_CPR,
+                    "cpr_ilu0": rv.PREC_CPR_ILU0}[args.precond]
+    opts.tile = tuple(int(t) for t in args.tile.split(","))
+    box = tuple(min(t if t > 0 else 8, d) for t, d in zip(opts.tile, (res.nx, res.ny, res.nz)))
     g = fim.Fim(res, options=opts, profile=True)
     g.set_initial_state()
     torch.cuda.synchronize()
@@ -201,7 +208,9 @@ def main():
                         "seeded log-normal perm (sigma 2), 2x2 BSR, dt 10 days",
             "cells": g.n, "block_rows": g.nrows, "nnzb": g.nnzb, "nb": g.nb,
             "tolerances": args.tol,
-            "precond": {0: "block-Jacobi", 2: "CPR (quasi-IMPES + aggregation AMG) + block-Jacobi"}[opts.precond],
+            "precond": {0: "block-Jacobi", 1: f"block-Jacobi ILU(0), boxes {box}",
+                        2: "CPR (quasi-IMPES + aggregation AMG) + block-Jacobi",
+                        3: f"CPR (quasi-IMPES + aggregation AMG) + block-Jacobi ILU(0), boxes {box}"}[opts.precond],
             "amg_cycle": {0: "V at the finest level, W below", 1: "V", 2: "W"}.get(
                 opts.amg_cycle, f"W on levels <= {opts.amg_cycle} cells, V above"),
             "gmres_restart": opts.restart,

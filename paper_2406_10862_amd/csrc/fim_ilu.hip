@@ -92,6 +92,72 @@ __device__ void factor_row(int row, const IluTiles &T, const Sys &sys, double *l
     for (int e = 0; e < B2; ++e) lu[(size_t)di * B2 + e] = inv[e];
 }
 
+// The same factorisation for a cell row without well columns, found from
+// the row's position: on a 7-point pattern the only entry ILU(0) changes
+// besides the lower blocks is the diagonal, D_i = A_ii - sum_k L_ik U_ki
+// over the lower neighbours k of the tile (in column order -z, -y, -x),
+// with U_ki the +z / +y / +x block of row k.  Returns false (nothing done)
+// for rows with well columns.
+template <int NB>
+__device__ bool factor_cell_row(int i, int j, int k, const Grid &g, const IluTiles &T,
+                                const TileBox &tb, const Sys &sys, double *lu, int *bad) {
+    constexpr int B2 = NB * NB;
+    const int r = i + g.nx * (j + g.ny * k);
+    const int q0 = sys.rowptr[r];
+    const int nlow = (k > 0) + (j > 0) + (i > 0);
+    const int nup = (i + 1 < g.nx) + (j + 1 < g.ny) + (k + 1 < g.nz);
+    if (sys.rowptr[r + 1] - q0 != nlow + 1 + nup) return false;
+    for (int q = q0; q < q0 + nlow + 1 + nup; ++q)
+#pragma unroll
+        for (int e = 0; e < B2; ++e) lu[(size_t)q * B2 + e] = sys.val[(size_t)q * B2 + e];
+    const int qd = q0 + nlow;
+    double d[B2];
+#pragma unroll
+    for (int e = 0; e < B2; ++e) d[e] = lu[(size_t)qd * B2 + e];
+    const int li = i - tb.i0, lj = j - tb.j0, lk = k - tb.k0;
+    // lower neighbours in column order; for each: its row index, the
+    // position of its diagonal and of its block towards row r
+    int qk = q0;
+#pragma unroll
+    for (int dir = 0; dir < 3; ++dir) {
+        const bool exists = dir == 0 ? k > 0 : (dir == 1 ? j > 0 : i > 0);
+        if (!exists) continue;
+        const bool in = dir == 0 ? lk > 0 : (dir == 1 ? lj > 0 : li > 0);
+        if (in) {
+            const int ki = i - (dir == 2), kj = j - (dir == 1), kk = k - (dir == 0);
+            const int rk = r - (dir == 0 ? g.nx * g.ny : (dir == 1 ? g.nx : 1));
+            const int qdk = sys.rowptr[rk] + (kk > 0) + (kj > 0) + (ki > 0);
+            // U_ki: +x, +y or +z block of row k
+            const int qki = qdk + 1 + (dir <= 1 ? (ki + 1 < g.nx) : 0) + (dir == 0 ? (kj + 1 < g.ny) : 0);
+            double a[B2], u[B2], l[B2], uk[B2], p[B2];
+#pragma unroll
+            for (int e = 0; e < B2; ++e) {
+                a[e] = lu[(size_t)qk * B2 + e];
+                u[e] = lu[(size_t)qdk * B2 + e];
+            }
+            block_mul<NB>(a, u, l);
+#pragma unroll
+            for (int e = 0; e < B2; ++e) {
+                lu[(size_t)qk * B2 + e] = l[e];
+                uk[e] = lu[(size_t)qki * B2 + e];
+            }
+            block_mul<NB>(l, uk, p);
+#pragma unroll
+            for (int e = 0; e < B2; ++e) d[e] -= p[e];
+        }
+        ++qk;
+    }
+    double inv[B2];
+    if (!invert_block<NB>(d, inv)) {
+        *bad = 1;
+#pragma unroll
+        for (int e = 0; e < B2; ++e) inv[e] = (e % (NB + 1) == 0) ? 1.0 : 0.0;
+    }
+#pragma unroll
+    for (int e = 0; e < B2; ++e) lu[(size_t)qd * B2 + e] = inv[e];
+    return true;
+}
+
 // One workgroup per tile, then one for the wells that stand alone.
 template <int NB>
 __global__ void k_ilu_factor(Grid g, IluTiles T, Sys sys, double *lu, int *bad) {
@@ -108,8 +174,9 @@ __global__ void k_ilu_factor(Grid g, IluTiles T, Sys sys, double *lu, int *bad) 
         for (int p = threadIdx.x; p < tb.txe * tb.tye; p += blockDim.x) {
             const int li = p % tb.txe, lj = p / tb.txe, lk = s - li - lj;
             if (lk < 0 || lk >= tb.tze) continue;
-            const int row = (tb.i0 + li) + g.nx * ((tb.j0 + lj) + g.ny * (tb.k0 + lk));
-            factor_row<NB>(row, T, sys, lu, bad);
+            const int i = tb.i0 + li, j = tb.j0 + lj, k = tb.k0 + lk;
+            if (!factor_cell_row<NB>(i, j, k, g, T, tb, sys, lu, bad))
+                factor_row<NB>(i + g.nx * (j + g.ny * k), T, sys, lu, bad);
         }
         __syncthreads();
     }
@@ -127,6 +194,153 @@ __device__ inline void sub_mv(double (&acc)[NB], const double *blk, const double
 #pragma unroll
         for (int c = 1; c < NB; ++c) t += blk[r * NB + c] * v[c];
         acc[r] -= t;
+    }
+}
+
+template <int NB>
+struct Blk {
+    double v[NB * NB];
+};
+
+template <int NB>
+__device__ inline void load_blk(Blk<NB> &dst, const double *src) {
+#pragma unroll
+    for (int e = 0; e < NB * NB; ++e) dst.v[e] = src[e];
+}
+
+// The tile's wells, between the forward and backward sweeps over its cells:
+// forward over their perforated cells (all in the tile), then x = inv(U) y
+// (well rows have no upper part).
+template <int NB>
+__device__ void solve_tile_wells(const Grid &g, const TileBox &tb, const Sys &sys,
+                                 const double *lu, const double *b, double *y, const IluTiles &T,
+                                 int w0, int nwt, int ncell) {
+    constexpr int B2 = NB * NB;
+    const int n = g.n;
+    for (int e = threadIdx.x; e < nwt; e += blockDim.x) {
+        const int r = n + T.tw[w0 + e];
+        double acc[NB];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) acc[u] = b[(size_t)r * NB + u];
+        for (int q = sys.rowptr[r]; q < sys.rowptr[r + 1]; ++q) {
+            const int col = sys.colind[q];
+            if (col >= n) break;
+            const int ci = col % g.nx, cj = (col / g.nx) % g.ny, ck = col / (g.nx * g.ny);
+            const int lc = (ci - tb.i0) + tb.txe * ((cj - tb.j0) + tb.tye * (ck - tb.k0));
+            sub_mv<NB>(acc, lu + (size_t)q * B2, y + (size_t)lc * NB);
+        }
+        double xw[NB] = {};
+        sub_mv<NB>(xw, lu + (size_t)sys.diagpos[r] * B2, acc);
+#pragma unroll
+        for (int u = 0; u < NB; ++u) y[(size_t)(ncell + e) * NB + u] = -xw[u];
+    }
+}
+
+// Both sweeps over the cells of a tile whose (li, lj) pencils fit the
+// workgroup: thread (li, lj) owns the pencil and meets its cells in order
+// of lk, one per hyperplane, so it loads the blocks of its next two cells
+// while the hyperplanes before them are solved.  Row starts and the right
+// side are staged in LDS first.  Same arithmetic, same order, as the
+// general sweeps.
+template <int NB>
+__device__ void solve_cells_pencils(const Grid &g, const TileBox &tb, const Sys &sys,
+                                    const double *__restrict__ lu, const double *__restrict__ b,
+                                    double *y, int *rp, const IluTiles &T, int blk, int w0, int nwt,
+                                    int ncell) {
+    constexpr int B2 = NB * NB;
+    const int sxy = tb.txe * tb.tye;
+    for (int l = threadIdx.x; l < ncell; l += blockDim.x) {
+        const int li = l % tb.txe, lj = (l / tb.txe) % tb.tye, lk = l / sxy;
+        const int r = (tb.i0 + li) + g.nx * ((tb.j0 + lj) + g.ny * (tb.k0 + lk));
+        rp[l] = sys.rowptr[r];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) y[(size_t)l * NB + u] = b[(size_t)r * NB + u];
+    }
+    __syncthreads();
+    const bool own = (int)threadIdx.x < sxy;
+    const int li = threadIdx.x % tb.txe, lj = threadIdx.x / tb.txe;
+    const int i = tb.i0 + li, j = tb.j0 + lj;
+    const int nlev = tb.txe + tb.tye + tb.tze - 2;
+    // forward: lower blocks -z, -y, -x of cell lk
+    auto lower = [&](int lk, Blk<NB> &bz, Blk<NB> &by, Blk<NB> &bx) {
+        const int k = tb.k0 + lk;
+        const int q = rp[li + tb.txe * (lj + tb.tye * lk)];
+        const int qy = q + (k > 0), qx = qy + (j > 0);
+        if (lk > 0) load_blk<NB>(bz, lu + (size_t)q * B2);
+        if (lj > 0) load_blk<NB>(by, lu + (size_t)qy * B2);
+        if (li > 0) load_blk<NB>(bx, lu + (size_t)qx * B2);
+    };
+    Blk<NB> cz, cy, cx, nz, ny, nx;
+    if (own) {
+        lower(0, cz, cy, cx);
+        if (tb.tze > 1) lower(1, nz, ny, nx);
+    }
+    for (int s = 0; s < nlev; ++s) {
+        const int lk = s - li - lj;
+        if (own && lk >= 0 && lk < tb.tze) {
+            const int l = li + tb.txe * (lj + tb.tye * lk);
+            double acc[NB];
+#pragma unroll
+            for (int u = 0; u < NB; ++u) acc[u] = y[(size_t)l * NB + u];
+            if (lk > 0) sub_mv<NB>(acc, cz.v, y + (size_t)(l - sxy) * NB);
+            if (lj > 0) sub_mv<NB>(acc, cy.v, y + (size_t)(l - tb.txe) * NB);
+            if (li > 0) sub_mv<NB>(acc, cx.v, y + (size_t)(l - 1) * NB);
+#pragma unroll
+            for (int u = 0; u < NB; ++u) y[(size_t)l * NB + u] = acc[u];
+            cz = nz;
+            cy = ny;
+            cx = nx;
+            if (lk + 2 < tb.tze) lower(lk + 2, nz, ny, nx);
+        }
+        __syncthreads();
+    }
+    solve_tile_wells<NB>(g, tb, sys, lu, b, y, T, w0, nwt, ncell);
+    __syncthreads();
+    // backward: +x, +y, +z blocks and the inverted diagonal of cell lk
+    auto upper = [&](int lk, Blk<NB> &ux, Blk<NB> &uy, Blk<NB> &uz, Blk<NB> &dd) {
+        const int k = tb.k0 + lk;
+        const int qd = rp[li + tb.txe * (lj + tb.tye * lk)] + (k > 0) + (j > 0) + (i > 0);
+        const int qy = qd + 1 + (i + 1 < g.nx), qz = qy + (j + 1 < g.ny);
+        load_blk<NB>(dd, lu + (size_t)qd * B2);
+        if (li + 1 < tb.txe) load_blk<NB>(ux, lu + (size_t)(qd + 1) * B2);
+        if (lj + 1 < tb.tye) load_blk<NB>(uy, lu + (size_t)qy * B2);
+        if (lk + 1 < tb.tze) load_blk<NB>(uz, lu + (size_t)qz * B2);
+    };
+    Blk<NB> ax, ay, az, ad, bx2, by2, bz2, bd;
+    if (own) {
+        upper(tb.tze - 1, ax, ay, az, ad);
+        if (tb.tze > 1) upper(tb.tze - 2, bx2, by2, bz2, bd);
+    }
+    for (int s = nlev - 1; s >= 0; --s) {
+        const int lk = s - li - lj;
+        if (own && lk >= 0 && lk < tb.tze) {
+            const int k = tb.k0 + lk;
+            const int r = i + g.nx * (j + g.ny * k), l = li + tb.txe * (lj + tb.tye * lk);
+            double acc[NB];
+#pragma unroll
+            for (int u = 0; u < NB; ++u) acc[u] = y[(size_t)l * NB + u];
+            if (li + 1 < tb.txe) sub_mv<NB>(acc, ax.v, y + (size_t)(l + 1) * NB);
+            if (lj + 1 < tb.tye) sub_mv<NB>(acc, ay.v, y + (size_t)(l + tb.txe) * NB);
+            if (lk + 1 < tb.tze) sub_mv<NB>(acc, az.v, y + (size_t)(l + sxy) * NB);
+            // well columns (perforated cells): the wells of this tile
+            const int qw = rp[l] + (k > 0) + (j > 0) + (i > 0) + 1 + (i + 1 < g.nx) + (j + 1 < g.ny) +
+                           (k + 1 < g.nz);
+            for (int q = qw; q < sys.rowptr[r + 1]; ++q) {
+                const int w = sys.colind[q] - g.n;
+                if (T.rtile[g.n + w] == blk)
+                    sub_mv<NB>(acc, lu + (size_t)q * B2, y + (size_t)(ncell + T.wlocal[w]) * NB);
+            }
+            double xr[NB] = {};
+            sub_mv<NB>(xr, ad.v, acc);
+#pragma unroll
+            for (int u = 0; u < NB; ++u) y[(size_t)l * NB + u] = -xr[u];
+            ax = bx2;
+            ay = by2;
+            az = bz2;
+            ad = bd;
+            if (lk - 2 >= 0) upper(lk - 2, bx2, by2, bz2, bd);
+        }
+        __syncthreads();
     }
 }
 
@@ -157,6 +371,10 @@ __global__ void k_ilu_solve(Grid g, IluTiles T, Sys sys, const double *__restric
     const int sxy = tb.txe * tb.tye, ncell = sxy * tb.tze;
     const int w0 = T.twp[blk], nwt = T.twp[blk + 1] - w0;
     const int nlev = tb.txe + tb.tye + tb.tze - 2;
+    if (sxy <= (int)blockDim.x) {
+        solve_cells_pencils<NB>(g, tb, sys, lu, b, y, reinterpret_cast<int *>(y + (size_t)(ncell + T.maxwells) * NB),
+                                T, blk, w0, nwt, ncell);
+    } else {
     // forward over the hyperplanes
     for (int s = 0; s < nlev; ++s) {
         for (int p = threadIdx.x; p < sxy; p += blockDim.x) {
@@ -182,25 +400,7 @@ __global__ void k_ilu_solve(Grid g, IluTiles T, Sys sys, const double *__restric
         }
         __syncthreads();
     }
-    // the tile's wells: lower part = their perforated cells, all in the tile
-    for (int e = threadIdx.x; e < nwt; e += blockDim.x) {
-        const int r = n + T.tw[w0 + e];
-        double acc[NB];
-#pragma unroll
-        for (int u = 0; u < NB; ++u) acc[u] = b[(size_t)r * NB + u];
-        for (int q = sys.rowptr[r]; q < sys.rowptr[r + 1]; ++q) {
-            const int col = sys.colind[q];
-            if (col >= n) break;
-            const int ci = col % g.nx, cj = (col / g.nx) % g.ny, ck = col / (g.nx * g.ny);
-            const int lc = (ci - tb.i0) + tb.txe * ((cj - tb.j0) + tb.tye * (ck - tb.k0));
-            sub_mv<NB>(acc, lu + (size_t)q * B2, y + (size_t)lc * NB);
-        }
-        // well rows have no upper part: x = inv(U_ww) y
-        double xw[NB] = {};
-        sub_mv<NB>(xw, lu + (size_t)sys.diagpos[r] * B2, acc);
-#pragma unroll
-        for (int u = 0; u < NB; ++u) y[(size_t)(ncell + e) * NB + u] = -xw[u];
-    }
+    solve_tile_wells<NB>(g, tb, sys, lu, b, y, T, w0, nwt, ncell);
     __syncthreads();
     // backward over the hyperplanes
     for (int s = nlev - 1; s >= 0; --s) {
@@ -237,6 +437,7 @@ __global__ void k_ilu_solve(Grid g, IluTiles T, Sys sys, const double *__restric
             for (int u = 0; u < NB; ++u) y[(size_t)l * NB + u] = -xr[u];
         }
         __syncthreads();
+    }
     }
     for (int l = threadIdx.x; l < ncell + nwt; l += blockDim.x) {
         int r;
@@ -315,7 +516,9 @@ int ilu_threads(const IluTiles &T) {
 }
 
 size_t ilu_solve_lds(int nb, const IluTiles &T) {
-    return (size_t)(T.tx * T.ty * T.tz + T.maxwells) * nb * sizeof(double);
+    // the tile's vector, then its row starts (pencil sweeps)
+    return (size_t)(T.tx * T.ty * T.tz + T.maxwells) * nb * sizeof(double) +
+           (size_t)T.tx * T.ty * T.tz * sizeof(int);
 }
 
 hipError_t ilu_allow_lds(int nb, size_t bytes) {

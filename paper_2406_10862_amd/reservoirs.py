@@ -90,7 +90,7 @@ class Options:
     max_lin: int = 400
     restart: int = 30
     max_cuts: int = 8
-    precond: int = PREC_CPR
+    precond: int = PREC_CPR_ILU0
     precision: int = FP64
     amg_cycle: int = 0          # 0 = V at the finest level, W below; 1 = V; 2 = W; >=16 by size
     amg_sweeps: int = 1
