@@ -40,17 +40,30 @@ __device__ inline TileBox tile_box(const Grid &g, const IluTiles &T, int b) {
     return t;
 }
 
-// ILU(0) of one row in place (lu holds A's values on entry for rows not yet
-// factored): IKJ form restricted to the row's tile.  The row's lower
-// neighbours in its tile are factored already.
+// Copy of A's blocks [q0, q1) into lu by the whole workgroup (contiguous,
+// 16-byte accesses).
+__device__ inline void copy_blocks(const double *__restrict__ val, double *__restrict__ lu,
+                                   long q0, long q1, int b2) {
+    typedef double d2v __attribute__((ext_vector_type(2)));
+    const long e0 = q0 * b2, e1 = q1 * b2;        // element range
+    long e = e0 + threadIdx.x * 2;
+    if (e0 & 1) {                                  // odd start: one scalar first
+        if (threadIdx.x == 0) lu[e0] = val[e0];
+        e = e0 + 1 + threadIdx.x * 2;
+    }
+    for (; e + 1 < e1; e += 2L * blockDim.x)
+        *reinterpret_cast<d2v *>(lu + e) = *reinterpret_cast<const d2v *>(val + e);
+    if (e < e1) lu[e] = val[e];
+}
+
+// ILU(0) of one row in place (lu holds A's values for the row on entry):
+// IKJ form restricted to the row's tile.  The row's lower neighbours in its
+// tile are factored already.
 template <int NB>
 __device__ void factor_row(int row, const IluTiles &T, const Sys &sys, double *lu, int *bad) {
     constexpr int B2 = NB * NB;
     const int t = T.rtile[row];
     const int b0 = sys.rowptr[row], b1 = sys.rowptr[row + 1];
-    for (int q = b0; q < b1; ++q)
-#pragma unroll
-        for (int e = 0; e < B2; ++e) lu[(size_t)q * B2 + e] = sys.val[(size_t)q * B2 + e];
     for (int qk = b0; qk < b1; ++qk) {
         const int k = sys.colind[qk];
         if (k >= row) break;
@@ -107,9 +120,6 @@ __device__ bool factor_cell_row(int i, int j, int k, const Grid &g, const IluTil
     const int nlow = (k > 0) + (j > 0) + (i > 0);
     const int nup = (i + 1 < g.nx) + (j + 1 < g.ny) + (k + 1 < g.nz);
     if (sys.rowptr[r + 1] - q0 != nlow + 1 + nup) return false;
-    for (int q = q0; q < q0 + nlow + 1 + nup; ++q)
-#pragma unroll
-        for (int e = 0; e < B2; ++e) lu[(size_t)q * B2 + e] = sys.val[(size_t)q * B2 + e];
     const int qd = q0 + nlow;
     double d[B2];
 #pragma unroll
@@ -158,17 +168,53 @@ __device__ bool factor_cell_row(int i, int j, int k, const Grid &g, const IluTil
     return true;
 }
 
-// One workgroup per tile, then one for the wells that stand alone.
+// inverse of the diagonal block of a row that is a subdomain of its own
 template <int NB>
-__global__ void k_ilu_factor(Grid g, IluTiles T, Sys sys, double *lu, int *bad) {
+__device__ void factor_alone(int row, const Sys &sys, double *lu, int *bad) {
+    constexpr int B2 = NB * NB;
+    const int di = sys.diagpos[row];
+    double d[B2], inv[B2];
+#pragma unroll
+    for (int e = 0; e < B2; ++e) d[e] = lu[(size_t)di * B2 + e];
+    if (!invert_block<NB>(d, inv)) {
+        *bad = 1;
+#pragma unroll
+        for (int e = 0; e < B2; ++e) inv[e] = (e % (NB + 1) == 0) ? 1.0 : 0.0;
+    }
+#pragma unroll
+    for (int e = 0; e < B2; ++e) lu[(size_t)di * B2 + e] = inv[e];
+}
+
+// One workgroup per tile, then one for the wells that stand alone.  The
+// tile's rows (cells and its wells) are copied from A first, each x-row of
+// the tile being one contiguous run of blocks.
+template <int NB>
+__global__ __launch_bounds__(256) void k_ilu_factor(Grid g, IluTiles T, Sys sys, double *lu,
+                                                    int *bad) {
+    constexpr int B2 = NB * NB;
     const int b = blockIdx.x;
     const int ntiles = T.ntx * T.nty * T.ntz;
     if (b >= ntiles) {
+        for (int e = 0; e < T.nsingle; ++e) {
+            const int r = g.n + T.single[e];
+            copy_blocks(sys.val, lu, sys.rowptr[r], sys.rowptr[r + 1], B2);
+        }
+        __syncthreads();
         for (int e = threadIdx.x; e < T.nsingle; e += blockDim.x)
-            factor_row<NB>(g.n + T.single[e], T, sys, lu, bad);
+            factor_alone<NB>(g.n + T.single[e], sys, lu, bad);
         return;
     }
     const TileBox tb = tile_box(g, T, b);
+    for (int seg = 0; seg < tb.tye * tb.tze; ++seg) {
+        const int j = tb.j0 + seg % tb.tye, k = tb.k0 + seg / tb.tye;
+        const int r0 = tb.i0 + g.nx * (j + g.ny * k);
+        copy_blocks(sys.val, lu, sys.rowptr[r0], sys.rowptr[r0 + tb.txe], B2);
+    }
+    for (int e = T.twp[b]; e < T.twp[b + 1]; ++e) {
+        const int r = g.n + T.tw[e];
+        copy_blocks(sys.val, lu, sys.rowptr[r], sys.rowptr[r + 1], B2);
+    }
+    __syncthreads();
     const int nlev = tb.txe + tb.tye + tb.tze - 2;
     for (int s = 0; s < nlev; ++s) {
         for (int p = threadIdx.x; p < tb.txe * tb.tye; p += blockDim.x) {
@@ -348,7 +394,7 @@ __device__ void solve_cells_pencils(const Grid &g, const TileBox &tb, const Sys 
 // every tile; zp, when given, is added to the first slot of every row of x
 // (the pressure correction of the CPR first stage).
 template <int NB>
-__global__ void k_ilu_solve(Grid g, IluTiles T, Sys sys, const double *__restrict__ lu,
+__global__ __launch_bounds__(256) void k_ilu_solve(Grid g, IluTiles T, Sys sys, const double *__restrict__ lu,
                             const double *__restrict__ b, const double *__restrict__ zp,
                             double *__restrict__ x) {
     constexpr int B2 = NB * NB;

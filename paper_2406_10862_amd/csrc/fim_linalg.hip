@@ -28,7 +28,7 @@ constexpr int kMaxDots = kMaxRestart + 1;   // basis vectors + the vector itself
 // and index arrays.  NT selects non-temporal loads of the matrix (no
 // allocation in L2/MALL); REMAP walks the rows XCD by XCD.
 constexpr int kSpmvG = 8, kSpmvV = 1;
-constexpr bool kSpmvNT = true, kSpmvRemap = false;
+constexpr bool kSpmvNT = false, kSpmvRemap = false;
 
 template <bool NT, class T>
 __device__ inline T ldm(const T *p) {
