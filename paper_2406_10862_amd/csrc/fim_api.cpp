@@ -121,7 +121,7 @@ struct fim_ctx {
     IluTiles ilu{};
     int ilu_dims[3] = {0, 0, 0};
     std::vector<int> perf_cell_h;                   // perforated cell of each perforation
-    double *lu = nullptr, *cprt = nullptr, *zp = nullptr;
+    double *lu = nullptr;
     int *ilu_bad = nullptr;
     int sub_root = -1;                              // first level of the fused sub-cycle
     int *sub_ops = nullptr;                         // [kSubOps] its phase list
@@ -909,8 +909,6 @@ static void build_ilu(fim_ctx *c) {
     HIPCHECK(ilu_allow_lds(c->nb, ilu_solve_lds(c->nb, T)));
     if (!c->lu) {
         c->lu = c->alloc<double>((size_t)c->nnzb * c->nb * c->nb);
-        c->cprt = c->alloc<double>(c->nvec);
-        c->zp = c->alloc<double>(c->nrows);
         c->ilu_bad = c->alloc<int>(1);
     }
     c->ilu = T;
@@ -935,12 +933,12 @@ static void precondition(fim_ctx *c, const double *w, const double *hptr, double
     if (c->opt.precond == FIM_PREC_CPR_ILU0) {
         launch_cpr_restrict(c->s, c->nb, c->n, c->nw, c->lv[0], c->split0, w, hptr, v, c->wq);
         amg_cycle(c, 0);
-        launch_cpr_resid(c->s, c->nb, c->n, c->nw, c->lv[0], c->split0, c->colsplit, c->sys(), c->ap,
-                         hptr ? v : w, c->cprt, c->zp);
-        launch_ilu_solve(c->s, c->nb, c->g, c->ilu, c->sys(), c->lu, c->cprt, c->zp, z);
+        const IluRhs R{hptr ? v : w, c->ap, c->colsplit, c->split0, c->lv[0].x, 2 * c->lv[0].half};
+        launch_ilu_solve(c->s, c->nb, c->g, c->ilu, c->sys(), c->lu, R, z);
     } else if (c->opt.precond == FIM_PREC_ILU0) {
         if (hptr) launch_normalize(c->s, c->nvec, w, hptr, v);
-        launch_ilu_solve(c->s, c->nb, c->g, c->ilu, c->sys(), c->lu, hptr ? v : w, nullptr, z);
+        const IluRhs R{hptr ? v : w, nullptr, nullptr, nullptr, nullptr, 0};
+        launch_ilu_solve(c->s, c->nb, c->g, c->ilu, c->sys(), c->lu, R, z);
     } else if (c->opt.precond == FIM_PREC_CPR) {
         launch_cpr_restrict(c->s, c->nb, c->n, c->nw, c->lv[0], c->split0, w, hptr, v, c->wq);
         amg_cycle(c, 0);

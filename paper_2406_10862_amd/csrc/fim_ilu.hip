@@ -254,20 +254,57 @@ __device__ inline void load_blk(Blk<NB> &dst, const double *src) {
     for (int e = 0; e < NB * NB; ++e) dst.v[e] = src[e];
 }
 
+// Right-hand side of row r: b, or for the CPR second stage the residual
+// v - A x1 of the first stage (A x1 from the compact pressure column, x1
+// the level-0 pressure correction), whose correction corr(r) is added to the
+// first slot of the result.
+// (the first eight blocks of the row issue their loads together; longer
+// rows, of perforated cells and wells, finish in a loop)
+template <int NB>
+__device__ inline void rhs_row(const IluRhs &R, const Sys &sys, int r, double (&acc)[NB],
+                               int q0 = -1) {
+#pragma unroll
+    for (int u = 0; u < NB; ++u) acc[u] = R.b[(size_t)r * NB + u];
+    if (!R.ap) return;
+    if (q0 < 0) q0 = sys.rowptr[r];
+    const int q1 = sys.rowptr[r + 1];
+    constexpr int K = 8;
+    int cs[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) cs[k] = (q0 + k < q1) ? R.colsplit[q0 + k] : -1;
+    double p[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) p[k] = cs[k] >= 0 ? R.px[cs[k]] : 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        if (cs[k] >= 0)
+#pragma unroll
+            for (int u = 0; u < NB; ++u) acc[u] -= R.ap[(size_t)(q0 + k) * NB + u] * p[k];
+    for (int q = q0 + K; q < q1; ++q) {
+        const double pq = R.px[R.colsplit[q]];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) acc[u] -= R.ap[(size_t)q * NB + u] * pq;
+    }
+}
+
+__device__ inline double rhs_corr(const IluRhs &R, int n, int r) {
+    if (!R.ap) return 0.0;
+    return r < n ? R.px[R.split0[r]] : R.px[R.nsplit + (r - n)];
+}
+
 // The tile's wells, between the forward and backward sweeps over its cells:
 // forward over their perforated cells (all in the tile), then x = inv(U) y
 // (well rows have no upper part).
 template <int NB>
 __device__ void solve_tile_wells(const Grid &g, const TileBox &tb, const Sys &sys,
-                                 const double *lu, const double *b, double *y, const IluTiles &T,
+                                 const double *lu, const IluRhs &R, double *y, const IluTiles &T,
                                  int w0, int nwt, int ncell) {
     constexpr int B2 = NB * NB;
     const int n = g.n;
     for (int e = threadIdx.x; e < nwt; e += blockDim.x) {
         const int r = n + T.tw[w0 + e];
         double acc[NB];
-#pragma unroll
-        for (int u = 0; u < NB; ++u) acc[u] = b[(size_t)r * NB + u];
+        rhs_row<NB>(R, sys, r, acc);
         for (int q = sys.rowptr[r]; q < sys.rowptr[r + 1]; ++q) {
             const int col = sys.colind[q];
             if (col >= n) break;
@@ -290,17 +327,35 @@ __device__ void solve_tile_wells(const Grid &g, const TileBox &tb, const Sys &sy
 // general sweeps.
 template <int NB>
 __device__ void solve_cells_pencils(const Grid &g, const TileBox &tb, const Sys &sys,
-                                    const double *__restrict__ lu, const double *__restrict__ b,
+                                    const double *__restrict__ lu, const IluRhs &R,
                                     double *y, int *rp, const IluTiles &T, int blk, int w0, int nwt,
                                     int ncell) {
     constexpr int B2 = NB * NB;
     const int sxy = tb.txe * tb.tye;
-    for (int l = threadIdx.x; l < ncell; l += blockDim.x) {
-        const int li = l % tb.txe, lj = (l / tb.txe) % tb.tye, lk = l / sxy;
-        const int r = (tb.i0 + li) + g.nx * ((tb.j0 + lj) + g.ny * (tb.k0 + lk));
-        rp[l] = sys.rowptr[r];
+    // two rows per thread at a time so their loads overlap
+    for (int l0 = threadIdx.x; l0 < ncell; l0 += 2 * blockDim.x) {
+        int rr[2], q0[2];
+        bool on[2];
 #pragma unroll
-        for (int u = 0; u < NB; ++u) y[(size_t)l * NB + u] = b[(size_t)r * NB + u];
+        for (int h = 0; h < 2; ++h) {
+            const int l = l0 + h * blockDim.x;
+            on[h] = l < ncell;
+            const int li = l % tb.txe, lj = (l / tb.txe) % tb.tye, lk = l / sxy;
+            rr[h] = on[h] ? (tb.i0 + li) + g.nx * ((tb.j0 + lj) + g.ny * (tb.k0 + lk)) : 0;
+            q0[h] = on[h] ? sys.rowptr[rr[h]] : 0;
+        }
+        double acc[2][NB];
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+            if (on[h]) rhs_row<NB>(R, sys, rr[h], acc[h], q0[h]);
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+            if (on[h]) {
+                const int l = l0 + h * blockDim.x;
+                rp[l] = q0[h];
+#pragma unroll
+                for (int u = 0; u < NB; ++u) y[(size_t)l * NB + u] = acc[h][u];
+            }
     }
     __syncthreads();
     const bool own = (int)threadIdx.x < sxy;
@@ -340,7 +395,7 @@ __device__ void solve_cells_pencils(const Grid &g, const TileBox &tb, const Sys 
         }
         __syncthreads();
     }
-    solve_tile_wells<NB>(g, tb, sys, lu, b, y, T, w0, nwt, ncell);
+    solve_tile_wells<NB>(g, tb, sys, lu, R, y, T, w0, nwt, ncell);
     __syncthreads();
     // backward: +x, +y, +z blocks and the inverted diagonal of cell lk
     auto upper = [&](int lk, Blk<NB> &ux, Blk<NB> &uy, Blk<NB> &uz, Blk<NB> &dd) {
@@ -390,13 +445,12 @@ __device__ void solve_cells_pencils(const Grid &g, const TileBox &tb, const Sys 
     }
 }
 
-// x = M^-1 b: forward (L y = b, L unit lower) and backward (U x = y) inside
-// every tile; zp, when given, is added to the first slot of every row of x
-// (the pressure correction of the CPR first stage).
+// x = M^-1 rhs: forward (L y = rhs, L unit lower) and backward (U x = y)
+// inside every tile; for the CPR second stage the first-stage correction is
+// added to the first slot of every row of x.
 template <int NB>
 __global__ __launch_bounds__(256) void k_ilu_solve(Grid g, IluTiles T, Sys sys, const double *__restrict__ lu,
-                            const double *__restrict__ b, const double *__restrict__ zp,
-                            double *__restrict__ x) {
+                            IluRhs R, double *__restrict__ x) {
     constexpr int B2 = NB * NB;
     extern __shared__ double y[];
     const int blk = blockIdx.x;
@@ -405,11 +459,11 @@ __global__ __launch_bounds__(256) void k_ilu_solve(Grid g, IluTiles T, Sys sys, 
     if (blk >= ntiles) {
         for (int e = threadIdx.x; e < T.nsingle; e += blockDim.x) {
             const int r = n + T.single[e];
-            double acc[NB] = {};
-            sub_mv<NB>(acc, lu + (size_t)sys.diagpos[r] * B2, b + (size_t)r * NB);
+            double rhs[NB], acc[NB] = {};
+            rhs_row<NB>(R, sys, r, rhs);
+            sub_mv<NB>(acc, lu + (size_t)sys.diagpos[r] * B2, rhs);
 #pragma unroll
-            for (int u = 0; u < NB; ++u)
-                x[(size_t)r * NB + u] = -acc[u] + ((u == 0 && zp) ? zp[r] : 0.0);
+            for (int u = 0; u < NB; ++u) x[(size_t)r * NB + u] = -acc[u] + (u == 0 ? rhs_corr(R, n, r) : 0.0);
         }
         return;
     }
@@ -418,7 +472,7 @@ __global__ __launch_bounds__(256) void k_ilu_solve(Grid g, IluTiles T, Sys sys, 
     const int w0 = T.twp[blk], nwt = T.twp[blk + 1] - w0;
     const int nlev = tb.txe + tb.tye + tb.tze - 2;
     if (sxy <= (int)blockDim.x) {
-        solve_cells_pencils<NB>(g, tb, sys, lu, b, y, reinterpret_cast<int *>(y + (size_t)(ncell + T.maxwells) * NB),
+        solve_cells_pencils<NB>(g, tb, sys, lu, R, y, reinterpret_cast<int *>(y + (size_t)(ncell + T.maxwells) * NB),
                                 T, blk, w0, nwt, ncell);
     } else {
     // forward over the hyperplanes
@@ -429,8 +483,7 @@ __global__ __launch_bounds__(256) void k_ilu_solve(Grid g, IluTiles T, Sys sys, 
             const int i = tb.i0 + li, j = tb.j0 + lj, k = tb.k0 + lk;
             const int r = i + g.nx * (j + g.ny * k), l = li + tb.txe * (lj + tb.tye * lk);
             double acc[NB];
-#pragma unroll
-            for (int u = 0; u < NB; ++u) acc[u] = b[(size_t)r * NB + u];
+            rhs_row<NB>(R, sys, r, acc);
             int q = sys.rowptr[r];
             if (k > 0) {
                 if (lk > 0) sub_mv<NB>(acc, lu + (size_t)q * B2, y + (size_t)(l - sxy) * NB);
@@ -446,7 +499,7 @@ __global__ __launch_bounds__(256) void k_ilu_solve(Grid g, IluTiles T, Sys sys, 
         }
         __syncthreads();
     }
-    solve_tile_wells<NB>(g, tb, sys, lu, b, y, T, w0, nwt, ncell);
+    solve_tile_wells<NB>(g, tb, sys, lu, R, y, T, w0, nwt, ncell);
     __syncthreads();
     // backward over the hyperplanes
     for (int s = nlev - 1; s >= 0; --s) {
@@ -495,7 +548,7 @@ __global__ __launch_bounds__(256) void k_ilu_solve(Grid g, IluTiles T, Sys sys, 
         }
 #pragma unroll
         for (int u = 0; u < NB; ++u)
-            x[(size_t)r * NB + u] = y[(size_t)l * NB + u] + ((u == 0 && zp) ? zp[r] : 0.0);
+            x[(size_t)r * NB + u] = y[(size_t)l * NB + u] + (u == 0 ? rhs_corr(R, n, r) : 0.0);
     }
 }
 
@@ -507,42 +560,6 @@ __global__ __launch_bounds__(kBlock) void k_normalize(long nvec, const double *_
     if (e >= nvec) return;
     const double h = *hptr;
     v[e] = (h > 0.0 && isfinite(h)) ? w[e] / h : 0.0;
-}
-
-// Residual of the CPR first stage for the second: t = v - A x1, with x1 the
-// pressure correction in the pressure slot of every row (A x1 from the
-// compact pressure column ap); zp[r] = that correction.  G lanes per row.
-template <int NB, int G>
-__global__ __launch_bounds__(kBlock) void k_cpr_resid(int n, int nw, AmgLevel L,
-                                                      const int *__restrict__ split0,
-                                                      const int *__restrict__ colsplit, Sys sys,
-                                                      const double *__restrict__ ap,
-                                                      const double *__restrict__ v,
-                                                      double *__restrict__ t,
-                                                      double *__restrict__ zp) {
-    const int lg = threadIdx.x & (G - 1);
-    const long bk = xcd_block(blockIdx.x, gridDim.x);
-    const int r = (int)((bk * blockDim.x + threadIdx.x) / G);
-    const int nrows = n + nw;
-    double a[NB];
-#pragma unroll
-    for (int e = 0; e < NB; ++e) a[e] = 0.0;
-    if (r < nrows) {
-        const int b = sys.rowptr[r], e = sys.rowptr[r + 1];
-        for (int q = b + lg; q < e; q += G) {
-            const double p = L.x[__builtin_nontemporal_load(colsplit + q)];
-#pragma unroll
-            for (int u = 0; u < NB; ++u) a[u] += __builtin_nontemporal_load(ap + (size_t)q * NB + u) * p;
-        }
-    }
-#pragma unroll
-    for (int off = G / 2; off >= 1; off >>= 1)
-#pragma unroll
-        for (int u = 0; u < NB; ++u) a[u] += __shfl_xor(a[u], off, 64);
-    if (r >= nrows || lg != 0) return;
-#pragma unroll
-    for (int u = 0; u < NB; ++u) t[(size_t)r * NB + u] = v[(size_t)r * NB + u] - a[u];
-    zp[r] = r < n ? L.x[split0[r]] : L.x[2 * L.half + (r - n)];
 }
 
 // ---------------------------------------------------------------------------
@@ -576,33 +593,19 @@ hipError_t ilu_allow_lds(int nb, size_t bytes) {
 }
 
 void launch_ilu_solve(hipStream_t s, int nb, Grid g, const IluTiles &T, Sys sys,
-                      const double *lu, const double *b, const double *zp, double *x) {
+                      const double *lu, const IluRhs &R, double *x) {
     const int nblk = T.ntx * T.nty * T.ntz + (T.nsingle > 0 ? 1 : 0);
     const int bs = ilu_threads(T);
     const size_t lds = ilu_solve_lds(nb, T);
     if (nb == 2)
-        hipLaunchKernelGGL(k_ilu_solve<2>, dim3(nblk), dim3(bs), lds, s, g, T, sys, lu, b, zp, x);
+        hipLaunchKernelGGL(k_ilu_solve<2>, dim3(nblk), dim3(bs), lds, s, g, T, sys, lu, R, x);
     else
-        hipLaunchKernelGGL(k_ilu_solve<3>, dim3(nblk), dim3(bs), lds, s, g, T, sys, lu, b, zp, x);
+        hipLaunchKernelGGL(k_ilu_solve<3>, dim3(nblk), dim3(bs), lds, s, g, T, sys, lu, R, x);
 }
 
 void launch_normalize(hipStream_t s, long nvec, const double *w, const double *hptr, double *v) {
     hipLaunchKernelGGL(k_normalize, dim3((unsigned)((nvec + kBlock - 1) / kBlock)), dim3(kBlock), 0,
                        s, nvec, w, hptr, v);
-}
-
-void launch_cpr_resid(hipStream_t s, int nb, int n, int nw, const AmgLevel &L, const int *split0,
-                      const int *colsplit, Sys sys, const double *ap, const double *v, double *t,
-                      double *zp) {
-    constexpr int G = 8;
-    const long threads = ((long)n + nw) * G;
-    const dim3 grid((unsigned)((threads + kBlock - 1) / kBlock));
-    if (nb == 2)
-        hipLaunchKernelGGL((k_cpr_resid<2, G>), grid, dim3(kBlock), 0, s, n, nw, L, split0, colsplit,
-                           sys, ap, v, t, zp);
-    else
-        hipLaunchKernelGGL((k_cpr_resid<3, G>), grid, dim3(kBlock), 0, s, n, nw, L, split0, colsplit,
-                           sys, ap, v, t, zp);
 }
 
 }  // namespace fim

@@ -186,12 +186,19 @@ size_t ilu_solve_lds(int nb, const IluTiles &T);
 hipError_t ilu_allow_lds(int nb, size_t bytes);
 void launch_ilu_factor(hipStream_t s, int nb, Grid g, const IluTiles &T, Sys sys, double *lu,
                        int *bad);
+// right-hand side of a solve: b, or (ap set) the residual b - A x1 of the CPR
+// first stage with x1 = px in level-0 AMG order, x1 added back to slot 0
+struct IluRhs {
+    const double *b;
+    const double *ap;           // [nnzb][nb] pressure column of A, or null
+    const int *colsplit;        // [nnzb] column -> level-0 entry
+    const int *split0;          // [n] cell -> level-0 entry
+    const double *px;           // level-0 iterate (cells, then wells)
+    int nsplit;                 // 2*half of level 0 (first well entry)
+};
 void launch_ilu_solve(hipStream_t s, int nb, Grid g, const IluTiles &T, Sys sys,
-                      const double *lu, const double *b, const double *zp, double *x);
+                      const double *lu, const IluRhs &R, double *x);
 void launch_normalize(hipStream_t s, long nvec, const double *w, const double *hptr, double *v);
-void launch_cpr_resid(hipStream_t s, int nb, int n, int nw, const AmgLevel &L, const int *split0,
-                      const int *colsplit, Sys sys, const double *ap, const double *v, double *t,
-                      double *zp);
 
 // A cycle is a sequence of phases on levels: colour sweeps, well sweeps,
 // restrictions, corrections and the dense coarsest solve.  The
