@@ -321,9 +321,9 @@ __device__ void solve_tile_wells(const Grid &g, const TileBox &tb, const Sys &sy
 
 // Both sweeps over the cells of a tile whose (li, lj) pencils fit the
 // workgroup: thread (li, lj) owns the pencil and meets its cells in order
-// of lk, one per hyperplane, so it loads the blocks of its next two cells
-// while the hyperplanes before them are solved.  Row starts and the right
-// side are staged in LDS first.  Same arithmetic, same order, as the
+// of lk, one per hyperplane, so it loads the blocks of its next kAhead
+// cells while the hyperplanes before them are solved.  Row starts and the
+// right side are staged in LDS first.  Same arithmetic, same order, as the
 // general sweeps.
 template <int NB>
 __device__ void solve_cells_pencils(const Grid &g, const TileBox &tb, const Sys &sys,
@@ -331,6 +331,7 @@ __device__ void solve_cells_pencils(const Grid &g, const TileBox &tb, const Sys 
                                     double *y, int *rp, const IluTiles &T, int blk, int w0, int nwt,
                                     int ncell) {
     constexpr int B2 = NB * NB;
+    constexpr int kAhead = 2;                     // deeper costs occupancy (VGPRs)
     const int sxy = tb.txe * tb.tye;
     // two rows per thread at a time so their loads overlap
     for (int l0 = threadIdx.x; l0 < ncell; l0 += 2 * blockDim.x) {
@@ -371,11 +372,12 @@ __device__ void solve_cells_pencils(const Grid &g, const TileBox &tb, const Sys 
         if (lj > 0) load_blk<NB>(by, lu + (size_t)qy * B2);
         if (li > 0) load_blk<NB>(bx, lu + (size_t)qx * B2);
     };
-    Blk<NB> cz, cy, cx, nz, ny, nx;
-    if (own) {
-        lower(0, cz, cy, cx);
-        if (tb.tze > 1) lower(1, nz, ny, nx);
-    }
+    // blocks of the next kAhead cells of the pencil, in flight
+    Blk<NB> fz[kAhead], fy[kAhead], fx[kAhead];
+    if (own)
+#pragma unroll
+        for (int a = 0; a < kAhead; ++a)
+            if (a < tb.tze) lower(a, fz[a], fy[a], fx[a]);
     for (int s = 0; s < nlev; ++s) {
         const int lk = s - li - lj;
         if (own && lk >= 0 && lk < tb.tze) {
@@ -383,15 +385,18 @@ __device__ void solve_cells_pencils(const Grid &g, const TileBox &tb, const Sys 
             double acc[NB];
 #pragma unroll
             for (int u = 0; u < NB; ++u) acc[u] = y[(size_t)l * NB + u];
-            if (lk > 0) sub_mv<NB>(acc, cz.v, y + (size_t)(l - sxy) * NB);
-            if (lj > 0) sub_mv<NB>(acc, cy.v, y + (size_t)(l - tb.txe) * NB);
-            if (li > 0) sub_mv<NB>(acc, cx.v, y + (size_t)(l - 1) * NB);
+            if (lk > 0) sub_mv<NB>(acc, fz[0].v, y + (size_t)(l - sxy) * NB);
+            if (lj > 0) sub_mv<NB>(acc, fy[0].v, y + (size_t)(l - tb.txe) * NB);
+            if (li > 0) sub_mv<NB>(acc, fx[0].v, y + (size_t)(l - 1) * NB);
 #pragma unroll
             for (int u = 0; u < NB; ++u) y[(size_t)l * NB + u] = acc[u];
-            cz = nz;
-            cy = ny;
-            cx = nx;
-            if (lk + 2 < tb.tze) lower(lk + 2, nz, ny, nx);
+#pragma unroll
+            for (int a = 0; a + 1 < kAhead; ++a) {
+                fz[a] = fz[a + 1];
+                fy[a] = fy[a + 1];
+                fx[a] = fx[a + 1];
+            }
+            if (lk + kAhead < tb.tze) lower(lk + kAhead, fz[kAhead - 1], fy[kAhead - 1], fx[kAhead - 1]);
         }
         __syncthreads();
     }
@@ -407,11 +412,11 @@ __device__ void solve_cells_pencils(const Grid &g, const TileBox &tb, const Sys 
         if (lj + 1 < tb.tye) load_blk<NB>(uy, lu + (size_t)qy * B2);
         if (lk + 1 < tb.tze) load_blk<NB>(uz, lu + (size_t)qz * B2);
     };
-    Blk<NB> ax, ay, az, ad, bx2, by2, bz2, bd;
-    if (own) {
-        upper(tb.tze - 1, ax, ay, az, ad);
-        if (tb.tze > 1) upper(tb.tze - 2, bx2, by2, bz2, bd);
-    }
+    Blk<NB> gx[kAhead], gy[kAhead], gz[kAhead], gd[kAhead];
+    if (own)
+#pragma unroll
+        for (int a = 0; a < kAhead; ++a)
+            if (a < tb.tze) upper(tb.tze - 1 - a, gx[a], gy[a], gz[a], gd[a]);
     for (int s = nlev - 1; s >= 0; --s) {
         const int lk = s - li - lj;
         if (own && lk >= 0 && lk < tb.tze) {
@@ -420,9 +425,9 @@ __device__ void solve_cells_pencils(const Grid &g, const TileBox &tb, const Sys 
             double acc[NB];
 #pragma unroll
             for (int u = 0; u < NB; ++u) acc[u] = y[(size_t)l * NB + u];
-            if (li + 1 < tb.txe) sub_mv<NB>(acc, ax.v, y + (size_t)(l + 1) * NB);
-            if (lj + 1 < tb.tye) sub_mv<NB>(acc, ay.v, y + (size_t)(l + tb.txe) * NB);
-            if (lk + 1 < tb.tze) sub_mv<NB>(acc, az.v, y + (size_t)(l + sxy) * NB);
+            if (li + 1 < tb.txe) sub_mv<NB>(acc, gx[0].v, y + (size_t)(l + 1) * NB);
+            if (lj + 1 < tb.tye) sub_mv<NB>(acc, gy[0].v, y + (size_t)(l + tb.txe) * NB);
+            if (lk + 1 < tb.tze) sub_mv<NB>(acc, gz[0].v, y + (size_t)(l + sxy) * NB);
             // well columns (perforated cells): the wells of this tile
             const int qw = rp[l] + (k > 0) + (j > 0) + (i > 0) + 1 + (i + 1 < g.nx) + (j + 1 < g.ny) +
                            (k + 1 < g.nz);
@@ -432,14 +437,18 @@ __device__ void solve_cells_pencils(const Grid &g, const TileBox &tb, const Sys 
                     sub_mv<NB>(acc, lu + (size_t)q * B2, y + (size_t)(ncell + T.wlocal[w]) * NB);
             }
             double xr[NB] = {};
-            sub_mv<NB>(xr, ad.v, acc);
+            sub_mv<NB>(xr, gd[0].v, acc);
 #pragma unroll
             for (int u = 0; u < NB; ++u) y[(size_t)l * NB + u] = -xr[u];
-            ax = bx2;
-            ay = by2;
-            az = bz2;
-            ad = bd;
-            if (lk - 2 >= 0) upper(lk - 2, bx2, by2, bz2, bd);
+#pragma unroll
+            for (int a = 0; a + 1 < kAhead; ++a) {
+                gx[a] = gx[a + 1];
+                gy[a] = gy[a + 1];
+                gz[a] = gz[a + 1];
+                gd[a] = gd[a + 1];
+            }
+            if (lk - kAhead >= 0)
+                upper(lk - kAhead, gx[kAhead - 1], gy[kAhead - 1], gz[kAhead - 1], gd[kAhead - 1]);
         }
         __syncthreads();
     }
@@ -573,6 +582,8 @@ void launch_ilu_factor(hipStream_t s, int nb, Grid g, const IluTiles &T, Sys sys
     else hipLaunchKernelGGL(k_ilu_factor<3>, dim3(nblk), dim3(bs), 0, s, g, T, sys, lu, bad);
 }
 
+// One thread per (li, lj) pencil, in whole waves (more waves per tile were
+// measured slower: they all wait at every hyperplane barrier).
 int ilu_threads(const IluTiles &T) {
     const int pairs = T.tx * T.ty;
     return pairs >= 256 ? 256 : ((pairs + 63) / 64) * 64;
