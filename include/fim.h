@@ -67,7 +67,7 @@ enum { FIM_BHP = 0, FIM_RATE = 1 };                         /* well control */
 enum { FIM_UNSAT = 0, FIM_SAT = 1 };                        /* phase-state flag */
 enum { FIM_PREC_BJ = 0, FIM_PREC_ILU0 = 1, FIM_PREC_CPR = 2,  /* preconditioner */
        FIM_PREC_CPR_ILU0 = 3 };
-enum { FIM_FP64 = 0 };                                      /* precision mode */
+enum { FIM_FP64 = 0, FIM_MIXED = 1 };                       /* precision mode */
 
 /* Cartesian grid: dx[nx], dy[ny], dz[nz] in ft, top = depth of the top face. */
 typedef struct {
@@ -152,7 +152,12 @@ typedef struct {
  * single-workgroup launch (0 = default 4096, negative = every phase
  * launched separately; the result is the same bit for bit).  profile != 0
  * brackets every SpMV launch of fim_step with HIP events and reports their
- * summed duration in fim_step_report. */
+ * summed duration in fim_step_report.  precision FIM_MIXED (with an ILU(0)
+ * preconditioner) runs every GMRES restart cycle in single precision: a
+ * float copy of the Jacobian, float Krylov vectors, ILU(0) factors and
+ * pressure column (sums in double), stopping after a 1e-5 reduction; each
+ * restart is an FP64 refinement step on the true residual b - J x, so the
+ * converged solution meets lin_rtol in FP64. */
 typedef struct {
     double tol_cnv, tol_mb, tol_dp, tol_ds, tol_well;
     double ds_max, dp_max, lin_rtol;

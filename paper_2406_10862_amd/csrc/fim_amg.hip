@@ -158,17 +158,17 @@ __device__ inline double pcoef(const double *__restrict__ val, int q, const doub
 // Also copies the pressure column of every block of the row (rows of
 // cells and wells) into ap[q][NB], the only part of A that the second CPR
 // stage multiplies.
-template <int NB>
+template <int NB, class LT>
 __global__ __launch_bounds__(kBlock) void k_amg_extract(AmgLevel L, Grid g, Wells wl, Sys sys,
                                                         double *__restrict__ wq,
-                                                        double *__restrict__ ap) {
+                                                        LT *__restrict__ ap) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int n = g.n;
     const int stride = 2 * L.half;
     if (t < n + L.nw)
         for (int q = sys.rowptr[t]; q < sys.rowptr[t + 1]; ++q)
 #pragma unroll
-            for (int u = 0; u < NB; ++u) ap[(size_t)q * NB + u] = sys.val[(size_t)q * NB * NB + u * NB];
+            for (int u = 0; u < NB; ++u) ap[(size_t)q * NB + u] = (LT)sys.val[(size_t)q * NB * NB + u * NB];
     if (t < n) {
         const int c = t, nx = g.nx, ny = g.ny, nxy = nx * ny;
         const int i = c % nx, j = (c / nx) % ny, k = c / nxy;
@@ -686,14 +686,15 @@ __global__ __launch_bounds__(kSubThreads) void k_amg_subcycle(AmgSub P) {
 // ---------------------------------------------------------------------------
 // CPR stage kernels
 
-// v = w / h (the new Arnoldi vector) and the pressure right-hand side
-// b_p = W^T v of the first level.
-template <int NB>
+// v = w / h (the new Arnoldi vector; h = 1 without hptr; stored when v is
+// given, in v's precision) and the pressure right-hand side b_p = W^T v of
+// the first level.
+template <int NB, class WT, class VT>
 __global__ __launch_bounds__(kBlock) void k_cpr_restrict(int n, int nw, AmgLevel L,
                                                          const int *__restrict__ split0,
-                                                         const double *__restrict__ w,
+                                                         const WT *__restrict__ w,
                                                          const double *__restrict__ hptr,
-                                                         double *__restrict__ v,
+                                                         VT *__restrict__ v,
                                                          const double *__restrict__ wq) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n + nw) return;
@@ -706,9 +707,9 @@ __global__ __launch_bounds__(kBlock) void k_cpr_restrict(int n, int nw, AmgLevel
     double a[NB];
 #pragma unroll
     for (int e = 0; e < NB; ++e) {
-        const double we = w[(size_t)r * NB + e];
+        const double we = (double)w[(size_t)r * NB + e];
         a[e] = zero ? 0.0 : (hptr ? we / h : we);
-        if (hptr) v[(size_t)r * NB + e] = a[e];
+        if (v) v[(size_t)r * NB + e] = (VT)a[e];
     }
     if (r < n) {
         double s = 0.0;
@@ -776,11 +777,26 @@ __global__ __launch_bounds__(kBlock) void k_cpr_finish(int n, int nw, AmgLevel L
 
 static inline dim3 grid_for(long n, int bs) { return dim3((unsigned)((n + bs - 1) / bs)); }
 
+template <class LT>
+static void extract_impl(hipStream_t s, int nb, const AmgLevel &L, Grid g, Wells w, Sys sys,
+                         double *wq, LT *ap) {
+    const long n = (long)g.n + L.nw;
+    if (nb == 2)
+        hipLaunchKernelGGL((k_amg_extract<2, LT>), grid_for(n, kBlock), dim3(kBlock), 0, s, L, g, w,
+                           sys, wq, ap);
+    else
+        hipLaunchKernelGGL((k_amg_extract<3, LT>), grid_for(n, kBlock), dim3(kBlock), 0, s, L, g, w,
+                           sys, wq, ap);
+}
+
 void launch_amg_extract(hipStream_t s, int nb, const AmgLevel &L, Grid g, Wells w, Sys sys,
                         double *wq, double *ap) {
-    const long n = (long)g.n + L.nw;
-    if (nb == 2) hipLaunchKernelGGL(k_amg_extract<2>, grid_for(n, kBlock), dim3(kBlock), 0, s, L, g, w, sys, wq, ap);
-    else hipLaunchKernelGGL(k_amg_extract<3>, grid_for(n, kBlock), dim3(kBlock), 0, s, L, g, w, sys, wq, ap);
+    extract_impl(s, nb, L, g, w, sys, wq, ap);
+}
+
+void launch_amg_extract(hipStream_t s, int nb, const AmgLevel &L, Grid g, Wells w, Sys sys,
+                        double *wq, float *ap) {
+    extract_impl(s, nb, L, g, w, sys, wq, ap);
 }
 
 void launch_amg_coarsen(hipStream_t s, const AmgLevel &F, const AmgLevel &C, const int *cfs_ptr,
@@ -837,16 +853,35 @@ void launch_amg_correct(hipStream_t s, const AmgLevel &F, const AmgLevel &C) {
     hipLaunchKernelGGL(k_amg_correct, grid_for(2L * F.half + F.nw, kBlock), dim3(kBlock), 0, s, F, C);
 }
 
+template <class WT, class VT>
+static void restrict_impl(hipStream_t s, int nb, int n, int nw, const AmgLevel &L,
+                          const int *split0, const WT *w, const double *hptr, VT *v,
+                          const double *wq) {
+    const long rows = (long)n + nw;
+    if (nb == 2)
+        hipLaunchKernelGGL((k_cpr_restrict<2, WT, VT>), grid_for(rows, kBlock), dim3(kBlock), 0, s, n,
+                           nw, L, split0, w, hptr, v, wq);
+    else
+        hipLaunchKernelGGL((k_cpr_restrict<3, WT, VT>), grid_for(rows, kBlock), dim3(kBlock), 0, s, n,
+                           nw, L, split0, w, hptr, v, wq);
+}
+
 void launch_cpr_restrict(hipStream_t s, int nb, int n, int nw, const AmgLevel &L,
                          const int *split0, const double *w, const double *hptr, double *v,
                          const double *wq) {
-    const long rows = (long)n + nw;
-    if (nb == 2)
-        hipLaunchKernelGGL(k_cpr_restrict<2>, grid_for(rows, kBlock), dim3(kBlock), 0, s, n, nw, L,
-                           split0, w, hptr, v, wq);
-    else
-        hipLaunchKernelGGL(k_cpr_restrict<3>, grid_for(rows, kBlock), dim3(kBlock), 0, s, n, nw, L,
-                           split0, w, hptr, v, wq);
+    restrict_impl(s, nb, n, nw, L, split0, w, hptr, v, wq);
+}
+
+void launch_cpr_restrict(hipStream_t s, int nb, int n, int nw, const AmgLevel &L,
+                         const int *split0, const double *w, const double *hptr, float *v,
+                         const double *wq) {
+    restrict_impl(s, nb, n, nw, L, split0, w, hptr, v, wq);
+}
+
+void launch_cpr_restrict(hipStream_t s, int nb, int n, int nw, const AmgLevel &L,
+                         const int *split0, const float *w, const double *hptr, float *v,
+                         const double *wq) {
+    restrict_impl(s, nb, n, nw, L, split0, w, hptr, v, wq);
 }
 
 void launch_cpr_finish(hipStream_t s, int nb, int n, int nw, const AmgLevel &L,

@@ -14,6 +14,8 @@
 #include <new>
 #include <numeric>
 #include <string>
+#include <stdexcept>
+#include <type_traits>
 #include <vector>
 
 #include "fim.h"
@@ -122,6 +124,11 @@ struct fim_ctx {
     int ilu_dims[3] = {0, 0, 0};
     std::vector<int> perf_cell_h;                   // perforated cell of each perforation
     double *lu = nullptr;
+    // mixed precision: single-precision copies for the inner solves
+    bool mixed = false;
+    int m32 = 0;
+    float *val32 = nullptr, *V32 = nullptr, *Z32 = nullptr, *w32 = nullptr, *lu32 = nullptr,
+          *ap32 = nullptr;
     int *ilu_bad = nullptr;
     int sub_root = -1;                              // first level of the fused sub-cycle
     int *sub_ops = nullptr;                         // [kSubOps] its phase list
@@ -225,7 +232,11 @@ static void check_options(const fim_options *o) {
     REQUIRE(o->amg_sweeps >= 0 && o->amg_sweeps <= 8, "amg_sweeps must be in [0, 8]");
     REQUIRE(o->graphs == 0 || o->graphs == 1, "graphs must be 0 or 1");
     REQUIRE(o->forcing == 0 || o->forcing == 1, "forcing must be 0 or 1");
-    REQUIRE(o->precision == FIM_FP64, "unknown precision mode %d", o->precision);
+    REQUIRE(o->precision == FIM_FP64 || o->precision == FIM_MIXED, "unknown precision mode %d",
+            o->precision);
+    REQUIRE(o->precision == FIM_FP64 || o->precond == FIM_PREC_ILU0 ||
+                o->precond == FIM_PREC_CPR_ILU0,
+            "mixed precision needs an ILU(0) preconditioner (FIM_PREC_ILU0 or FIM_PREC_CPR_ILU0)");
     REQUIRE(o->amg_fused <= (1 << 20), "amg_fused must be at most 2^20 cells");
 }
 
@@ -389,6 +400,7 @@ static void build_amg(fim_ctx *c, const std::vector<int> &sorted_cells,
 
 static void build_subcycle(fim_ctx *c);
 static void build_ilu(fim_ctx *c);
+static void ensure_mixed(fim_ctx *c);
 
 static int create_impl(const fim_grid *grid, const fim_rock *rock, const fim_fluid *fl,
                        int32_t nwells, const fim_well *wells, const fim_options *opt,
@@ -631,6 +643,7 @@ static int create_impl(const fim_grid *grid, const fim_rock *rock, const fim_flu
         }
         build_subcycle(c);
         build_ilu(c);
+        ensure_mixed(c);
         const size_t np = (size_t)(kMaxRestart + 2) * 2048 + (size_t)2048 * 16;
         c->partials = c->alloc<double>(np);
         c->scal = c->alloc<double>(S_COUNT);
@@ -915,7 +928,40 @@ static void build_ilu(fim_ctx *c) {
     for (int a = 0; a < 3; ++a) c->ilu_dims[a] = d[a];
 }
 
+// Single-precision buffers of the mixed mode: the Jacobian, the Krylov basis
+// and its preconditioned images, the ILU(0) factors and the pressure column.
+static void ensure_mixed(fim_ctx *c) {
+    c->mixed = c->opt.precision == FIM_MIXED;
+    if (!c->mixed) return;
+    const size_t bs = (size_t)c->nb * c->nb;
+    if (!c->val32) {
+        c->val32 = c->alloc<float>((size_t)c->nnzb * bs);
+        c->w32 = c->alloc<float>(c->nvec);
+        c->lu32 = c->alloc<float>((size_t)c->nnzb * bs);
+        c->ap32 = c->alloc<float>((size_t)c->nnzb * c->nb);
+    }
+    if (c->m32 < c->m) {
+        c->release(c->V32);
+        c->release(c->Z32);
+        c->V32 = c->alloc<float>((size_t)(c->m + 1) * c->nvec);
+        c->Z32 = c->alloc<float>((size_t)(c->m + 1) * c->nvec);
+        c->m32 = c->m;
+    }
+}
+
 static void prec_setup(fim_ctx *c) {
+    if (c->mixed) {
+        launch_to_float(c->s, (long)c->nnzb * c->nb * c->nb, c->val, c->val32);
+        launch_ilu_factor(c->s, c->nb, c->g, c->ilu, c->sys(), c->lu32, c->ilu_bad);
+        if (uses_cpr(c->opt)) {
+            launch_amg_extract(c->s, c->nb, c->lv[0], c->g, c->wells(), c->sys(), c->wq, c->ap32);
+            for (size_t l = 1; l < c->lv.size(); ++l)
+                launch_amg_coarsen(c->s, c->lv[l - 1], c->lv[l], c->cfs_ptr[l], c->cfs_idx[l]);
+            launch_amg_coarsest_setup(c->s, c->lv.back(), c->Mden, c->Minv, c->colk, c->amg_bad);
+        }
+        c->prec_ready = true;
+        return;
+    }
     if (!uses_ilu(c->opt)) launch_bj_setup(c->s, c->nb, c->nrows, c->diagpos, c->val, c->dinv, c->bad);
     else launch_ilu_factor(c->s, c->nb, c->g, c->ilu, c->sys(), c->lu, c->ilu_bad);
     if (uses_cpr(c->opt)) {
@@ -927,32 +973,78 @@ static void prec_setup(fim_ctx *c) {
     c->prec_ready = true;
 }
 
+// Buffers of the Krylov solver in element type T (double, or float for the
+// inner solves of the mixed mode).
+template <class T>
+struct Kry;
+template <>
+struct Kry<double> {
+    static double *V(fim_ctx *c) { return c->V; }
+    static double *Z(fim_ctx *c) { return c->Z; }
+    static double *w(fim_ctx *c) { return c->w; }
+    static const double *val(fim_ctx *c) { return c->val; }
+    static const double *lu(fim_ctx *c) { return c->lu; }
+    static const double *ap(fim_ctx *c) { return c->ap; }
+};
+template <>
+struct Kry<float> {
+    static float *V(fim_ctx *c) { return c->V32; }
+    static float *Z(fim_ctx *c) { return c->Z32; }
+    static float *w(fim_ctx *c) { return c->w32; }
+    static const float *val(fim_ctx *c) { return c->val32; }
+    static const float *lu(fim_ctx *c) { return c->lu32; }
+    static const float *ap(fim_ctx *c) { return c->ap32; }
+};
+
 // z = M^-1 v.  With hptr set, v = w / *hptr is formed (and stored) first,
-// as for a new Arnoldi vector; without it v = w.
-static void precondition(fim_ctx *c, const double *w, const double *hptr, double *v, double *z) {
+// as for a new Arnoldi vector; without it v = w (stored in v's precision
+// when v is given).  WT / T: element types of w and of v, z.
+template <class WT, class T>
+static void precondition(fim_ctx *c, const WT *w, const double *hptr, T *v, T *z) {
+    constexpr bool same = std::is_same<WT, T>::value;
     if (c->opt.precond == FIM_PREC_CPR_ILU0) {
         launch_cpr_restrict(c->s, c->nb, c->n, c->nw, c->lv[0], c->split0, w, hptr, v, c->wq);
         amg_cycle(c, 0);
-        const IluRhs R{hptr ? v : w, c->ap, c->colsplit, c->split0, c->lv[0].x, 2 * c->lv[0].half};
-        launch_ilu_solve(c->s, c->nb, c->g, c->ilu, c->sys(), c->lu, R, z);
+        const T *rhs = v;
+        if constexpr (same) {
+            if (!v) rhs = w;
+        }
+        const IluRhs<T, T> R{rhs, Kry<T>::ap(c), c->colsplit, c->split0, c->lv[0].x,
+                             2 * c->lv[0].half};
+        launch_ilu_solve(c->s, c->nb, c->g, c->ilu, c->sys(), Kry<T>::lu(c), R, z);
     } else if (c->opt.precond == FIM_PREC_ILU0) {
-        if (hptr) launch_normalize(c->s, c->nvec, w, hptr, v);
-        const IluRhs R{hptr ? v : w, nullptr, nullptr, nullptr, nullptr, 0};
-        launch_ilu_solve(c->s, c->nb, c->g, c->ilu, c->sys(), c->lu, R, z);
-    } else if (c->opt.precond == FIM_PREC_CPR) {
-        launch_cpr_restrict(c->s, c->nb, c->n, c->nw, c->lv[0], c->split0, w, hptr, v, c->wq);
-        amg_cycle(c, 0);
-        launch_cpr_finish(c->s, c->nb, c->n, c->nw, c->lv[0], c->split0, c->colsplit, c->sys(), c->ap, hptr ? v : w,
-                          c->dinv, z);
-    } else if (hptr) {
-        launch_normalize_precond(c->s, c->nb, c->nrows, w, hptr, v, z, c->dinv);
+        const T *rhs = v;
+        if (hptr) {
+            launch_normalize(c->s, c->nvec, w, hptr, v);
+        } else if constexpr (same) {
+            rhs = w;
+        } else {
+            launch_to_float(c->s, c->nvec, w, v);
+        }
+        const IluRhs<T, T> R{rhs, nullptr, nullptr, nullptr, nullptr, 0};
+        launch_ilu_solve(c->s, c->nb, c->g, c->ilu, c->sys(), Kry<T>::lu(c), R, z);
     } else {
-        launch_bj_apply(c->s, c->nb, c->nrows, c->dinv, w, z);
+        if constexpr (std::is_same<T, double>::value && same) {
+            if (c->opt.precond == FIM_PREC_CPR) {
+                launch_cpr_restrict(c->s, c->nb, c->n, c->nw, c->lv[0], c->split0, w, hptr, v,
+                                    c->wq);
+                amg_cycle(c, 0);
+                launch_cpr_finish(c->s, c->nb, c->n, c->nw, c->lv[0], c->split0, c->colsplit,
+                                  c->sys(), c->ap, hptr ? v : w, c->dinv, z);
+            } else if (hptr) {
+                launch_normalize_precond(c->s, c->nb, c->nrows, w, hptr, v, z, c->dinv);
+            } else {
+                launch_bj_apply(c->s, c->nb, c->nrows, c->dinv, w, z);
+            }
+        } else {
+            throw std::logic_error("preconditioner not available in single precision");
+        }
     }
 }
 
-// SpMV inside the solver, optionally bracketed by events
-static void solver_spmv(fim_ctx *c, const double *xin, double *yout, bool profile) {
+// SpMV inside the solver (y = J x in T), optionally bracketed by events
+template <class T>
+static void solver_spmv(fim_ctx *c, const T *xin, T *yout, bool profile) {
     if (profile) {
         if (c->spmv_used + 2 > (int)c->spmv_ev.size()) {
             // pool full: drain it
@@ -965,12 +1057,12 @@ static void solver_spmv(fim_ctx *c, const double *xin, double *yout, bool profil
             c->spmv_used = 0;
         }
         HIPCHECK(hipEventRecord(c->spmv_ev[c->spmv_used], c->s));
-        launch_spmv(c->s, c->nb, c->nrows, c->rowptr, c->colind, c->val, xin, yout);
+        launch_spmv(c->s, c->nb, c->nrows, c->rowptr, c->colind, Kry<T>::val(c), xin, yout);
         HIPCHECK(hipEventRecord(c->spmv_ev[c->spmv_used + 1], c->s));
         c->spmv_used += 2;
         c->spmv_calls += 1;
     } else {
-        launch_spmv(c->s, c->nb, c->nrows, c->rowptr, c->colind, c->val, xin, yout);
+        launch_spmv(c->s, c->nb, c->nrows, c->rowptr, c->colind, Kry<T>::val(c), xin, yout);
     }
 }
 
@@ -995,28 +1087,31 @@ static void drain_spmv_events(fim_ctx *c) {
 // Arnoldi step j after its SpMV (w = J z_j): two Gram-Schmidt passes (the
 // second gated on the device), the new basis vector and its preconditioned
 // image, and the copy of the Hessenberg column to pinned host memory.
+template <class T>
 static void arnoldi_rest(fim_ctx *c, int j) {
     const long nv = c->nvec;
     const int LD = kMaxRestart + 2;
     double *col = c->H + (size_t)j * LD;
     double *pinH = c->pin + S_COUNT;
-    launch_multidot(c->s, nv, j + 1, c->V, c->w, c->partials, col, nullptr);
-    launch_update_norm(c->s, nv, j + 1, c->V, col, c->w, c->partials, col + j + 1,
-                       nullptr, c->reorth, nullptr);
-    launch_multidot(c->s, nv, j + 1, c->V, c->w, c->partials, c->tmp, c->reorth);
-    launch_update_norm(c->s, nv, j + 1, c->V, c->tmp, c->w, c->partials, col + j + 1,
-                       c->reorth, nullptr, col);
-    precondition(c, c->w, col + j + 1, c->V + (size_t)(j + 1) * nv, c->Z + (size_t)(j + 1) * nv);
+    T *V = Kry<T>::V(c), *Z = Kry<T>::Z(c), *w = Kry<T>::w(c);
+    launch_multidot(c->s, nv, j + 1, V, w, c->partials, col, nullptr);
+    launch_update_norm(c->s, nv, j + 1, V, col, w, c->partials, col + j + 1, nullptr, c->reorth,
+                       nullptr);
+    launch_multidot(c->s, nv, j + 1, V, w, c->partials, c->tmp, c->reorth);
+    launch_update_norm(c->s, nv, j + 1, V, c->tmp, w, c->partials, col + j + 1, c->reorth,
+                       nullptr, col);
+    precondition<T, T>(c, w, col + j + 1, V + (size_t)(j + 1) * nv, Z + (size_t)(j + 1) * nv);
     HIPCHECK(hipMemcpyAsync(pinH + (size_t)j * LD, col, (j + 2) * sizeof(double),
                             hipMemcpyDeviceToHost, c->s));
 }
 
+template <class T>
 static void arnoldi_rest_graph(fim_ctx *c, int j) {
     if (!c->step_exec[j]) {
         hipGraph_t graph = nullptr;
         HIPCHECK(hipStreamBeginCapture(c->s, hipStreamCaptureModeThreadLocal));
         try {
-            arnoldi_rest(c, j);
+            arnoldi_rest<T>(c, j);
         } catch (...) {
             (void)hipStreamEndCapture(c->s, &graph);
             if (graph) (void)hipGraphDestroy(graph);
@@ -1051,8 +1146,15 @@ struct Forcing {
     }
 };
 
-static int gmres(fim_ctx *c, const double *bvec, double *xvec, int max_it, double rtol,
-                 bool profile, int *iters_out, double *relres_out, Forcing *forcing = nullptr) {
+// In the mixed mode (T = float) every restart cycle is a single-precision
+// inner solve of J d = r / ||r|| and every restart an FP64 refinement step
+// (x += d, r = b - J x with the FP64 Jacobian); a cycle stops once its
+// estimate fell kInner below its start, the limit of single precision.
+template <class T>
+static int gmres_t(fim_ctx *c, const double *bvec, double *xvec, int max_it, double rtol,
+                   bool profile, int *iters_out, double *relres_out, Forcing *forcing) {
+    constexpr double kInner = std::is_same<T, float>::value ? 1e-5 : 0.0;
+    T *V = Kry<T>::V(c), *Z = Kry<T>::Z(c), *w = Kry<T>::w(c);
     const int m = c->m;
     const long nv = c->nvec;
     const int LD = kMaxRestart + 2;          // stride of a Hessenberg column
@@ -1078,15 +1180,16 @@ static int gmres(fim_ctx *c, const double *bvec, double *xvec, int max_it, doubl
     double relres = 1.0;
 
     auto enqueue = [&](int j) {
-        solver_spmv(c, c->Z + (size_t)j * nv, c->w, profile);
-        if (c->opt.graphs) arnoldi_rest_graph(c, j);
-        else arnoldi_rest(c, j);
+        solver_spmv<T>(c, Z + (size_t)j * nv, w, profile);
+        if (c->opt.graphs) arnoldi_rest_graph<T>(c, j);
+        else arnoldi_rest<T>(c, j);
         HIPCHECK(hipEventRecord(colev[j], c->s));
     };
 
     {
         for (;;) {
-            precondition(c, rvec, beta_dev, c->V, c->Z);
+            precondition<double, T>(c, rvec, beta_dev, V, Z);
+            const double stop = std::max(rtol * bnorm, kInner * beta);
             std::fill(g.begin(), g.end(), 0.0);
             g[0] = beta;
             int k = 0;
@@ -1111,7 +1214,7 @@ static int gmres(fim_ctx *c, const double *bvec, double *xvec, int max_it, doubl
                 g[j] = cs[j] * g[j];
                 k = j + 1;
                 const bool breakdown = !(h[j + 1] > 0.0) || !std::isfinite(h[j + 1]);
-                if (std::fabs(g[j + 1]) <= rtol * bnorm || k == m || total + k >= max_it ||
+                if (std::fabs(g[j + 1]) <= stop || k == m || total + k >= max_it ||
                     breakdown || !std::isfinite(g[j + 1]))
                     break;
             }
@@ -1124,8 +1227,8 @@ static int gmres(fim_ctx *c, const double *bvec, double *xvec, int max_it, doubl
             }
             for (int i = 0; i < k; ++i) piny[i] = y[i];
             HIPCHECK(hipMemcpyAsync(c->ydev, piny, k * sizeof(double), hipMemcpyHostToDevice, c->s));
-            launch_axpy_multi(c->s, nv, k, c->Z, c->ydev, xvec);
-            solver_spmv(c, xvec, c->t, profile);
+            launch_axpy_multi(c->s, nv, k, Z, c->ydev, xvec);
+            launch_spmv(c->s, c->nb, c->nrows, c->rowptr, c->colind, c->val, xvec, c->t);
             launch_residual(c->s, nv, bvec, c->t, c->r, c->partials, c->scal + S_RES);
             d2h_scalars(c, S_RES, 2);
             c->sync();
@@ -1143,6 +1246,13 @@ static int gmres(fim_ctx *c, const double *bvec, double *xvec, int max_it, doubl
     *iters_out = total;
     *relres_out = relres;
     return status;
+}
+
+static int gmres(fim_ctx *c, const double *bvec, double *xvec, int max_it, double rtol,
+                 bool profile, int *iters_out, double *relres_out, Forcing *forcing = nullptr) {
+    if (c->mixed)
+        return gmres_t<float>(c, bvec, xvec, max_it, rtol, profile, iters_out, relres_out, forcing);
+    return gmres_t<double>(c, bvec, xvec, max_it, rtol, profile, iters_out, relres_out, forcing);
 }
 
 // ---------------------------------------------------------------------------
@@ -1387,6 +1497,8 @@ int fim_set_options(fim_ctx *c, const fim_options *opt) {
         c->opt = *opt;
         build_subcycle(c);
         build_ilu(c);
+        ensure_mixed(c);
+        c->prec_ready = false;
         return FIM_OK;
     });
 }
@@ -1534,7 +1646,12 @@ int fim_precond_apply(fim_ctx *c, const double *xh, double *yh) {
         }
         prec_setup(c);
         HIPCHECK(hipMemcpyAsync(c->b, xh, c->nvec * 8, hipMemcpyHostToDevice, c->s));
-        precondition(c, c->b, nullptr, nullptr, c->t);
+        if (c->mixed) {
+            precondition<double, float>(c, c->b, nullptr, c->V32, c->Z32);
+            launch_to_double(c->s, c->nvec, c->Z32, c->t);
+        } else {
+            precondition<double, double>(c, c->b, nullptr, nullptr, c->t);
+        }
         HIPCHECK(hipMemcpyAsync(yh, c->t, c->nvec * 8, hipMemcpyDeviceToHost, c->s));
         c->sync();
         return FIM_OK;

@@ -42,25 +42,29 @@ __device__ inline TileBox tile_box(const Grid &g, const IluTiles &T, int b) {
 
 // Copy of A's blocks [q0, q1) into lu by the whole workgroup (contiguous,
 // 16-byte accesses).
-__device__ inline void copy_blocks(const double *__restrict__ val, double *__restrict__ lu,
-                                   long q0, long q1, int b2) {
+template <class LT>
+__device__ inline void copy_blocks(const double *__restrict__ val, LT *__restrict__ lu, long q0,
+                                   long q1, int b2) {
     typedef double d2v __attribute__((ext_vector_type(2)));
     const long e0 = q0 * b2, e1 = q1 * b2;        // element range
     long e = e0 + threadIdx.x * 2;
     if (e0 & 1) {                                  // odd start: one scalar first
-        if (threadIdx.x == 0) lu[e0] = val[e0];
+        if (threadIdx.x == 0) lu[e0] = (LT)val[e0];
         e = e0 + 1 + threadIdx.x * 2;
     }
-    for (; e + 1 < e1; e += 2L * blockDim.x)
-        *reinterpret_cast<d2v *>(lu + e) = *reinterpret_cast<const d2v *>(val + e);
-    if (e < e1) lu[e] = val[e];
+    for (; e + 1 < e1; e += 2L * blockDim.x) {
+        const d2v v = *reinterpret_cast<const d2v *>(val + e);
+        lu[e] = (LT)v.x;
+        lu[e + 1] = (LT)v.y;
+    }
+    if (e < e1) lu[e] = (LT)val[e];
 }
 
 // ILU(0) of one row in place (lu holds A's values for the row on entry):
 // IKJ form restricted to the row's tile.  The row's lower neighbours in its
 // tile are factored already.
-template <int NB>
-__device__ void factor_row(int row, const IluTiles &T, const Sys &sys, double *lu, int *bad) {
+template <int NB, class LT>
+__device__ void factor_row(int row, const IluTiles &T, const Sys &sys, LT *lu, int *bad) {
     constexpr int B2 = NB * NB;
     const int t = T.rtile[row];
     const int b0 = sys.rowptr[row], b1 = sys.rowptr[row + 1];
@@ -71,12 +75,12 @@ __device__ void factor_row(int row, const IluTiles &T, const Sys &sys, double *l
         double a[B2], u[B2], l[B2];
 #pragma unroll
         for (int e = 0; e < B2; ++e) {
-            a[e] = lu[(size_t)qk * B2 + e];
-            u[e] = lu[(size_t)sys.diagpos[k] * B2 + e];
+            a[e] = (double)lu[(size_t)qk * B2 + e];
+            u[e] = (double)lu[(size_t)sys.diagpos[k] * B2 + e];
         }
         block_mul<NB>(a, u, l);
 #pragma unroll
-        for (int e = 0; e < B2; ++e) lu[(size_t)qk * B2 + e] = l[e];
+        for (int e = 0; e < B2; ++e) lu[(size_t)qk * B2 + e] = (LT)l[e];
         const int k0 = sys.rowptr[k], k1 = sys.rowptr[k + 1];
         for (int qj = qk + 1; qj < b1; ++qj) {
             const int j = sys.colind[qj];
@@ -85,24 +89,25 @@ __device__ void factor_row(int row, const IluTiles &T, const Sys &sys, double *l
                 if (sys.colind[qkj] != j) continue;
                 double ukj[B2], p[B2];
 #pragma unroll
-                for (int e = 0; e < B2; ++e) ukj[e] = lu[(size_t)qkj * B2 + e];
+                for (int e = 0; e < B2; ++e) ukj[e] = (double)lu[(size_t)qkj * B2 + e];
                 block_mul<NB>(l, ukj, p);
 #pragma unroll
-                for (int e = 0; e < B2; ++e) lu[(size_t)qj * B2 + e] -= p[e];
+                for (int e = 0; e < B2; ++e)
+                    lu[(size_t)qj * B2 + e] = (LT)((double)lu[(size_t)qj * B2 + e] - p[e]);
             }
         }
     }
     const int di = sys.diagpos[row];
     double d[B2], inv[B2];
 #pragma unroll
-    for (int e = 0; e < B2; ++e) d[e] = lu[(size_t)di * B2 + e];
+    for (int e = 0; e < B2; ++e) d[e] = (double)lu[(size_t)di * B2 + e];
     if (!invert_block<NB>(d, inv)) {
         *bad = 1;
 #pragma unroll
         for (int e = 0; e < B2; ++e) inv[e] = (e % (NB + 1) == 0) ? 1.0 : 0.0;
     }
 #pragma unroll
-    for (int e = 0; e < B2; ++e) lu[(size_t)di * B2 + e] = inv[e];
+    for (int e = 0; e < B2; ++e) lu[(size_t)di * B2 + e] = (LT)inv[e];
 }
 
 // The same factorisation for a cell row without well columns, found from
@@ -111,9 +116,9 @@ __device__ void factor_row(int row, const IluTiles &T, const Sys &sys, double *l
 // over the lower neighbours k of the tile (in column order -z, -y, -x),
 // with U_ki the +z / +y / +x block of row k.  Returns false (nothing done)
 // for rows with well columns.
-template <int NB>
+template <int NB, class LT>
 __device__ bool factor_cell_row(int i, int j, int k, const Grid &g, const IluTiles &T,
-                                const TileBox &tb, const Sys &sys, double *lu, int *bad) {
+                                const TileBox &tb, const Sys &sys, LT *lu, int *bad) {
     constexpr int B2 = NB * NB;
     const int r = i + g.nx * (j + g.ny * k);
     const int q0 = sys.rowptr[r];
@@ -123,7 +128,7 @@ __device__ bool factor_cell_row(int i, int j, int k, const Grid &g, const IluTil
     const int qd = q0 + nlow;
     double d[B2];
 #pragma unroll
-    for (int e = 0; e < B2; ++e) d[e] = lu[(size_t)qd * B2 + e];
+    for (int e = 0; e < B2; ++e) d[e] = (double)lu[(size_t)qd * B2 + e];
     const int li = i - tb.i0, lj = j - tb.j0, lk = k - tb.k0;
     // lower neighbours in column order; for each: its row index, the
     // position of its diagonal and of its block towards row r
@@ -142,14 +147,14 @@ __device__ bool factor_cell_row(int i, int j, int k, const Grid &g, const IluTil
             double a[B2], u[B2], l[B2], uk[B2], p[B2];
 #pragma unroll
             for (int e = 0; e < B2; ++e) {
-                a[e] = lu[(size_t)qk * B2 + e];
-                u[e] = lu[(size_t)qdk * B2 + e];
+                a[e] = (double)lu[(size_t)qk * B2 + e];
+                u[e] = (double)lu[(size_t)qdk * B2 + e];
             }
             block_mul<NB>(a, u, l);
 #pragma unroll
             for (int e = 0; e < B2; ++e) {
-                lu[(size_t)qk * B2 + e] = l[e];
-                uk[e] = lu[(size_t)qki * B2 + e];
+                lu[(size_t)qk * B2 + e] = (LT)l[e];
+                uk[e] = (double)lu[(size_t)qki * B2 + e];
             }
             block_mul<NB>(l, uk, p);
 #pragma unroll
@@ -164,32 +169,32 @@ __device__ bool factor_cell_row(int i, int j, int k, const Grid &g, const IluTil
         for (int e = 0; e < B2; ++e) inv[e] = (e % (NB + 1) == 0) ? 1.0 : 0.0;
     }
 #pragma unroll
-    for (int e = 0; e < B2; ++e) lu[(size_t)qd * B2 + e] = inv[e];
+    for (int e = 0; e < B2; ++e) lu[(size_t)qd * B2 + e] = (LT)inv[e];
     return true;
 }
 
 // inverse of the diagonal block of a row that is a subdomain of its own
-template <int NB>
-__device__ void factor_alone(int row, const Sys &sys, double *lu, int *bad) {
+template <int NB, class LT>
+__device__ void factor_alone(int row, const Sys &sys, LT *lu, int *bad) {
     constexpr int B2 = NB * NB;
     const int di = sys.diagpos[row];
     double d[B2], inv[B2];
 #pragma unroll
-    for (int e = 0; e < B2; ++e) d[e] = lu[(size_t)di * B2 + e];
+    for (int e = 0; e < B2; ++e) d[e] = (double)lu[(size_t)di * B2 + e];
     if (!invert_block<NB>(d, inv)) {
         *bad = 1;
 #pragma unroll
         for (int e = 0; e < B2; ++e) inv[e] = (e % (NB + 1) == 0) ? 1.0 : 0.0;
     }
 #pragma unroll
-    for (int e = 0; e < B2; ++e) lu[(size_t)di * B2 + e] = inv[e];
+    for (int e = 0; e < B2; ++e) lu[(size_t)di * B2 + e] = (LT)inv[e];
 }
 
 // One workgroup per tile, then one for the wells that stand alone.  The
 // tile's rows (cells and its wells) are copied from A first, each x-row of
 // the tile being one contiguous run of blocks.
-template <int NB>
-__global__ __launch_bounds__(256) void k_ilu_factor(Grid g, IluTiles T, Sys sys, double *lu,
+template <int NB, class LT>
+__global__ __launch_bounds__(256) void k_ilu_factor(Grid g, IluTiles T, Sys sys, LT *lu,
                                                     int *bad) {
     constexpr int B2 = NB * NB;
     const int b = blockIdx.x;
@@ -201,7 +206,7 @@ __global__ __launch_bounds__(256) void k_ilu_factor(Grid g, IluTiles T, Sys sys,
         }
         __syncthreads();
         for (int e = threadIdx.x; e < T.nsingle; e += blockDim.x)
-            factor_alone<NB>(g.n + T.single[e], sys, lu, bad);
+            factor_alone<NB, LT>(g.n + T.single[e], sys, lu, bad);
         return;
     }
     const TileBox tb = tile_box(g, T, b);
@@ -221,24 +226,24 @@ __global__ __launch_bounds__(256) void k_ilu_factor(Grid g, IluTiles T, Sys sys,
             const int li = p % tb.txe, lj = p / tb.txe, lk = s - li - lj;
             if (lk < 0 || lk >= tb.tze) continue;
             const int i = tb.i0 + li, j = tb.j0 + lj, k = tb.k0 + lk;
-            if (!factor_cell_row<NB>(i, j, k, g, T, tb, sys, lu, bad))
-                factor_row<NB>(i + g.nx * (j + g.ny * k), T, sys, lu, bad);
+            if (!factor_cell_row<NB, LT>(i, j, k, g, T, tb, sys, lu, bad))
+                factor_row<NB, LT>(i + g.nx * (j + g.ny * k), T, sys, lu, bad);
         }
         __syncthreads();
     }
     for (int e = T.twp[b] + threadIdx.x; e < T.twp[b + 1]; e += blockDim.x)
-        factor_row<NB>(g.n + T.tw[e], T, sys, lu, bad);
+        factor_row<NB, LT>(g.n + T.tw[e], T, sys, lu, bad);
 }
 
 // acc -= blk * v (block-vector product summed first, as a matrix-vector
 // product would)
-template <int NB>
-__device__ inline void sub_mv(double (&acc)[NB], const double *blk, const double *v) {
+template <int NB, class BT>
+__device__ inline void sub_mv(double (&acc)[NB], const BT *blk, const double *v) {
 #pragma unroll
     for (int r = 0; r < NB; ++r) {
-        double t = blk[r * NB] * v[0];
+        double t = (double)blk[r * NB] * v[0];
 #pragma unroll
-        for (int c = 1; c < NB; ++c) t += blk[r * NB + c] * v[c];
+        for (int c = 1; c < NB; ++c) t += (double)blk[r * NB + c] * v[c];
         acc[r] -= t;
     }
 }
@@ -248,10 +253,10 @@ struct Blk {
     double v[NB * NB];
 };
 
-template <int NB>
-__device__ inline void load_blk(Blk<NB> &dst, const double *src) {
+template <int NB, class LT>
+__device__ inline void load_blk(Blk<NB> &dst, const LT *src) {
 #pragma unroll
-    for (int e = 0; e < NB * NB; ++e) dst.v[e] = src[e];
+    for (int e = 0; e < NB * NB; ++e) dst.v[e] = (double)src[e];
 }
 
 // Right-hand side of row r: b, or for the CPR second stage the residual
@@ -260,11 +265,11 @@ __device__ inline void load_blk(Blk<NB> &dst, const double *src) {
 // first slot of the result.
 // (the first eight blocks of the row issue their loads together; longer
 // rows, of perforated cells and wells, finish in a loop)
-template <int NB>
-__device__ inline void rhs_row(const IluRhs &R, const Sys &sys, int r, double (&acc)[NB],
+template <int NB, class RT>
+__device__ inline void rhs_row(const RT &R, const Sys &sys, int r, double (&acc)[NB],
                                int q0 = -1) {
 #pragma unroll
-    for (int u = 0; u < NB; ++u) acc[u] = R.b[(size_t)r * NB + u];
+    for (int u = 0; u < NB; ++u) acc[u] = (double)R.b[(size_t)r * NB + u];
     if (!R.ap) return;
     if (q0 < 0) q0 = sys.rowptr[r];
     const int q1 = sys.rowptr[r + 1];
@@ -279,15 +284,16 @@ __device__ inline void rhs_row(const IluRhs &R, const Sys &sys, int r, double (&
     for (int k = 0; k < K; ++k)
         if (cs[k] >= 0)
 #pragma unroll
-            for (int u = 0; u < NB; ++u) acc[u] -= R.ap[(size_t)(q0 + k) * NB + u] * p[k];
+            for (int u = 0; u < NB; ++u) acc[u] -= (double)R.ap[(size_t)(q0 + k) * NB + u] * p[k];
     for (int q = q0 + K; q < q1; ++q) {
         const double pq = R.px[R.colsplit[q]];
 #pragma unroll
-        for (int u = 0; u < NB; ++u) acc[u] -= R.ap[(size_t)q * NB + u] * pq;
+        for (int u = 0; u < NB; ++u) acc[u] -= (double)R.ap[(size_t)q * NB + u] * pq;
     }
 }
 
-__device__ inline double rhs_corr(const IluRhs &R, int n, int r) {
+template <class RT>
+__device__ inline double rhs_corr(const RT &R, int n, int r) {
     if (!R.ap) return 0.0;
     return r < n ? R.px[R.split0[r]] : R.px[R.nsplit + (r - n)];
 }
@@ -295,9 +301,9 @@ __device__ inline double rhs_corr(const IluRhs &R, int n, int r) {
 // The tile's wells, between the forward and backward sweeps over its cells:
 // forward over their perforated cells (all in the tile), then x = inv(U) y
 // (well rows have no upper part).
-template <int NB>
+template <int NB, class LT, class RT>
 __device__ void solve_tile_wells(const Grid &g, const TileBox &tb, const Sys &sys,
-                                 const double *lu, const IluRhs &R, double *y, const IluTiles &T,
+                                 const LT *lu, const RT &R, double *y, const IluTiles &T,
                                  int w0, int nwt, int ncell) {
     constexpr int B2 = NB * NB;
     const int n = g.n;
@@ -325,9 +331,9 @@ __device__ void solve_tile_wells(const Grid &g, const TileBox &tb, const Sys &sy
 // cells while the hyperplanes before them are solved.  Row starts and the
 // right side are staged in LDS first.  Same arithmetic, same order, as the
 // general sweeps.
-template <int NB>
+template <int NB, class LT, class RT>
 __device__ void solve_cells_pencils(const Grid &g, const TileBox &tb, const Sys &sys,
-                                    const double *__restrict__ lu, const IluRhs &R,
+                                    const LT *__restrict__ lu, const RT &R,
                                     double *y, int *rp, const IluTiles &T, int blk, int w0, int nwt,
                                     int ncell) {
     constexpr int B2 = NB * NB;
@@ -400,7 +406,7 @@ __device__ void solve_cells_pencils(const Grid &g, const TileBox &tb, const Sys 
         }
         __syncthreads();
     }
-    solve_tile_wells<NB>(g, tb, sys, lu, R, y, T, w0, nwt, ncell);
+    solve_tile_wells<NB, LT>(g, tb, sys, lu, R, y, T, w0, nwt, ncell);
     __syncthreads();
     // backward: +x, +y, +z blocks and the inverted diagonal of cell lk
     auto upper = [&](int lk, Blk<NB> &ux, Blk<NB> &uy, Blk<NB> &uz, Blk<NB> &dd) {
@@ -457,9 +463,10 @@ __device__ void solve_cells_pencils(const Grid &g, const TileBox &tb, const Sys 
 // x = M^-1 rhs: forward (L y = rhs, L unit lower) and backward (U x = y)
 // inside every tile; for the CPR second stage the first-stage correction is
 // added to the first slot of every row of x.
-template <int NB>
-__global__ __launch_bounds__(256) void k_ilu_solve(Grid g, IluTiles T, Sys sys, const double *__restrict__ lu,
-                            IluRhs R, double *__restrict__ x) {
+template <int NB, class LT, class VT>
+__global__ __launch_bounds__(256) void k_ilu_solve(Grid g, IluTiles T, Sys sys,
+                                                   const LT *__restrict__ lu, IluRhs<VT, LT> R,
+                                                   VT *__restrict__ x) {
     constexpr int B2 = NB * NB;
     extern __shared__ double y[];
     const int blk = blockIdx.x;
@@ -472,7 +479,7 @@ __global__ __launch_bounds__(256) void k_ilu_solve(Grid g, IluTiles T, Sys sys, 
             rhs_row<NB>(R, sys, r, rhs);
             sub_mv<NB>(acc, lu + (size_t)sys.diagpos[r] * B2, rhs);
 #pragma unroll
-            for (int u = 0; u < NB; ++u) x[(size_t)r * NB + u] = -acc[u] + (u == 0 ? rhs_corr(R, n, r) : 0.0);
+            for (int u = 0; u < NB; ++u) x[(size_t)r * NB + u] = (VT)(-acc[u] + (u == 0 ? rhs_corr(R, n, r) : 0.0));
         }
         return;
     }
@@ -481,7 +488,7 @@ __global__ __launch_bounds__(256) void k_ilu_solve(Grid g, IluTiles T, Sys sys, 
     const int w0 = T.twp[blk], nwt = T.twp[blk + 1] - w0;
     const int nlev = tb.txe + tb.tye + tb.tze - 2;
     if (sxy <= (int)blockDim.x) {
-        solve_cells_pencils<NB>(g, tb, sys, lu, R, y, reinterpret_cast<int *>(y + (size_t)(ncell + T.maxwells) * NB),
+        solve_cells_pencils<NB, LT>(g, tb, sys, lu, R, y, reinterpret_cast<int *>(y + (size_t)(ncell + T.maxwells) * NB),
                                 T, blk, w0, nwt, ncell);
     } else {
     // forward over the hyperplanes
@@ -508,7 +515,7 @@ __global__ __launch_bounds__(256) void k_ilu_solve(Grid g, IluTiles T, Sys sys, 
         }
         __syncthreads();
     }
-    solve_tile_wells<NB>(g, tb, sys, lu, R, y, T, w0, nwt, ncell);
+    solve_tile_wells<NB, LT>(g, tb, sys, lu, R, y, T, w0, nwt, ncell);
     __syncthreads();
     // backward over the hyperplanes
     for (int s = nlev - 1; s >= 0; --s) {
@@ -557,33 +564,43 @@ __global__ __launch_bounds__(256) void k_ilu_solve(Grid g, IluTiles T, Sys sys, 
         }
 #pragma unroll
         for (int u = 0; u < NB; ++u)
-            x[(size_t)r * NB + u] = y[(size_t)l * NB + u] + (u == 0 ? rhs_corr(R, n, r) : 0.0);
+            x[(size_t)r * NB + u] = (VT)(y[(size_t)l * NB + u] + (u == 0 ? rhs_corr(R, n, r) : 0.0));
     }
 }
 
 // v = w / h for a new Arnoldi vector (zero when h is not a positive number)
-__global__ __launch_bounds__(kBlock) void k_normalize(long nvec, const double *__restrict__ w,
+template <class WT, class VT>
+__global__ __launch_bounds__(kBlock) void k_normalize(long nvec, const WT *__restrict__ w,
                                                       const double *__restrict__ hptr,
-                                                      double *__restrict__ v) {
+                                                      VT *__restrict__ v) {
     const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= nvec) return;
     const double h = *hptr;
-    v[e] = (h > 0.0 && isfinite(h)) ? w[e] / h : 0.0;
+    v[e] = (VT)((h > 0.0 && isfinite(h)) ? (double)w[e] / h : 0.0);
 }
 
 // ---------------------------------------------------------------------------
 // launchers
 
-void launch_ilu_factor(hipStream_t s, int nb, Grid g, const IluTiles &T, Sys sys, double *lu,
-                       int *bad) {
+template <class LT>
+static void ilu_factor_impl(hipStream_t s, int nb, Grid g, const IluTiles &T, Sys sys, LT *lu,
+                            int *bad) {
     const int nblk = T.ntx * T.nty * T.ntz + (T.nsingle > 0 ? 1 : 0);
     const int bs = ilu_threads(T);
-    if (nb == 2) hipLaunchKernelGGL(k_ilu_factor<2>, dim3(nblk), dim3(bs), 0, s, g, T, sys, lu, bad);
-    else hipLaunchKernelGGL(k_ilu_factor<3>, dim3(nblk), dim3(bs), 0, s, g, T, sys, lu, bad);
+    if (nb == 2) hipLaunchKernelGGL((k_ilu_factor<2, LT>), dim3(nblk), dim3(bs), 0, s, g, T, sys, lu, bad);
+    else hipLaunchKernelGGL((k_ilu_factor<3, LT>), dim3(nblk), dim3(bs), 0, s, g, T, sys, lu, bad);
 }
 
-// One thread per (li, lj) pencil, in whole waves (more waves per tile were
-// measured slower: they all wait at every hyperplane barrier).
+void launch_ilu_factor(hipStream_t s, int nb, Grid g, const IluTiles &T, Sys sys, double *lu,
+                       int *bad) {
+    ilu_factor_impl(s, nb, g, T, sys, lu, bad);
+}
+
+void launch_ilu_factor(hipStream_t s, int nb, Grid g, const IluTiles &T, Sys sys, float *lu,
+                       int *bad) {
+    ilu_factor_impl(s, nb, g, T, sys, lu, bad);
+}
+
 int ilu_threads(const IluTiles &T) {
     const int pairs = T.tx * T.ty;
     return pairs >= 256 ? 256 : ((pairs + 63) / 64) * 64;
@@ -595,28 +612,59 @@ size_t ilu_solve_lds(int nb, const IluTiles &T) {
            (size_t)T.tx * T.ty * T.tz * sizeof(int);
 }
 
-hipError_t ilu_allow_lds(int nb, size_t bytes) {
+template <class LT, class VT>
+static hipError_t allow_lds_impl(int nb, size_t bytes) {
     if (nb == 2)
-        return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ilu_solve<2>),
+        return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ilu_solve<2, LT, VT>),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ilu_solve<3>),
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ilu_solve<3, LT, VT>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-void launch_ilu_solve(hipStream_t s, int nb, Grid g, const IluTiles &T, Sys sys,
-                      const double *lu, const IluRhs &R, double *x) {
+hipError_t ilu_allow_lds(int nb, size_t bytes) {
+    hipError_t e = allow_lds_impl<double, double>(nb, bytes);
+    if (e == hipSuccess) e = allow_lds_impl<float, float>(nb, bytes);
+    return e;
+}
+
+template <class LT, class VT>
+static void ilu_solve_impl(hipStream_t s, int nb, Grid g, const IluTiles &T, Sys sys,
+                           const LT *lu, const IluRhs<VT, LT> &R, VT *x) {
     const int nblk = T.ntx * T.nty * T.ntz + (T.nsingle > 0 ? 1 : 0);
     const int bs = ilu_threads(T);
     const size_t lds = ilu_solve_lds(nb, T);
     if (nb == 2)
-        hipLaunchKernelGGL(k_ilu_solve<2>, dim3(nblk), dim3(bs), lds, s, g, T, sys, lu, R, x);
+        hipLaunchKernelGGL((k_ilu_solve<2, LT, VT>), dim3(nblk), dim3(bs), lds, s, g, T, sys, lu, R, x);
     else
-        hipLaunchKernelGGL(k_ilu_solve<3>, dim3(nblk), dim3(bs), lds, s, g, T, sys, lu, R, x);
+        hipLaunchKernelGGL((k_ilu_solve<3, LT, VT>), dim3(nblk), dim3(bs), lds, s, g, T, sys, lu, R, x);
+}
+
+void launch_ilu_solve(hipStream_t s, int nb, Grid g, const IluTiles &T, Sys sys,
+                      const double *lu, const IluRhs<double, double> &R, double *x) {
+    ilu_solve_impl(s, nb, g, T, sys, lu, R, x);
+}
+
+void launch_ilu_solve(hipStream_t s, int nb, Grid g, const IluTiles &T, Sys sys,
+                      const float *lu, const IluRhs<float, float> &R, float *x) {
+    ilu_solve_impl(s, nb, g, T, sys, lu, R, x);
+}
+
+template <class WT, class VT>
+static void normalize_impl(hipStream_t s, long nvec, const WT *w, const double *hptr, VT *v) {
+    hipLaunchKernelGGL((k_normalize<WT, VT>), dim3((unsigned)((nvec + kBlock - 1) / kBlock)),
+                       dim3(kBlock), 0, s, nvec, w, hptr, v);
 }
 
 void launch_normalize(hipStream_t s, long nvec, const double *w, const double *hptr, double *v) {
-    hipLaunchKernelGGL(k_normalize, dim3((unsigned)((nvec + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                       s, nvec, w, hptr, v);
+    normalize_impl(s, nvec, w, hptr, v);
+}
+
+void launch_normalize(hipStream_t s, long nvec, const double *w, const double *hptr, float *v) {
+    normalize_impl(s, nvec, w, hptr, v);
+}
+
+void launch_normalize(hipStream_t s, long nvec, const float *w, const double *hptr, float *v) {
+    normalize_impl(s, nvec, w, hptr, v);
 }
 
 }  // namespace fim

@@ -129,6 +129,10 @@ int update_blocks(int n);
 // ---- linear algebra kernels (fim_linalg.hip) --------------------------------
 void launch_spmv(hipStream_t s, int nb, int nrows, const int *rowptr, const int *colind,
                  const double *val, const double *x, double *y);
+void launch_spmv(hipStream_t s, int nb, int nrows, const int *rowptr, const int *colind,
+                 const float *val, const float *x, float *y);
+void launch_to_float(hipStream_t s, long n, const double *x, float *y);
+void launch_to_double(hipStream_t s, long n, const float *x, double *y);
 void launch_bj_setup(hipStream_t s, int nb, int nrows, const int *diagpos, const double *val,
                      double *dinv, int *bad);
 void launch_bj_apply(hipStream_t s, int nb, int nrows, const double *dinv, const double *x,
@@ -140,19 +144,28 @@ void launch_normalize_precond(hipStream_t s, int nb, int nrows, const double *w,
                               const double *hptr, double *v, double *z, const double *dinv);
 void launch_multidot(hipStream_t s, long nvec, int nv, const double *V, const double *w,
                      double *partials, double *dst, const int *gate);
+void launch_multidot(hipStream_t s, long nvec, int nv, const float *V, const float *w,
+                     double *partials, double *dst, const int *gate);
 void launch_update_norm(hipStream_t s, long nvec, int nv, const double *V, const double *coef,
                         double *w, double *partials, double *hnext, const int *gate,
+                        int *reorth, double *hacc);
+void launch_update_norm(hipStream_t s, long nvec, int nv, const float *V, const double *coef,
+                        float *w, double *partials, double *hnext, const int *gate,
                         int *reorth, double *hacc);
 void launch_residual(hipStream_t s, long nvec, const double *b, const double *Ax, double *r,
                      double *partials, double *out);
 void launch_scale_copy(hipStream_t s, long nvec, const double *x, double a, double *y);
 void launch_axpy_multi(hipStream_t s, long nvec, int k, const double *Z, const double *y,
                        double *x);
+void launch_axpy_multi(hipStream_t s, long nvec, int k, const float *Z, const double *y,
+                       double *x);
 
 // ---- CPR / pressure AMG kernels (fim_amg.hip) -----------------------------------
 constexpr int kCoarseMax = 64;       // cells of the level that is inverted densely
 void launch_amg_extract(hipStream_t s, int nb, const AmgLevel &L, Grid g, Wells w, Sys sys,
                         double *wq, double *ap);
+void launch_amg_extract(hipStream_t s, int nb, const AmgLevel &L, Grid g, Wells w, Sys sys,
+                        double *wq, float *ap);
 void launch_amg_coarsen(hipStream_t s, const AmgLevel &F, const AmgLevel &C, const int *cfs_ptr,
                         const int *cfs_idx);
 void launch_amg_coarsest_setup(hipStream_t s, const AmgLevel &L, double *M, double *Minv,
@@ -165,6 +178,12 @@ void launch_amg_restrict(hipStream_t s, const AmgLevel &F, const AmgLevel &C);
 void launch_amg_correct(hipStream_t s, const AmgLevel &F, const AmgLevel &C);
 void launch_cpr_restrict(hipStream_t s, int nb, int n, int nw, const AmgLevel &L,
                          const int *split0, const double *w, const double *hptr, double *v,
+                         const double *wq);
+void launch_cpr_restrict(hipStream_t s, int nb, int n, int nw, const AmgLevel &L,
+                         const int *split0, const double *w, const double *hptr, float *v,
+                         const double *wq);
+void launch_cpr_restrict(hipStream_t s, int nb, int n, int nw, const AmgLevel &L,
+                         const int *split0, const float *w, const double *hptr, float *v,
                          const double *wq);
 void launch_cpr_finish(hipStream_t s, int nb, int n, int nw, const AmgLevel &L,
                        const int *split0, const int *colsplit, Sys sys, const double *ap,
@@ -186,19 +205,27 @@ size_t ilu_solve_lds(int nb, const IluTiles &T);
 hipError_t ilu_allow_lds(int nb, size_t bytes);
 void launch_ilu_factor(hipStream_t s, int nb, Grid g, const IluTiles &T, Sys sys, double *lu,
                        int *bad);
+void launch_ilu_factor(hipStream_t s, int nb, Grid g, const IluTiles &T, Sys sys, float *lu,
+                       int *bad);
 // right-hand side of a solve: b, or (ap set) the residual b - A x1 of the CPR
-// first stage with x1 = px in level-0 AMG order, x1 added back to slot 0
+// first stage with x1 = px in level-0 AMG order, x1 added back to slot 0.
+// VT: element type of b (and of the result), LT: of ap (and of the factors).
+template <class VT, class LT>
 struct IluRhs {
-    const double *b;
-    const double *ap;           // [nnzb][nb] pressure column of A, or null
+    const VT *b;
+    const LT *ap;               // [nnzb][nb] pressure column of A, or null
     const int *colsplit;        // [nnzb] column -> level-0 entry
     const int *split0;          // [n] cell -> level-0 entry
     const double *px;           // level-0 iterate (cells, then wells)
     int nsplit;                 // 2*half of level 0 (first well entry)
 };
 void launch_ilu_solve(hipStream_t s, int nb, Grid g, const IluTiles &T, Sys sys,
-                      const double *lu, const IluRhs &R, double *x);
+                      const double *lu, const IluRhs<double, double> &R, double *x);
+void launch_ilu_solve(hipStream_t s, int nb, Grid g, const IluTiles &T, Sys sys,
+                      const float *lu, const IluRhs<float, float> &R, float *x);
 void launch_normalize(hipStream_t s, long nvec, const double *w, const double *hptr, double *v);
+void launch_normalize(hipStream_t s, long nvec, const double *w, const double *hptr, float *v);
+void launch_normalize(hipStream_t s, long nvec, const float *w, const double *hptr, float *v);
 
 // A cycle is a sequence of phases on levels: colour sweeps, well sweeps,
 // restrictions, corrections and the dense coarsest solve.  The

@@ -36,12 +36,17 @@ __device__ inline T ldm(const T *p) {
     else return *p;
 }
 
-template <int NB, int G, int V, bool NT, bool REMAP>
+typedef float f2 __attribute__((ext_vector_type(2)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// MT / VT: element types of the matrix values and of x, y (double, or float
+// for the inner solves of the mixed-precision mode); sums in double.
+template <int NB, int G, int V, bool NT, bool REMAP, class MT, class VT>
 __global__ __launch_bounds__(kBlock) void k_spmv(int nrows, const int *__restrict__ rowptr,
                                                  const int *__restrict__ colind,
-                                                 const double *__restrict__ val,
-                                                 const double *__restrict__ x,
-                                                 double *__restrict__ y) {
+                                                 const MT *__restrict__ val,
+                                                 const VT *__restrict__ x,
+                                                 VT *__restrict__ y) {
     const int lg = threadIdx.x & (G - 1);
     const long blk = REMAP ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
     const int row = (int)((blk * blockDim.x + threadIdx.x) / G);
@@ -59,13 +64,19 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int nrows, const int *__restric
                 const int q = q0 + u;
                 if (q < e) {
                     col[u] = ldm<NT>(colind + q);
-                    if constexpr (NB == 2) {
+                    if constexpr (NB == 2 && sizeof(MT) == 8) {
                         const d2 *blk2 = reinterpret_cast<const d2 *>(val + (size_t)q * 4);
                         const d2 r0 = ldm<NT>(blk2), r1 = ldm<NT>(blk2 + 1);
                         a[u][0] = r0.x;
                         a[u][1] = r0.y;
                         a[u][2] = r1.x;
                         a[u][3] = r1.y;
+                    } else if constexpr (NB == 2) {
+                        const f4 b4 = ldm<NT>(reinterpret_cast<const f4 *>(val + (size_t)q * 4));
+                        a[u][0] = b4.x;
+                        a[u][1] = b4.y;
+                        a[u][2] = b4.z;
+                        a[u][3] = b4.w;
                     } else {
 #pragma unroll
                         for (int t = 0; t < NB * NB; ++t) a[u][t] = ldm<NT>(val + (size_t)q * NB * NB + t);
@@ -76,8 +87,12 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int nrows, const int *__restric
             for (int u = 0; u < V; ++u) {
                 if (q0 + u < e) {
                     double xv[NB];
-                    if constexpr (NB == 2) {
+                    if constexpr (NB == 2 && sizeof(VT) == 8) {
                         const d2 v2 = *reinterpret_cast<const d2 *>(x + (size_t)col[u] * 2);
+                        xv[0] = v2.x;
+                        xv[1] = v2.y;
+                    } else if constexpr (NB == 2) {
+                        const f2 v2 = *reinterpret_cast<const f2 *>(x + (size_t)col[u] * 2);
                         xv[0] = v2.x;
                         xv[1] = v2.y;
                     } else {
@@ -100,30 +115,41 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int nrows, const int *__restric
 #pragma unroll
         for (int e = 0; e < NB; ++e) acc[e] += __shfl_xor(acc[e], off, 64);
     if (row < nrows && lg == 0) {
-        if constexpr (NB == 2) {
+        if constexpr (NB == 2 && sizeof(VT) == 8) {
             d2 o;
             o.x = acc[0];
             o.y = acc[1];
             *reinterpret_cast<d2 *>(y + (size_t)row * 2) = o;
         } else {
 #pragma unroll
-            for (int e = 0; e < NB; ++e) y[(size_t)row * NB + e] = acc[e];
+            for (int e = 0; e < NB; ++e) y[(size_t)row * NB + e] = (VT)acc[e];
         }
     }
 }
 
-void launch_spmv(hipStream_t s, int nb, int nrows, const int *rowptr, const int *colind,
-                 const double *val, const double *x, double *y) {
+template <class MT, class VT>
+static void spmv_impl(hipStream_t s, int nb, int nrows, const int *rowptr, const int *colind,
+                      const MT *val, const VT *x, VT *y) {
     constexpr int G = kSpmvG, V = kSpmvV;
     constexpr bool NT = kSpmvNT, RM = kSpmvRemap;
     const long threads = (long)nrows * G;
     dim3 grid((unsigned)((threads + kBlock - 1) / kBlock)), block(kBlock);
     if (nb == 2)
-        hipLaunchKernelGGL((k_spmv<2, G, V, NT, RM>), grid, block, 0, s, nrows, rowptr, colind, val,
-                           x, y);
+        hipLaunchKernelGGL((k_spmv<2, G, V, NT, RM, MT, VT>), grid, block, 0, s, nrows, rowptr,
+                           colind, val, x, y);
     else
-        hipLaunchKernelGGL((k_spmv<3, G, V, NT, RM>), grid, block, 0, s, nrows, rowptr, colind, val,
-                           x, y);
+        hipLaunchKernelGGL((k_spmv<3, G, V, NT, RM, MT, VT>), grid, block, 0, s, nrows, rowptr,
+                           colind, val, x, y);
+}
+
+void launch_spmv(hipStream_t s, int nb, int nrows, const int *rowptr, const int *colind,
+                 const double *val, const double *x, double *y) {
+    spmv_impl(s, nb, nrows, rowptr, colind, val, x, y);
+}
+
+void launch_spmv(hipStream_t s, int nb, int nrows, const int *rowptr, const int *colind,
+                 const float *val, const float *x, float *y) {
+    spmv_impl(s, nb, nrows, rowptr, colind, val, x, y);
 }
 
 // ---------------------------------------------------------------------------
@@ -274,9 +300,10 @@ void launch_normalize_precond(hipStream_t s, int nb, int nrows, const double *w,
 constexpr int kDotGroup = 8;
 constexpr int kDotCols = 2048;
 
+template <class T>
 __global__ __launch_bounds__(kBlock) void k_multidot_part(long nvec, int nv,
-                                                          const double *__restrict__ V,
-                                                          const double *__restrict__ w,
+                                                          const T *__restrict__ V,
+                                                          const T *__restrict__ w,
                                                           double *__restrict__ partials,
                                                           const int *gate) {
     if (gate && *gate == 0) return;
@@ -287,10 +314,11 @@ __global__ __launch_bounds__(kBlock) void k_multidot_part(long nvec, int nv,
     const bool self = blockIdx.y == 0;            // the first group also forms <w, w>
     for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < nvec;
          e += (long)gridDim.x * blockDim.x) {
-        const double we = w[e];
+        const double we = (double)w[e];
 #pragma unroll
         for (int i = 0; i < kDotGroup; ++i)
-            if (g0 + i < nv) acc[i] += __builtin_nontemporal_load(V + (size_t)(g0 + i) * nvec + e) * we;
+            if (g0 + i < nv)
+                acc[i] += (double)__builtin_nontemporal_load(V + (size_t)(g0 + i) * nvec + e) * we;
         if (self) acc[kDotGroup] += we * we;
     }
     __shared__ double sh[kDotGroup + 1][kWaves];
@@ -331,15 +359,26 @@ __global__ __launch_bounds__(kBlock) void k_multidot_sum(int ncols, const double
     }
 }
 
-void launch_multidot(hipStream_t s, long nvec, int nv, const double *V, const double *w,
-                     double *partials, double *dst, const int *gate) {
+template <class T>
+static void multidot_impl(hipStream_t s, long nvec, int nv, const T *V, const T *w,
+                          double *partials, double *dst, const int *gate) {
     long cols = (nvec + kBlock - 1) / kBlock;
     cols = cols < kDotCols ? (cols > 0 ? cols : 1) : kDotCols;
     const int groups = (nv + kDotGroup - 1) / kDotGroup > 0 ? (nv + kDotGroup - 1) / kDotGroup : 1;
-    hipLaunchKernelGGL(k_multidot_part, dim3((unsigned)cols, groups), dim3(kBlock), 0, s, nvec, nv,
-                       V, w, partials, gate);
+    hipLaunchKernelGGL(k_multidot_part<T>, dim3((unsigned)cols, groups), dim3(kBlock), 0, s, nvec,
+                       nv, V, w, partials, gate);
     hipLaunchKernelGGL(k_multidot_sum, dim3(nv + 1), dim3(kBlock), 0, s, (int)cols, partials, dst,
                        gate);
+}
+
+void launch_multidot(hipStream_t s, long nvec, int nv, const double *V, const double *w,
+                     double *partials, double *dst, const int *gate) {
+    multidot_impl(s, nvec, nv, V, w, partials, dst, gate);
+}
+
+void launch_multidot(hipStream_t s, long nvec, int nv, const float *V, const float *w,
+                     double *partials, double *dst, const int *gate) {
+    multidot_impl(s, nvec, nv, V, w, partials, dst, gate);
 }
 
 // w -= sum_{i<nv} coef[i] V_i and the partials of ||w||^2.  The finishing
@@ -348,9 +387,10 @@ void launch_multidot(hipStream_t s, long nvec, int nv, const double *V, const do
 // the norm dropped below a tenth of ||w_before|| = sqrt(coef[nv]) (a
 // DGKS-type test for severe cancellation).  Both are skipped when
 // *gate == 0.
+template <class T>
 __global__ __launch_bounds__(kBlock) void k_update_norm(long nvec, int nv,
-                                                        const double *__restrict__ V,
-                                                        const double *coef, double *w,
+                                                        const T *__restrict__ V,
+                                                        const double *coef, T *w,
                                                         double *partials, const int *gate) {
     if (gate && *gate == 0) return;
     __shared__ double c[kMaxDots];
@@ -360,11 +400,13 @@ __global__ __launch_bounds__(kBlock) void k_update_norm(long nvec, int nv,
     const bool mx[1] = {false};
     for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < nvec;
          e += (long)gridDim.x * blockDim.x) {
-        double a = w[e];
+        double a = (double)w[e];
 #pragma unroll 8
-        for (int i = 0; i < nv; ++i) a -= c[i] * __builtin_nontemporal_load(V + (size_t)i * nvec + e);
-        w[e] = a;
-        v[0] += a * a;
+        for (int i = 0; i < nv; ++i)
+            a -= c[i] * (double)__builtin_nontemporal_load(V + (size_t)i * nvec + e);
+        const T at = (T)a;                         // the norm of what is stored
+        w[e] = at;
+        v[0] += (double)at * (double)at;
     }
     block_partials<1>(v, mx, partials);
 }
@@ -385,14 +427,27 @@ __global__ __launch_bounds__(kBlock) void k_update_finish(int nparts, int nv, co
     }
 }
 
-void launch_update_norm(hipStream_t s, long nvec, int nv, const double *V, const double *coef,
-                        double *w, double *partials, double *hnext, const int *gate, int *reorth,
-                        double *hacc) {
+template <class T>
+static void update_norm_impl(hipStream_t s, long nvec, int nv, const T *V, const double *coef,
+                             T *w, double *partials, double *hnext, const int *gate, int *reorth,
+                             double *hacc) {
     const int nblk = vec_blocks(nvec);
-    hipLaunchKernelGGL(k_update_norm, dim3(nblk), dim3(kBlock), 0, s, nvec, nv, V, coef, w,
+    hipLaunchKernelGGL(k_update_norm<T>, dim3(nblk), dim3(kBlock), 0, s, nvec, nv, V, coef, w,
                        partials, gate);
     hipLaunchKernelGGL(k_update_finish, dim3(1), dim3(kBlock), 0, s, nblk, nv, coef, partials,
                        hnext, gate, reorth, hacc);
+}
+
+void launch_update_norm(hipStream_t s, long nvec, int nv, const double *V, const double *coef,
+                        double *w, double *partials, double *hnext, const int *gate, int *reorth,
+                        double *hacc) {
+    update_norm_impl(s, nvec, nv, V, coef, w, partials, hnext, gate, reorth, hacc);
+}
+
+void launch_update_norm(hipStream_t s, long nvec, int nv, const float *V, const double *coef,
+                        float *w, double *partials, double *hnext, const int *gate, int *reorth,
+                        double *hacc) {
+    update_norm_impl(s, nvec, nv, V, coef, w, partials, hnext, gate, reorth, hacc);
 }
 
 // r = b - Ax; out[0] = ||r||^2, out[1] = ||r||
@@ -419,8 +474,9 @@ void launch_residual(hipStream_t s, long nvec, const double *b, const double *Ax
 
 // x += sum_{i<k} y_i Z_i (the flexible-GMRES update with stored
 // preconditioned vectors)
+template <class T>
 __global__ __launch_bounds__(kBlock) void k_axpy_multi(long nvec, int k,
-                                                       const double *__restrict__ Z,
+                                                       const T *__restrict__ Z,
                                                        const double *__restrict__ y,
                                                        double *__restrict__ x) {
     __shared__ double ys[kMaxRestart + 1];
@@ -429,14 +485,45 @@ __global__ __launch_bounds__(kBlock) void k_axpy_multi(long nvec, int k,
     for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < nvec;
          e += (long)gridDim.x * blockDim.x) {
         double a = x[e];
-        for (int i = 0; i < k; ++i) a += ys[i] * Z[(size_t)i * nvec + e];
+        for (int i = 0; i < k; ++i) a += ys[i] * (double)Z[(size_t)i * nvec + e];
         x[e] = a;
     }
 }
 
 void launch_axpy_multi(hipStream_t s, long nvec, int k, const double *Z, const double *y,
                        double *x) {
-    hipLaunchKernelGGL(k_axpy_multi, dim3(vec_blocks(nvec)), dim3(kBlock), 0, s, nvec, k, Z, y, x);
+    hipLaunchKernelGGL(k_axpy_multi<double>, dim3(vec_blocks(nvec)), dim3(kBlock), 0, s, nvec, k,
+                       Z, y, x);
+}
+
+void launch_axpy_multi(hipStream_t s, long nvec, int k, const float *Z, const double *y,
+                       double *x) {
+    hipLaunchKernelGGL(k_axpy_multi<float>, dim3(vec_blocks(nvec)), dim3(kBlock), 0, s, nvec, k,
+                       Z, y, x);
+}
+
+// y = (float) x, element by element (single-precision copies for the inner
+// solves of the mixed-precision mode)
+__global__ __launch_bounds__(kBlock) void k_to_float(long n, const double *__restrict__ x,
+                                                     float *__restrict__ y) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long)gridDim.x * blockDim.x)
+        y[i] = (float)x[i];
+}
+
+void launch_to_float(hipStream_t s, long n, const double *x, float *y) {
+    hipLaunchKernelGGL(k_to_float, dim3(vec_blocks(n)), dim3(kBlock), 0, s, n, x, y);
+}
+
+__global__ __launch_bounds__(kBlock) void k_to_double(long n, const float *__restrict__ x,
+                                                      double *__restrict__ y) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long)gridDim.x * blockDim.x)
+        y[i] = (double)x[i];
+}
+
+void launch_to_double(hipStream_t s, long n, const float *x, double *y) {
+    hipLaunchKernelGGL(k_to_double, dim3(vec_blocks(n)), dim3(kBlock), 0, s, n, x, y);
 }
 
 __global__ __launch_bounds__(kBlock) void k_scale_copy(long nvec, const double *__restrict__ x,

@@ -81,6 +81,10 @@ def test_validation_rejects_bad_input_without_a_device():
     _expect_arg_error(r, "porosity")
     _expect_arg_error(base, "restart", restart=0)
     _expect_arg_error(base, "restart", restart=41)
+    _expect_arg_error(base, "mixed precision needs an ILU", precision=rv.MIXED,
+                      precond=rv.PREC_CPR)
+    _expect_arg_error(base, "unknown precision", precision=7)
+    _expect_arg_error(base, "tile sizes", tile=(4, -1, 2))
     r = base.copy()
     r.wells.append(rv.Well(rv.INJ_GAS, rv.RATE, 10.0, np.array([5], np.int32)))
     _expect_arg_error(r, "gas injection needs model 3")

@@ -351,6 +351,54 @@ def test_fused_amg_cycle_in_full_steps():
         assert np.array_equal(states[0][k], states[1][k]), k
 
 
+# ---------------------------------------------------------------------------
+# mixed precision: single-precision inner cycles, FP64 refinement
+
+@pytest.mark.parametrize("cfg,precond", [(c, p) for c in ("c1", "c2s", "odd")
+                                         for p in (rv.PREC_ILU0, rv.PREC_CPR_ILU0)])
+def test_mixed_precision_linear_solve_reaches_fp64_accuracy(cfg, precond):
+    res = {"c1": rv.config_c1, "c2s": lambda: rv.config_c2_small(7, 9, 3),
+           "odd": lambda: rv.config_c2_small(13, 17, 5)}[cfg]()
+    g, o = pair(res)
+    g.fim_set_options(rv.Options(lin_rtol=1e-12, max_lin=3000, restart=40, precond=precond,
+                                 precision=rv.MIXED, tile=(4, 4, 2)))
+    R, rowptr, colind, val = g.fim_assemble(10.0)
+    A = fr.bsr_to_dense(rowptr, colind, val, g.nb)
+    xd = np.linalg.solve(A, R)
+    x, rc, it, rr = g.fim_linear_solve(R)
+    assert rc == fim.FIM_OK and rr <= 1e-12, (rc, it, rr)
+    assert np.linalg.norm(A @ x - R) <= 1e-11 * np.linalg.norm(R)
+    assert np.abs(x - xd).max() <= 1e-8 * np.abs(xd).max()
+
+
+def test_mixed_precision_preconditioner_is_the_ilu0_in_single_precision():
+    res = rv.config_c2_small(13, 17, 5)
+    g = fim.Fim(res, options=rv.Options(precond=rv.PREC_ILU0, tile=(4, 5, 2),
+                                        precision=rv.MIXED))
+    g.set_initial_state()
+    R, rowptr, colind, val = g.fim_assemble(10.0)
+    tiles = fr.ilu_tiles(res.nx, res.ny, res.nz, (4, 5, 2), [w.cells for w in res.wells])
+    lu = fr.bilu0_tiled(rowptr, colind, val, g.nb, tiles)
+    x = np.random.default_rng(83).normal(size=len(R))
+    y = g.fim_precond_apply(x)
+    yo = fr.bilu0_solve(rowptr, colind, lu, x, g.nb)
+    err = np.abs(y - yo).max() / np.abs(yo).max()
+    assert 1e-12 < err <= 1e-4, err          # single-precision factors, not FP64 ones
+
+
+@pytest.mark.parametrize("cfg", ["c1", "c2s"])
+def test_mixed_precision_steps_match_oracle(cfg):
+    if cfg == "c1":
+        res, nsteps, tile = rv.config_c1(), 10, (5, 5, 3)
+    else:
+        res, nsteps, tile = rv.config_c2_small(13, 17, 5, nsteps=3), 3, (5, 6, 3)
+    g, o, errs = run_parity_steps(res, nsteps, options=rv.Options(
+        precond=rv.PREC_CPR_ILU0, precision=rv.MIXED, tile=tile))
+    worst = {k: max(e[k] for e in errs) for k in errs[0]}
+    print("mixed-precision parity per quantity:", worst)
+    assert all(v <= STATE_TOL for v in worst.values()), worst
+
+
 def test_linear_solve_zero_rhs():
     g, o = pair(rv.config_c2_small(5, 5, 2))
     R, *_ = g.fim_assemble(10.0)
