@@ -7,8 +7,9 @@ then block-Jacobi ILU(0) over 8x8x8 boxes), Newton updates and cuts, all in
 the HIP library.  Inputs are seeded synthetic data resident in HBM before timing.
 
 Prints one JSON line with the throughput, the roofline of the dominant
-kernel (BSR SpMV, timed with HIP events on the library's stream inside the
-timed steps) and the FP64 oracle's throughput on the host as a baseline.
+kernel (BSR SpMV inside the timed steps, each launch stamping its own start
+and end into a pair of HIP events on the library's stream) and the FP64
+oracle's throughput on the host as a baseline.
 """
 import argparse
 import json
@@ -108,6 +109,65 @@ def spmv_only(reps):
                       "copy_bytes_written": copy_bytes, "reps": reps}), flush=True)
 
 
+def summarize_pmc(fetch_csv, write_csv, spmv_log, out, commands):
+    """HBM bytes per SpMV launch from two rocprofv3 --pmc runs of --spmv-only
+    (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch). Each counter is scaled by
+    what it reads for the 160 MiB device copy of the same run. SPMV_LOG is the
+    output of a --spmv-only run without the profiler (algorithmic bytes and
+    the launch time with a 160 MiB copy between launches)."""
+    import csv
+    import collections
+
+    def per_kernel(path, counter):
+        acc = collections.defaultdict(list)
+        for r in csv.DictReader(open(path)):
+            if r.get("Counter_Name") == counter:
+                acc[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+        return {k: sum(v) / len(v) for k, v in acc.items()}, {k: max(v) for k, v in acc.items()}
+
+    f, fmax = per_kernel(fetch_csv, "FETCH_SIZE")
+    w, wmax = per_kernel(write_csv, "WRITE_SIZE")
+    spmv = [k for k in f if "k_spmv" in k][0]
+    copy = [k for k in f if "copy" in k.lower() and "spmv" not in k][0]
+    line = [l for l in open(spmv_log) if l.startswith("{")][-1]
+    info = json.loads(line)
+    kib160 = 160 * 1024.0
+    rf, wf = kib160 / fmax[copy], kib160 / wmax[copy]
+    total = (f[spmv] * rf + w[spmv] * wf) * 1024
+    d = {"kernel": spmv.split("(")[0].replace("void ", "")
+         + " (BSR SpMV of the 1.1M-cell Jacobian, launched back to back)",
+         "fetch_kib_per_dispatch": f[spmv], "write_kib_per_dispatch": w[spmv],
+         "calibration": {"copy_kernel": copy.split("(")[0], "copy_fetch_kib_for_160MiB": fmax[copy],
+                         "read_factor": rf, "copy_write_kib_for_160MiB": wmax[copy],
+                         "write_factor": wf},
+         "bytes_per_launch": total, "algorithmic_bytes_per_launch": info["spmv_bytes"],
+         "traffic_over_algorithmic": total / info["spmv_bytes"],
+         "spmv_avg_us_plain_run": info["spmv_avg_us"],
+         "commands": commands}
+    json.dump(d, open(out, "w"), indent=1)
+    print(json.dumps(d, indent=1))
+
+
+def summarize_stats(stats_csv, out, title, command, note):
+    """Markdown table of a rocprofv3 --kernel-trace --stats kernel summary."""
+    import csv
+
+    rows = list(csv.DictReader(open(stats_csv)))
+    tot = sum(float(r["TotalDurationNs"]) for r in rows)
+    lines = [f"# {title}", "", "Command (from the repository root):", "", "```", command, "```",
+             "", note, "", "| kernel | calls | avg us | total ms | share |",
+             "|---|---:|---:|---:|---:|"]
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"]))[:30]:
+        name = r["Name"].split("(")[0].replace("void ", "")
+        lines.append(f"| `{name}` | {int(r['Calls'])} | {float(r['AverageNs']) / 1e3:.2f} | "
+                     f"{float(r['TotalDurationNs']) / 1e6:.2f} | "
+                     f"{100 * float(r['TotalDurationNs']) / tot:.1f}% |")
+    lines += ["", f"Total kernel time {tot / 1e6:.1f} ms over "
+                  f"{sum(int(r['Calls']) for r in rows)} launches."]
+    open(out, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -125,7 +185,21 @@ def main():
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "spmv_c2_traffic.json"))
     ap.add_argument("--spmv-only", type=int, default=0, metavar="REPS",
                     help="time only the SpMV of the 1.1M-cell Jacobian (profiler counter runs)")
+    ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "SPMV_LOG", "OUT"),
+                    help="write the SpMV traffic JSON from two --pmc runs of --spmv-only")
+    ap.add_argument("--stats-summary", nargs=2, metavar=("STATS_CSV", "OUT"),
+                    help="write a markdown table of a rocprofv3 kernel_stats.csv")
+    ap.add_argument("--title", default="")
+    ap.add_argument("--command", action="append", default=[],
+                    help="command recorded in a summary (repeatable)")
+    ap.add_argument("--note", default="")
     args = ap.parse_args()
+    if args.pmc_summary:
+        summarize_pmc(*args.pmc_summary, args.command)
+        return
+    if args.stats_summary:
+        summarize_stats(*args.stats_summary, args.title, "\n".join(args.command), args.note)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the FIM path has no multi-GPU "
               "implementation (no halo exchange or distributed reductions)", file=sys.stderr)

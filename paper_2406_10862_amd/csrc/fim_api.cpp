@@ -1042,7 +1042,8 @@ static void precondition(fim_ctx *c, const WT *w, const double *hptr, T *v, T *z
     }
 }
 
-// SpMV inside the solver (y = J x in T), optionally bracketed by events
+// SpMV inside the solver (y = J x in T); when profiling, the launch stamps
+// the kernel's start and end into a pair of events
 template <class T>
 static void solver_spmv(fim_ctx *c, const T *xin, T *yout, bool profile) {
     if (profile) {
@@ -1056,9 +1057,9 @@ static void solver_spmv(fim_ctx *c, const T *xin, T *yout, bool profile) {
             }
             c->spmv_used = 0;
         }
-        HIPCHECK(hipEventRecord(c->spmv_ev[c->spmv_used], c->s));
-        launch_spmv(c->s, c->nb, c->nrows, c->rowptr, c->colind, Kry<T>::val(c), xin, yout);
-        HIPCHECK(hipEventRecord(c->spmv_ev[c->spmv_used + 1], c->s));
+        launch_spmv(c->s, c->nb, c->nrows, c->rowptr, c->colind, Kry<T>::val(c), xin, yout,
+                    c->spmv_ev[c->spmv_used], c->spmv_ev[c->spmv_used + 1]);
+        HIPCHECK(hipGetLastError());
         c->spmv_used += 2;
         c->spmv_calls += 1;
     } else {

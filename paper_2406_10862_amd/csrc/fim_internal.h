@@ -128,9 +128,11 @@ int update_blocks(int n);
 
 // ---- linear algebra kernels (fim_linalg.hip) --------------------------------
 void launch_spmv(hipStream_t s, int nb, int nrows, const int *rowptr, const int *colind,
-                 const double *val, const double *x, double *y);
+                 const double *val, const double *x, double *y, hipEvent_t e0 = nullptr,
+                 hipEvent_t e1 = nullptr);
 void launch_spmv(hipStream_t s, int nb, int nrows, const int *rowptr, const int *colind,
-                 const float *val, const float *x, float *y);
+                 const float *val, const float *x, float *y, hipEvent_t e0 = nullptr,
+                 hipEvent_t e1 = nullptr);
 void launch_to_float(hipStream_t s, long n, const double *x, float *y);
 void launch_to_double(hipStream_t s, long n, const float *x, double *y);
 void launch_bj_setup(hipStream_t s, int nb, int nrows, const int *diagpos, const double *val,

@@ -187,6 +187,36 @@ def test_spmv_matches_oracle_random_patterns(nb, nrows):
     assert np.all(np.abs(y - yo) <= 1e-14 * scale + 1e-300)
 
 
+@pytest.mark.parametrize("nb", [2, 3])
+def test_spmv_without_blocks_writes_zeros(nb):
+    nrows = 300
+    rowptr = np.zeros(nrows + 1, np.int32)
+    y = _gpu_spmv(rowptr, np.zeros(0, np.int32), np.zeros(0), np.ones(nrows * nb), nb)
+    assert np.array_equal(y, np.zeros(nrows * nb))
+
+
+@pytest.mark.parametrize("nb", [2, 3])
+@pytest.mark.parametrize("nrows", [129, 517])
+def test_spmv_lanes_past_a_row_end_contribute_nothing(nb, nrows):
+    """Leading empty rows, rows of every length around the lane-group width
+    and a ragged last workgroup; x[0] is NaN and no block uses column 0, so
+    a value read by a lane with no block of its own would show up."""
+    rng = np.random.default_rng(nrows + nb)
+    lens = np.concatenate([np.zeros(70, int), np.arange(nrows - 70) % 19])
+    rowptr = np.zeros(nrows + 1, np.int32)
+    rowptr[1:] = np.cumsum(lens)
+    colind = np.concatenate([np.sort(rng.choice(np.arange(1, nrows), size=L, replace=False))
+                             for L in lens]).astype(np.int32)
+    val = rng.normal(size=len(colind) * nb * nb)
+    x = rng.normal(size=nrows * nb)
+    x[:nb] = np.nan
+    y = _gpu_spmv(rowptr, colind, val, x, nb)
+    yo = fr.bsr_spmv(rowptr, colind, val, x, nb)
+    scale = fr.bsr_spmv(rowptr, colind, np.abs(val), np.abs(x), nb)
+    assert np.all(np.isfinite(y))
+    assert np.all(np.abs(y - yo) <= 1e-14 * scale + 1e-300)
+
+
 def test_spmv_on_the_fim_jacobian():
     res = rv.config_c2_small(13, 17, 5)
     rng = np.random.default_rng(41)
