@@ -429,6 +429,50 @@ def test_mixed_precision_steps_match_oracle(cfg):
     assert all(v <= STATE_TOL for v in worst.values()), worst
 
 
+# three-phase black oil on the 200x200x50 layout (gas injector at the
+# centre, four corner producers), FP64 and mixed precision
+
+@pytest.mark.parametrize("precision", [rv.FP64, rv.MIXED])
+def test_c3_shaped_steps_match_oracle(precision):
+    res = rv.config_c3(24, 20, 6)
+    g, o, errs = run_parity_steps(res, 3, options=rv.Options(
+        precond=rv.PREC_CPR_ILU0, precision=precision, tile=(6, 5, 3)))
+    worst = {k: max(e[k] for e in errs) for k in errs[0]}
+    print("c3-shaped parity per quantity:", worst)
+    assert all(v <= STATE_TOL for v in worst.values()), worst
+
+
+@pytest.mark.parametrize("precision", [rv.FP64, rv.MIXED])
+def test_c3_full_size_step_solves_the_oracle_equations(precision):
+    """2,000,000 cells: the oracle's Newton run is out of reach here, but
+    its discrete system evaluated at the GPU's end state must satisfy the
+    convergence tests the step claims (CNV, MB per component, well
+    equations).  The step is one day long: the 30-day schedule entry
+    needs cuts (the injector puts about 2.7 pore volumes a day into its
+    cells), which this check of a single backward-Euler system avoids."""
+    res = rv.config_c3()
+    opt = rv.Options(precond=rv.PREC_CPR_ILU0, precision=precision)
+    g = fim.Fim(res, options=opt)
+    o = fr.OracleModel(res)
+    g.fim_set_state(o.P, o.Sw, o.X, o.flag, o.pbhp)
+    dt = 1.0
+    A0 = o.accum()
+    rc, rep = g.fim_step(dt)
+    print(f"c3 step: rc={rc} newton={rep.newton_iters} linear={rep.linear_iters} "
+          f"cuts={rep.cuts}")
+    assert rc == fim.FIM_OK and rep.cuts == 0
+    st = g.fim_get_state()
+    end = dict(P=st["P"], Sw=st["Sw"], X=st["X"], flag=st["flag"], pbhp=st["pbhp"])
+    R, _ = o.assemble(dt, A0, jacobian=False, **end)
+    cnv, mb = o.conv(R, dt, **end)
+    print("oracle CNV", cnv, "MB", mb)
+    assert cnv.max() <= opt.tol_cnv and mb.max() <= opt.tol_mb
+    Rw = np.asarray(R).reshape(-1, 3)[g.n:, 0]
+    scale = np.array([abs(w.target) for w in res.wells])
+    assert np.all(np.abs(Rw) <= opt.tol_well * scale), Rw
+    assert (st["flag"] == rv.SAT).any()
+
+
 def test_linear_solve_zero_rhs():
     g, o = pair(rv.config_c2_small(5, 5, 2))
     R, *_ = g.fim_assemble(10.0)
