@@ -177,16 +177,102 @@ def summarize_stats(stats_csv, out, title, command, note):
     print("\n".join(lines))
 
 
+def ensemble_bench(args):
+    """Ensemble cell-steps/s: the 256 realisations of the c4 recipe advanced
+    together by fim_ensemble_run, every realisation on its own stream."""
+    import numpy as np
+    import torch
+
+    from paper_2406_10862_amd import fim, reservoirs as rv
+
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    dims = rv.config_c4_members(args.members)
+    res = [rv.config_c4_member(r, d) for r, d in enumerate(dims)]
+    opts = tolerances(args.tol)
+    members = [fim.Fim(r, options=opts, profile=True) for r in res]
+    for m in members:
+        m.set_initial_state()
+    cells = np.array([m.n for m in members], dtype=np.int64)
+    torch.cuda.synchronize()
+    log(f"setup {time.perf_counter() - t0:.1f}s: {len(members)} members, {cells.sum()} cells")
+    nsteps = args.steps if args.steps is not None else len(res[0].schedule)
+    sched = np.array([[r.schedule[s % len(r.schedule)] for s in range(max(nsteps, args.warmup))]
+                      for r in res])
+    if args.warmup:
+        rc, status, _ = fim.fim_ensemble_run(members, sched[:, :args.warmup], args.workers)
+        log(f"warm-up: rc={rc}")
+        for m in members:
+            m.set_initial_state()
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    rc, status, reps = fim.fim_ensemble_run(members, sched[:, :nsteps], args.workers)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    done = (status == fim.FIM_OK).sum(axis=1)
+    newton = sum(r.newton_iters for row in reps for r in row)
+    linear = sum(r.linear_iters for row in reps for r in row)
+    cuts = sum(r.cuts for row in reps for r in row)
+    spmv_bytes_total = sum(spmv_bytes(m.nnzb, m.nrows, m.nb) * sum(r.spmv_calls for r in reps[k])
+                           for k, m in enumerate(members))
+    spmv_s = sum(r.spmv_ms for row in reps for r in row) * 1e-3
+    calls = sum(r.spmv_calls for row in reps for r in row)
+    achieved = spmv_bytes_total / spmv_s / 1e9 if spmv_s > 0 else None
+    log(f"ensemble: rc={rc} member-steps ok {int(done.sum())}/{len(members) * nsteps} "
+        f"newton={newton} linear={linear} cuts={cuts} wall={wall:.2f}s")
+    out = {
+        "metric": "ensemble cell-steps/s, 256 realisations (nx, ny ~ U{20..64}, nz ~ U{5..16})",
+        "value": float((cells * done).sum() / wall),
+        "unit": "cell-steps/s",
+        "n_gpus": 1,
+        "steps": nsteps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / nsteps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"ensemble of {len(members)} two-phase dead-oil realisations, "
+                        f"{int(cells.sum())} cells in all, seeded log-normal perm (sigma 1), "
+                        "rate injector and BHP producer at opposite corners, dt 15 days",
+            "members": len(members), "cells": int(cells.sum()), "workers": args.workers,
+            "tolerances": args.tol, "newton_iters": newton, "linear_iters": linear,
+            "cuts": cuts, "member_steps_ok": int(done.sum()),
+            "newton_iters_per_s": newton / wall,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_spmv<2,8> (BSR SpMV inside GMRES, all members)",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS if achieved else None,
+            "traffic": None,
+            "launches": calls,
+            "avg_launch_us": spmv_s * 1e6 / calls if calls else None,
+        },
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20,
-                    help="timed steps of the schedule, from the initial state (20 = all of it)")
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps of the schedule from the initial state (default: all of "
+                         "it, 20 at c2, 10 at c3, 30 at c4)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--tol", choices=["parity", "paper"], default="parity")
-    ap.add_argument("--config", choices=["c2", "c3"], default="c2",
+    ap.add_argument("--config", choices=["c2", "c3", "c4"], default="c2",
                     help="c2: the 1.1M-cell dead-oil five-spot (the headline); c3: the "
-                         "2M-cell three-phase black-oil case (10 steps of 30 days)")
+                         "2M-cell three-phase black-oil case (10 steps of 30 days); c4: the "
+                         "ensemble of 256 small realisations (30 steps of 15 days)")
+    ap.add_argument("--members", type=int, default=256, help="c4: realisations")
+    ap.add_argument("--workers", type=int, default=16,
+                    help="c4: realisations in flight at a time (host threads and streams)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cycle", type=int, default=0,
                     help="AMG cycle: 0 V at the finest level and W below, 1 V, 2 W, >=16 W on "
@@ -221,6 +307,10 @@ def main():
         spmv_only(args.spmv_only)
         return
 
+    if args.config == "c4":
+        ensemble_bench(args)
+        return
+
     import torch
 
     from paper_2406_10862_amd import fim, reservoirs as rv
@@ -231,6 +321,8 @@ def main():
     res = rv.config_c2() if args.config == "c2" else rv.config_c3()
     if args.config == "c3":
         args.no_cpu = True
+    if args.steps is None:
+        args.steps = len(res.schedule)
     opts = tolerances(args.tol)
     opts.amg_cycle = args.cycle
     opts.precond = {"bj": rv.PREC_BJ, "ilu0": rv.PREC_ILU0, "cpr": rv.PREC_CPR,

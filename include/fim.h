@@ -55,6 +55,7 @@ extern "C" {
 enum {
     FIM_OK = 0,
     FIM_NOT_CONVERGED = 1,
+    FIM_SKIPPED = 2,          /* ensemble step not run (its member stopped earlier) */
     FIM_E_ARG = -1,
     FIM_E_NOMEM = -2,
     FIM_E_HIP = -3,
@@ -151,8 +152,9 @@ typedef struct {
  * the first level with at most amg_fused cells and wells down, runs as a
  * single-workgroup launch (0 = default 4096, negative = every phase
  * launched separately; the result is the same bit for bit).  profile != 0
- * brackets every SpMV launch of fim_step with HIP events and reports their
- * summed duration in fim_step_report.  precision FIM_MIXED (with an ILU(0)
+ * has every Krylov SpMV launch of fim_step stamp its own start and end into
+ * a pair of HIP events and reports the summed kernel time in
+ * fim_step_report.  precision FIM_MIXED (with an ILU(0)
  * preconditioner) runs every GMRES restart cycle in single precision: a
  * float copy of the Jacobian, float Krylov vectors, ILU(0) factors and
  * pressure column (sums in double), stopping after a 1e-5 reduction; each
@@ -208,6 +210,27 @@ int fim_get_state(fim_ctx *ctx, double *p, double *sw, double *x3, int8_t *flag,
  * backward-Euler system, halving the step on failure.  Advances the state
  * in place; fills rep (may be NULL).  Returns FIM_OK or FIM_NOT_CONVERGED. */
 int fim_step(fim_ctx *ctx, double dt_days, fim_step_report *rep);
+
+/* An ensemble of independent reservoirs (for instance realisations of one
+ * field): advances members[0..count) by nsteps time steps each.  Step s of
+ * member k is exactly fim_step(members[k], dt[k*nsteps + s],
+ * &reports[k*nsteps + s]) (the time step of Sec. 3.3.2), so every member
+ * computes bitwise what it computes when stepped alone.  Running many
+ * members at once is this library's addition, not a method of the paper:
+ * up to `workers` members are in flight together (workers <= 0: 16), each
+ * driven by its own host thread on its own stream, taken in order of
+ * decreasing cell count.
+ *   members: distinct contexts (a context is never stepped by two threads);
+ *   dt[count*nsteps] (days), status[count*nsteps] (required),
+ *   reports[count*nsteps] (may be NULL).
+ * A member stops at its first step that does not return FIM_OK; its later
+ * entries get FIM_SKIPPED.  Returns FIM_OK when every step returned FIM_OK,
+ * FIM_NOT_CONVERGED when a member stopped on that status, or a negative
+ * code some member's step returned (fim_last_error() on the calling
+ * thread gives that step's message).  The calling thread waits for every
+ * member. */
+int fim_ensemble_run(int32_t count, fim_ctx *const *members, int32_t nsteps, const double *dt,
+                     int32_t workers, fim_step_report *reports, int32_t *status);
 
 /* Surface rates q[w*3 + i] (component i = water, oil, gas; production
  * positive, injection negative) and bottom-hole pressures at the state. */

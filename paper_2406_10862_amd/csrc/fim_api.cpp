@@ -5,16 +5,20 @@
 // few scalars per iteration and solves the small Hessenberg least-squares
 // problem of GMRES; every vector and matrix operation is a HIP kernel.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <string>
 #include <stdexcept>
+#include <system_error>
+#include <thread>
 #include <type_traits>
 #include <vector>
 
@@ -847,7 +851,9 @@ static void build_subcycle(fim_ctx *c) {
     HIPCHECK(hipMemcpyAsync(c->sub_ops, ops.data(), ops.size() * sizeof(int),
                             hipMemcpyHostToDevice, c->s));
     c->sync();
-    HIPCHECK(amg_subcycle_allow_lds(amg_subcycle_lds(sub)));
+    // the device's limit rather than this context's need: every context sets
+    // the same value, so none lowers the limit another one launches under
+    HIPCHECK(amg_subcycle_allow_lds((size_t)lds_max));
     sub.ops = c->sub_ops;
     sub.Minv = c->Minv;
     c->sub = sub;
@@ -919,7 +925,7 @@ static void build_ilu(fim_ctx *c) {
     T.single = c->upload(single.data(), std::max<size_t>(single.size(), 1));
     T.nsingle = (int)single.size();
     c->sync();                                  // the host vectors above are temporaries
-    HIPCHECK(ilu_allow_lds(c->nb, ilu_solve_lds(c->nb, T)));
+    HIPCHECK(ilu_allow_lds(c->nb, (size_t)lds_max));   // the device's limit, as above
     if (!c->lu) {
         c->lu = c->alloc<double>((size_t)c->nnzb * c->nb * c->nb);
         c->ilu_bad = c->alloc<int>(1);
@@ -1556,6 +1562,72 @@ int fim_step(fim_ctx *c, double dt_days, fim_step_report *rep) {
     return guarded([&] {
         REQUIRE(c, "context is NULL");
         return step_impl(c, dt_days, rep);
+    });
+}
+
+int fim_ensemble_run(int32_t count, fim_ctx *const *members, int32_t nsteps, const double *dt,
+                     int32_t workers, fim_step_report *reports, int32_t *status) {
+    return guarded([&]() -> int {
+        REQUIRE(count >= 0 && nsteps >= 0, "count and nsteps must be >= 0");
+        if (count == 0 || nsteps == 0) return FIM_OK;
+        REQUIRE(members && dt && status, "members, dt and status are required");
+        std::vector<fim_ctx *> seen(members, members + count);
+        for (int k = 0; k < count; ++k) REQUIRE(members[k], "member %d is NULL", k);
+        std::sort(seen.begin(), seen.end());
+        REQUIRE(std::adjacent_find(seen.begin(), seen.end()) == seen.end(),
+                "a context appears twice among the members");
+        // longest first: the run ends with the small members
+        std::vector<int> order(count);
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int a, int b) { return members[a]->n > members[b]->n; });
+        const int nthreads = std::min<int>(count, workers > 0 ? workers : 16);
+        std::atomic<int> next{0};
+        std::mutex mu;
+        int first_err = 0;
+        bool stopped = false;
+        std::string first_msg;
+        auto work = [&] {
+            for (;;) {
+                const int i = next.fetch_add(1);
+                if (i >= count) return;
+                const int k = order[i];
+                fim_ctx *c = members[k];
+                int rc = hipSetDevice(c->dev) == hipSuccess ? FIM_OK : FIM_E_HIP;
+                if (rc != FIM_OK) set_err("hipSetDevice(%d) failed for member %d", c->dev, k);
+                for (int st = 0; st < nsteps; ++st) {
+                    const size_t e = (size_t)k * nsteps + st;
+                    if (rc != FIM_OK) {
+                        status[e] = FIM_SKIPPED;
+                        if (reports) reports[e] = fim_step_report{};
+                        continue;
+                    }
+                    rc = fim_step(c, dt[e], reports ? reports + e : nullptr);
+                    status[e] = rc;
+                }
+                if (rc != FIM_OK) {
+                    std::lock_guard<std::mutex> lk(mu);
+                    stopped = true;
+                    if (rc < 0 && first_err == 0) {
+                        first_err = rc;
+                        first_msg = g_err;          // this thread's message
+                    }
+                }
+            }
+        };
+        std::vector<std::thread> pool;
+        try {
+            for (int t = 1; t < nthreads; ++t) pool.emplace_back(work);
+        } catch (const std::system_error &) {
+            // fewer threads than asked for: the ones running share the work
+        }
+        work();                                     // the calling thread takes part
+        for (auto &t : pool) t.join();
+        if (first_err) {
+            g_err = first_msg;
+            return first_err;
+        }
+        return stopped ? FIM_NOT_CONVERGED : FIM_OK;
     });
 }
 

@@ -17,7 +17,7 @@ from . import reservoirs as rv
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfim.so")
 
-FIM_OK, FIM_NOT_CONVERGED = 0, 1
+FIM_OK, FIM_NOT_CONVERGED, FIM_SKIPPED = 0, 1, 2
 FIM_E_ARG, FIM_E_NOMEM, FIM_E_HIP, FIM_E_STATE = -1, -2, -3, -4
 FIM_MAX_SUB = 256
 
@@ -79,7 +79,8 @@ class FimStepReport(C.Structure):
 EXPORTS = ["fim_create", "fim_destroy", "fim_last_error", "fim_sizes", "fim_set_options",
            "fim_set_state", "fim_set_state_dev", "fim_get_state", "fim_step",
            "fim_get_well_rates", "fim_static", "fim_set_iterate", "fim_props",
-           "fim_assemble", "fim_precond_apply", "fim_linear_solve", "fim_bsr_spmv"]
+           "fim_assemble", "fim_precond_apply", "fim_linear_solve", "fim_bsr_spmv",
+           "fim_ensemble_run"]
 
 _LIB = None
 
@@ -125,6 +126,8 @@ def lib():
     L.fim_precond_apply.argtypes = [vp, f64p, f64p]
     L.fim_linear_solve.argtypes = [vp, f64p, f64p, i32p, f64p]
     L.fim_bsr_spmv.argtypes = [C.c_int32, C.c_int32, vp, vp, vp, vp, vp, vp]
+    L.fim_ensemble_run.argtypes = [C.c_int32, C.POINTER(vp), C.c_int32, f64p, C.c_int32,
+                                   C.POINTER(FimStepReport), i32p]
     for f in EXPORTS:
         if f not in ("fim_destroy", "fim_last_error"):
             getattr(L, f).restype = C.c_int32
@@ -329,3 +332,18 @@ def fim_bsr_spmv(nrows, nb, rowptr, colind, val, x, y, stream=None):
     ptr = lambda t: C.c_void_p(t.data_ptr())
     _check(lib().fim_bsr_spmv(int(nrows), int(nb), ptr(rowptr), ptr(colind), ptr(val), ptr(x),
                               ptr(y), s), "fim_bsr_spmv")
+
+
+def fim_ensemble_run(members, dt, workers=0):
+    """Advance the contexts `members` (Fim objects) by dt.shape[1] steps each,
+    up to `workers` at a time (fim_ensemble_run); dt[k, s] is step s of
+    member k.  Returns (rc, status[count, nsteps], reports[count][nsteps])."""
+    count = len(members)
+    dt = np.ascontiguousarray(np.broadcast_to(np.asarray(dt, np.float64), (count, np.shape(dt)[-1])))
+    nsteps = dt.shape[1]
+    handles = (C.c_void_p * max(count, 1))(*[m.h for m in members])
+    status = np.zeros((count, nsteps), np.int32)
+    reps = (FimStepReport * max(count * nsteps, 1))()
+    rc = _check(lib().fim_ensemble_run(count, handles, nsteps, _p(dt, f64p), int(workers),
+                                       reps, _p(status, i32p)), "fim_ensemble_run")
+    return rc, status, [[reps[k * nsteps + s] for s in range(nsteps)] for k in range(count)]

@@ -633,3 +633,64 @@ def test_forcing_term_reaches_the_same_root():
         outs.append(g.fim_get_state())
     e = state_errors(outs[1], outs[0], res.fluid, 2)
     assert all(v <= STATE_TOL for v in e.values()), e
+
+
+# ---------------------------------------------------------------------------
+# ensembles of independent realisations (fim_ensemble_run)
+
+ENSEMBLE_DIMS = [(12, 10, 3), (9, 14, 4), (16, 8, 2), (7, 7, 5), (20, 11, 3), (6, 13, 2)]
+
+
+def _ensemble_members(options=None):
+    res = [rv.config_c4_member(r, d) for r, d in enumerate(ENSEMBLE_DIMS)]
+    members = [fim.Fim(r, options=options) for r in res]
+    for m in members:
+        m.set_initial_state()
+    return res, members
+
+
+def test_ensemble_members_equal_their_runs_alone():
+    nsteps = 3
+    res, members = _ensemble_members()
+    dt = np.array([r.schedule[:nsteps] for r in res])
+    rc, status, reps = fim.fim_ensemble_run(members, dt, workers=4)
+    assert rc == fim.FIM_OK and np.all(status == fim.FIM_OK)
+    for k, r in enumerate(res):
+        alone = fim.Fim(r)
+        alone.set_initial_state()
+        for s in range(nsteps):
+            rc1, rep1 = alone.fim_step(dt[k, s])
+            assert rc1 == fim.FIM_OK
+            assert (rep1.newton_iters, rep1.linear_iters, rep1.cuts) == \
+                (reps[k][s].newton_iters, reps[k][s].linear_iters, reps[k][s].cuts)
+        a, b = alone.fim_get_state(), members[k].fim_get_state()
+        for q in a:
+            assert np.array_equal(a[q], b[q]), (k, q)
+
+
+def test_ensemble_member_matches_oracle():
+    res = rv.config_c4_member(3, (11, 9, 4))
+    g, o, errs = run_parity_steps(res, 3)
+    worst = {k: max(e[k] for e in errs) for k in errs[0]}
+    assert all(v <= STATE_TOL for v in worst.values()), worst
+
+
+def test_ensemble_stops_a_failing_member_and_finishes_the_others():
+    res, members = _ensemble_members()
+    # one Newton iteration and no cuts: the first step of that member fails
+    members[2].fim_set_options(rv.Options(max_newton=1, max_cuts=0))
+    dt = np.array([r.schedule[:2] for r in res])
+    rc, status, reps = fim.fim_ensemble_run(members, dt, workers=3)
+    assert rc == fim.FIM_NOT_CONVERGED
+    assert status[2, 0] == fim.FIM_NOT_CONVERGED and status[2, 1] == fim.FIM_SKIPPED
+    others = np.delete(status, 2, axis=0)
+    assert np.all(others == fim.FIM_OK)
+    # the failed member is back at its step-start state
+    st = members[2].fim_get_state()
+    assert np.all(st["P"] == res[2].p0) and np.all(st["Sw"] == res[2].sw0)
+
+
+def test_ensemble_rejects_a_context_given_twice():
+    res, members = _ensemble_members()
+    with pytest.raises(fim.FimError, match="twice"):
+        fim.fim_ensemble_run([members[0], members[1], members[0]], [[15.0]], workers=2)
