@@ -211,6 +211,36 @@ int fim_get_state(fim_ctx *ctx, double *p, double *sw, double *x3, int8_t *flag,
  * in place; fills rep (may be NULL).  Returns FIM_OK or FIM_NOT_CONVERGED. */
 int fim_step(fim_ctx *ctx, double dt_days, fim_step_report *rep);
 
+/* Discrete adjoint: the gradient of a production mismatch with respect to
+ * the log-permeability of every cell.  The paper has no adjoint; the
+ * gradient is that of the discrete system it solves, the backward-Euler
+ * residual of eqs. (1)-(2) with the fluxes and wells of Sec. 3.2.3-3.2.4.
+ *   theta_c = ln k_c, with kx, ky and kz of cell c scaled together
+ *   (porosity held fixed; an explicit well index does not depend on k, a
+ *   Peaceman one scales with k);
+ *   J = sum over the nsteps schedule steps s and the producers w of
+ *       (q_o,w(x_s) - q_obs[s*nwells + w])^2, q_o,w the surface oil rate of
+ *       the well at the end of step s (stb/d); q_obs entries of other wells
+ *       are ignored (q_obs may be NULL without wells).
+ * From the current state, runs the nsteps steps of dt[nsteps] (days) as
+ * fim_step does, keeping the state after every accepted sub-step on the
+ * device, then the backward sweep over the sub-steps, each a transposed
+ * Jacobian solve (FP64, block-Jacobi ILU(0) of J^T, or point-block Jacobi
+ * when that is the context's preconditioner, relative residual 1e-12).
+ * grad[ncells] (host) receives dJ/dtheta.  On FIM_OK the state is the end
+ * of the forward run.  FIM_NOT_CONVERGED: a forward step failed (the state
+ * is the start state and grad is not written) or an adjoint solve did not
+ * converge (the state is the end of the forward run). */
+typedef struct {
+    int32_t steps, substeps, cuts, newton_iters, linear_iters, adjoint_iters;
+    double objective;                    /* J */
+    double adjoint_relres;               /* largest final relative residual of the adjoint solves */
+    double t_forward_ms, t_adjoint_ms;   /* host wall time of the forward run and the sweep */
+} fim_adjoint_report;
+
+int fim_adjoint_gradient(fim_ctx *ctx, int32_t nsteps, const double *dt, const double *q_obs,
+                         double *grad, fim_adjoint_report *rep);
+
 /* An ensemble of independent reservoirs (for instance realisations of one
  * field): advances members[0..count) by nsteps time steps each.  Step s of
  * member k is exactly fim_step(members[k], dt[k*nsteps + s],

@@ -11,6 +11,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <chrono>
+#include <functional>
 #include <limits>
 #include <mutex>
 #include <new>
@@ -151,6 +153,19 @@ struct fim_ctx {
     int spmv_used = 0;
     double spmv_ms = 0.0;
     int spmv_calls = 0;
+    // discrete adjoint: the state after every accepted sub-step of the
+    // forward run and the work arrays of the backward sweep
+    double *wi_dk = nullptr;                        // [nperf] 1: WI ~ k (Peaceman), 0: explicit
+    int *tperm = nullptr;                           // [nnzb] block of J^T -> block of J
+    double *valT = nullptr;                         // [nnzb][nb][nb]
+    double *lam[2] = {}, *arhs = nullptr, *grad = nullptr, *objp = nullptr, *objw = nullptr,
+           *qobs = nullptr;
+    size_t qobs_len = 0;
+    struct Ckpt {
+        double *P, *Sw, *X, *pbhp;
+        int8_t *flag;
+    };
+    std::vector<Ckpt> ckpt;
 
     Wells wells() const {
         Wells W;
@@ -464,7 +479,7 @@ static int create_impl(const fim_grid *grid, const fim_rock *rock, const fim_flu
 
         // wells: perforations sorted by cell within each well
         std::vector<int> sorted_cells;
-        std::vector<double> wi_sorted, rw(nwells), skin(nwells);
+        std::vector<double> wi_sorted, wi_dk_h, rw(nwells), skin(nwells);
         c->wps.assign(nwells + 1, 0);
         std::vector<int> pwell_h;
         int src_base = 0;
@@ -492,6 +507,7 @@ static int create_impl(const fim_grid *grid, const fim_rock *rock, const fim_flu
                 pwell_h.push_back(wl);
                 c->perf_src.push_back(src_base + idx[q]);
                 wi_sorted.push_back(W.wi ? W.wi[idx[q]] : 0.0);
+                wi_dk_h.push_back(W.wi ? 0.0 : 1.0);
                 if (W.wi) REQUIRE(W.wi[idx[q]] > 0, "well %d: explicit WI must be > 0", wl);
             }
             src_base += W.nperf;
@@ -587,6 +603,7 @@ static int create_impl(const fim_grid *grid, const fim_rock *rock, const fim_flu
         c->pcell = c->upload(sorted_cells.data(), c->nperf);
         c->pwell = c->upload(pwell_h.data(), c->nperf);
         c->wi = c->upload(wi_sorted.data(), c->nperf);
+        c->wi_dk = c->upload(wi_dk_h.data(), c->nperf);
         c->wrw = c->upload(rw.data(), nwells);
         c->wskin = c->upload(skin.data(), nwells);
         c->cps = c->upload(cps.data(), n + 1);
@@ -1352,7 +1369,10 @@ static bool newton(fim_ctx *c, double dt, NewtonStats &st) {
     }
 }
 
-static int step_impl(fim_ctx *c, double dt, fim_step_report *rep) {
+// on_accept (optional) runs after every accepted sub-step with its length,
+// while the state is the sub-step's end state
+static int step_impl(fim_ctx *c, double dt, fim_step_report *rep,
+                     const std::function<void(double)> *on_accept = nullptr) {
     REQUIRE(dt > 0 && std::isfinite(dt), "dt must be > 0");
     if (!c->state_set) {
         set_err("state not set (call fim_set_state first)");
@@ -1377,6 +1397,7 @@ static int step_impl(fim_ctx *c, double dt, fim_step_report *rep) {
             remaining -= tdt;
             if (r.nsub < FIM_MAX_SUB) r.dt_sub[r.nsub] = tdt;
             r.nsub++;
+            if (on_accept) (*on_accept)(tdt);
         } else {
             restore_state(c, 1);
             r.cuts++;
@@ -1409,6 +1430,208 @@ static int step_impl(fim_ctx *c, double dt, fim_step_report *rep) {
     r.last_dp = st.last_dp;
     r.last_ds = st.last_ds;
     r.well_res = st.well_res;
+    if (rep) *rep = r;
+    return status;
+}
+
+// ---------------------------------------------------------------------------
+// discrete adjoint of the backward-Euler system
+
+// copy the current state to checkpoint m (allocated on first use), or back
+static void put_ckpt(fim_ctx *c, size_t m) {
+    const size_t n = c->n;
+    while (c->ckpt.size() <= m) {
+        fim_ctx::Ckpt k{c->alloc<double>(n), c->alloc<double>(n), c->alloc<double>(n),
+                        c->alloc<double>(std::max(c->nw, 1)), c->alloc<int8_t>(n)};
+        c->ckpt.push_back(k);
+    }
+    const fim_ctx::Ckpt &k = c->ckpt[m];
+    HIPCHECK(hipMemcpyAsync(k.P, c->P, n * 8, hipMemcpyDeviceToDevice, c->s));
+    HIPCHECK(hipMemcpyAsync(k.Sw, c->Sw, n * 8, hipMemcpyDeviceToDevice, c->s));
+    HIPCHECK(hipMemcpyAsync(k.X, c->X, n * 8, hipMemcpyDeviceToDevice, c->s));
+    HIPCHECK(hipMemcpyAsync(k.flag, c->flag, n, hipMemcpyDeviceToDevice, c->s));
+    if (c->nw) HIPCHECK(hipMemcpyAsync(k.pbhp, c->pbhp, c->nw * 8, hipMemcpyDeviceToDevice, c->s));
+}
+
+static void get_ckpt(fim_ctx *c, size_t m) {
+    const size_t n = c->n;
+    const fim_ctx::Ckpt &k = c->ckpt[m];
+    HIPCHECK(hipMemcpyAsync(c->P, k.P, n * 8, hipMemcpyDeviceToDevice, c->s));
+    HIPCHECK(hipMemcpyAsync(c->Sw, k.Sw, n * 8, hipMemcpyDeviceToDevice, c->s));
+    HIPCHECK(hipMemcpyAsync(c->X, k.X, n * 8, hipMemcpyDeviceToDevice, c->s));
+    HIPCHECK(hipMemcpyAsync(c->flag, k.flag, n, hipMemcpyDeviceToDevice, c->s));
+    if (c->nw) HIPCHECK(hipMemcpyAsync(c->pbhp, k.pbhp, c->nw * 8, hipMemcpyDeviceToDevice, c->s));
+}
+
+// The transpose permutation of the (structurally symmetric) pattern and the
+// work arrays of the backward sweep, once per context.
+static void ensure_adjoint(fim_ctx *c) {
+    if (c->tperm) return;
+    const int nr = c->nrows;
+    std::vector<int> rp(nr + 1), ci(c->nnzb), perm(c->nnzb, -1);
+    HIPCHECK(hipMemcpyAsync(rp.data(), c->rowptr, (nr + 1) * sizeof(int), hipMemcpyDeviceToHost, c->s));
+    HIPCHECK(hipMemcpyAsync(ci.data(), c->colind, c->nnzb * sizeof(int), hipMemcpyDeviceToHost, c->s));
+    c->sync();
+    for (int r = 0; r < nr; ++r)
+        for (int q = rp[r]; q < rp[r + 1]; ++q) {
+            const int col = ci[q];
+            for (int t = rp[col]; t < rp[col + 1]; ++t)
+                if (ci[t] == r) {
+                    perm[q] = t;
+                    break;
+                }
+            REQUIRE(perm[q] >= 0, "block (%d, %d) has no transposed partner", r, col);
+        }
+    c->tperm = c->upload(perm.data(), perm.size());
+    c->valT = c->alloc<double>((size_t)c->nnzb * c->nb * c->nb);
+    c->lam[0] = c->alloc<double>(c->nvec);
+    c->lam[1] = c->alloc<double>(c->nvec);
+    c->arhs = c->alloc<double>(c->nvec);
+    c->grad = c->alloc<double>(c->n);
+    c->objp = c->alloc<double>((size_t)std::max(c->nperf, 1) * (c->nb + 1));
+    c->objw = c->alloc<double>(2 * std::max(c->nw, 1));
+    c->sync();
+}
+
+// Forward: nsteps time steps of fim_step, keeping the state after every
+// accepted sub-step m = 1..M (state 0 = the start).  Backward, m = M..1:
+//   J_m^T lam_m = (1/dt_{m+1}) (dA(x_m)/dx_m)^T lam_{m+1} - (dJ/dx_m)^T
+// (the first term absent for m = M, the second only where a schedule step
+// ends), then grad += lam_m^T dR_m/dtheta (+ dJ/dtheta at schedule ends).
+// The transposed systems are solved by FGMRES with block-Jacobi ILU(0) of
+// J^T (point-block Jacobi when that is the context's preconditioner), in
+// FP64, to a relative residual of 1e-12.
+static int adjoint_impl(fim_ctx *c, int nsteps, const double *dt, const double *qobs_h,
+                        double *grad_h, fim_adjoint_report *rep) {
+    using clock = std::chrono::steady_clock;
+    REQUIRE(nsteps >= 1, "nsteps must be >= 1");
+    REQUIRE(dt && grad_h, "dt and grad are required");
+    REQUIRE(qobs_h || c->nw == 0, "q_obs is required");
+    if (!c->state_set) {
+        set_err("state not set (call fim_set_state first)");
+        throw StateError();
+    }
+    ensure_adjoint(c);
+    fim_adjoint_report r{};
+    const auto t0 = clock::now();
+    std::vector<double> hsub;              // accepted sub-step lengths
+    std::vector<int> send(1, -1);          // schedule step that ends at sub-step m, else -1
+    put_ckpt(c, 0);
+    const std::function<void(double)> hook = [&](double h) {
+        hsub.push_back(h);
+        send.push_back(-1);
+        put_ckpt(c, hsub.size());
+    };
+    for (int st = 0; st < nsteps; ++st) {
+        fim_step_report sr{};
+        const int status = step_impl(c, dt[st], &sr, &hook);
+        r.steps += status == FIM_OK;
+        r.cuts += sr.cuts;
+        r.newton_iters += sr.newton_iters;
+        r.linear_iters += sr.linear_iters;
+        if (status != FIM_OK) {
+            get_ckpt(c, 0);
+            props(c, true);
+            c->sync();
+            r.substeps = (int)hsub.size();
+            if (rep) *rep = r;
+            return FIM_NOT_CONVERGED;
+        }
+        send.back() = st;
+    }
+    c->sync();
+    const auto t1 = clock::now();
+    const int M = (int)hsub.size();
+    r.substeps = M;
+    const size_t nq = (size_t)nsteps * c->nw;
+    if (nq > c->qobs_len) {
+        c->release(c->qobs);
+        c->qobs = c->alloc<double>(nq);
+        c->qobs_len = nq;
+    }
+    if (nq) HIPCHECK(hipMemcpyAsync(c->qobs, qobs_h, nq * 8, hipMemcpyHostToDevice, c->s));
+    HIPCHECK(hipMemsetAsync(c->grad, 0, c->n * sizeof(double), c->s));
+    // the transposed solves: FP64, no CPR (its pressure stage is built for J)
+    const fim_options saved = c->opt;
+    const bool saved_mixed = c->mixed;
+    c->opt.precond = c->opt.precond == FIM_PREC_BJ ? FIM_PREC_BJ : FIM_PREC_ILU0;
+    c->mixed = false;
+    c->drop_graphs();
+    std::vector<double> jw((size_t)nsteps * 2 * std::max(c->nw, 1), 0.0);
+    int status = FIM_OK;
+    try {
+        build_ilu(c);
+        const int max_it = std::max(c->opt.max_lin, 1000);
+        double *lam_next = nullptr;
+        int cur = 0;
+        for (int m = M; m >= 1; --m) {
+            get_ckpt(c, m - 1);
+            props(c, true);                         // A(x_{m-1})
+            get_ckpt(c, m);
+            props(c, false);
+            assemble(c, hsub[m - 1]);               // J_m
+            const int st = send[m];
+            const double *objp = nullptr, *objw = nullptr;
+            if (st >= 0 && c->nw) {
+                launch_adj_objective(c->s, c->nb, c->wells(), c->n, c->P, c->pbhp, c->rec,
+                                     c->wi_dk, c->qobs + (size_t)st * c->nw, c->objp, c->objw);
+                HIPCHECK(hipMemcpyAsync(jw.data() + (size_t)st * 2 * c->nw, c->objw,
+                                        2 * c->nw * 8, hipMemcpyDeviceToHost, c->s));
+                objp = c->objp;
+                objw = c->objw;
+            }
+            launch_adj_rhs(c->s, c->nb, c->wells(), c->n, c->rec, lam_next,
+                           m < M ? 1.0 / hsub[m] : 0.0, objp, objw, c->arhs);
+            launch_bsr_transpose(c->s, c->nb, c->nnzb, c->tperm, c->val, c->valT);
+            std::swap(c->val, c->valT);
+            double *lam = c->lam[cur];
+            int li = 0;
+            double rr = 0.0;
+            int gs = 0;
+            try {
+                prec_setup(c);
+                gs = gmres_t<double>(c, c->arhs, lam, max_it, 1e-12, false, &li, &rr, nullptr);
+            } catch (...) {
+                std::swap(c->val, c->valT);
+                throw;
+            }
+            std::swap(c->val, c->valT);
+            r.adjoint_iters += li;
+            r.adjoint_relres = std::max(r.adjoint_relres, rr);
+            if (gs != 0) {
+                set_err("adjoint solve of sub-step %d did not converge (relative residual %.3g)",
+                        m, rr);
+                status = FIM_NOT_CONVERGED;
+                break;
+            }
+            launch_adj_grad(c->s, c->nb, c->g, c->wells(), c->depth, c->tx, c->ty, c->tz, c->kx,
+                            c->ky, c->kz, c->dx, c->dy, c->dz, c->P, c->pbhp, c->rec, c->wi_dk,
+                            lam, objp, c->grad);
+            lam_next = lam;
+            cur ^= 1;
+        }
+        if (status == FIM_OK)
+            HIPCHECK(hipMemcpyAsync(grad_h, c->grad, c->n * 8, hipMemcpyDeviceToHost, c->s));
+        c->sync();
+    } catch (...) {
+        c->opt = saved;
+        c->mixed = saved_mixed;
+        c->drop_graphs();
+        throw;
+    }
+    c->opt = saved;
+    c->mixed = saved_mixed;
+    c->drop_graphs();
+    // leave the context at the end of the forward run
+    get_ckpt(c, M);
+    props(c, true);
+    c->jac_ready = false;
+    c->prec_ready = false;
+    c->sync();
+    for (int st = 0; st < nsteps; ++st)
+        for (int wl = 0; wl < c->nw; ++wl) r.objective += jw[(size_t)st * 2 * c->nw + 2 * wl + 1];
+    r.t_forward_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    r.t_adjoint_ms = std::chrono::duration<double, std::milli>(clock::now() - t1).count();
     if (rep) *rep = r;
     return status;
 }
@@ -1562,6 +1785,14 @@ int fim_step(fim_ctx *c, double dt_days, fim_step_report *rep) {
     return guarded([&] {
         REQUIRE(c, "context is NULL");
         return step_impl(c, dt_days, rep);
+    });
+}
+
+int fim_adjoint_gradient(fim_ctx *c, int32_t nsteps, const double *dt, const double *q_obs,
+                         double *grad, fim_adjoint_report *rep) {
+    return guarded([&] {
+        REQUIRE(c, "context is NULL");
+        return adjoint_impl(c, nsteps, dt, q_obs, grad, rep);
     });
 }
 

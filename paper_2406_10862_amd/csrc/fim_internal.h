@@ -123,6 +123,20 @@ void launch_newton_update(hipStream_t s, int nb, Phys f, int n, int nw, const do
                           double *out);
 void launch_well_rates(hipStream_t s, int nb, Wells w, const double *P, const double *pbhp,
                        const double *rec, int n, double *q);
+// discrete adjoint (fim_phys.hip, fim_linalg.hip)
+void launch_adj_objective(hipStream_t s, int nb, Wells w, int n, const double *P,
+                          const double *pbhp, const double *rec, const double *wi_dk,
+                          const double *qobs, double *objp, double *objw);
+void launch_adj_rhs(hipStream_t s, int nb, Wells w, int n, const double *rec,
+                    const double *lam_next, double rdt_next, const double *objp,
+                    const double *objw, double *rhs);
+void launch_adj_grad(hipStream_t s, int nb, Grid g, Wells w, const double *depth,
+                     const double *tx, const double *ty, const double *tz, const double *kx,
+                     const double *ky, const double *kz, const double *dx, const double *dy,
+                     const double *dz, const double *P, const double *pbhp, const double *rec,
+                     const double *wi_dk, const double *lam, const double *objp, double *grad);
+void launch_bsr_transpose(hipStream_t s, int nb, long nnzb, const int *tperm, const double *val,
+                          double *valT);
 int conv_blocks(int n);
 int update_blocks(int n);
 

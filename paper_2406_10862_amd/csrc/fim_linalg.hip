@@ -221,6 +221,33 @@ void launch_spmv(hipStream_t s, int nb, int nrows, const int *rowptr, const int 
 }
 
 // ---------------------------------------------------------------------------
+// J^T on J's (structurally symmetric) pattern: block q = (r, c) of J^T is
+// the transpose of block tperm[q] = (c, r) of J.
+template <int NB>
+__global__ __launch_bounds__(kBlock) void k_bsr_transpose(long nnzb, const int *__restrict__ tperm,
+                                                          const double *__restrict__ val,
+                                                          double *__restrict__ valT) {
+    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nnzb) return;
+    const double *src = val + (size_t)tperm[q] * NB * NB;
+    double *dst = valT + (size_t)q * NB * NB;
+#pragma unroll
+    for (int e = 0; e < NB; ++e)
+#pragma unroll
+        for (int u = 0; u < NB; ++u) dst[e * NB + u] = src[u * NB + e];
+}
+
+void launch_bsr_transpose(hipStream_t s, int nb, long nnzb, const int *tperm, const double *val,
+                          double *valT) {
+    if (nnzb <= 0) return;
+    dim3 grid((unsigned)((nnzb + kBlock - 1) / kBlock)), block(kBlock);
+    if (nb == 2)
+        hipLaunchKernelGGL(k_bsr_transpose<2>, grid, block, 0, s, nnzb, tperm, val, valT);
+    else
+        hipLaunchKernelGGL(k_bsr_transpose<3>, grid, block, 0, s, nnzb, tperm, val, valT);
+}
+
+// ---------------------------------------------------------------------------
 // block Jacobi: inverse of each diagonal block
 
 

@@ -705,6 +705,165 @@ __global__ __launch_bounds__(64) void k_well_rates(Wells w, const double *__rest
 }
 
 // ---------------------------------------------------------------------------
+// discrete adjoint of the backward-Euler system
+//
+// The parameter of cell c is theta_c = ln k_c, with kx, ky and kz of the
+// cell scaled together.  The residual depends on it through the face
+// transmissibilities (harmonic, so dT/dtheta_c = T g_o/(g_c + g_o) with g the
+// half-cell conductances k A/h of the face's two cells) and through the
+// Peaceman well indices (WI ~ sqrt(kx ky), so dWI/dtheta_c = WI; an explicit
+// WI does not depend on k: wi_dk = 0).  The objective is the production
+// mismatch J = sum over schedule-step ends and producers of
+// (q_o,w - q_obs,w)^2, q_o,w the surface oil rate of the well.
+
+// Objective terms at the end of a schedule step, one wave per well:
+// r_w = q_o,w - qobs[w]; per perforation p of a producer
+// objp[p][u] = 2 r_w dq_o,p/dx_u (u < NB) and objp[p][NB] = 2 r_w q_o,p wi_dk[p]
+// (dJ/dtheta of its cell); per well objw[2w] = 2 r_w dq_o,w/dPbhp and
+// objw[2w+1] = r_w^2.  Other wells get zeros.
+template <int NB>
+__global__ __launch_bounds__(64) void k_adj_objective(Wells w, int n,
+                                                      const double *__restrict__ P,
+                                                      const double *__restrict__ pbhp,
+                                                      const double *__restrict__ rec,
+                                                      const double *__restrict__ wi_dk,
+                                                      const double *__restrict__ qobs,
+                                                      double *__restrict__ objp,
+                                                      double *__restrict__ objw) {
+    const int wl = blockIdx.x, lane = threadIdx.x;
+    const int p0 = w.wps[wl], np = w.wps[wl + 1] - p0;
+    const bool prod = w.kind[wl] == kProd;
+    double s[2] = {0.0, 0.0};
+    if (prod)
+        for (int p = lane; p < np; p += 64) {
+            const int pid = p0 + p, c = w.pcell[pid];
+            double qr[NB], dq[NB][NB], dqb[NB];
+            perf_rate<NB>(kProd, w.wi[pid], P[c], pbhp[wl], rec, n, c, qr, dq, dqb);
+            s[0] += qr[1];
+            s[1] += dqb[1];
+        }
+    const bool mx[2] = {false, false};
+    wave_reduce<2>(s, mx);
+    const double r = prod ? s[0] - qobs[wl] : 0.0;
+    for (int p = lane; p < np; p += 64) {
+        const int pid = p0 + p, c = w.pcell[pid];
+        double *o = objp + (size_t)pid * (NB + 1);
+        double qr[NB], dq[NB][NB], dqb[NB];
+        if (prod) perf_rate<NB>(kProd, w.wi[pid], P[c], pbhp[wl], rec, n, c, qr, dq, dqb);
+#pragma unroll
+        for (int u = 0; u < NB; ++u) o[u] = prod ? 2.0 * r * dq[1][u] : 0.0;
+        o[NB] = prod ? 2.0 * r * qr[1] * wi_dk[pid] : 0.0;
+    }
+    if (lane == 0) {
+        objw[2 * wl] = 2.0 * r * s[1];
+        objw[2 * wl + 1] = r * r;
+    }
+}
+
+// Right side of the adjoint system of a sub-step: on the cell rows
+// (1/dt_next) (dA/dx)^T lam_next (lam_next null on the last sub-step), minus
+// dJ/dx when the sub-step ends a schedule step (objp, objw non-null).
+template <int NB>
+__global__ __launch_bounds__(kBlock) void k_adj_rhs(Wells w, int n, int nw,
+                                                    const double *__restrict__ rec,
+                                                    const double *__restrict__ lam_next,
+                                                    double rdt_next,
+                                                    const double *__restrict__ objp,
+                                                    const double *__restrict__ objw,
+                                                    double *__restrict__ rhs) {
+    using RI = Rec<NB>;
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n + nw) return;
+    double out[NB];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) out[u] = 0.0;
+    if (r < n) {
+        if (lam_next) {
+#pragma unroll
+            for (int u = 0; u < NB; ++u) {
+                double a = 0.0;
+#pragma unroll
+                for (int i = 0; i < NB; ++i)
+                    a += rec[(size_t)(RI::ACC + i * RI::G + 1 + u) * n + r] * lam_next[(size_t)r * NB + i];
+                out[u] = a * rdt_next;
+            }
+        }
+        if (objp)
+            for (int pp = w.cps[r]; pp < w.cps[r + 1]; ++pp) {
+                const double *o = objp + (size_t)w.cperf[pp] * (NB + 1);
+#pragma unroll
+                for (int u = 0; u < NB; ++u) out[u] -= o[u];
+            }
+    } else if (objw) {
+        out[0] = -objw[2 * (r - n)];
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) rhs[(size_t)r * NB + u] = out[u];
+}
+
+// grad[c] += lam^T dR/dtheta_c (+ dJ/dtheta_c when objp is non-null) at
+// the state of the sub-step, cell-centric: the faces of c, then its
+// perforations (their own rows, and the well row of a rate-controlled well).
+template <int NB>
+__global__ __launch_bounds__(kBlock) void k_adj_grad(
+    Grid g, Wells w, const double *__restrict__ depth, const double *__restrict__ tx,
+    const double *__restrict__ ty, const double *__restrict__ tz, const double *__restrict__ kx,
+    const double *__restrict__ ky, const double *__restrict__ kz, const double *__restrict__ dx,
+    const double *__restrict__ dy, const double *__restrict__ dz, const double *__restrict__ P,
+    const double *__restrict__ pbhp, const double *__restrict__ rec,
+    const double *__restrict__ wi_dk, const double *__restrict__ lam,
+    const double *__restrict__ objp, double *__restrict__ grad) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = g.n;
+    if (c >= n) return;
+    const int nx = g.nx, nxy = g.nx * g.ny;
+    const int i = c % nx, j = (c / nx) % g.ny, k = c / nxy;
+    Side<NB> me, nbr;
+    load_side<NB>(rec, n, c, P, depth, me);
+    double lc[NB];
+#pragma unroll
+    for (int e = 0; e < NB; ++e) lc[e] = lam[(size_t)c * NB + e];
+    double acc = 0.0;
+    // face to cell cn; rc = h/k of this cell's half, ro of the other's
+    auto face = [&](int cn, double T, double rc, double ro, bool lower) {
+        if (!(T > 0.0)) return;
+        load_side<NB>(rec, n, cn, P, depth, nbr);
+        double F[NB], dK[NB][NB], dL[NB][NB];
+        double d = 0.0;
+        if (lower) {            // flux from cn into c: R_cn += F, R_c -= F
+            face_flux<NB>(T, nbr, me, F, dK, dL);
+#pragma unroll
+            for (int e = 0; e < NB; ++e) d += (lam[(size_t)cn * NB + e] - lc[e]) * F[e];
+        } else {                // flux from c into cn: R_c += F, R_cn -= F
+            face_flux<NB>(T, me, nbr, F, dK, dL);
+#pragma unroll
+            for (int e = 0; e < NB; ++e) d += (lc[e] - lam[(size_t)cn * NB + e]) * F[e];
+        }
+        acc += d * (rc / (rc + ro));
+    };
+    if (k > 0) face(c - nxy, tz[c - nxy], 0.5 * dz[k] / kz[c], 0.5 * dz[k - 1] / kz[c - nxy], true);
+    if (j > 0) face(c - nx, ty[c - nx], 0.5 * dy[j] / ky[c], 0.5 * dy[j - 1] / ky[c - nx], true);
+    if (i > 0) face(c - 1, tx[c - 1], 0.5 * dx[i] / kx[c], 0.5 * dx[i - 1] / kx[c - 1], true);
+    if (i + 1 < nx) face(c + 1, tx[c], 0.5 * dx[i] / kx[c], 0.5 * dx[i + 1] / kx[c + 1], false);
+    if (j + 1 < g.ny) face(c + nx, ty[c], 0.5 * dy[j] / ky[c], 0.5 * dy[j + 1] / ky[c + nx], false);
+    if (k + 1 < g.nz) face(c + nxy, tz[c], 0.5 * dz[k] / kz[c], 0.5 * dz[k + 1] / kz[c + nxy], false);
+    for (int pp = w.cps[c]; pp < w.cps[c + 1]; ++pp) {
+        const int p = w.cperf[pp];
+        const int wl = w.pwell[p];
+        double qr[NB], dq[NB][NB], dqb[NB];
+        perf_rate<NB>(w.kind[wl], w.wi[p], me.P, pbhp[wl], rec, n, c, qr, dq, dqb);
+        double t = 0.0;
+#pragma unroll
+        for (int e = 0; e < NB; ++e) t += lc[e] * qr[e];
+        const int ii = (w.kind[wl] == kInjGas) ? 2 : 0;        // the rate row's component
+        if (w.ctrl[wl] == kRate && ii < NB) t -= lam[(size_t)(n + wl) * NB] * qr[ii];
+        acc += t * wi_dk[p];
+        if (objp) acc += objp[(size_t)p * (NB + 1) + NB];
+    }
+    grad[c] += acc;
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 
 static inline int blocks_for(long n, int bs) { return (int)((n + bs - 1) / bs); }
@@ -795,6 +954,44 @@ void launch_well_rates(hipStream_t s, int nb, Wells w, const double *P, const do
         hipLaunchKernelGGL(k_well_rates<2>, dim3(w.nw), dim3(64), 0, s, w, P, pbhp, rec, n, q);
     else
         hipLaunchKernelGGL(k_well_rates<3>, dim3(w.nw), dim3(64), 0, s, w, P, pbhp, rec, n, q);
+}
+
+void launch_adj_objective(hipStream_t s, int nb, Wells w, int n, const double *P,
+                          const double *pbhp, const double *rec, const double *wi_dk,
+                          const double *qobs, double *objp, double *objw) {
+    if (!w.nw) return;
+    if (nb == 2)
+        hipLaunchKernelGGL(k_adj_objective<2>, dim3(w.nw), dim3(64), 0, s, w, n, P, pbhp, rec,
+                           wi_dk, qobs, objp, objw);
+    else
+        hipLaunchKernelGGL(k_adj_objective<3>, dim3(w.nw), dim3(64), 0, s, w, n, P, pbhp, rec,
+                           wi_dk, qobs, objp, objw);
+}
+
+void launch_adj_rhs(hipStream_t s, int nb, Wells w, int n, const double *rec,
+                    const double *lam_next, double rdt_next, const double *objp,
+                    const double *objw, double *rhs) {
+    dim3 grid(blocks_for((long)n + w.nw, kBlock)), block(kBlock);
+    if (nb == 2)
+        hipLaunchKernelGGL(k_adj_rhs<2>, grid, block, 0, s, w, n, w.nw, rec, lam_next, rdt_next,
+                           objp, objw, rhs);
+    else
+        hipLaunchKernelGGL(k_adj_rhs<3>, grid, block, 0, s, w, n, w.nw, rec, lam_next, rdt_next,
+                           objp, objw, rhs);
+}
+
+void launch_adj_grad(hipStream_t s, int nb, Grid g, Wells w, const double *depth,
+                     const double *tx, const double *ty, const double *tz, const double *kx,
+                     const double *ky, const double *kz, const double *dx, const double *dy,
+                     const double *dz, const double *P, const double *pbhp, const double *rec,
+                     const double *wi_dk, const double *lam, const double *objp, double *grad) {
+    dim3 grid(blocks_for(g.n, kBlock)), block(kBlock);
+    if (nb == 2)
+        hipLaunchKernelGGL(k_adj_grad<2>, grid, block, 0, s, g, w, depth, tx, ty, tz, kx, ky, kz,
+                           dx, dy, dz, P, pbhp, rec, wi_dk, lam, objp, grad);
+    else
+        hipLaunchKernelGGL(k_adj_grad<3>, grid, block, 0, s, g, w, depth, tx, ty, tz, kx, ky, kz,
+                           dx, dy, dz, P, pbhp, rec, wi_dk, lam, objp, grad);
 }
 
 }  // namespace fim

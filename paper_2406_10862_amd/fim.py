@@ -76,11 +76,19 @@ class FimStepReport(C.Structure):
                 ("dt_sub", C.c_double * FIM_MAX_SUB)]
 
 
+class FimAdjointReport(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("substeps", C.c_int32), ("cuts", C.c_int32),
+                ("newton_iters", C.c_int32), ("linear_iters", C.c_int32),
+                ("adjoint_iters", C.c_int32), ("objective", C.c_double),
+                ("adjoint_relres", C.c_double), ("t_forward_ms", C.c_double),
+                ("t_adjoint_ms", C.c_double)]
+
+
 EXPORTS = ["fim_create", "fim_destroy", "fim_last_error", "fim_sizes", "fim_set_options",
            "fim_set_state", "fim_set_state_dev", "fim_get_state", "fim_step",
            "fim_get_well_rates", "fim_static", "fim_set_iterate", "fim_props",
            "fim_assemble", "fim_precond_apply", "fim_linear_solve", "fim_bsr_spmv",
-           "fim_ensemble_run"]
+           "fim_ensemble_run", "fim_adjoint_gradient"]
 
 _LIB = None
 
@@ -126,6 +134,8 @@ def lib():
     L.fim_precond_apply.argtypes = [vp, f64p, f64p]
     L.fim_linear_solve.argtypes = [vp, f64p, f64p, i32p, f64p]
     L.fim_bsr_spmv.argtypes = [C.c_int32, C.c_int32, vp, vp, vp, vp, vp, vp]
+    L.fim_adjoint_gradient.argtypes = [vp, C.c_int32, f64p, f64p, f64p,
+                                       C.POINTER(FimAdjointReport)]
     L.fim_ensemble_run.argtypes = [C.c_int32, C.POINTER(vp), C.c_int32, f64p, C.c_int32,
                                    C.POINTER(FimStepReport), i32p]
     for f in EXPORTS:
@@ -270,6 +280,18 @@ class Fim:
         _check(lib().fim_get_state(self.h, _p(P, f64p), _p(Sw, f64p), _p(X, f64p),
                                    _p(flag, i8p), _p(bhp, f64p)), "fim_get_state")
         return dict(P=P, Sw=Sw, X=X, flag=flag, pbhp=bhp[: self.nw])
+
+    def fim_adjoint_gradient(self, dt, q_obs):
+        """dJ/d(ln k) of every cell for J = sum_s sum_producers (q_o - q_obs[s, w])^2
+        over the steps dt (fim_adjoint_gradient).  Returns (rc, grad, report)."""
+        dt = _f64(np.atleast_1d(dt))
+        qo = _f64(np.asarray(q_obs, dtype=np.float64).reshape(len(dt), self.nw)) if self.nw else None
+        grad = np.zeros(self.n)
+        rep = FimAdjointReport()
+        rc = _check(lib().fim_adjoint_gradient(self.h, len(dt), _p(dt, f64p), _p(qo, f64p),
+                                               _p(grad, f64p), C.byref(rep)),
+                    "fim_adjoint_gradient")
+        return rc, grad, rep
 
     def fim_step(self, dt):
         rep = FimStepReport()

@@ -694,3 +694,65 @@ def test_ensemble_rejects_a_context_given_twice():
     res, members = _ensemble_members()
     with pytest.raises(fim.FimError, match="twice"):
         fim.fim_ensemble_run([members[0], members[1], members[0]], [[15.0]], workers=2)
+
+
+# ---------------------------------------------------------------------------
+# discrete adjoint (fim_adjoint_gradient) against the oracle's adjoint
+
+def _adjoint_case(cfg):
+    if cfg == "c5":
+        res = rv.config_c5(12, 10, 4)
+        qobs = np.random.default_rng(11).uniform(0.0, 60.0, size=(4, len(res.wells)))
+        return res, res.schedule[:4], qobs
+    res = rv.config_c1()
+    qobs = np.random.default_rng(12).uniform(0.0, 2000.0, size=(3, len(res.wells)))
+    return res, res.schedule[:3], qobs
+
+
+@pytest.mark.parametrize("cfg", ["c5", "c1"])
+def test_adjoint_gradient_matches_oracle(cfg):
+    from oracle.adjoint import AdjointOracle
+    res, dts, qobs = _adjoint_case(cfg)
+    Jo, go = AdjointOracle(res).gradient(dts, qobs)
+    g, o = pair(res, options=rv.Options(tile=(5, 5, 3)))
+    rc, grad, rep = g.fim_adjoint_gradient(dts, qobs)
+    print(f"adjoint {cfg}: J {rep.objective:.6e} (oracle {Jo:.6e}) substeps {rep.substeps} "
+          f"adjoint iterations {rep.adjoint_iters} relres {rep.adjoint_relres:.2e} "
+          f"forward {rep.t_forward_ms:.1f} ms adjoint {rep.t_adjoint_ms:.1f} ms")
+    assert rc == fim.FIM_OK and rep.steps == len(dts)
+    assert abs(rep.objective - Jo) <= 1e-10 * Jo
+    err = np.abs(grad - go).max() / np.abs(go).max()
+    print("gradient error relative to max |grad|:", err)
+    assert err <= 1e-8
+
+
+def test_adjoint_leaves_the_forward_end_state():
+    res, dts, qobs = _adjoint_case("c5")
+    g1 = fim.Fim(res)
+    g1.set_initial_state()
+    rc, grad, rep = g1.fim_adjoint_gradient(dts, qobs)
+    assert rc == fim.FIM_OK
+    g2 = fim.Fim(res)
+    g2.set_initial_state()
+    for dt in dts:
+        assert g2.fim_step(dt)[0] == fim.FIM_OK
+    a, b = g1.fim_get_state(), g2.fim_get_state()
+    for q in a:
+        assert np.array_equal(a[q], b[q]), q
+    # and the run goes on from there exactly as the plain one
+    assert g1.fim_step(res.schedule[4])[0] == fim.FIM_OK
+    assert g2.fim_step(res.schedule[4])[0] == fim.FIM_OK
+    assert np.array_equal(g1.fim_get_state()["P"], g2.fim_get_state()["P"])
+    # a second gradient from the new state reuses the context's buffers
+    rc, grad2, rep2 = g1.fim_adjoint_gradient(dts[:2], qobs[:2])
+    assert rc == fim.FIM_OK and np.all(np.isfinite(grad2))
+
+
+def test_adjoint_in_a_mixed_precision_context_matches_oracle():
+    from oracle.adjoint import AdjointOracle
+    res, dts, qobs = _adjoint_case("c5")
+    Jo, go = AdjointOracle(res).gradient(dts, qobs)
+    g, o = pair(res, options=rv.Options(precision=rv.MIXED, tile=(5, 5, 3)))
+    rc, grad, rep = g.fim_adjoint_gradient(dts, qobs)
+    assert rc == fim.FIM_OK
+    assert np.abs(grad - go).max() <= 1e-8 * np.abs(go).max()
