@@ -258,6 +258,106 @@ def ensemble_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def adjoint_bench(args):
+    """Adjoint time / forward time of the gradient of the production
+    mismatch on the 200k-cell field; the observed oil rates come from a
+    forward run of a second field (seed 50610863)."""
+    import copy
+
+    import numpy as np
+    import torch
+
+    from paper_2406_10862_amd import fim, reservoirs as rv
+
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    torch.cuda.set_device(0)
+    opts = tolerances(args.tol)
+    res = rv.config_c5()
+    obs_field = rv.config_c5(seed=50610863)
+    nsteps = args.steps if args.steps is not None else len(res.schedule)
+    dts = np.array(res.schedule[:nsteps])
+    prod = [w for w, wl in enumerate(res.wells) if wl.kind == rv.PROD]
+
+    def oil_rates(r, extra=None):
+        """Producer oil rates at every step end of a forward run, and J."""
+        g = fim.Fim(r, options=opts)
+        g.set_initial_state()
+        q = np.zeros((nsteps, len(r.wells)))
+        for s_, dt in enumerate(dts):
+            rc, _ = g.fim_step(dt)
+            assert rc == fim.FIM_OK, "forward step failed"
+            q[s_] = g.fim_get_well_rates()[0][:, 1]
+        return q
+
+    t0 = time.perf_counter()
+    qobs = oil_rates(obs_field)
+    log(f"observations from the second field: {time.perf_counter() - t0:.1f}s")
+    g = fim.Fim(res, options=opts)
+    g.set_initial_state()
+    # warm-up: one gradient over two steps (first launches, graph capture)
+    for _ in range(args.warmup):
+        g.fim_adjoint_gradient(dts[:2], qobs[:2])
+        g.set_initial_state()
+    torch.cuda.synchronize()
+    rc, grad, rep = g.fim_adjoint_gradient(dts, qobs)
+    if rc != fim.FIM_OK:
+        log(f"adjoint gradient: rc={rc} ({fim.lib().fim_last_error().decode()}); steps "
+            f"{rep.steps} substeps {rep.substeps} adjoint iterations {rep.adjoint_iters} "
+            f"largest relres {rep.adjoint_relres:.2e}")
+        sys.exit(1)
+    log(f"J {rep.objective:.6e} forward {rep.t_forward_ms:.0f} ms adjoint {rep.t_adjoint_ms:.0f} ms "
+        f"substeps {rep.substeps} newton {rep.newton_iters} linear {rep.linear_iters} "
+        f"adjoint iterations {rep.adjoint_iters} relres {rep.adjoint_relres:.1e}")
+    fd = None
+    if args.fd_cells > 0:
+        cells = np.random.default_rng(5).choice(g.n, size=args.fd_cells, replace=False)
+        h = 1e-3
+        errs = []
+        for c in cells:
+            Js = []
+            for sgn in (1, -1):
+                r2 = copy.deepcopy(res)
+                f = np.exp(sgn * h)
+                r2.kx[c] *= f
+                r2.ky[c] *= f
+                r2.kz[c] *= f
+                q = oil_rates(r2)
+                Js.append(float(((q[:, prod] - qobs[:, prod]) ** 2).sum()))
+            d = (Js[0] - Js[1]) / (2 * h)
+            errs.append(abs(grad[c] - d) / max(abs(d), 1e-300))
+            log(f"FD cell {c}: adjoint {grad[c]:.8e} central difference {d:.8e} "
+                f"relative error {errs[-1]:.2e}")
+        fd = {"cells": int(args.fd_cells), "seed": 5, "h": h, "max_rel_err": max(errs),
+              "median_rel_err": float(np.median(errs))}
+    out = {
+        "metric": "adjoint time / forward time, gradient of a production mismatch w.r.t. ln k "
+                  "at 200k cells",
+        "value": rep.t_adjoint_ms / rep.t_forward_ms,
+        "unit": "ratio",
+        "n_gpus": 1,
+        "steps": nsteps,
+        "warmup": args.warmup,
+        "ms_per_step": (rep.t_forward_ms + rep.t_adjoint_ms) / nsteps,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "two-phase dead-oil five-spot 100x100x20 = 200,000 cells, seeded "
+                        "log-normal perm (sigma 1), 20 steps of 30 days; observed oil rates "
+                        "of the 4 producers from a second field (seed 50610863)",
+            "cells": g.n, "tolerances": args.tol,
+            "forward_ms": rep.t_forward_ms, "adjoint_ms": rep.t_adjoint_ms,
+            "objective": rep.objective, "substeps": rep.substeps,
+            "newton_iters": rep.newton_iters, "linear_iters": rep.linear_iters,
+            "adjoint_iters": rep.adjoint_iters, "adjoint_relres": rep.adjoint_relres,
+            "fd_check": fd,
+        },
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -266,10 +366,15 @@ def main():
                          "it, 20 at c2, 10 at c3, 30 at c4)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--tol", choices=["parity", "paper"], default="parity")
-    ap.add_argument("--config", choices=["c2", "c3", "c4"], default="c2",
+    ap.add_argument("--config", choices=["c2", "c3", "c4", "c5"], default="c2",
                     help="c2: the 1.1M-cell dead-oil five-spot (the headline); c3: the "
                          "2M-cell three-phase black-oil case (10 steps of 30 days); c4: the "
-                         "ensemble of 256 small realisations (30 steps of 15 days)")
+                         "ensemble of 256 small realisations (30 steps of 15 days); c5: the "
+                         "gradient of a production mismatch by the discrete adjoint (200k cells, "
+                         "20 steps of 30 days)")
+    ap.add_argument("--fd-cells", type=int, default=0,
+                    help="c5: also check the gradient by central differences on this many "
+                         "cells (drawn with seed 5, h = 1e-3 in ln k; two forward runs each)")
     ap.add_argument("--members", type=int, default=256, help="c4: realisations")
     ap.add_argument("--workers", type=int, default=16,
                     help="c4: realisations in flight at a time (host threads and streams)")
@@ -309,6 +414,9 @@ def main():
 
     if args.config == "c4":
         ensemble_bench(args)
+        return
+    if args.config == "c5":
+        adjoint_bench(args)
         return
 
     import torch

@@ -225,8 +225,10 @@ int fim_step(fim_ctx *ctx, double dt_days, fim_step_report *rep);
  * From the current state, runs the nsteps steps of dt[nsteps] (days) as
  * fim_step does, keeping the state after every accepted sub-step on the
  * device, then the backward sweep over the sub-steps, each a transposed
- * Jacobian solve (FP64, block-Jacobi ILU(0) of J^T, or point-block Jacobi
- * when that is the context's preconditioner, relative residual 1e-12).
+ * Jacobian solve (FP64 FGMRES to a relative residual of 1e-12, with CPR for
+ * J^T: the pressure component restricted, the transposed pressure operator
+ * by the aggregation AMG, prolongation by the quasi-IMPES weights, then
+ * block-Jacobi ILU(0) of J^T).
  * grad[ncells] (host) receives dJ/dtheta.  On FIM_OK the state is the end
  * of the forward run.  FIM_NOT_CONVERGED: a forward step failed (the state
  * is the start state and grad is not written) or an adjoint solve did not

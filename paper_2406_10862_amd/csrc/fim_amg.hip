@@ -198,6 +198,77 @@ __global__ __launch_bounds__(kBlock) void k_amg_extract(AmgLevel L, Grid g, Well
     }
 }
 
+// CPR for a transposed Jacobian (the adjoint systems).  With the forward
+// quasi-IMPES weights W (rows of J combined) and the pressure injection P_p,
+// the pressure operator of J is A_p = W^T J P_p; for J^T the first stage
+// restricts the pressure component, solves A_p^T = P_p^T J^T W and prolongs
+// with W.  From the blocks of J^T: A_p^T(c, c') = sum_i J^T(c, c')[0][i] w_i(c'),
+// i.e. the first row of every block weighted by its column cell's weights
+// (the BHP slot for a well column).  apT[q][u] = sum_i J^T_q[u][i] w_i(col q)
+// gives J^T x1 for x1 = W mu in the fused second stage.
+template <int NB>
+__global__ __launch_bounds__(kBlock) void k_cprT_weights(int n, Sys sysT, double *__restrict__ wq) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    const double *dT = sysT.val + (size_t)sysT.diagpos[c] * NB * NB;
+    double d[NB * NB], w[NB];
+#pragma unroll
+    for (int e = 0; e < NB; ++e)
+#pragma unroll
+        for (int u = 0; u < NB; ++u) d[e * NB + u] = dT[u * NB + e];   // J's diagonal block
+    qi_weights<NB>(d, w);
+#pragma unroll
+    for (int e = 0; e < NB; ++e) wq[(size_t)c * NB + e] = w[e];
+}
+
+template <int NB>
+__global__ __launch_bounds__(kBlock) void k_cprT_extract(AmgLevel L, Grid g, Wells wl, Sys sysT,
+                                                         const double *__restrict__ wq,
+                                                         double *__restrict__ ap) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = g.n;
+    if (t >= n + L.nw) return;
+    for (int q = sysT.rowptr[t]; q < sysT.rowptr[t + 1]; ++q) {
+        const int col = sysT.colind[q];
+        double w[NB];
+#pragma unroll
+        for (int e = 0; e < NB; ++e) w[e] = col < n ? wq[(size_t)col * NB + e] : (e == 0 ? 1.0 : 0.0);
+        const double *b = sysT.val + (size_t)q * NB * NB;
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            double a = 0.0;
+#pragma unroll
+            for (int e = 0; e < NB; ++e) a += b[u * NB + e] * w[e];
+            ap[(size_t)q * NB + u] = a;
+        }
+    }
+    auto coef = [&](int q) { return ap[(size_t)q * NB]; };
+    if (t < n) {
+        const int c = t, nx = g.nx, ny = g.ny, nxy = nx * ny;
+        const int i = c % nx, j = (c / nx) % ny, k = c / nxy;
+        const int s = split_of(L, i, j, k);
+        const int stride = 2 * L.half;
+        int q = sysT.rowptr[c];
+        double a[7];
+        a[5] = (k > 0) ? coef(q++) : 0.0;
+        a[3] = (j > 0) ? coef(q++) : 0.0;
+        a[1] = (i > 0) ? coef(q++) : 0.0;
+        a[0] = coef(q++);
+        a[2] = (i + 1 < nx) ? coef(q++) : 0.0;
+        a[4] = (j + 1 < ny) ? coef(q++) : 0.0;
+        a[6] = (k + 1 < g.nz) ? coef(q++) : 0.0;
+#pragma unroll
+        for (int d = 0; d < 7; ++d) L.a[(size_t)d * stride + s] = a[d];
+        for (int pp = wl.cps[c]; pp < wl.cps[c + 1]; ++pp) L.acw[wl.cperf[pp]] = coef(q++);
+    } else {
+        const int wi = t - n;
+        const int base = sysT.rowptr[n + wi];
+        const int p0 = L.sps[wi], np = L.sps[wi + 1] - p0;
+        for (int p = 0; p < np; ++p) L.awc[p0 + p] = coef(base + p);
+        L.aww[wi] = coef(base + np);
+    }
+}
+
 // Galerkin coarsening with piecewise-constant aggregates: couplings inside an
 // aggregate move to the coarse diagonal, couplings across an aggregate face
 // add up on the coarse stencil slot of that face.
@@ -792,6 +863,20 @@ static void extract_impl(hipStream_t s, int nb, const AmgLevel &L, Grid g, Wells
 void launch_amg_extract(hipStream_t s, int nb, const AmgLevel &L, Grid g, Wells w, Sys sys,
                         double *wq, double *ap) {
     extract_impl(s, nb, L, g, w, sys, wq, ap);
+}
+
+void launch_cprT_extract(hipStream_t s, int nb, const AmgLevel &L, Grid g, Wells w, Sys sysT,
+                         double *wq, double *ap) {
+    const long n = (long)g.n + L.nw;
+    if (nb == 2) {
+        hipLaunchKernelGGL(k_cprT_weights<2>, grid_for(g.n, kBlock), dim3(kBlock), 0, s, g.n, sysT, wq);
+        hipLaunchKernelGGL(k_cprT_extract<2>, grid_for(n, kBlock), dim3(kBlock), 0, s, L, g, w, sysT,
+                           wq, ap);
+    } else {
+        hipLaunchKernelGGL(k_cprT_weights<3>, grid_for(g.n, kBlock), dim3(kBlock), 0, s, g.n, sysT, wq);
+        hipLaunchKernelGGL(k_cprT_extract<3>, grid_for(n, kBlock), dim3(kBlock), 0, s, L, g, w, sysT,
+                           wq, ap);
+    }
 }
 
 void launch_amg_extract(hipStream_t s, int nb, const AmgLevel &L, Grid g, Wells w, Sys sys,

@@ -125,6 +125,10 @@ struct fim_ctx {
     std::vector<const int *> cfs_ptr, cfs_idx;     // coarse slot -> fine slots, per level
     double *Mden = nullptr, *Minv = nullptr, *colk = nullptr, *wq = nullptr;
     double *ap = nullptr;                           // [nnzb][nb] pressure column of A
+    // weights of the first CPR stage: restriction (null: the quasi-IMPES
+    // weights wq) and prolongation (null: the pressure slot)
+    const double *cpr_rw = nullptr, *cpr_pw = nullptr;
+    double *e0w = nullptr;                          // [n][nb] (1, 0, ..): the pressure component
     // block-Jacobi ILU(0): tiles, factors and the CPR second-stage scratch
     IluTiles ilu{};
     int ilu_dims[3] = {0, 0, 0};
@@ -1026,14 +1030,15 @@ template <class WT, class T>
 static void precondition(fim_ctx *c, const WT *w, const double *hptr, T *v, T *z) {
     constexpr bool same = std::is_same<WT, T>::value;
     if (c->opt.precond == FIM_PREC_CPR_ILU0) {
-        launch_cpr_restrict(c->s, c->nb, c->n, c->nw, c->lv[0], c->split0, w, hptr, v, c->wq);
+        launch_cpr_restrict(c->s, c->nb, c->n, c->nw, c->lv[0], c->split0, w, hptr, v,
+                            c->cpr_rw ? c->cpr_rw : c->wq);
         amg_cycle(c, 0);
         const T *rhs = v;
         if constexpr (same) {
             if (!v) rhs = w;
         }
         const IluRhs<T, T> R{rhs, Kry<T>::ap(c), c->colsplit, c->split0, c->lv[0].x,
-                             2 * c->lv[0].half};
+                             2 * c->lv[0].half, c->cpr_pw};
         launch_ilu_solve(c->s, c->nb, c->g, c->ilu, c->sys(), Kry<T>::lu(c), R, z);
     } else if (c->opt.precond == FIM_PREC_ILU0) {
         const T *rhs = v;
@@ -1490,7 +1495,22 @@ static void ensure_adjoint(fim_ctx *c) {
     c->grad = c->alloc<double>(c->n);
     c->objp = c->alloc<double>((size_t)std::max(c->nperf, 1) * (c->nb + 1));
     c->objw = c->alloc<double>(2 * std::max(c->nw, 1));
+    std::vector<double> e0((size_t)c->n * c->nb, 0.0);
+    for (int cell = 0; cell < c->n; ++cell) e0[(size_t)cell * c->nb] = 1.0;
+    c->e0w = c->upload(e0.data(), e0.size());
     c->sync();
+}
+
+// Preconditioner of J^T (held in c->val): ILU(0) of J^T in the boxes, and the
+// transposed CPR first stage (pressure component restricted, A_p^T by the
+// aggregation AMG, prolongation by the quasi-IMPES weights).
+static void adjoint_prec_setup(fim_ctx *c) {
+    launch_ilu_factor(c->s, c->nb, c->g, c->ilu, c->sys(), c->lu, c->ilu_bad);
+    launch_cprT_extract(c->s, c->nb, c->lv[0], c->g, c->wells(), c->sys(), c->wq, c->ap);
+    for (size_t l = 1; l < c->lv.size(); ++l)
+        launch_amg_coarsen(c->s, c->lv[l - 1], c->lv[l], c->cfs_ptr[l], c->cfs_idx[l]);
+    launch_amg_coarsest_setup(c->s, c->lv.back(), c->Mden, c->Minv, c->colk, c->amg_bad);
+    c->prec_ready = true;
 }
 
 // Forward: nsteps time steps of fim_step, keeping the state after every
@@ -1498,9 +1518,9 @@ static void ensure_adjoint(fim_ctx *c) {
 //   J_m^T lam_m = (1/dt_{m+1}) (dA(x_m)/dx_m)^T lam_{m+1} - (dJ/dx_m)^T
 // (the first term absent for m = M, the second only where a schedule step
 // ends), then grad += lam_m^T dR_m/dtheta (+ dJ/dtheta at schedule ends).
-// The transposed systems are solved by FGMRES with block-Jacobi ILU(0) of
-// J^T (point-block Jacobi when that is the context's preconditioner), in
-// FP64, to a relative residual of 1e-12.
+// The transposed systems are solved by FGMRES in FP64 to a relative
+// residual of 1e-12, preconditioned by CPR for J^T: the transposed pressure
+// stage, then block-Jacobi ILU(0) of J^T.
 static int adjoint_impl(fim_ctx *c, int nsteps, const double *dt, const double *qobs_h,
                         double *grad_h, fim_adjoint_report *rep) {
     using clock = std::chrono::steady_clock;
@@ -1551,11 +1571,13 @@ static int adjoint_impl(fim_ctx *c, int nsteps, const double *dt, const double *
     }
     if (nq) HIPCHECK(hipMemcpyAsync(c->qobs, qobs_h, nq * 8, hipMemcpyHostToDevice, c->s));
     HIPCHECK(hipMemsetAsync(c->grad, 0, c->n * sizeof(double), c->s));
-    // the transposed solves: FP64, no CPR (its pressure stage is built for J)
+    // the transposed solves: FP64, CPR for J^T with the ILU(0) second stage
     const fim_options saved = c->opt;
     const bool saved_mixed = c->mixed;
-    c->opt.precond = c->opt.precond == FIM_PREC_BJ ? FIM_PREC_BJ : FIM_PREC_ILU0;
+    c->opt.precond = FIM_PREC_CPR_ILU0;
     c->mixed = false;
+    c->cpr_rw = c->e0w;
+    c->cpr_pw = c->wq;
     c->drop_graphs();
     std::vector<double> jw((size_t)nsteps * 2 * std::max(c->nw, 1), 0.0);
     int status = FIM_OK;
@@ -1589,7 +1611,7 @@ static int adjoint_impl(fim_ctx *c, int nsteps, const double *dt, const double *
             double rr = 0.0;
             int gs = 0;
             try {
-                prec_setup(c);
+                adjoint_prec_setup(c);
                 gs = gmres_t<double>(c, c->arhs, lam, max_it, 1e-12, false, &li, &rr, nullptr);
             } catch (...) {
                 std::swap(c->val, c->valT);
@@ -1616,11 +1638,13 @@ static int adjoint_impl(fim_ctx *c, int nsteps, const double *dt, const double *
     } catch (...) {
         c->opt = saved;
         c->mixed = saved_mixed;
+        c->cpr_rw = c->cpr_pw = nullptr;
         c->drop_graphs();
         throw;
     }
     c->opt = saved;
     c->mixed = saved_mixed;
+    c->cpr_rw = c->cpr_pw = nullptr;
     c->drop_graphs();
     // leave the context at the end of the forward run
     get_ckpt(c, M);

@@ -292,10 +292,14 @@ __device__ inline void rhs_row(const RT &R, const Sys &sys, int r, double (&acc)
     }
 }
 
-template <class RT>
-__device__ inline double rhs_corr(const RT &R, int n, int r) {
+// the first-stage correction in component u of row r: the pressure slot,
+// or every component scaled by the prolongation weights pw of its cell
+template <int NB, class RT>
+__device__ inline double rhs_corr(const RT &R, int n, int r, int u) {
     if (!R.ap) return 0.0;
-    return r < n ? R.px[R.split0[r]] : R.px[R.nsplit + (r - n)];
+    const double mu = r < n ? R.px[R.split0[r]] : R.px[R.nsplit + (r - n)];
+    if (R.pw && r < n) return R.pw[(size_t)r * NB + u] * mu;
+    return u == 0 ? mu : 0.0;
 }
 
 // The tile's wells, between the forward and backward sweeps over its cells:
@@ -479,7 +483,7 @@ __global__ __launch_bounds__(256) void k_ilu_solve(Grid g, IluTiles T, Sys sys,
             rhs_row<NB>(R, sys, r, rhs);
             sub_mv<NB>(acc, lu + (size_t)sys.diagpos[r] * B2, rhs);
 #pragma unroll
-            for (int u = 0; u < NB; ++u) x[(size_t)r * NB + u] = (VT)(-acc[u] + (u == 0 ? rhs_corr(R, n, r) : 0.0));
+            for (int u = 0; u < NB; ++u) x[(size_t)r * NB + u] = (VT)(-acc[u] + rhs_corr<NB>(R, n, r, u));
         }
         return;
     }
@@ -564,7 +568,7 @@ __global__ __launch_bounds__(256) void k_ilu_solve(Grid g, IluTiles T, Sys sys,
         }
 #pragma unroll
         for (int u = 0; u < NB; ++u)
-            x[(size_t)r * NB + u] = (VT)(y[(size_t)l * NB + u] + (u == 0 ? rhs_corr(R, n, r) : 0.0));
+            x[(size_t)r * NB + u] = (VT)(y[(size_t)l * NB + u] + rhs_corr<NB>(R, n, r, u));
     }
 }
 

@@ -180,6 +180,8 @@ void launch_axpy_multi(hipStream_t s, long nvec, int k, const float *Z, const do
 constexpr int kCoarseMax = 64;       // cells of the level that is inverted densely
 void launch_amg_extract(hipStream_t s, int nb, const AmgLevel &L, Grid g, Wells w, Sys sys,
                         double *wq, double *ap);
+void launch_cprT_extract(hipStream_t s, int nb, const AmgLevel &L, Grid g, Wells w, Sys sysT,
+                         double *wq, double *ap);
 void launch_amg_extract(hipStream_t s, int nb, const AmgLevel &L, Grid g, Wells w, Sys sys,
                         double *wq, float *ap);
 void launch_amg_coarsen(hipStream_t s, const AmgLevel &F, const AmgLevel &C, const int *cfs_ptr,
@@ -234,6 +236,8 @@ struct IluRhs {
     const int *split0;          // [n] cell -> level-0 entry
     const double *px;           // level-0 iterate (cells, then wells)
     int nsplit;                 // 2*half of level 0 (first well entry)
+    const double *pw = nullptr; // [n][nb] prolongation weights of the correction, or null
+                                // (pressure slot only)
 };
 void launch_ilu_solve(hipStream_t s, int nb, Grid g, const IluTiles &T, Sys sys,
                       const double *lu, const IluRhs<double, double> &R, double *x);
