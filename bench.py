@@ -315,7 +315,7 @@ def adjoint_bench(args):
     fd = None
     if args.fd_cells > 0:
         cells = np.random.default_rng(5).choice(g.n, size=args.fd_cells, replace=False)
-        h = 1e-3
+        h = args.fd_h
         errs = []
         J0 = float(((oil_rates(res)[:, prod] - qobs[:, prod]) ** 2).sum())
         for c in cells:
@@ -378,9 +378,10 @@ def main():
                          "ensemble of 256 small realisations (30 steps of 15 days); c5: the "
                          "gradient of a production mismatch by the discrete adjoint (200k cells, "
                          "20 steps of 30 days)")
+    ap.add_argument("--fd-h", type=float, default=1e-3, help="c5: the central-difference step")
     ap.add_argument("--fd-cells", type=int, default=0,
                     help="c5: also check the gradient by central differences on this many "
-                         "cells (drawn with seed 5, h = 1e-3 in ln k; two forward runs each)")
+                         "cells (drawn with seed 5, step --fd-h in ln k; two forward runs each)")
     ap.add_argument("--members", type=int, default=256, help="c4: realisations")
     ap.add_argument("--workers", type=int, default=16,
                     help="c4: realisations in flight at a time (host threads and streams)")
