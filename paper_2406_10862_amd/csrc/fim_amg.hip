@@ -419,6 +419,80 @@ __global__ __launch_bounds__(1024) void k_dense_invert(int n, double *__restrict
     }
 }
 
+// The same Gauss-Jordan elimination with [A | A^-1] in LDS (n <= kDenseLds):
+// one wave finds the pivot with shuffles (largest magnitude, the smallest
+// row on ties, as above), the workgroup updates, three barriers per pivot.
+constexpr int kDenseLds = 96;
+size_t dense_lds_bytes(int n) { return ((size_t)2 * n * n + n) * sizeof(double); }
+
+__global__ __launch_bounds__(1024) void k_dense_invert_lds(int n, const double *__restrict__ Ag,
+                                                           double *__restrict__ Ainv, int *bad) {
+    extern __shared__ double sm[];
+    double *A = sm, *X = sm + (size_t)n * n, *colk = sm + (size_t)2 * n * n;
+    __shared__ int piv;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int e = tid; e < n * n; e += nt) {
+        A[e] = Ag[e];
+        X[e] = ((e / n) == (e % n)) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    for (int k = 0; k < n; ++k) {
+        if (tid < 64) {
+            double best = -1.0;
+            int bidx = k;
+            for (int r = k + tid; r < n; r += 64) {
+                const double v = fabs(A[(size_t)r * n + k]);
+                if (v > best) {
+                    best = v;
+                    bidx = r;
+                }
+            }
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) {
+                const double ob = __shfl_xor(best, off, 64);
+                const int oi = __shfl_xor(bidx, off, 64);
+                if (ob > best || (ob == best && oi < bidx)) {
+                    best = ob;
+                    bidx = oi;
+                }
+            }
+            if (tid == 0) {
+                piv = bidx;
+                if (!(best > 0.0)) *bad = 1;
+            }
+        }
+        __syncthreads();
+        const int p = piv;
+        const double dk = A[(size_t)p * n + k];           // the pivot, before any write
+        const double rdk = (dk != 0.0) ? 1.0 / dk : 0.0;
+        // the pivot column after the swap of rows k and p, read before it changes
+        for (int r = tid; r < n; r += nt) colk[r] = A[(size_t)((r == p) ? k : r) * n + k];
+        __syncthreads();
+        // row k <- row p scaled, row p <- old row k
+        for (int c = tid; c < n; c += nt) {
+            const double ak = A[(size_t)k * n + c], xk = X[(size_t)k * n + c];
+            const double ap = A[(size_t)p * n + c], xp = X[(size_t)p * n + c];
+            A[(size_t)k * n + c] = ap * rdk;
+            X[(size_t)k * n + c] = xp * rdk;
+            if (p != k) {
+                A[(size_t)p * n + c] = ak;
+                X[(size_t)p * n + c] = xk;
+            }
+        }
+        __syncthreads();
+        for (int e = tid; e < n * n; e += nt) {
+            const int r = e / n, c = e % n;
+            if (r == k) continue;
+            const double f = colk[r];
+            if (f == 0.0) continue;
+            A[e] -= f * A[(size_t)k * n + c];
+            X[e] -= f * X[(size_t)k * n + c];
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < n * n; e += nt) Ainv[e] = X[e];
+}
+
 // x[row] = (Minv b)[row] by the 64 lanes of one wave
 __device__ inline void dense_row(int n, const double *__restrict__ M, const double *b, double *x,
                                  int row, int lane) {
@@ -696,29 +770,31 @@ __device__ __forceinline__ void subcycle_phase(int op, const AmgLevel &F, const 
 __global__ __launch_bounds__(kSubThreads) void k_amg_subcycle(AmgSub P) {
     extern __shared__ double lds[];
     int *ldi = reinterpret_cast<int *>(lds + P.ldoubles);
-    const int tid = threadIdx.x, nt = blockDim.x;
-    // padded entries of the coarse right-hand sides are never restricted
-    // to but are read by the dense solve: start from zeros as in HBM
-    for (int k = 0; k < P.nlev; ++k) {
-        const AmgLevel &L = P.lv[k];
-        const int n = 2 * L.half + L.nw;
-        for (int e = tid; e < n; e += nt) lds[P.off[k][kSubB] + e] = (k == 0) ? L.b[e] : 0.0;
-        if (P.off[k][kSubA] >= 0) lds_copy(lds + P.off[k][kSubA], L.a, 14 * L.half);
-        lds_copy(lds + P.off[k][kSubAcw], L.acw, L.nslot);
-        lds_copy(lds + P.off[k][kSubAwc], L.awc, L.nslot);
-        lds_copy(ldi + P.off[k][kSubCps], L.cps, 2 * L.half + 1);
-        lds_copy(ldi + P.off[k][kSubCslot], L.cslot, L.nslot);
-        lds_copy(ldi + P.off[k][kSubSwell], L.swell, L.nslot);
-        lds_copy(ldi + P.off[k][kSubScell], L.scell, L.nslot);
-        lds_copy(ldi + P.off[k][kSubSps], L.sps, L.nw + 1);
+    const int tid = threadIdx.x;
+    // Stage the image: the levels' iterates, right-hand sides (the root's
+    // written there by the launch before, padded entries zero), well-slot
+    // structure, the stencils and dense inverse that fit and the phase list
+    // live in HBM laid out as here.  Every thread issues all its loads
+    // before its first store.
+    {
+        constexpr int U = 8;
+        uint4 *l16 = reinterpret_cast<uint4 *>(lds);
+        const int nt = blockDim.x;
+        for (int base = 0; base < P.img_n16; base += U * nt) {
+            uint4 v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = base + u * nt + tid;
+                v[u] = P.img[e < P.img_n16 ? e : 0];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = base + u * nt + tid;
+                if (e < P.img_n16) l16[e] = v[u];
+            }
+        }
     }
-    if (P.minvoff >= 0) {
-        const AmgLevel &L = P.lv[P.nlev - 1];
-        const int n = 2 * L.half + L.nw;
-        lds_copy(lds + P.minvoff, P.Minv, n * n);
-    }
-    int *ops = ldi + P.opsoff;
-    lds_copy(ops, P.ops, P.nops);
+    const int *ops = ldi + P.opsoff;
     __syncthreads();
     auto level = [&](int k) {
         AmgLevel L = P.lv[k];
@@ -751,7 +827,7 @@ __global__ __launch_bounds__(kSubThreads) void k_amg_subcycle(AmgSub P) {
         __syncthreads();
     }
     const AmgLevel &R = P.lv[0];
-    for (int e = tid; e < 2 * R.half + R.nw; e += nt) R.x[e] = lds[P.off[0][kSubX] + e];
+    for (int e = tid; e < 2 * R.half + R.nw; e += blockDim.x) R.x[e] = lds[P.off[0][kSubX] + e];
 }
 
 // ---------------------------------------------------------------------------
@@ -894,7 +970,17 @@ void launch_amg_coarsest_setup(hipStream_t s, const AmgLevel &L, double *M, doub
                                double *colk, int *bad) {
     const int n = 2 * L.half + L.nw;
     hipLaunchKernelGGL(k_amg_dense, grid_for(n, 64), dim3(64), 0, s, L, M);
-    hipLaunchKernelGGL(k_dense_invert, dim3(1), dim3(1024), 0, s, n, M, Minv, colk, bad);
+    if (n <= kDenseLds)
+        hipLaunchKernelGGL(k_dense_invert_lds, dim3(1), dim3(1024), dense_lds_bytes(n), s, n, M, Minv,
+                           bad);
+    else
+        hipLaunchKernelGGL(k_dense_invert, dim3(1), dim3(1024), 0, s, n, M, Minv, colk, bad);
+}
+
+hipError_t dense_allow_lds() {
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_dense_invert_lds),
+                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)dense_lds_bytes(kDenseLds));
 }
 
 void launch_amg_coarsest_solve(hipStream_t s, const AmgLevel &L, const double *Minv) {
@@ -921,8 +1007,10 @@ void launch_amg_restrict(hipStream_t s, const AmgLevel &F, const AmgLevel &C) {
                        s, F, C);
 }
 
+// rounded up to whole 16-byte units: the prologue stages the image in those
 size_t amg_subcycle_lds(const AmgSub &P) {
-    return (size_t)P.ldoubles * sizeof(double) + ((size_t)P.opsoff + P.nops) * sizeof(int);
+    const size_t b = (size_t)P.ldoubles * sizeof(double) + ((size_t)P.opsoff + P.nops) * sizeof(int);
+    return (b + 15) & ~(size_t)15;
 }
 
 hipError_t amg_subcycle_allow_lds(size_t bytes) {

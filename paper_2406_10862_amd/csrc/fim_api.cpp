@@ -417,6 +417,7 @@ static void build_amg(fim_ctx *c, const std::vector<int> &sorted_cells,
     c->Minv = c->alloc<double>(n * n);
     c->colk = c->alloc<double>(n);
     c->amg_bad = c->alloc<int>(1);
+    HIPCHECK(dense_allow_lds());                // the same value for every context
     c->wq = c->alloc<double>((size_t)c->n * c->nb);
     c->ap = c->alloc<double>((size_t)c->nnzb * c->nb);
 }
@@ -871,12 +872,58 @@ static void build_subcycle(fim_ctx *c) {
     if (!c->sub_ops) c->sub_ops = c->alloc<int>(kSubOps);
     HIPCHECK(hipMemcpyAsync(c->sub_ops, ops.data(), ops.size() * sizeof(int),
                             hipMemcpyHostToDevice, c->s));
+    // The LDS image in HBM: the arrays of the sub-cycle's levels move into
+    // one buffer laid out as the launch's LDS, and every kernel reads and
+    // writes them there (the launch before writes the root's right-hand
+    // side in place), so a launch stages them with one flat copy.  An
+    // earlier image stays allocated: levels outside this one may still point
+    // into it.
+    const size_t bytes = amg_subcycle_lds(sub);
+    char *img = c->alloc<char>(bytes);
+    HIPCHECK(hipMemsetAsync(img, 0, bytes, c->s));
+    double *imd = reinterpret_cast<double *>(img);
+    int *imi = reinterpret_cast<int *>(imd + sub.ldoubles);
+    auto move_d = [&](double *&p, int off, long count) {
+        if (count > 0)
+            HIPCHECK(hipMemcpyAsync(imd + off, p, count * 8, hipMemcpyDeviceToDevice, c->s));
+        p = imd + off;
+    };
+    auto move_i = [&](const int *&p, int off, long count) {
+        if (count > 0)
+            HIPCHECK(hipMemcpyAsync(imi + off, p, count * 4, hipMemcpyDeviceToDevice, c->s));
+        p = imi + off;
+    };
+    for (int k = 0; k < sub.nlev; ++k) {
+        AmgLevel &Lk = c->lv[root + k];
+        const int *o = sub.off[k];
+        const long n = 2L * Lk.half + Lk.nw;
+        move_d(Lk.x, o[kSubX], n);
+        move_d(Lk.b, o[kSubB], n);
+        move_d(Lk.acw, o[kSubAcw], Lk.nslot);
+        move_d(Lk.awc, o[kSubAwc], Lk.nslot);
+        if (o[kSubA] >= 0) move_d(Lk.a, o[kSubA], 14L * Lk.half);
+        move_i(Lk.cps, o[kSubCps], 2L * Lk.half + 1);
+        move_i(Lk.cslot, o[kSubCslot], Lk.nslot);
+        move_i(Lk.swell, o[kSubSwell], Lk.nslot);
+        move_i(Lk.scell, o[kSubScell], Lk.nslot);
+        move_i(Lk.sps, o[kSubSps], Lk.nw + 1);
+        sub.lv[k] = Lk;
+    }
+    if (sub.minvoff >= 0) {
+        const AmgLevel &Lc = c->lv[L - 1];
+        const long nc = 2L * Lc.half + Lc.nw;
+        move_d(c->Minv, sub.minvoff, nc * nc);
+    }
+    HIPCHECK(hipMemcpyAsync(imi + sub.opsoff, ops.data(), ops.size() * sizeof(int),
+                            hipMemcpyHostToDevice, c->s));
     c->sync();
     // the device's limit rather than this context's need: every context sets
     // the same value, so none lowers the limit another one launches under
     HIPCHECK(amg_subcycle_allow_lds((size_t)lds_max));
     sub.ops = c->sub_ops;
     sub.Minv = c->Minv;
+    sub.img = reinterpret_cast<const uint4 *>(img);
+    sub.img_n16 = (int)(bytes / 16);
     c->sub = sub;
     c->sub_root = root;
 }

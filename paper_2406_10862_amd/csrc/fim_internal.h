@@ -277,9 +277,12 @@ struct AmgSub {
     int nops;
     const double *Minv;                // dense inverse of the coarsest level
     int minvoff;                       // its LDS offset (doubles), -1 = read from HBM
+    const uint4 *img;                  // the LDS image in HBM (the levels' arrays live in it)
+    int img_n16;                       // its size in 16-byte units
 };
 size_t amg_subcycle_lds(const AmgSub &P);          // dynamic LDS bytes of one launch
 hipError_t amg_subcycle_allow_lds(size_t bytes);
+hipError_t dense_allow_lds();                      // LDS of the coarsest-level inverse
 void launch_amg_subcycle(hipStream_t s, const AmgSub &P);
 
 }  // namespace fim

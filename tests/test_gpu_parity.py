@@ -756,3 +756,18 @@ def test_adjoint_in_a_mixed_precision_context_matches_oracle():
     rc, grad, rep = g.fim_adjoint_gradient(dts, qobs)
     assert rc == fim.FIM_OK
     assert np.abs(grad - go).max() <= 1e-8 * np.abs(go).max()
+
+
+def test_steps_match_oracle_with_a_large_coarsest_level():
+    """90 single-column producers make the coarsest AMG level (cells plus
+    wells) larger than the LDS inverse takes: its dense inverse runs in HBM."""
+    res = rv.config_c2_small(12, 14, 3, nsteps=2)
+    # 3x4x1 cells at the coarsest level (16 entries with the padding) + 95 wells
+    cols = [(i, j) for j in range(1, 13) for i in range(1, 11) if (i, j) != (5, 6)][:90]
+    for (i, j) in cols:
+        res.wells.append(rv.Well(rv.PROD, rv.BHP, 5000.0,
+                                 rv.column_cells(res.nx, res.ny, res.nz, i, j)))
+    g, o, errs = run_parity_steps(res, 2, options=rv.Options(tile=(6, 7, 3)))
+    worst = {k: max(e[k] for e in errs) for k in errs[0]}
+    assert len(res.wells) > 90
+    assert all(v <= STATE_TOL for v in worst.values()), worst
