@@ -515,28 +515,39 @@ __global__ __launch_bounds__(256) void k_dense_gemv(int n, const double *__restr
 // ---------------------------------------------------------------------------
 // cycle kernels
 
+// Value of neighbour d of p (ns its split index), or of p itself when the
+// neighbour is outside the grid (in = false): the stencil coefficient of a
+// missing neighbour is zero on every level, so the stencil loops multiply
+// by it without a branch and their loads need no wait in between.
+// M: the read mode as a constant (the sweeps' modes are fixed per launch or
+// phase), or -1 to take it from mode.
+template <int M>
 __device__ inline double read_cell(const AmgLevel &L, const AmgLevel &C, int mode, int ns,
-                                   const Pos &p, int d) {
-    if (mode & kCellsZero) return 0.0;
+                                   const Pos &p, int d, bool in) {
+    const int m = M >= 0 ? M : mode;
+    if (m & kCellsZero) return 0.0;
     double v = L.x[ns];
-    if (mode & kCellsCorr) {
-        int ni, nj, nk;
-        nbr_ijk(p, d, ni, nj, nk);
+    if (m & kCellsCorr) {
+        int ni = p.i, nj = p.j, nk = p.k;
+        if (in) nbr_ijk(p, d, ni, nj, nk);
         v += C.x[split_of(C, ni >> 1, nj >> 1, nk >> 1)];
     }
     return v;
 }
 
+template <int M>
 __device__ inline double read_well(const AmgLevel &L, const AmgLevel &C, int mode, int w) {
-    if (mode & kWellsZero) return 0.0;
+    const int m = M >= 0 ? M : mode;
+    if (m & kWellsZero) return 0.0;
     double v = L.x[2 * L.half + w];
-    if (mode & kWellsCorr) v += C.x[2 * C.half + w];
+    if (m & kWellsCorr) v += C.x[2 * C.half + w];
     return v;
 }
 
 // Gauss-Seidel value of cell h of one colour (cells of one colour are not
 // coupled to each other, so a colour sweep is exact and order-free);
 // padded cells get 0.
+template <int M>
 __device__ inline double sweep_value(const AmgLevel &L, const AmgLevel &C, int color, int mode,
                                      int h) {
     const int s = color * L.half + h;
@@ -547,18 +558,20 @@ __device__ inline double sweep_value(const AmgLevel &L, const AmgLevel &C, int c
 #pragma unroll
     for (int d = 1; d < 7; ++d) {
         int ns;
-        if (nbr(L, p, d, ns)) acc -= L.a[(size_t)d * stride + s] * read_cell(L, C, mode, ns, p, d);
+        const bool in = nbr(L, p, d, ns);
+        acc -= L.a[(size_t)d * stride + s] * read_cell<M>(L, C, mode, in ? ns : s, p, d, in);
     }
     for (int q = L.cps[s]; q < L.cps[s + 1]; ++q) {
         const int sl = L.cslot[q];
-        acc -= L.acw[sl] * read_well(L, C, mode, L.swell[sl]);
+        acc -= L.acw[sl] * read_well<M>(L, C, mode, L.swell[sl]);
     }
     return acc / L.a[s];
 }
 
+template <int M>
 __device__ inline void sweep_item(const AmgLevel &L, const AmgLevel &C, int color, int mode,
                                   int h) {
-    L.x[color * L.half + h] = sweep_value(L, C, color, mode, h);
+    L.x[color * L.half + h] = sweep_value<M>(L, C, color, mode, h);
 }
 
 // The first pre-smoothing pair from a zero iterate (wells still zero) in
@@ -579,7 +592,8 @@ __device__ inline void presmooth_item(const AmgLevel &L, int h) {
 #pragma unroll
     for (int d = 1; d < 7; ++d) {
         int ns;
-        if (nbr(L, p, d, ns)) acc -= L.a[(size_t)d * stride + s] * red_from_zero(L, ns);
+        const bool in = nbr(L, p, d, ns);
+        acc -= L.a[(size_t)d * stride + s] * red_from_zero(L, in ? ns : s);
     }
     for (int q = L.cps[s]; q < L.cps[s + 1]; ++q) acc -= L.acw[L.cslot[q]] * 0.0;
     L.x[s] = acc / L.a[s];
@@ -590,10 +604,11 @@ __global__ __launch_bounds__(kBlock) void k_amg_presmooth(AmgLevel L) {
     if (h < L.half) presmooth_item(L, h);
 }
 
+template <int M>
 __global__ __launch_bounds__(kBlock) void k_amg_sweep(AmgLevel L, AmgLevel C, int color,
                                                       int mode) {
     const int h = blockIdx.x * blockDim.x + threadIdx.x;
-    if (h < L.half) sweep_item(L, C, color, mode, h);
+    if (h < L.half) sweep_item<M>(L, C, color, mode, h);
 }
 
 // wells: one wave per well, lanes stride over its slots
@@ -621,7 +636,8 @@ __device__ inline double cell_residual(const AmgLevel &L, int s, const Pos &p) {
 #pragma unroll
     for (int d = 1; d < 7; ++d) {
         int ns;
-        if (nbr(L, p, d, ns)) r -= L.a[(size_t)d * stride + s] * L.x[ns];
+        const bool in = nbr(L, p, d, ns);
+        r -= L.a[(size_t)d * stride + s] * L.x[in ? ns : s];
     }
     for (int q = L.cps[s]; q < L.cps[s + 1]; ++q) {
         const int sl = L.cslot[q];
@@ -724,6 +740,21 @@ __device__ inline void lds_copy(T *dst, const T *src, int n) {
     for (int e = threadIdx.x; e < n; e += blockDim.x) dst[e] = src[e];
 }
 
+// a colour sweep by the whole workgroup, two entries per thread at a time
+// so their loads overlap
+template <int M>
+__device__ __forceinline__ void sweep_phase(const AmgLevel &F, const AmgLevel &C, int color,
+                                            int mode) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int h = tid; h < F.half; h += 2 * nt) {
+        const int h2 = h + nt;
+        const double v1 = sweep_value<M>(F, C, color, mode, h);
+        const double v2 = (h2 < F.half) ? sweep_value<M>(F, C, color, mode, h2) : 0.0;
+        F.x[color * F.half + h] = v1;
+        if (h2 < F.half) F.x[color * F.half + h2] = v2;
+    }
+}
+
 // One phase of the sub-cycle on level F (coarser neighbour C) by the whole
 // workgroup.  Inlined once with the coefficients of F in LDS and once with
 // them in HBM, so every access has a known address space.
@@ -736,13 +767,11 @@ __device__ __forceinline__ void subcycle_phase(int op, const AmgLevel &F, const 
         for (int h = tid; h < F.half; h += nt) presmooth_item(F, h);
     } else if (kind == kOpSweep) {
         const int color = (op >> 8) & 1, mode = (op >> 12) & 15;
-        // two entries per thread at a time so their loads overlap
-        for (int h = tid; h < F.half; h += 2 * nt) {
-            const int h2 = h + nt;
-            const double v1 = sweep_value(F, C, color, mode, h);
-            const double v2 = (h2 < F.half) ? sweep_value(F, C, color, mode, h2) : 0.0;
-            F.x[color * F.half + h] = v1;
-            if (h2 < F.half) F.x[color * F.half + h2] = v2;
+        switch (mode) {
+            case 0: sweep_phase<0>(F, C, color, mode); break;
+            case kWellsCorr: sweep_phase<kWellsCorr>(F, C, color, mode); break;
+            case kCellsCorr | kWellsCorr: sweep_phase<kCellsCorr | kWellsCorr>(F, C, color, mode); break;
+            default: sweep_phase<-1>(F, C, color, mode);
         }
     } else if (kind == kOpWells) {
         for (int w = wave; w < F.nw; w += nwaves) well_sweep_item(F, w, lane);
@@ -989,7 +1018,21 @@ void launch_amg_coarsest_solve(hipStream_t s, const AmgLevel &L, const double *M
 }
 
 void launch_amg_sweep(hipStream_t s, const AmgLevel &L, const AmgLevel &C, int color, int mode) {
-    hipLaunchKernelGGL(k_amg_sweep, grid_for(L.half, kBlock), dim3(kBlock), 0, s, L, C, color, mode);
+    const dim3 grid = grid_for(L.half, kBlock), block(kBlock);
+    switch (mode) {
+        case 0:
+            hipLaunchKernelGGL(k_amg_sweep<0>, grid, block, 0, s, L, C, color, mode);
+            break;
+        case kWellsCorr:
+            hipLaunchKernelGGL(k_amg_sweep<kWellsCorr>, grid, block, 0, s, L, C, color, mode);
+            break;
+        case kCellsCorr | kWellsCorr:
+            hipLaunchKernelGGL(k_amg_sweep<kCellsCorr | kWellsCorr>, grid, block, 0, s, L, C,
+                               color, mode);
+            break;
+        default:
+            hipLaunchKernelGGL(k_amg_sweep<-1>, grid, block, 0, s, L, C, color, mode);
+    }
 }
 
 void launch_amg_presmooth(hipStream_t s, const AmgLevel &L) {
