@@ -759,7 +759,7 @@ __device__ __forceinline__ void sweep_phase(const AmgLevel &F, const AmgLevel &C
 // workgroup.  Inlined once with the coefficients of F in LDS and once with
 // them in HBM, so every access has a known address space.
 __device__ __forceinline__ void subcycle_phase(int op, const AmgLevel &F, const AmgLevel &C,
-                                               const double *Minv) {
+                                               const double *Minv, double *rbuf) {
     const int tid = threadIdx.x, nt = blockDim.x;
     const int wave = tid >> 6, lane = tid & 63, nwaves = nt >> 6;
     const int kind = op & 15;
@@ -776,16 +776,35 @@ __device__ __forceinline__ void subcycle_phase(int op, const AmgLevel &F, const 
     } else if (kind == kOpWells) {
         for (int w = wave; w < F.nw; w += nwaves) well_sweep_item(F, w, lane);
     } else if (kind == kOpRestrict) {
-        // two rounds of children per pass so their loads overlap; the trip
-        // count is uniform over the workgroup (shuffles inside)
-        const int n8 = 8 * C.nx * C.ny * C.nz;
-        for (int base = 0; base < n8; base += 2 * nt) {
-            const int t1 = base + tid, t2 = t1 + nt;
-            int h1, h2;
-            const double r1 = restrict_child(F, C, t1 >> 3, t1 & 7, t1 < n8, h1);
-            const double r2 = restrict_child(F, C, t2 >> 3, t2 & 7, t2 < n8, h2);
-            restrict_sum(C, t1 >> 3, t1 & 7, t1 < n8, r1, h1);
-            restrict_sum(C, t2 >> 3, t2 & 7, t2 < n8, r2, h2);
+        // The fine residuals in split order first (the stencil loads of a
+        // wave are then contiguous; by aggregate every child's loads fall
+        // on lines of their own), into rbuf; then every coarse cell sums
+        // its children from there in the (k, j, i) order of the per-level
+        // launch, so the sums are the same bit for bit.
+        for (int s = tid; s < 2 * F.half; s += 2 * nt) {
+            const int s2 = s + nt;
+            const Pos p1 = pos_of(F, s);
+            const double r1 = p1.i >= F.nx ? 0.0 : cell_residual(F, s, p1);
+            double r2 = 0.0;
+            if (s2 < 2 * F.half) {
+                const Pos p2 = pos_of(F, s2);
+                r2 = p2.i >= F.nx ? 0.0 : cell_residual(F, s2, p2);
+            }
+            rbuf[s] = r1;
+            if (s2 < 2 * F.half) rbuf[s2] = r2;
+        }
+        __syncthreads();
+        const int nc = C.nx * C.ny * C.nz;
+        for (int t = tid; t < nc; t += nt) {
+            const int JK = fdiv(t, C.mnx), I = t - JK * C.nx;
+            const int K = fdiv(JK, C.mny), J = JK - K * C.ny;
+            double sum = 0.0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int i = 2 * I + (q & 1), j = 2 * J + ((q >> 1) & 1), k = 2 * K + (q >> 2);
+                if (i < F.nx && j < F.ny && k < F.nz) sum += rbuf[split_pos(F, pos_at(F, i, j, k))];
+            }
+            C.b[split_of(C, I, J, K)] = sum;
         }
         for (int w = wave; w < F.nw; w += nwaves) restrict_well(F, C, w, lane);
     } else if (kind == kOpCorrect) {
@@ -824,6 +843,7 @@ __global__ __launch_bounds__(kSubThreads) void k_amg_subcycle(AmgSub P) {
         }
     }
     const int *ops = ldi + P.opsoff;
+    double *rbuf = lds + P.rbufoff;                  // fine residuals of a restriction
     __syncthreads();
     auto level = [&](int k) {
         AmgLevel L = P.lv[k];
@@ -844,14 +864,14 @@ __global__ __launch_bounds__(kSubThreads) void k_amg_subcycle(AmgSub P) {
         const AmgLevel C = level(l + 1);
         if ((op & 15) == kOpCoarse) {
             const AmgLevel F = level(l);
-            if (P.minvoff >= 0) subcycle_phase(op, F, C, lds + P.minvoff);
-            else subcycle_phase(op, F, C, P.Minv);
+            if (P.minvoff >= 0) subcycle_phase(op, F, C, lds + P.minvoff, rbuf);
+            else subcycle_phase(op, F, C, P.Minv, rbuf);
         } else if (P.off[l][kSubA] >= 0) {
             AmgLevel F = level(l);
             F.a = lds + P.off[l][kSubA];
-            subcycle_phase(op, F, C, P.Minv);
+            subcycle_phase(op, F, C, P.Minv, rbuf);
         } else {
-            subcycle_phase(op, level(l), C, P.Minv);
+            subcycle_phase(op, level(l), C, P.Minv, rbuf);
         }
         __syncthreads();
     }

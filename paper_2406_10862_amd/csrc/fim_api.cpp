@@ -841,6 +841,8 @@ static void build_subcycle(fim_ctx *c) {
             o[kSubSps] = o[kSubScell] + Lk.nslot;
             ni += 2L * Lk.half + 1 + 3L * Lk.nslot + Lk.nw + 1;
         }
+        sub.rbufoff = (int)nd;                   // the root's 2*half fine residuals
+        nd += 2L * sub.lv[0].half;
         sub.ldoubles = (int)nd;
         sub.opsoff = (int)ni;
         sub.nops = (int)ops.size();

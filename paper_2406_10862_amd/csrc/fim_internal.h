@@ -277,6 +277,7 @@ struct AmgSub {
     int nops;
     const double *Minv;                // dense inverse of the coarsest level
     int minvoff;                       // its LDS offset (doubles), -1 = read from HBM
+    int rbufoff;                       // LDS offset (doubles) of the restriction's scratch
     const uint4 *img;                  // the LDS image in HBM (the levels' arrays live in it)
     int img_n16;                       // its size in 16-byte units
 };
