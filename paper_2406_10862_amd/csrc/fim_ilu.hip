@@ -274,17 +274,26 @@ __device__ inline void rhs_row(const RT &R, const Sys &sys, int r, double (&acc)
     if (q0 < 0) q0 = sys.rowptr[r];
     const int q1 = sys.rowptr[r + 1];
     constexpr int K = 8;
+    // a slot past the row's end loads the row's last block (every row has
+    // one) and is dropped by a select: no branch between the loads
     int cs[K];
+    double a[K][NB];
 #pragma unroll
-    for (int k = 0; k < K; ++k) cs[k] = (q0 + k < q1) ? R.colsplit[q0 + k] : -1;
+    for (int k = 0; k < K; ++k) {
+        const int q = min(q0 + k, q1 - 1);
+        cs[k] = R.colsplit[q];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) a[k][u] = (double)R.ap[(size_t)q * NB + u];
+    }
     double p[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) p[k] = cs[k] >= 0 ? R.px[cs[k]] : 0.0;
+    for (int k = 0; k < K; ++k) p[k] = R.px[cs[k]];
 #pragma unroll
-    for (int k = 0; k < K; ++k)
-        if (cs[k] >= 0)
+    for (int k = 0; k < K; ++k) {
+        const bool on = q0 + k < q1;
 #pragma unroll
-            for (int u = 0; u < NB; ++u) acc[u] -= (double)R.ap[(size_t)(q0 + k) * NB + u] * p[k];
+        for (int u = 0; u < NB; ++u) acc[u] -= (on ? a[k][u] : 0.0) * (on ? p[k] : 0.0);
+    }
     for (int q = q0 + K; q < q1; ++q) {
         const double pq = R.px[R.colsplit[q]];
 #pragma unroll
