@@ -388,7 +388,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cycle", type=int, default=0,
                     help="AMG cycle: 0 V at the finest level and W below, 1 V, 2 W, >=16 W on "
-                         "levels of at most that many cells")
+                         "levels of at most that many cells, <=-16 V at the finest level and on "
+                         "levels of at most -value cells, W between")
     ap.add_argument("--precond", default="cpr_ilu0", choices=["bj", "ilu0", "cpr", "cpr_ilu0"])
     ap.add_argument("--tile", default="0,0,0", help="block-Jacobi ILU(0) box, e.g. 4,4,16")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
@@ -524,7 +525,9 @@ def main():
                         2: "CPR (quasi-IMPES + aggregation AMG) + block-Jacobi",
                         3: f"CPR (quasi-IMPES + aggregation AMG) + block-Jacobi ILU(0), boxes {box}"}[opts.precond],
             "amg_cycle": {0: "V at the finest level, W below", 1: "V", 2: "W"}.get(
-                opts.amg_cycle, f"W on levels <= {opts.amg_cycle} cells, V above"),
+                opts.amg_cycle, f"W on levels <= {opts.amg_cycle} cells, V above"
+                if opts.amg_cycle > 0 else
+                f"V at the finest level and on levels <= {-opts.amg_cycle} cells, W between"),
             "gmres_restart": opts.restart,
             "newton_iters": newton, "linear_iters": linear, "cuts": cuts,
             "linear_per_newton": linear / newton if newton else None,

@@ -137,7 +137,9 @@ typedef struct {
  * (FIM_PREC_ILU0) or by CPR (FIM_PREC_CPR, FIM_PREC_CPR_ILU0): a quasi-IMPES pressure
  * stage solved by one aggregation-AMG cycle (amg_cycle 1 = V, 2 = W, 0 =
  * default: V at the finest level and W below it, a value >= 16 = W on the
- * levels with at most that many cells and wells and V above them; amg_sweeps red-black Gauss-Seidel sweeps before and after the
+ * levels with at most that many cells and wells and V above them, a value
+ * <= -16 = V at the finest level and on the levels with at most -amg_cycle
+ * cells and wells, W on the others; amg_sweeps red-black Gauss-Seidel sweeps before and after the
  * coarse correction, 0 = default 1) followed by block Jacobi on the
  * remaining residual (FIM_PREC_CPR_ILU0: block-Jacobi ILU(0) on it).
  * Block-Jacobi ILU(0) (paper Sec. 5.1): the subdomains are boxes of

@@ -134,6 +134,7 @@ struct fim_ctx {
     int ilu_dims[3] = {0, 0, 0};
     std::vector<int> perf_cell_h;                   // perforated cell of each perforation
     double *lu = nullptr;
+    size_t lu_elems = 0, lu32_elems = 0;            // allocated elements of lu, lu32
     // mixed precision: single-precision copies for the inner solves
     bool mixed = false;
     int m32 = 0;
@@ -250,8 +251,8 @@ static void check_options(const fim_options *o) {
     REQUIRE(o->precond >= FIM_PREC_BJ && o->precond <= FIM_PREC_CPR_ILU0,
             "unknown preconditioner %d", o->precond);
     REQUIRE(o->tile_nx >= 0 && o->tile_ny >= 0 && o->tile_nz >= 0, "tile sizes must be >= 0");
-    REQUIRE(o->amg_cycle >= 0 && (o->amg_cycle <= 2 || o->amg_cycle >= 16),
-            "amg_cycle must be 0, 1, 2 or a level size >= 16");
+    REQUIRE((o->amg_cycle >= 0 && o->amg_cycle <= 2) || o->amg_cycle >= 16 || o->amg_cycle <= -16,
+            "amg_cycle must be 0, 1, 2 or a level size >= 16 or <= -16");
     REQUIRE(o->amg_sweeps >= 0 && o->amg_sweeps <= 8, "amg_sweeps must be in [0, 8]");
     REQUIRE(o->graphs == 0 || o->graphs == 1, "graphs must be 0 or 1");
     REQUIRE(o->forcing == 0 || o->forcing == 1, "forcing must be 0 or 1");
@@ -762,6 +763,7 @@ static void amg_cycle(fim_ctx *c, int l, std::vector<int> *rec = nullptr, int ro
     const int cyc = c->opt.amg_cycle;
     int gamma = (cyc == 1 || (cyc == 0 && l == 0)) ? 1 : 2;
     if (cyc >= 16 && 2L * F.half + F.nw > cyc) gamma = 1;   // V above the size limit
+    if (cyc <= -16) gamma = (l > 0 && 2L * F.half + F.nw > -(long)cyc) ? 2 : 1;  // V at and below
     if (l + 1 == L - 1) gamma = 1;             // the coarsest level is solved exactly
     auto sweep = [&](int color, int mode) {
         if (rec) rec->push_back(amg_op(kOpSweep, rl, color, mode));
@@ -982,6 +984,11 @@ static void build_ilu(fim_ctx *c) {
         tw.insert(tw.end(), joined[t].begin(), joined[t].end());
         T.maxwells = std::max(T.maxwells, (int)joined[t].size());
     }
+    // sweep records for tiles whose pencils fit one workgroup
+    T.psteps = T.tx + T.ty + T.tz - 2;
+    T.prec = T.tx * T.ty * T.tz;
+    T.poff = (T.tx * T.ty <= 256 && ilu_rank_ints(T) <= 4096)
+                 ? ((long)c->nnzb * c->nb * c->nb + 3) / 4 * 4 : -1;
     int dev = 0, lds_max = 0;
     HIPCHECK(hipGetDevice(&dev));
     HIPCHECK(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
@@ -996,10 +1003,17 @@ static void build_ilu(fim_ctx *c) {
     T.nsingle = (int)single.size();
     c->sync();                                  // the host vectors above are temporaries
     HIPCHECK(ilu_allow_lds(c->nb, (size_t)lds_max));   // the device's limit, as above
-    if (!c->lu) {
-        c->lu = c->alloc<double>((size_t)c->nnzb * c->nb * c->nb);
-        c->ilu_bad = c->alloc<int>(1);
+    const size_t elems = ilu_factor_elems(c->nb, c->nnzb, T, sizeof(double));
+    if (c->lu_elems < elems) {
+        c->drop_graphs();                       // captured steps name the old buffers
+        c->release(c->lu);
+        c->release(c->lu32);
+        c->lu32 = nullptr;
+        c->lu32_elems = 0;
+        c->lu = c->alloc<double>(elems);
+        c->lu_elems = elems;
     }
+    if (!c->ilu_bad) c->ilu_bad = c->alloc<int>(1);
     c->ilu = T;
     for (int a = 0; a < 3; ++a) c->ilu_dims[a] = d[a];
 }
@@ -1013,8 +1027,14 @@ static void ensure_mixed(fim_ctx *c) {
     if (!c->val32) {
         c->val32 = c->alloc<float>((size_t)c->nnzb * bs);
         c->w32 = c->alloc<float>(c->nvec);
-        c->lu32 = c->alloc<float>((size_t)c->nnzb * bs);
         c->ap32 = c->alloc<float>((size_t)c->nnzb * c->nb);
+    }
+    const size_t e32 = ilu_factor_elems(c->nb, c->nnzb, c->ilu, sizeof(float));
+    if (c->lu32_elems < e32) {
+        c->drop_graphs();
+        c->release(c->lu32);
+        c->lu32 = c->alloc<float>(e32);
+        c->lu32_elems = e32;
     }
     if (c->m32 < c->m) {
         c->release(c->V32);

@@ -110,15 +110,39 @@ __device__ void factor_row(int row, const IluTiles &T, const Sys &sys, LT *lu, i
     for (int e = 0; e < B2; ++e) lu[(size_t)di * B2 + e] = (LT)inv[e];
 }
 
+// elements of a record of nblk blocks, rounded to whole 16-byte chunks
+__host__ __device__ constexpr int rec_elems(int nblk, int nb, int esize) {
+    return (nblk * nb * nb + 16 / esize - 1) / (16 / esize) * (16 / esize);
+}
+
+// Element index of the first chunk, and the chunk stride in elements, of
+// the records (ne elements, w per chunk) of cell (li, lj) at step s;
+// element j is at start + (j / w) * stride + j % w.
+struct RecPos {
+    int start, stride;
+};
+__device__ inline RecPos rec_pos(const IluTiles &T, const int *roff, int s, int li, int lj, int ne,
+                                 int w) {
+    const int *cnt = roff + T.psteps * T.ty, *first = cnt + T.psteps;
+    const int c = cnt[s], f = first[s];
+    return RecPos{f * ne + (roff[s * T.ty + lj] + li - f) * w, c * w};
+}
+__device__ inline int rec_at(const RecPos &p, int j, int w) {
+    return p.start + (j / w) * p.stride + j % w;
+}
+
 // The same factorisation for a cell row without well columns, found from
-// the row's position: on a 7-point pattern the only entry ILU(0) changes
+// the row's position (lo, up: the tile's sweep records, pl, pu: the row's
+// places in them): on a 7-point pattern the only entry ILU(0) changes
 // besides the lower blocks is the diagonal, D_i = A_ii - sum_k L_ik U_ki
 // over the lower neighbours k of the tile (in column order -z, -y, -x),
 // with U_ki the +z / +y / +x block of row k.  Returns false (nothing done)
 // for rows with well columns.
 template <int NB, class LT>
 __device__ bool factor_cell_row(int i, int j, int k, const Grid &g, const IluTiles &T,
-                                const TileBox &tb, const Sys &sys, LT *lu, int *bad) {
+                                const TileBox &tb, const Sys &sys, LT *lu, int *bad,
+                                LT *lo = nullptr, LT *up = nullptr, RecPos pl = {}, RecPos pu = {}) {
+    constexpr int W = 16 / sizeof(LT);
     constexpr int B2 = NB * NB;
     const int r = i + g.nx * (j + g.ny * k);
     const int q0 = sys.rowptr[r];
@@ -130,14 +154,32 @@ __device__ bool factor_cell_row(int i, int j, int k, const Grid &g, const IluTil
 #pragma unroll
     for (int e = 0; e < B2; ++e) d[e] = (double)lu[(size_t)qd * B2 + e];
     const int li = i - tb.i0, lj = j - tb.j0, lk = k - tb.k0;
+    if (up) {
+        // sweep records: the upper blocks (unchanged by the factorisation),
+        // zero where the neighbour lies outside the tile
+        const int qux = qd + 1, quy = qux + (i + 1 < g.nx), quz = quy + (j + 1 < g.ny);
+        const bool hx = li + 1 < tb.txe, hy = lj + 1 < tb.tye, hz = lk + 1 < tb.tze;
+#pragma unroll
+        for (int e = 0; e < B2; ++e) {
+            const LT vx = lu[(size_t)(hx ? qux : qd) * B2 + e];
+            const LT vy = lu[(size_t)(hy ? quy : qd) * B2 + e];
+            const LT vz = lu[(size_t)(hz ? quz : qd) * B2 + e];
+            up[rec_at(pu, B2 + e, W)] = hx ? vx : (LT)0;
+            up[rec_at(pu, 2 * B2 + e, W)] = hy ? vy : (LT)0;
+            up[rec_at(pu, 3 * B2 + e, W)] = hz ? vz : (LT)0;
+        }
+    }
     // lower neighbours in column order; for each: its row index, the
     // position of its diagonal and of its block towards row r
     int qk = q0;
 #pragma unroll
     for (int dir = 0; dir < 3; ++dir) {
         const bool exists = dir == 0 ? k > 0 : (dir == 1 ? j > 0 : i > 0);
-        if (!exists) continue;
         const bool in = dir == 0 ? lk > 0 : (dir == 1 ? lj > 0 : li > 0);
+        if (lo && !in)
+#pragma unroll
+            for (int e = 0; e < B2; ++e) lo[rec_at(pl, dir * B2 + e, W)] = (LT)0;
+        if (!exists) continue;
         if (in) {
             const int ki = i - (dir == 2), kj = j - (dir == 1), kk = k - (dir == 0);
             const int rk = r - (dir == 0 ? g.nx * g.ny : (dir == 1 ? g.nx : 1));
@@ -154,6 +196,7 @@ __device__ bool factor_cell_row(int i, int j, int k, const Grid &g, const IluTil
 #pragma unroll
             for (int e = 0; e < B2; ++e) {
                 lu[(size_t)qk * B2 + e] = (LT)l[e];
+                if (lo) lo[rec_at(pl, dir * B2 + e, W)] = (LT)l[e];
                 uk[e] = (double)lu[(size_t)qki * B2 + e];
             }
             block_mul<NB>(l, uk, p);
@@ -169,7 +212,10 @@ __device__ bool factor_cell_row(int i, int j, int k, const Grid &g, const IluTil
         for (int e = 0; e < B2; ++e) inv[e] = (e % (NB + 1) == 0) ? 1.0 : 0.0;
     }
 #pragma unroll
-    for (int e = 0; e < B2; ++e) lu[(size_t)qd * B2 + e] = (LT)inv[e];
+    for (int e = 0; e < B2; ++e) {
+        lu[(size_t)qd * B2 + e] = (LT)inv[e];
+        if (up) up[rec_at(pu, e, W)] = (LT)inv[e];
+    }
     return true;
 }
 
@@ -190,9 +236,106 @@ __device__ void factor_alone(int row, const Sys &sys, LT *lu, int *bad) {
     for (int e = 0; e < B2; ++e) lu[(size_t)di * B2 + e] = (LT)inv[e];
 }
 
+// Sweep records of a tile whose pencils fit the workgroup.  The thread of
+// pencil (li, lj) meets cell (li, lj, lk) at step s = li + lj + lk of both
+// sweeps; the cell's records hold the blocks it uses there.  Lower records:
+// the -z, -y, -x blocks; upper records: the inverted diagonal, then the +x,
+// +y, +z blocks; a neighbour outside the tile has a zero block, so the
+// sweeps multiply without a branch.  Couplings to wells stay in A's layout.
+// The cells of a step are numbered consecutively (ilu_rank_table) and the
+// step's records stored in 16-byte chunks of w = 16 / element-size
+// elements, chunk by chunk: element j of the cell at position q of step s
+// (c cells, first cell number f, ne elements per record rounded up to a
+// multiple of w) sits at f * ne + (j / w) * w * c + q * w + j % w, so the
+// threads active at one step read and write adjacent chunks.
+
+// Byte offset (from the factors' start) of tile b's lower (upper = false)
+// or upper records; a tile's records of one kind take prec * rec_elems
+// elements.
+__host__ __device__ inline size_t rec_region(const IluTiles &T, int nb, int esize, int b,
+                                             bool upper) {
+    const size_t lo = (size_t)T.prec * rec_elems(3, nb, esize) * esize;
+    const size_t up = (size_t)T.prec * rec_elems(4, nb, esize) * esize;
+    const size_t ntiles = (size_t)T.ntx * T.nty * T.ntz;
+    size_t off = (size_t)T.poff * esize;
+    if (upper) off += ntiles * lo + (size_t)b * up;
+    else off += (size_t)b * lo;
+    return off;
+}
+
+size_t ilu_factor_elems(int nb, long nnzb, const IluTiles &T, int esize) {
+    const size_t base = (size_t)nnzb * nb * nb;
+    if (T.poff < 0) return base;
+    return (size_t)T.poff + (size_t)T.ntx * T.nty * T.ntz * T.prec *
+                                (rec_elems(3, nb, esize) + rec_elems(4, nb, esize));
+}
+
+int ilu_rank_ints(const IluTiles &T) { return T.psteps * T.ty + 2 * T.psteps; }
+
+// Numbering of a tile's cells: step by step (s = li + lj + lk), and within
+// a step by (lj, li).  roff[s * T.ty + lj] + li is the number of cell
+// (li, lj, s - li - lj); cnt[s] and first[s] are the number of cells of
+// step s and the number of its first cell.  Built by the whole workgroup
+// (two barriers).
+__device__ void ilu_rank_table(const TileBox &tb, const IluTiles &T, int *roff) {
+    int *cnt = roff + T.psteps * T.ty, *first = cnt + T.psteps;
+    const int S = tb.txe + tb.tye + tb.tze - 2;
+    for (int s = threadIdx.x; s < S; s += blockDim.x) {
+        int acc = 0;
+        for (int lj = 0; lj < tb.tye; ++lj) {
+            const int lo = max(0, s - lj - (tb.tze - 1)), hi = min(tb.txe - 1, s - lj);
+            roff[s * T.ty + lj] = acc - lo;
+            acc += max(0, hi - lo + 1);
+        }
+        cnt[s] = acc;
+    }
+    __syncthreads();
+    for (int s = threadIdx.x; s < S; s += blockDim.x) {
+        int base = 0;
+        for (int q = 0; q < s; ++q) base += cnt[q];
+        for (int lj = 0; lj < tb.tye; ++lj) roff[s * T.ty + lj] += base;
+        first[s] = base;
+    }
+    __syncthreads();
+}
+
+// Write the sweep records of cell (li, lj, lk) of tile b from its finished
+// row (rows with well columns; the others write theirs while factored).
+template <int NB, class LT>
+__device__ inline void pack_cell(const Grid &g, const IluTiles &T, const TileBox &tb,
+                                 const Sys &sys, LT *lu, int b, int li, int lj, int lk,
+                                 const int *roff) {
+    constexpr int B2 = NB * NB;
+    const int i = tb.i0 + li, j = tb.j0 + lj, k = tb.k0 + lk;
+    const int qz = sys.rowptr[i + g.nx * (j + g.ny * k)];
+    const int qy = qz + (k > 0), qx = qy + (j > 0), qd = qx + (i > 0);
+    const int qux = qd + 1, quy = qux + (i + 1 < g.nx), quz = quy + (j + 1 < g.ny);
+    const int src[7] = {lk > 0 ? qz : -1, lj > 0 ? qy : -1, li > 0 ? qx : -1, qd,
+                        li + 1 < tb.txe ? qux : -1, lj + 1 < tb.tye ? quy : -1,
+                        lk + 1 < tb.tze ? quz : -1};
+    const int s = li + lj + lk;
+    constexpr int W = 16 / sizeof(LT);
+    const RecPos pl = rec_pos(T, roff, s, li, lj, rec_elems(3, NB, sizeof(LT)), W);
+    const RecPos pu = rec_pos(T, roff, s, li, lj, rec_elems(4, NB, sizeof(LT)), W);
+    char *base = reinterpret_cast<char *>(lu);
+    LT *lo = reinterpret_cast<LT *>(base + rec_region(T, NB, sizeof(LT), b, false));
+    LT *up = reinterpret_cast<LT *>(base + rec_region(T, NB, sizeof(LT), b, true));
+#pragma unroll
+    for (int m = 0; m < 7; ++m) {
+        const int q = src[m] >= 0 ? src[m] : qd;
+#pragma unroll
+        for (int e = 0; e < B2; ++e) {
+            const LT v = src[m] >= 0 ? lu[(size_t)q * B2 + e] : (LT)0;
+            if (m < 3) lo[rec_at(pl, m * B2 + e, W)] = v;
+            else up[rec_at(pu, (m - 3) * B2 + e, W)] = v;
+        }
+    }
+}
+
 // One workgroup per tile, then one for the wells that stand alone.  The
 // tile's rows (cells and its wells) are copied from A first, each x-row of
-// the tile being one contiguous run of blocks.
+// the tile being one contiguous run of blocks.  Tiles with sweep records
+// write each cell's as soon as its row is factored.
 template <int NB, class LT>
 __global__ __launch_bounds__(256) void k_ilu_factor(Grid g, IluTiles T, Sys sys, LT *lu,
                                                     int *bad) {
@@ -210,6 +353,8 @@ __global__ __launch_bounds__(256) void k_ilu_factor(Grid g, IluTiles T, Sys sys,
         return;
     }
     const TileBox tb = tile_box(g, T, b);
+    extern __shared__ int roff[];
+    if (T.poff >= 0) ilu_rank_table(tb, T, roff);
     for (int seg = 0; seg < tb.tye * tb.tze; ++seg) {
         const int j = tb.j0 + seg % tb.tye, k = tb.k0 + seg / tb.tye;
         const int r0 = tb.i0 + g.nx * (j + g.ny * k);
@@ -226,8 +371,21 @@ __global__ __launch_bounds__(256) void k_ilu_factor(Grid g, IluTiles T, Sys sys,
             const int li = p % tb.txe, lj = p / tb.txe, lk = s - li - lj;
             if (lk < 0 || lk >= tb.tze) continue;
             const int i = tb.i0 + li, j = tb.j0 + lj, k = tb.k0 + lk;
-            if (!factor_cell_row<NB, LT>(i, j, k, g, T, tb, sys, lu, bad))
+            LT *lo = nullptr, *up = nullptr;
+            RecPos pl{}, pu{};
+            if (T.poff >= 0) {
+                constexpr int W = 16 / sizeof(LT);
+                pl = rec_pos(T, roff, s, li, lj, rec_elems(3, NB, sizeof(LT)), W);
+                pu = rec_pos(T, roff, s, li, lj, rec_elems(4, NB, sizeof(LT)), W);
+                char *base = reinterpret_cast<char *>(lu);
+                lo = reinterpret_cast<LT *>(base + rec_region(T, NB, sizeof(LT), b, false));
+                up = reinterpret_cast<LT *>(base + rec_region(T, NB, sizeof(LT), b, true));
+            }
+            if (!factor_cell_row<NB, LT>(i, j, k, g, T, tb, sys, lu, bad, lo, up, pl, pu)) {
                 factor_row<NB, LT>(i + g.nx * (j + g.ny * k), T, sys, lu, bad);
+                // a row with well columns: its records from the finished row
+                if (T.poff >= 0) pack_cell<NB, LT>(g, T, tb, sys, lu, b, li, lj, lk, roff);
+            }
         }
         __syncthreads();
     }
@@ -267,12 +425,12 @@ __device__ inline void load_blk(Blk<NB> &dst, const LT *src) {
 // rows, of perforated cells and wells, finish in a loop)
 template <int NB, class RT>
 __device__ inline void rhs_row(const RT &R, const Sys &sys, int r, double (&acc)[NB],
-                               int q0 = -1) {
+                               int q0 = -1, int q1 = -1) {
 #pragma unroll
     for (int u = 0; u < NB; ++u) acc[u] = (double)R.b[(size_t)r * NB + u];
     if (!R.ap) return;
     if (q0 < 0) q0 = sys.rowptr[r];
-    const int q1 = sys.rowptr[r + 1];
+    if (q1 < 0) q1 = sys.rowptr[r + 1];
     constexpr int K = 8;
     // a slot past the row's end loads the row's last block (every row has
     // one) and is dropped by a select: no branch between the loads
@@ -338,23 +496,55 @@ __device__ void solve_tile_wells(const Grid &g, const TileBox &tb, const Sys &sy
     }
 }
 
+// Third word of a raw buffer resource on this architecture (32-bit data,
+// no swizzle); the range check returns zeros past num_records.
+constexpr int kBufferWord3 = 0x00020000;
+
+// The NBLK blocks of a sweep record: 16-byte chunk c at byte offset
+// off + c * stride of buffer rs (an offset past the buffer's end gives
+// zeros, without a memory access).
+template <int NB, class LT, int NBLK>
+__device__ inline void load_rec(Blk<NB> (&X)[NBLK], __amdgpu_buffer_rsrc_t rs, int off, int stride) {
+    constexpr int B2 = NB * NB, W = 16 / sizeof(LT), nc = rec_elems(NBLK, NB, sizeof(LT)) / W;
+    typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+    u4 raw[nc];
+#pragma unroll
+    for (int c = 0; c < nc; ++c) raw[c] = __builtin_amdgcn_raw_buffer_load_b128(rs, off + c * stride, 0, 0);
+    LT e[nc * W];
+    __builtin_memcpy(e, raw, sizeof(raw));
+#pragma unroll
+    for (int m = 0; m < NBLK; ++m)
+#pragma unroll
+        for (int q = 0; q < B2; ++q) X[m].v[q] = (double)e[m * B2 + q];
+}
+
+// Workgroup barrier ordering LDS only.  __syncthreads() also orders global
+// memory, so it waits for every load in flight, the sweep prefetches
+// included; the sweeps exchange values through LDS alone.
+__device__ inline void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Both sweeps over the cells of a tile whose (li, lj) pencils fit the
 // workgroup: thread (li, lj) owns the pencil and meets its cells in order
-// of lk, one per hyperplane, so it loads the blocks of its next kAhead
-// cells while the hyperplanes before them are solved.  Row starts and the
-// right side are staged in LDS first.  Same arithmetic, same order, as the
-// general sweeps.
+// of lk, one per hyperplane, reading their blocks from the tile's sweep
+// records two steps ahead.  Row starts and the right side are staged in LDS
+// first.  Same arithmetic, same order, as the general sweeps.
 template <int NB, class LT, class RT>
 __device__ void solve_cells_pencils(const Grid &g, const TileBox &tb, const Sys &sys,
                                     const LT *__restrict__ lu, const RT &R,
                                     double *y, int *rp, const IluTiles &T, int blk, int w0, int nwt,
                                     int ncell) {
     constexpr int B2 = NB * NB;
-    constexpr int kAhead = 2;                     // deeper costs occupancy (VGPRs)
     const int sxy = tb.txe * tb.tye;
+    int *re = rp + ncell;                          // row ends
+    int *roff = re + ncell;                        // record order
+    ilu_rank_table(tb, T, roff);
     // two rows per thread at a time so their loads overlap
     for (int l0 = threadIdx.x; l0 < ncell; l0 += 2 * blockDim.x) {
-        int rr[2], q0[2];
+        int rr[2], q0[2], q1[2];
         bool on[2];
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -363,113 +553,144 @@ __device__ void solve_cells_pencils(const Grid &g, const TileBox &tb, const Sys 
             const int li = l % tb.txe, lj = (l / tb.txe) % tb.tye, lk = l / sxy;
             rr[h] = on[h] ? (tb.i0 + li) + g.nx * ((tb.j0 + lj) + g.ny * (tb.k0 + lk)) : 0;
             q0[h] = on[h] ? sys.rowptr[rr[h]] : 0;
+            q1[h] = on[h] ? sys.rowptr[rr[h] + 1] : 0;
         }
         double acc[2][NB];
 #pragma unroll
         for (int h = 0; h < 2; ++h)
-            if (on[h]) rhs_row<NB>(R, sys, rr[h], acc[h], q0[h]);
+            if (on[h]) rhs_row<NB>(R, sys, rr[h], acc[h], q0[h], q1[h]);
 #pragma unroll
         for (int h = 0; h < 2; ++h)
             if (on[h]) {
                 const int l = l0 + h * blockDim.x;
                 rp[l] = q0[h];
+                re[l] = q1[h];
 #pragma unroll
                 for (int u = 0; u < NB; ++u) y[(size_t)l * NB + u] = acc[h][u];
             }
     }
     __syncthreads();
     const bool own = (int)threadIdx.x < sxy;
-    const int li = threadIdx.x % tb.txe, lj = threadIdx.x / tb.txe;
+    const int li = own ? threadIdx.x % tb.txe : 0, lj = own ? threadIdx.x / tb.txe : 0;
     const int i = tb.i0 + li, j = tb.j0 + lj;
     const int nlev = tb.txe + tb.tye + tb.tze - 2;
-    // forward: lower blocks -z, -y, -x of cell lk
-    auto lower = [&](int lk, Blk<NB> &bz, Blk<NB> &by, Blk<NB> &bx) {
-        const int k = tb.k0 + lk;
-        const int q = rp[li + tb.txe * (lj + tb.tye * lk)];
-        const int qy = q + (k > 0), qx = qy + (j > 0);
-        if (lk > 0) load_blk<NB>(bz, lu + (size_t)q * B2);
-        if (lj > 0) load_blk<NB>(by, lu + (size_t)qy * B2);
-        if (li > 0) load_blk<NB>(bx, lu + (size_t)qx * B2);
+    // the thread's cells come at steps s0 .. s1; a prefetch for a step
+    // outside them reads past the end of the tile's record buffer, which
+    // returns zeros without a memory access, so every lane issues the same
+    // loads and no wait covers more than the record about to be used
+    const int s0 = li + lj, s1 = s0 + tb.tze - 1;
+    auto mine = [&](int s) { return own && s >= s0 && s <= s1; };
+    // a lane without a pencil (tiles narrower than the workgroup) reads and
+    // writes a slot of its own past the tile's vector, never a cell's
+    const int ldummy = ncell + T.maxwells;
+    auto clampstep = [&](int s) { return s < s0 ? s0 : (s > s1 ? s1 : s); };
+    // forward: y -= Lz y(-z) + Ly y(-y) + Lx y(-x), zero blocks at the tile's
+    // faces (the cell's own y stands in for the missing neighbour)
+    Blk<NB> fa[3], fb[3];
+    const char *lub = reinterpret_cast<const char *>(lu);
+    constexpr int kES = sizeof(LT), kW = 16 / kES;
+    constexpr int kEL = rec_elems(3, NB, kES), kEU = rec_elems(4, NB, kES);
+    const int nrec = T.prec;
+    // byte offset and chunk stride of the record of step s (for a step
+    // without a cell of this thread: the end of the buffer, which reads
+    // zeros)
+    auto recoff = [&](int s, int ne, int &stride) {
+        const RecPos p = rec_pos(T, roff, clampstep(s), li, lj, ne, kW);
+        stride = p.stride * kES;
+        return mine(s) ? p.start * kES : nrec * ne * kES;
     };
-    // blocks of the next kAhead cells of the pencil, in flight
-    Blk<NB> fz[kAhead], fy[kAhead], fx[kAhead];
-    if (own)
+    const __amdgpu_buffer_rsrc_t rsl = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<char *>(lub + rec_region(T, NB, sizeof(LT), blk, false)), 0, nrec * kEL * kES,
+        kBufferWord3);
+    auto lower = [&](int s, Blk<NB> (&X)[3]) {
+        int stride;
+        const int off = recoff(s, kEL, stride);
+        load_rec<NB, LT, 3>(X, rsl, off, stride);
+    };
+    // every lane computes (a lane without a cell at step s on its nearest
+    // cell, discarded), so the record buffers are consumed on one path
+    auto fstep = [&](int s, const Blk<NB> (&X)[3]) {
+        const int lk = clampstep(s) - s0, l = own ? li + tb.txe * (lj + tb.tye * lk) : ldummy;
+        double acc[NB];
 #pragma unroll
-        for (int a = 0; a < kAhead; ++a)
-            if (a < tb.tze) lower(a, fz[a], fy[a], fx[a]);
-    for (int s = 0; s < nlev; ++s) {
-        const int lk = s - li - lj;
-        if (own && lk >= 0 && lk < tb.tze) {
-            const int l = li + tb.txe * (lj + tb.tye * lk);
-            double acc[NB];
+        for (int u = 0; u < NB; ++u) acc[u] = y[(size_t)l * NB + u];
+        sub_mv<NB>(acc, X[0].v, y + (size_t)(own && lk > 0 ? l - sxy : l) * NB);
+        sub_mv<NB>(acc, X[1].v, y + (size_t)(own && lj > 0 ? l - tb.txe : l) * NB);
+        sub_mv<NB>(acc, X[2].v, y + (size_t)(own && li > 0 ? l - 1 : l) * NB);
+        // a lane without a cell at step s writes back its own cell's value
+        // unchanged (pencils are disjoint, so no other lane writes there)
+        const bool on = mine(s);
 #pragma unroll
-            for (int u = 0; u < NB; ++u) acc[u] = y[(size_t)l * NB + u];
-            if (lk > 0) sub_mv<NB>(acc, fz[0].v, y + (size_t)(l - sxy) * NB);
-            if (lj > 0) sub_mv<NB>(acc, fy[0].v, y + (size_t)(l - tb.txe) * NB);
-            if (li > 0) sub_mv<NB>(acc, fx[0].v, y + (size_t)(l - 1) * NB);
-#pragma unroll
-            for (int u = 0; u < NB; ++u) y[(size_t)l * NB + u] = acc[u];
-#pragma unroll
-            for (int a = 0; a + 1 < kAhead; ++a) {
-                fz[a] = fz[a + 1];
-                fy[a] = fy[a + 1];
-                fx[a] = fx[a + 1];
-            }
-            if (lk + kAhead < tb.tze) lower(lk + kAhead, fz[kAhead - 1], fy[kAhead - 1], fx[kAhead - 1]);
+        for (int u = 0; u < NB; ++u) {
+            const double old = y[(size_t)l * NB + u];
+            y[(size_t)l * NB + u] = on ? acc[u] : old;
         }
-        __syncthreads();
+    };
+    // two record buffers by the parity of the step: the one used at step s
+    // is refilled for step s + 2 right after (an even number of steps, the
+    // last one possibly empty, keeps the loop body free of branches)
+    lower(0, fa);
+    __builtin_amdgcn_sched_barrier(0);            // keep the loads in step order
+    lower(1, fb);
+    for (int s = 0; s < nlev; s += 2) {
+        fstep(s, fa);
+        lower(s + 2, fa);
+        lds_barrier();
+        fstep(s + 1, fb);
+        lower(s + 3, fb);
+        lds_barrier();
     }
+    __syncthreads();
     solve_tile_wells<NB, LT>(g, tb, sys, lu, R, y, T, w0, nwt, ncell);
     __syncthreads();
-    // backward: +x, +y, +z blocks and the inverted diagonal of cell lk
-    auto upper = [&](int lk, Blk<NB> &ux, Blk<NB> &uy, Blk<NB> &uz, Blk<NB> &dd) {
-        const int k = tb.k0 + lk;
-        const int qd = rp[li + tb.txe * (lj + tb.tye * lk)] + (k > 0) + (j > 0) + (i > 0);
-        const int qy = qd + 1 + (i + 1 < g.nx), qz = qy + (j + 1 < g.ny);
-        load_blk<NB>(dd, lu + (size_t)qd * B2);
-        if (li + 1 < tb.txe) load_blk<NB>(ux, lu + (size_t)(qd + 1) * B2);
-        if (lj + 1 < tb.tye) load_blk<NB>(uy, lu + (size_t)qy * B2);
-        if (lk + 1 < tb.tze) load_blk<NB>(uz, lu + (size_t)qz * B2);
+    // backward: y -= Ux y(+x) + Uy y(+y) + Uz y(+z) + the tile's wells, then
+    // x = -inv(U_kk) y (the diagonal record holds the inverted pivot)
+    Blk<NB> ga[4], gb[4];
+    const __amdgpu_buffer_rsrc_t rsu = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<char *>(lub + rec_region(T, NB, sizeof(LT), blk, true)), 0, nrec * kEU * kES,
+        kBufferWord3);
+    auto upper = [&](int s, Blk<NB> (&X)[4]) {
+        int stride;
+        const int off = recoff(s, kEU, stride);
+        load_rec<NB, LT, 4>(X, rsu, off, stride);
     };
-    Blk<NB> gx[kAhead], gy[kAhead], gz[kAhead], gd[kAhead];
-    if (own)
+    auto bstep = [&](int s, const Blk<NB> (&X)[4]) {
+        const bool on = mine(s);
+        const int lk = clampstep(s) - s0, k = tb.k0 + lk;
+        const int l = own ? li + tb.txe * (lj + tb.tye * lk) : ldummy;
+        double acc[NB];
 #pragma unroll
-        for (int a = 0; a < kAhead; ++a)
-            if (a < tb.tze) upper(tb.tze - 1 - a, gx[a], gy[a], gz[a], gd[a]);
-    for (int s = nlev - 1; s >= 0; --s) {
-        const int lk = s - li - lj;
-        if (own && lk >= 0 && lk < tb.tze) {
-            const int k = tb.k0 + lk;
-            const int r = i + g.nx * (j + g.ny * k), l = li + tb.txe * (lj + tb.tye * lk);
-            double acc[NB];
-#pragma unroll
-            for (int u = 0; u < NB; ++u) acc[u] = y[(size_t)l * NB + u];
-            if (li + 1 < tb.txe) sub_mv<NB>(acc, gx[0].v, y + (size_t)(l + 1) * NB);
-            if (lj + 1 < tb.tye) sub_mv<NB>(acc, gy[0].v, y + (size_t)(l + tb.txe) * NB);
-            if (lk + 1 < tb.tze) sub_mv<NB>(acc, gz[0].v, y + (size_t)(l + sxy) * NB);
-            // well columns (perforated cells): the wells of this tile
-            const int qw = rp[l] + (k > 0) + (j > 0) + (i > 0) + 1 + (i + 1 < g.nx) + (j + 1 < g.ny) +
-                           (k + 1 < g.nz);
-            for (int q = qw; q < sys.rowptr[r + 1]; ++q) {
-                const int w = sys.colind[q] - g.n;
-                if (T.rtile[g.n + w] == blk)
-                    sub_mv<NB>(acc, lu + (size_t)q * B2, y + (size_t)(ncell + T.wlocal[w]) * NB);
-            }
-            double xr[NB] = {};
-            sub_mv<NB>(xr, gd[0].v, acc);
-#pragma unroll
-            for (int u = 0; u < NB; ++u) y[(size_t)l * NB + u] = -xr[u];
-#pragma unroll
-            for (int a = 0; a + 1 < kAhead; ++a) {
-                gx[a] = gx[a + 1];
-                gy[a] = gy[a + 1];
-                gz[a] = gz[a + 1];
-                gd[a] = gd[a + 1];
-            }
-            if (lk - kAhead >= 0)
-                upper(lk - kAhead, gx[kAhead - 1], gy[kAhead - 1], gz[kAhead - 1], gd[kAhead - 1]);
+        for (int u = 0; u < NB; ++u) acc[u] = y[(size_t)l * NB + u];
+        sub_mv<NB>(acc, X[1].v, y + (size_t)(own && li + 1 < tb.txe ? l + 1 : l) * NB);
+        sub_mv<NB>(acc, X[2].v, y + (size_t)(own && lj + 1 < tb.tye ? l + tb.txe : l) * NB);
+        sub_mv<NB>(acc, X[3].v, y + (size_t)(own && lk + 1 < tb.tze ? l + sxy : l) * NB);
+        // well columns (perforated cells): the wells of this tile
+        const int qw = rp[own ? l : 0] + (k > 0) + (j > 0) + (i > 0) + 1 + (i + 1 < g.nx) + (j + 1 < g.ny) +
+                       (k + 1 < g.nz);
+        const int qe = on ? re[own ? l : 0] : qw;
+        for (int q = qw; q < qe; ++q) {
+            const int w = sys.colind[q] - g.n;
+            if (T.rtile[g.n + w] == blk)
+                sub_mv<NB>(acc, lu + (size_t)q * B2, y + (size_t)(ncell + T.wlocal[w]) * NB);
         }
-        __syncthreads();
+        double xr[NB] = {};
+        sub_mv<NB>(xr, X[0].v, acc);
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const double old = y[(size_t)l * NB + u];
+            y[(size_t)l * NB + u] = on ? -xr[u] : old;
+        }
+    };
+    upper(nlev - 1, ga);
+    __builtin_amdgcn_sched_barrier(0);
+    upper(nlev - 2, gb);
+    for (int s = nlev - 1; s >= 0; s -= 2) {
+        bstep(s, ga);
+        upper(s - 2, ga);
+        lds_barrier();
+        bstep(s - 1, gb);
+        upper(s - 3, gb);
+        lds_barrier();
     }
 }
 
@@ -500,8 +721,8 @@ __global__ __launch_bounds__(256) void k_ilu_solve(Grid g, IluTiles T, Sys sys,
     const int sxy = tb.txe * tb.tye, ncell = sxy * tb.tze;
     const int w0 = T.twp[blk], nwt = T.twp[blk + 1] - w0;
     const int nlev = tb.txe + tb.tye + tb.tze - 2;
-    if (sxy <= (int)blockDim.x) {
-        solve_cells_pencils<NB, LT>(g, tb, sys, lu, R, y, reinterpret_cast<int *>(y + (size_t)(ncell + T.maxwells) * NB),
+    if (T.poff >= 0 && sxy <= (int)blockDim.x) {
+        solve_cells_pencils<NB, LT>(g, tb, sys, lu, R, y, reinterpret_cast<int *>(y + (size_t)(ncell + T.maxwells + 1) * NB),
                                 T, blk, w0, nwt, ncell);
     } else {
     // forward over the hyperplanes
@@ -600,8 +821,9 @@ static void ilu_factor_impl(hipStream_t s, int nb, Grid g, const IluTiles &T, Sy
                             int *bad) {
     const int nblk = T.ntx * T.nty * T.ntz + (T.nsingle > 0 ? 1 : 0);
     const int bs = ilu_threads(T);
-    if (nb == 2) hipLaunchKernelGGL((k_ilu_factor<2, LT>), dim3(nblk), dim3(bs), 0, s, g, T, sys, lu, bad);
-    else hipLaunchKernelGGL((k_ilu_factor<3, LT>), dim3(nblk), dim3(bs), 0, s, g, T, sys, lu, bad);
+    const size_t lds = T.poff >= 0 ? (size_t)ilu_rank_ints(T) * sizeof(int) : 0;
+    if (nb == 2) hipLaunchKernelGGL((k_ilu_factor<2, LT>), dim3(nblk), dim3(bs), lds, s, g, T, sys, lu, bad);
+    else hipLaunchKernelGGL((k_ilu_factor<3, LT>), dim3(nblk), dim3(bs), lds, s, g, T, sys, lu, bad);
 }
 
 void launch_ilu_factor(hipStream_t s, int nb, Grid g, const IluTiles &T, Sys sys, double *lu,
@@ -620,9 +842,11 @@ int ilu_threads(const IluTiles &T) {
 }
 
 size_t ilu_solve_lds(int nb, const IluTiles &T) {
-    // the tile's vector, then its row starts (pencil sweeps)
-    return (size_t)(T.tx * T.ty * T.tz + T.maxwells) * nb * sizeof(double) +
-           (size_t)T.tx * T.ty * T.tz * sizeof(int);
+    // the tile's vector and a spare slot, then its row starts and ends and
+    // its record order (pencil sweeps)
+    return (size_t)(T.tx * T.ty * T.tz + T.maxwells + 1) * nb * sizeof(double) +
+           (size_t)2 * T.tx * T.ty * T.tz * sizeof(int) +
+           (T.poff >= 0 ? (size_t)ilu_rank_ints(T) * sizeof(int) : 0);
 }
 
 template <class LT, class VT>

@@ -217,7 +217,19 @@ struct IluTiles {
     const int *wlocal;          // [nw] slot of a joined well among its tile's wells
     const int *single;          // [nsingle] wells that stand alone
     int nsingle, maxwells;      // maxwells: most wells joined to one tile
+    // Sweep records of tiles whose pencils fit one workgroup (tx*ty <= 256):
+    // element offset from the factors' start (a multiple of 4 elements, so
+    // 16-byte aligned for float and double factors), steps tx+ty+tz-2 and
+    // records (cells) per tile; poff < 0 when the tiles take the general
+    // sweeps.
+    long poff;
+    int psteps, prec;
 };
+// ints of LDS the record order of a tile takes (see ilu_rank_table)
+int ilu_rank_ints(const IluTiles &T);
+// elements of esize bytes in the factor buffer (the factors in the layout
+// of A, then the sweep records when T.poff >= 0)
+size_t ilu_factor_elems(int nb, long nnzb, const IluTiles &T, int esize);
 int ilu_threads(const IluTiles &T);
 size_t ilu_solve_lds(int nb, const IluTiles &T);
 hipError_t ilu_allow_lds(int nb, size_t bytes);
