@@ -600,14 +600,14 @@ __device__ inline void presmooth_item(const AmgLevel &L, int h) {
 }
 
 __global__ __launch_bounds__(kBlock) void k_amg_presmooth(AmgLevel L) {
-    const int h = blockIdx.x * blockDim.x + threadIdx.x;
+    const int h = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (h < L.half) presmooth_item(L, h);
 }
 
 template <int M>
 __global__ __launch_bounds__(kBlock) void k_amg_sweep(AmgLevel L, AmgLevel C, int color,
                                                       int mode) {
-    const int h = blockIdx.x * blockDim.x + threadIdx.x;
+    const int h = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (h < L.half) sweep_item<M>(L, C, color, mode, h);
 }
 
@@ -697,13 +697,14 @@ __device__ inline void restrict_well(const AmgLevel &F, const AmgLevel &C, int w
 
 // coarse cells (8 lanes each) then wells (one wave each)
 __global__ __launch_bounds__(kBlock) void k_amg_restrict(AmgLevel F, AmgLevel C) {
-    const long t8 = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int bx = xcd_block(blockIdx.x, gridDim.x);
+    const long t8 = (long)bx * blockDim.x + threadIdx.x;
     const long n8 = 8L * C.nx * C.ny * C.nz;
     const int cell_blocks = (int)((n8 + kBlock - 1) / kBlock);
-    if ((int)blockIdx.x < cell_blocks) {
+    if (bx < cell_blocks) {
         restrict_group(F, C, (int)(t8 >> 3), (int)(t8 & 7), t8 < n8);
     } else {
-        const int w = (((int)blockIdx.x - cell_blocks) * kBlock + threadIdx.x) >> 6;
+        const int w = ((bx - cell_blocks) * kBlock + threadIdx.x) >> 6;
         if (w < F.nw) restrict_well(F, C, w, threadIdx.x & 63);
     }
 }
@@ -721,7 +722,7 @@ __device__ inline void correct_item(const AmgLevel &F, const AmgLevel &C, int t)
 }
 
 __global__ __launch_bounds__(kBlock) void k_amg_correct(AmgLevel F, AmgLevel C) {
-    correct_item(F, C, blockIdx.x * blockDim.x + threadIdx.x);
+    correct_item(F, C, xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x);
 }
 
 // The coarse part of a cycle in one workgroup.  Below a few thousand cells

@@ -340,7 +340,7 @@ template <int NB, class LT>
 __global__ __launch_bounds__(256) void k_ilu_factor(Grid g, IluTiles T, Sys sys, LT *lu,
                                                     int *bad) {
     constexpr int B2 = NB * NB;
-    const int b = blockIdx.x;
+    const int b = xcd_block(blockIdx.x, gridDim.x);   // contiguous tiles per XCD
     const int ntiles = T.ntx * T.nty * T.ntz;
     if (b >= ntiles) {
         for (int e = 0; e < T.nsingle; ++e) {
@@ -703,7 +703,9 @@ __global__ __launch_bounds__(256) void k_ilu_solve(Grid g, IluTiles T, Sys sys,
                                                    VT *__restrict__ x) {
     constexpr int B2 = NB * NB;
     extern __shared__ double y[];
-    const int blk = blockIdx.x;
+    // each XCD takes one contiguous run of tiles (neighbouring tiles share
+    // lines of the level-0 iterate and of the rows at their faces)
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
     const int ntiles = T.ntx * T.nty * T.ntz;
     const int n = g.n;
     if (blk >= ntiles) {
