@@ -162,34 +162,42 @@ template <int NB, class LT>
 __global__ __launch_bounds__(kBlock) void k_amg_extract(AmgLevel L, Grid g, Wells wl, Sys sys,
                                                         double *__restrict__ wq,
                                                         LT *__restrict__ ap) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    // a group of 8 lanes per row, lane lg on the row's blocks lg, lg + 8, ...
+    // (adjacent lanes read adjacent blocks); every lane forms the row's
+    // weights from the diagonal block
+    constexpr int G = 8;
+    const int lg = threadIdx.x & (G - 1);
+    const int t = (int)(((long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) / G);
     const int n = g.n;
     const int stride = 2 * L.half;
-    if (t < n + L.nw)
-        for (int q = sys.rowptr[t]; q < sys.rowptr[t + 1]; ++q)
+    if (t >= n + L.nw) return;
+    const int q0 = sys.rowptr[t], q1 = sys.rowptr[t + 1];
+    for (int q = q0 + lg; q < q1; q += G)
 #pragma unroll
-            for (int u = 0; u < NB; ++u) ap[(size_t)q * NB + u] = (LT)sys.val[(size_t)q * NB * NB + u * NB];
+        for (int u = 0; u < NB; ++u) ap[(size_t)q * NB + u] = (LT)sys.val[(size_t)q * NB * NB + u * NB];
     if (t < n) {
         const int c = t, nx = g.nx, ny = g.ny, nxy = nx * ny;
         const int i = c % nx, j = (c / nx) % ny, k = c / nxy;
         double w[NB];
         qi_weights<NB>(sys.val + (size_t)sys.diagpos[c] * NB * NB, w);
+        if (lg == 0)
 #pragma unroll
-        for (int e = 0; e < NB; ++e) wq[(size_t)c * NB + e] = w[e];
+            for (int e = 0; e < NB; ++e) wq[(size_t)c * NB + e] = w[e];
         const int s = split_of(L, i, j, k);
-        int q = sys.rowptr[c];
-        double a[7];
-        a[5] = (k > 0) ? pcoef<NB>(sys.val, q++, w) : 0.0;
-        a[3] = (j > 0) ? pcoef<NB>(sys.val, q++, w) : 0.0;
-        a[1] = (i > 0) ? pcoef<NB>(sys.val, q++, w) : 0.0;
-        a[0] = pcoef<NB>(sys.val, q++, w);
-        a[2] = (i + 1 < nx) ? pcoef<NB>(sys.val, q++, w) : 0.0;
-        a[4] = (j + 1 < ny) ? pcoef<NB>(sys.val, q++, w) : 0.0;
-        a[6] = (k + 1 < g.nz) ? pcoef<NB>(sys.val, q++, w) : 0.0;
-#pragma unroll
-        for (int d = 0; d < 7; ++d) L.a[(size_t)d * stride + s] = a[d];
-        for (int pp = wl.cps[c]; pp < wl.cps[c + 1]; ++pp) L.acw[wl.cperf[pp]] = pcoef<NB>(sys.val, q++, w);
-    } else if (t < n + L.nw) {
+        // the row's 7-point blocks in their order -z, -y, -x, diagonal, +x,
+        // +y, +z (those that exist), then its well columns
+        const unsigned mask = (k > 0) | (j > 0) << 1 | (i > 0) << 2 | 1u << 3 | (i + 1 < nx) << 4 |
+                              (j + 1 < ny) << 5 | (k + 1 < g.nz) << 6;
+        if (lg < 7) {
+            // slot lg holds stencil entry d of L.a (diagonal, -x, +x, -y, +y, -z, +z)
+            const int d = (0x6420135 >> (4 * lg)) & 15;
+            const int q = q0 + __popc(mask & ((1u << lg) - 1));
+            L.a[(size_t)d * stride + s] = ((mask >> lg) & 1) ? pcoef<NB>(sys.val, q, w) : 0.0;
+        } else {
+            int q = q0 + __popc(mask);
+            for (int pp = wl.cps[c]; pp < wl.cps[c + 1]; ++pp) L.acw[wl.cperf[pp]] = pcoef<NB>(sys.val, q++, w);
+        }
+    } else if (lg == 0) {
         const int wi = t - n;
         const int base = sys.rowptr[n + wi];
         const int p0 = L.sps[wi], np = L.sps[wi + 1] - p0;
@@ -349,7 +357,8 @@ __global__ void k_amg_dense(AmgLevel L, double *__restrict__ M) {
 }
 
 // Gauss-Jordan inverse with partial pivoting by one workgroup; A is
-// overwritten, Ainv receives the inverse, *bad is set on a zero pivot.
+// overwritten, Ainv receives the inverse transposed, *bad is set on a zero
+// pivot.
 __global__ __launch_bounds__(1024) void k_dense_invert(int n, double *__restrict__ A,
                                                        double *__restrict__ Ainv,
                                                        double *__restrict__ colk, int *bad) {
@@ -417,11 +426,21 @@ __global__ __launch_bounds__(1024) void k_dense_invert(int n, double *__restrict
         }
         __syncthreads();
     }
+    // stored transposed (the coarse solve reads it by columns)
+    for (int e = tid; e < n * n; e += nt) {
+        const int r = e / n, c = e % n;
+        if (r < c) {
+            const double t = Ainv[e];
+            Ainv[e] = Ainv[(size_t)c * n + r];
+            Ainv[(size_t)c * n + r] = t;
+        }
+    }
 }
 
 // The same Gauss-Jordan elimination with [A | A^-1] in LDS (n <= kDenseLds):
 // one wave finds the pivot with shuffles (largest magnitude, the smallest
-// row on ties, as above), the workgroup updates, three barriers per pivot.
+// row on ties, as above), the workgroup updates, three barriers per pivot;
+// the inverse is stored transposed, as above.
 constexpr int kDenseLds = 96;
 size_t dense_lds_bytes(int n) { return ((size_t)2 * n * n + n) * sizeof(double); }
 
@@ -490,26 +509,36 @@ __global__ __launch_bounds__(1024) void k_dense_invert_lds(int n, const double *
         }
         __syncthreads();
     }
-    for (int e = tid; e < n * n; e += nt) Ainv[e] = X[e];
+    for (int e = tid; e < n * n; e += nt) Ainv[(size_t)(e % n) * n + e / n] = X[e];   // transposed
 }
 
-// x[row] = (Minv b)[row] by the 64 lanes of one wave
-__device__ inline void dense_row(int n, const double *__restrict__ M, const double *b, double *x,
-                                 int row, int lane) {
+// (Minv b)[row] by one thread, the columns in order; the inverse is stored
+// transposed (MT[c * n + r] = Minv[r][c]), so the threads of consecutive
+// rows read consecutive words
+__device__ inline double dense_row(int n, const double *__restrict__ MT, const double *b,
+                                   int row) {
     double s = 0.0;
-    for (int c = lane; c < n; c += 64) s += M[(size_t)row * n + c] * b[c];
+    int c = 0;
+    for (; c + 8 <= n; c += 8) {             // eight columns' loads in flight at once
+        double m[8], v[8];
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
-    if (lane == 0) x[row] = s;
+        for (int u = 0; u < 8; ++u) {
+            m[u] = MT[(size_t)(c + u) * n + row];
+            v[u] = b[c + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += m[u] * v[u];
+    }
+    for (; c < n; ++c) s += MT[(size_t)c * n + row] * b[c];
+    return s;
 }
 
-// x = Minv b, one wave per row
-__global__ __launch_bounds__(256) void k_dense_gemv(int n, const double *__restrict__ M,
+// x = Minv b, one thread per row
+__global__ __launch_bounds__(256) void k_dense_gemv(int n, const double *__restrict__ MT,
                                                     const double *__restrict__ b,
                                                     double *__restrict__ x) {
-    const int row = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    if (row >= n) return;
-    dense_row(n, M, b, x, row, threadIdx.x & 63);
+    const int row = blockIdx.x * blockDim.x + threadIdx.x;
+    if (row < n) x[row] = dense_row(n, MT, b, row);
 }
 
 // ---------------------------------------------------------------------------
@@ -812,7 +841,7 @@ __device__ __forceinline__ void subcycle_phase(int op, const AmgLevel &F, const 
         for (int t = tid; t < 2 * F.half + F.nw; t += nt) correct_item(F, C, t);
     } else {
         const int n = 2 * F.half + F.nw;
-        for (int row = wave; row < n; row += nwaves) dense_row(n, Minv, F.b, F.x, row, lane);
+        for (int row = tid; row < n; row += nt) F.x[row] = dense_row(n, Minv, F.b, row);
     }
 }
 
@@ -979,11 +1008,11 @@ static void extract_impl(hipStream_t s, int nb, const AmgLevel &L, Grid g, Wells
                          double *wq, LT *ap) {
     const long n = (long)g.n + L.nw;
     if (nb == 2)
-        hipLaunchKernelGGL((k_amg_extract<2, LT>), grid_for(n, kBlock), dim3(kBlock), 0, s, L, g, w,
-                           sys, wq, ap);
+        hipLaunchKernelGGL((k_amg_extract<2, LT>), grid_for(8 * n, kBlock), dim3(kBlock), 0, s, L, g,
+                           w, sys, wq, ap);
     else
-        hipLaunchKernelGGL((k_amg_extract<3, LT>), grid_for(n, kBlock), dim3(kBlock), 0, s, L, g, w,
-                           sys, wq, ap);
+        hipLaunchKernelGGL((k_amg_extract<3, LT>), grid_for(8 * n, kBlock), dim3(kBlock), 0, s, L, g,
+                           w, sys, wq, ap);
 }
 
 void launch_amg_extract(hipStream_t s, int nb, const AmgLevel &L, Grid g, Wells w, Sys sys,
@@ -1035,7 +1064,7 @@ hipError_t dense_allow_lds() {
 
 void launch_amg_coarsest_solve(hipStream_t s, const AmgLevel &L, const double *Minv) {
     const int n = 2 * L.half + L.nw;
-    hipLaunchKernelGGL(k_dense_gemv, grid_for((long)n * 64, 256), dim3(256), 0, s, n, Minv, L.b, L.x);
+    hipLaunchKernelGGL(k_dense_gemv, grid_for((long)n, 256), dim3(256), 0, s, n, Minv, L.b, L.x);
 }
 
 void launch_amg_sweep(hipStream_t s, const AmgLevel &L, const AmgLevel &C, int color, int mode) {
