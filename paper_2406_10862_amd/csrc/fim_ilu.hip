@@ -131,44 +131,54 @@ __device__ inline int rec_at(const RecPos &p, int j, int w) {
     return p.start + (j / w) * p.stride + j % w;
 }
 
-// The same factorisation for a cell row without well columns, found from
-// the row's position (lo, up: the tile's sweep records, pl, pu: the row's
-// places in them): on a 7-point pattern the only entry ILU(0) changes
-// besides the lower blocks is the diagonal, D_i = A_ii - sum_k L_ik U_ki
-// over the lower neighbours k of the tile (in column order -z, -y, -x),
-// with U_ki the +z / +y / +x block of row k.  Returns false (nothing done)
-// for rows with well columns.
+// The same factorisation for a cell row, found from the row's position and
+// read from A directly (the row is not copied first): on a 7-point pattern
+// ILU(0) changes, besides the lower blocks L_ik = A_ik inv(U_kk), only the
+// diagonal, D_i = A_ii - sum_k L_ik U_ki over the lower neighbours k of the
+// tile (in column order -z, -y, -x; U_ki the +z / +y / +x block of row k,
+// A's own), and the columns of wells of the tile that perforate both i and
+// k, A_iw -= L_ik U_kw.  The upper blocks are A's.  The row's blocks go to
+// lu (couplings leaving the tile unchanged) and, when lo / up are given,
+// to the tile's sweep records at pl / pu.
 template <int NB, class LT>
-__device__ bool factor_cell_row(int i, int j, int k, const Grid &g, const IluTiles &T,
-                                const TileBox &tb, const Sys &sys, LT *lu, int *bad,
+__device__ void factor_cell_row(int i, int j, int k, const Grid &g, const IluTiles &T,
+                                const TileBox &tb, int tile, const Sys &sys, LT *lu, int *bad,
                                 LT *lo = nullptr, LT *up = nullptr, RecPos pl = {}, RecPos pu = {}) {
     constexpr int W = 16 / sizeof(LT);
     constexpr int B2 = NB * NB;
+    const double *A = sys.val;
     const int r = i + g.nx * (j + g.ny * k);
-    const int q0 = sys.rowptr[r];
+    const int q0 = sys.rowptr[r], q1 = sys.rowptr[r + 1];
     const int nlow = (k > 0) + (j > 0) + (i > 0);
     const int nup = (i + 1 < g.nx) + (j + 1 < g.ny) + (k + 1 < g.nz);
-    if (sys.rowptr[r + 1] - q0 != nlow + 1 + nup) return false;
     const int qd = q0 + nlow;
     double d[B2];
 #pragma unroll
-    for (int e = 0; e < B2; ++e) d[e] = (double)lu[(size_t)qd * B2 + e];
+    for (int e = 0; e < B2; ++e) d[e] = A[(size_t)qd * B2 + e];
     const int li = i - tb.i0, lj = j - tb.j0, lk = k - tb.k0;
-    if (up) {
-        // sweep records: the upper blocks (unchanged by the factorisation),
-        // zero where the neighbour lies outside the tile
+    {
+        // upper blocks: A's, into lu and (zero where the neighbour lies
+        // outside the tile) into the sweep record
         const int qux = qd + 1, quy = qux + (i + 1 < g.nx), quz = quy + (j + 1 < g.ny);
-        const bool hx = li + 1 < tb.txe, hy = lj + 1 < tb.tye, hz = lk + 1 < tb.tze;
+        const bool ex[3] = {i + 1 < g.nx, j + 1 < g.ny, k + 1 < g.nz};
+        const bool hin[3] = {li + 1 < tb.txe, lj + 1 < tb.tye, lk + 1 < tb.tze};
+        const int qu[3] = {qux, quy, quz};
 #pragma unroll
-        for (int e = 0; e < B2; ++e) {
-            const LT vx = lu[(size_t)(hx ? qux : qd) * B2 + e];
-            const LT vy = lu[(size_t)(hy ? quy : qd) * B2 + e];
-            const LT vz = lu[(size_t)(hz ? quz : qd) * B2 + e];
-            up[rec_at(pu, B2 + e, W)] = hx ? vx : (LT)0;
-            up[rec_at(pu, 2 * B2 + e, W)] = hy ? vy : (LT)0;
-            up[rec_at(pu, 3 * B2 + e, W)] = hz ? vz : (LT)0;
+        for (int m = 0; m < 3; ++m) {
+#pragma unroll
+            for (int e = 0; e < B2; ++e) {
+                const double v = A[(size_t)(ex[m] ? qu[m] : qd) * B2 + e];
+                if (ex[m]) lu[(size_t)qu[m] * B2 + e] = (LT)v;
+                if (up) up[rec_at(pu, (m + 1) * B2 + e, W)] = hin[m] ? (LT)v : (LT)0;
+            }
         }
     }
+    // the row's well columns (perforated cells): A's values, updated below
+    // for wells of this tile
+    const int qw0 = qd + 1 + nup;
+    for (int q = qw0; q < q1; ++q)
+#pragma unroll
+        for (int e = 0; e < B2; ++e) lu[(size_t)q * B2 + e] = (LT)A[(size_t)q * B2 + e];
     // lower neighbours in column order; for each: its row index, the
     // position of its diagonal and of its block towards row r
     int qk = q0;
@@ -183,25 +193,49 @@ __device__ bool factor_cell_row(int i, int j, int k, const Grid &g, const IluTil
         if (in) {
             const int ki = i - (dir == 2), kj = j - (dir == 1), kk = k - (dir == 0);
             const int rk = r - (dir == 0 ? g.nx * g.ny : (dir == 1 ? g.nx : 1));
-            const int qdk = sys.rowptr[rk] + (kk > 0) + (kj > 0) + (ki > 0);
-            // U_ki: +x, +y or +z block of row k
+            const int qk0 = sys.rowptr[rk];
+            const int qdk = qk0 + (kk > 0) + (kj > 0) + (ki > 0);
+            // U_ki: +x, +y or +z block of row k (A's)
             const int qki = qdk + 1 + (dir <= 1 ? (ki + 1 < g.nx) : 0) + (dir == 0 ? (kj + 1 < g.ny) : 0);
             double a[B2], u[B2], l[B2], uk[B2], p[B2];
 #pragma unroll
             for (int e = 0; e < B2; ++e) {
-                a[e] = (double)lu[(size_t)qk * B2 + e];
+                a[e] = A[(size_t)qk * B2 + e];
                 u[e] = (double)lu[(size_t)qdk * B2 + e];
+                uk[e] = A[(size_t)qki * B2 + e];
             }
             block_mul<NB>(a, u, l);
 #pragma unroll
             for (int e = 0; e < B2; ++e) {
                 lu[(size_t)qk * B2 + e] = (LT)l[e];
                 if (lo) lo[rec_at(pl, dir * B2 + e, W)] = (LT)l[e];
-                uk[e] = (double)lu[(size_t)qki * B2 + e];
             }
             block_mul<NB>(l, uk, p);
 #pragma unroll
             for (int e = 0; e < B2; ++e) d[e] -= p[e];
+            // shared well columns: A_iw -= L_ik U_kw (row k's well blocks
+            // follow its 7-point part)
+            if (qw0 < q1) {
+                const int nupk = (ki + 1 < g.nx) + (kj + 1 < g.ny) + (kk + 1 < g.nz);
+                const int qkw0 = qdk + 1 + nupk, qk1 = sys.rowptr[rk + 1];
+                for (int q = qw0; q < q1; ++q) {
+                    const int col = sys.colind[q];
+                    if (T.rtile[col] != tile) continue;
+                    for (int qq = qkw0; qq < qk1; ++qq) {
+                        if (sys.colind[qq] != col) continue;
+                        double ukw[B2], pw[B2];
+#pragma unroll
+                        for (int e = 0; e < B2; ++e) ukw[e] = (double)lu[(size_t)qq * B2 + e];
+                        block_mul<NB>(l, ukw, pw);
+#pragma unroll
+                        for (int e = 0; e < B2; ++e)
+                            lu[(size_t)q * B2 + e] = (LT)((double)lu[(size_t)q * B2 + e] - pw[e]);
+                    }
+                }
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < B2; ++e) lu[(size_t)qk * B2 + e] = (LT)A[(size_t)qk * B2 + e];
         }
         ++qk;
     }
@@ -216,7 +250,6 @@ __device__ bool factor_cell_row(int i, int j, int k, const Grid &g, const IluTil
         lu[(size_t)qd * B2 + e] = (LT)inv[e];
         if (up) up[rec_at(pu, e, W)] = (LT)inv[e];
     }
-    return true;
 }
 
 // inverse of the diagonal block of a row that is a subdomain of its own
@@ -299,43 +332,10 @@ __device__ void ilu_rank_table(const TileBox &tb, const IluTiles &T, int *roff) 
     __syncthreads();
 }
 
-// Write the sweep records of cell (li, lj, lk) of tile b from its finished
-// row (rows with well columns; the others write theirs while factored).
-template <int NB, class LT>
-__device__ inline void pack_cell(const Grid &g, const IluTiles &T, const TileBox &tb,
-                                 const Sys &sys, LT *lu, int b, int li, int lj, int lk,
-                                 const int *roff) {
-    constexpr int B2 = NB * NB;
-    const int i = tb.i0 + li, j = tb.j0 + lj, k = tb.k0 + lk;
-    const int qz = sys.rowptr[i + g.nx * (j + g.ny * k)];
-    const int qy = qz + (k > 0), qx = qy + (j > 0), qd = qx + (i > 0);
-    const int qux = qd + 1, quy = qux + (i + 1 < g.nx), quz = quy + (j + 1 < g.ny);
-    const int src[7] = {lk > 0 ? qz : -1, lj > 0 ? qy : -1, li > 0 ? qx : -1, qd,
-                        li + 1 < tb.txe ? qux : -1, lj + 1 < tb.tye ? quy : -1,
-                        lk + 1 < tb.tze ? quz : -1};
-    const int s = li + lj + lk;
-    constexpr int W = 16 / sizeof(LT);
-    const RecPos pl = rec_pos(T, roff, s, li, lj, rec_elems(3, NB, sizeof(LT)), W);
-    const RecPos pu = rec_pos(T, roff, s, li, lj, rec_elems(4, NB, sizeof(LT)), W);
-    char *base = reinterpret_cast<char *>(lu);
-    LT *lo = reinterpret_cast<LT *>(base + rec_region(T, NB, sizeof(LT), b, false));
-    LT *up = reinterpret_cast<LT *>(base + rec_region(T, NB, sizeof(LT), b, true));
-#pragma unroll
-    for (int m = 0; m < 7; ++m) {
-        const int q = src[m] >= 0 ? src[m] : qd;
-#pragma unroll
-        for (int e = 0; e < B2; ++e) {
-            const LT v = src[m] >= 0 ? lu[(size_t)q * B2 + e] : (LT)0;
-            if (m < 3) lo[rec_at(pl, m * B2 + e, W)] = v;
-            else up[rec_at(pu, (m - 3) * B2 + e, W)] = v;
-        }
-    }
-}
-
 // One workgroup per tile, then one for the wells that stand alone.  The
-// tile's rows (cells and its wells) are copied from A first, each x-row of
-// the tile being one contiguous run of blocks.  Tiles with sweep records
-// write each cell's as soon as its row is factored.
+// tile's well rows are copied from A first; its cell rows are read from A
+// as they are factored, hyperplane by hyperplane, and tiles with sweep
+// records write each cell's as soon as its row is done.
 template <int NB, class LT>
 __global__ __launch_bounds__(256) void k_ilu_factor(Grid g, IluTiles T, Sys sys, LT *lu,
                                                     int *bad) {
@@ -355,11 +355,8 @@ __global__ __launch_bounds__(256) void k_ilu_factor(Grid g, IluTiles T, Sys sys,
     const TileBox tb = tile_box(g, T, b);
     extern __shared__ int roff[];
     if (T.poff >= 0) ilu_rank_table(tb, T, roff);
-    for (int seg = 0; seg < tb.tye * tb.tze; ++seg) {
-        const int j = tb.j0 + seg % tb.tye, k = tb.k0 + seg / tb.tye;
-        const int r0 = tb.i0 + g.nx * (j + g.ny * k);
-        copy_blocks(sys.val, lu, sys.rowptr[r0], sys.rowptr[r0 + tb.txe], B2);
-    }
+    // the tile's well rows are factored in place after its cells (the cell
+    // rows are read from A as they are factored)
     for (int e = T.twp[b]; e < T.twp[b + 1]; ++e) {
         const int r = g.n + T.tw[e];
         copy_blocks(sys.val, lu, sys.rowptr[r], sys.rowptr[r + 1], B2);
@@ -381,11 +378,7 @@ __global__ __launch_bounds__(256) void k_ilu_factor(Grid g, IluTiles T, Sys sys,
                 lo = reinterpret_cast<LT *>(base + rec_region(T, NB, sizeof(LT), b, false));
                 up = reinterpret_cast<LT *>(base + rec_region(T, NB, sizeof(LT), b, true));
             }
-            if (!factor_cell_row<NB, LT>(i, j, k, g, T, tb, sys, lu, bad, lo, up, pl, pu)) {
-                factor_row<NB, LT>(i + g.nx * (j + g.ny * k), T, sys, lu, bad);
-                // a row with well columns: its records from the finished row
-                if (T.poff >= 0) pack_cell<NB, LT>(g, T, tb, sys, lu, b, li, lj, lk, roff);
-            }
+            factor_cell_row<NB, LT>(i, j, k, g, T, tb, b, sys, lu, bad, lo, up, pl, pu);
         }
         __syncthreads();
     }
