@@ -987,14 +987,17 @@ static void build_ilu(fim_ctx *c) {
     // sweep records for tiles whose pencils fit one workgroup
     T.psteps = T.tx + T.ty + T.tz - 2;
     T.prec = T.tx * T.ty * T.tz;
-    T.poff = (T.tx * T.ty <= 256 && ilu_rank_ints(T) <= 4096)
+    T.nnzb = c->nnzb;
+    // (byte offsets of the raw buffers over A and the factors stay below 2^31)
+    T.poff = (T.tx * T.ty <= 256 && ilu_rank_ints(T) <= 4096 &&
+              (double)c->nnzb * c->nb * c->nb * sizeof(double) < 2147483648.0)
                  ? ((long)c->nnzb * c->nb * c->nb + 3) / 4 * 4 : -1;
     int dev = 0, lds_max = 0;
     HIPCHECK(hipGetDevice(&dev));
     HIPCHECK(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    REQUIRE(ilu_solve_lds(c->nb, T) <= (size_t)lds_max,
+    REQUIRE(ilu_solve_lds(c->nb, T) <= (size_t)lds_max && ilu_factor_lds(c->nb, T) <= (size_t)lds_max,
             "ILU(0) tile %d x %d x %d needs %zu bytes of LDS (at most %d)", T.tx, T.ty, T.tz,
-            ilu_solve_lds(c->nb, T), lds_max);
+            std::max(ilu_solve_lds(c->nb, T), ilu_factor_lds(c->nb, T)), lds_max);
     T.rtile = c->upload(rtile.data(), rtile.size());
     T.twp = c->upload(twp.data(), twp.size());
     T.tw = c->upload(tw.data(), std::max<size_t>(tw.size(), 1));

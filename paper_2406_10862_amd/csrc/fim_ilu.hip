@@ -24,6 +24,37 @@
 
 namespace fim {
 
+// Third word of a raw buffer resource on this architecture (32-bit data,
+// no swizzle).  Its range check gives zeros for loads and drops stores at
+// or past num_records, without a memory access: the sweeps and the
+// factorisation use that for lanes without a row at a step.
+constexpr int kBufferWord3 = 0x00020000;
+typedef unsigned int bu2 __attribute__((ext_vector_type(2)));
+
+__device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void *p, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, (int)bytes, kBufferWord3);
+}
+__device__ inline double buf_ld(__amdgpu_buffer_rsrc_t rs, int off) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+}
+template <class LT>
+__device__ inline void buf_st(__amdgpu_buffer_rsrc_t rs, int off, double v) {
+    if constexpr (sizeof(LT) == 8)
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(bu2, v), rs, off, 0, 0);
+    else
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, (float)v), rs, off, 0, 0);
+}
+
+// Workgroup barrier ordering LDS only.  __syncthreads() also orders global
+// memory, so it waits for every load in flight, the sweep prefetches
+// included; the sweeps and the pencil factorisation exchange values through LDS
+// alone.
+__device__ inline void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 struct TileBox {
     int i0, j0, k0, txe, tye, tze;   // origin and extents (clipped at the grid edge)
 };
@@ -303,7 +334,7 @@ size_t ilu_factor_elems(int nb, long nnzb, const IluTiles &T, int esize) {
                                 (rec_elems(3, nb, esize) + rec_elems(4, nb, esize));
 }
 
-int ilu_rank_ints(const IluTiles &T) { return T.psteps * T.ty + 2 * T.psteps; }
+__host__ __device__ int ilu_rank_ints(const IluTiles &T) { return T.psteps * T.ty + 2 * T.psteps; }
 
 // Numbering of a tile's cells: step by step (s = li + lj + lk), and within
 // a step by (lj, li).  roff[s * T.ty + lj] + li is the number of cell
@@ -332,6 +363,218 @@ __device__ void ilu_rank_table(const TileBox &tb, const IluTiles &T, int *roff) 
     __syncthreads();
 }
 
+// 16 bytes (two doubles or four floats of a block row-major) to raw buffer
+// rs at byte offset off, from v[0..16/sizeof(LT))
+template <class LT>
+__device__ inline void buf_st16(__amdgpu_buffer_rsrc_t rs, int off, const double *v) {
+    typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+    if constexpr (sizeof(LT) == 8) {
+        const double w[2] = {v[0], v[1]};
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, w), rs, off, 0, 0);
+    } else {
+        const float w[4] = {(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, w), rs, off, 0, 0);
+    }
+}
+
+// The hyperplane walk of a tile with sweep records and 2x2 blocks, one
+// pencil per thread: the arithmetic of factor_cell_row, row by row in the
+// same order, with the inverted pivot and the +x / +y blocks of each
+// finished row handed to the threads of the next hyperplane through LDS
+// (the -z ones stay in the thread's registers) and the A blocks of a
+// thread's next row loaded one step ahead.  Every lane runs every step, on
+// its nearest row when it has none at that step, with its loads and stores
+// then at the end of raw buffers (zeros, dropped), so no branch separates a
+// load from its use.  Tiles with wells of their own order global memory
+// between steps (their rows' well columns are updated from the finished rows
+// below them).
+template <class LT>
+__device__ void factor_pencils(const Grid &g, const IluTiles &T, const TileBox &tb, int b,
+                               const Sys &sys, LT *lu, long nnzb, int *bad, const int *roff,
+                               int *qrow, double *xch, bool wells) {
+    constexpr int NB = 2, B2 = 4, ES = sizeof(LT), W = 16 / ES;
+    constexpr int kEL = rec_elems(3, NB, ES), kEU = rec_elems(4, NB, ES);
+    const int nt = blockDim.x, tid = threadIdx.x;
+    const int sxy = tb.txe * tb.tye, ncell = sxy * tb.tze;
+    const bool own = tid < sxy;
+    const int li = own ? tid % tb.txe : 0, lj = own ? tid / tb.txe : 0;
+    const int i = tb.i0 + li, j = tb.j0 + lj;
+    const int s0 = li + lj, s1 = s0 + tb.tze - 1, nlev = tb.txe + tb.tye + tb.tze - 2;
+    int *qend = qrow + T.prec;
+    for (int l = tid; l < ncell; l += nt) {
+        const int a = l % tb.txe, c = (l / tb.txe) % tb.tye, e = l / sxy;
+        const int r = (tb.i0 + a) + g.nx * ((tb.j0 + c) + g.ny * (tb.k0 + e));
+        qrow[l] = sys.rowptr[r];
+        qend[l] = sys.rowptr[r + 1];
+    }
+    __syncthreads();
+    const unsigned abytes = (unsigned)((size_t)nnzb * B2 * sizeof(double));
+    const unsigned lbytes = (unsigned)((size_t)nnzb * B2 * ES);
+    const unsigned lobytes = (unsigned)(T.prec * kEL * ES), upbytes = (unsigned)(T.prec * kEU * ES);
+    char *base = reinterpret_cast<char *>(lu);
+    const __amdgpu_buffer_rsrc_t ra = make_rsrc(sys.val, abytes);
+    const __amdgpu_buffer_rsrc_t rl = make_rsrc(lu, lbytes);
+    const __amdgpu_buffer_rsrc_t rlo = make_rsrc(base + rec_region(T, NB, ES, b, false), lobytes);
+    const __amdgpu_buffer_rsrc_t rup = make_rsrc(base + rec_region(T, NB, ES, b, true), upbytes);
+    auto mine = [&](int s) { return own && s >= s0 && s <= s1; };
+    auto clampstep = [&](int s) { return s < s0 ? s0 : (s > s1 ? s1 : s); };
+    // the 7-point blocks of a row: -z, -y, -x, diagonal, +x, +y, +z
+    struct Row {
+        int q[7];
+        bool ex[7];
+    };
+    auto row_at = [&](int s) {
+        const int lk = clampstep(s) - s0, k = tb.k0 + lk;
+        Row R;
+        const int q0 = qrow[li + tb.txe * (lj + tb.tye * lk)];
+        R.ex[0] = k > 0; R.ex[1] = j > 0; R.ex[2] = i > 0; R.ex[3] = true;
+        R.ex[4] = i + 1 < g.nx; R.ex[5] = j + 1 < g.ny; R.ex[6] = k + 1 < g.nz;
+        R.q[0] = q0;
+        R.q[1] = R.q[0] + R.ex[0];
+        R.q[2] = R.q[1] + R.ex[1];
+        R.q[3] = R.q[2] + R.ex[2];
+        R.q[4] = R.q[3] + 1;
+        R.q[5] = R.q[4] + R.ex[4];
+        R.q[6] = R.q[5] + R.ex[5];
+        return R;
+    };
+    // A's blocks of the row at step s (zeros for a missing block or step)
+    auto load7 = [&](int s, double (&X)[7][B2]) {
+        const Row R = row_at(s);
+        const bool on = mine(s);
+#pragma unroll
+        for (int m = 0; m < 7; ++m) {
+            const int off = (on && R.ex[m]) ? R.q[m] * (B2 * 8) : (int)abytes;
+#pragma unroll
+            for (int e = 0; e < B2; ++e) X[m][e] = buf_ld(ra, off + 8 * e);
+        }
+    };
+    double pz_inv[B2] = {}, pz_u[B2] = {};        // the -z row: inverted pivot, +z block
+    auto step = [&](int s, const double (&X)[7][B2]) {
+        const bool on = mine(s);
+        const int lk = clampstep(s) - s0, k = tb.k0 + lk;
+        const int l = li + tb.txe * (lj + tb.tye * lk);
+        const Row R = row_at(s);
+        const bool in[3] = {lk > 0, lj > 0, li > 0};
+        const double *nby = xch + ((size_t)(((s - 1) & 1) * nt + (own && lj > 0 ? tid - tb.txe : tid))) * 3 * B2;
+        const double *nbx = xch + ((size_t)(((s - 1) & 1) * nt + (own && li > 0 ? tid - 1 : tid))) * 3 * B2;
+        double d[B2], L[3][B2];
+#pragma unroll
+        for (int e = 0; e < B2; ++e) d[e] = X[3][e];
+#pragma unroll
+        for (int dir = 0; dir < 3; ++dir) {
+            double u[B2], uk[B2];
+#pragma unroll
+            for (int e = 0; e < B2; ++e) {
+                u[e] = dir == 0 ? pz_inv[e] : (dir == 1 ? nby[e] : nbx[e]);
+                uk[e] = dir == 0 ? pz_u[e] : (dir == 1 ? nby[2 * B2 + e] : nbx[B2 + e]);
+            }
+            double l2[B2], p[B2];
+            block_mul<NB>(X[dir], u, l2);
+            block_mul<NB>(l2, uk, p);
+#pragma unroll
+            for (int e = 0; e < B2; ++e) {
+                L[dir][e] = in[dir] ? l2[e] : 0.0;
+                d[e] -= in[dir] ? p[e] : 0.0;
+            }
+        }
+        // well columns of a perforated row (tiles with wells of their own)
+        const int qw0 = R.q[6] + R.ex[6];
+        const int q1 = on ? qend[l] : qw0;
+        for (int q = qw0; q < q1; ++q) {
+            const int col = sys.colind[q];
+            double acc[B2];
+#pragma unroll
+            for (int e = 0; e < B2; ++e) acc[e] = (double)(LT)sys.val[(size_t)q * B2 + e];
+            if (T.rtile[col] == b)
+#pragma unroll
+                for (int dir = 0; dir < 3; ++dir) {
+                    if (!in[dir]) continue;
+                    const int rk = (i - (dir == 2)) + g.nx * ((j - (dir == 1)) + g.ny * (k - (dir == 0)));
+                    for (int qq = sys.rowptr[rk]; qq < sys.rowptr[rk + 1]; ++qq) {
+                        if (sys.colind[qq] != col) continue;
+                        double ukw[B2], pw[B2];
+#pragma unroll
+                        for (int e = 0; e < B2; ++e) ukw[e] = (double)lu[(size_t)qq * B2 + e];
+                        block_mul<NB>(L[dir], ukw, pw);
+#pragma unroll
+                        for (int e = 0; e < B2; ++e) acc[e] = (double)(LT)(acc[e] - pw[e]);
+                    }
+                }
+#pragma unroll
+            for (int e = 0; e < B2; ++e) lu[(size_t)q * B2 + e] = (LT)acc[e];
+        }
+        double inv[B2];
+        if (!invert_block<NB>(d, inv)) {
+            if (on) *bad = 1;
+#pragma unroll
+            for (int e = 0; e < B2; ++e) inv[e] = (e % (NB + 1) == 0) ? 1.0 : 0.0;
+        }
+        // the row in lu: L (A's block for a neighbour outside the tile), the
+        // inverted pivot, A's upper blocks
+        double blk[7][B2];
+#pragma unroll
+        for (int e = 0; e < B2; ++e) {
+#pragma unroll
+            for (int dir = 0; dir < 3; ++dir) blk[dir][e] = in[dir] ? L[dir][e] : X[dir][e];
+            blk[3][e] = inv[e];
+            blk[4][e] = X[4][e];
+            blk[5][e] = X[5][e];
+            blk[6][e] = X[6][e];
+        }
+#pragma unroll
+        for (int m = 0; m < 7; ++m) {
+            const int off = (on && R.ex[m]) ? R.q[m] * (B2 * ES) : (int)lbytes;
+#pragma unroll
+            for (int c = 0; c < B2 / W; ++c) buf_st16<LT>(rl, off + 16 * c, blk[m] + c * W);
+        }
+        // the sweep records (zero blocks towards neighbours outside the tile)
+        const bool hin[3] = {li + 1 < tb.txe, lj + 1 < tb.tye, lk + 1 < tb.tze};
+        double lo[kEL] = {}, up[kEU] = {};
+#pragma unroll
+        for (int e = 0; e < B2; ++e) {
+#pragma unroll
+            for (int dir = 0; dir < 3; ++dir) lo[dir * B2 + e] = L[dir][e];
+            up[e] = (double)(LT)inv[e];
+            up[B2 + e] = hin[0] ? X[4][e] : 0.0;
+            up[2 * B2 + e] = hin[1] ? X[5][e] : 0.0;
+            up[3 * B2 + e] = hin[2] ? X[6][e] : 0.0;
+        }
+        const int sc = clampstep(s);
+        const RecPos pl = rec_pos(T, roff, sc, li, lj, kEL, W), pu = rec_pos(T, roff, sc, li, lj, kEU, W);
+#pragma unroll
+        for (int c = 0; c < kEL / W; ++c)
+            buf_st16<LT>(rlo, on ? (pl.start + c * pl.stride) * ES : (int)lobytes, lo + c * W);
+#pragma unroll
+        for (int c = 0; c < kEU / W; ++c)
+            buf_st16<LT>(rup, on ? (pu.start + c * pu.stride) * ES : (int)upbytes, up + c * W);
+        // for the next hyperplane: this row's inverted pivot (as stored) and
+        // its +x, +y blocks in LDS, its +z block and pivot in registers
+        double *mine_slot = xch + ((size_t)((s & 1) * nt + tid)) * 3 * B2;
+#pragma unroll
+        for (int e = 0; e < B2; ++e) {
+            const double is = (double)(LT)inv[e];
+            mine_slot[e] = is;
+            mine_slot[B2 + e] = X[4][e];
+            mine_slot[2 * B2 + e] = X[5][e];
+            pz_inv[e] = is;
+            pz_u[e] = X[6][e];
+        }
+    };
+    double XA[7][B2], XB[7][B2];
+    load7(0, XA);
+    for (int s = 0; s < nlev; s += 2) {
+        load7(s + 1, XB);
+        step(s, XA);
+        if (wells) __syncthreads();
+        else lds_barrier();
+        load7(s + 2, XA);
+        step(s + 1, XB);
+        if (wells) __syncthreads();
+        else lds_barrier();
+    }
+}
+
 // One workgroup per tile, then one for the wells that stand alone.  The
 // tile's well rows are copied from A first; its cell rows are read from A
 // as they are factored, hyperplane by hyperplane, and tiles with sweep
@@ -353,7 +596,9 @@ __global__ __launch_bounds__(256) void k_ilu_factor(Grid g, IluTiles T, Sys sys,
         return;
     }
     const TileBox tb = tile_box(g, T, b);
-    extern __shared__ int roff[];
+    extern __shared__ double fsm[];
+    double *xch = fsm;                                   // pencil path: 2 x threads x 3 blocks
+    int *roff = reinterpret_cast<int *>(fsm + (NB == 2 ? (size_t)2 * blockDim.x * 3 * B2 : 0));
     if (T.poff >= 0) ilu_rank_table(tb, T, roff);
     // the tile's well rows are factored in place after its cells (the cell
     // rows are read from A as they are factored)
@@ -362,6 +607,16 @@ __global__ __launch_bounds__(256) void k_ilu_factor(Grid g, IluTiles T, Sys sys,
         copy_blocks(sys.val, lu, sys.rowptr[r], sys.rowptr[r + 1], B2);
     }
     __syncthreads();
+    if constexpr (NB == 2) {
+        if (T.poff >= 0) {
+            factor_pencils<LT>(g, T, tb, b, sys, lu, T.nnzb, bad, roff, roff + ilu_rank_ints(T), xch,
+                               T.twp[b + 1] > T.twp[b]);
+            __syncthreads();
+            for (int e = T.twp[b] + threadIdx.x; e < T.twp[b + 1]; e += blockDim.x)
+                factor_row<NB, LT>(g.n + T.tw[e], T, sys, lu, bad);
+            return;
+        }
+    }
     const int nlev = tb.txe + tb.tye + tb.tze - 2;
     for (int s = 0; s < nlev; ++s) {
         for (int p = threadIdx.x; p < tb.txe * tb.tye; p += blockDim.x) {
@@ -489,10 +744,6 @@ __device__ void solve_tile_wells(const Grid &g, const TileBox &tb, const Sys &sy
     }
 }
 
-// Third word of a raw buffer resource on this architecture (32-bit data,
-// no swizzle); the range check returns zeros past num_records.
-constexpr int kBufferWord3 = 0x00020000;
-
 // The NBLK blocks of a sweep record: 16-byte chunk c at byte offset
 // off + c * stride of buffer rs (an offset past the buffer's end gives
 // zeros, without a memory access).
@@ -509,15 +760,6 @@ __device__ inline void load_rec(Blk<NB> (&X)[NBLK], __amdgpu_buffer_rsrc_t rs, i
     for (int m = 0; m < NBLK; ++m)
 #pragma unroll
         for (int q = 0; q < B2; ++q) X[m].v[q] = (double)e[m * B2 + q];
-}
-
-// Workgroup barrier ordering LDS only.  __syncthreads() also orders global
-// memory, so it waits for every load in flight, the sweep prefetches
-// included; the sweeps exchange values through LDS alone.
-__device__ inline void lds_barrier() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-    __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 // Both sweeps over the cells of a tile whose (li, lj) pencils fit the
@@ -816,9 +1058,11 @@ static void ilu_factor_impl(hipStream_t s, int nb, Grid g, const IluTiles &T, Sy
                             int *bad) {
     const int nblk = T.ntx * T.nty * T.ntz + (T.nsingle > 0 ? 1 : 0);
     const int bs = ilu_threads(T);
-    const size_t lds = T.poff >= 0 ? (size_t)ilu_rank_ints(T) * sizeof(int) : 0;
-    if (nb == 2) hipLaunchKernelGGL((k_ilu_factor<2, LT>), dim3(nblk), dim3(bs), lds, s, g, T, sys, lu, bad);
-    else hipLaunchKernelGGL((k_ilu_factor<3, LT>), dim3(nblk), dim3(bs), lds, s, g, T, sys, lu, bad);
+    const size_t lds = ilu_factor_lds(nb, T);
+    if (nb == 2)
+        hipLaunchKernelGGL((k_ilu_factor<2, LT>), dim3(nblk), dim3(bs), lds, s, g, T, sys, lu, bad);
+    else
+        hipLaunchKernelGGL((k_ilu_factor<3, LT>), dim3(nblk), dim3(bs), lds, s, g, T, sys, lu, bad);
 }
 
 void launch_ilu_factor(hipStream_t s, int nb, Grid g, const IluTiles &T, Sys sys, double *lu,
@@ -829,6 +1073,15 @@ void launch_ilu_factor(hipStream_t s, int nb, Grid g, const IluTiles &T, Sys sys
 void launch_ilu_factor(hipStream_t s, int nb, Grid g, const IluTiles &T, Sys sys, float *lu,
                        int *bad) {
     ilu_factor_impl(s, nb, g, T, sys, lu, bad);
+}
+
+// LDS of the factorisation: the exchange slots and row starts / ends of the
+// pencil path (2x2 blocks), then the record order
+size_t ilu_factor_lds(int nb, const IluTiles &T) {
+    if (T.poff < 0) return 0;
+    const size_t xch = nb == 2 ? (size_t)2 * ilu_threads(T) * 3 * nb * nb * sizeof(double) : 0;
+    const size_t rows = nb == 2 ? (size_t)2 * T.prec * sizeof(int) : 0;
+    return xch + (size_t)ilu_rank_ints(T) * sizeof(int) + rows;
 }
 
 int ilu_threads(const IluTiles &T) {
@@ -846,11 +1099,21 @@ size_t ilu_solve_lds(int nb, const IluTiles &T) {
 
 template <class LT, class VT>
 static hipError_t allow_lds_impl(int nb, size_t bytes) {
-    if (nb == 2)
-        return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ilu_solve<2, LT, VT>),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ilu_solve<3, LT, VT>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    hipError_t e;
+    if (nb == 2) {
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ilu_solve<2, LT, VT>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ilu_factor<2, LT>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        return e;
+    }
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ilu_solve<3, LT, VT>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ilu_factor<3, LT>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    return e;
 }
 
 hipError_t ilu_allow_lds(int nb, size_t bytes) {

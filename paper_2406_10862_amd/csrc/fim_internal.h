@@ -224,9 +224,12 @@ struct IluTiles {
     // sweeps.
     long poff;
     int psteps, prec;
+    long nnzb;                  // blocks of A
 };
+// LDS bytes of the factorisation kernel
+size_t ilu_factor_lds(int nb, const IluTiles &T);
 // ints of LDS the record order of a tile takes (see ilu_rank_table)
-int ilu_rank_ints(const IluTiles &T);
+__host__ __device__ int ilu_rank_ints(const IluTiles &T);
 // elements of esize bytes in the factor buffer (the factors in the layout
 // of A, then the sweep records when T.poff >= 0)
 size_t ilu_factor_elems(int nb, long nnzb, const IluTiles &T, int esize);
