@@ -438,20 +438,25 @@ __device__ void factor_pencils(const Grid &g, const IluTiles &T, const TileBox &
         R.q[6] = R.q[5] + R.ex[5];
         return R;
     };
-    // A's blocks of the row at step s (zeros for a missing block or step)
-    auto load7 = [&](int s, double (&X)[7][B2]) {
+    // A's blocks m0 .. m0+nm-1 of the row at step s (zeros for a missing
+    // block or step)
+    auto loadA = [&](int s, int m0, int nm, double (*X)[B2]) {
         const Row R = row_at(s);
         const bool on = mine(s);
 #pragma unroll
-        for (int m = 0; m < 7; ++m) {
-            const int off = (on && R.ex[m]) ? R.q[m] * (B2 * 8) : (int)abytes;
+        for (int m = 0; m < 4; ++m) {
+            if (m >= nm) break;
+            const int off = (on && R.ex[m0 + m]) ? R.q[m0 + m] * (B2 * 8) : (int)abytes;
 #pragma unroll
             for (int e = 0; e < B2; ++e) X[m][e] = buf_ld(ra, off + 8 * e);
         }
     };
     double pz_inv[B2] = {}, pz_u[B2] = {};        // the -z row: inverted pivot, +z block
-    auto step = [&](int s, const double (&X)[7][B2]) {
+    auto step = [&](int s, const double (&X)[4][B2]) {
         const bool on = mine(s);
+        // the upper blocks, needed only at the end of the step
+        double U[3][B2];
+        loadA(s, 4, 3, U);
         const int lk = clampstep(s) - s0, k = tb.k0 + lk;
         const int l = li + tb.txe * (lj + tb.tye * lk);
         const Row R = row_at(s);
@@ -512,42 +517,41 @@ __device__ void factor_pencils(const Grid &g, const IluTiles &T, const TileBox &
         }
         // the row in lu: L (A's block for a neighbour outside the tile), the
         // inverted pivot, A's upper blocks
-        double blk[7][B2];
-#pragma unroll
-        for (int e = 0; e < B2; ++e) {
-#pragma unroll
-            for (int dir = 0; dir < 3; ++dir) blk[dir][e] = in[dir] ? L[dir][e] : X[dir][e];
-            blk[3][e] = inv[e];
-            blk[4][e] = X[4][e];
-            blk[5][e] = X[5][e];
-            blk[6][e] = X[6][e];
-        }
 #pragma unroll
         for (int m = 0; m < 7; ++m) {
             const int off = (on && R.ex[m]) ? R.q[m] * (B2 * ES) : (int)lbytes;
 #pragma unroll
-            for (int c = 0; c < B2 / W; ++c) buf_st16<LT>(rl, off + 16 * c, blk[m] + c * W);
+            for (int c = 0; c < B2 / W; ++c) {
+                double v[W];
+#pragma unroll
+                for (int w = 0; w < W; ++w) {
+                    const int e = c * W + w;
+                    v[w] = m < 3 ? (in[m] ? L[m][e] : X[m][e]) : (m == 3 ? inv[e] : U[m - 4][e]);
+                }
+                buf_st16<LT>(rl, off + 16 * c, v);
+            }
         }
         // the sweep records (zero blocks towards neighbours outside the tile)
         const bool hin[3] = {li + 1 < tb.txe, lj + 1 < tb.tye, lk + 1 < tb.tze};
-        double lo[kEL] = {}, up[kEU] = {};
-#pragma unroll
-        for (int e = 0; e < B2; ++e) {
-#pragma unroll
-            for (int dir = 0; dir < 3; ++dir) lo[dir * B2 + e] = L[dir][e];
-            up[e] = (double)(LT)inv[e];
-            up[B2 + e] = hin[0] ? X[4][e] : 0.0;
-            up[2 * B2 + e] = hin[1] ? X[5][e] : 0.0;
-            up[3 * B2 + e] = hin[2] ? X[6][e] : 0.0;
-        }
         const int sc = clampstep(s);
         const RecPos pl = rec_pos(T, roff, sc, li, lj, kEL, W), pu = rec_pos(T, roff, sc, li, lj, kEU, W);
 #pragma unroll
-        for (int c = 0; c < kEL / W; ++c)
-            buf_st16<LT>(rlo, on ? (pl.start + c * pl.stride) * ES : (int)lobytes, lo + c * W);
+        for (int c = 0; c < kEL / W; ++c) {
+            double v[W];
 #pragma unroll
-        for (int c = 0; c < kEU / W; ++c)
-            buf_st16<LT>(rup, on ? (pu.start + c * pu.stride) * ES : (int)upbytes, up + c * W);
+            for (int w = 0; w < W; ++w) v[w] = L[(c * W + w) / B2][(c * W + w) % B2];
+            buf_st16<LT>(rlo, on ? (pl.start + c * pl.stride) * ES : (int)lobytes, v);
+        }
+#pragma unroll
+        for (int c = 0; c < kEU / W; ++c) {
+            double v[W];
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                const int m = (c * W + w) / B2, e = (c * W + w) % B2;
+                v[w] = m == 0 ? inv[e] : (hin[m - 1] ? U[m - 1][e] : 0.0);
+            }
+            buf_st16<LT>(rup, on ? (pu.start + c * pu.stride) * ES : (int)upbytes, v);
+        }
         // for the next hyperplane: this row's inverted pivot (as stored) and
         // its +x, +y blocks in LDS, its +z block and pivot in registers
         double *mine_slot = xch + ((size_t)((s & 1) * nt + tid)) * 3 * B2;
@@ -555,20 +559,20 @@ __device__ void factor_pencils(const Grid &g, const IluTiles &T, const TileBox &
         for (int e = 0; e < B2; ++e) {
             const double is = (double)(LT)inv[e];
             mine_slot[e] = is;
-            mine_slot[B2 + e] = X[4][e];
-            mine_slot[2 * B2 + e] = X[5][e];
+            mine_slot[B2 + e] = U[0][e];
+            mine_slot[2 * B2 + e] = U[1][e];
             pz_inv[e] = is;
-            pz_u[e] = X[6][e];
+            pz_u[e] = U[2][e];
         }
     };
-    double XA[7][B2], XB[7][B2];
-    load7(0, XA);
+    double XA[4][B2], XB[4][B2];                 // lower and diagonal blocks, a step ahead
+    loadA(0, 0, 4, XA);
     for (int s = 0; s < nlev; s += 2) {
-        load7(s + 1, XB);
+        loadA(s + 1, 0, 4, XB);
         step(s, XA);
         if (wells) __syncthreads();
         else lds_barrier();
-        load7(s + 2, XA);
+        loadA(s + 2, 0, 4, XA);
         step(s + 1, XB);
         if (wells) __syncthreads();
         else lds_barrier();
