@@ -163,7 +163,8 @@ __device__ inline int rec_at(const RecPos &p, int j, int w) {
 }
 
 // The same factorisation for a cell row, found from the row's position and
-// read from A directly (the row is not copied first): on a 7-point pattern
+// read from A's values at A (A itself, or the row's copy in lu): on a
+// 7-point pattern
 // ILU(0) changes, besides the lower blocks L_ik = A_ik inv(U_kk), only the
 // diagonal, D_i = A_ii - sum_k L_ik U_ki over the lower neighbours k of the
 // tile (in column order -z, -y, -x; U_ki the +z / +y / +x block of row k,
@@ -171,13 +172,13 @@ __device__ inline int rec_at(const RecPos &p, int j, int w) {
 // k, A_iw -= L_ik U_kw.  The upper blocks are A's.  The row's blocks go to
 // lu (couplings leaving the tile unchanged) and, when lo / up are given,
 // to the tile's sweep records at pl / pu.
-template <int NB, class LT>
+template <int NB, class LT, class ST>
 __device__ void factor_cell_row(int i, int j, int k, const Grid &g, const IluTiles &T,
-                                const TileBox &tb, int tile, const Sys &sys, LT *lu, int *bad,
-                                LT *lo = nullptr, LT *up = nullptr, RecPos pl = {}, RecPos pu = {}) {
+                                const TileBox &tb, int tile, const Sys &sys, const ST *A, LT *lu,
+                                int *bad, LT *lo = nullptr, LT *up = nullptr, RecPos pl = {},
+                                RecPos pu = {}) {
     constexpr int W = 16 / sizeof(LT);
     constexpr int B2 = NB * NB;
-    const double *A = sys.val;
     const int r = i + g.nx * (j + g.ny * k);
     const int q0 = sys.rowptr[r], q1 = sys.rowptr[r + 1];
     const int nlow = (k > 0) + (j > 0) + (i > 0);
@@ -185,7 +186,7 @@ __device__ void factor_cell_row(int i, int j, int k, const Grid &g, const IluTil
     const int qd = q0 + nlow;
     double d[B2];
 #pragma unroll
-    for (int e = 0; e < B2; ++e) d[e] = A[(size_t)qd * B2 + e];
+    for (int e = 0; e < B2; ++e) d[e] = (double)A[(size_t)qd * B2 + e];
     const int li = i - tb.i0, lj = j - tb.j0, lk = k - tb.k0;
     {
         // upper blocks: A's, into lu and (zero where the neighbour lies
@@ -198,7 +199,7 @@ __device__ void factor_cell_row(int i, int j, int k, const Grid &g, const IluTil
         for (int m = 0; m < 3; ++m) {
 #pragma unroll
             for (int e = 0; e < B2; ++e) {
-                const double v = A[(size_t)(ex[m] ? qu[m] : qd) * B2 + e];
+                const double v = (double)A[(size_t)(ex[m] ? qu[m] : qd) * B2 + e];
                 if (ex[m]) lu[(size_t)qu[m] * B2 + e] = (LT)v;
                 if (up) up[rec_at(pu, (m + 1) * B2 + e, W)] = hin[m] ? (LT)v : (LT)0;
             }
@@ -231,9 +232,9 @@ __device__ void factor_cell_row(int i, int j, int k, const Grid &g, const IluTil
             double a[B2], u[B2], l[B2], uk[B2], p[B2];
 #pragma unroll
             for (int e = 0; e < B2; ++e) {
-                a[e] = A[(size_t)qk * B2 + e];
+                a[e] = (double)A[(size_t)qk * B2 + e];
                 u[e] = (double)lu[(size_t)qdk * B2 + e];
-                uk[e] = A[(size_t)qki * B2 + e];
+                uk[e] = (double)A[(size_t)qki * B2 + e];
             }
             block_mul<NB>(a, u, l);
 #pragma unroll
@@ -621,6 +622,14 @@ __global__ __launch_bounds__(256) void k_ilu_factor(Grid g, IluTiles T, Sys sys,
             return;
         }
     }
+    // other tiles: the cell rows copied first (each x-row of the tile one
+    // contiguous run of blocks), then factored in place from the copy
+    for (int seg = 0; seg < tb.tye * tb.tze; ++seg) {
+        const int j = tb.j0 + seg % tb.tye, k = tb.k0 + seg / tb.tye;
+        const int r0 = tb.i0 + g.nx * (j + g.ny * k);
+        copy_blocks(sys.val, lu, sys.rowptr[r0], sys.rowptr[r0 + tb.txe], B2);
+    }
+    __syncthreads();
     const int nlev = tb.txe + tb.tye + tb.tze - 2;
     for (int s = 0; s < nlev; ++s) {
         for (int p = threadIdx.x; p < tb.txe * tb.tye; p += blockDim.x) {
@@ -637,7 +646,7 @@ __global__ __launch_bounds__(256) void k_ilu_factor(Grid g, IluTiles T, Sys sys,
                 lo = reinterpret_cast<LT *>(base + rec_region(T, NB, sizeof(LT), b, false));
                 up = reinterpret_cast<LT *>(base + rec_region(T, NB, sizeof(LT), b, true));
             }
-            factor_cell_row<NB, LT>(i, j, k, g, T, tb, b, sys, lu, bad, lo, up, pl, pu);
+            factor_cell_row<NB, LT, LT>(i, j, k, g, T, tb, b, sys, lu, lu, bad, lo, up, pl, pu);
         }
         __syncthreads();
     }
