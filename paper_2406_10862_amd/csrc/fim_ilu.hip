@@ -790,26 +790,25 @@ __device__ void solve_cells_pencils(const Grid &g, const TileBox &tb, const Sys 
     int *re = rp + ncell;                          // row ends
     int *roff = re + ncell;                        // record order
     ilu_rank_table(tb, T, roff);
-    // two rows per thread at a time so their loads overlap
+    // two rows per thread at a time so their loads overlap (a slot past the
+    // tile's cells works on its last cell and stores nothing: no branch
+    // between the loads)
     for (int l0 = threadIdx.x; l0 < ncell; l0 += 2 * blockDim.x) {
         int rr[2], q0[2], q1[2];
-        bool on[2];
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            const int l = l0 + h * blockDim.x;
-            on[h] = l < ncell;
+            const int l = min(l0 + h * (int)blockDim.x, ncell - 1);
             const int li = l % tb.txe, lj = (l / tb.txe) % tb.tye, lk = l / sxy;
-            rr[h] = on[h] ? (tb.i0 + li) + g.nx * ((tb.j0 + lj) + g.ny * (tb.k0 + lk)) : 0;
-            q0[h] = on[h] ? sys.rowptr[rr[h]] : 0;
-            q1[h] = on[h] ? sys.rowptr[rr[h] + 1] : 0;
+            rr[h] = (tb.i0 + li) + g.nx * ((tb.j0 + lj) + g.ny * (tb.k0 + lk));
+            q0[h] = sys.rowptr[rr[h]];
+            q1[h] = sys.rowptr[rr[h] + 1];
         }
         double acc[2][NB];
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
-            if (on[h]) rhs_row<NB>(R, sys, rr[h], acc[h], q0[h], q1[h]);
+        for (int h = 0; h < 2; ++h) rhs_row<NB>(R, sys, rr[h], acc[h], q0[h], q1[h]);
 #pragma unroll
         for (int h = 0; h < 2; ++h)
-            if (on[h]) {
+            if (l0 + h * (int)blockDim.x < ncell) {
                 const int l = l0 + h * blockDim.x;
                 rp[l] = q0[h];
                 re[l] = q1[h];
