@@ -581,7 +581,6 @@ __device__ inline double sweep_value(const AmgLevel &L, const AmgLevel &C, int c
                                      int h) {
     const int s = color * L.half + h;
     const Pos p = pos_of(L, s);
-    if (p.i >= L.nx) return 0.0;
     const int stride = 2 * L.half;
     double acc = L.b[s];
 #pragma unroll
@@ -594,7 +593,9 @@ __device__ inline double sweep_value(const AmgLevel &L, const AmgLevel &C, int c
         const int sl = L.cslot[q];
         acc -= L.acw[sl] * read_well<M>(L, C, mode, L.swell[sl]);
     }
-    return acc / L.a[s];
+    // a padded cell (its neighbours in the grid are valid entries) is
+    // computed like the others and dropped here: no branch before the loads
+    return p.i >= L.nx ? 0.0 : acc / L.a[s];
 }
 
 template <int M>
@@ -608,14 +609,12 @@ __device__ inline void sweep_item(const AmgLevel &L, const AmgLevel &C, int colo
 // h gets its Gauss-Seidel value from those red values, computed on the fly.
 __device__ inline double red_from_zero(const AmgLevel &L, int s) { return L.b[s] / L.a[s]; }
 
-__device__ inline void presmooth_item(const AmgLevel &L, int h) {
-    L.x[h] = (pos_of(L, h).i >= L.nx) ? 0.0 : red_from_zero(L, h);
+// (red and black values of entry h; padded cells computed and dropped)
+__device__ inline void presmooth_values(const AmgLevel &L, int h, double &red, double &black) {
+    const double r0 = red_from_zero(L, h);
+    red = (pos_of(L, h).i >= L.nx) ? 0.0 : r0;
     const int s = L.half + h;
     const Pos p = pos_of(L, s);
-    if (p.i >= L.nx) {
-        L.x[s] = 0.0;
-        return;
-    }
     const int stride = 2 * L.half;
     double acc = L.b[s];
 #pragma unroll
@@ -625,7 +624,14 @@ __device__ inline void presmooth_item(const AmgLevel &L, int h) {
         acc -= L.a[(size_t)d * stride + s] * red_from_zero(L, in ? ns : s);
     }
     for (int q = L.cps[s]; q < L.cps[s + 1]; ++q) acc -= L.acw[L.cslot[q]] * 0.0;
-    L.x[s] = acc / L.a[s];
+    black = p.i >= L.nx ? 0.0 : acc / L.a[s];
+}
+
+__device__ inline void presmooth_item(const AmgLevel &L, int h) {
+    double red, black;
+    presmooth_values(L, h, red, black);
+    L.x[h] = red;
+    L.x[L.half + h] = black;
 }
 
 __global__ __launch_bounds__(kBlock) void k_amg_presmooth(AmgLevel L) {
@@ -683,15 +689,16 @@ __device__ inline double cell_residual(const AmgLevel &L, int s, const Pos &p) {
 // the wave must call it (shuffles); on = false marks lanes past the end.
 __device__ inline double restrict_child(const AmgLevel &F, const AmgLevel &C, int t, int q,
                                         bool on, int &have) {
-    have = 0;
-    if (!on) return 0.0;
-    const int JK = fdiv(t, C.mnx), I = t - JK * C.nx;
+    // a missing child (or a lane past the end) computes the residual of a
+    // cell that exists and drops it: no branch before the loads
+    const int tc = on ? t : 0;
+    const int JK = fdiv(tc, C.mnx), I = tc - JK * C.nx;
     const int K = fdiv(JK, C.mny), J = JK - K * C.ny;
     const int i = 2 * I + (q & 1), j = 2 * J + ((q >> 1) & 1), k = 2 * K + (q >> 2);
-    if (i >= F.nx || j >= F.ny || k >= F.nz) return 0.0;
-    have = 1;
-    const Pos p = pos_at(F, i, j, k);
-    return cell_residual(F, split_pos(F, p), p);
+    have = on && i < F.nx && j < F.ny && k < F.nz;
+    const Pos p = pos_at(F, min(i, F.nx - 1), min(j, F.ny - 1), min(k, F.nz - 1));
+    const double r = cell_residual(F, split_pos(F, p), p);
+    return have ? r : 0.0;
 }
 
 __device__ inline void restrict_sum(const AmgLevel &C, int t, int q, bool on, double r,
@@ -794,6 +801,8 @@ __device__ __forceinline__ void subcycle_phase(int op, const AmgLevel &F, const 
     const int wave = tid >> 6, lane = tid & 63, nwaves = nt >> 6;
     const int kind = op & 15;
     if (kind == kOpPresmooth) {
+        // (one entry per thread at a time: on one CU the clamped second
+        // entry of a branch-free pair costs more issue slots than it saves)
         for (int h = tid; h < F.half; h += nt) presmooth_item(F, h);
     } else if (kind == kOpSweep) {
         const int color = (op >> 8) & 1, mode = (op >> 12) & 15;
@@ -814,13 +823,14 @@ __device__ __forceinline__ void subcycle_phase(int op, const AmgLevel &F, const 
         for (int s = tid; s < 2 * F.half; s += 2 * nt) {
             const int s2 = s + nt;
             const Pos p1 = pos_of(F, s);
-            const double r1 = p1.i >= F.nx ? 0.0 : cell_residual(F, s, p1);
+            const double c1 = cell_residual(F, s, p1);
             double r2 = 0.0;
             if (s2 < 2 * F.half) {
                 const Pos p2 = pos_of(F, s2);
-                r2 = p2.i >= F.nx ? 0.0 : cell_residual(F, s2, p2);
+                const double c2 = cell_residual(F, s2, p2);
+                r2 = p2.i >= F.nx ? 0.0 : c2;
             }
-            rbuf[s] = r1;
+            rbuf[s] = p1.i >= F.nx ? 0.0 : c1;
             if (s2 < 2 * F.half) rbuf[s2] = r2;
         }
         __syncthreads();
