@@ -1109,8 +1109,9 @@ static void precondition(fim_ctx *c, const WT *w, const double *hptr, T *v, T *z
         if constexpr (same) {
             if (!v) rhs = w;
         }
-        const IluRhs<T, T> R{rhs, Kry<T>::ap(c), c->colsplit, c->split0, c->lv[0].x,
-                             2 * c->lv[0].half, c->cpr_pw};
+        IluRhs<T, T> R{rhs, Kry<T>::ap(c), c->colsplit, c->split0, c->lv[0].x,
+                       2 * c->lv[0].half, c->cpr_pw};
+        R.nxp = c->lv[0].nxp;
         launch_ilu_solve(c->s, c->nb, c->g, c->ilu, c->sys(), Kry<T>::lu(c), R, z);
     } else if (c->opt.precond == FIM_PREC_ILU0) {
         const T *rhs = v;

@@ -720,6 +720,67 @@ __device__ inline void rhs_row(const RT &R, const Sys &sys, int r, double (&acc)
     }
 }
 
+// The right sides of H cell rows of the grid's 7-point pattern (cells
+// (ci, cj, ck), rows rr, blocks q0 .. q1 - 1): rhs_row's values, summed in
+// the same order.  A cell row holds the blocks of its existing neighbours
+// first, in column order (-z, -y, -x, the cell, +x, +y, +z), then its well
+// columns.  A neighbour's level-0 entry follows from the cell's own (the
+// colour flips, the unsplit index moves by the neighbour's offset), so only
+// well columns read colsplit.  Every row's stencil loads are issued before
+// the first product: a missing neighbour loads a block of the row, reads
+// its entry past the end of a raw buffer (zero, without a memory access)
+// and is dropped by a select.
+template <int NB, int H, class RT>
+__device__ inline void rhs_cells(const RT &R, const Grid &g, const int (&ci)[H],
+                                 const int (&cj)[H], const int (&ck)[H], const int (&rr)[H],
+                                 const int (&q0)[H], const int (&q1)[H], double (&acc)[H][NB]) {
+#pragma unroll
+    for (int h = 0; h < H; ++h)
+#pragma unroll
+        for (int u = 0; u < NB; ++u) acc[h][u] = (double)R.b[(size_t)rr[h] * NB + u];
+    if (!R.ap) return;
+    const int half = R.nsplit >> 1, pz = R.nxp * g.ny;
+    const int dcc[7] = {-pz, -R.nxp, -1, 0, 1, R.nxp, pz};
+    const __amdgpu_buffer_rsrc_t rpx = make_rsrc(R.px, (unsigned)R.nsplit * 8u);
+    bool ex[H][7];
+    double a[H][7][NB], p[H][7];
+    int qe[H];
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+        const int i = ci[h], j = cj[h], k = ck[h];
+        const bool e[7] = {k > 0, j > 0, i > 0, true, i + 1 < g.nx, j + 1 < g.ny, k + 1 < g.nz};
+        const int cc = i + R.nxp * (j + g.ny * k);
+        const int par = (i + j + k) & 1;
+        const int own = (par ? half : 0) + (cc >> 1), oth = par ? 0 : half;
+        int q = q0[h];
+#pragma unroll
+        for (int d = 0; d < 7; ++d) {
+            ex[h][d] = e[d];
+            const int qd = min(q, q1[h] - 1);
+            q += e[d];
+            const int sd = d == 3 ? own : oth + ((cc + dcc[d]) >> 1);
+#pragma unroll
+            for (int u = 0; u < NB; ++u) a[h][d][u] = (double)R.ap[(size_t)qd * NB + u];
+            p[h][d] = buf_ld(rpx, e[d] ? sd * 8 : R.nsplit * 8);
+        }
+        qe[h] = q;
+    }
+#pragma unroll
+    for (int h = 0; h < H; ++h)
+#pragma unroll
+        for (int d = 0; d < 7; ++d)
+#pragma unroll
+            for (int u = 0; u < NB; ++u)
+                acc[h][u] -= (ex[h][d] ? a[h][d][u] : 0.0) * (ex[h][d] ? p[h][d] : 0.0);
+#pragma unroll
+    for (int h = 0; h < H; ++h)
+        for (int q = qe[h]; q < q1[h]; ++q) {
+            const double pq = R.px[R.colsplit[q]];
+#pragma unroll
+            for (int u = 0; u < NB; ++u) acc[h][u] -= (double)R.ap[(size_t)q * NB + u] * pq;
+        }
+}
+
 // the first-stage correction in component u of row r: the pressure slot,
 // or every component scaled by the prolongation weights pw of its cell
 template <int NB, class RT>
@@ -790,24 +851,26 @@ __device__ void solve_cells_pencils(const Grid &g, const TileBox &tb, const Sys 
     int *re = rp + ncell;                          // row ends
     int *roff = re + ncell;                        // record order
     ilu_rank_table(tb, T, roff);
-    // two rows per thread at a time so their loads overlap (a slot past the
+    // kH rows per thread at a time so their loads overlap (a slot past the
     // tile's cells works on its last cell and stores nothing: no branch
     // between the loads)
-    for (int l0 = threadIdx.x; l0 < ncell; l0 += 2 * blockDim.x) {
-        int rr[2], q0[2], q1[2];
+    constexpr int kH = NB == 2 ? 3 : 2;
+    for (int l0 = threadIdx.x; l0 < ncell; l0 += kH * blockDim.x) {
+        int rr[kH], q0[kH], q1[kH], ci[kH], cj[kH], ck[kH];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
+        for (int h = 0; h < kH; ++h) {
             const int l = min(l0 + h * (int)blockDim.x, ncell - 1);
-            const int li = l % tb.txe, lj = (l / tb.txe) % tb.tye, lk = l / sxy;
-            rr[h] = (tb.i0 + li) + g.nx * ((tb.j0 + lj) + g.ny * (tb.k0 + lk));
+            ci[h] = tb.i0 + l % tb.txe;
+            cj[h] = tb.j0 + (l / tb.txe) % tb.tye;
+            ck[h] = tb.k0 + l / sxy;
+            rr[h] = ci[h] + g.nx * (cj[h] + g.ny * ck[h]);
             q0[h] = sys.rowptr[rr[h]];
             q1[h] = sys.rowptr[rr[h] + 1];
         }
-        double acc[2][NB];
+        double acc[kH][NB];
+        rhs_cells<NB, kH>(R, g, ci, cj, ck, rr, q0, q1, acc);
 #pragma unroll
-        for (int h = 0; h < 2; ++h) rhs_row<NB>(R, sys, rr[h], acc[h], q0[h], q1[h]);
-#pragma unroll
-        for (int h = 0; h < 2; ++h)
+        for (int h = 0; h < kH; ++h)
             if (l0 + h * (int)blockDim.x < ncell) {
                 const int l = l0 + h * blockDim.x;
                 rp[l] = q0[h];

@@ -253,6 +253,8 @@ struct IluRhs {
     int nsplit;                 // 2*half of level 0 (first well entry)
     const double *pw = nullptr; // [n][nb] prolongation weights of the correction, or null
                                 // (pressure slot only)
+    int nxp = 0;                // level-0 row length of the split numbering (nx rounded
+                                // up to even): a cell's neighbours' entries follow from its own
 };
 void launch_ilu_solve(hipStream_t s, int nb, Grid g, const IluTiles &T, Sys sys,
                       const double *lu, const IluRhs<double, double> &R, double *x);

@@ -395,6 +395,36 @@ void launch_normalize_precond(hipStream_t s, int nb, int nrows, const double *w,
 constexpr int kDotGroup = 8;
 constexpr int kDotCols = 2048;
 
+// The products of one group of NG vectors with w, and <w, w> when self: a
+// thread takes U of its grid-stride elements at a time and issues all their
+// loads before the first product (an element past the end re-reads the
+// thread's first one and is dropped by a select), so even a group of one
+// vector keeps several loads in flight.
+template <class T, int NG>
+__device__ inline void multidot_group(long nvec, const T *__restrict__ V, const T *__restrict__ w,
+                                      bool self, double (&acc)[kDotGroup + 1]) {
+    constexpr int U = NG <= 2 ? 4 : 2;
+    const long S = (long)gridDim.x * blockDim.x;
+    for (long e0 = (long)blockIdx.x * blockDim.x + threadIdx.x; e0 < nvec; e0 += U * S) {
+        double we[U], v[U][NG];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const long e = e0 + u * S < nvec ? e0 + u * S : e0;
+            we[u] = (double)w[e];
+#pragma unroll
+            for (int i = 0; i < NG; ++i)
+                v[u][i] = (double)__builtin_nontemporal_load(V + (size_t)i * nvec + e);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const double wu = e0 + u * S < nvec ? we[u] : 0.0;
+#pragma unroll
+            for (int i = 0; i < NG; ++i) acc[i] += v[u][i] * wu;
+            if (self) acc[kDotGroup] += wu * wu;
+        }
+    }
+}
+
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_multidot_part(long nvec, int nv,
                                                           const T *__restrict__ V,
@@ -403,36 +433,42 @@ __global__ __launch_bounds__(kBlock) void k_multidot_part(long nvec, int nv,
                                                           const int *gate) {
     if (gate && *gate == 0) return;
     const int g0 = blockIdx.y * kDotGroup;
+    const int ng = min(kDotGroup, nv - g0);
     double acc[kDotGroup + 1];
 #pragma unroll
     for (int i = 0; i <= kDotGroup; ++i) acc[i] = 0.0;
     const bool self = blockIdx.y == 0;            // the first group also forms <w, w>
-    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < nvec;
-         e += (long)gridDim.x * blockDim.x) {
-        const double we = (double)w[e];
-#pragma unroll
-        for (int i = 0; i < kDotGroup; ++i)
-            if (g0 + i < nv)
-                acc[i] += (double)__builtin_nontemporal_load(V + (size_t)(g0 + i) * nvec + e) * we;
-        if (self) acc[kDotGroup] += we * we;
+    const T *Vg = V + (size_t)g0 * nvec;
+    switch (ng) {
+    case 1: multidot_group<T, 1>(nvec, Vg, w, self, acc); break;
+    case 2: multidot_group<T, 2>(nvec, Vg, w, self, acc); break;
+    case 3: multidot_group<T, 3>(nvec, Vg, w, self, acc); break;
+    case 4: multidot_group<T, 4>(nvec, Vg, w, self, acc); break;
+    case 5: multidot_group<T, 5>(nvec, Vg, w, self, acc); break;
+    case 6: multidot_group<T, 6>(nvec, Vg, w, self, acc); break;
+    case 7: multidot_group<T, 7>(nvec, Vg, w, self, acc); break;
+    default: multidot_group<T, kDotGroup>(nvec, Vg, w, self, acc); break;
     }
     __shared__ double sh[kDotGroup + 1][kWaves];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
     for (int i = 0; i <= kDotGroup; ++i) {
-        double a = acc[i];
+        if (i < ng || (i == kDotGroup && self)) {
+            double a = acc[i];
 #pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) a += __shfl_xor(a, off, 64);
-        if (lane == 0) sh[i][wid] = a;
+            for (int off = 32; off >= 1; off >>= 1) a += __shfl_xor(a, off, 64);
+            if (lane == 0) sh[i][wid] = a;
+        }
     }
     __syncthreads();
     if (threadIdx.x <= kDotGroup) {
         const int i = threadIdx.x;
-        double a = sh[i][0];
-        for (int w2 = 1; w2 < kWaves; ++w2) a += sh[i][w2];
-        const int slot = (i < kDotGroup) ? g0 + i : nv;
-        if ((i < kDotGroup && slot < nv) || (i == kDotGroup && self))
+        if ((i < kDotGroup && i < ng) || (i == kDotGroup && self)) {
+            double a = sh[i][0];
+            for (int w2 = 1; w2 < kWaves; ++w2) a += sh[i][w2];
+            const int slot = (i < kDotGroup) ? g0 + i : nv;
             partials[(size_t)slot * gridDim.x + blockIdx.x] = a;
+        }
     }
 }
 
