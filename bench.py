@@ -92,6 +92,9 @@ def spmv_only(reps):
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    fim.fim_bsr_spmv(g.nrows, g.nb, trp, tci, tv, x, y)   # untimed: first-launch costs
+    dst.copy_(src)
+    torch.cuda.synchronize()
     t_spmv = t_copy = 0.0
     for _ in range(reps):
         ev[0].record(stream)
@@ -113,7 +116,7 @@ def spmv_source_sha():
     """sha256 of the source file that holds the SpMV kernel."""
     import hashlib
 
-    path = os.path.join(ROOT, "paper_2406_10862_amd", "csrc", "fim_linalg.hip")
+    path = os.path.join(ROOT, "paper_2406_10862_amd", "csrc", "fim_spmv.hip")
     return hashlib.sha256(open(path, "rb").read()).hexdigest()
 
 

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfim.so")
-SOURCES = ["fim_phys.hip", "fim_linalg.hip", "fim_amg.hip", "fim_ilu.hip", "fim_api.cpp"]
+SOURCES = ["fim_phys.hip", "fim_spmv.hip", "fim_linalg.hip", "fim_amg.hip", "fim_ilu.hip", "fim_api.cpp"]
 ARCH = os.environ.get("FIM_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

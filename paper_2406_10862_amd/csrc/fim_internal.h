@@ -140,7 +140,7 @@ void launch_bsr_transpose(hipStream_t s, int nb, long nnzb, const int *tperm, co
 int conv_blocks(int n);
 int update_blocks(int n);
 
-// ---- linear algebra kernels (fim_linalg.hip) --------------------------------
+// ---- linear algebra kernels (fim_spmv.hip, fim_linalg.hip) -----------------
 void launch_spmv(hipStream_t s, int nb, int nrows, const int *rowptr, const int *colind,
                  const double *val, const double *x, double *y, hipEvent_t e0 = nullptr,
                  hipEvent_t e1 = nullptr);
