@@ -245,6 +245,7 @@ def test_block_jacobi_apply_matches_oracle(cfg):
 
 @pytest.mark.parametrize("cfg,tile", [("c1", "grid"), ("c2s", "grid"), ("odd", (4, 5, 2)),
                                       ("odd", (1, 1, 1)), ("odd", (13, 1, 5)), ("wells", (8, 8, 8)),
+                                      ("wells", (8, 16, 8)),
                                       ("line", "grid"), ("line", (1, 7, 1))])
 def test_ilu0_apply_matches_oracle(cfg, tile):
     # block-Jacobi ILU(0) over boxes (natural-order BILU(0) when one box
@@ -471,6 +472,34 @@ def test_c3_full_size_step_solves_the_oracle_equations(precision):
     scale = np.array([abs(w.target) for w in res.wells])
     assert np.all(np.abs(Rw) <= opt.tol_well * scale), Rw
     assert (st["flag"] == rv.SAT).any()
+
+
+def test_c2_full_size_step_solves_the_oracle_equations():
+    """1,122,000 cells in the launch configuration of the benchmark (CPR
+    with block-Jacobi ILU(0) over 8x16x8 boxes, FP64, GMRES(40), the
+    parity tolerances): the first 10-day step from the initial state.  The
+    oracle's Newton run is out of reach here; its discrete system at the
+    GPU's end state must pass the convergence tests the step claims."""
+    res = rv.config_c2()
+    opt = rv.Options(max_lin=400, restart=40, max_newton=30, tile=(8, 16, 8))
+    g = fim.Fim(res, options=opt)
+    o = fr.OracleModel(res)
+    g.fim_set_state(o.P, o.Sw, o.X, o.flag, o.pbhp)
+    dt = res.schedule[0]
+    A0 = o.accum()
+    rc, rep = g.fim_step(dt)
+    print(f"c2 step: rc={rc} newton={rep.newton_iters} linear={rep.linear_iters} "
+          f"cuts={rep.cuts}")
+    assert rc == fim.FIM_OK and rep.cuts == 0
+    st = g.fim_get_state()
+    end = dict(P=st["P"], Sw=st["Sw"], X=st["X"], flag=st["flag"], pbhp=st["pbhp"])
+    R, _ = o.assemble(dt, A0, jacobian=False, **end)
+    cnv, mb = o.conv(R, dt, **end)
+    print("oracle CNV", cnv, "MB", mb)
+    assert cnv.max() <= opt.tol_cnv and mb.max() <= opt.tol_mb
+    Rw = np.asarray(R).reshape(-1, 2)[g.n:, 0]
+    scale = np.array([abs(w.target) for w in res.wells])
+    assert np.all(np.abs(Rw) <= opt.tol_well * scale), Rw
 
 
 def test_linear_solve_zero_rhs():
