@@ -393,6 +393,8 @@ def main():
                     help="AMG cycle: 0 V at the finest level and W below, 1 V, 2 W, >=16 W on "
                          "levels of at most that many cells, <=-16 V at the finest level and on "
                          "levels of at most -value cells, W between")
+    ap.add_argument("--amg-sweeps", type=int, default=0,
+                    help="red-black sweep pairs before and after each coarse correction (0 = 1)")
     ap.add_argument("--precond", default="cpr_ilu0", choices=["bj", "ilu0", "cpr", "cpr_ilu0"])
     ap.add_argument("--tile", default=None,
                     help="block-Jacobi ILU(0) box, e.g. 4,4,16 (default: 8,16,8 for c2, the "
@@ -446,6 +448,7 @@ def main():
         args.steps = len(res.schedule)
     opts = tolerances(args.tol)
     opts.amg_cycle = args.cycle
+    opts.amg_sweeps = args.amg_sweeps
     opts.precond = {"bj": rv.PREC_BJ, "ilu0": rv.PREC_ILU0, "cpr": rv.PREC_CPR,
                     "cpr_ilu0": rv.PREC_CPR_ILU0}[args.precond]
     if args.tile is None:
