@@ -745,6 +745,49 @@ __global__ __launch_bounds__(kBlock) void k_amg_restrict(AmgLevel F, AmgLevel C)
     }
 }
 
+// Restriction on large levels, by row segments: a block takes up to kSegAgg
+// aggregates along i of one coarse row (J, K).  Its four waves compute the
+// residuals of the segment's fine cells, one fine row (j, k) each, so a
+// wave's loads of a stencil array fall on two runs of consecutive entries
+// (the two colours) rather than on eight half-lines; the residuals go to
+// LDS and each aggregate then sums its existing children in the same
+// (k, j, i) order as k_amg_restrict, so the sums are the same bit for bit.
+constexpr int kSegAgg = 32;
+constexpr int kSegPairHalf = 1 << 18;      // levels with at least this many entries per colour
+
+__global__ __launch_bounds__(kBlock) void k_amg_restrict_rows(AmgLevel F, AmgLevel C, int nseg,
+                                                              int cell_blocks) {
+    const int bx = xcd_block(blockIdx.x, gridDim.x);
+    if (bx >= cell_blocks) {
+        const int w = ((bx - cell_blocks) * kBlock + threadIdx.x) >> 6;
+        if (w < F.nw) restrict_well(F, C, w, threadIdx.x & 63);
+        return;
+    }
+    __shared__ double rr[4][2 * kSegAgg];
+    const int seg = bx % nseg, JK = bx / nseg;
+    const int J = JK % C.ny, K = JK / C.ny;
+    const int I0 = seg * kSegAgg;
+    const int row = threadIdx.x >> 6, li = threadIdx.x & 63;
+    const int i = 2 * I0 + li, j = 2 * J + (row & 1), k = 2 * K + (row >> 1);
+    const bool have = i < F.nx && j < F.ny && k < F.nz;
+    // a lane without a cell computes the residual of the segment's first
+    // cell (which always exists) and stores nothing: no branch before the loads
+    const Pos p = pos_at(F, have ? i : 2 * I0, have ? j : 2 * J, have ? k : 2 * K);
+    const double r = cell_residual(F, split_pos(F, p), p);
+    if (have) rr[row][li] = r;
+    __syncthreads();
+    const int I = I0 + (int)threadIdx.x;
+    if (threadIdx.x < kSegAgg && I < C.nx) {
+        double sum = 0.0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int ci = 2 * I + (q & 1), cj = 2 * J + ((q >> 1) & 1), ck = 2 * K + (q >> 2);
+            if (ci < F.nx && cj < F.ny && ck < F.nz) sum += rr[q >> 1][2 * threadIdx.x + (q & 1)];
+        }
+        C.b[split_of(C, I, J, K)] = sum;
+    }
+}
+
 // x_fine += P x_coarse at fine entry t
 __device__ inline void correct_item(const AmgLevel &F, const AmgLevel &C, int t) {
     if (t < 2 * F.half) {
@@ -1104,6 +1147,14 @@ void launch_amg_well_sweep(hipStream_t s, const AmgLevel &L) {
 }
 
 void launch_amg_restrict(hipStream_t s, const AmgLevel &F, const AmgLevel &C) {
+    if (F.half >= kSegPairHalf) {
+        const int nseg = (C.nx + kSegAgg - 1) / kSegAgg;
+        const long cell_blocks = (long)nseg * C.ny * C.nz;
+        const long well_blocks = (64L * F.nw + kBlock - 1) / kBlock;
+        hipLaunchKernelGGL(k_amg_restrict_rows, dim3((unsigned)(cell_blocks + well_blocks)),
+                           dim3(kBlock), 0, s, F, C, nseg, (int)cell_blocks);
+        return;
+    }
     const long cell_blocks = (8L * C.nx * C.ny * C.nz + kBlock - 1) / kBlock;
     const long well_blocks = (64L * F.nw + kBlock - 1) / kBlock;
     hipLaunchKernelGGL(k_amg_restrict, dim3((unsigned)(cell_blocks + well_blocks)), dim3(kBlock), 0,
