@@ -977,6 +977,17 @@ __global__ __launch_bounds__(kBlock) void k_cpr_restrict(int n, int nw, AmgLevel
                                                          const double *__restrict__ wq) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n + nw) return;
+    // the weights and the split index are loaded with w (a well row loads
+    // those of the last cell and does not use them: no branch before the
+    // loads); n >= 1
+    const int rc = r < n ? r : n - 1;
+    double we[NB], q[NB];
+#pragma unroll
+    for (int e = 0; e < NB; ++e) {
+        we[e] = (double)w[(size_t)r * NB + e];
+        q[e] = wq[(size_t)rc * NB + e];
+    }
+    const int sp = split0[rc];
     bool zero = false;
     double h = 1.0;
     if (hptr) {
@@ -986,15 +997,14 @@ __global__ __launch_bounds__(kBlock) void k_cpr_restrict(int n, int nw, AmgLevel
     double a[NB];
 #pragma unroll
     for (int e = 0; e < NB; ++e) {
-        const double we = (double)w[(size_t)r * NB + e];
-        a[e] = zero ? 0.0 : (hptr ? we / h : we);
+        a[e] = zero ? 0.0 : (hptr ? we[e] / h : we[e]);
         if (v) v[(size_t)r * NB + e] = (VT)a[e];
     }
     if (r < n) {
         double s = 0.0;
 #pragma unroll
-        for (int e = 0; e < NB; ++e) s += wq[(size_t)r * NB + e] * a[e];
-        L.b[split0[r]] = s;
+        for (int e = 0; e < NB; ++e) s += q[e] * a[e];
+        L.b[sp] = s;
     } else {
         L.b[2 * L.half + (r - n)] = a[0];
     }
