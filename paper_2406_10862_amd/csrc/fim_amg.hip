@@ -576,12 +576,19 @@ __device__ inline double read_well(const AmgLevel &L, const AmgLevel &C, int mod
 // Gauss-Seidel value of cell h of one colour (cells of one colour are not
 // coupled to each other, so a colour sweep is exact and order-free);
 // padded cells get 0.
-template <int M>
+// (Early: the divisor is read with the stencil and the division is not
+// behind a branch, which pays in the multi-block kernels that stream HBM;
+// in the one-workgroup sub-cycle, issue-bound with its data in LDS, the
+// padded lanes' extra division costs more.  Same value either way.)
+template <int M, bool Early>
 __device__ inline double sweep_value(const AmgLevel &L, const AmgLevel &C, int color, int mode,
                                      int h) {
     const int s = color * L.half + h;
     const Pos p = pos_of(L, s);
     const int stride = 2 * L.half;
+    const bool pad = p.i >= L.nx;
+    // (Early: a padded cell divides 0 by 1)
+    const double dg = Early ? L.a[s] : 1.0;
     double acc = L.b[s];
 #pragma unroll
     for (int d = 1; d < 7; ++d) {
@@ -595,13 +602,14 @@ __device__ inline double sweep_value(const AmgLevel &L, const AmgLevel &C, int c
     }
     // a padded cell (its neighbours in the grid are valid entries) is
     // computed like the others and dropped here: no branch before the loads
-    return p.i >= L.nx ? 0.0 : acc / L.a[s];
+    if (Early) return (pad ? 0.0 : acc) / (pad ? 1.0 : dg);
+    return pad ? 0.0 : acc / L.a[s];
 }
 
-template <int M>
+template <int M, bool Early = false>
 __device__ inline void sweep_item(const AmgLevel &L, const AmgLevel &C, int color, int mode,
                                   int h) {
-    L.x[color * L.half + h] = sweep_value<M>(L, C, color, mode, h);
+    L.x[color * L.half + h] = sweep_value<M, Early>(L, C, color, mode, h);
 }
 
 // The first pre-smoothing pair from a zero iterate (wells still zero) in
@@ -610,12 +618,15 @@ __device__ inline void sweep_item(const AmgLevel &L, const AmgLevel &C, int colo
 __device__ inline double red_from_zero(const AmgLevel &L, int s) { return L.b[s] / L.a[s]; }
 
 // (red and black values of entry h; padded cells computed and dropped)
+template <bool Early>
 __device__ inline void presmooth_values(const AmgLevel &L, int h, double &red, double &black) {
     const double r0 = red_from_zero(L, h);
     red = (pos_of(L, h).i >= L.nx) ? 0.0 : r0;
     const int s = L.half + h;
     const Pos p = pos_of(L, s);
     const int stride = 2 * L.half;
+    const bool pad = p.i >= L.nx;
+    const double dg = Early ? L.a[s] : 1.0;     // (as in sweep_value)
     double acc = L.b[s];
 #pragma unroll
     for (int d = 1; d < 7; ++d) {
@@ -624,26 +635,27 @@ __device__ inline void presmooth_values(const AmgLevel &L, int h, double &red, d
         acc -= L.a[(size_t)d * stride + s] * red_from_zero(L, in ? ns : s);
     }
     for (int q = L.cps[s]; q < L.cps[s + 1]; ++q) acc -= L.acw[L.cslot[q]] * 0.0;
-    black = p.i >= L.nx ? 0.0 : acc / L.a[s];
+    black = Early ? (pad ? 0.0 : acc) / (pad ? 1.0 : dg) : (pad ? 0.0 : acc / L.a[s]);
 }
 
+template <bool Early = false>
 __device__ inline void presmooth_item(const AmgLevel &L, int h) {
     double red, black;
-    presmooth_values(L, h, red, black);
+    presmooth_values<Early>(L, h, red, black);
     L.x[h] = red;
     L.x[L.half + h] = black;
 }
 
 __global__ __launch_bounds__(kBlock) void k_amg_presmooth(AmgLevel L) {
     const int h = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (h < L.half) presmooth_item(L, h);
+    if (h < L.half) presmooth_item<true>(L, h);
 }
 
 template <int M>
 __global__ __launch_bounds__(kBlock) void k_amg_sweep(AmgLevel L, AmgLevel C, int color,
                                                       int mode) {
     const int h = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (h < L.half) sweep_item<M>(L, C, color, mode, h);
+    if (h < L.half) sweep_item<M, true>(L, C, color, mode, h);
 }
 
 // wells: one wave per well, lanes stride over its slots
@@ -828,8 +840,8 @@ __device__ __forceinline__ void sweep_phase(const AmgLevel &F, const AmgLevel &C
     const int tid = threadIdx.x, nt = blockDim.x;
     for (int h = tid; h < F.half; h += 2 * nt) {
         const int h2 = h + nt;
-        const double v1 = sweep_value<M>(F, C, color, mode, h);
-        const double v2 = (h2 < F.half) ? sweep_value<M>(F, C, color, mode, h2) : 0.0;
+        const double v1 = sweep_value<M, false>(F, C, color, mode, h);
+        const double v2 = (h2 < F.half) ? sweep_value<M, false>(F, C, color, mode, h2) : 0.0;
         F.x[color * F.half + h] = v1;
         if (h2 < F.half) F.x[color * F.half + h2] = v2;
     }
