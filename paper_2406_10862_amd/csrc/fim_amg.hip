@@ -667,9 +667,12 @@ __device__ inline double well_row_sum(const AmgLevel &L, int w, int lane) {
     return acc;
 }
 
+// (every lane reads the row's b and diagonal with its slots and stores the
+// same value, so no load waits behind the reduction and a lane-0 branch)
 __device__ inline void well_sweep_item(const AmgLevel &L, int w, int lane) {
+    const double bw = L.b[2 * L.half + w], aw = L.aww[w];
     const double sum = well_row_sum(L, w, lane);
-    if (lane == 0) L.x[2 * L.half + w] = (L.b[2 * L.half + w] - sum) / L.aww[w];
+    L.x[2 * L.half + w] = (bw - sum) / aw;
 }
 
 __global__ __launch_bounds__(kBlock) void k_amg_well_sweep(AmgLevel L) {
