@@ -740,10 +740,13 @@ __device__ inline void restrict_group(const AmgLevel &F, const AmgLevel &C, int 
 }
 
 // a well is its own aggregate: its coarse right-hand side is its residual
+// (b, the diagonal and x of the row are read with its slots and every lane
+// stores the same value, as in well_sweep_item)
 __device__ inline void restrict_well(const AmgLevel &F, const AmgLevel &C, int w, int lane) {
     const int f = 2 * F.half + w;
+    const double bw = F.b[f], aw = F.aww[w], xw = F.x[f];
     const double sum = well_row_sum(F, w, lane);
-    if (lane == 0) C.b[2 * C.half + w] = F.b[f] - F.aww[w] * F.x[f] - sum;
+    C.b[2 * C.half + w] = bw - aw * xw - sum;
 }
 
 // coarse cells (8 lanes each) then wells (one wave each)
