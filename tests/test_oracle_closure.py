@@ -1,0 +1,219 @@
+"""Pins of three parts of the oracle's black-oil closure and well model that
+the generic invariants (mass balance, finite differences, continuity at the
+bubble point) do not fix, each against values computed here by hand from the
+table columns and the Corey curves:
+
+* undersaturated oil above the bubble point (Sec. 2.1 black-oil closure; the
+  reading B_o = B_o,sat(P_b)(1 - c_o (P - P_b)), mu_o = mu_o,sat(P_b)(1 +
+  c_mu (P - P_b)) with P_b from the inverse of the Rs column);
+* injector perforations (Sec. 3.2.4, AllWells; the reading
+  q = -WI (sum_j kr_j/mu_j) b_inj (P_bhp - P) for pure water or free gas),
+  as rates at a state and as a single-cell backward-Euler step solved by
+  bisection;
+* the gas component's connection flux (Sec. 3.2.4, BulkConn, eqs. (1)-(2)):
+  free gas moves with the gas potential from the gas-upwind cell, dissolved
+  gas with the oil potential from the oil-upwind cell.
+
+Everything on the expected side uses numpy interpolation of the input table
+columns and closed forms written out here; nothing comes from the GPU path.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2406_10862_amd import reservoirs as rv
+from oracle.fimref import OracleModel, prop_index
+from tests.helpers import box
+
+FT3_PER_BBL = 5.615
+DARCY = 0.001127
+
+
+def corey(s_num, denom, krmax, n=2.0):
+    s = min(max(s_num / denom, 0.0), 1.0)
+    return krmax * s ** n
+
+
+def water_b(fl, P):
+    return math.exp(fl.cw * (P - fl.pw_ref)) / fl.bw_ref
+
+
+def one_cell(fl, P, Sw, X=0.0, flag=0, wells=()):
+    return OracleModel(box(1, 1, 1, fluid=fl, p0=P, sw0=Sw, x0=X, flag0=flag, wells=wells))
+
+
+# ---------------------------------------------------------------------------
+# undersaturated oil
+
+@pytest.mark.parametrize("Rs,dp", [(0.31, 1500.0), (0.83, 240.0), (1.27, 3100.0)])
+def test_undersaturated_oil_above_the_bubble_point(Rs, dp):
+    fl = rv.blackoil_fluid()
+    fl.cmu_us = 4e-5                     # a viscosibility that is not zero
+    Pb = float(np.interp(Rs, fl.rs, fl.p))
+    assert fl.p[0] < Pb < fl.p[-1]
+    P, Sw = Pb + dp, 0.34
+    Bob = float(np.interp(Pb, fl.p, fl.bo))
+    mub = float(np.interp(Pb, fl.p, fl.muo))
+    Bo = Bob * (1.0 - fl.co_us * (P - Pb))
+    muo = mub * (1.0 + fl.cmu_us * (P - Pb))
+    So = 1.0 - Sw
+    D = 1.0 - fl.swc - fl.sor - fl.sgc
+    kro = corey(So - fl.sor, D, fl.kro_max)
+    krw = corey(Sw - fl.swc, 1.0 - fl.swc - fl.sor, fl.krw_max)
+    pv = 100.0 * 100.0 * 10.0 * 0.2 / FT3_PER_BBL * (1.0 + 3e-6 * (P - 4700.0))
+
+    m = one_cell(fl, P, Sw, X=Rs, flag=rv.UNSAT)
+    pr = m.props()[:, 0]
+    ix = prop_index(3)
+    assert 1.0 / pr[ix["b_o"]] == pytest.approx(Bo, rel=1e-13)
+    assert pr[ix["Lam_o"]] == pytest.approx(kro / Bo / muo, rel=1e-13)
+    assert pr[ix["Lam_og"]] == pytest.approx(Rs * kro / Bo / muo, rel=1e-13)
+    assert pr[ix["lam_t"]] == pytest.approx(krw / fl.muw + kro / muo, rel=1e-13)
+    rho_o = (FT3_PER_BBL * fl.rho_sc[1] + Rs * fl.rho_sc[2]) / (FT3_PER_BBL * Bo)
+    assert pr[ix["gam_o"]] == pytest.approx(rho_o / 144.0, rel=1e-13)
+    assert pr[ix["A_o"]] == pytest.approx(pv * So / Bo, rel=1e-13)
+    assert pr[ix["A_g"]] == pytest.approx(pv * Rs * So / Bo, rel=1e-13)
+    # above the bubble point the oil is compressed: Bo falls with P
+    assert Bo < Bob
+
+
+# ---------------------------------------------------------------------------
+# injector perforations
+
+def test_water_injector_rate_at_a_state():
+    fl = rv.deadoil_fluid(swc=0.2, sor=0.2)
+    wi, pbhp, P, Sw = 1.7, 5600.0, 4823.0, 0.41
+    w = rv.Well(rv.INJ_WATER, rv.BHP, pbhp, np.array([0], np.int32), wi=np.array([wi]))
+    m = one_cell(fl, P, Sw, wells=[w])
+    q = m.well_rates()[0]
+    D = 1.0 - fl.swc - fl.sor
+    muo = float(np.interp(P, fl.p, fl.muo))
+    lt = corey(Sw - fl.swc, D, fl.krw_max) / fl.muw + corey(1 - Sw - fl.sor, D, fl.kro_max) / muo
+    expect = -wi * lt * water_b(fl, P) * (pbhp - P)
+    assert expect < 0                      # injection is negative
+    assert q[0] == pytest.approx(expect, rel=1e-13)
+    assert q[1] == 0.0 and q[2] == 0.0
+
+
+def test_gas_injector_rate_at_a_state():
+    fl = rv.blackoil_fluid()
+    wi, pbhp, P, Sw, Sg = 0.9, 4400.0, 3720.0, 0.3, 0.17
+    w = rv.Well(rv.INJ_GAS, rv.BHP, pbhp, np.array([0], np.int32), wi=np.array([wi]))
+    m = one_cell(fl, P, Sw, X=Sg, flag=rv.SAT, wells=[w])
+    q = m.well_rates()[0]
+    D = 1.0 - fl.swc - fl.sor - fl.sgc
+    So = 1.0 - Sw - Sg
+    muo = float(np.interp(P, fl.p, fl.muo))
+    mug = float(np.interp(P, fl.p, fl.mug))
+    bg = 1.0 / float(np.interp(P, fl.p, fl.bg))
+    lt = (corey(Sw - fl.swc, 1.0 - fl.swc - fl.sor, fl.krw_max) / fl.muw
+          + corey(So - fl.sor, D, fl.kro_max) / muo + corey(Sg - fl.sgc, D, fl.krg_max) / mug)
+    expect = -wi * lt * bg * (pbhp - P)
+    assert q[2] == pytest.approx(expect, rel=1e-13)
+    assert q[0] == 0.0 and q[1] == 0.0
+
+
+def bisect(f, lo, hi, iters=200):
+    flo = f(lo)
+    for _ in range(iters):
+        mid = 0.5 * (lo + hi)
+        fm = f(mid)
+        if (fm > 0) == (flo > 0):
+            lo, flo = mid, fm
+        else:
+            hi = mid
+        if hi - lo <= 1e-15 * max(abs(lo), 1.0):
+            break
+    return 0.5 * (lo + hi)
+
+
+def test_single_cell_water_injector_step_equals_bisection():
+    """A closed cell filled by one BHP water injector.  No oil leaves, so the
+    oil equation fixes Sw for every P: Sw(P) = 1 - A_o^n / (PV(P) b_o(P)).
+    The water equation is then a scalar equation in P, solved by bisection
+    with every property evaluated here."""
+    fl = rv.deadoil_fluid(swc=0.2, sor=0.2)
+    wi, pbhp, dt, P0, Sw0 = 0.8, 5600.0, 5.0, 4700.0, 0.35
+    w = rv.Well(rv.INJ_WATER, rv.BHP, pbhp, np.array([0], np.int32), wi=np.array([wi]))
+    res = box(1, 1, 1, dx=100.0, dy=100.0, dz=10.0, k=100.0, poro=0.2, fluid=fl,
+              wells=[w], p0=P0, sw0=Sw0, cr=3e-6)
+    pv_ref = 100.0 * 100.0 * 10.0 * 0.2 / FT3_PER_BBL
+    D = 1.0 - fl.swc - fl.sor
+
+    def bo(P):
+        return 1.0 / float(np.interp(P, fl.p, fl.bo))
+
+    def pv(P):
+        return pv_ref * (1.0 + res.cr * (P - res.pref))
+
+    Aw0 = pv(P0) * water_b(fl, P0) * Sw0
+    Ao0 = pv(P0) * bo(P0) * (1.0 - Sw0)
+
+    def sw_of(P):
+        return 1.0 - Ao0 / (pv(P) * bo(P))
+
+    def g(P):
+        S = sw_of(P)
+        lt = corey(S - fl.swc, D, fl.krw_max) / fl.muw + corey(1 - S - fl.sor, D, fl.kro_max) / 2.0
+        return (pv(P) * water_b(fl, P) * S - Aw0) / dt - wi * lt * water_b(fl, P) * (pbhp - P)
+
+    assert g(P0) < 0 < g(pbhp)
+    P_ref = bisect(g, P0, pbhp)
+    m = OracleModel(res)
+    st, rep = m.step(dt)
+    assert st == 0
+    assert m.P[0] == pytest.approx(P_ref, rel=1e-11)
+    assert m.Sw[0] == pytest.approx(sw_of(P_ref), abs=1e-11)
+    assert m.Sw[0] > Sw0
+
+
+# ---------------------------------------------------------------------------
+# the gas component's connection flux
+
+def test_dissolved_gas_moves_with_the_oil_potential():
+    """Two stacked saturated cells whose oil and gas potentials point opposite
+    ways across their face: oil flows down from the top cell, free gas up
+    from the bottom one.  At x = x^n (no accumulation term) and without wells
+    the residual is the face flux alone: F_w = T Lam_w dPhi_w and F_o = T Lam_o
+    dPhi_o from their upwind cells, and F_g = T Lam_g dPhi_g from the gas-upwind
+    cell plus T Rs Lam_o dPhi_o from the oil-upwind cell."""
+    fl = rv.blackoil_fluid()
+    dz, kh, kv = 20.0, 100.0, 10.0
+    res = box(1, 1, 2, dx=100.0, dy=100.0, dz=dz, k=kh, kv=kv, fluid=fl, flag0=rv.SAT)
+    P = np.array([3000.0, 3004.0])
+    Sw = np.array([0.30, 0.27])
+    Sg = np.array([0.20, 0.15])
+    flag = np.full(2, rv.SAT, np.int8)
+    m = OracleModel(res)
+    A = m.accum(P=P, Sw=Sw, X=Sg, flag=flag)
+    R, _ = m.assemble(1.0, Aold=A, P=P, Sw=Sw, X=Sg, flag=flag, jacobian=False)
+
+    D = 1.0 - fl.swc - fl.sor - fl.sgc
+    props = []
+    for c in range(2):
+        Bo = float(np.interp(P[c], fl.p, fl.bo))
+        Bg = float(np.interp(P[c], fl.p, fl.bg))
+        Rs = float(np.interp(P[c], fl.p, fl.rs))
+        muo = float(np.interp(P[c], fl.p, fl.muo))
+        mug = float(np.interp(P[c], fl.p, fl.mug))
+        bw = water_b(fl, P[c])
+        So = 1.0 - Sw[c] - Sg[c]
+        lam = [corey(Sw[c] - fl.swc, 1.0 - fl.swc - fl.sor, fl.krw_max) * bw / fl.muw,
+               corey(So - fl.sor, D, fl.kro_max) / Bo / muo,
+               corey(Sg[c] - fl.sgc, D, fl.krg_max) / Bg / mug]
+        gam = [fl.rho_sc[0] * bw / 144.0,
+               (FT3_PER_BBL * fl.rho_sc[1] + Rs * fl.rho_sc[2]) / (FT3_PER_BBL * Bo) / 144.0,
+               fl.rho_sc[2] / (FT3_PER_BBL * Bg) / 144.0]
+        props.append(dict(lam=lam, gam=gam, Rs=Rs))
+    zK, zL = 8000.0 + dz / 2, 8000.0 + dz + dz / 2
+    T = DARCY * 100.0 * 100.0 / (dz / 2 / kv + dz / 2 / kv)
+    dphi = [(P[0] - P[1]) - 0.5 * (props[0]["gam"][j] + props[1]["gam"][j]) * (zK - zL)
+            for j in range(3)]
+    assert dphi[1] > 0 > dphi[2]           # oil down from the top cell, gas up from below
+    up = [props[0] if d >= 0 else props[1] for d in dphi]
+    F = [T * up[0]["lam"][0] * dphi[0],
+         T * up[1]["lam"][1] * dphi[1],
+         T * up[2]["lam"][2] * dphi[2] + T * up[1]["Rs"] * up[1]["lam"][1] * dphi[1]]
+    np.testing.assert_allclose(R[0:3], F, rtol=1e-12)
+    np.testing.assert_allclose(R[3:6], -np.array(F), rtol=1e-12)
