@@ -127,7 +127,10 @@ typedef struct {
  * <= tol_cnv and MB_i = dt*|sum_c R_ic|/sum_c PV_c b_ic <= tol_mb, every
  * well residual divided by its derivative w.r.t. the BHP <= tol_well
  * (psi), and a last Newton update with max|dP| <= tol_dp (psi, cells and
- * wells) and max|dS| <= tol_ds.  Updates are chopped per cell to
+ * wells) and max|dS| <= tol_ds, and the iterate must be physical: every
+ * saturation (Sw, So and, model 3, Sg) in [-1e-6, 1 + 1e-6]; a converged
+ * iterate outside that range, like a non-finite residual, fails the Newton
+ * solve.  Updates are chopped per cell to
  * max|dS| <= ds_max and |dP| <= dp_max.  A failed Newton solve halves dt,
  * at most max_cuts times per step.  GMRES(restart) runs to relative
  * residual lin_rtol or max_lin iterations per Newton iteration (restart
@@ -153,7 +156,10 @@ typedef struct {
  * captured HIP graph.  amg_fused: the coarse part of the AMG cycle, from
  * the first level with at most amg_fused cells and wells down, runs as a
  * single-workgroup launch (0 = default 4096, negative = every phase
- * launched separately; the result is the same bit for bit).  profile != 0
+ * launched separately; the result is the same bit for bit).  amg_seg_rows:
+ * AMG levels with at least this many cells of each colour restrict by row
+ * segments (0 = default 2^18, negative = never; the sums are the same bit for
+ * bit either way).  profile != 0
  * has every Krylov SpMV launch of fim_step stamp its own start and end into
  * a pair of HIP events and reports the summed kernel time in
  * fim_step_report.  precision FIM_MIXED (with an ILU(0)
@@ -167,7 +173,7 @@ typedef struct {
     double ds_max, dp_max, lin_rtol;
     int32_t max_newton, max_lin, restart, max_cuts;
     int32_t precond, precision, profile, amg_cycle, amg_sweeps, graphs, forcing, amg_fused;
-    int32_t tile_nx, tile_ny, tile_nz, reserved;
+    int32_t tile_nx, tile_ny, tile_nz, amg_seg_rows;
 } fim_options;
 
 #define FIM_MAX_SUB 256
@@ -187,7 +193,11 @@ typedef struct fim_ctx fim_ctx;
  * work after; the context runs on a stream of its own on the current
  * device.  Validates sizes, table monotonicity, the positive total
  * compressibility of saturated rows (Bg*dRs/dP > dBo/dP), perforation
- * ranges and controls; returns FIM_E_ARG with a message on bad input. */
+ * ranges and controls; returns FIM_E_ARG with a message on bad input.
+ * Size limits (the kernels index with 32-bit integers): fewer than 2^28
+ * cells, and fewer than 2^31 Jacobian values (nnzb*nb*nb, nnzb = cells +
+ * twice the interior faces + twice the perforations + wells); both are
+ * checked from the grid dimensions before any array is read. */
 int fim_create(const fim_grid *grid, const fim_rock *rock, const fim_fluid *fluid,
                int32_t nwells, const fim_well *wells, const fim_options *opt,
                void *hip_stream, fim_ctx **out);
@@ -198,10 +208,18 @@ int fim_sizes(const fim_ctx *ctx, int32_t *ncells, int32_t *nb, int32_t *nwells,
               int32_t *nnzb, int32_t *nprops);
 int fim_set_options(fim_ctx *ctx, const fim_options *opt);
 
-/* State (the non-equilibrium InitReservoir: one state per cell).  p, sw,
- * x3 (ignored by model 2), flag: [ncells]; bhp: [nwells] or NULL, which
- * selects the target for BHP wells and the mean perforated-cell pressure
- * for rate wells.  Also records the state as the start of the next step. */
+/* State (the non-equilibrium InitReservoir of Sec. 3.3.1: one state per
+ * cell).  p, sw, x3 (ignored by model 2), flag: [ncells]; bhp: [nwells] or
+ * NULL, which selects the target for BHP wells and the mean perforated-cell
+ * pressure for rate wells.  Also records the state as the start of the next
+ * step.  The state is not validated: a non-finite or non-physical state
+ * makes the next fim_step fail its Newton solves and return
+ * FIM_NOT_CONVERGED with this state restored.
+ * fim_set_state_dev: the same with p_dev, sw_dev, x3_dev (float64) and
+ * flag_dev (int8) device pointers to [ncells] elements on the context's
+ * device, read in order after the work queued on the stream given to
+ * fim_create (bhp stays a host pointer); the caller keeps ownership and may
+ * reuse the buffers once the call returns. */
 int fim_set_state(fim_ctx *ctx, const double *p, const double *sw, const double *x3,
                   const int8_t *flag, const double *bhp);
 int fim_set_state_dev(fim_ctx *ctx, const double *p_dev, const double *sw_dev,
@@ -272,17 +290,20 @@ int fim_get_well_rates(fim_ctx *ctx, double *q_surf, double *bhp);
 
 /* ---- testing hooks ------------------------------------------------------ */
 
-/* Static data (cell volume ft3, centre depth ft, reference pore volume rb,
+/* Static data of Sec. 3.2.3-3.2.4 (the PreProcess and ROCK setup, and the
+ * well indices of AllWells): cell volume ft3, centre depth ft, reference pore volume rb,
  * transmissibility to the +x/+y/+z neighbour, 0 on the boundary, and the
  * per-perforation well index in input order).  Any pointer may be NULL. */
 int fim_static(fim_ctx *ctx, double *vol, double *depth, double *pvref, double *tx,
                double *ty, double *tz, double *wi);
 
-/* Set the Newton iterate without changing the step-start accumulation. */
+/* Set the Newton iterate of Sec. 3.2.5 without changing the step-start
+ * accumulation (the x^n of the backward-Euler residual). */
 int fim_set_iterate(fim_ctx *ctx, const double *p, const double *sw, const double *x3,
                     const int8_t *flag, const double *bhp);
 
-/* Property record at the current iterate, out[q*ncells + c], q in
+/* Property record of Sec. 3.2.3 (Bulk: PVT, SAT, ROCK, ACCU; the black-oil
+ * closure of Sec. 2.1) at the current iterate, out[q*ncells + c], q in
  * [0, nprops): with np = nb phases (water, oil[, gas]) and a group = one
  * value followed by its derivatives w.r.t. (P, Sw[, X]):
  *   np groups Lam_j = kr_j b_j/mu_j;  (nb==3) 1 group Lam_og = Rs*Lam_o;
@@ -291,25 +312,33 @@ int fim_set_iterate(fim_ctx *ctx, const double *p, const double *sw, const doubl
  *   1 value PV (rb at P). */
 int fim_props(fim_ctx *ctx, double *out);
 
-/* Residual R[(ncells+nwells)*nb] and Jacobian at the current iterate for a
- * step of dt days; rowptr[ncells+nwells+1], colind[nnzb],
- * val[nnzb*nb*nb].  Any output pointer may be NULL. */
+/* The first part of a FIM Newton iteration (Sec. 3.2.5): the residual of
+ * eqs. (1)-(2) with the connection and well terms of Sec. 3.2.4,
+ * R[(ncells+nwells)*nb], and its Jacobian at the current iterate for a step
+ * of dt days; rowptr[ncells+nwells+1], colind[nnzb], val[nnzb*nb*nb].  Any
+ * output pointer may be NULL. */
 int fim_assemble(fim_ctx *ctx, double dt, double *R, int32_t *rowptr, int32_t *colind,
                  double *val);
 
-/* y = M^-1 x with the configured preconditioner (block Jacobi or CPR) of
- * the last assembled Jacobian; x, y: [(ncells+nwells)*nb]. */
+/* y = M^-1 x with the configured preconditioner of Sec. 5.1 (block Jacobi,
+ * block-Jacobi ILU(0) or CPR) of the last assembled Jacobian;
+ * x, y: [(ncells+nwells)*nb] host arrays. */
 int fim_precond_apply(fim_ctx *ctx, const double *x, double *y);
 
-/* Solve J x = b with the last assembled Jacobian by the configured
- * preconditioned GMRES; b, x: [(ncells+nwells)*nb] (x is the output, the
+/* The linear solve of Sec. 3.3.3 (the solution and its iteration count),
+ * by the preconditioned flexible GMRES of Sec. 5.1: J x = b with the last
+ * assembled Jacobian; b, x: [(ncells+nwells)*nb] (x is the output, the
  * initial guess is zero).  iters and relres (true ||b - J x||/||b||) may
  * be NULL.  Returns FIM_OK or FIM_NOT_CONVERGED. */
 int fim_linear_solve(fim_ctx *ctx, const double *b, double *x, int32_t *iters,
                      double *relres);
 
-/* y = A x for a canonical BSR matrix of nrows block rows with nb in {2,3};
- * every pointer is a device pointer; queued on hip_stream, no sync. */
+/* The matrix-vector product inside the Krylov solver of Sec. 5.1: y = A x
+ * for a canonical BSR matrix of nrows block rows with nb in {2,3}
+ * (rowptr[nrows+1] and colind[nnzb] int32, val[nnzb*nb*nb] float64 row-major
+ * blocks, x and y [nrows*nb] float64, every pointer a device pointer on the
+ * current device; colind entries must lie in [0, nrows)).  Queued on
+ * hip_stream, no synchronisation; the caller keeps ownership. */
 int fim_bsr_spmv(int32_t nrows, int32_t nb, const int32_t *rowptr_dev,
                  const int32_t *colind_dev, const double *val_dev, const double *x_dev,
                  double *y_dev, void *hip_stream);

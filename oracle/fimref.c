@@ -1150,6 +1150,18 @@ static int solve_linear(const fr_model *m, const double *val, const double *R, d
     return ok;
 }
 
+/* 1 when every saturation (Sw, So, Sg) of the state lies in [-1e-6, 1 + 1e-6] */
+static int physical(const fr_model *m, const state_t *s) {
+    for (int c = 0; c < m->n; ++c) {
+        double sw = s->Sw[c];
+        double sg = (m->nb == 3 && s->flag[c] == FR_SAT) ? s->X[c] : 0.0;
+        double so = 1.0 - sw - sg;
+        double lo = fmin(fmin(sw, so), sg), hi = fmax(fmax(sw, so), sg);
+        if (!(lo >= -1e-6 && hi <= 1.0 + 1e-6)) return 0;
+    }
+    return 1;
+}
+
 /* Newton iterations for one sub-step; 1 on convergence. */
 static int newton(const fr_model *m, state_t *s, double dt, const fr_options *o, fr_report *rep) {
     int n = m->n, nb = m->nb;
@@ -1177,7 +1189,10 @@ static int newton(const fr_model *m, state_t *s, double dt, const fr_options *o,
                    well_rows_ok(m, R, val, o->tol_well);
         for (int i = 0; i < nb; ++i)
             conv = conv && rep->cnv[i] <= o->tol_cnv && rep->mb[i] <= o->tol_mb;
-        if (conv) { ok = 1; break; }
+        /* a root whose saturations leave [0, 1] by more than 1e-6 is not a
+         * physical state: the sub-step fails (a reading; the paper counts
+         * non-physical results among the failures that cut the step) */
+        if (conv) { ok = physical(m, s); break; }
         if (it >= o->max_newton) break;
         int li = 0;
         int lin_ok = solve_linear(m, val, R, dx, o, &li);

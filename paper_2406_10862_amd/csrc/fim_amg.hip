@@ -771,7 +771,6 @@ __global__ __launch_bounds__(kBlock) void k_amg_restrict(AmgLevel F, AmgLevel C)
 // LDS and each aggregate then sums its existing children in the same
 // (k, j, i) order as k_amg_restrict, so the sums are the same bit for bit.
 constexpr int kSegAgg = 32;
-constexpr int kSegPairHalf = 1 << 18;      // levels with at least this many entries per colour
 
 __global__ __launch_bounds__(kBlock) void k_amg_restrict_rows(AmgLevel F, AmgLevel C, int nseg,
                                                               int cell_blocks) {
@@ -1174,8 +1173,8 @@ void launch_amg_well_sweep(hipStream_t s, const AmgLevel &L) {
     if (L.nw) hipLaunchKernelGGL(k_amg_well_sweep, grid_for(64L * L.nw, kBlock), dim3(kBlock), 0, s, L);
 }
 
-void launch_amg_restrict(hipStream_t s, const AmgLevel &F, const AmgLevel &C) {
-    if (F.half >= kSegPairHalf) {
+void launch_amg_restrict(hipStream_t s, const AmgLevel &F, const AmgLevel &C, long seg_min) {
+    if (seg_min > 0 && F.half >= seg_min) {
         const int nseg = (C.nx + kSegAgg - 1) / kSegAgg;
         const long cell_blocks = (long)nseg * C.ny * C.nz;
         const long well_blocks = (64L * F.nw + kBlock - 1) / kBlock;

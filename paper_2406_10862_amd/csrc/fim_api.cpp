@@ -86,6 +86,9 @@ int guarded(F &&f) {
 // scalar slots in the device/pinned scalar area
 enum { S_CONV = 0, S_UPD = 16, S_NORM = 20, S_RES = 24, S_COUNT = 32 };
 
+// how far a saturation of a converged iterate may lie outside [0, 1]
+constexpr double kSatSlack = 1e-6;
+
 }  // namespace
 
 struct fim_ctx {
@@ -435,7 +438,21 @@ static int create_impl(const fim_grid *grid, const fim_rock *rock, const fim_flu
     REQUIRE(grid && rock && fl, "grid, rock and fluid are required");
     REQUIRE(grid->nx >= 1 && grid->ny >= 1 && grid->nz >= 1, "grid dimensions must be >= 1");
     const long nl = (long)grid->nx * grid->ny * grid->nz;
-    REQUIRE(nl < (1L << 28), "grid too large (%ld cells)", nl);
+    REQUIRE(nl < (1L << 28), "grid too large (%ld cells, at most 2^28 - 1)", nl);
+    REQUIRE(nwells >= 0 && (nwells == 0 || wells), "wells pointer required");
+    {
+        // the kernels address the Jacobian values with 32-bit integers: bound
+        // nnzb*nb*nb from the dimensions before any per-cell array is read
+        const long faces = (long)(grid->nx - 1) * grid->ny * grid->nz +
+                           (long)grid->nx * (grid->ny - 1) * grid->nz +
+                           (long)grid->nx * grid->ny * (grid->nz - 1);
+        long nperf = 0;
+        for (int wl = 0; wl < nwells; ++wl) nperf += std::max(wells[wl].nperf, 0);
+        const long nbb = (fl && fl->model == FIM_BLACKOIL_3P) ? 9 : 4;
+        const long nnzb = nl + 2 * faces + 2 * nperf + nwells;
+        REQUIRE(nnzb * nbb < (1L << 31),
+                "system too large: %ld blocks of %ld values (at most 2^31 - 1 values)", nnzb, nbb);
+    }
     REQUIRE(grid->dx && grid->dy && grid->dz, "dx, dy, dz are required");
     for (int i = 0; i < grid->nx; ++i) REQUIRE(grid->dx[i] > 0, "dx must be > 0");
     for (int i = 0; i < grid->ny; ++i) REQUIRE(grid->dy[i] > 0, "dy must be > 0");
@@ -471,7 +488,6 @@ static int create_impl(const fim_grid *grid, const fim_rock *rock, const fim_flu
     REQUIRE(fl->swc >= 0 && fl->sor >= 0 && fl->sgc >= 0 &&
                 fl->swc + fl->sor + (bo3 ? fl->sgc : 0.0) < 1,
             "end points must satisfy swc + sor (+ sgc) < 1");
-    REQUIRE(nwells >= 0 && (nwells == 0 || wells), "wells pointer required");
     check_options(opt);
 
     auto *c = new fim_ctx();
@@ -790,7 +806,8 @@ static void amg_cycle(fim_ctx *c, int l, std::vector<int> *rec = nullptr, int ro
             rec->push_back(amg_op(kOpRestrict, rl));
         } else {
             if (gv > 0) launch_amg_correct(c->s, F, C);
-            launch_amg_restrict(c->s, F, C);
+            const int sr = c->opt.amg_seg_rows;
+            launch_amg_restrict(c->s, F, C, sr == 0 ? (long)kSegRowsDefault : (long)sr);
         }
         amg_cycle(c, l + 1, rec, root);
     }
@@ -1385,7 +1402,7 @@ static bool debug_on() {
 static bool newton(fim_ctx *c, double dt, NewtonStats &st) {
     const fim_options &o = c->opt;
     const int nb = c->nb;
-    double last_dp = INFINITY, last_ds = INFINITY;
+    double last_dp = INFINITY, last_ds = INFINITY, last_viol = 0.0;
     bool pending_update = false;
     Forcing forcing;
     for (int it = 0;; ++it) {
@@ -1403,6 +1420,7 @@ static bool newton(fim_ctx *c, double dt, NewtonStats &st) {
         if (it > 0) {
             last_dp = c->pin[S_UPD];
             last_ds = c->pin[S_UPD + 1];
+            last_viol = c->pin[S_UPD + 2];
         }
         bool finite = std::isfinite(last_dp) || it == 0;
         bool conv = it > 0;
@@ -1424,7 +1442,10 @@ static bool newton(fim_ctx *c, double dt, NewtonStats &st) {
                          "[fim] dt %.4g it %d cnv %.2e %.2e mb %.2e %.2e well %.2e dp %.2e ds %.2e%s\n",
                          dt, it, st.cnv[0], st.cnv[1], st.mb[0], st.mb[1], wmax, last_dp, last_ds,
                          conv ? " converged" : "");
-        if (conv) return true;
+        // a converged iterate must be physical: a root with a saturation
+        // outside [0, 1] (beyond kSatSlack) fails the solve like a
+        // non-finite one
+        if (conv) return last_viol <= kSatSlack;
         if (it >= o.max_newton) return false;
 
         prec_setup(c);

@@ -192,7 +192,10 @@ void launch_amg_coarsest_solve(hipStream_t s, const AmgLevel &L, const double *M
 void launch_amg_sweep(hipStream_t s, const AmgLevel &L, const AmgLevel &C, int color, int mode);
 void launch_amg_well_sweep(hipStream_t s, const AmgLevel &L);
 void launch_amg_presmooth(hipStream_t s, const AmgLevel &L);
-void launch_amg_restrict(hipStream_t s, const AmgLevel &F, const AmgLevel &C);
+// seg_min: levels with at least this many entries per colour restrict by
+// row segments (<= 0: never); the sums are the same bit for bit
+constexpr int kSegRowsDefault = 1 << 18;
+void launch_amg_restrict(hipStream_t s, const AmgLevel &F, const AmgLevel &C, long seg_min);
 void launch_amg_correct(hipStream_t s, const AmgLevel &F, const AmgLevel &C);
 void launch_cpr_restrict(hipStream_t s, int nb, int n, int nw, const AmgLevel &L,
                          const int *split0, const double *w, const double *hptr, double *v,

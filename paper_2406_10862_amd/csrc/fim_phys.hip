@@ -606,7 +606,8 @@ __global__ __launch_bounds__(kBlock) void k_conv_finish(int nparts, const double
 
 // ---------------------------------------------------------------------------
 // Newton update: delta = -y; per-cell saturation chop and pressure clip,
-// three-phase variable switching; out = [max|dP| (cells and wells), max|dS|]
+// three-phase variable switching; out = [max|dP| (cells and wells), max|dS|,
+// largest distance of a saturation of the new iterate outside [0, 1]]
 
 template <int NB>
 __global__ __launch_bounds__(kBlock) void k_newton_update(Phys f, int n, int nw,
@@ -620,8 +621,8 @@ __global__ __launch_bounds__(kBlock) void k_newton_update(Phys f, int n, int nw,
     __shared__ double sm[6 * kMaxTableRows];
     TabL t;
     stage_table(f, sm, t);
-    double v[2] = {0.0, 0.0};
-    const bool mx[2] = {true, true};
+    double v[3] = {0.0, 0.0, 0.0};
+    const bool mx[3] = {true, true, true};
     for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
         double dP = -y[(size_t)c * NB];
         dP = fmin(fmax(dP, -dp_max), dp_max);
@@ -636,10 +637,12 @@ __global__ __launch_bounds__(kBlock) void k_newton_update(Phys f, int n, int nw,
             if (sat) dX *= a;
         }
         const double p = P[c] + dP;
+        const double sw = Sw[c] + dS;
         P[c] = p;
-        Sw[c] += dS;
+        Sw[c] = sw;
         v[0] = rop(v[0], fabs(dP), true);
         v[1] = rop(v[1], fabs(dS), true);
+        double sg = 0.0;
         if constexpr (NB == 3) {
             if (sat) v[1] = rop(v[1], fabs(dX), true);
             const double x = X[c] + dX;
@@ -651,11 +654,16 @@ __global__ __launch_bounds__(kBlock) void k_newton_update(Phys f, int n, int nw,
                 X[c] = 0.0;
             } else {
                 X[c] = x;
+                if (sat) sg = x;
             }
         }
+        // distance of the saturations (Sw, So, Sg) outside [0, 1]
+        const double so = 1.0 - sw - sg;
+        v[2] = rop(v[2], fmax(fmax(fmax(-sw, sw - 1.0), fmax(-so, so - 1.0)), fmax(-sg, sg - 1.0)),
+                   true);
         if (dP != dP || dS != dS || dX != dX) v[0] = NAN;
     }
-    block_partials<2>(v, mx, partials);
+    block_partials<3>(v, mx, partials);
 }
 
 // One block: combines the cell maxima and updates the well pressures (the
@@ -665,9 +673,9 @@ __global__ __launch_bounds__(kBlock) void k_newton_finish(int nparts, int n, int
                                                           const double *__restrict__ y,
                                                           double dp_max, double *pbhp,
                                                           const double *partials, double *out) {
-    const bool mx[2] = {true, true};
-    double a[2];
-    finish_partials<2>(nparts, mx, partials, a);
+    const bool mx[3] = {true, true, true};
+    double a[3];
+    finish_partials<3>(nparts, mx, partials, a);
     if (threadIdx.x == 0) {
         double m = a[0];
         for (int wl = 0; wl < nw; ++wl) {
@@ -679,6 +687,7 @@ __global__ __launch_bounds__(kBlock) void k_newton_finish(int nparts, int n, int
         }
         out[0] = m;
         out[1] = a[1];
+        out[2] = a[2];
     }
 }
 

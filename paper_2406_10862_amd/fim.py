@@ -62,7 +62,7 @@ class FimOptions(C.Structure):
                 ("profile", C.c_int32), ("amg_cycle", C.c_int32), ("amg_sweeps", C.c_int32),
                 ("graphs", C.c_int32), ("forcing", C.c_int32), ("amg_fused", C.c_int32),
                 ("tile_nx", C.c_int32), ("tile_ny", C.c_int32), ("tile_nz", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("amg_seg_rows", C.c_int32)]
 
 
 class FimStepReport(C.Structure):
@@ -159,6 +159,36 @@ def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
 
 
+def _tensor_shape(t, dtype, numel, name):
+    import torch
+
+    if not isinstance(t, torch.Tensor):
+        raise FimError(f"{name}: a torch tensor is required, got {type(t).__name__}")
+    if t.dtype != dtype:
+        raise FimError(f"{name}: dtype {t.dtype}, {dtype} required")
+    if not t.is_contiguous():
+        raise FimError(f"{name}: the tensor must be contiguous")
+    if t.numel() != numel:
+        raise FimError(f"{name}: {t.numel()} elements, {numel} required")
+
+
+def _tensor_device(t, name, device):
+    if t.device.type != "cuda":
+        raise FimError(f"{name}: a GPU tensor is required, got device {t.device}")
+    if device is not None and t.device.index != device:
+        raise FimError(f"{name}: on cuda:{t.device.index}, the context is on cuda:{device}")
+
+
+def dev_ptr(t, dtype, numel, name, device=None):
+    """data_ptr() of a torch tensor handed to a "_dev" entry point, after
+    checking what the library takes on trust: element type, contiguity,
+    element count and a GPU device (the given one when set).  Raises FimError
+    before anything is launched."""
+    _tensor_shape(t, dtype, numel, name)
+    _tensor_device(t, name, device)
+    return C.c_void_p(t.data_ptr())
+
+
 def current_stream():
     """hipStream_t of torch's current stream, or NULL without torch/GPU."""
     try:
@@ -170,6 +200,17 @@ def current_stream():
     return C.c_void_p(0)
 
 
+def _current_device():
+    """torch's current GPU index, or None without a GPU."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return torch.cuda.current_device()
+    except Exception:
+        pass
+    return None
+
+
 def options_struct(o: rv.Options, profile=False) -> FimOptions:
     return FimOptions(tol_cnv=o.tol_cnv, tol_mb=o.tol_mb, tol_dp=o.tol_dp, tol_ds=o.tol_ds,
                       tol_well=o.tol_well, ds_max=o.ds_max, dp_max=o.dp_max,
@@ -178,7 +219,8 @@ def options_struct(o: rv.Options, profile=False) -> FimOptions:
                       precision=o.precision, profile=1 if profile else 0,
                       amg_cycle=o.amg_cycle, amg_sweeps=o.amg_sweeps, graphs=o.graphs,
                       forcing=o.forcing, amg_fused=o.amg_fused,
-                      tile_nx=o.tile[0], tile_ny=o.tile[1], tile_nz=o.tile[2], reserved=0)
+                      tile_nx=o.tile[0], tile_ny=o.tile[1], tile_nz=o.tile[2],
+                      amg_seg_rows=o.amg_seg_rows)
 
 
 class Fim:
@@ -215,6 +257,7 @@ class Fim:
         self.options = options if options is not None else res.options
         opt = options_struct(self.options, profile)
         self.stream = current_stream() if stream is None else stream
+        self.device = _current_device()
         h = C.c_void_p()
         _check(L.fim_create(C.byref(grid), C.byref(rock), C.byref(fluid), len(res.wells),
                             wells, C.byref(opt), self.stream, C.byref(h)), "fim_create")
@@ -253,11 +296,21 @@ class Fim:
                                    _p(flag, i8p), _p(bhp, f64p)), "fim_set_state")
 
     def fim_set_state_dev(self, P, Sw, X=None, flag=None, bhp=None):
-        """Device tensors (torch) on the context's device and stream."""
-        ptr = lambda t: C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+        """Contiguous torch GPU tensors on the context's device: P, Sw, X
+        float64 and flag int8, ncells elements each (X and flag may be None);
+        read in order after the work on the context's stream."""
+        import torch
+
+        n, dv = self.n, self.device
+        pP = dev_ptr(P, torch.float64, n, "P", dv)
+        pS = dev_ptr(Sw, torch.float64, n, "Sw", dv)
+        pX = dev_ptr(X, torch.float64, n, "X", dv) if X is not None else C.c_void_p(0)
+        pF = dev_ptr(flag, torch.int8, n, "flag", dv) if flag is not None else C.c_void_p(0)
         bhp = _f64(bhp) if bhp is not None and len(bhp) else None
-        _check(lib().fim_set_state_dev(self.h, ptr(P), ptr(Sw), ptr(X), ptr(flag),
-                                       _p(bhp, f64p)), "fim_set_state_dev")
+        if bhp is not None and bhp.size != self.nw:
+            raise FimError(f"bhp: {bhp.size} values, {self.nw} wells")
+        _check(lib().fim_set_state_dev(self.h, pP, pS, pX, pF, _p(bhp, f64p)),
+               "fim_set_state_dev")
 
     def fim_set_iterate(self, P, Sw, X=None, flag=None, bhp=None):
         P, Sw = _f64(P), _f64(Sw)
@@ -349,11 +402,25 @@ class Fim:
 
 
 def fim_bsr_spmv(nrows, nb, rowptr, colind, val, x, y, stream=None):
-    """y = A x on torch device tensors (canonical BSR, interleaved vectors)."""
+    """y = A x on contiguous torch GPU tensors of one device (canonical BSR:
+    rowptr int32 [nrows+1], colind int32 [nnzb], val float64 [nnzb*nb*nb];
+    x, y float64 [nrows*nb] interleaved).  Column indices are not checked."""
+    import torch
+
+    nrows, nb = int(nrows), int(nb)
+    if nb not in (2, 3) or nrows < 0:
+        raise FimError(f"fim_bsr_spmv: nb {nb} (2 or 3) and nrows {nrows} (>= 0)")
+    nnzb = colind.numel() if isinstance(colind, torch.Tensor) else -1
+    ops = [(rowptr, torch.int32, nrows + 1, "rowptr"), (colind, torch.int32, nnzb, "colind"),
+           (val, torch.float64, nnzb * nb * nb, "val"), (x, torch.float64, nrows * nb, "x"),
+           (y, torch.float64, nrows * nb, "y")]
+    for t, dt, ne, name in ops:
+        _tensor_shape(t, dt, ne, name)
+    for t, _, _, name in ops:
+        _tensor_device(t, name, rowptr.device.index)
+    ptr = [C.c_void_p(t.data_ptr()) for t, _, _, _ in ops]
     s = current_stream() if stream is None else stream
-    ptr = lambda t: C.c_void_p(t.data_ptr())
-    _check(lib().fim_bsr_spmv(int(nrows), int(nb), ptr(rowptr), ptr(colind), ptr(val), ptr(x),
-                              ptr(y), s), "fim_bsr_spmv")
+    _check(lib().fim_bsr_spmv(nrows, nb, *ptr, s), "fim_bsr_spmv")
 
 
 def fim_ensemble_run(members, dt, workers=0):

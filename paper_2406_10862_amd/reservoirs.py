@@ -98,6 +98,7 @@ class Options:
     forcing: int = 1            # Eisenstat-Walker forcing term (lin_rtol is the floor)
     amg_fused: int = 0          # cells below which the AMG cycle runs fused (0 default, <0 off)
     tile: tuple = (0, 0, 0)     # block-Jacobi ILU(0) subdomain box (0 = 8 cells per axis)
+    amg_seg_rows: int = 0       # entries per colour from which AMG restricts by row segments
 
 
 @dataclass

@@ -119,3 +119,70 @@ def test_ensemble_rejects_bad_arguments_without_a_device():
     assert b"must be >= 0" in L.fim_last_error()
     assert L.fim_ensemble_run(2, None, 1, None, 4, None, None) == fim.FIM_E_ARG
     assert b"required" in L.fim_last_error()
+
+
+def _raw_create(nx, ny, nz, model=2, wells=()):
+    """fim_create on a grid given by its dimensions only: one-element arrays
+    stand in for every per-cell array, so the call must reject the size
+    before it reads any of them."""
+    L = fim.lib()
+    one = (C.c_double * 1)(1.0)
+    f64 = C.cast(one, fim.f64p)
+    grid = fim.FimGrid(nx, ny, nz, f64, f64, f64, 0.0)
+    rock = fim.FimRock(f64, f64, f64, f64, 0.0, 0.0)
+    fl = rv.deadoil_fluid() if model == 2 else rv.blackoil_fluid()
+    keep = [np.ascontiguousarray(a, np.float64) for a in (fl.p, fl.bo, fl.rs, fl.muo, fl.bg, fl.mug)]
+    ptr = [a.ctypes.data_as(fim.f64p) for a in keep]
+    fluid = fim.FimFluid(model=model, nrows=len(fl.p), p=ptr[0], bo=ptr[1], rs=ptr[2],
+                         muo=ptr[3], bg=ptr[4], mug=ptr[5])
+    wl = (fim.FimWell * max(len(wells), 1))(*wells)
+    opt = fim.options_struct(rv.Options())
+    h = C.c_void_p()
+    rc = L.fim_create(C.byref(grid), C.byref(rock), C.byref(fluid), len(wells), wl,
+                      C.byref(opt), C.c_void_p(0), C.byref(h))
+    return rc, L.fim_last_error().decode(), h
+
+
+def test_create_rejects_sizes_the_32_bit_indexing_cannot_address():
+    # 2^28 cells
+    rc, msg, h = _raw_create(1024, 1024, 256)
+    assert rc == fim.FIM_E_ARG and "grid too large" in msg and not h.value
+    # 10^8 cells: about 7*10^8 blocks, 2.8*10^9 values of 2x2 blocks
+    rc, msg, h = _raw_create(1000, 1000, 100)
+    assert rc == fim.FIM_E_ARG and "system too large" in msg and not h.value
+    # 3x3 blocks reach the limit at fewer cells: 40M cells, 2.5*10^9 values
+    rc, msg, h = _raw_create(400, 1000, 100, model=3)
+    assert rc == fim.FIM_E_ARG and "system too large" in msg and not h.value
+    # and the same grid with 2x2 blocks (1.1*10^9 values) passes the size
+    # check, to fail on the first per-cell array instead
+    rc, msg, h = _raw_create(400, 1000, 100, model=2)
+    assert "system too large" not in msg
+
+
+def test_device_tensor_checks_reject_bad_tensors_before_any_launch():
+    torch = pytest.importorskip("torch")
+    good = torch.zeros(12, dtype=torch.float64)
+    with pytest.raises(fim.FimError, match="dtype"):
+        fim.dev_ptr(good.float(), torch.float64, 12, "P")
+    with pytest.raises(fim.FimError, match="contiguous"):
+        fim.dev_ptr(torch.zeros(12, 2, dtype=torch.float64)[:, 0], torch.float64, 12, "P")
+    with pytest.raises(fim.FimError, match="elements"):
+        fim.dev_ptr(good[:11], torch.float64, 12, "P")
+    with pytest.raises(fim.FimError, match="GPU tensor"):
+        fim.dev_ptr(good, torch.float64, 12, "P")
+    with pytest.raises(fim.FimError, match="torch tensor"):
+        fim.dev_ptr(np.zeros(12), torch.float64, 12, "P")
+    # the SpMV wrapper checks every operand the same way
+    rp = torch.zeros(5, dtype=torch.int32)
+    ci = torch.zeros(3, dtype=torch.int32)
+    with pytest.raises(fim.FimError, match="rowptr: dtype"):
+        fim.fim_bsr_spmv(4, 2, rp.long(), ci, torch.zeros(12, dtype=torch.float64),
+                         torch.zeros(8, dtype=torch.float64), torch.zeros(8, dtype=torch.float64))
+    with pytest.raises(fim.FimError, match="val: .*elements"):
+        fim.fim_bsr_spmv(4, 2, rp, ci, torch.zeros(11, dtype=torch.float64),
+                         torch.zeros(8, dtype=torch.float64), torch.zeros(8, dtype=torch.float64))
+    with pytest.raises(fim.FimError, match="GPU tensor"):
+        fim.fim_bsr_spmv(4, 2, rp, ci, torch.zeros(12, dtype=torch.float64),
+                         torch.zeros(8, dtype=torch.float64), torch.zeros(8, dtype=torch.float64))
+    with pytest.raises(fim.FimError, match="nb 4"):
+        fim.fim_bsr_spmv(4, 4, rp, ci, None, None, None)

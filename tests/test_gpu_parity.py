@@ -168,8 +168,9 @@ def _gpu_spmv(rowptr, colind, val, x, nb):
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(d)
     y = torch.full((max(nrows * nb, 1),), np.nan, dtype=torch.float64, device=d)
     xs = t(x) if len(x) else torch.zeros(1, dtype=torch.float64, device=d)
+    # a matrix without blocks still passes one (unused) column index and block
     fim.fim_bsr_spmv(nrows, nb, t(rowptr), t(colind) if len(colind) else t(np.zeros(1, np.int32)),
-                     t(val) if len(val) else t(np.zeros(1)), xs, y)
+                     t(val) if len(val) else t(np.zeros(nb * nb)), xs, y)
     torch.cuda.synchronize()
     return y.cpu().numpy()[: nrows * nb]
 

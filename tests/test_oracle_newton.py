@@ -224,3 +224,42 @@ def test_restart_from_saved_state_is_bitwise_identical():
         assert c.step(dt)[0] == 0
     for k in ["P", "Sw", "X", "flag", "pbhp"]:
         assert np.array_equal(getattr(a, k), getattr(c, k)), k
+
+
+def test_non_finite_state_fails_every_cut_and_is_restored():
+    """A NaN in the state makes the residual non-finite: every sub-step
+    fails, dt is halved up to max_cuts times, then the step fails with the
+    state it started from (NaN included)."""
+    res = rv.config_c2_small(6, 6, 3)
+    m = OracleModel(res)
+    m.P[17] = np.nan
+    start = m.state()
+    st, rep = m.step(10.0, m.options(max_cuts=3))
+    assert st == 1 and rep.cuts == 4 and rep.nsub == 0 and rep.newton_iters == 0
+    for k, v in start.items():
+        assert np.array_equal(getattr(m, k), v, equal_nan=True), k
+
+
+@pytest.mark.parametrize("cfg", ["deadoil", "blackoil"])
+def test_negative_saturation_state_is_rejected_and_restored(cfg):
+    """A state with a negative water saturation in one cell reaches a root of
+    the discrete equations that keeps the negative saturation (no water can
+    flow out of a cell below connate saturation); a root outside [0, 1]
+    fails the sub-step, so every cut fails and the step returns with its
+    start state."""
+    if cfg == "deadoil":
+        res = rv.config_c2_small(6, 6, 3)
+    else:
+        res = rv.config_c1()
+    m = OracleModel(res)
+    m.Sw[11] = -0.05
+    start = m.state()
+    st, rep = m.step(res.schedule[0], m.options(max_cuts=2))
+    assert st == 1 and rep.cuts == 3 and rep.nsub == 0 and rep.newton_iters > 0
+    for k, v in start.items():
+        assert np.array_equal(getattr(m, k), v), k
+    # the same state with the cell at zero saturation steps normally
+    m2 = OracleModel(res)
+    m2.Sw[11] = 0.0
+    st, rep = m2.step(res.schedule[0], m2.options(max_cuts=2))
+    assert st == 0
