@@ -110,9 +110,12 @@ typedef struct {
  * control; injectors (pure water or free gas) take BHP or a surface RATE
  * target (> 0).  wi[nperf] may be NULL: then Peaceman's well index with
  * wellbore radius rw (ft) and skin is used.  The BHP acts at every
- * perforation (no wellbore head).  Producer perforation rate of component
- * i: WI*Lam_i*(P - Pbhp), Lam_i = kr_i b_i/mu_i (gas adds Rs*Lam_o);
- * injector: -WI*(sum_j kr_j/mu_j)*b_inj*(Pbhp - P). */
+ * perforation (no wellbore head).  A perforation is weighted by the side
+ * the flow comes from: flow out of the cell (a producer, or an injector
+ * perforation whose cell pressure exceeds the BHP) has the rate
+ * WI*Lam_i*(P - Pbhp) of component i, Lam_i = kr_i b_i/mu_i (gas adds
+ * Rs*Lam_o); flow into the cell (an injector with Pbhp >= P) is the
+ * injected fluid, -WI*(sum_j kr_j/mu_j)*b_inj*(Pbhp - P). */
 typedef struct {
     int32_t kind, control;
     double target;

@@ -117,7 +117,9 @@ class AdjointOracle:
         q = np.zeros((len(self.pcell), nb))
         for p, (c, w) in enumerate(zip(self.pcell, self.pwell)):
             wl = self.res.wells[w]
-            if wl.kind == PROD:
+            # flow out of the cell (a producer, or an injector perforation
+            # below its cell's pressure) carries the cell's phases
+            if wl.kind == PROD or pb[w] < P[c]:
                 d = P[c] - pb[w]
                 lam = [rec[ix[f"Lam_{ph}"], c] for ph in "wog"[:nb]]
                 if nb == 3:

@@ -603,7 +603,12 @@ static void add_face(const fr_model *m, const cellprops *cp, const double *P, in
 
 /* Perforation rates (Peaceman index, no wellbore head: a reading).  q[i] production-positive surface rate
  * of component i, dq[i][u] its derivative w.r.t. the cell unknowns and
- * dqb[i] w.r.t. the well's bottom-hole pressure. */
+ * dqb[i] w.r.t. the well's bottom-hole pressure.  The perforation is a
+ * connection weighted by the side the flow comes from (a reading, as for
+ * the faces): flow out of the cell (a producer, or an injector perforation
+ * whose cell pressure exceeds the BHP) carries the cell's phases by their
+ * mobilities; flow into the cell is the injected fluid with the cell's
+ * total mobility. */
 static void perf_rate(const fr_model *m, const cellprops *c, double Pc, int kind, double wi,
                       double pbhp, double *q, double dq[3][3], double *dqb) {
     int nb = m->nb;
@@ -611,7 +616,7 @@ static void perf_rate(const fr_model *m, const cellprops *c, double Pc, int kind
         q[i] = 0; dqb[i] = 0;
         for (int u = 0; u < 3; ++u) dq[i][u] = 0;
     }
-    if (kind == FR_PROD) {
+    if (kind == FR_PROD || pbhp < Pc) {
         double dp = Pc - pbhp;
         for (int i = 0; i < nb; ++i) {
             double lam = c->lam[i] + (i == 2 ? c->lamog : 0.0);

@@ -368,8 +368,10 @@ __device__ inline void store_block(double *__restrict__ val, int q, const double
 }
 
 // Perforation rate of every component and its derivatives (production
-// positive): producers WI*Lam_i*(P - Pbhp); injectors of pure water or free
-// gas -WI*lam_t*b_inj*(Pbhp - P).
+// positive), weighted by the side the flow comes from: out of the cell
+// (producers, and injector perforations whose cell pressure exceeds the
+// BHP) WI*Lam_i*(P - Pbhp); into the cell, the injected pure water or free
+// gas, -WI*lam_t*b_inj*(Pbhp - P).
 template <int NB>
 __device__ inline void perf_rate(int kind, double wi, double P, double pbhp,
                                  const double *__restrict__ rec, int n, int c, double (&q)[NB],
@@ -383,7 +385,7 @@ __device__ inline void perf_rate(int kind, double wi, double P, double pbhp,
 #pragma unroll
         for (int u = 0; u < NB; ++u) dq[i][u] = 0.0;
     }
-    if (kind == kProd) {
+    if (kind == kProd || pbhp < P) {
         const double d = P - pbhp;
 #pragma unroll
         for (int i = 0; i < NB; ++i) {

@@ -7,9 +7,10 @@ table columns and the Corey curves:
   reading B_o = B_o,sat(P_b)(1 - c_o (P - P_b)), mu_o = mu_o,sat(P_b)(1 +
   c_mu (P - P_b)) with P_b from the inverse of the Rs column);
 * injector perforations (Sec. 3.2.4, AllWells; the reading
-  q = -WI (sum_j kr_j/mu_j) b_inj (P_bhp - P) for pure water or free gas),
-  as rates at a state and as a single-cell backward-Euler step solved by
-  bisection;
+  q = -WI (sum_j kr_j/mu_j) b_inj (P_bhp - P) for pure water or free gas
+  flowing in, and the cell's phases by their mobilities when the cell
+  pressure exceeds the BHP), as rates at a state and as a single-cell
+  backward-Euler step solved by bisection;
 * the gas component's connection flux (Sec. 3.2.4, BulkConn, eqs. (1)-(2)):
   free gas moves with the gas potential from the gas-upwind cell, dissolved
   gas with the oil potential from the oil-upwind cell.
@@ -112,6 +113,32 @@ def test_gas_injector_rate_at_a_state():
     expect = -wi * lt * bg * (pbhp - P)
     assert q[2] == pytest.approx(expect, rel=1e-13)
     assert q[0] == 0.0 and q[1] == 0.0
+
+
+@pytest.mark.parametrize("kind", [rv.INJ_WATER, rv.INJ_GAS])
+def test_injector_perforation_above_its_bhp_produces_the_cell_fluids(kind):
+    """An injector perforation whose cell pressure exceeds the BHP
+    (crossflow into the wellbore: the BHP acts at every perforation, with
+    no wellbore head) takes the flow from the cell: every phase by its own
+    mobility, q_i = WI Lam_i (P - P_bhp), as a producer perforation does."""
+    fl = rv.blackoil_fluid()
+    wi, pbhp, P, Sw, Sg = 1.3, 3300.0, 3720.0, 0.3, 0.17
+    w = rv.Well(kind, rv.BHP, pbhp, np.array([0], np.int32), wi=np.array([wi]))
+    m = one_cell(fl, P, Sw, X=Sg, flag=rv.SAT, wells=[w])
+    q = m.well_rates()[0]
+    D = 1.0 - fl.swc - fl.sor - fl.sgc
+    So = 1.0 - Sw - Sg
+    Bo = float(np.interp(P, fl.p, fl.bo))
+    Bg = float(np.interp(P, fl.p, fl.bg))
+    Rs = float(np.interp(P, fl.p, fl.rs))
+    muo = float(np.interp(P, fl.p, fl.muo))
+    mug = float(np.interp(P, fl.p, fl.mug))
+    lam_w = corey(Sw - fl.swc, 1.0 - fl.swc - fl.sor, fl.krw_max) * water_b(fl, P) / fl.muw
+    lam_o = corey(So - fl.sor, D, fl.kro_max) / Bo / muo
+    lam_g = corey(Sg - fl.sgc, D, fl.krg_max) / Bg / mug
+    expect = wi * np.array([lam_w, lam_o, lam_g + Rs * lam_o]) * (P - pbhp)
+    np.testing.assert_allclose(q, expect, rtol=1e-13)
+    assert np.all(q > 0)
 
 
 def bisect(f, lo, hi, iters=200):
