@@ -234,6 +234,20 @@ int fim_get_state(fim_ctx *ctx, double *p, double *sw, double *x3, int8_t *flag,
  * in place; fills rep (may be NULL).  Returns FIM_OK or FIM_NOT_CONVERGED. */
 int fim_step(fim_ctx *ctx, double dt_days, fim_step_report *rep);
 
+/* fim_step for callers that cannot allocate device memory once the context
+ * exists (serving loops, harnesses that forbid allocation): the same step,
+ * bit for bit, that allocates no device memory.  Its reduction partials and
+ * scalar slots live in a static array of 65,568 doubles (512.25 KiB) that
+ * the library holds on every device it runs on until the process ends; the
+ * kernels are launched one by one (no graph executable is instantiated, the
+ * graphs option is ignored for the call) and the profile option is ignored.
+ * One step needs (restart + 1) * min(2048, ceil((ncells+nwells)*nb/256))
+ * doubles of partials (restart <= 31 always fits); a larger need is
+ * rejected with FIM_E_ARG before any work.  The array is shared by every
+ * call on a device: calls that overlap on one device (two threads, or
+ * fim_ensemble_run members) race and must not be made. */
+int fim_step_noalloc(fim_ctx *ctx, double dt_days, fim_step_report *rep);
+
 /* Discrete adjoint: the gradient of a production mismatch with respect to
  * the log-permeability of every cell.  The paper has no adjoint; the
  * gradient is that of the discrete system it solves, the backward-Euler

@@ -1803,6 +1803,82 @@ static void put_state(fim_ctx *c, const double *p, const double *sw, const doubl
 }
 
 // ---------------------------------------------------------------------------
+// the step without device allocation (fim_step_noalloc)
+//
+// The reduction partials and the scalar slots of a step live in one static
+// device array, `scratch`: every GPU the library runs on holds its own copy
+// until the process ends.  Host code never passes the array's name to a
+// kernel (on the host it is a stand-in, not a device address); the device
+// address comes from hipGetSymbolAddress, once per device with that device
+// current, and is kept per device.
+
+constexpr size_t kNoAllocPartials = (size_t)32 * 2048;   // reduction partials
+constexpr size_t kNoAllocDoubles = kNoAllocPartials + S_COUNT;   // + scalar slots
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch_dev[kMaxDevices] = {};
+
+// the device address of `scratch` on device dev
+static double *scratch_on(int dev) {
+    REQUIRE(dev >= 0 && dev < kMaxDevices, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        int cur = 0;
+        HIPCHECK(hipGetDevice(&cur));
+        if (cur != dev) HIPCHECK(hipSetDevice(dev));
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (cur != dev) HIPCHECK(hipSetDevice(cur));
+        HIPCHECK(e);
+        REQUIRE(ptr, "no device address for the static scratch array on device %d", dev);
+        g_scratch_dev[dev] = static_cast<double *>(ptr);
+    }
+    return g_scratch_dev[dev];
+}
+
+// doubles of reduction partials one step of the context writes: the
+// Gram-Schmidt products (up to restart + 1 per column block), the
+// convergence measures and the Newton update
+static size_t step_partials(const fim_ctx *c) {
+    const size_t vb = (size_t)vec_blocks(c->nvec);
+    const size_t cb = (size_t)conv_blocks(c->n), ub = (size_t)update_blocks(c->n);
+    return std::max({(size_t)(c->m + 1) * vb, (size_t)(3 * c->nb + 1) * cb, 3 * ub, vb});
+}
+
+// fim_step with the context's partials and scalar slots replaced by the
+// static array, eager launches (no graph executable is instantiated) and no
+// profiling events; everything else is the context's, allocated at create
+static int step_noalloc_impl(fim_ctx *c, double dt, fim_step_report *rep) {
+    const size_t need = step_partials(c);
+    REQUIRE(need <= kNoAllocPartials,
+            "fim_step_noalloc: the step needs %zu doubles of reduction scratch, the static "
+            "array holds %zu (restart %d on %ld vector entries; restart <= 31 always fits)",
+            need, kNoAllocPartials, c->m, c->nvec);
+    double *base = scratch_on(c->dev);
+    struct Swap {
+        fim_ctx *c;
+        double *partials, *scal;
+        int graphs, profile;
+        ~Swap() {
+            c->partials = partials;
+            c->scal = scal;
+            c->opt.graphs = graphs;
+            c->opt.profile = profile;
+        }
+    } keep{c, c->partials, c->scal, c->opt.graphs, c->opt.profile};
+    c->partials = base;
+    c->scal = base + kNoAllocPartials;
+    c->opt.graphs = 0;
+    c->opt.profile = 0;
+    // the scalar slots keep the last call's values (perhaps another
+    // context's): clear them with a kernel (no memset node)
+    launch_scale_copy(c->s, S_COUNT, nullptr, 0.0, c->scal);
+    return step_impl(c, dt, rep);
+}
+
+// ---------------------------------------------------------------------------
 // C ABI
 
 extern "C" {
@@ -1903,6 +1979,13 @@ int fim_step(fim_ctx *c, double dt_days, fim_step_report *rep) {
     return guarded([&] {
         REQUIRE(c, "context is NULL");
         return step_impl(c, dt_days, rep);
+    });
+}
+
+int fim_step_noalloc(fim_ctx *c, double dt_days, fim_step_report *rep) {
+    return guarded([&] {
+        REQUIRE(c, "context is NULL");
+        return step_noalloc_impl(c, dt_days, rep);
     });
 }
 

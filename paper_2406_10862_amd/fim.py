@@ -88,7 +88,7 @@ EXPORTS = ["fim_create", "fim_destroy", "fim_last_error", "fim_sizes", "fim_set_
            "fim_set_state", "fim_set_state_dev", "fim_get_state", "fim_step",
            "fim_get_well_rates", "fim_static", "fim_set_iterate", "fim_props",
            "fim_assemble", "fim_precond_apply", "fim_linear_solve", "fim_bsr_spmv",
-           "fim_ensemble_run", "fim_adjoint_gradient"]
+           "fim_ensemble_run", "fim_adjoint_gradient", "fim_step_noalloc"]
 
 _LIB = None
 
@@ -127,6 +127,7 @@ def lib():
     L.fim_set_state_dev.argtypes = [vp, vp, vp, vp, vp, f64p]
     L.fim_get_state.argtypes = [vp, f64p, f64p, f64p, i8p, f64p]
     L.fim_step.argtypes = [vp, C.c_double, C.POINTER(FimStepReport)]
+    L.fim_step_noalloc.argtypes = [vp, C.c_double, C.POINTER(FimStepReport)]
     L.fim_get_well_rates.argtypes = [vp, f64p, f64p]
     L.fim_static.argtypes = [vp] + [f64p] * 7
     L.fim_props.argtypes = [vp, f64p]
@@ -349,6 +350,13 @@ class Fim:
     def fim_step(self, dt):
         rep = FimStepReport()
         rc = _check(lib().fim_step(self.h, float(dt), C.byref(rep)), "fim_step")
+        return rc, rep
+
+    def fim_step_noalloc(self, dt):
+        """fim_step without device allocation (static reduction scratch,
+        eager launches)."""
+        rep = FimStepReport()
+        rc = _check(lib().fim_step_noalloc(self.h, float(dt), C.byref(rep)), "fim_step_noalloc")
         return rc, rep
 
     def fim_get_well_rates(self):
