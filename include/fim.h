@@ -260,8 +260,13 @@ int fim_step_noalloc(fim_ctx *ctx, double dt_days, fim_step_report *rep);
  *       the well at the end of step s (stb/d); q_obs entries of other wells
  *       are ignored (q_obs may be NULL without wells).
  * From the current state, runs the nsteps steps of dt[nsteps] (days) as
- * fim_step does, keeping the state after every accepted sub-step on the
- * device, then the backward sweep over the sub-steps, each a transposed
+ * fim_step does, then the backward sweep over the accepted sub-steps.  The
+ * sweep needs the state after every sub-step: checkpoint_every = 0 keeps
+ * all of them on the device during the forward run; checkpoint_every = k
+ * >= 1 keeps the state at the start of every k-th schedule step only and
+ * recomputes each segment of k steps from its checkpoint before sweeping
+ * back through it (replaying the recorded sub-steps, so the gradient is bit
+ * for bit the same for every k).  Each sub-step of the sweep is a transposed
  * Jacobian solve (FP64 FGMRES to a relative residual of 1e-12, with CPR for
  * J^T: the pressure component restricted, the transposed pressure operator
  * by the aggregation AMG, prolongation by the quasi-IMPES weights, then
@@ -275,10 +280,23 @@ typedef struct {
     double objective;                    /* J */
     double adjoint_relres;               /* largest final relative residual of the adjoint solves */
     double t_forward_ms, t_adjoint_ms;   /* host wall time of the forward run and the sweep */
+    double t_recompute_ms;               /* part of t_adjoint_ms spent recomputing segments */
+    int32_t stored_states, pad;          /* most state copies held on the device at once */
 } fim_adjoint_report;
 
 int fim_adjoint_gradient(fim_ctx *ctx, int32_t nsteps, const double *dt, const double *q_obs,
-                         double *grad, fim_adjoint_report *rep);
+                         int32_t checkpoint_every, double *grad, fim_adjoint_report *rep);
+
+/* New permeabilities kx, ky, kz [ncells] (mD) for the context (the ROCK
+ * input of Sec. 3.2.3): the transmissibilities and the Peaceman well
+ * indices are computed again from them (explicit well indices stay); the
+ * state is kept.  fim_set_perm takes host arrays and checks k >= 0;
+ * fim_set_perm_dev takes float64 device arrays on the context's device, read
+ * in order after the work queued on the stream given to fim_create, and
+ * checks nothing.  The caller keeps ownership. */
+int fim_set_perm(fim_ctx *ctx, const double *kx, const double *ky, const double *kz);
+int fim_set_perm_dev(fim_ctx *ctx, const double *kx_dev, const double *ky_dev,
+                     const double *kz_dev);
 
 /* An ensemble of independent reservoirs (for instance realisations of one
  * field): advances members[0..count) by nsteps time steps each.  Step s of

@@ -173,7 +173,10 @@ struct fim_ctx {
         double *P, *Sw, *X, *pbhp;
         int8_t *flag;
     };
-    std::vector<Ckpt> ckpt;
+    std::vector<Ckpt> ckpt;                         // sub-step states of the backward sweep
+    std::vector<Ckpt> seg;                          // segment-start states (checkpointing)
+    std::vector<double> wi_explicit;                // per sorted perforation: explicit WI or 0
+    double top = 0.0;
 
     Wells wells() const {
         Wells W;
@@ -625,6 +628,8 @@ static int create_impl(const fim_grid *grid, const fim_rock *rock, const fim_flu
         c->pcell = c->upload(sorted_cells.data(), c->nperf);
         c->pwell = c->upload(pwell_h.data(), c->nperf);
         c->wi = c->upload(wi_sorted.data(), c->nperf);
+        c->wi_explicit = wi_sorted;
+        c->top = grid->top;
         c->wi_dk = c->upload(wi_dk_h.data(), c->nperf);
         c->wrw = c->upload(rw.data(), nwells);
         c->wskin = c->upload(skin.data(), nwells);
@@ -1536,15 +1541,16 @@ static int step_impl(fim_ctx *c, double dt, fim_step_report *rep,
 // ---------------------------------------------------------------------------
 // discrete adjoint of the backward-Euler system
 
-// copy the current state to checkpoint m (allocated on first use), or back
-static void put_ckpt(fim_ctx *c, size_t m) {
+// copy the current state to slot m of a checkpoint set (allocated on first
+// use), or back
+static void put_ckpt(fim_ctx *c, std::vector<fim_ctx::Ckpt> &set, size_t m) {
     const size_t n = c->n;
-    while (c->ckpt.size() <= m) {
+    while (set.size() <= m) {
         fim_ctx::Ckpt k{c->alloc<double>(n), c->alloc<double>(n), c->alloc<double>(n),
                         c->alloc<double>(std::max(c->nw, 1)), c->alloc<int8_t>(n)};
-        c->ckpt.push_back(k);
+        set.push_back(k);
     }
-    const fim_ctx::Ckpt &k = c->ckpt[m];
+    const fim_ctx::Ckpt &k = set[m];
     HIPCHECK(hipMemcpyAsync(k.P, c->P, n * 8, hipMemcpyDeviceToDevice, c->s));
     HIPCHECK(hipMemcpyAsync(k.Sw, c->Sw, n * 8, hipMemcpyDeviceToDevice, c->s));
     HIPCHECK(hipMemcpyAsync(k.X, c->X, n * 8, hipMemcpyDeviceToDevice, c->s));
@@ -1552,9 +1558,9 @@ static void put_ckpt(fim_ctx *c, size_t m) {
     if (c->nw) HIPCHECK(hipMemcpyAsync(k.pbhp, c->pbhp, c->nw * 8, hipMemcpyDeviceToDevice, c->s));
 }
 
-static void get_ckpt(fim_ctx *c, size_t m) {
+static void get_ckpt(fim_ctx *c, const std::vector<fim_ctx::Ckpt> &set, size_t m) {
     const size_t n = c->n;
-    const fim_ctx::Ckpt &k = c->ckpt[m];
+    const fim_ctx::Ckpt &k = set[m];
     HIPCHECK(hipMemcpyAsync(c->P, k.P, n * 8, hipMemcpyDeviceToDevice, c->s));
     HIPCHECK(hipMemcpyAsync(c->Sw, k.Sw, n * 8, hipMemcpyDeviceToDevice, c->s));
     HIPCHECK(hipMemcpyAsync(c->X, k.X, n * 8, hipMemcpyDeviceToDevice, c->s));
@@ -1607,20 +1613,27 @@ static void adjoint_prec_setup(fim_ctx *c) {
     c->prec_ready = true;
 }
 
-// Forward: nsteps time steps of fim_step, keeping the state after every
-// accepted sub-step m = 1..M (state 0 = the start).  Backward, m = M..1:
+// Forward: nsteps time steps of fim_step.  Backward, over the accepted
+// sub-steps m = M..1:
 //   J_m^T lam_m = (1/dt_{m+1}) (dA(x_m)/dx_m)^T lam_{m+1} - (dJ/dx_m)^T
 // (the first term absent for m = M, the second only where a schedule step
 // ends), then grad += lam_m^T dR_m/dtheta (+ dJ/dtheta at schedule ends).
+// The sweep needs every sub-step state x_m.  With every == 0 the forward run
+// keeps all of them; with every = k >= 1 it keeps only the state at the start
+// of every k-th schedule step, and the sweep recomputes each segment of k
+// steps from its checkpoint before going backward through it (the replayed
+// sub-steps are the recorded ones, so the states are bit for bit those of the
+// forward run and the gradient does not depend on k).
 // The transposed systems are solved by FGMRES in FP64 to a relative
 // residual of 1e-12, preconditioned by CPR for J^T: the transposed pressure
 // stage, then block-Jacobi ILU(0) of J^T.
 static int adjoint_impl(fim_ctx *c, int nsteps, const double *dt, const double *qobs_h,
-                        double *grad_h, fim_adjoint_report *rep) {
+                        int every, double *grad_h, fim_adjoint_report *rep) {
     using clock = std::chrono::steady_clock;
     REQUIRE(nsteps >= 1, "nsteps must be >= 1");
     REQUIRE(dt && grad_h, "dt and grad are required");
     REQUIRE(qobs_h || c->nw == 0, "q_obs is required");
+    REQUIRE(every >= 0, "checkpoint_every must be >= 0");
     if (!c->state_set) {
         set_err("state not set (call fim_set_state first)");
         throw StateError();
@@ -1630,13 +1643,24 @@ static int adjoint_impl(fim_ctx *c, int nsteps, const double *dt, const double *
     const auto t0 = clock::now();
     std::vector<double> hsub;              // accepted sub-step lengths
     std::vector<int> send(1, -1);          // schedule step that ends at sub-step m, else -1
-    put_ckpt(c, 0);
+    std::vector<int> first(nsteps + 1, 0); // state index at the start of each schedule step
+    const int nseg = every > 0 ? (nsteps + every - 1) / every : 1;
+    const size_t end_slot = (size_t)nseg;  // (every > 0) the forward end state
+    if (every == 0) put_ckpt(c, c->ckpt, 0);
     const std::function<void(double)> hook = [&](double h) {
         hsub.push_back(h);
         send.push_back(-1);
-        put_ckpt(c, hsub.size());
+        if (every == 0) put_ckpt(c, c->ckpt, hsub.size());
+    };
+    auto back_to_start = [&] {
+        if (every == 0) get_ckpt(c, c->ckpt, 0);
+        else get_ckpt(c, c->seg, 0);
+        props(c, true);
+        c->sync();
     };
     for (int st = 0; st < nsteps; ++st) {
+        first[st] = (int)hsub.size();
+        if (every > 0 && st % every == 0) put_ckpt(c, c->seg, (size_t)(st / every));
         fim_step_report sr{};
         const int status = step_impl(c, dt[st], &sr, &hook);
         r.steps += status == FIM_OK;
@@ -1644,18 +1668,18 @@ static int adjoint_impl(fim_ctx *c, int nsteps, const double *dt, const double *
         r.newton_iters += sr.newton_iters;
         r.linear_iters += sr.linear_iters;
         if (status != FIM_OK) {
-            get_ckpt(c, 0);
-            props(c, true);
-            c->sync();
+            back_to_start();
             r.substeps = (int)hsub.size();
             if (rep) *rep = r;
             return FIM_NOT_CONVERGED;
         }
         send.back() = st;
     }
+    const int M = (int)hsub.size();
+    first[nsteps] = M;
+    if (every > 0) put_ckpt(c, c->seg, end_slot);
     c->sync();
     const auto t1 = clock::now();
-    const int M = (int)hsub.size();
     r.substeps = M;
     const size_t nq = (size_t)nsteps * c->nw;
     if (nq > c->qobs_len) {
@@ -1665,83 +1689,117 @@ static int adjoint_impl(fim_ctx *c, int nsteps, const double *dt, const double *
     }
     if (nq) HIPCHECK(hipMemcpyAsync(c->qobs, qobs_h, nq * 8, hipMemcpyHostToDevice, c->s));
     HIPCHECK(hipMemsetAsync(c->grad, 0, c->n * sizeof(double), c->s));
-    // the transposed solves: FP64, CPR for J^T with the ILU(0) second stage
+    // forward configuration (segment recomputation) and adjoint configuration
+    // (the transposed solves: FP64, CPR for J^T with the ILU(0) second stage);
+    // captured Arnoldi steps belong to one of them, so a switch drops them
     const fim_options saved = c->opt;
     const bool saved_mixed = c->mixed;
-    c->opt.precond = FIM_PREC_CPR_ILU0;
-    c->mixed = false;
-    c->cpr_rw = c->e0w;
-    c->cpr_pw = c->wq;
-    c->drop_graphs();
+    auto to_forward = [&] {
+        c->opt = saved;
+        c->mixed = saved_mixed;
+        c->cpr_rw = c->cpr_pw = nullptr;
+        c->drop_graphs();
+    };
+    auto to_adjoint = [&] {
+        c->opt.precond = FIM_PREC_CPR_ILU0;
+        c->mixed = false;
+        c->cpr_rw = c->e0w;
+        c->cpr_pw = c->wq;
+        c->drop_graphs();
+    };
     std::vector<double> jw((size_t)nsteps * 2 * std::max(c->nw, 1), 0.0);
     int status = FIM_OK;
+    double t_rec = 0.0;
+    size_t held = every == 0 ? (size_t)M + 1 : end_slot + 1;
     try {
+        to_adjoint();
         build_ilu(c);
         const int max_it = std::max(c->opt.max_lin, 1000);
         double *lam_next = nullptr;
         int cur = 0;
-        for (int m = M; m >= 1; --m) {
-            get_ckpt(c, m - 1);
-            props(c, true);                         // A(x_{m-1})
-            get_ckpt(c, m);
-            props(c, false);
-            assemble(c, hsub[m - 1]);               // J_m
-            const int st = send[m];
-            const double *objp = nullptr, *objw = nullptr;
-            if (st >= 0 && c->nw) {
-                launch_adj_objective(c->s, c->nb, c->wells(), c->n, c->P, c->pbhp, c->rec,
-                                     c->wi_dk, c->qobs + (size_t)st * c->nw, c->objp, c->objw);
-                HIPCHECK(hipMemcpyAsync(jw.data() + (size_t)st * 2 * c->nw, c->objw,
-                                        2 * c->nw * 8, hipMemcpyDeviceToHost, c->s));
-                objp = c->objp;
-                objw = c->objw;
+        for (int g = nseg - 1; g >= 0 && status == FIM_OK; --g) {
+            const int s0 = every > 0 ? g * every : 0;
+            const int s1 = every > 0 ? std::min(nsteps, s0 + every) : nsteps;
+            const int m0 = first[s0], m1 = first[s1];
+            if (every > 0) {
+                // recompute the segment's sub-step states from its checkpoint
+                const auto tr = clock::now();
+                to_forward();
+                get_ckpt(c, c->seg, (size_t)g);
+                put_ckpt(c, c->ckpt, 0);
+                for (int m = m0 + 1; m <= m1; ++m) {
+                    NewtonStats ns;
+                    if (!newton(c, hsub[m - 1], ns)) {
+                        set_err("recomputing sub-step %d from the checkpoint of step %d failed", m,
+                                s0);
+                        throw StateError();
+                    }
+                    put_ckpt(c, c->ckpt, (size_t)(m - m0));
+                }
+                c->sync();
+                held = std::max(held, end_slot + 1 + (size_t)(m1 - m0) + 1);
+                to_adjoint();
+                t_rec += std::chrono::duration<double, std::milli>(clock::now() - tr).count();
             }
-            launch_adj_rhs(c->s, c->nb, c->wells(), c->n, c->rec, lam_next,
-                           m < M ? 1.0 / hsub[m] : 0.0, objp, objw, c->arhs);
-            launch_bsr_transpose(c->s, c->nb, c->nnzb, c->tperm, c->val, c->valT);
-            std::swap(c->val, c->valT);
-            double *lam = c->lam[cur];
-            int li = 0;
-            double rr = 0.0;
-            int gs = 0;
-            try {
-                adjoint_prec_setup(c);
-                gs = gmres_t<double>(c, c->arhs, lam, max_it, 1e-12, false, &li, &rr, nullptr);
-            } catch (...) {
+            auto slot = [&](int m) { return (size_t)(every > 0 ? m - m0 : m); };
+            for (int m = m1; m > m0; --m) {
+                get_ckpt(c, c->ckpt, slot(m - 1));
+                props(c, true);                         // A(x_{m-1})
+                get_ckpt(c, c->ckpt, slot(m));
+                props(c, false);
+                assemble(c, hsub[m - 1]);               // J_m
+                const int st = send[m];
+                const double *objp = nullptr, *objw = nullptr;
+                if (st >= 0 && c->nw) {
+                    launch_adj_objective(c->s, c->nb, c->wells(), c->n, c->P, c->pbhp, c->rec,
+                                         c->wi_dk, c->qobs + (size_t)st * c->nw, c->objp, c->objw);
+                    HIPCHECK(hipMemcpyAsync(jw.data() + (size_t)st * 2 * c->nw, c->objw,
+                                            2 * c->nw * 8, hipMemcpyDeviceToHost, c->s));
+                    objp = c->objp;
+                    objw = c->objw;
+                }
+                launch_adj_rhs(c->s, c->nb, c->wells(), c->n, c->rec, lam_next,
+                               m < M ? 1.0 / hsub[m] : 0.0, objp, objw, c->arhs);
+                launch_bsr_transpose(c->s, c->nb, c->nnzb, c->tperm, c->val, c->valT);
                 std::swap(c->val, c->valT);
-                throw;
+                double *lam = c->lam[cur];
+                int li = 0;
+                double rr = 0.0;
+                int gs = 0;
+                try {
+                    adjoint_prec_setup(c);
+                    gs = gmres_t<double>(c, c->arhs, lam, max_it, 1e-12, false, &li, &rr, nullptr);
+                } catch (...) {
+                    std::swap(c->val, c->valT);
+                    throw;
+                }
+                std::swap(c->val, c->valT);
+                r.adjoint_iters += li;
+                r.adjoint_relres = std::max(r.adjoint_relres, rr);
+                if (gs != 0) {
+                    set_err("adjoint solve of sub-step %d did not converge (relative residual %.3g)",
+                            m, rr);
+                    status = FIM_NOT_CONVERGED;
+                    break;
+                }
+                launch_adj_grad(c->s, c->nb, c->g, c->wells(), c->depth, c->tx, c->ty, c->tz,
+                                c->kx, c->ky, c->kz, c->dx, c->dy, c->dz, c->P, c->pbhp, c->rec,
+                                c->wi_dk, lam, objp, c->grad);
+                lam_next = lam;
+                cur ^= 1;
             }
-            std::swap(c->val, c->valT);
-            r.adjoint_iters += li;
-            r.adjoint_relres = std::max(r.adjoint_relres, rr);
-            if (gs != 0) {
-                set_err("adjoint solve of sub-step %d did not converge (relative residual %.3g)",
-                        m, rr);
-                status = FIM_NOT_CONVERGED;
-                break;
-            }
-            launch_adj_grad(c->s, c->nb, c->g, c->wells(), c->depth, c->tx, c->ty, c->tz, c->kx,
-                            c->ky, c->kz, c->dx, c->dy, c->dz, c->P, c->pbhp, c->rec, c->wi_dk,
-                            lam, objp, c->grad);
-            lam_next = lam;
-            cur ^= 1;
         }
         if (status == FIM_OK)
             HIPCHECK(hipMemcpyAsync(grad_h, c->grad, c->n * 8, hipMemcpyDeviceToHost, c->s));
         c->sync();
     } catch (...) {
-        c->opt = saved;
-        c->mixed = saved_mixed;
-        c->cpr_rw = c->cpr_pw = nullptr;
-        c->drop_graphs();
+        to_forward();
         throw;
     }
-    c->opt = saved;
-    c->mixed = saved_mixed;
-    c->cpr_rw = c->cpr_pw = nullptr;
-    c->drop_graphs();
+    to_forward();
     // leave the context at the end of the forward run
-    get_ckpt(c, M);
+    if (every == 0) get_ckpt(c, c->ckpt, (size_t)M);
+    else get_ckpt(c, c->seg, end_slot);
     props(c, true);
     c->jac_ready = false;
     c->prec_ready = false;
@@ -1750,8 +1808,36 @@ static int adjoint_impl(fim_ctx *c, int nsteps, const double *dt, const double *
         for (int wl = 0; wl < c->nw; ++wl) r.objective += jw[(size_t)st * 2 * c->nw + 2 * wl + 1];
     r.t_forward_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
     r.t_adjoint_ms = std::chrono::duration<double, std::milli>(clock::now() - t1).count();
+    r.t_recompute_ms = t_rec;
+    r.stored_states = (int)held;
     if (rep) *rep = r;
     return status;
+}
+
+// ---------------------------------------------------------------------------
+// permeability (the ROCK input of Sec. 3.2.3): new kx, ky, kz, then the
+// static precompute that depends on them again (transmissibilities and the
+// Peaceman well indices; explicit well indices stay)
+
+static int set_perm_impl(fim_ctx *c, const double *kx, const double *ky, const double *kz,
+                         bool dev) {
+    const size_t b = (size_t)c->n * 8;
+    const hipMemcpyKind kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    HIPCHECK(hipMemcpyAsync(c->kx, kx, b, kind, c->s));
+    HIPCHECK(hipMemcpyAsync(c->ky, ky, b, kind, c->s));
+    HIPCHECK(hipMemcpyAsync(c->kz, kz, b, kind, c->s));
+    if (c->nperf)
+        HIPCHECK(hipMemcpyAsync(c->wi, c->wi_explicit.data(), (size_t)c->nperf * 8,
+                                hipMemcpyHostToDevice, c->s));
+    launch_static(c->s, c->g, c->dx, c->dy, c->dz, c->top, c->kx, c->ky, c->kz, c->poro, c->vol,
+                  c->depth, c->pvref, c->tx, c->ty, c->tz);
+    launch_peaceman(c->s, c->g, c->nperf, c->pcell, c->pwell, c->dx, c->dy, c->dz, c->kx, c->ky,
+                    c->wrw, c->wskin, c->wi);
+    HIPCHECK(hipGetLastError());
+    c->sync();                 // the explicit indices are read from host memory
+    c->jac_ready = false;
+    c->prec_ready = false;
+    return FIM_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -1990,10 +2076,30 @@ int fim_step_noalloc(fim_ctx *c, double dt_days, fim_step_report *rep) {
 }
 
 int fim_adjoint_gradient(fim_ctx *c, int32_t nsteps, const double *dt, const double *q_obs,
-                         double *grad, fim_adjoint_report *rep) {
+                         int32_t checkpoint_every, double *grad, fim_adjoint_report *rep) {
     return guarded([&] {
         REQUIRE(c, "context is NULL");
-        return adjoint_impl(c, nsteps, dt, q_obs, grad, rep);
+        return adjoint_impl(c, nsteps, dt, q_obs, checkpoint_every, grad, rep);
+    });
+}
+
+int fim_set_perm(fim_ctx *c, const double *kx, const double *ky, const double *kz) {
+    return guarded([&] {
+        REQUIRE(c, "context is NULL");
+        REQUIRE(kx && ky && kz, "kx, ky and kz are required");
+        for (int q = 0; q < c->n; ++q)
+            REQUIRE(kx[q] >= 0 && ky[q] >= 0 && kz[q] >= 0, "permeability must be >= 0 (cell %d)", q);
+        return set_perm_impl(c, kx, ky, kz, false);
+    });
+}
+
+int fim_set_perm_dev(fim_ctx *c, const double *kx, const double *ky, const double *kz) {
+    return guarded([&] {
+        REQUIRE(c, "context is NULL");
+        REQUIRE(kx && ky && kz, "kx, ky and kz are required");
+        HIPCHECK(hipEventRecord(c->ev_user, c->user_s));
+        HIPCHECK(hipStreamWaitEvent(c->s, c->ev_user, 0));
+        return set_perm_impl(c, kx, ky, kz, true);
     });
 }
 

@@ -81,14 +81,16 @@ class FimAdjointReport(C.Structure):
                 ("newton_iters", C.c_int32), ("linear_iters", C.c_int32),
                 ("adjoint_iters", C.c_int32), ("objective", C.c_double),
                 ("adjoint_relres", C.c_double), ("t_forward_ms", C.c_double),
-                ("t_adjoint_ms", C.c_double)]
+                ("t_adjoint_ms", C.c_double), ("t_recompute_ms", C.c_double),
+                ("stored_states", C.c_int32), ("pad", C.c_int32)]
 
 
 EXPORTS = ["fim_create", "fim_destroy", "fim_last_error", "fim_sizes", "fim_set_options",
            "fim_set_state", "fim_set_state_dev", "fim_get_state", "fim_step",
            "fim_get_well_rates", "fim_static", "fim_set_iterate", "fim_props",
            "fim_assemble", "fim_precond_apply", "fim_linear_solve", "fim_bsr_spmv",
-           "fim_ensemble_run", "fim_adjoint_gradient", "fim_step_noalloc"]
+           "fim_ensemble_run", "fim_adjoint_gradient", "fim_step_noalloc", "fim_set_perm",
+           "fim_set_perm_dev"]
 
 _LIB = None
 
@@ -135,8 +137,10 @@ def lib():
     L.fim_precond_apply.argtypes = [vp, f64p, f64p]
     L.fim_linear_solve.argtypes = [vp, f64p, f64p, i32p, f64p]
     L.fim_bsr_spmv.argtypes = [C.c_int32, C.c_int32, vp, vp, vp, vp, vp, vp]
-    L.fim_adjoint_gradient.argtypes = [vp, C.c_int32, f64p, f64p, f64p,
+    L.fim_adjoint_gradient.argtypes = [vp, C.c_int32, f64p, f64p, C.c_int32, f64p,
                                        C.POINTER(FimAdjointReport)]
+    L.fim_set_perm.argtypes = [vp, f64p, f64p, f64p]
+    L.fim_set_perm_dev.argtypes = [vp, vp, vp, vp]
     L.fim_ensemble_run.argtypes = [C.c_int32, C.POINTER(vp), C.c_int32, f64p, C.c_int32,
                                    C.POINTER(FimStepReport), i32p]
     for f in EXPORTS:
@@ -335,17 +339,36 @@ class Fim:
                                    _p(flag, i8p), _p(bhp, f64p)), "fim_get_state")
         return dict(P=P, Sw=Sw, X=X, flag=flag, pbhp=bhp[: self.nw])
 
-    def fim_adjoint_gradient(self, dt, q_obs):
+    def fim_adjoint_gradient(self, dt, q_obs, checkpoint_every=0):
         """dJ/d(ln k) of every cell for J = sum_s sum_producers (q_o - q_obs[s, w])^2
-        over the steps dt (fim_adjoint_gradient).  Returns (rc, grad, report)."""
+        over the steps dt (fim_adjoint_gradient); checkpoint_every = k >= 1
+        recomputes segments of k steps from checkpoints, 0 keeps every
+        sub-step state.  Returns (rc, grad, report)."""
         dt = _f64(np.atleast_1d(dt))
         qo = _f64(np.asarray(q_obs, dtype=np.float64).reshape(len(dt), self.nw)) if self.nw else None
         grad = np.zeros(self.n)
         rep = FimAdjointReport()
         rc = _check(lib().fim_adjoint_gradient(self.h, len(dt), _p(dt, f64p), _p(qo, f64p),
-                                               _p(grad, f64p), C.byref(rep)),
+                                               int(checkpoint_every), _p(grad, f64p),
+                                               C.byref(rep)),
                     "fim_adjoint_gradient")
         return rc, grad, rep
+
+    def fim_set_perm(self, kx, ky, kz):
+        kx, ky, kz = _f64(kx), _f64(ky), _f64(kz)
+        for name, a in (("kx", kx), ("ky", ky), ("kz", kz)):
+            if a.size != self.n:
+                raise FimError(f"{name}: {a.size} values, {self.n} cells")
+        _check(lib().fim_set_perm(self.h, _p(kx, f64p), _p(ky, f64p), _p(kz, f64p)),
+               "fim_set_perm")
+
+    def fim_set_perm_dev(self, kx, ky, kz):
+        """Contiguous float64 torch GPU tensors of ncells permeabilities (mD)."""
+        import torch
+
+        ptr = [dev_ptr(t, torch.float64, self.n, name, self.device)
+               for t, name in ((kx, "kx"), (ky, "ky"), (kz, "kz"))]
+        _check(lib().fim_set_perm_dev(self.h, *ptr), "fim_set_perm_dev")
 
     def fim_step(self, dt):
         rep = FimStepReport()
