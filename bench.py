@@ -240,7 +240,7 @@ def summarize_stats(stats_csv, out, title, command, note):
 
 def ensemble_bench(args):
     """Ensemble cell-steps/s: the 256 realisations of the c4 recipe advanced
-    together by fim_ensemble_run, every realisation on its own stream."""
+    together by fim_ensemble_run, one launch per kernel for all of them."""
     import numpy as np
     import torch
 
@@ -252,7 +252,7 @@ def ensemble_bench(args):
     dims = rv.config_c4_members(args.members)
     res = [rv.config_c4_member(r, d) for r, d in enumerate(dims)]
     opts = tolerances(args.tol)
-    members = [fim.Fim(r, options=opts, profile=True) for r in res]
+    members = [fim.Fim(r, options=opts) for r in res]
     for m in members:
         m.set_initial_state()
     cells = np.array([m.n for m in members], dtype=np.int64)
@@ -262,24 +262,19 @@ def ensemble_bench(args):
     sched = np.array([[r.schedule[s % len(r.schedule)] for s in range(max(nsteps, args.warmup))]
                       for r in res])
     if args.warmup:
-        rc, status, _ = fim.fim_ensemble_run(members, sched[:, :args.warmup], args.workers)
+        rc, status, _ = fim.fim_ensemble_run(members, sched[:, :args.warmup])
         log(f"warm-up: rc={rc}")
         for m in members:
             m.set_initial_state()
     torch.cuda.synchronize()
     t_start = time.perf_counter()
-    rc, status, reps = fim.fim_ensemble_run(members, sched[:, :nsteps], args.workers)
+    rc, status, reps = fim.fim_ensemble_run(members, sched[:, :nsteps])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
     done = (status == fim.FIM_OK).sum(axis=1)
     newton = sum(r.newton_iters for row in reps for r in row)
     linear = sum(r.linear_iters for row in reps for r in row)
     cuts = sum(r.cuts for row in reps for r in row)
-    spmv_bytes_total = sum(spmv_bytes(m.nnzb, m.nrows, m.nb) * sum(r.spmv_calls for r in reps[k])
-                           for k, m in enumerate(members))
-    spmv_s = sum(r.spmv_ms for row in reps for r in row) * 1e-3
-    calls = sum(r.spmv_calls for row in reps for r in row)
-    achieved = spmv_bytes_total / spmv_s / 1e9 if spmv_s > 0 else None
     log(f"ensemble: rc={rc} member-steps ok {int(done.sum())}/{len(members) * nsteps} "
         f"newton={newton} linear={linear} cuts={cuts} wall={wall:.2f}s")
     out = {
@@ -299,22 +294,14 @@ def ensemble_bench(args):
             "workload": f"ensemble of {len(members)} two-phase dead-oil realisations, "
                         f"{int(cells.sum())} cells in all, seeded log-normal perm (sigma 1), "
                         "rate injector and BHP producer at opposite corners, dt 15 days",
-            "members": len(members), "cells": int(cells.sum()), "workers": args.workers,
+            "members": len(members), "cells": int(cells.sum()),
+            "execution": "one launch per kernel for all members (batched), lockstep FGMRES "
+                         "restart cycles, Newton rounds over the members with work",
             "tolerances": args.tol, "newton_iters": newton, "linear_iters": linear,
             "cuts": cuts, "member_steps_ok": int(done.sum()),
             "newton_iters_per_s": newton / wall,
         },
-        "roofline": {
-            "bound": "hbm",
-            "kernel": "k_spmv<2,8> (BSR SpMV inside GMRES, all members)",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS if achieved else None,
-            "traffic": None,
-            "launches": calls,
-            "avg_launch_us": spmv_s * 1e6 / calls if calls else None,
-        },
+        "roofline": None,
     }
     print(json.dumps(out), flush=True)
 
@@ -514,8 +501,6 @@ def main():
                     help="c5: also check the gradient by central differences on this many "
                          "cells (drawn with seed 5, step --fd-h in ln k; two forward runs each)")
     ap.add_argument("--members", type=int, default=256, help="c4: realisations")
-    ap.add_argument("--workers", type=int, default=16,
-                    help="c4: realisations in flight at a time (host threads and streams)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cycle", type=int, default=0,
                     help="AMG cycle: 0 V at the finest level and W below, 1 V, 2 W, >=16 W on "

@@ -299,25 +299,31 @@ int fim_set_perm_dev(fim_ctx *ctx, const double *kx_dev, const double *ky_dev,
                      const double *kz_dev);
 
 /* An ensemble of independent reservoirs (for instance realisations of one
- * field): advances members[0..count) by nsteps time steps each.  Step s of
- * member k is exactly fim_step(members[k], dt[k*nsteps + s],
- * &reports[k*nsteps + s]) (the time step of Sec. 3.3.2), so every member
- * computes bitwise what it computes when stepped alone.  Running many
- * members at once is this library's addition, not a method of the paper:
- * up to `workers` members are in flight together (workers <= 0: 16), each
- * driven by its own host thread on its own stream, taken in order of
- * decreasing cell count.
- *   members: distinct contexts (a context is never stepped by two threads);
+ * field) advanced together: members[0..count) by nsteps time steps each,
+ * step s of member k with dt[k*nsteps + s] days.  Every member takes
+ * exactly the steps fim_step takes (the time step of Sec. 3.3.2 with the
+ * Newton iteration of Sec. 3.2.5 and the CPR-FGMRES of Sec. 5.1), with its
+ * own tolerances, cuts and iteration counts, and computes bit for bit what
+ * fim_step computes for it.  Running them together is this library's
+ * addition, not a method of the paper: every kernel is one launch for all
+ * the members (a member's blocks run on the member's own buffers; flags in
+ * device memory select the members that take part), the Newton iterations
+ * advance in rounds over the members that have work, and the members that
+ * need a linear solve share one FGMRES whose restart cycles run in lockstep
+ * (a member stops inside a cycle on its own test).
+ * Members must use CPR with block-Jacobi ILU(0) (FIM_PREC_CPR_ILU0) in
+ * FP64, one block size, device and GMRES restart, ILU(0) boxes of one
+ * workgroup size and coarsest AMG levels of at most 96 entries (FIM_E_ARG
+ * otherwise); contexts are distinct and their states set.
  *   dt[count*nsteps] (days), status[count*nsteps] (required),
- *   reports[count*nsteps] (may be NULL).
+ *   reports[count*nsteps] (may be NULL; phase times and SpMV counts are 0).
  * A member stops at its first step that does not return FIM_OK; its later
  * entries get FIM_SKIPPED.  Returns FIM_OK when every step returned FIM_OK,
  * FIM_NOT_CONVERGED when a member stopped on that status, or a negative
- * code some member's step returned (fim_last_error() on the calling
- * thread gives that step's message).  The calling thread waits for every
- * member. */
+ * code.  The calling thread waits for the whole run; afterwards every
+ * member's state is its end state, as after its own fim_step calls. */
 int fim_ensemble_run(int32_t count, fim_ctx *const *members, int32_t nsteps, const double *dt,
-                     int32_t workers, fim_step_report *reports, int32_t *status);
+                     fim_step_report *reports, int32_t *status);
 
 /* Surface rates q[w*3 + i] (component i = water, oil, gas; production
  * positive, injection negative) and bottom-hole pressures at the state. */

@@ -159,15 +159,15 @@ __device__ inline double pcoef(const double *__restrict__ val, int q, const doub
 // cells and wells) into ap[q][NB], the only part of A that the second CPR
 // stage multiplies.
 template <int NB, class LT>
-__global__ __launch_bounds__(kBlock) void k_amg_extract(AmgLevel L, Grid g, Wells wl, Sys sys,
-                                                        double *__restrict__ wq,
-                                                        LT *__restrict__ ap) {
+__device__ __forceinline__ void amg_extract_body(int bid, int nblk, const AmgLevel &L,
+                                                 const Grid &g, const Wells &wl, const Sys &sys,
+                                                 double *__restrict__ wq, LT *__restrict__ ap) {
     // a group of 8 lanes per row, lane lg on the row's blocks lg, lg + 8, ...
     // (adjacent lanes read adjacent blocks); every lane forms the row's
     // weights from the diagonal block
     constexpr int G = 8;
     const int lg = threadIdx.x & (G - 1);
-    const int t = (int)(((long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) / G);
+    const int t = (int)(((long)xcd_block(bid, nblk) * blockDim.x + threadIdx.x) / G);
     const int n = g.n;
     const int stride = 2 * L.half;
     if (t >= n + L.nw) return;
@@ -204,6 +204,13 @@ __global__ __launch_bounds__(kBlock) void k_amg_extract(AmgLevel L, Grid g, Well
         for (int p = 0; p < np; ++p) L.awc[p0 + p] = sys.val[(size_t)(base + p) * NB * NB];
         L.aww[wi] = sys.val[(size_t)(base + np) * NB * NB];
     }
+}
+
+template <int NB, class LT>
+__global__ __launch_bounds__(kBlock) void k_amg_extract(AmgLevel L, Grid g, Wells wl, Sys sys,
+                                                        double *__restrict__ wq,
+                                                        LT *__restrict__ ap) {
+    amg_extract_body<NB, LT>(blockIdx.x, gridDim.x, L, g, wl, sys, wq, ap);
 }
 
 // CPR for a transposed Jacobian (the adjoint systems).  With the forward
@@ -280,10 +287,10 @@ __global__ __launch_bounds__(kBlock) void k_cprT_extract(AmgLevel L, Grid g, Wel
 // Galerkin coarsening with piecewise-constant aggregates: couplings inside an
 // aggregate move to the coarse diagonal, couplings across an aggregate face
 // add up on the coarse stencil slot of that face.
-__global__ __launch_bounds__(kBlock) void k_amg_coarsen(AmgLevel F, AmgLevel C,
-                                                        const int *__restrict__ cfs_ptr,
-                                                        const int *__restrict__ cfs_idx) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void amg_coarsen_body(int bid, const AmgLevel &F, const AmgLevel &C,
+                                                 const int *__restrict__ cfs_ptr,
+                                                 const int *__restrict__ cfs_idx) {
+    const int t = bid * blockDim.x + threadIdx.x;
     const int ncs = 2 * C.half;
     const int fstride = 2 * F.half;
     if (t < ncs) {
@@ -325,10 +332,15 @@ __global__ __launch_bounds__(kBlock) void k_amg_coarsen(AmgLevel F, AmgLevel C,
     }
 }
 
+__global__ __launch_bounds__(kBlock) void k_amg_coarsen(AmgLevel F, AmgLevel C,
+                                                        const int *__restrict__ cfs_ptr,
+                                                        const int *__restrict__ cfs_idx) {
+    amg_coarsen_body(blockIdx.x, F, C, cfs_ptr, cfs_idx);
+}
+
 // dense matrix of the coarsest level: rows/cols are split indices, then wells
-__global__ void k_amg_dense(AmgLevel L, double *__restrict__ M) {
+__device__ __forceinline__ void amg_dense_row(const AmgLevel &L, double *__restrict__ M, int t) {
     const int n = 2 * L.half + L.nw;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
     double *row = M + (size_t)t * n;
     for (int c = 0; c < n; ++c) row[c] = 0.0;
@@ -354,6 +366,10 @@ __global__ void k_amg_dense(AmgLevel L, double *__restrict__ M) {
         row[t] = L.aww[w];
         for (int q = L.sps[w]; q < L.sps[w + 1]; ++q) row[L.scell[q]] += L.awc[q];
     }
+}
+
+__global__ void k_amg_dense(AmgLevel L, double *__restrict__ M) {
+    amg_dense_row(L, M, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // Gauss-Jordan inverse with partial pivoting by one workgroup; A is
@@ -444,9 +460,9 @@ __global__ __launch_bounds__(1024) void k_dense_invert(int n, double *__restrict
 constexpr int kDenseLds = 96;
 size_t dense_lds_bytes(int n) { return ((size_t)2 * n * n + n) * sizeof(double); }
 
-__global__ __launch_bounds__(1024) void k_dense_invert_lds(int n, const double *__restrict__ Ag,
-                                                           double *__restrict__ Ainv, int *bad) {
-    extern __shared__ double sm[];
+__device__ __forceinline__ void dense_invert_lds_body(int n, const double *__restrict__ Ag,
+                                                      double *__restrict__ Ainv, int *bad,
+                                                      double *sm) {
     double *A = sm, *X = sm + (size_t)n * n, *colk = sm + (size_t)2 * n * n;
     __shared__ int piv;
     const int tid = threadIdx.x, nt = blockDim.x;
@@ -510,6 +526,12 @@ __global__ __launch_bounds__(1024) void k_dense_invert_lds(int n, const double *
         __syncthreads();
     }
     for (int e = tid; e < n * n; e += nt) Ainv[(size_t)(e % n) * n + e / n] = X[e];   // transposed
+}
+
+__global__ __launch_bounds__(1024) void k_dense_invert_lds(int n, const double *__restrict__ Ag,
+                                                           double *__restrict__ Ainv, int *bad) {
+    extern __shared__ double sm[];
+    dense_invert_lds_body(n, Ag, Ainv, bad, sm);
 }
 
 // (Minv b)[row] by one thread, the columns in order; the inverse is stored
@@ -986,13 +1008,13 @@ __global__ __launch_bounds__(kSubThreads) void k_amg_subcycle(AmgSub P) {
 // given, in v's precision) and the pressure right-hand side b_p = W^T v of
 // the first level.
 template <int NB, class WT, class VT>
-__global__ __launch_bounds__(kBlock) void k_cpr_restrict(int n, int nw, AmgLevel L,
-                                                         const int *__restrict__ split0,
-                                                         const WT *__restrict__ w,
-                                                         const double *__restrict__ hptr,
-                                                         VT *__restrict__ v,
-                                                         const double *__restrict__ wq) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void cpr_restrict_body(int bid, int n, int nw, const AmgLevel &L,
+                                                  const int *__restrict__ split0,
+                                                  const WT *__restrict__ w,
+                                                  const double *__restrict__ hptr,
+                                                  VT *__restrict__ v,
+                                                  const double *__restrict__ wq) {
+    const int r = bid * blockDim.x + threadIdx.x;
     if (r >= n + nw) return;
     // the weights and the split index are loaded with w (a well row loads
     // those of the last cell and does not use them: no branch before the
@@ -1025,6 +1047,16 @@ __global__ __launch_bounds__(kBlock) void k_cpr_restrict(int n, int nw, AmgLevel
     } else {
         L.b[2 * L.half + (r - n)] = a[0];
     }
+}
+
+template <int NB, class WT, class VT>
+__global__ __launch_bounds__(kBlock) void k_cpr_restrict(int n, int nw, AmgLevel L,
+                                                         const int *__restrict__ split0,
+                                                         const WT *__restrict__ w,
+                                                         const double *__restrict__ hptr,
+                                                         VT *__restrict__ v,
+                                                         const double *__restrict__ wq) {
+    cpr_restrict_body<NB, WT, VT>(blockIdx.x, n, nw, L, split0, w, hptr, v, wq);
 }
 
 // z = x1 + D^-1 (v - A x1), x1 = the pressure correction in the pressure
@@ -1249,6 +1281,123 @@ void launch_cpr_finish(hipStream_t s, int nb, int n, int nw, const AmgLevel &L,
     else
         hipLaunchKernelGGL((k_cpr_finish<3, G>), grid_for(threads, kBlock), dim3(kBlock), 0, s, n,
                            nw, L, split0, colsplit, sys, ap, v, dinv, z);
+}
+
+// ---------------------------------------------------------------------------
+// batched launches over the members of an ensemble
+
+template <int NB>
+__global__ __launch_bounds__(kBlock) void kb_amg_extract(const Member *__restrict__ mem, Batch B) {
+    int m, b, nb;
+    if (!batch_view(B, m, b, nb)) return;
+    const Member &M = mem[m];
+    amg_extract_body<NB, double>(b, nb, M.lv[0], M.g, M.wells, M.sys, M.wq, M.ap);
+}
+
+__global__ __launch_bounds__(kBlock) void kb_amg_coarsen(const Member *__restrict__ mem, Batch B,
+                                                         int l) {
+    int m, b, nb;
+    if (!batch_view(B, m, b, nb)) return;
+    const Member &M = mem[m];
+    if (l >= M.nlev) return;
+    amg_coarsen_body(b, M.lv[l - 1], M.lv[l], M.cfs_ptr[l], M.cfs_idx[l]);
+}
+
+// the dense matrix of the member's coarsest level and its inverse, by one
+// workgroup (the rows by the threads, then the Gauss-Jordan elimination in
+// LDS of the single-member launch)
+__global__ __launch_bounds__(1024) void kb_amg_coarsest(const Member *__restrict__ mem, Batch B) {
+    int m, b, nb;
+    if (!batch_view(B, m, b, nb)) return;
+    const Member &M = mem[m];
+    const AmgLevel &L = M.lv[M.nlev - 1];
+    const int n = 2 * L.half + L.nw;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) amg_dense_row(L, M.Mden, t);
+    __syncthreads();
+    extern __shared__ double sm[];
+    dense_invert_lds_body(n, M.Mden, M.Minv, M.amg_bad, sm);
+}
+
+// the first CPR stage's restriction: of the first vector of a restart
+// cycle (j < 0: b / ||b|| in the first cycle, r / ||r|| after it) or of the
+// new Arnoldi vector w / h_{j+1,j} (j >= 0), stored in V
+template <int NB>
+__global__ __launch_bounds__(kBlock) void kb_cpr_restrict(const Member *__restrict__ mem, Batch B,
+                                                          int j, int first_bit, int s_norm,
+                                                          int s_res) {
+    int m, b, nb;
+    if (!batch_view(B, m, b, nb)) return;
+    const Member &M = mem[m];
+    const double *w;
+    const double *h;
+    double *v;
+    if (j < 0) {
+        const bool first = (B.flags[m] & first_bit) != 0;
+        w = first ? M.sys.R : M.r;
+        h = M.scal + (first ? s_norm : s_res) + 1;
+        v = M.V;
+    } else {
+        w = M.w;
+        h = M.H + (size_t)j * (kMaxRestart + 2) + j + 1;
+        v = M.V + (size_t)(j + 1) * M.nvec;
+    }
+    cpr_restrict_body<NB, double, double>(b, M.n, M.nw, M.lv[0], M.split0, w, h, v, M.wq);
+}
+
+// The member's whole AMG cycle by one workgroup, its phase list walked
+// with every level's arrays in HBM (the phases and per-entry arithmetic of
+// the per-level launches, so the result is bit for bit theirs).
+__global__ __launch_bounds__(kSubThreads) void kb_amg_cycle(const Member *__restrict__ mem, Batch B) {
+    int m, b, nb;
+    if (!batch_view(B, m, b, nb)) return;
+    const Member &M = mem[m];
+    for (int o = 0; o < M.nops; ++o) {
+        const int op = __builtin_amdgcn_readfirstlane(M.ops[o]);
+        const int l = (op >> 4) & 15;
+        subcycle_phase(op, M.lv[l], M.lv[l + 1], M.Minv, M.rbuf);
+        __syncthreads();
+    }
+}
+
+void launchb_amg_extract(hipStream_t s, int nb, const Member *mem, Batch B, int total) {
+    if (total <= 0) return;
+    if (nb == 2) hipLaunchKernelGGL(kb_amg_extract<2>, dim3(total), dim3(kBlock), 0, s, mem, B);
+    else hipLaunchKernelGGL(kb_amg_extract<3>, dim3(total), dim3(kBlock), 0, s, mem, B);
+}
+
+void launchb_amg_coarsen(hipStream_t s, const Member *mem, Batch B, int total, int level) {
+    if (total > 0)
+        hipLaunchKernelGGL(kb_amg_coarsen, dim3(total), dim3(kBlock), 0, s, mem, B, level);
+}
+
+void launchb_amg_coarsest(hipStream_t s, const Member *mem, Batch one, int tone, int nmax) {
+    if (tone > 0)
+        hipLaunchKernelGGL(kb_amg_coarsest, dim3(tone), dim3(1024), dense_lds_bytes(nmax), s, mem,
+                           one);
+}
+
+hipError_t batch_allow_lds() {
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&kb_amg_coarsest),
+                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)dense_lds_bytes(kDenseLds));
+}
+
+int dense_lds_max() { return kDenseLds; }
+
+void launchb_cpr_restrict(hipStream_t s, int nb, const Member *mem, Batch B, int total, int j,
+                          int first_bit, int s_norm, int s_res) {
+    if (total <= 0) return;
+    if (nb == 2)
+        hipLaunchKernelGGL(kb_cpr_restrict<2>, dim3(total), dim3(kBlock), 0, s, mem, B, j,
+                           first_bit, s_norm, s_res);
+    else
+        hipLaunchKernelGGL(kb_cpr_restrict<3>, dim3(total), dim3(kBlock), 0, s, mem, B, j,
+                           first_bit, s_norm, s_res);
+}
+
+void launchb_amg_cycle(hipStream_t s, const Member *mem, Batch one, int tone) {
+    if (tone > 0)
+        hipLaunchKernelGGL(kb_amg_cycle, dim3(tone), dim3(kSubThreads), 0, s, mem, one);
 }
 
 }  // namespace fim

@@ -14,6 +14,7 @@
 #include <chrono>
 #include <functional>
 #include <limits>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <numeric>
@@ -1815,6 +1816,750 @@ static int adjoint_impl(fim_ctx *c, int nsteps, const double *dt, const double *
 }
 
 // ---------------------------------------------------------------------------
+// batched ensemble: the members advanced together, one launch per kernel
+// for all of them
+//
+// Every member keeps its own context (its buffers, options and schedule);
+// a launch covers all members, each member's blocks running the member's
+// own kernel bodies on the member's buffers, and per-member flags select
+// the members that take part in it.  The host keeps the Newton / time-step
+// state machine and the GMRES state of fim_step for every member, so a
+// member computes bit for bit what it computes alone.  Newton iterations
+// run in rounds: every member with work takes part in the round's
+// assembly; the members whose convergence check asks for a solve share one
+// lockstep FGMRES (restart cycles synchronised, a member frozen once its
+// own cycle stops), then one update.
+
+namespace {
+
+struct Shape {                    // block starts of one launch shape
+    int *d = nullptr;
+    int total = 0;
+};
+
+enum { kSave0 = 128, kSave1 = 256, kRestore0 = 512, kRestore1 = 1024 };
+
+struct GmState {
+    bool in_cycle = false, stopped = false, first = true;
+    int k = 0, total = 0, status = 1;
+    double bnorm = 0, beta = 0, rtol = 0, stop = 0, relres = 1;
+    std::vector<double> Hh, cs, sn, g, y;
+};
+
+struct MemRun {
+    int st = 0;                   // schedule step
+    bool stopped = false;         // no more work (all steps done, or one failed)
+    double dt = 0, remaining = 0, h = 0, tdt = 0;
+    int it = 0;
+    double last_dp = INFINITY, last_ds = INFINITY, last_viol = 0;
+    NewtonStats ns;
+    fim_step_report rep{};
+    Forcing forcing;
+    bool start_step = true, start_sub = true, solve = false;
+    GmState gm;
+};
+
+struct Ensemble {
+    std::vector<fim_ctx *> mem;
+    int nm = 0, nb = 0, m = 0, ilu_threads = 0, dense_n = 0;
+    size_t ilu_lds = 0;
+    hipStream_t s = nullptr;
+    std::vector<void *> owned;
+    Member *d_mem = nullptr;
+    StateSlots *d_slots = nullptr;
+    int *d_flags = nullptr, *d_k = nullptr;
+    double *d_dt = nullptr, *d_scal = nullptr, *d_ypack = nullptr;
+    int *h_flagring = nullptr;    // pinned ring of flag arrays
+    int ring = 0, ringpos = 0;
+    int *h_k = nullptr;
+    double *h_dt = nullptr, *h_scal = nullptr, *h_ypack = nullptr;
+    int ld_scal = 0, ld_y = 0;
+    Shape cells, rows, wells, conv, one, vec, spmv, tiles, extract, statecopy;
+    std::vector<Shape> coarsen, dot, dotsum;
+    std::vector<int> flags;
+
+    template <typename T>
+    T *dalloc(size_t count) {
+        void *p = nullptr;
+        if (count == 0) count = 1;
+        const hipError_t e = hipMalloc(&p, count * sizeof(T));
+        if (e != hipSuccess) {
+            set_err("hipMalloc of %zu bytes failed: %s", count * sizeof(T), hipGetErrorString(e));
+            throw std::bad_alloc();
+        }
+        owned.push_back(p);
+        return static_cast<T *>(p);
+    }
+    ~Ensemble() {
+        if (s) (void)hipStreamSynchronize(s);
+        for (void *p : owned) (void)hipFree(p);
+        for (void *p : {(void *)h_flagring, (void *)h_k, (void *)h_dt, (void *)h_scal,
+                        (void *)h_ypack})
+            if (p) (void)hipHostFree(p);
+        if (s) (void)hipStreamDestroy(s);
+    }
+
+    Shape shape(const std::function<int(const fim_ctx *)> &blocks) {
+        std::vector<int> h(nm + 1, 0);
+        for (int k = 0; k < nm; ++k) h[k + 1] = h[k] + std::max(0, blocks(mem[k]));
+        Shape sh;
+        sh.d = dalloc<int>(nm + 1);
+        HIPCHECK(hipMemcpy(sh.d, h.data(), (nm + 1) * sizeof(int), hipMemcpyHostToDevice));
+        sh.total = h[nm];
+        return sh;
+    }
+    Batch batch(const Shape &sh, int bit) const { return Batch{sh.d, d_flags, nm, bit}; }
+
+    // the host's flags to the device, in stream order (each copy from a
+    // pinned ring slot of its own, so a later write does not race it)
+    void put_flags() {
+        int *slot = h_flagring + (size_t)ringpos * nm;
+        ringpos = (ringpos + 1) % ring;
+        if (ringpos == 0) HIPCHECK(hipStreamSynchronize(s));
+        std::memcpy(slot, flags.data(), nm * sizeof(int));
+        HIPCHECK(hipMemcpyAsync(d_flags, slot, nm * sizeof(int), hipMemcpyHostToDevice, s));
+    }
+    void set(int bit, const std::function<bool(int)> &on) {
+        for (int k = 0; k < nm; ++k) flags[k] = on(k) ? (flags[k] | bit) : (flags[k] & ~bit);
+    }
+    bool any(int bit) const {
+        for (int f : flags)
+            if (f & bit) return true;
+        return false;
+    }
+    // the members' scalar slots [first, first + count) into h_scal[k * ld_scal + e]
+    void gather(int bit, int first, int count) {
+        launchb_gather_scalars(s, d_mem, batch(one, bit), one.total, first, count, d_scal, ld_scal);
+        HIPCHECK(hipMemcpyAsync(h_scal, d_scal, (size_t)nm * ld_scal * sizeof(double),
+                                hipMemcpyDeviceToHost, s));
+        HIPCHECK(hipStreamSynchronize(s));
+    }
+};
+
+// the batched configuration: CPR with the block-Jacobi ILU(0) second stage
+// in FP64, one block size, device, restart length and ILU(0) workgroup size
+void check_member(const fim_ctx *c, const fim_ctx *c0, int k) {
+    REQUIRE(c->opt.precond == FIM_PREC_CPR_ILU0 && c->opt.precision == FIM_FP64,
+            "member %d: the batched ensemble runs CPR with block-Jacobi ILU(0) in FP64", k);
+    REQUIRE(c->nb == c0->nb, "member %d: block size %d, member 0 has %d", k, c->nb, c0->nb);
+    REQUIRE(c->dev == c0->dev, "member %d is on device %d, member 0 on %d", k, c->dev, c0->dev);
+    REQUIRE(c->m == c0->m, "member %d: GMRES restart %d, member 0 has %d", k, c->m, c0->m);
+    REQUIRE(ilu_threads(c->ilu) == ilu_threads(c0->ilu),
+            "member %d: ILU(0) boxes of %d threads, member 0's of %d", k, ilu_threads(c->ilu),
+            ilu_threads(c0->ilu));
+    REQUIRE((int)c->lv.size() < kMaxLevels, "member %d: %zu AMG levels (at most %d)", k,
+            c->lv.size(), kMaxLevels - 1);
+    const AmgLevel &Lc = c->lv.back();
+    REQUIRE(2 * Lc.half + Lc.nw <= dense_lds_max(),
+            "member %d: coarsest AMG level of %d entries (at most %d)", k, 2 * Lc.half + Lc.nw,
+            dense_lds_max());
+    if (!c->state_set) {
+        set_err("member %d: state not set", k);
+        throw StateError();
+    }
+}
+
+std::unique_ptr<Ensemble> make_ensemble(int count, fim_ctx *const *members) {
+    auto E = std::make_unique<Ensemble>();
+    E->mem.assign(members, members + count);
+    E->nm = count;
+    E->flags.assign(count, 0);
+    fim_ctx *c0 = members[0];
+    for (int k = 0; k < count; ++k) check_member(members[k], c0, k);
+    E->nb = c0->nb;
+    E->m = c0->m;
+    HIPCHECK(hipSetDevice(c0->dev));
+    HIPCHECK(hipStreamCreateWithFlags(&E->s, hipStreamNonBlocking));
+    for (fim_ctx *c : E->mem) c->sync();       // every member's earlier work is done
+    int lds_max = 0;
+    HIPCHECK(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, c0->dev));
+    std::vector<Member> hm(count);
+    std::vector<StateSlots> hs(count);
+    for (int k = 0; k < count; ++k) {
+        fim_ctx *c = members[k];
+        Member &M = hm[k];
+        std::memset(static_cast<void *>(&M), 0, sizeof M);
+        M.g = c->g;
+        M.f = c->phys;
+        M.wells = c->wells();
+        M.sys = c->sys();
+        M.n = c->n;
+        M.nw = c->nw;
+        M.nb = c->nb;
+        M.nrows = c->nrows;
+        M.m = c->m;
+        M.nvec = c->nvec;
+        M.ds_max = c->opt.ds_max;
+        M.dp_max = c->opt.dp_max;
+        M.pvref = c->pvref;
+        M.depth = c->depth;
+        M.tx = c->tx;
+        M.ty = c->ty;
+        M.tz = c->tz;
+        M.P = c->P;
+        M.Sw = c->Sw;
+        M.X = c->X;
+        M.pbhp = c->pbhp;
+        M.flag = c->flag;
+        M.rec = c->rec;
+        M.aold = c->aold;
+        M.wmeas = c->wmeas;
+        M.partials = c->partials;
+        M.scal = c->scal;
+        M.V = c->V;
+        M.Z = c->Z;
+        M.w = c->w;
+        M.x = c->x;
+        M.b = c->b;
+        M.r = c->r;
+        M.t = c->t;
+        M.H = c->H;
+        M.tmp = c->tmp;
+        M.ydev = c->ydev;
+        M.reorth = c->reorth;
+        M.T = c->ilu;
+        M.lu = c->lu;
+        M.ilu_bad = c->ilu_bad;
+        M.nlev = (int)c->lv.size();
+        for (int l = 0; l < M.nlev; ++l) {
+            M.lv[l] = c->lv[l];
+            M.cfs_ptr[l] = c->cfs_ptr[l];
+            M.cfs_idx[l] = c->cfs_idx[l];
+        }
+        M.split0 = c->split0;
+        M.colsplit = c->colsplit;
+        M.wq = c->wq;
+        M.ap = c->ap;
+        M.Mden = c->Mden;
+        M.Minv = c->Minv;
+        M.colk = c->colk;
+        M.amg_bad = c->amg_bad;
+        // the member's whole cycle from its finest level, and the
+        // restriction's scratch
+        std::vector<int> ops;
+        amg_cycle(c, 0, &ops, 0);
+        int *dops = E->dalloc<int>(ops.size());
+        HIPCHECK(hipMemcpy(dops, ops.data(), ops.size() * sizeof(int), hipMemcpyHostToDevice));
+        M.ops = dops;
+        M.nops = (int)ops.size();
+        M.rbuf = E->dalloc<double>(2 * (size_t)c->lv[0].half);
+        for (int q = 0; q < 2; ++q) {
+            hs[k].P[q] = c->sP[q];
+            hs[k].Sw[q] = c->sSw[q];
+            hs[k].X[q] = c->sX[q];
+            hs[k].pbhp[q] = c->spb[q];
+            hs[k].flag[q] = c->sflag[q];
+        }
+        E->ilu_lds = std::max({E->ilu_lds, ilu_solve_lds(c->nb, c->ilu), ilu_factor_lds(c->nb, c->ilu)});
+        const AmgLevel &Lc = c->lv.back();
+        E->dense_n = std::max(E->dense_n, 2 * Lc.half + Lc.nw);
+    }
+    REQUIRE(E->ilu_lds <= (size_t)lds_max, "ILU(0) boxes need %zu bytes of LDS (at most %d)",
+            E->ilu_lds, lds_max);
+    E->ilu_threads = ilu_threads(c0->ilu);
+    HIPCHECK(ilu_batch_allow_lds(E->nb, (size_t)lds_max));
+    HIPCHECK(batch_allow_lds());
+    E->d_mem = E->dalloc<Member>(count);
+    HIPCHECK(hipMemcpy(E->d_mem, hm.data(), count * sizeof(Member), hipMemcpyHostToDevice));
+    E->d_slots = E->dalloc<StateSlots>(count);
+    HIPCHECK(hipMemcpy(E->d_slots, hs.data(), count * sizeof(StateSlots), hipMemcpyHostToDevice));
+    E->d_flags = E->dalloc<int>(count);
+    E->d_k = E->dalloc<int>(count);
+    E->d_dt = E->dalloc<double>(count);
+    E->ld_scal = S_NORM + 4;
+    E->ld_y = kMaxRestart + 2;
+    E->d_scal = E->dalloc<double>((size_t)count * E->ld_scal);
+    E->d_ypack = E->dalloc<double>((size_t)count * E->ld_y);
+    E->ring = 4 * (kMaxRestart + 8);
+    HIPCHECK(hipHostMalloc((void **)&E->h_flagring, (size_t)E->ring * count * sizeof(int),
+                           hipHostMallocDefault));
+    HIPCHECK(hipHostMalloc((void **)&E->h_k, count * sizeof(int), hipHostMallocDefault));
+    HIPCHECK(hipHostMalloc((void **)&E->h_dt, count * sizeof(double), hipHostMallocDefault));
+    HIPCHECK(hipHostMalloc((void **)&E->h_scal, (size_t)count * E->ld_scal * sizeof(double),
+                           hipHostMallocDefault));
+    HIPCHECK(hipHostMalloc((void **)&E->h_ypack, (size_t)count * E->ld_y * sizeof(double),
+                           hipHostMallocDefault));
+    // launch shapes: the block counts of the single-member launches
+    E->cells = E->shape([](const fim_ctx *c) { return blocks_for_cells(c->n); });
+    E->rows = E->shape([](const fim_ctx *c) { return blocks_for_cells(c->nrows); });
+    E->statecopy = E->shape([](const fim_ctx *c) { return blocks_for_cells(std::max(c->n, c->nw)); });
+    E->wells = E->shape([](const fim_ctx *c) { return c->nw; });
+    E->conv = E->shape([](const fim_ctx *c) { return conv_blocks(c->n); });
+    E->one = E->shape([](const fim_ctx *) { return 1; });
+    E->vec = E->shape([](const fim_ctx *c) { return vec_blocks(c->nvec); });
+    E->spmv = E->shape([](const fim_ctx *c) { return spmv_blocks(c->nb, c->nrows); });
+    E->tiles = E->shape([](const fim_ctx *c) {
+        return c->ilu.ntx * c->ilu.nty * c->ilu.ntz + (c->ilu.nsingle > 0 ? 1 : 0);
+    });
+    E->extract = E->shape([](const fim_ctx *c) {
+        return (int)((8L * (c->n + c->nw) + kBlock - 1) / kBlock);
+    });
+    int maxlev = 0;
+    for (fim_ctx *c : E->mem) maxlev = std::max(maxlev, (int)c->lv.size());
+    E->coarsen.resize(maxlev);
+    for (int l = 1; l < maxlev; ++l)
+        E->coarsen[l] = E->shape([l](const fim_ctx *c) {
+            if (l >= (int)c->lv.size()) return 0;
+            const AmgLevel &C = c->lv[l];
+            return (int)((2L * C.half + C.nslot + C.nw + kBlock - 1) / kBlock);
+        });
+    const int maxg = dot_groups(E->m);
+    E->dot.resize(maxg + 1);
+    for (int g = 1; g <= maxg; ++g)
+        E->dot[g] = E->shape([g](const fim_ctx *c) { return vec_blocks(c->nvec) * g; });
+    E->dotsum.resize(E->m + 1);
+    for (int j = 0; j < E->m; ++j)
+        E->dotsum[j] = E->shape([j](const fim_ctx *) { return j + 2; });
+    return E;
+}
+
+// The preconditioner of every member with kOnSolve (prec_setup in FP64 with
+// CPR and block-Jacobi ILU(0))
+void batch_prec_setup(Ensemble &E) {
+    launchb_ilu_factor(E.s, E.nb, E.d_mem, E.batch(E.tiles, kOnSolve), E.tiles.total,
+                       E.ilu_threads, E.ilu_lds);
+    launchb_amg_extract(E.s, E.nb, E.d_mem, E.batch(E.extract, kOnSolve), E.extract.total);
+    for (size_t l = 1; l < E.coarsen.size(); ++l)
+        launchb_amg_coarsen(E.s, E.d_mem, E.batch(E.coarsen[l], kOnSolve), E.coarsen[l].total,
+                            (int)l);
+    launchb_amg_coarsest(E.s, E.d_mem, E.batch(E.one, kOnSolve), E.one.total, E.dense_n);
+}
+
+// z = M^-1 v of the members with kOnCycle: the first vector of a restart
+// cycle (j < 0) or the new Arnoldi vector of step j
+void batch_precondition(Ensemble &E, int j) {
+    launchb_cpr_restrict(E.s, E.nb, E.d_mem, E.batch(E.rows, kOnCycle), E.rows.total, j,
+                         kFirstCycle, S_NORM, S_RES);
+    launchb_amg_cycle(E.s, E.d_mem, E.batch(E.one, kOnCycle), E.one.total);
+    launchb_ilu_solve(E.s, E.nb, E.d_mem, E.batch(E.tiles, kOnCycle), E.tiles.total, j,
+                      E.ilu_threads, E.ilu_lds);
+}
+
+// Arnoldi step j of the members with kOnCycle (arnoldi_rest after the SpMV),
+// the Hessenberg columns packed into d_scal... into d_ypack's neighbour
+void batch_arnoldi(Ensemble &E, int j, double *dcols, double *hcols, int ld) {
+    launchb_spmv(E.s, E.nb, E.d_mem, E.batch(E.spmv, kOnCycle), E.spmv.total, j);
+    const Shape &dp = E.dot[dot_groups(j + 1)];
+    launchb_multidot(E.s, E.d_mem, E.batch(dp, kOnCycle), dp.total, E.batch(E.dotsum[j], kOnCycle),
+                     E.dotsum[j].total, j, false);
+    launchb_update_norm(E.s, E.d_mem, E.batch(E.vec, kOnCycle), E.vec.total,
+                        E.batch(E.one, kOnCycle), E.one.total, j, false);
+    launchb_multidot(E.s, E.d_mem, E.batch(dp, kOnCycle), dp.total, E.batch(E.dotsum[j], kOnCycle),
+                     E.dotsum[j].total, j, true);
+    launchb_update_norm(E.s, E.d_mem, E.batch(E.vec, kOnCycle), E.vec.total,
+                        E.batch(E.one, kOnCycle), E.one.total, j, true);
+    batch_precondition(E, j);
+    launchb_hcols(E.s, E.d_mem, E.batch(E.one, kOnCycle), E.one.total, j, dcols, ld);
+    HIPCHECK(hipMemcpyAsync(hcols, dcols, (size_t)E.nm * ld * sizeof(double),
+                            hipMemcpyDeviceToHost, E.s));
+}
+
+}  // namespace
+
+namespace {
+
+// FGMRES of the members with solve set (J x = R of each member, lin_rtol or
+// its forcing term, max_lin iterations): gmres_t<double> of every member,
+// with the restart cycles in lockstep.  Fills gm.status / total / relres.
+void batch_gmres(Ensemble &E, std::vector<MemRun> &runs, double *dcols, double *hcols) {
+    const int nm = E.nm, m = E.m, LDH = kMaxRestart + 2;
+    const size_t colstride = (size_t)nm * LDH;       // one step's packed columns
+    E.set(kOnSolve, [&](int k) { return runs[k].solve; });
+    E.set(kOnCycle | kOnFinish | kFirstCycle, [](int) { return false; });
+    E.put_flags();
+    launchb_scale_zero(E.s, E.d_mem, E.batch(E.vec, kOnSolve), E.vec.total);
+    launchb_norm_b(E.s, E.d_mem, E.batch(E.vec, kOnSolve), E.vec.total, E.batch(E.one, kOnSolve),
+                   E.one.total, S_NORM);
+    E.gather(kOnSolve, S_NORM, 2);
+    for (int k = 0; k < nm; ++k) {
+        MemRun &R = runs[k];
+        if (!R.solve) continue;
+        GmState &G = R.gm;
+        fim_ctx *c = E.mem[k];
+        G = GmState{};
+        G.bnorm = E.h_scal[(size_t)k * E.ld_scal + 1];
+        G.Hh.assign((size_t)(m + 1) * m, 0.0);
+        G.cs.assign(m, 0.0);
+        G.sn.assign(m, 0.0);
+        G.g.assign(m + 1, 0.0);
+        G.y.assign(m, 0.0);
+        if (!(G.bnorm > 0.0)) {                // zero right side, or not a number
+            G.relres = G.bnorm == 0.0 ? 0.0 : NAN;
+            G.status = G.bnorm == 0.0 ? 0 : -1;
+            continue;
+        }
+        G.rtol = R.forcing.next(c->opt, G.bnorm);
+        G.beta = G.bnorm;
+        G.in_cycle = true;
+        G.first = true;
+    }
+    for (;;) {
+        // one restart cycle of the members still solving
+        bool anyc = false;
+        for (int k = 0; k < nm; ++k) {
+            GmState &G = runs[k].gm;
+            if (!runs[k].solve || !G.in_cycle) continue;
+            anyc = true;
+            G.stopped = false;
+            G.k = 0;
+            G.stop = G.rtol * G.bnorm;
+            std::fill(G.g.begin(), G.g.end(), 0.0);
+            G.g[0] = G.beta;
+        }
+        if (!anyc) break;
+        auto cycle_member = [&](int k) { return runs[k].solve && runs[k].gm.in_cycle; };
+        E.set(kOnCycle, cycle_member);
+        E.set(kFirstCycle, [&](int k) { return cycle_member(k) && runs[k].gm.first; });
+        E.put_flags();
+        batch_precondition(E, -1);
+        // step 0 for every member in the cycle, then look ahead one step
+        std::vector<std::vector<char>> took(m, std::vector<char>(nm, 0));
+        for (int k = 0; k < nm; ++k) took[0][k] = cycle_member(k);
+        E.set(kFirstCycle, [](int) { return false; });
+        E.put_flags();
+        batch_arnoldi(E, 0, dcols, hcols, LDH);
+        std::vector<hipEvent_t> done(m, nullptr);
+        auto record = [&](int j) {
+            if (!done[j]) HIPCHECK(hipEventCreateWithFlags(&done[j], hipEventDisableTiming));
+            HIPCHECK(hipEventRecord(done[j], E.s));
+        };
+        record(0);
+        (void)colstride;
+        try {
+            for (int j = 0;; ++j) {
+                if (j + 1 < m) {
+                    bool any = false;
+                    for (int k = 0; k < nm; ++k) {
+                        const GmState &G = runs[k].gm;
+                        const int max_it = E.mem[k]->opt.max_lin;
+                        took[j + 1][k] = cycle_member(k) && !G.stopped && G.total + j + 1 < max_it;
+                        any = any || took[j + 1][k];
+                    }
+                    if (any) {
+                        E.set(kOnCycle, [&](int k) { return took[j + 1][k] != 0; });
+                        E.put_flags();
+                        batch_arnoldi(E, j + 1, dcols + (size_t)(j + 1) * colstride,
+                                      hcols + (size_t)(j + 1) * colstride, LDH);
+                        record(j + 1);
+                    }
+                }
+                HIPCHECK(hipEventSynchronize(done[j]));
+                bool all_stopped = true;
+                for (int k = 0; k < nm; ++k) {
+                    GmState &G = runs[k].gm;
+                    if (!cycle_member(k)) continue;
+                    if (G.stopped || !took[j][k]) {
+                        G.stopped = true;
+                        continue;
+                    }
+                    const int max_it = E.mem[k]->opt.max_lin;
+                    const double *h = hcols + (size_t)j * colstride + (size_t)k * LDH;
+                    std::vector<double> &Hh = G.Hh;
+                    for (int i = 0; i <= j + 1; ++i) Hh[(size_t)i * m + j] = h[i];
+                    for (int i = 0; i < j; ++i) {
+                        const double a = Hh[(size_t)i * m + j], bq = Hh[(size_t)(i + 1) * m + j];
+                        Hh[(size_t)i * m + j] = G.cs[i] * a + G.sn[i] * bq;
+                        Hh[(size_t)(i + 1) * m + j] = -G.sn[i] * a + G.cs[i] * bq;
+                    }
+                    const double a = Hh[(size_t)j * m + j], bq = Hh[(size_t)(j + 1) * m + j];
+                    const double den = std::hypot(a, bq);
+                    G.cs[j] = den > 0 ? a / den : 1.0;
+                    G.sn[j] = den > 0 ? bq / den : 0.0;
+                    Hh[(size_t)j * m + j] = den;
+                    Hh[(size_t)(j + 1) * m + j] = 0.0;
+                    G.g[j + 1] = -G.sn[j] * G.g[j];
+                    G.g[j] = G.cs[j] * G.g[j];
+                    G.k = j + 1;
+                    const bool breakdown = !(h[j + 1] > 0.0) || !std::isfinite(h[j + 1]);
+                    if (std::fabs(G.g[j + 1]) <= G.stop || G.k == m || G.total + G.k >= max_it ||
+                        breakdown || !std::isfinite(G.g[j + 1]))
+                        G.stopped = true;
+                    else
+                        all_stopped = false;
+                }
+                if (all_stopped) break;
+            }
+        } catch (...) {
+            for (hipEvent_t e : done)
+                if (e) (void)hipEventDestroy(e);
+            throw;
+        }
+        HIPCHECK(hipStreamSynchronize(E.s));
+        for (hipEvent_t e : done)
+            if (e) (void)hipEventDestroy(e);
+        // the cycle's end: x += Z y, then the true residual
+        for (int k = 0; k < nm; ++k) {
+            GmState &G = runs[k].gm;
+            E.h_k[k] = 0;
+            if (!cycle_member(k)) continue;
+            const int kk = G.k;
+            G.total += kk;
+            for (int i = kk - 1; i >= 0; --i) {
+                double sacc = G.g[i];
+                for (int jj = i + 1; jj < kk; ++jj) sacc -= G.Hh[(size_t)i * m + jj] * G.y[jj];
+                G.y[i] = sacc / G.Hh[(size_t)i * m + i];
+            }
+            for (int i = 0; i < kk; ++i) E.h_ypack[(size_t)k * E.ld_y + i] = G.y[i];
+            E.h_k[k] = kk;
+        }
+        HIPCHECK(hipMemcpyAsync(E.d_ypack, E.h_ypack, (size_t)nm * E.ld_y * sizeof(double),
+                                hipMemcpyHostToDevice, E.s));
+        HIPCHECK(hipMemcpyAsync(E.d_k, E.h_k, nm * sizeof(int), hipMemcpyHostToDevice, E.s));
+        E.set(kOnFinish, cycle_member);
+        E.set(kOnCycle, [](int) { return false; });
+        E.put_flags();
+        launchb_axpy(E.s, E.d_mem, E.batch(E.vec, kOnFinish), E.vec.total, E.d_k, E.d_ypack, E.ld_y);
+        launchb_spmv(E.s, E.nb, E.d_mem, E.batch(E.spmv, kOnFinish), E.spmv.total, -1);
+        launchb_residual(E.s, E.d_mem, E.batch(E.vec, kOnFinish), E.vec.total,
+                         E.batch(E.one, kOnFinish), E.one.total, S_RES);
+        E.gather(kOnFinish, S_RES, 2);
+        for (int k = 0; k < nm; ++k) {
+            GmState &G = runs[k].gm;
+            if (!cycle_member(k)) continue;
+            const int max_it = E.mem[k]->opt.max_lin;
+            G.beta = E.h_scal[(size_t)k * E.ld_scal + 1];
+            G.relres = G.beta / G.bnorm;
+            G.first = false;
+            if (G.relres <= G.rtol) {
+                G.status = 0;
+                G.in_cycle = false;
+            } else if (G.total >= max_it || !std::isfinite(G.relres)) {
+                G.status = 1;
+                G.in_cycle = false;
+            }
+        }
+        E.set(kOnFinish, [](int) { return false; });
+    }
+}
+
+}  // namespace
+
+namespace {
+
+// fim_ensemble_run: every member's steps by the state machine of step_impl
+// and newton(), in rounds of batched launches
+int ensemble_impl(int count, fim_ctx *const *members, int nsteps, const double *dt,
+                  fim_step_report *reports, int32_t *status) {
+    std::unique_ptr<Ensemble> EP = make_ensemble(count, members);
+    Ensemble &E = *EP;
+    const int nm = E.nm, m = E.m, LDH = kMaxRestart + 2;
+    std::vector<MemRun> runs(nm);
+    for (int k = 0; k < nm; ++k) {
+        for (int s = 0; s < nsteps; ++s) {
+            status[(size_t)k * nsteps + s] = FIM_SKIPPED;
+            if (reports) reports[(size_t)k * nsteps + s] = fim_step_report{};
+        }
+        REQUIRE(dt[(size_t)k * nsteps] > 0, "member %d: dt must be > 0", k);
+    }
+    // the Hessenberg columns of every step of a cycle, packed by member
+    const size_t ncol = (size_t)(m + 1) * nm * LDH;
+    double *dcols = E.dalloc<double>(ncol);
+    double *hcols = nullptr;
+    HIPCHECK(hipHostMalloc((void **)&hcols, ncol * sizeof(double), hipHostMallocDefault));
+    struct PinGuard {
+        double *p;
+        ~PinGuard() { if (p) (void)hipHostFree(p); }
+    } pin_guard{hcols};
+    int result = FIM_OK;
+    auto finish_step = [&](int k, int st_code) {
+        MemRun &R = runs[k];
+        fim_step_report &r = R.rep;
+        r.newton_iters = R.ns.newton;
+        r.linear_iters = R.ns.linear;
+        r.converged = st_code == FIM_OK;
+        r.dt_done = st_code == FIM_OK ? R.dt : 0.0;
+        for (int i = 0; i < 3; ++i) {
+            r.cnv[i] = R.ns.cnv[i];
+            r.mb[i] = R.ns.mb[i];
+        }
+        r.last_dp = R.ns.last_dp;
+        r.last_ds = R.ns.last_ds;
+        r.well_res = R.ns.well_res;
+        status[(size_t)k * nsteps + R.st] = st_code;
+        if (reports) reports[(size_t)k * nsteps + R.st] = r;
+        if (st_code != FIM_OK) {
+            R.stopped = true;
+            result = FIM_NOT_CONVERGED;
+            return;
+        }
+        R.st++;
+        R.start_step = true;
+        if (R.st >= nsteps) R.stopped = true;
+    };
+    for (int k = 0; k < nm; ++k) runs[k].stopped = nsteps == 0;
+    for (;;) {
+        // new steps and sub-steps: the state copies of step_impl
+        bool work = false;
+        for (int k = 0; k < nm; ++k) {
+            MemRun &R = runs[k];
+            E.flags[k] &= ~(kSave0 | kSave1);
+            if (R.stopped) continue;
+            work = true;
+            if (R.start_step) {
+                R.dt = dt[(size_t)k * nsteps + R.st];
+                REQUIRE(R.dt > 0 && std::isfinite(R.dt), "member %d: dt must be > 0", k);
+                R.remaining = R.dt;
+                R.h = R.dt;
+                R.rep = fim_step_report{};
+                R.ns = NewtonStats{};
+                E.flags[k] |= kSave0;
+                R.start_step = false;
+                R.start_sub = true;
+            }
+            if (R.start_sub) {
+                R.tdt = std::min(R.h, R.remaining);
+                R.it = 0;
+                R.last_dp = R.last_ds = INFINITY;
+                R.last_viol = 0.0;
+                R.forcing = Forcing{};
+                E.flags[k] |= kSave1;
+                R.start_sub = false;
+            }
+        }
+        if (!work) break;
+        if (E.any(kSave0) || E.any(kSave1)) {
+            E.put_flags();
+            if (E.any(kSave0))
+                launchb_state_copy(E.s, E.d_mem, E.statecopy.d, E.d_flags, nm, E.statecopy.total,
+                                   E.d_slots, 0, kSave0, 0);
+            if (E.any(kSave1))
+                launchb_state_copy(E.s, E.d_mem, E.statecopy.d, E.d_flags, nm, E.statecopy.total,
+                                   E.d_slots, 1, kSave1, 0);
+        }
+        // assembly round: properties (step-start accumulation at it = 0),
+        // residual and Jacobian, convergence measures
+        for (int k = 0; k < nm; ++k) {
+            const MemRun &R = runs[k];
+            E.h_dt[k] = R.tdt;
+            const bool on = !R.stopped;
+            E.flags[k] = (E.flags[k] & ~(kOnNewton | kAold | kOnSolve | kOnUpdate | kSave0 | kSave1)) |
+                         (on ? kOnNewton : 0) | (on && R.it == 0 ? kAold : 0);
+        }
+        HIPCHECK(hipMemcpyAsync(E.d_dt, E.h_dt, nm * sizeof(double), hipMemcpyHostToDevice, E.s));
+        E.put_flags();
+        launchb_props(E.s, E.nb, E.d_mem, E.batch(E.cells, kOnNewton), E.cells.total);
+        launchb_assemble(E.s, E.nb, E.d_mem, E.batch(E.cells, kOnNewton), E.cells.total,
+                         E.batch(E.wells, kOnNewton), E.wells.total, E.d_dt);
+        launchb_conv(E.s, E.nb, E.d_mem, E.batch(E.conv, kOnNewton), E.conv.total,
+                     E.batch(E.one, kOnNewton), E.one.total, E.d_dt, S_CONV);
+        E.gather(kOnNewton, S_CONV, S_NORM - S_CONV);
+        // the convergence check of newton() for every member
+        std::vector<int> fail(nm, 0), ok(nm, 0);
+        for (int k = 0; k < nm; ++k) {
+            MemRun &R = runs[k];
+            R.solve = false;
+            if (R.stopped) continue;
+            fim_ctx *c = E.mem[k];
+            const fim_options &o = c->opt;
+            const int nb = c->nb;
+            const double *sc = E.h_scal + (size_t)k * E.ld_scal + S_CONV;
+            if (R.it > 0) {
+                R.last_dp = sc[S_UPD - S_CONV];
+                R.last_ds = sc[S_UPD - S_CONV + 1];
+                R.last_viol = sc[S_UPD - S_CONV + 2];
+            }
+            bool finite = std::isfinite(R.last_dp) || R.it == 0;
+            bool conv = R.it > 0;
+            for (int i = 0; i < nb; ++i) {
+                R.ns.cnv[i] = sc[i];
+                R.ns.mb[i] = R.tdt * std::fabs(sc[nb + i]) / sc[2 * nb + i];
+                finite = finite && std::isfinite(R.ns.cnv[i]) && std::isfinite(R.ns.mb[i]);
+                conv = conv && R.ns.cnv[i] <= o.tol_cnv && R.ns.mb[i] <= o.tol_mb;
+            }
+            const double wmax = sc[3 * nb];
+            R.ns.last_dp = R.last_dp;
+            R.ns.last_ds = R.last_ds;
+            R.ns.well_res = wmax;
+            finite = finite && std::isfinite(wmax);
+            if (!finite) {
+                fail[k] = 1;
+                continue;
+            }
+            conv = conv && wmax <= o.tol_well && R.last_dp <= o.tol_dp && R.last_ds <= o.tol_ds;
+            if (conv) {
+                if (R.last_viol <= kSatSlack) ok[k] = 1;
+                else fail[k] = 1;
+                continue;
+            }
+            if (R.it >= o.max_newton) {
+                fail[k] = 1;
+                continue;
+            }
+            R.solve = true;
+        }
+        // solve and update for the members that go on
+        bool anysolve = false;
+        for (int k = 0; k < nm; ++k) anysolve = anysolve || runs[k].solve;
+        if (anysolve) {
+            E.set(kOnSolve, [&](int k) { return runs[k].solve; });
+            E.put_flags();
+            batch_prec_setup(E);
+            batch_gmres(E, runs, dcols, hcols);
+            for (int k = 0; k < nm; ++k) {
+                MemRun &R = runs[k];
+                if (!R.solve) continue;
+                const GmState &G = R.gm;
+                R.ns.linear += G.total;
+                R.ns.newton += 1;
+                if (G.status != 0 && !(std::isfinite(G.relres) && G.relres < 1.0)) {
+                    fail[k] = 1;
+                    R.solve = false;
+                }
+            }
+            E.set(kOnUpdate, [&](int k) { return runs[k].solve; });
+            E.set(kOnSolve, [](int) { return false; });
+            E.put_flags();
+            launchb_newton_update(E.s, E.nb, E.d_mem, E.batch(E.conv, kOnUpdate), E.conv.total,
+                                  E.batch(E.one, kOnUpdate), E.one.total, S_UPD);
+            for (int k = 0; k < nm; ++k)
+                if (runs[k].solve) runs[k].it++;
+        }
+        // accepted and failed sub-steps (step_impl)
+        for (int k = 0; k < nm; ++k) {
+            MemRun &R = runs[k];
+            E.flags[k] &= ~(kRestore0 | kRestore1 | kOnUpdate);
+            if (ok[k]) {
+                R.remaining -= R.tdt;
+                if (R.rep.nsub < FIM_MAX_SUB) R.rep.dt_sub[R.rep.nsub] = R.tdt;
+                R.rep.nsub++;
+                R.start_sub = true;
+                if (!(R.remaining > 1e-12 * R.dt)) finish_step(k, FIM_OK);
+            } else if (fail[k]) {
+                E.flags[k] |= kRestore1;
+                R.rep.cuts++;
+                if (R.rep.cuts > E.mem[k]->opt.max_cuts) {
+                    E.flags[k] |= kRestore0;
+                    finish_step(k, FIM_NOT_CONVERGED);
+                } else {
+                    R.h = 0.5 * R.tdt;
+                    R.start_sub = true;
+                }
+            }
+        }
+        if (E.any(kRestore1) || E.any(kRestore0)) {
+            E.put_flags();
+            if (E.any(kRestore1))
+                launchb_state_copy(E.s, E.d_mem, E.statecopy.d, E.d_flags, nm, E.statecopy.total,
+                                   E.d_slots, 1, 0, kRestore1);
+            if (E.any(kRestore0))
+                launchb_state_copy(E.s, E.d_mem, E.statecopy.d, E.d_flags, nm, E.statecopy.total,
+                                   E.d_slots, 0, 0, kRestore0);
+        }
+    }
+    HIPCHECK(hipStreamSynchronize(E.s));
+    // the step-start accumulation of every member's next step, on its stream
+    for (fim_ctx *c : E.mem) {
+        props(c, true);
+        c->jac_ready = false;
+        c->prec_ready = false;
+    }
+    for (fim_ctx *c : E.mem) c->sync();
+    return result;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
 // permeability (the ROCK input of Sec. 3.2.3): new kx, ky, kz, then the
 // static precompute that depends on them again (transmissibilities and the
 // Peaceman well indices; explicit well indices stay)
@@ -2104,7 +2849,7 @@ int fim_set_perm_dev(fim_ctx *c, const double *kx, const double *ky, const doubl
 }
 
 int fim_ensemble_run(int32_t count, fim_ctx *const *members, int32_t nsteps, const double *dt,
-                     int32_t workers, fim_step_report *reports, int32_t *status) {
+                     fim_step_report *reports, int32_t *status) {
     return guarded([&]() -> int {
         REQUIRE(count >= 0 && nsteps >= 0, "count and nsteps must be >= 0");
         if (count == 0 || nsteps == 0) return FIM_OK;
@@ -2114,58 +2859,7 @@ int fim_ensemble_run(int32_t count, fim_ctx *const *members, int32_t nsteps, con
         std::sort(seen.begin(), seen.end());
         REQUIRE(std::adjacent_find(seen.begin(), seen.end()) == seen.end(),
                 "a context appears twice among the members");
-        // longest first: the run ends with the small members
-        std::vector<int> order(count);
-        std::iota(order.begin(), order.end(), 0);
-        std::stable_sort(order.begin(), order.end(),
-                         [&](int a, int b) { return members[a]->n > members[b]->n; });
-        const int nthreads = std::min<int>(count, workers > 0 ? workers : 16);
-        std::atomic<int> next{0};
-        std::mutex mu;
-        int first_err = 0;
-        bool stopped = false;
-        std::string first_msg;
-        auto work = [&] {
-            for (;;) {
-                const int i = next.fetch_add(1);
-                if (i >= count) return;
-                const int k = order[i];
-                fim_ctx *c = members[k];
-                int rc = hipSetDevice(c->dev) == hipSuccess ? FIM_OK : FIM_E_HIP;
-                if (rc != FIM_OK) set_err("hipSetDevice(%d) failed for member %d", c->dev, k);
-                for (int st = 0; st < nsteps; ++st) {
-                    const size_t e = (size_t)k * nsteps + st;
-                    if (rc != FIM_OK) {
-                        status[e] = FIM_SKIPPED;
-                        if (reports) reports[e] = fim_step_report{};
-                        continue;
-                    }
-                    rc = fim_step(c, dt[e], reports ? reports + e : nullptr);
-                    status[e] = rc;
-                }
-                if (rc != FIM_OK) {
-                    std::lock_guard<std::mutex> lk(mu);
-                    stopped = true;
-                    if (rc < 0 && first_err == 0) {
-                        first_err = rc;
-                        first_msg = g_err;          // this thread's message
-                    }
-                }
-            }
-        };
-        std::vector<std::thread> pool;
-        try {
-            for (int t = 1; t < nthreads; ++t) pool.emplace_back(work);
-        } catch (const std::system_error &) {
-            // fewer threads than asked for: the ones running share the work
-        }
-        work();                                     // the calling thread takes part
-        for (auto &t : pool) t.join();
-        if (first_err) {
-            g_err = first_msg;
-            return first_err;
-        }
-        return stopped ? FIM_NOT_CONVERGED : FIM_OK;
+        return ensemble_impl(count, members, nsteps, dt, reports, status);
     });
 }
 

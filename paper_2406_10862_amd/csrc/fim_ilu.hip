@@ -585,10 +585,10 @@ __device__ void factor_pencils(const Grid &g, const IluTiles &T, const TileBox &
 // as they are factored, hyperplane by hyperplane, and tiles with sweep
 // records write each cell's as soon as its row is done.
 template <int NB, class LT>
-__global__ __launch_bounds__(256) void k_ilu_factor(Grid g, IluTiles T, Sys sys, LT *lu,
-                                                    int *bad) {
+__device__ __forceinline__ void ilu_factor_body(int hb, int nblk, const Grid &g, const IluTiles &T,
+                                                const Sys &sys, LT *lu, int *bad) {
     constexpr int B2 = NB * NB;
-    const int b = xcd_block(blockIdx.x, gridDim.x);   // contiguous tiles per XCD
+    const int b = xcd_block(hb, nblk);                // contiguous tiles per XCD
     const int ntiles = T.ntx * T.nty * T.ntz;
     if (b >= ntiles) {
         for (int e = 0; e < T.nsingle; ++e) {
@@ -652,6 +652,12 @@ __global__ __launch_bounds__(256) void k_ilu_factor(Grid g, IluTiles T, Sys sys,
     }
     for (int e = T.twp[b] + threadIdx.x; e < T.twp[b + 1]; e += blockDim.x)
         factor_row<NB, LT>(g.n + T.tw[e], T, sys, lu, bad);
+}
+
+template <int NB, class LT>
+__global__ __launch_bounds__(256) void k_ilu_factor(Grid g, IluTiles T, Sys sys, LT *lu,
+                                                    int *bad) {
+    ilu_factor_body<NB, LT>(blockIdx.x, gridDim.x, g, T, sys, lu, bad);
 }
 
 // acc -= blk * v (block-vector product summed first, as a matrix-vector
@@ -1008,14 +1014,14 @@ __device__ void solve_cells_pencils(const Grid &g, const TileBox &tb, const Sys 
 // inside every tile; for the CPR second stage the first-stage correction is
 // added to the first slot of every row of x.
 template <int NB, class LT, class VT>
-__global__ __launch_bounds__(256) void k_ilu_solve(Grid g, IluTiles T, Sys sys,
-                                                   const LT *__restrict__ lu, IluRhs<VT, LT> R,
-                                                   VT *__restrict__ x) {
+__device__ __forceinline__ void ilu_solve_body(int hb, int nblk, const Grid &g, const IluTiles &T,
+                                               const Sys &sys, const LT *__restrict__ lu,
+                                               const IluRhs<VT, LT> &R, VT *__restrict__ x,
+                                               double *y) {
     constexpr int B2 = NB * NB;
-    extern __shared__ double y[];
     // each XCD takes one contiguous run of tiles (neighbouring tiles share
     // lines of the level-0 iterate and of the rows at their faces)
-    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int blk = xcd_block(hb, nblk);
     const int ntiles = T.ntx * T.nty * T.ntz;
     const int n = g.n;
     if (blk >= ntiles) {
@@ -1112,6 +1118,14 @@ __global__ __launch_bounds__(256) void k_ilu_solve(Grid g, IluTiles T, Sys sys,
         for (int u = 0; u < NB; ++u)
             x[(size_t)r * NB + u] = (VT)(y[(size_t)l * NB + u] + rhs_corr<NB>(R, n, r, u));
     }
+}
+
+template <int NB, class LT, class VT>
+__global__ __launch_bounds__(256) void k_ilu_solve(Grid g, IluTiles T, Sys sys,
+                                                   const LT *__restrict__ lu, IluRhs<VT, LT> R,
+                                                   VT *__restrict__ x) {
+    extern __shared__ double y[];
+    ilu_solve_body<NB, LT, VT>(blockIdx.x, gridDim.x, g, T, sys, lu, R, x, y);
 }
 
 // v = w / h for a new Arnoldi vector (zero when h is not a positive number)
@@ -1235,6 +1249,69 @@ void launch_normalize(hipStream_t s, long nvec, const double *w, const double *h
 
 void launch_normalize(hipStream_t s, long nvec, const float *w, const double *hptr, float *v) {
     normalize_impl(s, nvec, w, hptr, v);
+}
+
+// ---------------------------------------------------------------------------
+// batched launches over the members of an ensemble (every member's tiles,
+// one workgroup each, with the member's CPR right-hand side)
+
+template <int NB>
+__global__ __launch_bounds__(256) void kb_ilu_factor(const Member *__restrict__ mem, Batch B) {
+    int m, b, nb;
+    if (!batch_view(B, m, b, nb)) return;
+    const Member &M = mem[m];
+    ilu_factor_body<NB, double>(b, nb, M.g, M.T, M.sys, M.lu, M.ilu_bad);
+}
+
+// z = M^-1 v for the first vector of a restart cycle (j < 0: V_0 -> Z_0) or
+// the new Arnoldi vector (j >= 0: V_{j+1} -> Z_{j+1})
+template <int NB>
+__global__ __launch_bounds__(256) void kb_ilu_solve(const Member *__restrict__ mem, Batch B, int j) {
+    int m, b, nb;
+    if (!batch_view(B, m, b, nb)) return;
+    const Member &M = mem[m];
+    extern __shared__ double y[];
+    const size_t off = (size_t)(j + 1) * M.nvec;
+    IluRhs<double, double> R{M.V + off, M.ap, M.colsplit, M.split0, M.lv[0].x, 2 * M.lv[0].half,
+                             nullptr};
+    R.nxp = M.lv[0].nxp;
+    ilu_solve_body<NB, double, double>(b, nb, M.g, M.T, M.sys, M.lu, R, M.Z + off, y);
+}
+
+void launchb_ilu_factor(hipStream_t s, int nb, const Member *mem, Batch B, int total, int threads,
+                        size_t lds) {
+    if (total <= 0) return;
+    if (nb == 2)
+        hipLaunchKernelGGL(kb_ilu_factor<2>, dim3(total), dim3(threads), lds, s, mem, B);
+    else
+        hipLaunchKernelGGL(kb_ilu_factor<3>, dim3(total), dim3(threads), lds, s, mem, B);
+}
+
+void launchb_ilu_solve(hipStream_t s, int nb, const Member *mem, Batch B, int total, int j,
+                       int threads, size_t lds) {
+    if (total <= 0) return;
+    if (nb == 2)
+        hipLaunchKernelGGL(kb_ilu_solve<2>, dim3(total), dim3(threads), lds, s, mem, B, j);
+    else
+        hipLaunchKernelGGL(kb_ilu_solve<3>, dim3(total), dim3(threads), lds, s, mem, B, j);
+}
+
+hipError_t ilu_batch_allow_lds(int nb, size_t bytes) {
+    hipError_t e;
+    if (nb == 2) {
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&kb_ilu_solve<2>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute(reinterpret_cast<const void *>(&kb_ilu_factor<2>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        return e;
+    }
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&kb_ilu_solve<3>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&kb_ilu_factor<3>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    return e;
 }
 
 }  // namespace fim

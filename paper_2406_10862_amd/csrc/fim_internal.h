@@ -137,8 +137,12 @@ void launch_adj_grad(hipStream_t s, int nb, Grid g, Wells w, const double *depth
                      const double *wi_dk, const double *lam, const double *objp, double *grad);
 void launch_bsr_transpose(hipStream_t s, int nb, long nnzb, const int *tperm, const double *val,
                           double *valT);
-int conv_blocks(int n);
-int update_blocks(int n);
+// blocks of the convergence and update reductions (capped: few partials)
+__host__ __device__ inline int conv_blocks(int n) {
+    const int b = (n + kBlock - 1) / kBlock;
+    return b < 2048 ? b : 2048;
+}
+__host__ __device__ inline int update_blocks(int n) { return conv_blocks(n); }
 
 // ---- linear algebra kernels (fim_spmv.hip, fim_linalg.hip) -----------------
 void launch_spmv(hipStream_t s, int nb, int nrows, const int *rowptr, const int *colind,
@@ -153,8 +157,12 @@ void launch_bj_setup(hipStream_t s, int nb, int nrows, const int *diagpos, const
                      double *dinv, int *bad);
 void launch_bj_apply(hipStream_t s, int nb, int nrows, const double *dinv, const double *x,
                      double *y);
-// partial-sum helpers shared by the Krylov kernels
-int vec_blocks(long nvec);
+// partial-sum helpers shared by the Krylov kernels: blocks of a vector
+// kernel, capped at 2048 (8 per CU) so a reduction has few partials
+__host__ __device__ inline int vec_blocks(long nvec) {
+    const long b = (nvec + kBlock - 1) / kBlock;
+    return (int)(b < 2048 ? (b > 0 ? b : 1) : 2048);
+}
 void launch_norm2(hipStream_t s, long nvec, const double *x, double *partials, double *out);
 void launch_normalize_precond(hipStream_t s, int nb, int nrows, const double *w,
                               const double *hptr, double *v, double *z, const double *dinv);
@@ -305,5 +313,124 @@ size_t amg_subcycle_lds(const AmgSub &P);          // dynamic LDS bytes of one l
 hipError_t amg_subcycle_allow_lds(size_t bytes);
 hipError_t dense_allow_lds();                      // LDS of the coarsest-level inverse
 void launch_amg_subcycle(hipStream_t s, const AmgSub &P);
+
+// ---- batched launches over the members of an ensemble ------------------------
+//
+// One launch covers many independent reservoirs (members).  Member m takes
+// the blocks [bstart[m], bstart[m+1]) of the grid; it works in the launch
+// when flags[m] has the launch's bit, and its blocks exit at once otherwise.
+// Inside, a member's blocks compute exactly what the member's own launch
+// computes (the kernel bodies take the block index and count of the
+// member's part instead of blockIdx.x / gridDim.x), so a member advanced in
+// a batch is bit for bit the member advanced alone.
+constexpr int kMaxLevels = 16;                      // AMG levels of one member
+enum { kOnNewton = 1, kAold = 2, kOnSolve = 4, kOnCycle = 8, kOnFinish = 16, kOnUpdate = 32,
+       kFirstCycle = 64 };
+
+struct Batch {
+    const int *bstart;      // [nm+1] first block of every member (device)
+    const int *flags;       // [nm] what every member takes part in (device)
+    int nm, bit;
+};
+
+// Everything one member's kernels read: its grid, fluid, wells and system,
+// and the device buffers of its context (all owned by the member's context).
+struct Member {
+    Grid g;
+    Phys f;
+    Wells wells;
+    Sys sys;
+    int n, nw, nb, nrows, m;
+    long nvec;
+    double ds_max, dp_max;
+    const double *pvref, *depth, *tx, *ty, *tz;
+    double *P, *Sw, *X, *pbhp;
+    int8_t *flag;
+    double *rec, *aold, *wmeas, *partials, *scal;
+    double *V, *Z, *w, *x, *b, *r, *t, *H, *tmp, *ydev;
+    int *reorth;
+    // CPR with the block-Jacobi ILU(0) second stage
+    IluTiles T;
+    double *lu;
+    int *ilu_bad;
+    int nlev;
+    AmgLevel lv[kMaxLevels];
+    const int *cfs_ptr[kMaxLevels], *cfs_idx[kMaxLevels];
+    const int *split0, *colsplit;
+    double *wq, *ap, *Mden, *Minv, *colk;
+    int *amg_bad;
+    const int *ops;         // the member's whole AMG cycle, as a phase list
+    int nops;
+    double *rbuf;           // residuals of a restriction (2*half of level 0)
+};
+
+// the two save slots of a member's state (step start, sub-step start)
+struct StateSlots {
+    double *P[2], *Sw[2], *X[2], *pbhp[2];
+    int8_t *flag[2];
+};
+
+// member m and its block view (b, nb) of this block of a batched launch;
+// false when the member does not take part
+__device__ inline bool batch_view(const Batch &B, int &m, int &b, int &nb) {
+    const int bx = blockIdx.x;
+    int lo = 0, hi = B.nm - 1;
+    while (lo < hi) {                   // the last member whose first block is <= bx
+        const int mid = (lo + hi + 1) >> 1;
+        if (B.bstart[mid] <= bx) lo = mid;
+        else hi = mid - 1;
+    }
+    m = lo;
+    b = bx - B.bstart[m];
+    nb = B.bstart[m + 1] - B.bstart[m];
+    return (B.flags[m] & B.bit) != 0;
+}
+
+// Launchers: (stream, member table, batch, total blocks = bstart[nm]).
+// The per-member block counts are those of the single launches; "one"
+// batches take one block per member.  Scalar slots (slot, s_norm, s_res)
+// are offsets into each member's scal array.
+int blocks_for_cells(int n);
+int spmv_blocks(int nb, int nrows);
+int dot_groups(int nv);
+int dense_lds_max();
+hipError_t batch_allow_lds();
+hipError_t ilu_batch_allow_lds(int nb, size_t bytes);
+void launchb_props(hipStream_t s, int nb, const Member *mem, Batch B, int total);
+void launchb_assemble(hipStream_t s, int nb, const Member *mem, Batch cells, int tcells,
+                      Batch wells, int twells, const double *dt);
+void launchb_conv(hipStream_t s, int nb, const Member *mem, Batch part, int tpart, Batch one,
+                  int tone, const double *dt, int slot);
+void launchb_newton_update(hipStream_t s, int nb, const Member *mem, Batch part, int tpart,
+                           Batch one, int tone, int slot);
+void launchb_state_copy(hipStream_t s, const Member *mem, const int *bstart, const int *flags,
+                        int nm, int total, const StateSlots *slots, int k, int save_bit,
+                        int restore_bit);
+void launchb_gather_scalars(hipStream_t s, const Member *mem, Batch one, int tone, int first,
+                            int count, double *packed, int ld);
+void launchb_scale_zero(hipStream_t s, const Member *mem, Batch B, int total);
+void launchb_norm_b(hipStream_t s, const Member *mem, Batch part, int tpart, Batch one, int tone,
+                    int slot);
+void launchb_spmv(hipStream_t s, int nb, const Member *mem, Batch B, int total, int j);
+void launchb_multidot(hipStream_t s, const Member *mem, Batch part, int tpart, Batch sum,
+                      int tsum, int j, bool second);
+void launchb_update_norm(hipStream_t s, const Member *mem, Batch part, int tpart, Batch one,
+                         int tone, int j, bool second);
+void launchb_hcols(hipStream_t s, const Member *mem, Batch one, int tone, int j, double *packed,
+                   int ld);
+void launchb_axpy(hipStream_t s, const Member *mem, Batch B, int total, const int *kcount,
+                  const double *ypacked, int ld);
+void launchb_residual(hipStream_t s, const Member *mem, Batch part, int tpart, Batch one,
+                      int tone, int slot);
+void launchb_cpr_restrict(hipStream_t s, int nb, const Member *mem, Batch B, int total, int j,
+                          int first_bit, int s_norm, int s_res);
+void launchb_amg_cycle(hipStream_t s, const Member *mem, Batch one, int tone);
+void launchb_amg_extract(hipStream_t s, int nb, const Member *mem, Batch B, int total);
+void launchb_amg_coarsen(hipStream_t s, const Member *mem, Batch B, int total, int level);
+void launchb_amg_coarsest(hipStream_t s, const Member *mem, Batch one, int tone, int nmax);
+void launchb_ilu_factor(hipStream_t s, int nb, const Member *mem, Batch B, int total, int threads,
+                        size_t lds);
+void launchb_ilu_solve(hipStream_t s, int nb, const Member *mem, Batch B, int total, int j,
+                       int threads, size_t lds);
 
 }  // namespace fim

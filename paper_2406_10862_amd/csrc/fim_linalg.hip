@@ -112,14 +112,9 @@ void launch_bj_apply(hipStream_t s, int nb, int nrows, const double *dinv, const
 // per-block partials of a reduction stay few; every thread walks the vector
 // with a grid stride.
 
-int vec_blocks(long nvec) {
-    long b = (nvec + kBlock - 1) / kBlock;
-    return (int)(b < 2048 ? (b > 0 ? b : 1) : 2048);
-}
 
 // out[0] = sum of the partials, out[1] = its square root (a norm finish)
-__global__ __launch_bounds__(kBlock) void k_finish_norm(int nparts, const double *partials,
-                                                        double *out) {
+__device__ __forceinline__ void finish_norm_body(int nparts, const double *partials, double *out) {
     const bool mx[1] = {false};
     double a[1];
     finish_partials<1>(nparts, mx, partials, a);
@@ -129,17 +124,26 @@ __global__ __launch_bounds__(kBlock) void k_finish_norm(int nparts, const double
     }
 }
 
+__global__ __launch_bounds__(kBlock) void k_finish_norm(int nparts, const double *partials,
+                                                        double *out) {
+    finish_norm_body(nparts, partials, out);
+}
+
 // out[0] = ||x||^2, out[1] = ||x||
-__global__ __launch_bounds__(kBlock) void k_norm2(long nvec, const double *__restrict__ x,
-                                                  double *partials) {
+__device__ __forceinline__ void norm2_body(int bid, int nblk, long nvec,
+                                           const double *__restrict__ x, double *partials) {
     double v[1] = {0.0};
     const bool mx[1] = {false};
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < nvec;
-         i += (long)gridDim.x * blockDim.x) {
+    for (long i = (long)bid * blockDim.x + threadIdx.x; i < nvec; i += (long)nblk * blockDim.x) {
         const double a = x[i];
         v[0] += a * a;
     }
-    block_partials<1>(v, mx, partials);
+    block_partials<1>(v, mx, partials, bid, nblk);
+}
+
+__global__ __launch_bounds__(kBlock) void k_norm2(long nvec, const double *__restrict__ x,
+                                                  double *partials) {
+    norm2_body(blockIdx.x, gridDim.x, nvec, x, partials);
 }
 
 void launch_norm2(hipStream_t s, long nvec, const double *x, double *partials, double *out) {
@@ -197,11 +201,12 @@ constexpr int kDotCols = 2048;
 // thread's first one and is dropped by a select), so even a group of one
 // vector keeps several loads in flight.
 template <class T, int NG>
-__device__ inline void multidot_group(long nvec, const T *__restrict__ V, const T *__restrict__ w,
-                                      bool self, double (&acc)[kDotGroup + 1]) {
+__device__ inline void multidot_group(int bx, int nbx, long nvec, const T *__restrict__ V,
+                                      const T *__restrict__ w, bool self,
+                                      double (&acc)[kDotGroup + 1]) {
     constexpr int U = NG <= 2 ? 4 : 2;
-    const long S = (long)gridDim.x * blockDim.x;
-    for (long e0 = (long)blockIdx.x * blockDim.x + threadIdx.x; e0 < nvec; e0 += U * S) {
+    const long S = (long)nbx * blockDim.x;
+    for (long e0 = (long)bx * blockDim.x + threadIdx.x; e0 < nvec; e0 += U * S) {
         double we[U], v[U][NG];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -222,28 +227,28 @@ __device__ inline void multidot_group(long nvec, const T *__restrict__ V, const 
 }
 
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_multidot_part(long nvec, int nv,
-                                                          const T *__restrict__ V,
-                                                          const T *__restrict__ w,
-                                                          double *__restrict__ partials,
-                                                          const int *gate) {
+__device__ __forceinline__ void multidot_part_body(int bx, int nbx, int by, long nvec, int nv,
+                                                   const T *__restrict__ V,
+                                                   const T *__restrict__ w,
+                                                   double *__restrict__ partials,
+                                                   const int *gate) {
     if (gate && *gate == 0) return;
-    const int g0 = blockIdx.y * kDotGroup;
+    const int g0 = by * kDotGroup;
     const int ng = min(kDotGroup, nv - g0);
     double acc[kDotGroup + 1];
 #pragma unroll
     for (int i = 0; i <= kDotGroup; ++i) acc[i] = 0.0;
-    const bool self = blockIdx.y == 0;            // the first group also forms <w, w>
+    const bool self = by == 0;                    // the first group also forms <w, w>
     const T *Vg = V + (size_t)g0 * nvec;
     switch (ng) {
-    case 1: multidot_group<T, 1>(nvec, Vg, w, self, acc); break;
-    case 2: multidot_group<T, 2>(nvec, Vg, w, self, acc); break;
-    case 3: multidot_group<T, 3>(nvec, Vg, w, self, acc); break;
-    case 4: multidot_group<T, 4>(nvec, Vg, w, self, acc); break;
-    case 5: multidot_group<T, 5>(nvec, Vg, w, self, acc); break;
-    case 6: multidot_group<T, 6>(nvec, Vg, w, self, acc); break;
-    case 7: multidot_group<T, 7>(nvec, Vg, w, self, acc); break;
-    default: multidot_group<T, kDotGroup>(nvec, Vg, w, self, acc); break;
+    case 1: multidot_group<T, 1>(bx, nbx, nvec, Vg, w, self, acc); break;
+    case 2: multidot_group<T, 2>(bx, nbx, nvec, Vg, w, self, acc); break;
+    case 3: multidot_group<T, 3>(bx, nbx, nvec, Vg, w, self, acc); break;
+    case 4: multidot_group<T, 4>(bx, nbx, nvec, Vg, w, self, acc); break;
+    case 5: multidot_group<T, 5>(bx, nbx, nvec, Vg, w, self, acc); break;
+    case 6: multidot_group<T, 6>(bx, nbx, nvec, Vg, w, self, acc); break;
+    case 7: multidot_group<T, 7>(bx, nbx, nvec, Vg, w, self, acc); break;
+    default: multidot_group<T, kDotGroup>(bx, nbx, nvec, Vg, w, self, acc); break;
     }
     __shared__ double sh[kDotGroup + 1][kWaves];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -263,15 +268,24 @@ __global__ __launch_bounds__(kBlock) void k_multidot_part(long nvec, int nv,
             double a = sh[i][0];
             for (int w2 = 1; w2 < kWaves; ++w2) a += sh[i][w2];
             const int slot = (i < kDotGroup) ? g0 + i : nv;
-            partials[(size_t)slot * gridDim.x + blockIdx.x] = a;
+            partials[(size_t)slot * nbx + bx] = a;
         }
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_multidot_sum(int ncols, const double *__restrict__ partials,
-                                                         double *__restrict__ dst, const int *gate) {
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_multidot_part(long nvec, int nv,
+                                                          const T *__restrict__ V,
+                                                          const T *__restrict__ w,
+                                                          double *__restrict__ partials,
+                                                          const int *gate) {
+    multidot_part_body<T>(blockIdx.x, gridDim.x, blockIdx.y, nvec, nv, V, w, partials, gate);
+}
+
+__device__ __forceinline__ void multidot_sum_body(int slot, int ncols,
+                                                  const double *__restrict__ partials,
+                                                  double *__restrict__ dst, const int *gate) {
     if (gate && *gate == 0) return;
-    const int slot = blockIdx.x;
     double a = 0.0;
     for (int b = threadIdx.x; b < ncols; b += blockDim.x) a += partials[(size_t)slot * ncols + b];
     __shared__ double sh[kWaves];
@@ -284,6 +298,11 @@ __global__ __launch_bounds__(kBlock) void k_multidot_sum(int ncols, const double
         for (int w2 = 1; w2 < kWaves; ++w2) t += sh[w2];
         dst[slot] = t;
     }
+}
+
+__global__ __launch_bounds__(kBlock) void k_multidot_sum(int ncols, const double *__restrict__ partials,
+                                                         double *__restrict__ dst, const int *gate) {
+    multidot_sum_body(blockIdx.x, ncols, partials, dst, gate);
 }
 
 template <class T>
@@ -315,18 +334,16 @@ void launch_multidot(hipStream_t s, long nvec, int nv, const float *V, const flo
 // DGKS-type test for severe cancellation).  Both are skipped when
 // *gate == 0.
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_update_norm(long nvec, int nv,
-                                                        const T *__restrict__ V,
-                                                        const double *coef, T *w,
-                                                        double *partials, const int *gate) {
+__device__ __forceinline__ void update_norm_body(int bid, int nblk, long nvec, int nv,
+                                                 const T *__restrict__ V, const double *coef,
+                                                 T *w, double *partials, const int *gate) {
     if (gate && *gate == 0) return;
     __shared__ double c[kMaxDots];
     for (int i = threadIdx.x; i <= nv; i += blockDim.x) c[i] = coef[i];
     __syncthreads();
     double v[1] = {0.0};
     const bool mx[1] = {false};
-    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < nvec;
-         e += (long)gridDim.x * blockDim.x) {
+    for (long e = (long)bid * blockDim.x + threadIdx.x; e < nvec; e += (long)nblk * blockDim.x) {
         double a = (double)w[e];
 #pragma unroll 8
         for (int i = 0; i < nv; ++i)
@@ -335,13 +352,20 @@ __global__ __launch_bounds__(kBlock) void k_update_norm(long nvec, int nv,
         w[e] = at;
         v[0] += (double)at * (double)at;
     }
-    block_partials<1>(v, mx, partials);
+    block_partials<1>(v, mx, partials, bid, nblk);
 }
 
-__global__ __launch_bounds__(kBlock) void k_update_finish(int nparts, int nv, const double *coef,
-                                                          const double *partials, double *hnext,
-                                                          const int *gate, int *reorth,
-                                                          double *hacc) {
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_update_norm(long nvec, int nv,
+                                                        const T *__restrict__ V,
+                                                        const double *coef, T *w,
+                                                        double *partials, const int *gate) {
+    update_norm_body<T>(blockIdx.x, gridDim.x, nvec, nv, V, coef, w, partials, gate);
+}
+
+__device__ __forceinline__ void update_finish_body(int nparts, int nv, const double *coef,
+                                                   const double *partials, double *hnext,
+                                                   const int *gate, int *reorth, double *hacc) {
     if (gate && *gate == 0) return;
     const bool mx[1] = {false};
     double a[1];
@@ -352,6 +376,13 @@ __global__ __launch_bounds__(kBlock) void k_update_finish(int nparts, int nv, co
         if (reorth) *reorth = (a[0] < 1e-2 * coef[nv]) ? 1 : 0;
         *hnext = sqrt(a[0]);
     }
+}
+
+__global__ __launch_bounds__(kBlock) void k_update_finish(int nparts, int nv, const double *coef,
+                                                          const double *partials, double *hnext,
+                                                          const int *gate, int *reorth,
+                                                          double *hacc) {
+    update_finish_body(nparts, nv, coef, partials, hnext, gate, reorth, hacc);
 }
 
 template <class T>
@@ -378,18 +409,24 @@ void launch_update_norm(hipStream_t s, long nvec, int nv, const float *V, const 
 }
 
 // r = b - Ax; out[0] = ||r||^2, out[1] = ||r||
-__global__ __launch_bounds__(kBlock) void k_residual(long nvec, const double *__restrict__ b,
-                                                     const double *__restrict__ Ax,
-                                                     double *__restrict__ r, double *partials) {
+__device__ __forceinline__ void residual_body(int bid, int nblk, long nvec,
+                                              const double *__restrict__ b,
+                                              const double *__restrict__ Ax,
+                                              double *__restrict__ r, double *partials) {
     double v[1] = {0.0};
     const bool mx[1] = {false};
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < nvec;
-         i += (long)gridDim.x * blockDim.x) {
+    for (long i = (long)bid * blockDim.x + threadIdx.x; i < nvec; i += (long)nblk * blockDim.x) {
         const double a = b[i] - Ax[i];
         r[i] = a;
         v[0] += a * a;
     }
-    block_partials<1>(v, mx, partials);
+    block_partials<1>(v, mx, partials, bid, nblk);
+}
+
+__global__ __launch_bounds__(kBlock) void k_residual(long nvec, const double *__restrict__ b,
+                                                     const double *__restrict__ Ax,
+                                                     double *__restrict__ r, double *partials) {
+    residual_body(blockIdx.x, gridDim.x, nvec, b, Ax, r, partials);
 }
 
 void launch_residual(hipStream_t s, long nvec, const double *b, const double *Ax, double *r,
@@ -402,19 +439,26 @@ void launch_residual(hipStream_t s, long nvec, const double *b, const double *Ax
 // x += sum_{i<k} y_i Z_i (the flexible-GMRES update with stored
 // preconditioned vectors)
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_axpy_multi(long nvec, int k,
-                                                       const T *__restrict__ Z,
-                                                       const double *__restrict__ y,
-                                                       double *__restrict__ x) {
+__device__ __forceinline__ void axpy_multi_body(int bid, int nblk, long nvec, int k,
+                                                const T *__restrict__ Z,
+                                                const double *__restrict__ y,
+                                                double *__restrict__ x) {
     __shared__ double ys[kMaxRestart + 1];
     for (int i = threadIdx.x; i < k; i += blockDim.x) ys[i] = y[i];
     __syncthreads();
-    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < nvec;
-         e += (long)gridDim.x * blockDim.x) {
+    for (long e = (long)bid * blockDim.x + threadIdx.x; e < nvec; e += (long)nblk * blockDim.x) {
         double a = x[e];
         for (int i = 0; i < k; ++i) a += ys[i] * (double)Z[(size_t)i * nvec + e];
         x[e] = a;
     }
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_axpy_multi(long nvec, int k,
+                                                       const T *__restrict__ Z,
+                                                       const double *__restrict__ y,
+                                                       double *__restrict__ x) {
+    axpy_multi_body<T>(blockIdx.x, gridDim.x, nvec, k, Z, y, x);
 }
 
 void launch_axpy_multi(hipStream_t s, long nvec, int k, const double *Z, const double *y,
@@ -453,17 +497,163 @@ void launch_to_double(hipStream_t s, long n, const float *x, double *y) {
     hipLaunchKernelGGL(k_to_double, dim3(vec_blocks(n)), dim3(kBlock), 0, s, n, x, y);
 }
 
+__device__ __forceinline__ void scale_copy_body(int bid, int nblk, long nvec,
+                                                const double *__restrict__ x, double a,
+                                                double *__restrict__ y) {
+    for (long i = (long)bid * blockDim.x + threadIdx.x; i < nvec; i += (long)nblk * blockDim.x)
+        y[i] = x ? a * x[i] : a;
+}
+
 __global__ __launch_bounds__(kBlock) void k_scale_copy(long nvec, const double *__restrict__ x,
                                                        double a, double *__restrict__ y) {
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < nvec;
-         i += (long)gridDim.x * blockDim.x)
-        y[i] = x ? a * x[i] : a;
+    scale_copy_body(blockIdx.x, gridDim.x, nvec, x, a, y);
 }
 
 // y = a*x, or y = a everywhere when x is null (a fill kernel, so nothing here
 // records a memset node into a captured graph)
 void launch_scale_copy(hipStream_t s, long nvec, const double *x, double a, double *y) {
     hipLaunchKernelGGL(k_scale_copy, dim3(vec_blocks(nvec)), dim3(kBlock), 0, s, nvec, x, a, y);
+}
+
+// ---------------------------------------------------------------------------
+// batched launches over the members of an ensemble (FP64 Krylov vectors of
+// each member's context; the Hessenberg column of step j at H + j*LD)
+
+constexpr int kLD = kMaxRestart + 2;
+
+int dot_groups(int nv) { return (nv + kDotGroup - 1) / kDotGroup > 0 ? (nv + kDotGroup - 1) / kDotGroup : 1; }
+
+__global__ __launch_bounds__(kBlock) void kb_scale_zero(const Member *__restrict__ mem, Batch B) {
+    int m, b, nb;
+    if (!batch_view(B, m, b, nb)) return;
+    const Member &M = mem[m];
+    scale_copy_body(b, nb, M.nvec, nullptr, 0.0, M.x);
+}
+
+__global__ __launch_bounds__(kBlock) void kb_norm_b(const Member *__restrict__ mem, Batch B) {
+    int m, b, nb;
+    if (!batch_view(B, m, b, nb)) return;
+    const Member &M = mem[m];
+    norm2_body(b, nb, M.nvec, M.sys.R, M.partials);
+}
+
+__global__ __launch_bounds__(kBlock) void kb_finish_norm(const Member *__restrict__ mem, Batch B,
+                                                         int slot) {
+    int m, b, nb;
+    if (!batch_view(B, m, b, nb)) return;
+    const Member &M = mem[m];
+    finish_norm_body(vec_blocks(M.nvec), M.partials, M.scal + slot);
+}
+
+__global__ __launch_bounds__(kBlock) void kb_multidot_part(const Member *__restrict__ mem, Batch B,
+                                                           int j, int second) {
+    int m, b, nb;
+    if (!batch_view(B, m, b, nb)) return;
+    const Member &M = mem[m];
+    const int cols = vec_blocks(M.nvec);
+    multidot_part_body<double>(b % cols, cols, b / cols, M.nvec, j + 1, M.V, M.w, M.partials,
+                               second ? M.reorth : nullptr);
+}
+
+__global__ __launch_bounds__(kBlock) void kb_multidot_sum(const Member *__restrict__ mem, Batch B,
+                                                          int j, int second) {
+    int m, b, nb;
+    if (!batch_view(B, m, b, nb)) return;
+    const Member &M = mem[m];
+    multidot_sum_body(b, vec_blocks(M.nvec), M.partials, second ? M.tmp : M.H + (size_t)j * kLD,
+                      second ? M.reorth : nullptr);
+}
+
+__global__ __launch_bounds__(kBlock) void kb_update_norm(const Member *__restrict__ mem, Batch B,
+                                                         int j, int second) {
+    int m, b, nb;
+    if (!batch_view(B, m, b, nb)) return;
+    const Member &M = mem[m];
+    const double *col = M.H + (size_t)j * kLD;
+    update_norm_body<double>(b, nb, M.nvec, j + 1, M.V, second ? M.tmp : col, M.w, M.partials,
+                             second ? M.reorth : nullptr);
+}
+
+__global__ __launch_bounds__(kBlock) void kb_update_finish(const Member *__restrict__ mem, Batch B,
+                                                           int j, int second) {
+    int m, b, nb;
+    if (!batch_view(B, m, b, nb)) return;
+    const Member &M = mem[m];
+    double *col = M.H + (size_t)j * kLD;
+    if (second)
+        update_finish_body(vec_blocks(M.nvec), j + 1, M.tmp, M.partials, col + j + 1, M.reorth,
+                           nullptr, col);
+    else
+        update_finish_body(vec_blocks(M.nvec), j + 1, col, M.partials, col + j + 1, nullptr,
+                           M.reorth, nullptr);
+}
+
+__global__ void kb_hcols(const Member *__restrict__ mem, Batch B, int j, double *__restrict__ packed,
+                         int ld) {
+    int m, b, nb;
+    if (!batch_view(B, m, b, nb)) return;
+    const Member &M = mem[m];
+    for (int i = threadIdx.x; i < j + 2; i += blockDim.x)
+        packed[(size_t)m * ld + i] = M.H[(size_t)j * kLD + i];
+}
+
+__global__ __launch_bounds__(kBlock) void kb_axpy(const Member *__restrict__ mem, Batch B,
+                                                  const int *__restrict__ kcount,
+                                                  const double *__restrict__ ypacked, int ld) {
+    int m, b, nb;
+    if (!batch_view(B, m, b, nb)) return;
+    const Member &M = mem[m];
+    axpy_multi_body<double>(b, nb, M.nvec, kcount[m], M.Z, ypacked + (size_t)m * ld, M.x);
+}
+
+__global__ __launch_bounds__(kBlock) void kb_residual(const Member *__restrict__ mem, Batch B) {
+    int m, b, nb;
+    if (!batch_view(B, m, b, nb)) return;
+    const Member &M = mem[m];
+    residual_body(b, nb, M.nvec, M.sys.R, M.t, M.r, M.partials);
+}
+
+void launchb_scale_zero(hipStream_t s, const Member *mem, Batch B, int total) {
+    if (total > 0) hipLaunchKernelGGL(kb_scale_zero, dim3(total), dim3(kBlock), 0, s, mem, B);
+}
+
+void launchb_norm_b(hipStream_t s, const Member *mem, Batch part, int tpart, Batch one, int tone,
+                    int slot) {
+    if (tpart <= 0) return;
+    hipLaunchKernelGGL(kb_norm_b, dim3(tpart), dim3(kBlock), 0, s, mem, part);
+    hipLaunchKernelGGL(kb_finish_norm, dim3(tone), dim3(kBlock), 0, s, mem, one, slot);
+}
+
+void launchb_multidot(hipStream_t s, const Member *mem, Batch part, int tpart, Batch sum,
+                      int tsum, int j, bool second) {
+    if (tpart <= 0) return;
+    hipLaunchKernelGGL(kb_multidot_part, dim3(tpart), dim3(kBlock), 0, s, mem, part, j, (int)second);
+    hipLaunchKernelGGL(kb_multidot_sum, dim3(tsum), dim3(kBlock), 0, s, mem, sum, j, (int)second);
+}
+
+void launchb_update_norm(hipStream_t s, const Member *mem, Batch part, int tpart, Batch one,
+                         int tone, int j, bool second) {
+    if (tpart <= 0) return;
+    hipLaunchKernelGGL(kb_update_norm, dim3(tpart), dim3(kBlock), 0, s, mem, part, j, (int)second);
+    hipLaunchKernelGGL(kb_update_finish, dim3(tone), dim3(kBlock), 0, s, mem, one, j, (int)second);
+}
+
+void launchb_hcols(hipStream_t s, const Member *mem, Batch one, int tone, int j, double *packed,
+                   int ld) {
+    if (tone > 0) hipLaunchKernelGGL(kb_hcols, dim3(tone), dim3(64), 0, s, mem, one, j, packed, ld);
+}
+
+void launchb_axpy(hipStream_t s, const Member *mem, Batch B, int total, const int *kcount,
+                  const double *ypacked, int ld) {
+    if (total > 0)
+        hipLaunchKernelGGL(kb_axpy, dim3(total), dim3(kBlock), 0, s, mem, B, kcount, ypacked, ld);
+}
+
+void launchb_residual(hipStream_t s, const Member *mem, Batch part, int tpart, Batch one, int tone,
+                      int slot) {
+    if (tpart <= 0) return;
+    hipLaunchKernelGGL(kb_residual, dim3(tpart), dim3(kBlock), 0, s, mem, part);
+    hipLaunchKernelGGL(kb_finish_norm, dim3(tone), dim3(kBlock), 0, s, mem, one, slot);
 }
 
 }  // namespace fim

@@ -256,17 +256,17 @@ __device__ void cell_props(const Phys &f, const TabL &t, double pvref, double P,
 }
 
 template <int NB>
-__global__ __launch_bounds__(kBlock) void k_props(Phys f, int n, const double *__restrict__ pvref,
-                                                  const double *__restrict__ P,
-                                                  const double *__restrict__ Sw,
-                                                  const double *__restrict__ X,
-                                                  const int8_t *__restrict__ flag,
-                                                  double *__restrict__ rec,
-                                                  double *__restrict__ aold) {
+__device__ __forceinline__ void props_body(int bid, const Phys &f, int n,
+                                           const double *__restrict__ pvref,
+                                           const double *__restrict__ P,
+                                           const double *__restrict__ Sw,
+                                           const double *__restrict__ X,
+                                           const int8_t *__restrict__ flag,
+                                           double *__restrict__ rec, double *__restrict__ aold) {
     __shared__ double sm[6 * kMaxTableRows];
     TabL t;
     stage_table(f, sm, t);
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = bid * blockDim.x + threadIdx.x;
     if (c >= n) return;
     using RI = Rec<NB>;
     double r[RI::NREC];
@@ -276,6 +276,17 @@ __global__ __launch_bounds__(kBlock) void k_props(Phys f, int n, const double *_
     if (aold)
 #pragma unroll
         for (int i = 0; i < NB; ++i) aold[(size_t)i * n + c] = r[RI::ACC + i * RI::G];
+}
+
+template <int NB>
+__global__ __launch_bounds__(kBlock) void k_props(Phys f, int n, const double *__restrict__ pvref,
+                                                  const double *__restrict__ P,
+                                                  const double *__restrict__ Sw,
+                                                  const double *__restrict__ X,
+                                                  const int8_t *__restrict__ flag,
+                                                  double *__restrict__ rec,
+                                                  double *__restrict__ aold) {
+    props_body<NB>(blockIdx.x, f, n, pvref, P, Sw, X, flag, rec, aold);
 }
 
 // ---------------------------------------------------------------------------
@@ -416,13 +427,13 @@ __device__ inline void perf_rate(int kind, double wi, double P, double pbhp,
 }
 
 template <int NB>
-__global__ __launch_bounds__(kBlock) void k_assemble_cells(
-    Grid g, Wells w, Sys sys, const double *__restrict__ depth, const double *__restrict__ tx,
-    const double *__restrict__ ty, const double *__restrict__ tz, const double *__restrict__ P,
-    const double *__restrict__ pbhp, const double *__restrict__ rec,
-    const double *__restrict__ aold, double dt) {
+__device__ __forceinline__ void assemble_cells_body(
+    int bid, const Grid &g, const Wells &w, const Sys &sys, const double *__restrict__ depth,
+    const double *__restrict__ tx, const double *__restrict__ ty, const double *__restrict__ tz,
+    const double *__restrict__ P, const double *__restrict__ pbhp,
+    const double *__restrict__ rec, const double *__restrict__ aold, double dt) {
     using RI = Rec<NB>;
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = bid * blockDim.x + threadIdx.x;
     const int n = g.n;
     if (c >= n) return;
     const int nx = g.nx, nxy = g.nx * g.ny;
@@ -501,16 +512,25 @@ __global__ __launch_bounds__(kBlock) void k_assemble_cells(
     for (int e = 0; e < NB; ++e) sys.R[(size_t)c * NB + e] = R[e];
 }
 
+template <int NB>
+__global__ __launch_bounds__(kBlock) void k_assemble_cells(
+    Grid g, Wells w, Sys sys, const double *__restrict__ depth, const double *__restrict__ tx,
+    const double *__restrict__ ty, const double *__restrict__ tz, const double *__restrict__ P,
+    const double *__restrict__ pbhp, const double *__restrict__ rec,
+    const double *__restrict__ aold, double dt) {
+    assemble_cells_body<NB>(blockIdx.x, g, w, sys, depth, tx, ty, tz, P, pbhp, rec, aold, dt);
+}
+
 // Well rows: one wave per well.  Rate rows sum the injected component over
 // the perforations; BHP rows pin the bottom-hole pressure.  Slots >= 1 of a
 // well row are identity rows.  wmeas[w] = |R_w| / |dR_w/dPbhp| (psi).
 template <int NB>
-__global__ __launch_bounds__(64) void k_assemble_wells(Wells w, Sys sys, int n,
-                                                       const double *__restrict__ P,
-                                                       const double *__restrict__ pbhp,
-                                                       const double *__restrict__ rec,
-                                                       double *__restrict__ wmeas) {
-    const int wl = blockIdx.x, lane = threadIdx.x;
+__device__ __forceinline__ void assemble_wells_body(int wl, const Wells &w, const Sys &sys, int n,
+                                                    const double *__restrict__ P,
+                                                    const double *__restrict__ pbhp,
+                                                    const double *__restrict__ rec,
+                                                    double *__restrict__ wmeas) {
+    const int lane = threadIdx.x;
     const int row = n + wl, base = sys.rowptr[row];
     const int p0 = w.wps[wl], np = w.wps[wl + 1] - p0;
     const bool rate = w.ctrl[wl] == kRate;
@@ -558,15 +578,25 @@ __global__ __launch_bounds__(64) void k_assemble_wells(Wells w, Sys sys, int n,
     }
 }
 
+template <int NB>
+__global__ __launch_bounds__(64) void k_assemble_wells(Wells w, Sys sys, int n,
+                                                       const double *__restrict__ P,
+                                                       const double *__restrict__ pbhp,
+                                                       const double *__restrict__ rec,
+                                                       double *__restrict__ wmeas) {
+    assemble_wells_body<NB>(blockIdx.x, w, sys, n, P, pbhp, rec, wmeas);
+}
+
 // ---------------------------------------------------------------------------
 // convergence measures: out = [max_c dt|R_ic|/(PV b_i)], [sum_c R_ic],
 // [sum_c PV b_i], max well measure
 
 template <int NB>
-__global__ __launch_bounds__(kBlock) void k_conv(int n, int nw, const double *__restrict__ rec,
-                                                 const double *__restrict__ R,
-                                                 const double *__restrict__ wmeas, double dt,
-                                                 double *partials) {
+__device__ __forceinline__ void conv_body(int bid, int nblk, int n, int nw,
+                                          const double *__restrict__ rec,
+                                          const double *__restrict__ R,
+                                          const double *__restrict__ wmeas, double dt,
+                                          double *partials) {
     using RI = Rec<NB>;
     constexpr int K = 3 * NB + 1;
     double v[K];
@@ -576,7 +606,7 @@ __global__ __launch_bounds__(kBlock) void k_conv(int n, int nw, const double *__
         v[k] = 0.0;
         mx[k] = (k < NB) || (k == 3 * NB);
     }
-    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
+    for (int c = bid * blockDim.x + threadIdx.x; c < n; c += nblk * blockDim.x) {
         const double pv = rec[(size_t)RI::PV * n + c];
 #pragma unroll
         for (int e = 0; e < NB; ++e) {
@@ -587,14 +617,21 @@ __global__ __launch_bounds__(kBlock) void k_conv(int n, int nw, const double *__
             v[2 * NB + e] += scale;
         }
     }
-    if (blockIdx.x == 0)
+    if (bid == 0)
         for (int wl = threadIdx.x; wl < nw; wl += blockDim.x) v[3 * NB] = rop(v[3 * NB], wmeas[wl], true);
-    block_partials<K>(v, mx, partials);
+    block_partials<K>(v, mx, partials, bid, nblk);
 }
 
 template <int NB>
-__global__ __launch_bounds__(kBlock) void k_conv_finish(int nparts, const double *partials,
-                                                        double *out) {
+__global__ __launch_bounds__(kBlock) void k_conv(int n, int nw, const double *__restrict__ rec,
+                                                 const double *__restrict__ R,
+                                                 const double *__restrict__ wmeas, double dt,
+                                                 double *partials) {
+    conv_body<NB>(blockIdx.x, gridDim.x, n, nw, rec, R, wmeas, dt, partials);
+}
+
+template <int NB>
+__device__ __forceinline__ void conv_finish_body(int nparts, const double *partials, double *out) {
     constexpr int K = 3 * NB + 1;
     bool mx[K];
 #pragma unroll
@@ -606,26 +643,30 @@ __global__ __launch_bounds__(kBlock) void k_conv_finish(int nparts, const double
         for (int k = 0; k < K; ++k) out[k] = a[k];
 }
 
+template <int NB>
+__global__ __launch_bounds__(kBlock) void k_conv_finish(int nparts, const double *partials,
+                                                        double *out) {
+    conv_finish_body<NB>(nparts, partials, out);
+}
+
 // ---------------------------------------------------------------------------
 // Newton update: delta = -y; per-cell saturation chop and pressure clip,
 // three-phase variable switching; out = [max|dP| (cells and wells), max|dS|,
 // largest distance of a saturation of the new iterate outside [0, 1]]
 
 template <int NB>
-__global__ __launch_bounds__(kBlock) void k_newton_update(Phys f, int n, int nw,
-                                                          const double *__restrict__ y,
-                                                          double ds_max, double dp_max,
-                                                          double *__restrict__ P,
-                                                          double *__restrict__ Sw,
-                                                          double *__restrict__ X,
-                                                          int8_t *__restrict__ flag,
-                                                          double *partials) {
+__device__ __forceinline__ void newton_update_body(int bid, int nblk, const Phys &f, int n,
+                                                   const double *__restrict__ y, double ds_max,
+                                                   double dp_max, double *__restrict__ P,
+                                                   double *__restrict__ Sw,
+                                                   double *__restrict__ X,
+                                                   int8_t *__restrict__ flag, double *partials) {
     __shared__ double sm[6 * kMaxTableRows];
     TabL t;
     stage_table(f, sm, t);
     double v[3] = {0.0, 0.0, 0.0};
     const bool mx[3] = {true, true, true};
-    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
+    for (int c = bid * blockDim.x + threadIdx.x; c < n; c += nblk * blockDim.x) {
         double dP = -y[(size_t)c * NB];
         dP = fmin(fmax(dP, -dp_max), dp_max);
         double dS = -y[(size_t)c * NB + 1];
@@ -665,16 +706,30 @@ __global__ __launch_bounds__(kBlock) void k_newton_update(Phys f, int n, int nw,
                    true);
         if (dP != dP || dS != dS || dX != dX) v[0] = NAN;
     }
-    block_partials<3>(v, mx, partials);
+    block_partials<3>(v, mx, partials, bid, nblk);
+}
+
+template <int NB>
+__global__ __launch_bounds__(kBlock) void k_newton_update(Phys f, int n, int nw,
+                                                          const double *__restrict__ y,
+                                                          double ds_max, double dp_max,
+                                                          double *__restrict__ P,
+                                                          double *__restrict__ Sw,
+                                                          double *__restrict__ X,
+                                                          int8_t *__restrict__ flag,
+                                                          double *partials) {
+    (void)nw;
+    newton_update_body<NB>(blockIdx.x, gridDim.x, f, n, y, ds_max, dp_max, P, Sw, X, flag,
+                           partials);
 }
 
 // One block: combines the cell maxima and updates the well pressures (the
 // BHP unknowns follow the cells in y), clipped like the cell pressures.
 template <int NB>
-__global__ __launch_bounds__(kBlock) void k_newton_finish(int nparts, int n, int nw,
-                                                          const double *__restrict__ y,
-                                                          double dp_max, double *pbhp,
-                                                          const double *partials, double *out) {
+__device__ __forceinline__ void newton_finish_body(int nparts, int n, int nw,
+                                                   const double *__restrict__ y, double dp_max,
+                                                   double *pbhp, const double *partials,
+                                                   double *out) {
     const bool mx[3] = {true, true, true};
     double a[3];
     finish_partials<3>(nparts, mx, partials, a);
@@ -691,6 +746,14 @@ __global__ __launch_bounds__(kBlock) void k_newton_finish(int nparts, int n, int
         out[1] = a[1];
         out[2] = a[2];
     }
+}
+
+template <int NB>
+__global__ __launch_bounds__(kBlock) void k_newton_finish(int nparts, int n, int nw,
+                                                          const double *__restrict__ y,
+                                                          double dp_max, double *pbhp,
+                                                          const double *partials, double *out) {
+    newton_finish_body<NB>(nparts, n, nw, y, dp_max, pbhp, partials, out);
 }
 
 // Surface rates per well: q[w*3 + i], production positive.
@@ -878,8 +941,6 @@ __global__ __launch_bounds__(kBlock) void k_adj_grad(
 // launchers
 
 static inline int blocks_for(long n, int bs) { return (int)((n + bs - 1) / bs); }
-int conv_blocks(int n) { return min(blocks_for(n, kBlock), 2048); }
-int update_blocks(int n) { return min(blocks_for(n, kBlock), 2048); }
 
 void launch_static(hipStream_t s, Grid g, const double *dx, const double *dy, const double *dz,
                    double top, const double *kx, const double *ky, const double *kz,
@@ -1003,6 +1064,178 @@ void launch_adj_grad(hipStream_t s, int nb, Grid g, Wells w, const double *depth
     else
         hipLaunchKernelGGL(k_adj_grad<3>, grid, block, 0, s, g, w, depth, tx, ty, tz, kx, ky, kz,
                            dx, dy, dz, P, pbhp, rec, wi_dk, lam, objp, grad);
+}
+
+// ---------------------------------------------------------------------------
+// batched launches over the members of an ensemble (each member's blocks run
+// the bodies above on the member's own buffers)
+
+template <int NB>
+__global__ __launch_bounds__(kBlock) void kb_props(const Member *__restrict__ mem, Batch B) {
+    int m, b, nb;
+    if (!batch_view(B, m, b, nb)) return;
+    const Member &M = mem[m];
+    const bool ao = (B.flags[m] & kAold) != 0;
+    props_body<NB>(b, M.f, M.n, M.pvref, M.P, M.Sw, M.X, M.flag, M.rec, ao ? M.aold : nullptr);
+}
+
+template <int NB>
+__global__ __launch_bounds__(kBlock) void kb_assemble_cells(const Member *__restrict__ mem, Batch B,
+                                                            const double *__restrict__ dt) {
+    int m, b, nb;
+    if (!batch_view(B, m, b, nb)) return;
+    const Member &M = mem[m];
+    assemble_cells_body<NB>(b, M.g, M.wells, M.sys, M.depth, M.tx, M.ty, M.tz, M.P, M.pbhp, M.rec,
+                            M.aold, dt[m]);
+}
+
+template <int NB>
+__global__ __launch_bounds__(64) void kb_assemble_wells(const Member *__restrict__ mem, Batch B) {
+    int m, b, nb;
+    if (!batch_view(B, m, b, nb)) return;
+    const Member &M = mem[m];
+    assemble_wells_body<NB>(b, M.wells, M.sys, M.n, M.P, M.pbhp, M.rec, M.wmeas);
+}
+
+template <int NB>
+__global__ __launch_bounds__(kBlock) void kb_conv(const Member *__restrict__ mem, Batch B,
+                                                  const double *__restrict__ dt) {
+    int m, b, nb;
+    if (!batch_view(B, m, b, nb)) return;
+    const Member &M = mem[m];
+    conv_body<NB>(b, nb, M.n, M.nw, M.rec, M.sys.R, M.wmeas, dt[m], M.partials);
+}
+
+template <int NB>
+__global__ __launch_bounds__(kBlock) void kb_conv_finish(const Member *__restrict__ mem, Batch B,
+                                                         int slot) {
+    int m, b, nb;
+    if (!batch_view(B, m, b, nb)) return;
+    const Member &M = mem[m];
+    conv_finish_body<NB>(conv_blocks(M.n), M.partials, M.scal + slot);
+}
+
+template <int NB>
+__global__ __launch_bounds__(kBlock) void kb_newton_update(const Member *__restrict__ mem, Batch B) {
+    int m, b, nb;
+    if (!batch_view(B, m, b, nb)) return;
+    const Member &M = mem[m];
+    newton_update_body<NB>(b, nb, M.f, M.n, M.x, M.ds_max, M.dp_max, M.P, M.Sw, M.X, M.flag,
+                           M.partials);
+}
+
+template <int NB>
+__global__ __launch_bounds__(kBlock) void kb_newton_finish(const Member *__restrict__ mem, Batch B,
+                                                           int slot) {
+    int m, b, nb;
+    if (!batch_view(B, m, b, nb)) return;
+    const Member &M = mem[m];
+    newton_finish_body<NB>(update_blocks(M.n), M.n, M.nw, M.x, M.dp_max, M.pbhp, M.partials,
+                           M.scal + slot);
+}
+
+// Copies of the state (P, Sw, X, flag over the cells, the BHP over the
+// wells) between the live arrays and the save slots: to slot k when
+// flags[m] has save_bit, back from slot k when it has restore_bit.
+__global__ __launch_bounds__(kBlock) void kb_state_copy(const Member *__restrict__ mem,
+                                                        const int *__restrict__ bstart,
+                                                        const int *__restrict__ flags, int nm,
+                                                        const StateSlots *__restrict__ slots,
+                                                        int k, int save_bit, int restore_bit) {
+    Batch B{bstart, flags, nm, save_bit | restore_bit};
+    int m, b, nb;
+    if (!batch_view(B, m, b, nb)) return;
+    const Member &M = mem[m];
+    const StateSlots &S = slots[m];
+    const bool save = (flags[m] & save_bit) != 0;
+    const int c = b * blockDim.x + threadIdx.x;
+    if (c < M.n) {
+        if (save) {
+            S.P[k][c] = M.P[c];
+            S.Sw[k][c] = M.Sw[c];
+            S.X[k][c] = M.X[c];
+            S.flag[k][c] = M.flag[c];
+        } else {
+            M.P[c] = S.P[k][c];
+            M.Sw[c] = S.Sw[k][c];
+            M.X[c] = S.X[k][c];
+            M.flag[c] = S.flag[k][c];
+        }
+    }
+    if (c < M.nw) {
+        if (save) S.pbhp[k][c] = M.pbhp[c];
+        else M.pbhp[c] = S.pbhp[k][c];
+    }
+}
+
+// scal[first .. first + count) of every member that takes part, to
+// packed[m * ld + e]
+__global__ void kb_gather_scalars(const Member *__restrict__ mem, Batch B, int first, int count,
+                                  double *__restrict__ packed, int ld) {
+    int m, b, nb;
+    if (!batch_view(B, m, b, nb)) return;
+    const Member &M = mem[m];
+    for (int e = threadIdx.x; e < count; e += blockDim.x) packed[(size_t)m * ld + e] = M.scal[first + e];
+}
+
+int blocks_for_cells(int n) { return blocks_for(n, kBlock); }
+
+void launchb_props(hipStream_t s, int nb, const Member *mem, Batch B, int total) {
+    if (total <= 0) return;
+    if (nb == 2) hipLaunchKernelGGL(kb_props<2>, dim3(total), dim3(kBlock), 0, s, mem, B);
+    else hipLaunchKernelGGL(kb_props<3>, dim3(total), dim3(kBlock), 0, s, mem, B);
+}
+
+void launchb_assemble(hipStream_t s, int nb, const Member *mem, Batch cells, int tcells,
+                      Batch wells, int twells, const double *dt) {
+    if (nb == 2) {
+        if (tcells > 0)
+            hipLaunchKernelGGL(kb_assemble_cells<2>, dim3(tcells), dim3(kBlock), 0, s, mem, cells, dt);
+        if (twells > 0)
+            hipLaunchKernelGGL(kb_assemble_wells<2>, dim3(twells), dim3(64), 0, s, mem, wells);
+    } else {
+        if (tcells > 0)
+            hipLaunchKernelGGL(kb_assemble_cells<3>, dim3(tcells), dim3(kBlock), 0, s, mem, cells, dt);
+        if (twells > 0)
+            hipLaunchKernelGGL(kb_assemble_wells<3>, dim3(twells), dim3(64), 0, s, mem, wells);
+    }
+}
+
+void launchb_conv(hipStream_t s, int nb, const Member *mem, Batch part, int tpart, Batch one,
+                  int tone, const double *dt, int slot) {
+    if (nb == 2) {
+        hipLaunchKernelGGL(kb_conv<2>, dim3(tpart), dim3(kBlock), 0, s, mem, part, dt);
+        hipLaunchKernelGGL(kb_conv_finish<2>, dim3(tone), dim3(kBlock), 0, s, mem, one, slot);
+    } else {
+        hipLaunchKernelGGL(kb_conv<3>, dim3(tpart), dim3(kBlock), 0, s, mem, part, dt);
+        hipLaunchKernelGGL(kb_conv_finish<3>, dim3(tone), dim3(kBlock), 0, s, mem, one, slot);
+    }
+}
+
+void launchb_newton_update(hipStream_t s, int nb, const Member *mem, Batch part, int tpart,
+                           Batch one, int tone, int slot) {
+    if (nb == 2) {
+        hipLaunchKernelGGL(kb_newton_update<2>, dim3(tpart), dim3(kBlock), 0, s, mem, part);
+        hipLaunchKernelGGL(kb_newton_finish<2>, dim3(tone), dim3(kBlock), 0, s, mem, one, slot);
+    } else {
+        hipLaunchKernelGGL(kb_newton_update<3>, dim3(tpart), dim3(kBlock), 0, s, mem, part);
+        hipLaunchKernelGGL(kb_newton_finish<3>, dim3(tone), dim3(kBlock), 0, s, mem, one, slot);
+    }
+}
+
+void launchb_state_copy(hipStream_t s, const Member *mem, const int *bstart, const int *flags,
+                        int nm, int total, const StateSlots *slots, int k, int save_bit,
+                        int restore_bit) {
+    if (total > 0)
+        hipLaunchKernelGGL(kb_state_copy, dim3(total), dim3(kBlock), 0, s, mem, bstart, flags, nm,
+                           slots, k, save_bit, restore_bit);
+}
+
+void launchb_gather_scalars(hipStream_t s, const Member *mem, Batch one, int tone, int first,
+                            int count, double *packed, int ld) {
+    if (tone > 0)
+        hipLaunchKernelGGL(kb_gather_scalars, dim3(tone), dim3(64), 0, s, mem, one, first, count,
+                           packed, ld);
 }
 
 }  // namespace fim

@@ -49,12 +49,18 @@ __device__ inline void block_reduce(double (&v)[K], const bool (&mx)[K], double 
 // boundary makes them visible to the finishing kernel (a device-scope fence
 // per block would write back the whole L2 of the block's XCD).
 template <int K>
-__device__ inline void block_partials(double (&v)[K], const bool (&mx)[K], double *partials) {
+__device__ inline void block_partials(double (&v)[K], const bool (&mx)[K], double *partials,
+                                      int bid, int nblk) {
     __shared__ double sh[K][kWaves];
     block_reduce<K>(v, mx, sh);
     if (threadIdx.x == 0)
 #pragma unroll
-        for (int k = 0; k < K; ++k) partials[(size_t)k * gridDim.x + blockIdx.x] = v[k];
+        for (int k = 0; k < K; ++k) partials[(size_t)k * nblk + bid] = v[k];
+}
+
+template <int K>
+__device__ inline void block_partials(double (&v)[K], const bool (&mx)[K], double *partials) {
+    block_partials<K>(v, mx, partials, (int)blockIdx.x, (int)gridDim.x);
 }
 
 // Second half, run by a single block: combines nparts partials of each of

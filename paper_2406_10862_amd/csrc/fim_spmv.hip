@@ -87,15 +87,14 @@ constexpr int spmv_rows_per_block() { return kBlock / G * SpmvRows<NB>::R; }
 // MT / VT: element types of the matrix values and of x, y (double, or float
 // for the inner solves of the mixed-precision mode); sums in double.
 template <int NB, int G, class MT, class VT>
-__global__ __launch_bounds__(kBlock) void k_spmv(int nrows, const int *__restrict__ rowptr,
-                                                 const int *__restrict__ colind,
-                                                 const MT *__restrict__ val,
-                                                 const VT *__restrict__ x,
-                                                 VT *__restrict__ y) {
+__device__ __forceinline__ void spmv_body(int bid, int nrows, const int *__restrict__ rowptr,
+                                          const int *__restrict__ colind,
+                                          const MT *__restrict__ val, const VT *__restrict__ x,
+                                          VT *__restrict__ y) {
     constexpr int R = SpmvRows<NB>::R;
     constexpr int GPW = 64 / G;             // lane groups per wave
     const int lg = threadIdx.x & (G - 1);
-    const long wave = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const long wave = ((long)bid * blockDim.x + threadIdx.x) >> 6;
     const long row0 = wave * (GPW * R) + ((threadIdx.x & 63) / G);
     // Every lane loads from an address inside the arrays (its own block,
     // else the last block of its row; a lane whose row range ends at 0 reads
@@ -173,6 +172,28 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int nrows, const int *__restric
     }
 }
 
+template <int NB, int G, class MT, class VT>
+__global__ __launch_bounds__(kBlock) void k_spmv(int nrows, const int *__restrict__ rowptr,
+                                                 const int *__restrict__ colind,
+                                                 const MT *__restrict__ val,
+                                                 const VT *__restrict__ x,
+                                                 VT *__restrict__ y) {
+    spmv_body<NB, G, MT, VT>(blockIdx.x, nrows, rowptr, colind, val, x, y);
+}
+
+// Batched over the members of an ensemble: y = J z_j into w (j >= 0) or
+// y = J x into t (j < 0), each member with its own Jacobian.
+template <int NB>
+__global__ __launch_bounds__(kBlock) void kb_spmv(const Member *__restrict__ mem, Batch B, int j) {
+    int m, b, nb;
+    if (!batch_view(B, m, b, nb)) return;
+    const Member &M = mem[m];
+    const double *src = j >= 0 ? M.Z + (size_t)j * M.nvec : M.x;
+    double *dst = j >= 0 ? M.w : M.t;
+    spmv_body<NB, kSpmvG, double, double>(b, M.nrows, M.sys.rowptr, M.sys.colind, M.sys.val, src,
+                                          dst);
+}
+
 // With events e0/e1 the launch records the kernel's own start and end
 // timestamps in them (no dispatch gap between a marker and the kernel).
 template <class MT, class VT>
@@ -195,6 +216,17 @@ static void spmv_impl(hipStream_t s, int nb, int nrows, const int *rowptr, const
         hipLaunchKernelGGL((k_spmv<3, G, MT, VT>), grid, block, 0, s, nrows, rowptr, colind, val,
                            x, y);
     }
+}
+
+int spmv_blocks(int nb, int nrows) {
+    const int per = nb == 2 ? spmv_rows_per_block<2, kSpmvG>() : spmv_rows_per_block<3, kSpmvG>();
+    return (nrows + per - 1) / per;
+}
+
+void launchb_spmv(hipStream_t s, int nb, const Member *mem, Batch B, int total, int j) {
+    if (total <= 0) return;
+    if (nb == 2) hipLaunchKernelGGL(kb_spmv<2>, dim3(total), dim3(kBlock), 0, s, mem, B, j);
+    else hipLaunchKernelGGL(kb_spmv<3>, dim3(total), dim3(kBlock), 0, s, mem, B, j);
 }
 
 void launch_spmv(hipStream_t s, int nb, int nrows, const int *rowptr, const int *colind,

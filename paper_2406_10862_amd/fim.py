@@ -141,7 +141,7 @@ def lib():
                                        C.POINTER(FimAdjointReport)]
     L.fim_set_perm.argtypes = [vp, f64p, f64p, f64p]
     L.fim_set_perm_dev.argtypes = [vp, vp, vp, vp]
-    L.fim_ensemble_run.argtypes = [C.c_int32, C.POINTER(vp), C.c_int32, f64p, C.c_int32,
+    L.fim_ensemble_run.argtypes = [C.c_int32, C.POINTER(vp), C.c_int32, f64p,
                                    C.POINTER(FimStepReport), i32p]
     for f in EXPORTS:
         if f not in ("fim_destroy", "fim_last_error"):
@@ -454,16 +454,17 @@ def fim_bsr_spmv(nrows, nb, rowptr, colind, val, x, y, stream=None):
     _check(lib().fim_bsr_spmv(nrows, nb, *ptr, s), "fim_bsr_spmv")
 
 
-def fim_ensemble_run(members, dt, workers=0):
-    """Advance the contexts `members` (Fim objects) by dt.shape[1] steps each,
-    up to `workers` at a time (fim_ensemble_run); dt[k, s] is step s of
-    member k.  Returns (rc, status[count, nsteps], reports[count][nsteps])."""
+def fim_ensemble_run(members, dt):
+    """Advance the contexts `members` (Fim objects) together by dt.shape[1]
+    steps each (fim_ensemble_run: one launch per kernel for all of them);
+    dt[k, s] is step s of member k.  Returns (rc, status[count, nsteps],
+    reports[count][nsteps])."""
     count = len(members)
     dt = np.ascontiguousarray(np.broadcast_to(np.asarray(dt, np.float64), (count, np.shape(dt)[-1])))
     nsteps = dt.shape[1]
     handles = (C.c_void_p * max(count, 1))(*[m.h for m in members])
     status = np.zeros((count, nsteps), np.int32)
     reps = (FimStepReport * max(count * nsteps, 1))()
-    rc = _check(lib().fim_ensemble_run(count, handles, nsteps, _p(dt, f64p), int(workers),
-                                       reps, _p(status, i32p)), "fim_ensemble_run")
+    rc = _check(lib().fim_ensemble_run(count, handles, nsteps, _p(dt, f64p), reps,
+                                       _p(status, i32p)), "fim_ensemble_run")
     return rc, status, [[reps[k * nsteps + s] for s in range(nsteps)] for k in range(count)]

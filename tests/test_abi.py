@@ -113,11 +113,11 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
 def test_ensemble_rejects_bad_arguments_without_a_device():
     L = fim.lib()
     # nothing to do is not an error
-    assert L.fim_ensemble_run(0, None, 5, None, 4, None, None) == fim.FIM_OK
-    assert L.fim_ensemble_run(3, None, 0, None, 4, None, None) == fim.FIM_OK
-    assert L.fim_ensemble_run(-1, None, 1, None, 4, None, None) == fim.FIM_E_ARG
+    assert L.fim_ensemble_run(0, None, 5, None, None, None) == fim.FIM_OK
+    assert L.fim_ensemble_run(3, None, 0, None, None, None) == fim.FIM_OK
+    assert L.fim_ensemble_run(-1, None, 1, None, None, None) == fim.FIM_E_ARG
     assert b"must be >= 0" in L.fim_last_error()
-    assert L.fim_ensemble_run(2, None, 1, None, 4, None, None) == fim.FIM_E_ARG
+    assert L.fim_ensemble_run(2, None, 1, None, None, None) == fim.FIM_E_ARG
     assert b"required" in L.fim_last_error()
 
 

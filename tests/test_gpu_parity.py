@@ -5,6 +5,7 @@ import pytest
 
 from paper_2406_10862_amd import fim, reservoirs as rv
 from oracle import fimref as fr
+from oracle.fimref import OracleModel
 from tests.gpu_cases import (STATE_TOL, oracle_state, pair, run_parity_steps, state_errors)
 from tests.helpers import box, ramp_state, blackoil_mixed_state
 
@@ -704,7 +705,7 @@ def test_ensemble_members_equal_their_runs_alone():
     nsteps = 3
     res, members = _ensemble_members()
     dt = np.array([r.schedule[:nsteps] for r in res])
-    rc, status, reps = fim.fim_ensemble_run(members, dt, workers=4)
+    rc, status, reps = fim.fim_ensemble_run(members, dt)
     assert rc == fim.FIM_OK and np.all(status == fim.FIM_OK)
     for k, r in enumerate(res):
         alone = fim.Fim(r)
@@ -726,12 +727,38 @@ def test_ensemble_member_matches_oracle():
     assert all(v <= STATE_TOL for v in worst.values()), worst
 
 
+def test_ensemble_members_match_the_oracle_through_the_batched_entry_point():
+    """Members of uneven sizes advanced together by fim_ensemble_run, each
+    against the oracle's steps of the same member, element by element."""
+    dims = [(11, 9, 4), (7, 13, 3), (16, 6, 2), (9, 9, 5)]
+    res = [rv.config_c4_member(k, d) for k, d in enumerate(dims)]
+    nsteps = 3
+    oracles = []
+    for r in res:
+        o = OracleModel(r)
+        for s in range(nsteps):
+            st, rep = o.step(r.schedule[s])
+            assert st == 0 and rep.cuts == 0
+        oracles.append(o)
+    members = [fim.Fim(r) for r in res]
+    for m, o in zip(members, res):
+        m.set_initial_state()
+    dt = np.array([r.schedule[:nsteps] for r in res])
+    rc, status, reps = fim.fim_ensemble_run(members, dt)
+    assert rc == fim.FIM_OK and np.all(status == fim.FIM_OK)
+    for k, (m, o) in enumerate(zip(members, oracles)):
+        assert all(reps[k][s].cuts == 0 for s in range(nsteps))
+        e = state_errors(m.fim_get_state(), oracle_state(o), res[k].fluid, 2)
+        print(f"member {k} {dims[k]}: {e}")
+        assert all(v <= STATE_TOL for v in e.values()), (k, e)
+
+
 def test_ensemble_stops_a_failing_member_and_finishes_the_others():
     res, members = _ensemble_members()
     # one Newton iteration and no cuts: the first step of that member fails
     members[2].fim_set_options(rv.Options(max_newton=1, max_cuts=0))
     dt = np.array([r.schedule[:2] for r in res])
-    rc, status, reps = fim.fim_ensemble_run(members, dt, workers=3)
+    rc, status, reps = fim.fim_ensemble_run(members, dt)
     assert rc == fim.FIM_NOT_CONVERGED
     assert status[2, 0] == fim.FIM_NOT_CONVERGED and status[2, 1] == fim.FIM_SKIPPED
     others = np.delete(status, 2, axis=0)
@@ -744,7 +771,7 @@ def test_ensemble_stops_a_failing_member_and_finishes_the_others():
 def test_ensemble_rejects_a_context_given_twice():
     res, members = _ensemble_members()
     with pytest.raises(fim.FimError, match="twice"):
-        fim.fim_ensemble_run([members[0], members[1], members[0]], [[15.0]], workers=2)
+        fim.fim_ensemble_run([members[0], members[1], members[0]], [[15.0]])
 
 
 # ---------------------------------------------------------------------------

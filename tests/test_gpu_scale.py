@@ -1,0 +1,109 @@
+"""GPU parity at scale.
+
+* The 264,000-cell five-spot (the benchmark's recipe with 20 layers) in the
+  benchmark's launch configuration: the state after the first 10-day step
+  against the oracle's, element by element, from a fixture the oracle wrote
+  (tests/golden/make_fivespot_step_fixture.py; the oracle needs minutes
+  there, too long for a test).
+* The 2,000,000-cell three-phase case over its real first schedule entry of
+  30 days, which needs time-step cuts: the accepted sub-steps replayed in an
+  FP64 and a mixed-precision context, the two states compared after every
+  sub-step and the oracle's discrete system evaluated at each GPU state.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import fimref as fr
+from paper_2406_10862_amd import fim, reservoirs as rv
+from tests.gpu_cases import STATE_TOL, sg_rs
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    print(f"\n[gpu case] {request.node.nodeid}", flush=True)
+    yield
+
+
+def test_fivespot_264k_first_step_matches_the_oracle_element_by_element():
+    from tests.golden.make_fivespot_step_fixture import OUT, workload
+    if not os.path.exists(OUT):
+        pytest.skip("fixture not written (run tests/golden/make_fivespot_step_fixture.py)")
+    ref = np.load(OUT)
+    res = workload()
+    # the benchmark's options: CPR + block-Jacobi ILU(0) over 8x16x8 boxes,
+    # GMRES(40), graphs, the forcing term; the finest AMG level restricts by
+    # row segments as the 1.1M-cell level does
+    opt = rv.Options(max_lin=400, restart=40, max_newton=30, tile=(8, 16, 8),
+                     amg_seg_rows=1 << 16)
+    g = fim.Fim(res, options=opt)
+    g.set_initial_state()
+    newton = linear = 0
+    for h in ref["dt_sub"]:
+        rc, rep = g.fim_step(float(h))
+        assert rc == fim.FIM_OK and rep.cuts == 0
+        newton += rep.newton_iters
+        linear += rep.linear_iters
+    st = g.fim_get_state()
+    eP = np.abs(st["P"] - ref["P"]).max() / np.abs(ref["P"]).max()
+    eS = np.abs(st["Sw"] - ref["Sw"]).max()
+    eB = np.abs(st["pbhp"] - ref["pbhp"]).max() / np.abs(ref["pbhp"]).max()
+    print(f"264k five-spot step 1: GPU {newton} Newton / {linear} linear iterations "
+          f"(oracle {int(ref['newton'])} / {int(ref['linear'])}); e_P {eP:.2e} e_S {eS:.2e} "
+          f"e_bhp {eB:.2e}")
+    assert eP <= STATE_TOL and eS <= STATE_TOL and eB <= STATE_TOL
+
+
+def test_c3_first_30_day_entry_with_cuts_fp64_and_mixed():
+    res = rv.config_c3()
+    dt = res.schedule[0]
+    base = dict(precond=rv.PREC_CPR_ILU0)
+    g = fim.Fim(res, options=rv.Options(**base))
+    g.set_initial_state()
+    rc, rep = g.fim_step(dt)
+    assert rc == fim.FIM_OK
+    subs = [float(h) for h in rep.dt_sub[: rep.nsub]]
+    print(f"c3 first entry: {rep.cuts} cuts, accepted sub-steps {subs}")
+    assert rep.cuts >= 1 and abs(sum(subs) - dt) < 1e-9
+    end_fp64 = g.fim_get_state()
+    del g
+    o = fr.OracleModel(res)
+    ctx = {p: fim.Fim(res, options=rv.Options(**base, precision=p)) for p in (rv.FP64, rv.MIXED)}
+    for c in ctx.values():
+        c.set_initial_state()
+    prev = {p: c.fim_get_state() for p, c in ctx.items()}
+    opt = rv.Options()
+    for m, h in enumerate(subs):
+        states = {}
+        for p, c in ctx.items():
+            rc, r = c.fim_step(h)
+            assert rc == fim.FIM_OK and r.cuts == 0, (m, p)
+            states[p] = c.fim_get_state()
+        a, b = states[rv.FP64], states[rv.MIXED]
+        sg_a, rs_a = sg_rs(a, res.fluid)
+        sg_b, rs_b = sg_rs(b, res.fluid)
+        diff = {"P": np.abs(a["P"] - b["P"]).max() / np.abs(a["P"]).max(),
+                "Sw": np.abs(a["Sw"] - b["Sw"]).max(), "Sg": np.abs(sg_a - sg_b).max(),
+                "Rs": np.abs(rs_a - rs_b).max() / np.abs(rs_a).max()}
+        line = [f"sub-step {m} ({h:g} d): mixed vs FP64 " +
+                " ".join(f"{k} {v:.1e}" for k, v in diff.items())]
+        for p, st in states.items():
+            x0 = prev[p]
+            A0 = o.accum(P=x0["P"], Sw=x0["Sw"], X=x0["X"], flag=x0["flag"])
+            end = dict(P=st["P"], Sw=st["Sw"], X=st["X"], flag=st["flag"], pbhp=st["pbhp"])
+            R, _ = o.assemble(h, A0, jacobian=False, **end)
+            cnv, mb = o.conv(R, h, **end)
+            line.append(f"{'fp64' if p == rv.FP64 else 'mixed'}: oracle CNV {cnv.max():.1e} "
+                        f"MB {mb.max():.1e}")
+            assert cnv.max() <= opt.tol_cnv and mb.max() <= opt.tol_mb, (m, p, cnv, mb)
+        print("; ".join(line), flush=True)
+        assert all(v <= STATE_TOL for v in diff.values()), (m, diff)
+        prev = states
+    # the replay ends where the step with its own cuts ended
+    for k in end_fp64:
+        assert np.array_equal(end_fp64[k], prev[rv.FP64][k]), k
