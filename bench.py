@@ -261,6 +261,17 @@ def ensemble_bench(args):
     nsteps = args.steps if args.steps is not None else len(res[0].schedule)
     sched = np.array([[r.schedule[s % len(r.schedule)] for s in range(max(nsteps, args.warmup))]
                       for r in res])
+    tune = None
+    if not args.no_tune:
+        # the ILU(0) box by the autotuner: one trial step per candidate from
+        # the initial state (setup, outside the timed window)
+        t_t = time.perf_counter()
+        rc_t, rep_t = fim.fim_ensemble_tune(members, float(sched[0, 0]), 1, args.tune_cache)
+        tune = {"box": list(rep_t.box), "from_cache": bool(rep_t.from_cache),
+                "candidates": [list(rep_t.cand[c]) for c in range(rep_t.ncand)],
+                "trial_ms": [rep_t.trial_ms[c] for c in range(rep_t.ncand)] if rep_t.trials else None,
+                "tuning_s": time.perf_counter() - t_t}
+        log(f"tuner: box {tuple(rep_t.box)} (cache {bool(rep_t.from_cache)}) in {tune['tuning_s']:.1f}s")
     if args.warmup:
         rc, status, _ = fim.fim_ensemble_run(members, sched[:, :args.warmup])
         log(f"warm-up: rc={rc}")
@@ -295,8 +306,10 @@ def ensemble_bench(args):
                         f"{int(cells.sum())} cells in all, seeded log-normal perm (sigma 1), "
                         "rate injector and BHP producer at opposite corners, dt 15 days",
             "members": len(members), "cells": int(cells.sum()),
-            "execution": "one launch per kernel for all members (batched), lockstep FGMRES "
-                         "restart cycles, Newton rounds over the members with work",
+            "execution": "one launch per kernel for all members (batched), every Newton phase "
+                         "a captured HIP graph, lockstep FGMRES restart cycles, Newton rounds "
+                         "over the members with work",
+            "ilu_box_tuning": tune,
             "tolerances": args.tol, "newton_iters": newton, "linear_iters": linear,
             "cuts": cuts, "member_steps_ok": int(done.sum()),
             "newton_iters_per_s": newton / wall,
@@ -501,6 +514,10 @@ def main():
                     help="c5: also check the gradient by central differences on this many "
                          "cells (drawn with seed 5, step --fd-h in ln k; two forward runs each)")
     ap.add_argument("--members", type=int, default=256, help="c4: realisations")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="c4: keep the default ILU(0) box instead of the autotuner's")
+    ap.add_argument("--tune-cache", default=None,
+                    help="c4: the autotuner's cache file (default: none, always tune)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cycle", type=int, default=0,
                     help="AMG cycle: 0 V at the finest level and W below, 1 V, 2 W, >=16 W on "

@@ -325,6 +325,27 @@ int fim_set_perm_dev(fim_ctx *ctx, const double *kx_dev, const double *ky_dev,
 int fim_ensemble_run(int32_t count, fim_ctx *const *members, int32_t nsteps, const double *dt,
                      fim_step_report *reports, int32_t *status);
 
+/* Autotuner of the ensemble's block-Jacobi ILU(0) boxes (this library's
+ * addition: the box is its reading of the paper's block-Jacobi subdomains,
+ * Sec. 5.1).  Times trial_steps steps of dt_days of the whole batched
+ * ensemble from the members' current states with each candidate box
+ * (cand[0..ncand), all of 64 pencils), sets the fastest on every member
+ * (fim_set_options) and leaves every state as it found it.  The choice is
+ * cached in the text file cache_path (may be NULL: no cache) under a key of
+ * the block size, floor(log2) of the median member's cell count and the
+ * device; a call whose key is in the cache applies the cached box without
+ * trials (from_cache = 1).  FIM_NOT_CONVERGED when no candidate finished
+ * its trial steps (the members keep their boxes and states). */
+typedef struct {
+    int32_t box[3];                      /* chosen tile_nx, tile_ny, tile_nz */
+    int32_t from_cache, trials, ncand;
+    int32_t cand[16][3];
+    double trial_ms[16];                 /* wall time of each candidate's trial */
+} fim_tune_report;
+
+int fim_ensemble_tune(int32_t count, fim_ctx *const *members, double dt_days,
+                      int32_t trial_steps, const char *cache_path, fim_tune_report *rep);
+
 /* Surface rates q[w*3 + i] (component i = water, oil, gas; production
  * positive, injection negative) and bottom-hole pressures at the state. */
 int fim_get_well_rates(fim_ctx *ctx, double *q_surf, double *bhp);

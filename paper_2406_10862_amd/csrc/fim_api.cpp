@@ -14,6 +14,7 @@
 #include <chrono>
 #include <functional>
 #include <limits>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <new>
@@ -1839,6 +1840,11 @@ struct Shape {                    // block starts of one launch shape
 
 enum { kSave0 = 128, kSave1 = 256, kRestore0 = 512, kRestore1 = 1024 };
 
+// keys of the captured phases
+enum { kPhaseAssemble = 1, kPhaseSetup, kPhaseGmresInit, kPhaseCycleStart, kPhaseFinish,
+       kPhaseUpdate, kPhaseSave0, kPhaseSave1, kPhaseRestore0, kPhaseRestore1,
+       kPhaseArnoldi = 100 };
+
 struct GmState {
     bool in_cycle = false, stopped = false, first = true;
     int k = 0, total = 0, status = 1;
@@ -1877,6 +1883,8 @@ struct Ensemble {
     Shape cells, rows, wells, conv, one, vec, spmv, tiles, extract, statecopy;
     std::vector<Shape> coarsen, dot, dotsum;
     std::vector<int> flags;
+    std::map<int, hipGraphExec_t> graphs;     // captured phases, by key
+    bool use_graphs = true;
 
     template <typename T>
     T *dalloc(size_t count) {
@@ -1892,6 +1900,7 @@ struct Ensemble {
     }
     ~Ensemble() {
         if (s) (void)hipStreamSynchronize(s);
+        for (auto &g : graphs) (void)hipGraphExecDestroy(g.second);
         for (void *p : owned) (void)hipFree(p);
         for (void *p : {(void *)h_flagring, (void *)h_k, (void *)h_dt, (void *)h_scal,
                         (void *)h_ypack})
@@ -1909,6 +1918,35 @@ struct Ensemble {
         return sh;
     }
     Batch batch(const Shape &sh, int bit) const { return Batch{sh.d, d_flags, nm, bit}; }
+
+    // The launches of one phase: captured into a HIP graph on first use
+    // (every argument, flags array included, is fixed per key: what changes
+    // between rounds lives in device memory), then replayed.
+    void phase(int key, const std::function<void()> &f) {
+        if (!use_graphs) {
+            f();
+            return;
+        }
+        auto it = graphs.find(key);
+        if (it == graphs.end()) {
+            hipGraph_t g = nullptr;
+            HIPCHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            try {
+                f();
+            } catch (...) {
+                (void)hipStreamEndCapture(s, &g);
+                if (g) (void)hipGraphDestroy(g);
+                throw;
+            }
+            HIPCHECK(hipStreamEndCapture(s, &g));
+            hipGraphExec_t ex = nullptr;
+            const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            HIPCHECK(e);
+            it = graphs.emplace(key, ex).first;
+        }
+        HIPCHECK(hipGraphLaunch(it->second, s));
+    }
 
     // the host's flags to the device, in stream order (each copy from a
     // pinned ring slot of its own, so a later write does not race it)
@@ -1928,12 +1966,13 @@ struct Ensemble {
         return false;
     }
     // the members' scalar slots [first, first + count) into h_scal[k * ld_scal + e]
+    // (queued; read after a synchronisation)
     void gather(int bit, int first, int count) {
         launchb_gather_scalars(s, d_mem, batch(one, bit), one.total, first, count, d_scal, ld_scal);
         HIPCHECK(hipMemcpyAsync(h_scal, d_scal, (size_t)nm * ld_scal * sizeof(double),
                                 hipMemcpyDeviceToHost, s));
-        HIPCHECK(hipStreamSynchronize(s));
     }
+    void sync() { HIPCHECK(hipStreamSynchronize(s)); }
 };
 
 // the batched configuration: CPR with the block-Jacobi ILU(0) second stage
@@ -2167,10 +2206,13 @@ void batch_gmres(Ensemble &E, std::vector<MemRun> &runs, double *dcols, double *
     E.set(kOnSolve, [&](int k) { return runs[k].solve; });
     E.set(kOnCycle | kOnFinish | kFirstCycle, [](int) { return false; });
     E.put_flags();
-    launchb_scale_zero(E.s, E.d_mem, E.batch(E.vec, kOnSolve), E.vec.total);
-    launchb_norm_b(E.s, E.d_mem, E.batch(E.vec, kOnSolve), E.vec.total, E.batch(E.one, kOnSolve),
-                   E.one.total, S_NORM);
-    E.gather(kOnSolve, S_NORM, 2);
+    E.phase(kPhaseGmresInit, [&] {
+        launchb_scale_zero(E.s, E.d_mem, E.batch(E.vec, kOnSolve), E.vec.total);
+        launchb_norm_b(E.s, E.d_mem, E.batch(E.vec, kOnSolve), E.vec.total,
+                       E.batch(E.one, kOnSolve), E.one.total, S_NORM);
+        E.gather(kOnSolve, S_NORM, 2);
+    });
+    E.sync();
     for (int k = 0; k < nm; ++k) {
         MemRun &R = runs[k];
         if (!R.solve) continue;
@@ -2211,13 +2253,13 @@ void batch_gmres(Ensemble &E, std::vector<MemRun> &runs, double *dcols, double *
         E.set(kOnCycle, cycle_member);
         E.set(kFirstCycle, [&](int k) { return cycle_member(k) && runs[k].gm.first; });
         E.put_flags();
-        batch_precondition(E, -1);
+        E.phase(kPhaseCycleStart, [&] { batch_precondition(E, -1); });
         // step 0 for every member in the cycle, then look ahead one step
         std::vector<std::vector<char>> took(m, std::vector<char>(nm, 0));
         for (int k = 0; k < nm; ++k) took[0][k] = cycle_member(k);
         E.set(kFirstCycle, [](int) { return false; });
         E.put_flags();
-        batch_arnoldi(E, 0, dcols, hcols, LDH);
+        E.phase(kPhaseArnoldi, [&] { batch_arnoldi(E, 0, dcols, hcols, LDH); });
         std::vector<hipEvent_t> done(m, nullptr);
         auto record = [&](int j) {
             if (!done[j]) HIPCHECK(hipEventCreateWithFlags(&done[j], hipEventDisableTiming));
@@ -2238,8 +2280,10 @@ void batch_gmres(Ensemble &E, std::vector<MemRun> &runs, double *dcols, double *
                     if (any) {
                         E.set(kOnCycle, [&](int k) { return took[j + 1][k] != 0; });
                         E.put_flags();
-                        batch_arnoldi(E, j + 1, dcols + (size_t)(j + 1) * colstride,
-                                      hcols + (size_t)(j + 1) * colstride, LDH);
+                        E.phase(kPhaseArnoldi + j + 1, [&] {
+                            batch_arnoldi(E, j + 1, dcols + (size_t)(j + 1) * colstride,
+                                          hcols + (size_t)(j + 1) * colstride, LDH);
+                        });
                         record(j + 1);
                     }
                 }
@@ -2308,11 +2352,15 @@ void batch_gmres(Ensemble &E, std::vector<MemRun> &runs, double *dcols, double *
         E.set(kOnFinish, cycle_member);
         E.set(kOnCycle, [](int) { return false; });
         E.put_flags();
-        launchb_axpy(E.s, E.d_mem, E.batch(E.vec, kOnFinish), E.vec.total, E.d_k, E.d_ypack, E.ld_y);
-        launchb_spmv(E.s, E.nb, E.d_mem, E.batch(E.spmv, kOnFinish), E.spmv.total, -1);
-        launchb_residual(E.s, E.d_mem, E.batch(E.vec, kOnFinish), E.vec.total,
-                         E.batch(E.one, kOnFinish), E.one.total, S_RES);
-        E.gather(kOnFinish, S_RES, 2);
+        E.phase(kPhaseFinish, [&] {
+            launchb_axpy(E.s, E.d_mem, E.batch(E.vec, kOnFinish), E.vec.total, E.d_k, E.d_ypack,
+                         E.ld_y);
+            launchb_spmv(E.s, E.nb, E.d_mem, E.batch(E.spmv, kOnFinish), E.spmv.total, -1);
+            launchb_residual(E.s, E.d_mem, E.batch(E.vec, kOnFinish), E.vec.total,
+                             E.batch(E.one, kOnFinish), E.one.total, S_RES);
+            E.gather(kOnFinish, S_RES, 2);
+        });
+        E.sync();
         for (int k = 0; k < nm; ++k) {
             GmState &G = runs[k].gm;
             if (!cycle_member(k)) continue;
@@ -2420,11 +2468,15 @@ int ensemble_impl(int count, fim_ctx *const *members, int nsteps, const double *
         if (E.any(kSave0) || E.any(kSave1)) {
             E.put_flags();
             if (E.any(kSave0))
-                launchb_state_copy(E.s, E.d_mem, E.statecopy.d, E.d_flags, nm, E.statecopy.total,
-                                   E.d_slots, 0, kSave0, 0);
+                E.phase(kPhaseSave0, [&] {
+                    launchb_state_copy(E.s, E.d_mem, E.statecopy.d, E.d_flags, nm,
+                                       E.statecopy.total, E.d_slots, 0, kSave0, 0);
+                });
             if (E.any(kSave1))
-                launchb_state_copy(E.s, E.d_mem, E.statecopy.d, E.d_flags, nm, E.statecopy.total,
-                                   E.d_slots, 1, kSave1, 0);
+                E.phase(kPhaseSave1, [&] {
+                    launchb_state_copy(E.s, E.d_mem, E.statecopy.d, E.d_flags, nm,
+                                       E.statecopy.total, E.d_slots, 1, kSave1, 0);
+                });
         }
         // assembly round: properties (step-start accumulation at it = 0),
         // residual and Jacobian, convergence measures
@@ -2437,12 +2489,15 @@ int ensemble_impl(int count, fim_ctx *const *members, int nsteps, const double *
         }
         HIPCHECK(hipMemcpyAsync(E.d_dt, E.h_dt, nm * sizeof(double), hipMemcpyHostToDevice, E.s));
         E.put_flags();
-        launchb_props(E.s, E.nb, E.d_mem, E.batch(E.cells, kOnNewton), E.cells.total);
-        launchb_assemble(E.s, E.nb, E.d_mem, E.batch(E.cells, kOnNewton), E.cells.total,
-                         E.batch(E.wells, kOnNewton), E.wells.total, E.d_dt);
-        launchb_conv(E.s, E.nb, E.d_mem, E.batch(E.conv, kOnNewton), E.conv.total,
-                     E.batch(E.one, kOnNewton), E.one.total, E.d_dt, S_CONV);
-        E.gather(kOnNewton, S_CONV, S_NORM - S_CONV);
+        E.phase(kPhaseAssemble, [&] {
+            launchb_props(E.s, E.nb, E.d_mem, E.batch(E.cells, kOnNewton), E.cells.total);
+            launchb_assemble(E.s, E.nb, E.d_mem, E.batch(E.cells, kOnNewton), E.cells.total,
+                             E.batch(E.wells, kOnNewton), E.wells.total, E.d_dt);
+            launchb_conv(E.s, E.nb, E.d_mem, E.batch(E.conv, kOnNewton), E.conv.total,
+                         E.batch(E.one, kOnNewton), E.one.total, E.d_dt, S_CONV);
+            E.gather(kOnNewton, S_CONV, S_NORM - S_CONV);
+        });
+        E.sync();
         // the convergence check of newton() for every member
         std::vector<int> fail(nm, 0), ok(nm, 0);
         for (int k = 0; k < nm; ++k) {
@@ -2493,7 +2548,7 @@ int ensemble_impl(int count, fim_ctx *const *members, int nsteps, const double *
         if (anysolve) {
             E.set(kOnSolve, [&](int k) { return runs[k].solve; });
             E.put_flags();
-            batch_prec_setup(E);
+            E.phase(kPhaseSetup, [&] { batch_prec_setup(E); });
             batch_gmres(E, runs, dcols, hcols);
             for (int k = 0; k < nm; ++k) {
                 MemRun &R = runs[k];
@@ -2509,8 +2564,10 @@ int ensemble_impl(int count, fim_ctx *const *members, int nsteps, const double *
             E.set(kOnUpdate, [&](int k) { return runs[k].solve; });
             E.set(kOnSolve, [](int) { return false; });
             E.put_flags();
-            launchb_newton_update(E.s, E.nb, E.d_mem, E.batch(E.conv, kOnUpdate), E.conv.total,
-                                  E.batch(E.one, kOnUpdate), E.one.total, S_UPD);
+            E.phase(kPhaseUpdate, [&] {
+                launchb_newton_update(E.s, E.nb, E.d_mem, E.batch(E.conv, kOnUpdate),
+                                      E.conv.total, E.batch(E.one, kOnUpdate), E.one.total, S_UPD);
+            });
             for (int k = 0; k < nm; ++k)
                 if (runs[k].solve) runs[k].it++;
         }
@@ -2539,11 +2596,15 @@ int ensemble_impl(int count, fim_ctx *const *members, int nsteps, const double *
         if (E.any(kRestore1) || E.any(kRestore0)) {
             E.put_flags();
             if (E.any(kRestore1))
-                launchb_state_copy(E.s, E.d_mem, E.statecopy.d, E.d_flags, nm, E.statecopy.total,
-                                   E.d_slots, 1, 0, kRestore1);
+                E.phase(kPhaseRestore1, [&] {
+                    launchb_state_copy(E.s, E.d_mem, E.statecopy.d, E.d_flags, nm,
+                                       E.statecopy.total, E.d_slots, 1, 0, kRestore1);
+                });
             if (E.any(kRestore0))
-                launchb_state_copy(E.s, E.d_mem, E.statecopy.d, E.d_flags, nm, E.statecopy.total,
-                                   E.d_slots, 0, 0, kRestore0);
+                E.phase(kPhaseRestore0, [&] {
+                    launchb_state_copy(E.s, E.d_mem, E.statecopy.d, E.d_flags, nm,
+                                       E.statecopy.total, E.d_slots, 0, 0, kRestore0);
+                });
         }
     }
     HIPCHECK(hipStreamSynchronize(E.s));
@@ -2555,6 +2616,182 @@ int ensemble_impl(int count, fim_ctx *const *members, int nsteps, const double *
     }
     for (fim_ctx *c : E.mem) c->sync();
     return result;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// autotuner of the ensemble's block-Jacobi ILU(0) boxes
+//
+// The box sets both the ILU(0) preconditioner (fewer, larger boxes: fewer
+// linear iterations) and the cost of one application (longer hyperplane
+// sweeps per workgroup, fewer workgroups).  The tuner times trial steps of
+// the whole batched ensemble from its current state with every candidate
+// box, keeps the fastest, and caches the choice per (block size, size
+// bucket of the median member, device); a later call with the same key
+// applies the cached box without trials.  Candidates keep 64 pencils per
+// box (the batched ILU(0) launches take one workgroup size).
+
+namespace {
+
+const int kTuneBoxes[][3] = {{8, 8, 8}, {8, 8, 16}, {8, 8, 4}, {16, 4, 8}, {4, 16, 8}, {16, 4, 16}};
+constexpr int kTuneCand = sizeof(kTuneBoxes) / sizeof(kTuneBoxes[0]);
+
+struct SavedState {
+    double *P = nullptr, *Sw = nullptr, *X = nullptr, *pbhp = nullptr;
+    int8_t *flag = nullptr;
+};
+
+std::string tune_key(const std::vector<fim_ctx *> &mem) {
+    std::vector<int> n;
+    for (const fim_ctx *c : mem) n.push_back(c->n);
+    std::sort(n.begin(), n.end());
+    const int med = n[n.size() / 2];
+    int bucket = 0;
+    while ((1 << (bucket + 1)) <= med) ++bucket;            // floor(log2(median cells))
+    hipDeviceProp_t prop{};
+    HIPCHECK(hipGetDeviceProperties(&prop, mem[0]->dev));
+    std::string name = prop.gcnArchName;
+    for (char &ch : name)
+        if (ch == ' ') ch = '_';
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "nb%d_cells2^%d_%s", mem[0]->nb, bucket, name.c_str());
+    return buf;
+}
+
+bool tune_lookup(const char *path, const std::string &key, int (&box)[3]) {
+    if (!path) return false;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    char k[256];
+    int t[3];
+    bool found = false;
+    while (std::fscanf(f, "%255s %d %d %d", k, &t[0], &t[1], &t[2]) == 4)
+        if (key == k) {
+            for (int a = 0; a < 3; ++a) box[a] = t[a];
+            found = true;                                   // the last entry wins
+        }
+    std::fclose(f);
+    return found;
+}
+
+void set_box(fim_ctx *c, const int (&box)[3]) {
+    fim_options o = c->opt;
+    o.tile_nx = box[0];
+    o.tile_ny = box[1];
+    o.tile_nz = box[2];
+    REQUIRE(fim_set_options(c, &o) == FIM_OK, "%s", g_err.c_str());
+}
+
+int tune_impl(int count, fim_ctx *const *members, double dt, int trial_steps, const char *cache,
+              fim_tune_report *rep) {
+    REQUIRE(count >= 1 && members, "members are required");
+    REQUIRE(dt > 0 && std::isfinite(dt), "dt must be > 0");
+    REQUIRE(trial_steps >= 1, "trial_steps must be >= 1");
+    std::vector<fim_ctx *> mem(members, members + count);
+    for (int k = 0; k < count; ++k) {
+        REQUIRE(members[k], "member %d is NULL", k);
+        if (!members[k]->state_set) {
+            set_err("member %d: state not set", k);
+            throw StateError();
+        }
+    }
+    fim_tune_report r{};
+    r.ncand = kTuneCand;
+    for (int c = 0; c < kTuneCand; ++c)
+        for (int a = 0; a < 3; ++a) r.cand[c][a] = kTuneBoxes[c][a];
+    const std::string key = tune_key(mem);
+    int best[3];
+    if (tune_lookup(cache, key, best)) {
+        for (fim_ctx *c : mem) set_box(c, best);
+        r.from_cache = 1;
+        for (int a = 0; a < 3; ++a) r.box[a] = best[a];
+        if (rep) *rep = r;
+        return FIM_OK;
+    }
+    // the members' states, to start every trial from and to leave them in
+    std::vector<SavedState> saved(count);
+    std::vector<void *> bufs;
+    struct Free {
+        std::vector<void *> &b;
+        ~Free() {
+            for (void *p : b) (void)hipFree(p);
+        }
+    } free_bufs{bufs};
+    auto dal = [&](size_t bytes) {
+        void *p = nullptr;
+        HIPCHECK(hipMalloc(&p, std::max<size_t>(bytes, 8)));
+        bufs.push_back(p);
+        return p;
+    };
+    auto copy = [&](fim_ctx *c, SavedState &S, bool save) {
+        const size_t n = c->n;
+        auto cp = [&](void *a, void *b, size_t bytes) {
+            HIPCHECK(hipMemcpyAsync(save ? a : b, save ? b : a, bytes, hipMemcpyDeviceToDevice, c->s));
+        };
+        cp(S.P, c->P, n * 8);
+        cp(S.Sw, c->Sw, n * 8);
+        cp(S.X, c->X, n * 8);
+        cp(S.flag, c->flag, n);
+        if (c->nw) cp(S.pbhp, c->pbhp, c->nw * 8);
+        if (!save) props(c, true);
+    };
+    for (int k = 0; k < count; ++k) {
+        fim_ctx *c = mem[k];
+        SavedState &S = saved[k];
+        S.P = (double *)dal((size_t)c->n * 8);
+        S.Sw = (double *)dal((size_t)c->n * 8);
+        S.X = (double *)dal((size_t)c->n * 8);
+        S.flag = (int8_t *)dal(c->n);
+        S.pbhp = (double *)dal((size_t)std::max(c->nw, 1) * 8);
+        copy(c, S, true);
+    }
+    for (fim_ctx *c : mem) c->sync();
+    const int orig[3] = {mem[0]->opt.tile_nx, mem[0]->opt.tile_ny, mem[0]->opt.tile_nz};
+    std::vector<double> dts((size_t)count * trial_steps, dt);
+    std::vector<int32_t> st((size_t)count * trial_steps);
+    double best_ms = INFINITY;
+    int bi = -1;
+    for (int cand = 0; cand < kTuneCand; ++cand) {
+        for (fim_ctx *c : mem) set_box(c, kTuneBoxes[cand]);
+        for (int k = 0; k < count; ++k) copy(mem[k], saved[k], false);
+        for (fim_ctx *c : mem) c->sync();
+        const auto t0 = std::chrono::steady_clock::now();
+        const int rc = ensemble_impl(count, members, trial_steps, dts.data(), nullptr, st.data());
+        const double ms =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        r.trial_ms[cand] = rc == FIM_OK ? ms : INFINITY;
+        r.trials++;
+        if (rc == FIM_OK && ms < best_ms) {
+            best_ms = ms;
+            bi = cand;
+        }
+    }
+    if (bi < 0) {
+        // no candidate finished its trial steps: leave the members as they were
+        for (fim_ctx *c : mem) {
+            const int o[3] = {orig[0], orig[1], orig[2]};
+            set_box(c, o);
+        }
+        for (int k = 0; k < count; ++k) copy(mem[k], saved[k], false);
+        for (fim_ctx *c : mem) c->sync();
+        set_err("no candidate box finished the trial steps");
+        if (rep) *rep = r;
+        return FIM_NOT_CONVERGED;
+    }
+    for (int a = 0; a < 3; ++a) best[a] = kTuneBoxes[bi][a];
+    for (fim_ctx *c : mem) set_box(c, best);
+    for (int k = 0; k < count; ++k) copy(mem[k], saved[k], false);
+    for (fim_ctx *c : mem) c->sync();
+    if (cache) {
+        FILE *f = std::fopen(cache, "a");
+        REQUIRE(f, "cannot open the tuning cache %s", cache);
+        std::fprintf(f, "%s %d %d %d\n", key.c_str(), best[0], best[1], best[2]);
+        std::fclose(f);
+    }
+    for (int a = 0; a < 3; ++a) r.box[a] = best[a];
+    if (rep) *rep = r;
+    return FIM_OK;
 }
 
 }  // namespace
@@ -2860,6 +3097,13 @@ int fim_ensemble_run(int32_t count, fim_ctx *const *members, int32_t nsteps, con
         REQUIRE(std::adjacent_find(seen.begin(), seen.end()) == seen.end(),
                 "a context appears twice among the members");
         return ensemble_impl(count, members, nsteps, dt, reports, status);
+    });
+}
+
+int fim_ensemble_tune(int32_t count, fim_ctx *const *members, double dt_days,
+                      int32_t trial_steps, const char *cache_path, fim_tune_report *rep) {
+    return guarded([&] {
+        return tune_impl(count, members, dt_days, trial_steps, cache_path, rep);
     });
 }
 

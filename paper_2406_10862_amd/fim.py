@@ -85,12 +85,18 @@ class FimAdjointReport(C.Structure):
                 ("stored_states", C.c_int32), ("pad", C.c_int32)]
 
 
+class FimTuneReport(C.Structure):
+    _fields_ = [("box", C.c_int32 * 3), ("from_cache", C.c_int32), ("trials", C.c_int32),
+                ("ncand", C.c_int32), ("cand", (C.c_int32 * 3) * 16),
+                ("trial_ms", C.c_double * 16)]
+
+
 EXPORTS = ["fim_create", "fim_destroy", "fim_last_error", "fim_sizes", "fim_set_options",
            "fim_set_state", "fim_set_state_dev", "fim_get_state", "fim_step",
            "fim_get_well_rates", "fim_static", "fim_set_iterate", "fim_props",
            "fim_assemble", "fim_precond_apply", "fim_linear_solve", "fim_bsr_spmv",
            "fim_ensemble_run", "fim_adjoint_gradient", "fim_step_noalloc", "fim_set_perm",
-           "fim_set_perm_dev"]
+           "fim_set_perm_dev", "fim_ensemble_tune"]
 
 _LIB = None
 
@@ -140,6 +146,8 @@ def lib():
     L.fim_adjoint_gradient.argtypes = [vp, C.c_int32, f64p, f64p, C.c_int32, f64p,
                                        C.POINTER(FimAdjointReport)]
     L.fim_set_perm.argtypes = [vp, f64p, f64p, f64p]
+    L.fim_ensemble_tune.argtypes = [C.c_int32, C.POINTER(vp), C.c_double, C.c_int32, C.c_char_p,
+                                    C.POINTER(FimTuneReport)]
     L.fim_set_perm_dev.argtypes = [vp, vp, vp, vp]
     L.fim_ensemble_run.argtypes = [C.c_int32, C.POINTER(vp), C.c_int32, f64p,
                                    C.POINTER(FimStepReport), i32p]
@@ -468,3 +476,18 @@ def fim_ensemble_run(members, dt):
     rc = _check(lib().fim_ensemble_run(count, handles, nsteps, _p(dt, f64p), reps,
                                        _p(status, i32p)), "fim_ensemble_run")
     return rc, status, [[reps[k * nsteps + s] for s in range(nsteps)] for k in range(count)]
+
+
+def fim_ensemble_tune(members, dt, trial_steps=1, cache_path=None):
+    """Time trial steps of the batched ensemble with every candidate ILU(0)
+    box, set the fastest on every member and cache it (fim_ensemble_tune).
+    Returns (rc, report)."""
+    count = len(members)
+    handles = (C.c_void_p * max(count, 1))(*[m.h for m in members])
+    rep = FimTuneReport()
+    path = cache_path.encode() if cache_path else None
+    rc = _check(lib().fim_ensemble_tune(count, handles, float(dt), int(trial_steps), path,
+                                        C.byref(rep)), "fim_ensemble_tune")
+    for m in members:
+        m.options.tile = tuple(rep.box)
+    return rc, rep

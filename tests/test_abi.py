@@ -186,3 +186,10 @@ def test_device_tensor_checks_reject_bad_tensors_before_any_launch():
                          torch.zeros(8, dtype=torch.float64), torch.zeros(8, dtype=torch.float64))
     with pytest.raises(fim.FimError, match="nb 4"):
         fim.fim_bsr_spmv(4, 4, rp, ci, None, None, None)
+
+
+def test_tuner_rejects_bad_arguments_without_a_device():
+    L = fim.lib()
+    rep = fim.FimTuneReport()
+    assert L.fim_ensemble_tune(0, None, 15.0, 1, None, C.byref(rep)) == fim.FIM_E_ARG
+    assert b"members are required" in L.fim_last_error()
