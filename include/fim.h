@@ -395,6 +395,16 @@ int fim_precond_apply(fim_ctx *ctx, const double *x, double *y);
 int fim_linear_solve(fim_ctx *ctx, const double *b, double *x, int32_t *iters,
                      double *relres);
 
+/* The pressure operator of AMG level `level` of the CPR first stage (Sec.
+ * 5.1: AMG on the pressure equation) at the last assembled Jacobian (the
+ * preconditioner is set up first when needed): dims = {nx, ny, nz, nwells}
+ * of the level; A (may be NULL) receives it as a dense row-major matrix of
+ * (nx*ny*nz + nwells)^2 entries, cells in natural order, then wells.  Level
+ * 0 is the quasi-IMPES pressure matrix, level l + 1 the Galerkin product of
+ * level l with the piecewise-constant interpolation of 2x2x2 aggregates
+ * (wells their own aggregates).  FIM_E_ARG without a CPR preconditioner. */
+int fim_amg_level(fim_ctx *ctx, int32_t level, int32_t *dims, double *A);
+
 /* The matrix-vector product inside the Krylov solver of Sec. 5.1: y = A x
  * for a canonical BSR matrix of nrows block rows with nb in {2,3}
  * (rowptr[nrows+1] and colind[nnzb] int32, val[nnzb*nb*nb] float64 row-major

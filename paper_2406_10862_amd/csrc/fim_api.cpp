@@ -3227,6 +3227,74 @@ int fim_linear_solve(fim_ctx *c, const double *bh, double *xh, int32_t *iters, d
     });
 }
 
+int fim_amg_level(fim_ctx *c, int32_t level, int32_t *dims, double *A) {
+    return guarded([&] {
+        REQUIRE(c && dims, "context and dims are required");
+        REQUIRE(uses_cpr(c->opt), "the context's preconditioner has no AMG stage");
+        REQUIRE(level >= 0 && level < (int)c->lv.size(), "level %d of %zu", level, c->lv.size());
+        if (!c->jac_ready) {
+            set_err("no assembled Jacobian (call fim_assemble first)");
+            throw StateError();
+        }
+        if (!c->prec_ready) prec_setup(c);
+        const AmgLevel &L = c->lv[level];
+        dims[0] = L.nx;
+        dims[1] = L.ny;
+        dims[2] = L.nz;
+        dims[3] = L.nw;
+        if (!A) return FIM_OK;
+        const int ncs = 2 * L.half, nc = L.nx * L.ny * L.nz, N = nc + L.nw;
+        std::vector<double> a((size_t)7 * ncs), aww(std::max(L.nw, 1)), acw(std::max(L.nslot, 1)),
+            awc(std::max(L.nslot, 1));
+        std::vector<int> cps(ncs + 1), cslot(std::max(L.nslot, 1)), swell(std::max(L.nslot, 1)),
+            scell(std::max(L.nslot, 1)), sps(L.nw + 1);
+        auto get = [&](void *dst, const void *src, size_t bytes) {
+            if (bytes) HIPCHECK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, c->s));
+        };
+        get(a.data(), L.a, a.size() * 8);
+        get(aww.data(), L.aww, (size_t)L.nw * 8);
+        get(acw.data(), L.acw, (size_t)L.nslot * 8);
+        get(awc.data(), L.awc, (size_t)L.nslot * 8);
+        get(cps.data(), L.cps, cps.size() * 4);
+        get(cslot.data(), L.cslot, (size_t)L.nslot * 4);
+        get(swell.data(), L.swell, (size_t)L.nslot * 4);
+        get(scell.data(), L.scell, (size_t)L.nslot * 4);
+        get(sps.data(), L.sps, sps.size() * 4);
+        c->sync();
+        // split index (colour * half + (c >> 1), c = i + nxp (j + ny k)) <-> natural cell
+        std::vector<int> nat_of(ncs, -1);
+        auto split = [&](int i, int j, int k) {
+            const int cc = i + L.nxp * (j + L.ny * k);
+            return (((i + j + k) & 1) ? L.half : 0) + (cc >> 1);
+        };
+        for (int k = 0; k < L.nz; ++k)
+            for (int j = 0; j < L.ny; ++j)
+                for (int i = 0; i < L.nx; ++i) nat_of[split(i, j, k)] = i + L.nx * (j + L.ny * k);
+        std::fill(A, A + (size_t)N * N, 0.0);
+        const int di[7] = {0, -1, 1, 0, 0, 0, 0}, dj[7] = {0, 0, 0, -1, 1, 0, 0},
+                  dk[7] = {0, 0, 0, 0, 0, -1, 1};
+        for (int k = 0; k < L.nz; ++k)
+            for (int j = 0; j < L.ny; ++j)
+                for (int i = 0; i < L.nx; ++i) {
+                    const int sp = split(i, j, k), row = i + L.nx * (j + L.ny * k);
+                    for (int d = 0; d < 7; ++d) {
+                        const int ni = i + di[d], nj = j + dj[d], nk = k + dk[d];
+                        if (ni < 0 || nj < 0 || nk < 0 || ni >= L.nx || nj >= L.ny || nk >= L.nz)
+                            continue;
+                        A[(size_t)row * N + ni + L.nx * (nj + L.ny * nk)] += a[(size_t)d * ncs + sp];
+                    }
+                    for (int q = cps[sp]; q < cps[sp + 1]; ++q)
+                        A[(size_t)row * N + nc + swell[cslot[q]]] += acw[cslot[q]];
+                }
+        for (int w = 0; w < L.nw; ++w) {
+            const size_t row = (size_t)(nc + w) * N;
+            A[row + nc + w] += aww[w];
+            for (int q = sps[w]; q < sps[w + 1]; ++q) A[row + nat_of[scell[q]]] += awc[q];
+        }
+        return FIM_OK;
+    });
+}
+
 int fim_bsr_spmv(int32_t nrows, int32_t nb, const int32_t *rowptr, const int32_t *colind,
                  const double *val, const double *x, double *y, void *hip_stream) {
     return guarded([&] {

@@ -96,7 +96,7 @@ EXPORTS = ["fim_create", "fim_destroy", "fim_last_error", "fim_sizes", "fim_set_
            "fim_get_well_rates", "fim_static", "fim_set_iterate", "fim_props",
            "fim_assemble", "fim_precond_apply", "fim_linear_solve", "fim_bsr_spmv",
            "fim_ensemble_run", "fim_adjoint_gradient", "fim_step_noalloc", "fim_set_perm",
-           "fim_set_perm_dev", "fim_ensemble_tune"]
+           "fim_set_perm_dev", "fim_ensemble_tune", "fim_amg_level"]
 
 _LIB = None
 
@@ -146,6 +146,7 @@ def lib():
     L.fim_adjoint_gradient.argtypes = [vp, C.c_int32, f64p, f64p, C.c_int32, f64p,
                                        C.POINTER(FimAdjointReport)]
     L.fim_set_perm.argtypes = [vp, f64p, f64p, f64p]
+    L.fim_amg_level.argtypes = [vp, C.c_int32, i32p, f64p]
     L.fim_ensemble_tune.argtypes = [C.c_int32, C.POINTER(vp), C.c_double, C.c_int32, C.c_char_p,
                                     C.POINTER(FimTuneReport)]
     L.fim_set_perm_dev.argtypes = [vp, vp, vp, vp]
@@ -423,6 +424,25 @@ class Fim:
         _check(lib().fim_assemble(self.h, float(dt), _p(R, f64p), _p(rowptr, i32p),
                                   _p(colind, i32p), _p(val, f64p)), "fim_assemble")
         return R, rowptr, colind, val
+
+    def fim_amg_level(self, level):
+        """Dense pressure operator of one AMG level of the CPR stage (cells in
+        natural order, then wells) and its dims (nx, ny, nz, nwells)."""
+        dims = np.zeros(4, np.int32)
+        _check(lib().fim_amg_level(self.h, int(level), _p(dims, i32p), None), "fim_amg_level")
+        N = int(dims[0] * dims[1] * dims[2] + dims[3])
+        A = np.zeros((N, N))
+        _check(lib().fim_amg_level(self.h, int(level), _p(dims, i32p), _p(A, f64p)),
+               "fim_amg_level")
+        return A, tuple(int(v) for v in dims)
+
+    def fim_amg_levels(self):
+        """Number of AMG levels of the CPR stage."""
+        dims = np.zeros(4, np.int32)
+        n = 0
+        while lib().fim_amg_level(self.h, n, _p(dims, i32p), None) == FIM_OK:
+            n += 1
+        return n
 
     def fim_precond_apply(self, x):
         x = _f64(x)

@@ -1,0 +1,103 @@
+"""GPU pins of the CPR pressure hierarchy (Sec. 5.1: a pressure stage solved
+by AMG inside the block preconditioner) against the definitions, with no
+oracle code involved:
+
+* level 0 is the quasi-IMPES pressure matrix: every cell row of the
+  Jacobian combined with the first row of its diagonal block's inverse
+  (scaled to max |w| = 1), the pressure column of each block kept; a well
+  row keeps its own (BHP) entries;
+* level l + 1 is the Galerkin product P^T A_l P of level l with the
+  piecewise-constant interpolation of 2 x 2 x 2 aggregates (ragged at odd
+  dimensions), every well its own aggregate.
+
+Each level is checked against the product of the level above as the GPU
+holds it, so an error in one coarsening shows up at that level."""
+import numpy as np
+import pytest
+
+from paper_2406_10862_amd import fim, reservoirs as rv
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    print(f"\n[gpu case] {request.node.nodeid}", flush=True)
+    yield
+
+
+def _dense_pressure(g, rowptr, colind, val, nb):
+    n, nw = g.n, g.nrows - g.n
+    N = n + nw
+    blocks = val.reshape(-1, nb, nb)
+    A = np.zeros((N, N))
+    for r in range(N):
+        q0, q1 = rowptr[r], rowptr[r + 1]
+        if r < n:
+            d = next(blocks[q] for q in range(q0, q1) if colind[q] == r)
+            w = np.linalg.inv(d)[0]
+            m = np.abs(w).max()
+            w = w / m if np.isfinite(m) and m > 0 else np.eye(nb)[0]
+            for q in range(q0, q1):
+                A[r, colind[q]] += w @ blocks[q][:, 0]
+        else:
+            for q in range(q0, q1):
+                A[r, colind[q]] += blocks[q][0, 0]
+    return A
+
+
+def _interp(dims_f, dims_c):
+    nx, ny, nz, nw = dims_f
+    cx, cy, cz, cw = dims_c
+    assert cw == nw and (cx, cy, cz) == (-(-nx // 2), -(-ny // 2), -(-nz // 2))
+    nf, nc = nx * ny * nz, cx * cy * cz
+    P = np.zeros((nf + nw, nc + nw))
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                P[i + nx * (j + ny * k), i // 2 + cx * (j // 2 + cy * (k // 2))] = 1.0
+    P[nf:, nc:] = np.eye(nw)
+    return P
+
+
+@pytest.mark.parametrize("cfg", ["c5", "c3"])
+def test_pressure_hierarchy_is_quasi_impes_then_galerkin(cfg):
+    if cfg == "c5":
+        res = rv.config_c5(13, 10, 5)           # two phases, odd x and z
+    else:
+        res = rv.config_c3(9, 7, 5)             # three phases, every dimension odd
+    g = fim.Fim(res, options=rv.Options(precond=rv.PREC_CPR_ILU0, tile=(5, 5, 3)))
+    g.set_initial_state()
+    dt = float(res.schedule[0])
+    assert g.fim_step(dt)[0] == fim.FIM_OK      # a state away from the initial one
+    _, rowptr, colind, val = g.fim_assemble(dt)
+    nl = g.fim_amg_levels()
+    assert nl >= 2
+    A0, dims0 = g.fim_amg_level(0)
+    assert dims0 == (res.nx, res.ny, res.nz, len(res.wells))
+    ref = _dense_pressure(g, rowptr, colind, val, g.nb)
+    scale = np.abs(ref).max()
+    err = np.abs(A0 - ref).max() / scale
+    print(f"{cfg}: {nl} levels; level 0 {dims0} error {err:.1e}")
+    assert err <= 1e-13
+    prev, dprev = A0, dims0
+    for lvl in range(1, nl):
+        A, dims = g.fim_amg_level(lvl)
+        P = _interp(dprev, dims)
+        gal = P.T @ prev @ P
+        err = np.abs(A - gal).max() / np.abs(gal).max()
+        print(f"  level {lvl} {dims}: Galerkin error {err:.1e}")
+        assert err <= 1e-13
+        # a coarse well row and column carry the sums of the fine couplings
+        assert np.array_equal(A[-dims[3]:, -dims[3]:] != 0, gal[-dims[3]:, -dims[3]:] != 0)
+        prev, dprev = A, dims
+    assert dprev[0] * dprev[1] * dprev[2] <= 64
+
+
+def test_amg_level_rejects_contexts_without_cpr():
+    res = rv.config_c5(8, 6, 3)
+    g = fim.Fim(res, options=rv.Options(precond=rv.PREC_ILU0))
+    g.set_initial_state()
+    g.fim_assemble(float(res.schedule[0]))
+    with pytest.raises(fim.FimError, match="AMG"):
+        g.fim_amg_level(0)
