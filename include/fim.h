@@ -162,10 +162,14 @@ typedef struct {
  * launched separately; the result is the same bit for bit).  amg_seg_rows:
  * AMG levels with at least this many cells of each colour restrict by row
  * segments (0 = default 2^18, negative = never; the sums are the same bit for
- * bit either way).  profile != 0
- * has every Krylov SpMV launch of fim_step stamp its own start and end into
- * a pair of HIP events and reports the summed kernel time in
- * fim_step_report.  precision FIM_MIXED (with an ILU(0)
+ * bit either way).  gs_refine: the Arnoldi orthogonalisation is classical
+ * Gram-Schmidt; 1 adds a second pass whenever the first one cancelled more
+ * than 90% of the vector's norm, -1 never adds one (a single classical pass,
+ * PETSc's default for its GMRES family), 0 = default (-1).  reserved must be
+ * 0.  profile = k > 0
+ * has every k-th Krylov SpMV launch of fim_step (k = 1: every one) stamp
+ * its own start and end into a pair of HIP events and reports the summed
+ * kernel time of the stamped launches and their count in fim_step_report.  precision FIM_MIXED (with an ILU(0)
  * preconditioner) runs every GMRES restart cycle in single precision: a
  * float copy of the Jacobian, float Krylov vectors, ILU(0) factors and
  * pressure column (sums in double), stopping after a 1e-5 reduction; each
@@ -177,14 +181,16 @@ typedef struct {
     int32_t max_newton, max_lin, restart, max_cuts;
     int32_t precond, precision, profile, amg_cycle, amg_sweeps, graphs, forcing, amg_fused;
     int32_t tile_nx, tile_ny, tile_nz, amg_seg_rows;
+    int32_t gs_refine, reserved;
 } fim_options;
 
 #define FIM_MAX_SUB 256
 typedef struct {
-    int32_t newton_iters, linear_iters, cuts, converged, nsub, spmv_calls;
+    int32_t newton_iters, linear_iters, cuts, converged, nsub;
+    int32_t spmv_calls;                      /* SpMV launches stamped (options.profile) */
     double dt_done, cnv[3], mb[3];
     double t_assemble, t_linear, t_update;   /* device ms per phase */
-    double spmv_ms;                          /* summed SpMV kernel ms (HIP events) */
+    double spmv_ms;                          /* their summed kernel ms (HIP events) */
     double last_dp, last_ds, well_res;       /* last Newton check: update sizes, well measure */
     double dt_sub[FIM_MAX_SUB];              /* accepted sub-step sizes (days) */
 } fim_step_report;

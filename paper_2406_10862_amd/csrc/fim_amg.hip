@@ -589,6 +589,7 @@ __device__ inline double read_cell(const AmgLevel &L, const AmgLevel &C, int mod
 template <int M>
 __device__ inline double read_well(const AmgLevel &L, const AmgLevel &C, int mode, int w) {
     const int m = M >= 0 ? M : mode;
+    if (m & kWellsSnap) return L.xs[w];
     if (m & kWellsZero) return 0.0;
     double v = L.x[2 * L.half + w];
     if (m & kWellsCorr) v += C.x[2 * C.half + w];
@@ -641,9 +642,17 @@ __device__ inline double red_from_zero(const AmgLevel &L, int s) { return L.b[s]
 
 // (red and black values of entry h; padded cells computed and dropped)
 template <bool Early>
+__device__ inline double presmooth_black(const AmgLevel &L, int h);
+
+template <bool Early>
 __device__ inline void presmooth_values(const AmgLevel &L, int h, double &red, double &black) {
     const double r0 = red_from_zero(L, h);
     red = (pos_of(L, h).i >= L.nx) ? 0.0 : r0;
+    black = presmooth_black<Early>(L, h);
+}
+
+template <bool Early>
+__device__ inline double presmooth_black(const AmgLevel &L, int h) {
     const int s = L.half + h;
     const Pos p = pos_of(L, s);
     const int stride = 2 * L.half;
@@ -657,7 +666,7 @@ __device__ inline void presmooth_values(const AmgLevel &L, int h, double &red, d
         acc -= L.a[(size_t)d * stride + s] * red_from_zero(L, in ? ns : s);
     }
     for (int q = L.cps[s]; q < L.cps[s + 1]; ++q) acc -= L.acw[L.cslot[q]] * 0.0;
-    black = Early ? (pad ? 0.0 : acc) / (pad ? 1.0 : dg) : (pad ? 0.0 : acc / L.a[s]);
+    return Early ? (pad ? 0.0 : acc) / (pad ? 1.0 : dg) : (pad ? 0.0 : acc / L.a[s]);
 }
 
 template <bool Early = false>
@@ -668,38 +677,85 @@ __device__ inline void presmooth_item(const AmgLevel &L, int h) {
     L.x[L.half + h] = black;
 }
 
-__global__ __launch_bounds__(kBlock) void k_amg_presmooth(AmgLevel L) {
-    const int h = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (h < L.half) presmooth_item<true>(L, h);
-}
-
-template <int M>
-__global__ __launch_bounds__(kBlock) void k_amg_sweep(AmgLevel L, AmgLevel C, int color,
-                                                      int mode) {
-    const int h = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (h < L.half) sweep_item<M, true>(L, C, color, mode, h);
-}
-
-// wells: one wave per well, lanes stride over its slots
-__device__ inline double well_row_sum(const AmgLevel &L, int w, int lane) {
+// wells: one wave per well, lanes stride over its slots; xcell(s) gives
+// the value of the cell with split index s
+template <class XC>
+__device__ inline double well_row_sum_of(const AmgLevel &L, int w, int lane, XC xcell) {
     double acc = 0.0;
-    for (int q = L.sps[w] + lane; q < L.sps[w + 1]; q += 64) acc += L.awc[q] * L.x[L.scell[q]];
+    for (int q = L.sps[w] + lane; q < L.sps[w + 1]; q += 64) acc += L.awc[q] * xcell(L.scell[q]);
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
     return acc;
 }
 
-// (every lane reads the row's b and diagonal with its slots and stores the
-// same value, so no load waits behind the reduction and a lane-0 branch)
-__device__ inline void well_sweep_item(const AmgLevel &L, int w, int lane) {
+__device__ inline double well_row_sum(const AmgLevel &L, int w, int lane) {
+    return well_row_sum_of(L, w, lane, [&](int s) { return L.x[s]; });
+}
+
+// The Gauss-Seidel value of well w from the cell values xcell.  (Every lane
+// reads the row's b and diagonal with its slots and stores the same value,
+// so no load waits behind the reduction and a lane-0 branch.)
+template <class XC>
+__device__ inline void well_sweep_of(const AmgLevel &L, int w, int lane, XC xcell) {
     const double bw = L.b[2 * L.half + w], aw = L.aww[w];
-    const double sum = well_row_sum(L, w, lane);
+    const double sum = well_row_sum_of(L, w, lane, xcell);
     L.x[2 * L.half + w] = (bw - sum) / aw;
 }
 
-__global__ __launch_bounds__(kBlock) void k_amg_well_sweep(AmgLevel L) {
-    const int w = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    if (w < L.nw) well_sweep_item(L, w, threadIdx.x & 63);
+__device__ inline void well_sweep_item(const AmgLevel &L, int w, int lane) {
+    well_sweep_of(L, w, lane, [&](int s) { return L.x[s]; });
+}
+
+// The launched smoothing folds each well sweep into the kernel before it:
+// its first well_blocks blocks (dispatched first, so their chain of
+// dependent loads overlaps the cells' work; a multiple of the XCD count, so
+// the cell blocks keep their XCD mapping) take one wave per well and form
+// the cell values of the well's slots themselves, exactly as the cell
+// blocks compute them (a red value from the previous kernel, a black one
+// recomputed), so the well's value is that of a separate well sweep after
+// the kernel, bit for bit.  While the cell blocks run, the wells' old
+// values must stay readable: a colour-1 sweep reads them from the snapshot
+// L.xs that the colour-0 sweep before it wrote (kWellsSnap), and the first
+// pre-smoothing reads none (its wells are zero).
+__device__ inline int well_wave() { return ((int)blockIdx.x * kBlock + (int)threadIdx.x) >> 6; }
+
+__global__ __launch_bounds__(kBlock) void k_amg_presmooth(AmgLevel L, int well_blocks) {
+    if ((int)blockIdx.x >= well_blocks) {
+        const int nb = (int)gridDim.x - well_blocks;
+        const int h = xcd_block((int)blockIdx.x - well_blocks, nb) * blockDim.x + threadIdx.x;
+        if (h < L.half) presmooth_item<true>(L, h);
+        return;
+    }
+    const int w = well_wave();
+    if (w < L.nw)
+        well_sweep_of(L, w, threadIdx.x & 63, [&](int s) {
+            if (s >= L.half) return presmooth_black<true>(L, s - L.half);
+            return pos_of(L, s).i >= L.nx ? 0.0 : red_from_zero(L, s);
+        });
+}
+
+// Colour 0 (its well blocks store the snapshot of the wells' values as
+// read in mode) or colour 1 (mode includes kWellsSnap; its well blocks
+// compute the wells' Gauss-Seidel values).
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_amg_sweep(AmgLevel L, AmgLevel C, int color, int mode,
+                                                      int well_blocks) {
+    if ((int)blockIdx.x >= well_blocks) {
+        const int nb = (int)gridDim.x - well_blocks;
+        const int h = xcd_block((int)blockIdx.x - well_blocks, nb) * blockDim.x + threadIdx.x;
+        if (h < L.half) sweep_item<M, true>(L, C, color, mode, h);
+        return;
+    }
+    const int w = well_wave(), lane = threadIdx.x & 63;
+    if (w >= L.nw) return;
+    if (color == 0) {
+        if (lane == 0) L.xs[w] = read_well<M>(L, C, mode, w);
+        return;
+    }
+    well_sweep_of(L, w, lane, [&](int s) {
+        if (s < L.half) return L.x[s];
+        return sweep_value<M, true>(L, C, 1, mode, s - L.half);
+    });
 }
 
 __device__ inline double cell_residual(const AmgLevel &L, int s, const Pos &p) {
@@ -1179,30 +1235,43 @@ void launch_amg_coarsest_solve(hipStream_t s, const AmgLevel &L, const double *M
     hipLaunchKernelGGL(k_dense_gemv, grid_for((long)n, 256), dim3(256), 0, s, n, Minv, L.b, L.x);
 }
 
+// blocks of the wells (one wave each, rounded up to whole XCD rounds),
+// then those of the cells
+static inline int well_blocks_of(const AmgLevel &L) {
+    const int wb = (int)((64L * L.nw + kBlock - 1) / kBlock);
+    return (wb + kXcds - 1) / kXcds * kXcds;
+}
+static inline dim3 smooth_grid(const AmgLevel &L) {
+    return dim3((unsigned)(well_blocks_of(L) + (L.half + kBlock - 1) / kBlock));
+}
+
 void launch_amg_sweep(hipStream_t s, const AmgLevel &L, const AmgLevel &C, int color, int mode) {
-    const dim3 grid = grid_for(L.half, kBlock), block(kBlock);
+    // colour 1 reads the wells from the snapshot the colour-0 sweep took
+    if (color == 1) mode |= kWellsSnap;
+    const dim3 grid = smooth_grid(L), block(kBlock);
+    const int cb = well_blocks_of(L);
     switch (mode) {
-        case 0:
-            hipLaunchKernelGGL(k_amg_sweep<0>, grid, block, 0, s, L, C, color, mode);
-            break;
-        case kWellsCorr:
-            hipLaunchKernelGGL(k_amg_sweep<kWellsCorr>, grid, block, 0, s, L, C, color, mode);
-            break;
         case kCellsCorr | kWellsCorr:
             hipLaunchKernelGGL(k_amg_sweep<kCellsCorr | kWellsCorr>, grid, block, 0, s, L, C,
-                               color, mode);
+                               color, mode, cb);
+            break;
+        case kWellsCorr | kWellsSnap:
+            hipLaunchKernelGGL(k_amg_sweep<kWellsCorr | kWellsSnap>, grid, block, 0, s, L, C,
+                               color, mode, cb);
+            break;
+        case 0:
+            hipLaunchKernelGGL(k_amg_sweep<0>, grid, block, 0, s, L, C, color, mode, cb);
+            break;
+        case kWellsSnap:
+            hipLaunchKernelGGL(k_amg_sweep<kWellsSnap>, grid, block, 0, s, L, C, color, mode, cb);
             break;
         default:
-            hipLaunchKernelGGL(k_amg_sweep<-1>, grid, block, 0, s, L, C, color, mode);
+            hipLaunchKernelGGL(k_amg_sweep<-1>, grid, block, 0, s, L, C, color, mode, cb);
     }
 }
 
 void launch_amg_presmooth(hipStream_t s, const AmgLevel &L) {
-    hipLaunchKernelGGL(k_amg_presmooth, grid_for(L.half, kBlock), dim3(kBlock), 0, s, L);
-}
-
-void launch_amg_well_sweep(hipStream_t s, const AmgLevel &L) {
-    if (L.nw) hipLaunchKernelGGL(k_amg_well_sweep, grid_for(64L * L.nw, kBlock), dim3(kBlock), 0, s, L);
+    hipLaunchKernelGGL(k_amg_presmooth, smooth_grid(L), dim3(kBlock), 0, s, L, well_blocks_of(L));
 }
 
 void launch_amg_restrict(hipStream_t s, const AmgLevel &F, const AmgLevel &C, long seg_min) {

@@ -98,6 +98,7 @@ struct fim_ctx {
     hipStream_t user_s = nullptr;     // the caller's stream the work is ordered after
     hipEvent_t ev_user = nullptr;
     hipGraphExec_t step_exec[kMaxRestart] = {};   // Arnoldi step j after its SpMV
+    hipGraphExec_t step_full[kMaxRestart] = {};   // Arnoldi step j with its SpMV
     int dev = 0;
     fim_options opt{};
     Grid g{};
@@ -163,6 +164,7 @@ struct fim_ctx {
     int spmv_used = 0;
     double spmv_ms = 0.0;
     int spmv_calls = 0;
+    long spmv_seq = 0;                        // solver SpMVs since the context was made
     // discrete adjoint: the state after every accepted sub-step of the
     // forward run and the work arrays of the backward sweep
     double *wi_dk = nullptr;                        // [nperf] 1: WI ~ k (Peaceman), 0: explicit
@@ -223,11 +225,12 @@ struct fim_ctx {
     }
 
     void drop_graphs() {
-        for (auto &g : step_exec)
-            if (g) {
-                (void)hipGraphExecDestroy(g);
-                g = nullptr;
-            }
+        for (auto *set : {step_exec, step_full})
+            for (int j = 0; j < kMaxRestart; ++j)
+                if (set[j]) {
+                    (void)hipGraphExecDestroy(set[j]);
+                    set[j] = nullptr;
+                }
     }
 
     ~fim_ctx() {
@@ -270,6 +273,9 @@ static void check_options(const fim_options *o) {
                 o->precond == FIM_PREC_CPR_ILU0,
             "mixed precision needs an ILU(0) preconditioner (FIM_PREC_ILU0 or FIM_PREC_CPR_ILU0)");
     REQUIRE(o->amg_fused <= (1 << 20), "amg_fused must be at most 2^20 cells");
+    REQUIRE(o->gs_refine >= -1 && o->gs_refine <= 1, "gs_refine must be -1, 0 or 1");
+    REQUIRE(o->profile >= 0, "profile must be >= 0");
+    REQUIRE(o->reserved == 0, "reserved must be 0");
 }
 
 static void build_pattern(fim_ctx *c, std::vector<int> &rp, std::vector<int> &ci,
@@ -365,6 +371,7 @@ static void build_amg(fim_ctx *c, const std::vector<int> &sorted_cells,
         L.awc = c->alloc<double>(std::max(L.nslot, 1));
         L.x = c->alloc<double>(ncs + nw);
         L.b = c->alloc<double>(ncs + nw);
+        L.xs = c->alloc<double>(std::max(nw, 1));
         launch_scale_copy(c->s, ncs + nw, nullptr, 0.0, L.x);
         launch_scale_copy(c->s, ncs + nw, nullptr, 0.0, L.b);
         if (c->lv.empty()) {
@@ -792,10 +799,13 @@ static void amg_cycle(fim_ctx *c, int l, std::vector<int> *rec = nullptr, int ro
         if (rec) rec->push_back(amg_op(kOpSweep, rl, color, mode));
         else launch_amg_sweep(c->s, F, C, color, mode);
     };
+    // a launched well sweep is folded into the presmoothing or colour-1
+    // sweep before it (which then reads the wells from the snapshot the
+    // colour-0 sweep took); in one workgroup it stays a phase of its own,
+    // which is cheaper there than the recomputation the folding needs
     auto wells = [&] {
         if (F.nw == 0) return;
         if (rec) rec->push_back(amg_op(kOpWells, rl));
-        else launch_amg_well_sweep(c->s, F);
     };
     for (int sw = 0; sw < nu; ++sw) {
         if (sw == 0) {                          // both colours from a zero iterate
@@ -1167,11 +1177,17 @@ static void precondition(fim_ctx *c, const WT *w, const double *hptr, T *v, T *z
     }
 }
 
-// SpMV inside the solver (y = J x in T); when profiling, the launch stamps
-// the kernel's start and end into a pair of events
+// Whether the next solver SpMV stamps its start and end into a pair of
+// events: every opt.profile-th one when profiling (a stamp costs the launch
+// a wait of its own)
+static bool next_spmv_stamped(fim_ctx *c, bool profile) {
+    return profile && c->spmv_seq++ % c->opt.profile == 0;
+}
+
+// SpMV inside the solver (y = J x in T), stamped or not
 template <class T>
-static void solver_spmv(fim_ctx *c, const T *xin, T *yout, bool profile) {
-    if (profile) {
+static void solver_spmv(fim_ctx *c, const T *xin, T *yout, bool stamp) {
+    if (stamp) {
         if (c->spmv_used + 2 > (int)c->spmv_ev.size()) {
             // pool full: drain it
             HIPCHECK(hipEventSynchronize(c->spmv_ev[c->spmv_used - 1]));
@@ -1205,14 +1221,15 @@ static void drain_spmv_events(fim_ctx *c) {
 
 // ---------------------------------------------------------------------------
 // Flexible GMRES (right preconditioning, the preconditioned vectors Z kept)
-// with classical Gram-Schmidt and a DGKS-triggered second pass.  Solves
+// with classical Gram-Schmidt (a second, DGKS-triggered pass optional).  Solves
 // J x = b (b, x device vectors of the context), initial guess zero.  The host
 // stays one Arnoldi step behind the device: step j+1 is queued before the
 // Hessenberg column of step j is read.
 
-// Arnoldi step j after its SpMV (w = J z_j): two Gram-Schmidt passes (the
-// second gated on the device), the new basis vector and its preconditioned
-// image, and the copy of the Hessenberg column to pinned host memory.
+// Arnoldi step j after its SpMV (w = J z_j): a classical Gram-Schmidt pass
+// (and, with gs_refine = 1, a second one gated on the device), the new
+// basis vector and its preconditioned image; the Hessenberg column also
+// goes to pinned host memory.
 template <class T>
 static void arnoldi_rest(fim_ctx *c, int j) {
     const long nv = c->nvec;
@@ -1220,23 +1237,31 @@ static void arnoldi_rest(fim_ctx *c, int j) {
     double *col = c->H + (size_t)j * LD;
     double *pinH = c->pin + S_COUNT;
     T *V = Kry<T>::V(c), *Z = Kry<T>::Z(c), *w = Kry<T>::w(c);
+    const bool refine = c->opt.gs_refine > 0;
+    // the finishing kernels store the column in pinned host memory as well
+    // (a copy node at the end of the graph would cost a launch)
+    double *mirror = pinH + (size_t)j * LD;
     launch_multidot(c->s, nv, j + 1, V, w, c->partials, col, nullptr);
-    launch_update_norm(c->s, nv, j + 1, V, col, w, c->partials, col + j + 1, nullptr, c->reorth,
-                       nullptr);
-    launch_multidot(c->s, nv, j + 1, V, w, c->partials, c->tmp, c->reorth);
-    launch_update_norm(c->s, nv, j + 1, V, c->tmp, w, c->partials, col + j + 1, c->reorth,
-                       nullptr, col);
+    launch_update_norm(c->s, nv, j + 1, V, col, w, c->partials, col + j + 1, nullptr,
+                       refine ? c->reorth : nullptr, nullptr, mirror);
+    if (refine) {
+        launch_multidot(c->s, nv, j + 1, V, w, c->partials, c->tmp, c->reorth);
+        launch_update_norm(c->s, nv, j + 1, V, c->tmp, w, c->partials, col + j + 1, c->reorth,
+                           nullptr, col, mirror);
+    }
     precondition<T, T>(c, w, col + j + 1, V + (size_t)(j + 1) * nv, Z + (size_t)(j + 1) * nv);
-    HIPCHECK(hipMemcpyAsync(pinH + (size_t)j * LD, col, (j + 2) * sizeof(double),
-                            hipMemcpyDeviceToHost, c->s));
 }
 
+// Arnoldi step j as a captured graph: with its SpMV (w = J z_j) or, when
+// the SpMV was launched on its own (stamped), without it
 template <class T>
-static void arnoldi_rest_graph(fim_ctx *c, int j) {
-    if (!c->step_exec[j]) {
+static void arnoldi_graph(fim_ctx *c, int j, bool with_spmv) {
+    hipGraphExec_t &ex = with_spmv ? c->step_full[j] : c->step_exec[j];
+    if (!ex) {
         hipGraph_t graph = nullptr;
         HIPCHECK(hipStreamBeginCapture(c->s, hipStreamCaptureModeThreadLocal));
         try {
+            if (with_spmv) solver_spmv<T>(c, Kry<T>::Z(c) + (size_t)j * c->nvec, Kry<T>::w(c), false);
             arnoldi_rest<T>(c, j);
         } catch (...) {
             (void)hipStreamEndCapture(c->s, &graph);
@@ -1244,11 +1269,11 @@ static void arnoldi_rest_graph(fim_ctx *c, int j) {
             throw;
         }
         HIPCHECK(hipStreamEndCapture(c->s, &graph));
-        hipError_t e = hipGraphInstantiate(&c->step_exec[j], graph, nullptr, nullptr, 0);
+        hipError_t e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
         HIPCHECK(e);
     }
-    HIPCHECK(hipGraphLaunch(c->step_exec[j], c->s));
+    HIPCHECK(hipGraphLaunch(ex, c->s));
 }
 
 // Linear tolerance of a Newton iteration: the fixed lin_rtol, or the
@@ -1306,9 +1331,14 @@ static int gmres_t(fim_ctx *c, const double *bvec, double *xvec, int max_it, dou
     double relres = 1.0;
 
     auto enqueue = [&](int j) {
-        solver_spmv<T>(c, Z + (size_t)j * nv, w, profile);
-        if (c->opt.graphs) arnoldi_rest_graph<T>(c, j);
-        else arnoldi_rest<T>(c, j);
+        const bool stamp = next_spmv_stamped(c, profile);
+        if (c->opt.graphs && !stamp) {
+            arnoldi_graph<T>(c, j, true);
+        } else {
+            solver_spmv<T>(c, Z + (size_t)j * nv, w, stamp);
+            if (c->opt.graphs) arnoldi_graph<T>(c, j, false);
+            else arnoldi_rest<T>(c, j);
+        }
         HIPCHECK(hipEventRecord(colev[j], c->s));
     };
 
@@ -1885,6 +1915,7 @@ struct Ensemble {
     std::vector<int> flags;
     std::map<int, hipGraphExec_t> graphs;     // captured phases, by key
     bool use_graphs = true;
+    bool refine = true;        // the Gram-Schmidt second pass when cancelled
 
     template <typename T>
     T *dalloc(size_t count) {
@@ -1983,6 +2014,8 @@ void check_member(const fim_ctx *c, const fim_ctx *c0, int k) {
     REQUIRE(c->nb == c0->nb, "member %d: block size %d, member 0 has %d", k, c->nb, c0->nb);
     REQUIRE(c->dev == c0->dev, "member %d is on device %d, member 0 on %d", k, c->dev, c0->dev);
     REQUIRE(c->m == c0->m, "member %d: GMRES restart %d, member 0 has %d", k, c->m, c0->m);
+    REQUIRE((c->opt.gs_refine > 0) == (c0->opt.gs_refine > 0),
+            "member %d: Gram-Schmidt refinement differs from member 0's", k);
     REQUIRE(ilu_threads(c->ilu) == ilu_threads(c0->ilu),
             "member %d: ILU(0) boxes of %d threads, member 0's of %d", k, ilu_threads(c->ilu),
             ilu_threads(c0->ilu));
@@ -2007,6 +2040,7 @@ std::unique_ptr<Ensemble> make_ensemble(int count, fim_ctx *const *members) {
     for (int k = 0; k < count; ++k) check_member(members[k], c0, k);
     E->nb = c0->nb;
     E->m = c0->m;
+    E->refine = c0->opt.gs_refine > 0;
     HIPCHECK(hipSetDevice(c0->dev));
     HIPCHECK(hipStreamCreateWithFlags(&E->s, hipStreamNonBlocking));
     for (fim_ctx *c : E->mem) c->sync();       // every member's earlier work is done
@@ -2183,10 +2217,12 @@ void batch_arnoldi(Ensemble &E, int j, double *dcols, double *hcols, int ld) {
                      E.dotsum[j].total, j, false);
     launchb_update_norm(E.s, E.d_mem, E.batch(E.vec, kOnCycle), E.vec.total,
                         E.batch(E.one, kOnCycle), E.one.total, j, false);
-    launchb_multidot(E.s, E.d_mem, E.batch(dp, kOnCycle), dp.total, E.batch(E.dotsum[j], kOnCycle),
-                     E.dotsum[j].total, j, true);
-    launchb_update_norm(E.s, E.d_mem, E.batch(E.vec, kOnCycle), E.vec.total,
-                        E.batch(E.one, kOnCycle), E.one.total, j, true);
+    if (E.refine) {
+        launchb_multidot(E.s, E.d_mem, E.batch(dp, kOnCycle), dp.total,
+                         E.batch(E.dotsum[j], kOnCycle), E.dotsum[j].total, j, true);
+        launchb_update_norm(E.s, E.d_mem, E.batch(E.vec, kOnCycle), E.vec.total,
+                            E.batch(E.one, kOnCycle), E.one.total, j, true);
+    }
     batch_precondition(E, j);
     launchb_hcols(E.s, E.d_mem, E.batch(E.one, kOnCycle), E.one.total, j, dcols, ld);
     HIPCHECK(hipMemcpyAsync(hcols, dcols, (size_t)E.nm * ld * sizeof(double),

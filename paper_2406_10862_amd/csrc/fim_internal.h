@@ -97,6 +97,7 @@ struct AmgLevel {
     const int *cps;         // [2*half+1] split cell -> range in cslot
     const int *cslot;       // slot ids of each cell
     double *x, *b;          // [2*half + nw]: iterate, right-hand side
+    double *xs;             // [nw] the wells' values as the cells of a colour sweep read them
 };
 
 // ---- physics kernels (fim_phys.hip) ---------------------------------------
@@ -170,12 +171,13 @@ void launch_multidot(hipStream_t s, long nvec, int nv, const double *V, const do
                      double *partials, double *dst, const int *gate);
 void launch_multidot(hipStream_t s, long nvec, int nv, const float *V, const float *w,
                      double *partials, double *dst, const int *gate);
+// (mirror: see update_finish_body; nullptr for none)
 void launch_update_norm(hipStream_t s, long nvec, int nv, const double *V, const double *coef,
                         double *w, double *partials, double *hnext, const int *gate,
-                        int *reorth, double *hacc);
+                        int *reorth, double *hacc, double *mirror = nullptr);
 void launch_update_norm(hipStream_t s, long nvec, int nv, const float *V, const double *coef,
                         float *w, double *partials, double *hnext, const int *gate,
-                        int *reorth, double *hacc);
+                        int *reorth, double *hacc, double *mirror = nullptr);
 void launch_residual(hipStream_t s, long nvec, const double *b, const double *Ax, double *r,
                      double *partials, double *out);
 void launch_scale_copy(hipStream_t s, long nvec, const double *x, double a, double *y);
@@ -198,7 +200,6 @@ void launch_amg_coarsest_setup(hipStream_t s, const AmgLevel &L, double *M, doub
                                double *colk, int *bad);
 void launch_amg_coarsest_solve(hipStream_t s, const AmgLevel &L, const double *Minv);
 void launch_amg_sweep(hipStream_t s, const AmgLevel &L, const AmgLevel &C, int color, int mode);
-void launch_amg_well_sweep(hipStream_t s, const AmgLevel &L);
 void launch_amg_presmooth(hipStream_t s, const AmgLevel &L);
 // seg_min: levels with at least this many entries per colour restrict by
 // row segments (<= 0: never); the sums are the same bit for bit
@@ -217,7 +218,7 @@ void launch_cpr_restrict(hipStream_t s, int nb, int n, int nw, const AmgLevel &L
 void launch_cpr_finish(hipStream_t s, int nb, int n, int nw, const AmgLevel &L,
                        const int *split0, const int *colsplit, Sys sys, const double *ap,
                        const double *v, const double *dinv, double *z);
-enum { kCellsZero = 1, kCellsCorr = 2, kWellsZero = 4, kWellsCorr = 8 };
+enum { kCellsZero = 1, kCellsCorr = 2, kWellsZero = 4, kWellsCorr = 8, kWellsSnap = 16 };
 
 // ---- block-Jacobi ILU(0) over box subdomains (fim_ilu.hip) ------------------
 struct IluTiles {

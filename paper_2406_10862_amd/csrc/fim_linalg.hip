@@ -363,9 +363,13 @@ __global__ __launch_bounds__(kBlock) void k_update_norm(long nvec, int nv,
     update_norm_body<T>(blockIdx.x, gridDim.x, nvec, nv, V, coef, w, partials, gate);
 }
 
+// With mirror set, the finished column (hacc, or coef in a first pass:
+// nv coefficients and then hnext, which must follow them) is also stored
+// there, in pinned host memory, for the host's Givens rotations.
 __device__ __forceinline__ void update_finish_body(int nparts, int nv, const double *coef,
                                                    const double *partials, double *hnext,
-                                                   const int *gate, int *reorth, double *hacc) {
+                                                   const int *gate, int *reorth, double *hacc,
+                                                   double *mirror = nullptr) {
     if (gate && *gate == 0) return;
     const bool mx[1] = {false};
     double a[1];
@@ -375,37 +379,41 @@ __device__ __forceinline__ void update_finish_body(int nparts, int nv, const dou
             for (int i = 0; i < nv; ++i) hacc[i] += coef[i];
         if (reorth) *reorth = (a[0] < 1e-2 * coef[nv]) ? 1 : 0;
         *hnext = sqrt(a[0]);
+        if (mirror) {
+            const double *col = hacc ? hacc : coef;
+            for (int i = 0; i <= nv; ++i) mirror[i] = col[i];
+        }
     }
 }
 
 __global__ __launch_bounds__(kBlock) void k_update_finish(int nparts, int nv, const double *coef,
                                                           const double *partials, double *hnext,
                                                           const int *gate, int *reorth,
-                                                          double *hacc) {
-    update_finish_body(nparts, nv, coef, partials, hnext, gate, reorth, hacc);
+                                                          double *hacc, double *mirror) {
+    update_finish_body(nparts, nv, coef, partials, hnext, gate, reorth, hacc, mirror);
 }
 
 template <class T>
 static void update_norm_impl(hipStream_t s, long nvec, int nv, const T *V, const double *coef,
                              T *w, double *partials, double *hnext, const int *gate, int *reorth,
-                             double *hacc) {
+                             double *hacc, double *mirror) {
     const int nblk = vec_blocks(nvec);
     hipLaunchKernelGGL(k_update_norm<T>, dim3(nblk), dim3(kBlock), 0, s, nvec, nv, V, coef, w,
                        partials, gate);
     hipLaunchKernelGGL(k_update_finish, dim3(1), dim3(kBlock), 0, s, nblk, nv, coef, partials,
-                       hnext, gate, reorth, hacc);
+                       hnext, gate, reorth, hacc, mirror);
 }
 
 void launch_update_norm(hipStream_t s, long nvec, int nv, const double *V, const double *coef,
                         double *w, double *partials, double *hnext, const int *gate, int *reorth,
-                        double *hacc) {
-    update_norm_impl(s, nvec, nv, V, coef, w, partials, hnext, gate, reorth, hacc);
+                        double *hacc, double *mirror) {
+    update_norm_impl(s, nvec, nv, V, coef, w, partials, hnext, gate, reorth, hacc, mirror);
 }
 
 void launch_update_norm(hipStream_t s, long nvec, int nv, const float *V, const double *coef,
                         float *w, double *partials, double *hnext, const int *gate, int *reorth,
-                        double *hacc) {
-    update_norm_impl(s, nvec, nv, V, coef, w, partials, hnext, gate, reorth, hacc);
+                        double *hacc, double *mirror) {
+    update_norm_impl(s, nvec, nv, V, coef, w, partials, hnext, gate, reorth, hacc, mirror);
 }
 
 // r = b - Ax; out[0] = ||r||^2, out[1] = ||r||

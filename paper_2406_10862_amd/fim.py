@@ -62,7 +62,7 @@ class FimOptions(C.Structure):
                 ("profile", C.c_int32), ("amg_cycle", C.c_int32), ("amg_sweeps", C.c_int32),
                 ("graphs", C.c_int32), ("forcing", C.c_int32), ("amg_fused", C.c_int32),
                 ("tile_nx", C.c_int32), ("tile_ny", C.c_int32), ("tile_nz", C.c_int32),
-                ("amg_seg_rows", C.c_int32)]
+                ("amg_seg_rows", C.c_int32), ("gs_refine", C.c_int32), ("reserved", C.c_int32)]
 
 
 class FimStepReport(C.Structure):
@@ -230,11 +230,11 @@ def options_struct(o: rv.Options, profile=False) -> FimOptions:
                       tol_well=o.tol_well, ds_max=o.ds_max, dp_max=o.dp_max,
                       lin_rtol=o.lin_rtol, max_newton=o.max_newton, max_lin=o.max_lin,
                       restart=o.restart, max_cuts=o.max_cuts, precond=o.precond,
-                      precision=o.precision, profile=1 if profile else 0,
+                      precision=o.precision, profile=int(profile),
                       amg_cycle=o.amg_cycle, amg_sweeps=o.amg_sweeps, graphs=o.graphs,
                       forcing=o.forcing, amg_fused=o.amg_fused,
                       tile_nx=o.tile[0], tile_ny=o.tile[1], tile_nz=o.tile[2],
-                      amg_seg_rows=o.amg_seg_rows)
+                      amg_seg_rows=o.amg_seg_rows, gs_refine=o.gs_refine)
 
 
 class Fim:

@@ -99,6 +99,7 @@ class Options:
     amg_fused: int = 0          # cells below which the AMG cycle runs fused (0 default, <0 off)
     tile: tuple = (0, 0, 0)     # block-Jacobi ILU(0) subdomain box (0 = 8 cells per axis)
     amg_seg_rows: int = 0       # entries per colour from which AMG restricts by row segments
+    gs_refine: int = 0          # Gram-Schmidt second pass: 1 when cancelled, -1 never, 0 default (never)
 
 
 @dataclass
