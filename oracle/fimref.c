@@ -1130,7 +1130,11 @@ static int solve_linear(const fr_model *m, const double *val, const double *R, d
     double *rhs = (double *)xcalloc(nu, sizeof(double));
     for (size_t i = 0; i < nu; ++i) rhs[i] = -R[i];
     int ok = 0;
-    if ((int)nu <= o->dense_max) {
+    if (o->linsolve) {
+        int32_t it = 0;
+        ok = o->linsolve(o->linsolve_ctx, nrows, nb, m->rowptr, m->colind, val, rhs, dx, &it) == 0;
+        *iters = it;
+    } else if ((int)nu <= o->dense_max) {
         double *A = (double *)xcalloc(nu * nu, sizeof(double));
         for (int r = 0; r < nrows; ++r)
             for (int q = m->rowptr[r]; q < m->rowptr[r + 1]; ++q)

@@ -58,11 +58,22 @@ typedef struct {
     const double *wperf_wi;              /* [nperf]; <= 0 selects Peaceman */
 } fr_input;
 
+/* A caller-supplied solver of J x = rhs (J in the BSR layout of
+ * fr_assemble, x returned, *iters its iteration count); 0 on success.  It
+ * replaces the solver choice below, e.g. by a sparse direct solve for grids
+ * where GMRES with BILU(0) stalls. */
+typedef int32_t (*fr_linsolve_fn)(void *ctx, int32_t nrows, int32_t nb, const int32_t *rowptr,
+                                  const int32_t *colind, const double *val, const double *rhs,
+                                  double *x, int32_t *iters);
+
 typedef struct {
     double tol_cnv, tol_mb, tol_dp, tol_ds, tol_well;
     double ds_max, dp_max, lin_rtol;
     int32_t max_newton, max_lin, restart, max_cuts;
     int32_t dense_max;                   /* dense LU when unknowns <= this */
+    int32_t pad;
+    fr_linsolve_fn linsolve;             /* NULL: dense LU or GMRES with BILU(0) */
+    void *linsolve_ctx;
 } fr_options;
 
 #define FR_MAX_SUB 256

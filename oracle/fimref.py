@@ -45,8 +45,15 @@ class FrOptions(C.Structure):
         ("tol_ds", C.c_double), ("tol_well", C.c_double),
         ("ds_max", C.c_double), ("dp_max", C.c_double), ("lin_rtol", C.c_double),
         ("max_newton", C.c_int32), ("max_lin", C.c_int32), ("restart", C.c_int32),
-        ("max_cuts", C.c_int32), ("dense_max", C.c_int32),
+        ("max_cuts", C.c_int32), ("dense_max", C.c_int32), ("pad", C.c_int32),
+        ("linsolve", C.c_void_p), ("linsolve_ctx", C.c_void_p),
     ]
+
+
+# signature of FrOptions.linsolve (a ctypes callback; keep a reference to it)
+LINSOLVE_FN = C.CFUNCTYPE(C.c_int32, C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_int32),
+                          C.POINTER(C.c_int32), C.POINTER(C.c_double), C.POINTER(C.c_double),
+                          C.POINTER(C.c_double), C.POINTER(C.c_int32))
 
 
 MAX_SUB = 256
