@@ -193,6 +193,8 @@ typedef struct {
     double spmv_ms;                          /* their summed kernel ms (HIP events) */
     double last_dp, last_ds, well_res;       /* last Newton check: update sizes, well measure */
     double dt_sub[FIM_MAX_SUB];              /* accepted sub-step sizes (days) */
+    double gs_vectors;                       /* basis vectors orthogonalised against, summed
+                                                over the Arnoldi steps (j + 1 at step j) */
 } fim_step_report;
 
 typedef struct fim_ctx fim_ctx;

@@ -679,10 +679,20 @@ __device__ inline void presmooth_item(const AmgLevel &L, int h) {
 
 // wells: one wave per well, lanes stride over its slots; xcell(s) gives
 // the value of the cell with split index s
+// (two slots of a lane at a time, both cell values formed before either is
+// added: the sum runs in the same order as one slot at a time)
 template <class XC>
 __device__ inline double well_row_sum_of(const AmgLevel &L, int w, int lane, XC xcell) {
     double acc = 0.0;
-    for (int q = L.sps[w] + lane; q < L.sps[w + 1]; q += 64) acc += L.awc[q] * xcell(L.scell[q]);
+    const int q1 = L.sps[w + 1];
+    int q = L.sps[w] + lane;
+    for (; q + 64 < q1; q += 128) {
+        const double a0 = L.awc[q], a1 = L.awc[q + 64];
+        const double x0 = xcell(L.scell[q]), x1 = xcell(L.scell[q + 64]);
+        acc += a0 * x0;
+        acc += a1 * x1;
+    }
+    if (q < q1) acc += L.awc[q] * xcell(L.scell[q]);
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
     return acc;

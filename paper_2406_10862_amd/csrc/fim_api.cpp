@@ -164,6 +164,7 @@ struct fim_ctx {
     int spmv_used = 0;
     double spmv_ms = 0.0;
     int spmv_calls = 0;
+    double gs_vectors = 0.0;                  // basis vectors orthogonalised against (step)
     long spmv_seq = 0;                        // solver SpMVs since the context was made
     // discrete adjoint: the state after every accepted sub-step of the
     // forward run and the work arrays of the backward sweep
@@ -1331,6 +1332,7 @@ static int gmres_t(fim_ctx *c, const double *bvec, double *xvec, int max_it, dou
     double relres = 1.0;
 
     auto enqueue = [&](int j) {
+        c->gs_vectors += j + 1;
         const bool stamp = next_spmv_stamped(c, profile);
         if (c->opt.graphs && !stamp) {
             arnoldi_graph<T>(c, j, true);
@@ -1517,6 +1519,7 @@ static int step_impl(fim_ctx *c, double dt, fim_step_report *rep,
     fim_step_report r{};
     c->spmv_ms = 0;
     c->spmv_calls = 0;
+    c->gs_vectors = 0.0;
     c->spmv_used = 0;
     if (c->opt.profile && c->spmv_ev.empty()) {
         c->spmv_ev.resize(2048);
@@ -1563,6 +1566,7 @@ static int step_impl(fim_ctx *c, double dt, fim_step_report *rep,
     r.t_update = st.t_upd;
     r.spmv_ms = c->spmv_ms;
     r.spmv_calls = c->spmv_calls;
+    r.gs_vectors = c->gs_vectors;
     r.last_dp = st.last_dp;
     r.last_ds = st.last_ds;
     r.well_res = st.well_res;

@@ -73,7 +73,7 @@ class FimStepReport(C.Structure):
                 ("t_assemble", C.c_double), ("t_linear", C.c_double),
                 ("t_update", C.c_double), ("spmv_ms", C.c_double),
                 ("last_dp", C.c_double), ("last_ds", C.c_double), ("well_res", C.c_double),
-                ("dt_sub", C.c_double * FIM_MAX_SUB)]
+                ("dt_sub", C.c_double * FIM_MAX_SUB), ("gs_vectors", C.c_double)]
 
 
 class FimAdjointReport(C.Structure):
