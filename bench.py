@@ -8,9 +8,10 @@ the HIP library.  Inputs are seeded synthetic data resident in HBM before timing
 
 Prints one JSON line with the throughput and the three parts of the metric:
 Newton iterations/s (FP64; the mixed-precision form beside it), the
-roofline of the BSR SpMV the metric names (every launch inside the timed
-steps stamping its own start and end into a pair of HIP events on the
-library's stream; also timed cold, with 1 GiB written between launches),
+roofline of the BSR SpMV the metric names (every 8th launch inside the
+timed steps stamping its own start and end into a pair of HIP events on the
+library's stream; also timed cold, with 1 GiB written and another 1 GiB read
+between launches),
 and the adjoint/forward time of the gradient on the 200k-cell field.  The
 FP64 oracle's throughput on the host is the CPU baseline.
 """
