@@ -662,6 +662,8 @@ def main():
                          "levels of at most -value cells, W between")
     ap.add_argument("--amg-sweeps", type=int, default=0,
                     help="red-black sweep pairs before and after each coarse correction (0 = 1)")
+    ap.add_argument("--amg-exact", type=int, default=0,
+                    help="cells of a coarsest AMG level solved exactly by slabs (0: off)")
     ap.add_argument("--gs-refine", type=int, default=0, choices=[-1, 0, 1],
                     help="Gram-Schmidt second pass: 1 when the first cancelled, -1 never, 0 default (never)")
     ap.add_argument("--precond", default="cpr_ilu0", choices=["bj", "ilu0", "cpr", "cpr_ilu0"])
@@ -725,6 +727,7 @@ def main():
     opts.amg_cycle = args.cycle
     opts.amg_sweeps = args.amg_sweeps
     opts.gs_refine = args.gs_refine
+    opts.amg_exact = args.amg_exact
     opts.precond = {"bj": rv.PREC_BJ, "ilu0": rv.PREC_ILU0, "cpr": rv.PREC_CPR,
                     "cpr_ilu0": rv.PREC_CPR_ILU0}[args.precond]
     if args.tile is None:

@@ -165,8 +165,14 @@ typedef struct {
  * bit either way).  gs_refine: the Arnoldi orthogonalisation is classical
  * Gram-Schmidt; 1 adds a second pass whenever the first one cancelled more
  * than 90% of the vector's norm, -1 never adds one (a single classical pass,
- * PETSc's default for its GMRES family), 0 = default (-1).  reserved must be
- * 0.  profile = k > 0
+ * PETSc's default for its GMRES family), 0 = default (-1).  amg_exact > 0: the
+ * hierarchy stops at the first level below the finest with at most this
+ * many cells (<= 0 = never, the default) whose slabs (the cells of one
+ * coordinate of its longest axis) hold at most 96 cells and wells and whose
+ * every well lies in one slab; that level is solved exactly, by block
+ * elimination over the slabs, and the level above it then runs a V-cycle
+ * (otherwise the levels go down to at most 64 cells, inverted densely).  It
+ * is fixed when the context is created.  profile = k > 0
  * has every k-th Krylov SpMV launch of fim_step (k = 1: every one) stamp
  * its own start and end into a pair of HIP events and reports the summed
  * kernel time of the stamped launches and their count in fim_step_report.  precision FIM_MIXED (with an ILU(0)
@@ -181,7 +187,7 @@ typedef struct {
     int32_t max_newton, max_lin, restart, max_cuts;
     int32_t precond, precision, profile, amg_cycle, amg_sweeps, graphs, forcing, amg_fused;
     int32_t tile_nx, tile_ny, tile_nz, amg_seg_rows;
-    int32_t gs_refine, reserved;
+    int32_t gs_refine, amg_exact;
 } fim_options;
 
 #define FIM_MAX_SUB 256
@@ -412,6 +418,14 @@ int fim_linear_solve(fim_ctx *ctx, const double *b, double *x, int32_t *iters,
  * level l with the piecewise-constant interpolation of 2x2x2 aggregates
  * (wells their own aggregates).  FIM_E_ARG without a CPR preconditioner. */
 int fim_amg_level(fim_ctx *ctx, int32_t level, int32_t *dims, double *A);
+
+/* The coarsest AMG level's solve as the cycle runs it (Sec. 5.1, the
+ * pressure stage's coarse problem): x = A_c^-1 b for host arrays in the
+ * order of fim_amg_level (cells in natural order, then wells) of the last
+ * level, by block elimination over slabs when that level is solved exactly
+ * (option amg_exact), else by its dense inverse.  The level's own arrays
+ * are not touched.  FIM_E_ARG without a CPR preconditioner. */
+int fim_amg_coarse_solve(fim_ctx *ctx, const double *b, double *x);
 
 /* The matrix-vector product inside the Krylov solver of Sec. 5.1: y = A x
  * for a canonical BSR matrix of nrows block rows with nb in {2,3}

@@ -564,6 +564,301 @@ __global__ __launch_bounds__(256) void k_dense_gemv(int n, const double *__restr
 }
 
 // ---------------------------------------------------------------------------
+// exact coarsest solve by slabs (the block-tridiagonal form of the level:
+// slab b = the cells with coordinate b along the axis, in-slab position
+// p = u + nu * v over the other two axes, then the slab's wells)
+
+__device__ inline void slab_cell(const AmgExact &E, int b, int p, int &i, int &j, int &k) {
+    const int u = p % E.nu, v = p / E.nu;
+    if (E.axis == 0) {
+        i = b; j = u; k = v;
+    } else if (E.axis == 1) {
+        i = u; j = b; k = v;
+    } else {
+        i = u; j = v; k = b;
+    }
+}
+
+__device__ inline int slab_pos(const AmgExact &E, int i, int j, int k, int &b) {
+    if (E.axis == 0) {
+        b = i;
+        return j + E.nu * k;
+    }
+    if (E.axis == 1) {
+        b = j;
+        return i + E.nu * k;
+    }
+    b = k;
+    return i + E.nu * j;
+}
+
+// stencil entry d of the cell at slab b, position p
+__device__ inline double slab_coef(const AmgLevel &L, const AmgExact &E, int b, int p, int d) {
+    int i, j, k;
+    slab_cell(E, b, p, i, j, k);
+    return L.a[(size_t)d * 2 * L.half + split_of(L, i, j, k)];
+}
+
+// The block of slab b (m = ncs + its wells, row-major with stride m) into A.
+__device__ void slab_block(const AmgLevel &L, const AmgExact &E, int b, int m, double *A) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int e = tid; e < m * m; e += nt) A[e] = 0.0;
+    __syncthreads();
+    const int stride = 2 * L.half, w0 = E.swp[b];
+    for (int p = tid; p < E.ncs; p += nt) {
+        int i, j, k;
+        slab_cell(E, b, p, i, j, k);
+        const int s = split_of(L, i, j, k);
+        A[(size_t)p * m + p] = L.a[s];
+        const int u = p % E.nu, v = p / E.nu;
+#pragma unroll
+        for (int d = 1; d < 7; ++d) {
+            const int ax = (d - 1) >> 1;
+            if (ax == E.axis) continue;
+            const int sgn = (d & 1) ? -1 : 1;
+            // the first in-slab axis moves u, the second v
+            const bool first = ax == (E.axis == 0 ? 1 : 0);
+            const int nu = first ? u + sgn : u, nv = first ? v : v + sgn;
+            if (nu < 0 || nu >= E.nu || nv < 0 || nv >= E.nv) continue;
+            A[(size_t)p * m + nu + E.nu * nv] += L.a[(size_t)d * stride + s];
+        }
+        for (int q = L.cps[s]; q < L.cps[s + 1]; ++q) {
+            const int sl = L.cslot[q];
+            A[(size_t)p * m + E.ncs + E.wrank[L.swell[sl]]] += L.acw[sl];
+        }
+    }
+    for (int e = tid; e < E.swp[b + 1] - w0; e += nt) {
+        const int w = E.sw[w0 + e], row = E.ncs + e;
+        A[(size_t)row * m + row] += L.aww[w];
+        for (int q = L.sps[w]; q < L.sps[w + 1]; ++q) {
+            const Pos ps = pos_of(L, L.scell[q]);
+            int bb;
+            const int pc = slab_pos(E, ps.i, ps.j, ps.k, bb);
+            A[(size_t)row * m + pc] += L.awc[q];
+        }
+    }
+    __syncthreads();
+}
+
+// One workgroup: the Schur complements of the slabs in order, each
+// inverted in place (Gauss-Jordan without pivoting: the pressure operator's
+// Schur complements keep its diagonal dominance), stored to E.binv.
+// Element loops run rows over waves and columns over lanes (no division).
+__device__ void exact_factor_wg(const AmgLevel &L, const AmgExact &E, double *lds) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int lane = tid & 63, wave = tid >> 6, nwaves = nt >> 6;
+    const int mm = E.mmax * E.mmax;
+    double *A = lds, *P = lds + mm, *F = lds + 2 * mm;
+    double *am = F + E.mmax, *apv = am + E.mmax;   // couplings to the slab before
+    const int dm = 2 * E.axis + 1, dp = 2 * E.axis + 2;
+    int mprev = 0;
+    for (int b = 0; b < E.nslab; ++b) {
+        const int m = E.ncs + E.swp[b + 1] - E.swp[b];
+        if (b > 0)
+            for (int p = tid; p < E.ncs; p += nt) {
+                am[p] = slab_coef(L, E, b, p, dm);
+                apv[p] = slab_coef(L, E, b - 1, p, dp);
+            }
+        slab_block(L, E, b, m, A);                  // (ends with a barrier)
+        if (b > 0) {
+            // A_bb -= A_b,b-1 inv(D_b-1) A_b-1,b: both couplings are diagonal
+            // (a cell to the same position of the neighbouring slab)
+            for (int r = wave; r < E.ncs; r += nwaves)
+                for (int q = lane; q < E.ncs; q += 64)
+                    A[(size_t)r * m + q] -= am[r] * P[(size_t)r * mprev + q] * apv[q];
+            __syncthreads();
+        }
+        // Step kk: the pivot row scaled (its diagonal, the inverted pivot,
+        // written in step kk + 1 or after the last step: the pivot is read
+        // at the start of its own step), the pivot column saved; then every
+        // other row r takes a_rq - f_r a'_kq (a_rk becomes -f_r / piv).  A
+        // thread takes one column (lane, lane + 64) and the rows of its
+        // wave, so the pivot row's entry is loaded once.
+        double ip = 0.0;
+        for (int kk = 0; kk < m; ++kk) {
+            const double piv = A[(size_t)kk * m + kk];
+            if (tid == 0 && kk > 0) A[(size_t)(kk - 1) * m + kk - 1] = ip;
+            ip = 1.0 / piv;
+            if (tid == 0 && !(fabs(piv) > 0.0 && isfinite(piv))) *E.bad = 1;
+            for (int e = tid; e < m; e += nt) {
+                F[e] = e == kk ? 0.0 : A[(size_t)e * m + kk];
+                if (e != kk) A[(size_t)kk * m + e] *= ip;
+            }
+            lds_barrier();
+            // (rows wave + 16 t of the 16 waves, all of a thread's loads
+            // issued before its first product; a slot past the block reads
+            // entry 0 and stores nothing)
+            constexpr int kR = (kSlabMax + 15) / 16;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int q = lane + 64 * h;
+                const bool qon = q < m;
+                const int qq = qon ? q : 0;
+                const double akq = A[(size_t)kk * m + qq];
+                double a[kR], f[kR];
+#pragma unroll
+                for (int t = 0; t < kR; ++t) {
+                    const int r = wave + 16 * t, rr = r < m ? r : 0;
+                    a[t] = A[(size_t)rr * m + qq];
+                    f[t] = F[rr];
+                }
+#pragma unroll
+                for (int t = 0; t < kR; ++t) {
+                    const int r = wave + 16 * t;
+                    if (qon && r < m && r != kk)
+                        A[(size_t)r * m + q] = q == kk ? -f[t] * ip : a[t] - f[t] * akq;
+                }
+            }
+            lds_barrier();
+        }
+        if (tid == 0) A[(size_t)(m - 1) * m + m - 1] = ip;
+        lds_barrier();
+        double *dst = E.binv + (size_t)b * mm;
+        for (int e = tid; e < m * m; e += nt) dst[e] = A[e];
+        double *t = A;
+        A = P;
+        P = t;
+        mprev = m;
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_amg_exact_factor(AmgLevel L, AmgExact E) {
+    extern __shared__ double lds[];
+    exact_factor_wg(L, E, lds);
+}
+
+// The exact solve by the whole workgroup: x = A^-1 b of the level, through
+// z (LDS, [nslab][mmax]) and t ([mmax]).  Forward: z_b = inv(D_b) (b_b -
+// A_b,b-1 z_b-1); backward: x_b = z_b - inv(D_b) A_b,b+1 x_b+1.  A row of a
+// block product is summed by 8 lanes (columns lane, lane + 8, ...) and a
+// fixed shuffle tree.
+__device__ void exact_solve_wg(const AmgLevel &L, const AmgExact &E, double *z) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    double *t = z + (size_t)E.nslab * E.mmax;
+    // the cells' right-hand sides and couplings to the slabs before and
+    // after, staged in slab order
+    double *bb = t + E.mmax, *am = bb + (size_t)E.nslab * E.ncs, *apc = am + (size_t)E.nslab * E.ncs;
+    int *sp = reinterpret_cast<int *>(apc + (size_t)E.nslab * E.ncs);   // slab -> wells
+    const int mm = E.mmax * E.mmax, dm = 2 * E.axis + 1, dp = 2 * E.axis + 2;
+    {
+        // (the wells' right-hand sides go to their places in z, which the
+        // forward step of their slab reads before it writes there)
+        for (int e = tid; e <= E.nslab; e += nt) sp[e] = E.swp[e];
+        for (int b = tid; b < E.nslab; b += nt)
+            for (int q = E.swp[b]; q < E.swp[b + 1]; ++q)
+                z[(size_t)b * E.mmax + E.ncs + (q - E.swp[b])] = L.b[2 * L.half + E.sw[q]];
+        const int stride = 2 * L.half;
+        for (int e = tid; e < stride; e += nt) {
+            const Pos ps = pos_of(L, e);
+            if (ps.i >= L.nx) continue;
+            int b;
+            const int idx = slab_pos(E, ps.i, ps.j, ps.k, b);
+            const size_t o = (size_t)b * E.ncs + idx;
+            bb[o] = L.b[e];
+            am[o] = L.a[(size_t)dm * stride + e];
+            apc[o] = L.a[(size_t)dp * stride + e];
+        }
+        __syncthreads();
+    }
+    // a block product y = B t: row r (r < kSlabMax) is summed by the 32-lane
+    // group r % 32 in pass r / 32, lane l taking the columns l + 32 u; a
+    // block's entries for a thread are kU values (a slot past the block
+    // loads the block's first entry and is dropped)
+    constexpr int kP = (kSlabMax + 31) / 32, kC = (kSlabMax + 31) / 32, kU = kP * kC;
+    const int grp = tid >> 5, l32 = tid & 31;
+    auto slab_m = [&](int b) { return E.ncs + sp[b + 1] - sp[b]; };
+    auto fetch = [&](int b, double (&v)[kU]) {
+        const int m = slab_m(b);
+        const double *B = E.binv + (size_t)b * mm;
+#pragma unroll
+        for (int p = 0; p < kP; ++p) {
+            const int r = grp + 32 * p;
+#pragma unroll
+            for (int u = 0; u < kC; ++u) {
+                const int c = l32 + 32 * u;
+                v[p * kC + u] = B[(r < m && c < m) ? (size_t)r * m + c : 0];
+            }
+        }
+    };
+    auto product = [&](int b, const double (&v)[kU], bool sub) {
+        const int m = slab_m(b);
+#pragma unroll
+        for (int p = 0; p < kP; ++p) {
+            const int r = grp + 32 * p;
+            double acc = 0.0;
+#pragma unroll
+            for (int u = 0; u < kC; ++u) {
+                const int c = l32 + 32 * u;
+                const double tc = t[c < m ? c : 0];
+                acc += c < m ? v[p * kC + u] * tc : 0.0;
+            }
+#pragma unroll
+            for (int off = 16; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+            if (r < m && l32 == 0) {
+                double &zr = z[(size_t)b * E.mmax + r];
+                zr = sub ? zr - acc : acc;
+            }
+        }
+    };
+    // the sweep's steps: forward over the slabs, then backward from the
+    // second last; the block of step i + 1 is loaded during step i into
+    // the other register buffer (steps taken in pairs, so each buffer keeps
+    // its role), and the barriers order LDS only, so those loads stay in
+    // flight across them
+    const int nstep = 2 * E.nslab - 1;
+    auto slab_at = [&](int i) { return i < E.nslab ? i : 2 * E.nslab - 2 - i; };
+    auto step = [&](int i, const double (&cur)[kU], double (&nxt)[kU]) {
+        const int b = slab_at(i);
+        const bool back = i >= E.nslab;
+        const int m = slab_m(b);
+        for (int p = tid; p < m; p += nt) {
+            double v;
+            if (p < E.ncs) {
+                const size_t o = (size_t)b * E.ncs + p;
+                if (back) {
+                    v = apc[o] * z[(size_t)(b + 1) * E.mmax + p];
+                } else {
+                    v = bb[o];
+                    if (b > 0) v -= am[o] * z[(size_t)(b - 1) * E.mmax + p];
+                }
+            } else {
+                v = back ? 0.0 : z[(size_t)b * E.mmax + p];
+            }
+            t[p] = v;
+        }
+        if (i + 1 < nstep) fetch(slab_at(i + 1), nxt);
+        lds_barrier();
+        product(b, cur, back);
+        lds_barrier();
+    };
+    double va[kU], vb[kU];
+    fetch(0, va);
+    for (int i = 0; i < nstep; i += 2) {
+        step(i, va, vb);
+        if (i + 1 < nstep) step(i + 1, vb, va);
+    }
+    for (int e = tid; e < 2 * L.half; e += nt) {
+        const Pos ps = pos_of(L, e);
+        double v = 0.0;                             // padded entries stay zero
+        if (ps.i < L.nx) {
+            int b;
+            const int p = slab_pos(E, ps.i, ps.j, ps.k, b);
+            v = z[(size_t)b * E.mmax + p];
+        }
+        L.x[e] = v;
+    }
+    for (int b = tid; b < E.nslab; b += nt)
+        for (int q = E.swp[b]; q < E.swp[b + 1]; ++q)
+            L.x[2 * L.half + E.sw[q]] = z[(size_t)b * E.mmax + E.ncs + (q - E.swp[b])];
+}
+
+__global__ __launch_bounds__(1024) void k_amg_exact_solve(AmgLevel L, AmgExact E) {
+    extern __shared__ double lds[];
+    exact_solve_wg(L, E, lds);
+}
+
+// ---------------------------------------------------------------------------
 // cycle kernels
 
 // Value of neighbour d of p (ns its split index), or of p itself when the
@@ -944,7 +1239,9 @@ __device__ __forceinline__ void sweep_phase(const AmgLevel &F, const AmgLevel &C
 // workgroup.  Inlined once with the coefficients of F in LDS and once with
 // them in HBM, so every access has a known address space.
 __device__ __forceinline__ void subcycle_phase(int op, const AmgLevel &F, const AmgLevel &C,
-                                               const double *Minv, double *rbuf) {
+                                               const double *Minv, double *rbuf,
+                                               const AmgExact *ex = nullptr,
+                                               double *xs = nullptr) {
     const int tid = threadIdx.x, nt = blockDim.x;
     const int wave = tid >> 6, lane = tid & 63, nwaves = nt >> 6;
     const int kind = op & 15;
@@ -997,6 +1294,8 @@ __device__ __forceinline__ void subcycle_phase(int op, const AmgLevel &F, const 
         for (int w = wave; w < F.nw; w += nwaves) restrict_well(F, C, w, lane);
     } else if (kind == kOpCorrect) {
         for (int t = tid; t < 2 * F.half + F.nw; t += nt) correct_item(F, C, t);
+    } else if (ex) {
+        exact_solve_wg(F, *ex, xs);
     } else {
         const int n = 2 * F.half + F.nw;
         for (int row = tid; row < n; row += nt) F.x[row] = dense_row(n, Minv, F.b, row);
@@ -1255,6 +1554,41 @@ static inline dim3 smooth_grid(const AmgLevel &L) {
     return dim3((unsigned)(well_blocks_of(L) + (L.half + kBlock - 1) / kBlock));
 }
 
+size_t exact_solve_lds(const AmgExact &E) {
+    return ((size_t)E.nslab * E.mmax + E.mmax + 3 * (size_t)E.nslab * E.ncs + (E.nslab + 2) / 2) *
+           sizeof(double);
+}
+size_t exact_factor_lds(const AmgExact &E) {
+    return ((size_t)2 * E.mmax * E.mmax + 3 * E.mmax + 2) * sizeof(double);
+}
+
+// the largest LDS of a slab problem the plan admits (nslab * mmax <=
+// kExactSlabDoubles, ncs <= mmax <= kSlabMax), which every context shares
+static size_t exact_factor_lds_max() {
+    return ((size_t)2 * kSlabMax * kSlabMax + 3 * kSlabMax + 2) * sizeof(double);
+}
+static size_t exact_solve_lds_max() {
+    return ((size_t)4 * kExactSlabDoubles + kSlabMax + (kExactSlabDoubles + 2) / 2) * sizeof(double);
+}
+
+hipError_t exact_allow_lds() {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_amg_exact_factor),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)exact_factor_lds_max());
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_amg_exact_solve),
+                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)exact_solve_lds_max());
+}
+
+void launch_amg_exact_factor(hipStream_t s, const AmgLevel &L, const AmgExact &E) {
+    hipLaunchKernelGGL(k_amg_exact_factor, dim3(1), dim3(1024), exact_factor_lds(E), s, L, E);
+}
+
+void launch_amg_exact_solve(hipStream_t s, const AmgLevel &L, const AmgExact &E) {
+    hipLaunchKernelGGL(k_amg_exact_solve, dim3(1), dim3(1024), exact_solve_lds(E), s, L, E);
+}
+
 void launch_amg_sweep(hipStream_t s, const AmgLevel &L, const AmgLevel &C, int color, int mode) {
     // colour 1 reads the wells from the snapshot the colour-0 sweep took
     if (color == 1) mode |= kWellsSnap;
@@ -1390,10 +1724,14 @@ __global__ __launch_bounds__(1024) void kb_amg_coarsest(const Member *__restrict
     if (!batch_view(B, m, b, nb)) return;
     const Member &M = mem[m];
     const AmgLevel &L = M.lv[M.nlev - 1];
+    extern __shared__ double sm[];
+    if (M.exact) {
+        exact_factor_wg(L, M.ex, sm);
+        return;
+    }
     const int n = 2 * L.half + L.nw;
     for (int t = threadIdx.x; t < n; t += blockDim.x) amg_dense_row(L, M.Mden, t);
     __syncthreads();
-    extern __shared__ double sm[];
     dense_invert_lds_body(n, M.Mden, M.Minv, M.amg_bad, sm);
 }
 
@@ -1430,10 +1768,11 @@ __global__ __launch_bounds__(kSubThreads) void kb_amg_cycle(const Member *__rest
     int m, b, nb;
     if (!batch_view(B, m, b, nb)) return;
     const Member &M = mem[m];
+    extern __shared__ double xs[];               // the slab solve's vectors
     for (int o = 0; o < M.nops; ++o) {
         const int op = __builtin_amdgcn_readfirstlane(M.ops[o]);
         const int l = (op >> 4) & 15;
-        subcycle_phase(op, M.lv[l], M.lv[l + 1], M.Minv, M.rbuf);
+        subcycle_phase(op, M.lv[l], M.lv[l + 1], M.Minv, M.rbuf, M.exact ? &M.ex : nullptr, xs);
         __syncthreads();
     }
 }
@@ -1449,16 +1788,21 @@ void launchb_amg_coarsen(hipStream_t s, const Member *mem, Batch B, int total, i
         hipLaunchKernelGGL(kb_amg_coarsen, dim3(total), dim3(kBlock), 0, s, mem, B, level);
 }
 
-void launchb_amg_coarsest(hipStream_t s, const Member *mem, Batch one, int tone, int nmax) {
+void launchb_amg_coarsest(hipStream_t s, const Member *mem, Batch one, int tone, int nmax,
+                          size_t exact_lds) {
     if (tone > 0)
-        hipLaunchKernelGGL(kb_amg_coarsest, dim3(tone), dim3(1024), dense_lds_bytes(nmax), s, mem,
-                           one);
+        hipLaunchKernelGGL(kb_amg_coarsest, dim3(tone), dim3(1024),
+                           std::max(dense_lds_bytes(nmax), exact_lds), s, mem, one);
 }
 
 hipError_t batch_allow_lds() {
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(&kb_amg_coarsest),
+    hipError_t e = hipFuncSetAttribute(
+        reinterpret_cast<const void *>(&kb_amg_coarsest), hipFuncAttributeMaxDynamicSharedMemorySize,
+        (int)std::max(dense_lds_bytes(kDenseLds), exact_factor_lds_max()));
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&kb_amg_cycle),
                                hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)dense_lds_bytes(kDenseLds));
+                               (int)exact_solve_lds_max());
 }
 
 int dense_lds_max() { return kDenseLds; }
@@ -1474,9 +1818,9 @@ void launchb_cpr_restrict(hipStream_t s, int nb, const Member *mem, Batch B, int
                            first_bit, s_norm, s_res);
 }
 
-void launchb_amg_cycle(hipStream_t s, const Member *mem, Batch one, int tone) {
+void launchb_amg_cycle(hipStream_t s, const Member *mem, Batch one, int tone, size_t exact_lds) {
     if (tone > 0)
-        hipLaunchKernelGGL(kb_amg_cycle, dim3(tone), dim3(kSubThreads), 0, s, mem, one);
+        hipLaunchKernelGGL(kb_amg_cycle, dim3(tone), dim3(kSubThreads), exact_lds, s, mem, one);
 }
 
 }  // namespace fim

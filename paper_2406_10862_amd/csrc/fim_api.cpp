@@ -151,6 +151,8 @@ struct fim_ctx {
     int *sub_ops = nullptr;                         // [kSubOps] its phase list
     AmgSub sub{};
     int *amg_bad = nullptr;
+    bool exact_on = false;        // the coarsest level is solved by slabs (AmgExact)
+    AmgExact ex{};
     int *split0 = nullptr;                          // natural cell -> level-0 split index
     int *colsplit = nullptr;                        // [nnzb] column -> level-0 entry
     int *reorth = nullptr;
@@ -276,7 +278,7 @@ static void check_options(const fim_options *o) {
     REQUIRE(o->amg_fused <= (1 << 20), "amg_fused must be at most 2^20 cells");
     REQUIRE(o->gs_refine >= -1 && o->gs_refine <= 1, "gs_refine must be -1, 0 or 1");
     REQUIRE(o->profile >= 0, "profile must be >= 0");
-    REQUIRE(o->reserved == 0, "reserved must be 0");
+    REQUIRE(o->amg_exact >= -1 && o->amg_exact <= (1 << 20), "amg_exact must be in [-1, 2^20]");
 }
 
 static void build_pattern(fim_ctx *c, std::vector<int> &rp, std::vector<int> &ci,
@@ -317,6 +319,62 @@ static void alloc_krylov(fim_ctx *c, int m) {
     c->V = c->alloc<double>((size_t)(m + 1) * c->nvec);
     c->Z = c->alloc<double>((size_t)(m + 1) * c->nvec);
     c->H = c->alloc<double>((size_t)(m + 1) * (kMaxRestart + 2));
+}
+
+// Whether the level just built (nx x ny x nz cells; well slots at natural
+// cells slot_cell, of wells slot_well, ranges sps) can be the coarsest,
+// solved exactly by slabs: at most amg_exact cells (option; <= 0 = never,
+// the default), slabs along the longest axis of at most
+// kSlabMax cells and wells, and every well's cells in one slab.  On
+// success fills c->ex (device arrays uploaded) and sets c->exact_on.
+static bool plan_exact(fim_ctx *c, int nx, int ny, int nz, const std::vector<int> &slot_cell,
+                       const std::vector<int> &slot_well, const std::vector<int> &sps) {
+    if (c->opt.amg_exact <= 0) return false;           // 0: the default, off
+    const long cells = (long)nx * ny * nz;
+    if (cells > c->opt.amg_exact) return false;
+    const int dims[3] = {nx, ny, nz};
+    int axis = 0;
+    for (int a = 1; a < 3; ++a)
+        if (dims[a] > dims[axis]) axis = a;
+    AmgExact E{};
+    E.axis = axis;
+    E.nslab = dims[axis];
+    E.nu = axis == 0 ? ny : nx;
+    E.nv = axis == 2 ? ny : nz;
+    E.ncs = E.nu * E.nv;
+    const int nw = c->nw;
+    std::vector<int> wslab(nw, -1);
+    for (int w = 0; w < nw; ++w)
+        for (int q = sps[w]; q < sps[w + 1]; ++q) {
+            const int cn = slot_cell[q];
+            const int ci[3] = {cn % nx, (cn / nx) % ny, cn / (nx * ny)};
+            if (wslab[w] >= 0 && wslab[w] != ci[axis]) return false;   // a well across slabs
+            wslab[w] = ci[axis];
+        }
+    std::vector<int> swp(E.nslab + 1, 0), sw, wrank(std::max(nw, 1), 0);
+    for (int w = 0; w < nw; ++w)
+        if (wslab[w] >= 0) swp[wslab[w] + 1]++;
+    for (int b = 0; b < E.nslab; ++b) swp[b + 1] += swp[b];
+    int mwell = 0;
+    for (int b = 0; b < E.nslab; ++b) mwell = std::max(mwell, swp[b + 1] - swp[b]);
+    E.mmax = E.ncs + mwell;
+    if (E.mmax > kSlabMax || (long)E.nslab * E.mmax > kExactSlabDoubles) return false;
+    if ((int)swp[E.nslab] != nw) return false;             // a well without a slot
+    sw.resize(std::max(nw, 1));
+    {
+        std::vector<int> fill(swp.begin(), swp.end() - 1);
+        for (int w = 0; w < nw; ++w) {
+            wrank[w] = fill[wslab[w]] - swp[wslab[w]];
+            sw[fill[wslab[w]]++] = w;
+        }
+    }
+    E.swp = c->upload(swp.data(), swp.size());
+    E.sw = c->upload(sw.data(), sw.size());
+    E.wrank = c->upload(wrank.data(), wrank.size());
+    c->sync();
+    c->ex = E;
+    c->exact_on = true;
+    return true;
 }
 
 // Structured aggregation hierarchy of the pressure AMG (built once): level
@@ -387,6 +445,7 @@ static void build_amg(fim_ctx *c, const std::vector<int> &sorted_cells,
         L.cslot = c->upload(cslot.data(), cslot.size());
         c->sync();                  // the host vectors above are temporaries
         c->lv.push_back(L);
+        if (c->lv.size() > 1 && plan_exact(c, nx, ny, nz, slot_cell, slot_well, sps)) break;
         if ((long)nx * ny * nz <= kCoarseMax || (nx == 1 && ny == 1 && nz == 1)) break;
         // next level: coarse dimensions and the well slots they keep
         const int cnx = (nx + 1) / 2, cny = (ny + 1) / 2, cnz = (nz + 1) / 2;
@@ -428,15 +487,28 @@ static void build_amg(fim_ctx *c, const std::vector<int> &sorted_cells,
         slot_well.swap(nwell);
         sps.swap(nsps);
     }
-    const AmgLevel &Lc = c->lv.back();
-    const size_t n = 2 * (size_t)Lc.half + Lc.nw;
-    c->Mden = c->alloc<double>(n * n);
-    c->Minv = c->alloc<double>(n * n);
-    c->colk = c->alloc<double>(n);
     c->amg_bad = c->alloc<int>(1);
+    if (c->exact_on) {
+        c->ex.bad = c->amg_bad;
+        c->ex.binv = c->alloc<double>((size_t)c->ex.nslab * c->ex.mmax * c->ex.mmax);
+        HIPCHECK(exact_allow_lds());            // the same value for every context
+    } else {
+        const AmgLevel &Lc = c->lv.back();
+        const size_t n = 2 * (size_t)Lc.half + Lc.nw;
+        c->Mden = c->alloc<double>(n * n);
+        c->Minv = c->alloc<double>(n * n);
+        c->colk = c->alloc<double>(n);
+    }
     HIPCHECK(dense_allow_lds());                // the same value for every context
     c->wq = c->alloc<double>((size_t)c->n * c->nb);
     c->ap = c->alloc<double>((size_t)c->nnzb * c->nb);
+}
+
+// The coarsest level's solver from its current operator: the slab
+// factorisation, or the dense inverse.
+static void coarsest_setup(fim_ctx *c) {
+    if (c->exact_on) launch_amg_exact_factor(c->s, c->lv.back(), c->ex);
+    else launch_amg_coarsest_setup(c->s, c->lv.back(), c->Mden, c->Minv, c->colk, c->amg_bad);
 }
 
 static void build_subcycle(fim_ctx *c);
@@ -784,6 +856,7 @@ static void amg_cycle(fim_ctx *c, int l, std::vector<int> *rec = nullptr, int ro
     const int rl = l - root;
     if (l == L - 1) {
         if (rec) rec->push_back(amg_op(kOpCoarse, rl));
+        else if (c->exact_on) launch_amg_exact_solve(c->s, c->lv[l], c->ex);
         else launch_amg_coarsest_solve(c->s, c->lv[l], c->Minv);
         return;
     }
@@ -843,7 +916,8 @@ static void amg_cycle(fim_ctx *c, int l, std::vector<int> *rec = nullptr, int ro
 static void build_subcycle(fim_ctx *c) {
     c->sub_root = -1;
     const int L = (int)c->lv.size();
-    if (L == 0 || c->opt.amg_fused < 0) return;
+    // (a coarsest level solved by slabs is its own single-workgroup launch)
+    if (L == 0 || c->opt.amg_fused < 0 || c->exact_on) return;
     const long limit = c->opt.amg_fused > 0 ? c->opt.amg_fused : kFusedCellsDefault;
     int root = 0;
     while (root < L && 2L * c->lv[root].half + c->lv[root].nw > limit) ++root;
@@ -1091,7 +1165,7 @@ static void prec_setup(fim_ctx *c) {
             launch_amg_extract(c->s, c->nb, c->lv[0], c->g, c->wells(), c->sys(), c->wq, c->ap32);
             for (size_t l = 1; l < c->lv.size(); ++l)
                 launch_amg_coarsen(c->s, c->lv[l - 1], c->lv[l], c->cfs_ptr[l], c->cfs_idx[l]);
-            launch_amg_coarsest_setup(c->s, c->lv.back(), c->Mden, c->Minv, c->colk, c->amg_bad);
+            coarsest_setup(c);
         }
         c->prec_ready = true;
         return;
@@ -1102,7 +1176,7 @@ static void prec_setup(fim_ctx *c) {
         launch_amg_extract(c->s, c->nb, c->lv[0], c->g, c->wells(), c->sys(), c->wq, c->ap);
         for (size_t l = 1; l < c->lv.size(); ++l)
             launch_amg_coarsen(c->s, c->lv[l - 1], c->lv[l], c->cfs_ptr[l], c->cfs_idx[l]);
-        launch_amg_coarsest_setup(c->s, c->lv.back(), c->Mden, c->Minv, c->colk, c->amg_bad);
+        coarsest_setup(c);
     }
     c->prec_ready = true;
 }
@@ -1645,7 +1719,7 @@ static void adjoint_prec_setup(fim_ctx *c) {
     launch_cprT_extract(c->s, c->nb, c->lv[0], c->g, c->wells(), c->sys(), c->wq, c->ap);
     for (size_t l = 1; l < c->lv.size(); ++l)
         launch_amg_coarsen(c->s, c->lv[l - 1], c->lv[l], c->cfs_ptr[l], c->cfs_idx[l]);
-    launch_amg_coarsest_setup(c->s, c->lv.back(), c->Mden, c->Minv, c->colk, c->amg_bad);
+    coarsest_setup(c);
     c->prec_ready = true;
 }
 
@@ -1902,6 +1976,7 @@ struct MemRun {
 struct Ensemble {
     std::vector<fim_ctx *> mem;
     int nm = 0, nb = 0, m = 0, ilu_threads = 0, dense_n = 0;
+    size_t exact_factor_lds = 0, exact_solve_lds = 0;   // members with a slab-solved level
     size_t ilu_lds = 0;
     hipStream_t s = nullptr;
     std::vector<void *> owned;
@@ -2026,7 +2101,7 @@ void check_member(const fim_ctx *c, const fim_ctx *c0, int k) {
     REQUIRE((int)c->lv.size() < kMaxLevels, "member %d: %zu AMG levels (at most %d)", k,
             c->lv.size(), kMaxLevels - 1);
     const AmgLevel &Lc = c->lv.back();
-    REQUIRE(2 * Lc.half + Lc.nw <= dense_lds_max(),
+    REQUIRE(c->exact_on || 2 * Lc.half + Lc.nw <= dense_lds_max(),
             "member %d: coarsest AMG level of %d entries (at most %d)", k, 2 * Lc.half + Lc.nw,
             dense_lds_max());
     if (!c->state_set) {
@@ -2111,6 +2186,8 @@ std::unique_ptr<Ensemble> make_ensemble(int count, fim_ctx *const *members) {
         M.Minv = c->Minv;
         M.colk = c->colk;
         M.amg_bad = c->amg_bad;
+        M.exact = c->exact_on ? 1 : 0;
+        M.ex = c->ex;
         // the member's whole cycle from its finest level, and the
         // restriction's scratch
         std::vector<int> ops;
@@ -2129,7 +2206,12 @@ std::unique_ptr<Ensemble> make_ensemble(int count, fim_ctx *const *members) {
         }
         E->ilu_lds = std::max({E->ilu_lds, ilu_solve_lds(c->nb, c->ilu), ilu_factor_lds(c->nb, c->ilu)});
         const AmgLevel &Lc = c->lv.back();
-        E->dense_n = std::max(E->dense_n, 2 * Lc.half + Lc.nw);
+        if (c->exact_on) {
+            E->exact_factor_lds = std::max(E->exact_factor_lds, exact_factor_lds(c->ex));
+            E->exact_solve_lds = std::max(E->exact_solve_lds, exact_solve_lds(c->ex));
+        } else {
+            E->dense_n = std::max(E->dense_n, 2 * Lc.half + Lc.nw);
+        }
     }
     REQUIRE(E->ilu_lds <= (size_t)lds_max, "ILU(0) boxes need %zu bytes of LDS (at most %d)",
             E->ilu_lds, lds_max);
@@ -2199,7 +2281,8 @@ void batch_prec_setup(Ensemble &E) {
     for (size_t l = 1; l < E.coarsen.size(); ++l)
         launchb_amg_coarsen(E.s, E.d_mem, E.batch(E.coarsen[l], kOnSolve), E.coarsen[l].total,
                             (int)l);
-    launchb_amg_coarsest(E.s, E.d_mem, E.batch(E.one, kOnSolve), E.one.total, E.dense_n);
+    launchb_amg_coarsest(E.s, E.d_mem, E.batch(E.one, kOnSolve), E.one.total, E.dense_n,
+                         E.exact_factor_lds);
 }
 
 // z = M^-1 v of the members with kOnCycle: the first vector of a restart
@@ -2207,7 +2290,7 @@ void batch_prec_setup(Ensemble &E) {
 void batch_precondition(Ensemble &E, int j) {
     launchb_cpr_restrict(E.s, E.nb, E.d_mem, E.batch(E.rows, kOnCycle), E.rows.total, j,
                          kFirstCycle, S_NORM, S_RES);
-    launchb_amg_cycle(E.s, E.d_mem, E.batch(E.one, kOnCycle), E.one.total);
+    launchb_amg_cycle(E.s, E.d_mem, E.batch(E.one, kOnCycle), E.one.total, E.exact_solve_lds);
     launchb_ilu_solve(E.s, E.nb, E.d_mem, E.batch(E.tiles, kOnCycle), E.tiles.total, j,
                       E.ilu_threads, E.ilu_lds);
 }
@@ -3018,6 +3101,9 @@ int fim_set_options(fim_ctx *c, const fim_options *opt) {
     return guarded([&] {
         REQUIRE(c, "context is NULL");
         check_options(opt);
+        REQUIRE(opt->amg_exact == c->opt.amg_exact,
+                "amg_exact is fixed when the context is created (%d, not %d)", c->opt.amg_exact,
+                opt->amg_exact);
         c->sync();
         c->drop_graphs();        // captured steps depend on the options and buffers
         if (opt->restart > c->m) {
@@ -3331,6 +3417,44 @@ int fim_amg_level(fim_ctx *c, int32_t level, int32_t *dims, double *A) {
             A[row + nc + w] += aww[w];
             for (int q = sps[w]; q < sps[w + 1]; ++q) A[row + nat_of[scell[q]]] += awc[q];
         }
+        return FIM_OK;
+    });
+}
+
+int fim_amg_coarse_solve(fim_ctx *c, const double *b, double *x) {
+    return guarded([&] {
+        REQUIRE(c && b && x, "context, b and x are required");
+        REQUIRE(uses_cpr(c->opt), "the context's preconditioner has no AMG stage");
+        if (!c->jac_ready) {
+            set_err("no assembled Jacobian (call fim_assemble first)");
+            throw StateError();
+        }
+        if (!c->prec_ready) prec_setup(c);
+        AmgLevel L = c->lv.back();
+        const int nc = L.nx * L.ny * L.nz, ncs = 2 * L.half, n = ncs + L.nw;
+        // natural order <-> the level's colour-split order (padded entries 0)
+        std::vector<double> bs(n, 0.0), xs(n);
+        auto split = [&](int cn) {
+            const int i = cn % L.nx, j = (cn / L.nx) % L.ny, k = cn / (L.nx * L.ny);
+            const int cc = i + L.nxp * (j + L.ny * k);
+            return (((i + j + k) & 1) ? L.half : 0) + (cc >> 1);
+        };
+        for (int cn = 0; cn < nc; ++cn) bs[split(cn)] = b[cn];
+        for (int w = 0; w < L.nw; ++w) bs[ncs + w] = b[nc + w];
+        // private right-hand side and result: the level's own arrays are left alone
+        double *db = c->alloc<double>(n), *dx = c->alloc<double>(n);
+        HIPCHECK(hipMemcpyAsync(db, bs.data(), n * 8, hipMemcpyHostToDevice, c->s));
+        L.b = db;
+        L.x = dx;
+        if (c->exact_on) launch_amg_exact_solve(c->s, L, c->ex);
+        else launch_amg_coarsest_solve(c->s, L, c->Minv);
+        HIPCHECK(hipGetLastError());
+        HIPCHECK(hipMemcpyAsync(xs.data(), dx, n * 8, hipMemcpyDeviceToHost, c->s));
+        c->sync();
+        c->release(db);
+        c->release(dx);
+        for (int cn = 0; cn < nc; ++cn) x[cn] = xs[split(cn)];
+        for (int w = 0; w < L.nw; ++w) x[nc + w] = xs[ncs + w];
         return FIM_OK;
     });
 }

@@ -21,6 +21,7 @@
 
 #include "fim_block.h"
 #include "fim_internal.h"
+#include "fim_reduce.h"
 
 namespace fim {
 
@@ -45,15 +46,8 @@ __device__ inline void buf_st(__amdgpu_buffer_rsrc_t rs, int off, double v) {
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, (float)v), rs, off, 0, 0);
 }
 
-// Workgroup barrier ordering LDS only.  __syncthreads() also orders global
-// memory, so it waits for every load in flight, the sweep prefetches
-// included; the sweeps and the pencil factorisation exchange values through LDS
-// alone.
-__device__ inline void lds_barrier() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-    __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
+// (the sweeps and the pencil factorisation exchange values through LDS
+// alone: lds_barrier, from fim_reduce.h)
 
 struct TileBox {
     int i0, j0, k0, txe, tye, tze;   // origin and extents (clipped at the grid edge)

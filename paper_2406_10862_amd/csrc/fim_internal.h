@@ -199,6 +199,34 @@ void launch_amg_coarsen(hipStream_t s, const AmgLevel &F, const AmgLevel &C, con
 void launch_amg_coarsest_setup(hipStream_t s, const AmgLevel &L, double *M, double *Minv,
                                double *colk, int *bad);
 void launch_amg_coarsest_solve(hipStream_t s, const AmgLevel &L, const double *Minv);
+
+// Exact solve of a coarsest level of up to a few thousand cells by block
+// elimination over slabs: the cells of one coordinate value of the axis
+// (the level's longest) form a slab, the slabs couple only to their two
+// neighbours through the axis's stencil entries (diagonal blocks), and every
+// well lies in one slab and joins its block.  Setup: the Schur complements
+// D_b = A_bb - A_b,b-1 inv(D_b-1) A_b-1,b, each inverted in place by
+// Gauss-Jordan elimination; solve: forward and backward block substitution.
+constexpr int kSlabMax = 96;           // unknowns of one slab (cells and wells)
+constexpr int kExactCellsDefault = 4096;
+constexpr int kExactSlabDoubles = 4096;   // slabs x largest block: the solve's LDS vectors
+struct AmgExact {
+    int axis;                  // 0 = x, 1 = y, 2 = z
+    int nslab;                 // slabs (the level's extent along the axis)
+    int nu, nv;                // in-slab extents: position p = u + nu * v
+    int ncs;                   // cells per slab (nu * nv)
+    int mmax;                  // largest block (cells and the slab's wells)
+    const int *swp;            // [nslab + 1] slab -> range in sw
+    const int *sw;             // wells of each slab, ascending
+    const int *wrank;          // [nw] position of a well among its slab's wells
+    double *binv;              // [nslab][mmax][mmax] inverted Schur complements
+    int *bad;                  // set on a zero or non-finite pivot
+};
+size_t exact_solve_lds(const AmgExact &E);     // dynamic LDS of the solve (bytes)
+size_t exact_factor_lds(const AmgExact &E);    // and of the factorisation
+hipError_t exact_allow_lds();
+void launch_amg_exact_factor(hipStream_t s, const AmgLevel &L, const AmgExact &E);
+void launch_amg_exact_solve(hipStream_t s, const AmgLevel &L, const AmgExact &E);
 void launch_amg_sweep(hipStream_t s, const AmgLevel &L, const AmgLevel &C, int color, int mode);
 void launch_amg_presmooth(hipStream_t s, const AmgLevel &L);
 // seg_min: levels with at least this many entries per colour restrict by
@@ -360,6 +388,8 @@ struct Member {
     const int *split0, *colsplit;
     double *wq, *ap, *Mden, *Minv, *colk;
     int *amg_bad;
+    int exact;              // coarsest level solved by slabs (ex), else densely (Minv)
+    AmgExact ex;
     const int *ops;         // the member's whole AMG cycle, as a phase list
     int nops;
     double *rbuf;           // residuals of a restriction (2*half of level 0)
@@ -425,10 +455,11 @@ void launchb_residual(hipStream_t s, const Member *mem, Batch part, int tpart, B
                       int tone, int slot);
 void launchb_cpr_restrict(hipStream_t s, int nb, const Member *mem, Batch B, int total, int j,
                           int first_bit, int s_norm, int s_res);
-void launchb_amg_cycle(hipStream_t s, const Member *mem, Batch one, int tone);
+void launchb_amg_cycle(hipStream_t s, const Member *mem, Batch one, int tone, size_t exact_lds);
 void launchb_amg_extract(hipStream_t s, int nb, const Member *mem, Batch B, int total);
 void launchb_amg_coarsen(hipStream_t s, const Member *mem, Batch B, int total, int level);
-void launchb_amg_coarsest(hipStream_t s, const Member *mem, Batch one, int tone, int nmax);
+void launchb_amg_coarsest(hipStream_t s, const Member *mem, Batch one, int tone, int nmax,
+                          size_t exact_lds);
 void launchb_ilu_factor(hipStream_t s, int nb, const Member *mem, Batch B, int total, int threads,
                         size_t lds);
 void launchb_ilu_solve(hipStream_t s, int nb, const Member *mem, Batch B, int total, int j,

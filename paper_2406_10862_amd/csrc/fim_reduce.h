@@ -12,6 +12,15 @@ namespace fim {
 
 constexpr int kWaves = kBlock / 64;
 
+// Workgroup barrier ordering LDS only.  __syncthreads() also orders global
+// memory, so it waits for every load in flight, prefetches included; for
+// phases that exchange values through LDS alone.
+__device__ inline void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // sum, or a maximum that keeps NaN (a non-finite residual must not vanish)
 __device__ inline double rop(double a, double b, bool mx) {
     return mx ? ((b > a || b != b) ? b : a) : a + b;

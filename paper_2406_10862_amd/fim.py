@@ -62,7 +62,7 @@ class FimOptions(C.Structure):
                 ("profile", C.c_int32), ("amg_cycle", C.c_int32), ("amg_sweeps", C.c_int32),
                 ("graphs", C.c_int32), ("forcing", C.c_int32), ("amg_fused", C.c_int32),
                 ("tile_nx", C.c_int32), ("tile_ny", C.c_int32), ("tile_nz", C.c_int32),
-                ("amg_seg_rows", C.c_int32), ("gs_refine", C.c_int32), ("reserved", C.c_int32)]
+                ("amg_seg_rows", C.c_int32), ("gs_refine", C.c_int32), ("amg_exact", C.c_int32)]
 
 
 class FimStepReport(C.Structure):
@@ -96,7 +96,7 @@ EXPORTS = ["fim_create", "fim_destroy", "fim_last_error", "fim_sizes", "fim_set_
            "fim_get_well_rates", "fim_static", "fim_set_iterate", "fim_props",
            "fim_assemble", "fim_precond_apply", "fim_linear_solve", "fim_bsr_spmv",
            "fim_ensemble_run", "fim_adjoint_gradient", "fim_step_noalloc", "fim_set_perm",
-           "fim_set_perm_dev", "fim_ensemble_tune", "fim_amg_level"]
+           "fim_set_perm_dev", "fim_ensemble_tune", "fim_amg_level", "fim_amg_coarse_solve"]
 
 _LIB = None
 
@@ -147,6 +147,7 @@ def lib():
                                        C.POINTER(FimAdjointReport)]
     L.fim_set_perm.argtypes = [vp, f64p, f64p, f64p]
     L.fim_amg_level.argtypes = [vp, C.c_int32, i32p, f64p]
+    L.fim_amg_coarse_solve.argtypes = [vp, f64p, f64p]
     L.fim_ensemble_tune.argtypes = [C.c_int32, C.POINTER(vp), C.c_double, C.c_int32, C.c_char_p,
                                     C.POINTER(FimTuneReport)]
     L.fim_set_perm_dev.argtypes = [vp, vp, vp, vp]
@@ -234,7 +235,8 @@ def options_struct(o: rv.Options, profile=False) -> FimOptions:
                       amg_cycle=o.amg_cycle, amg_sweeps=o.amg_sweeps, graphs=o.graphs,
                       forcing=o.forcing, amg_fused=o.amg_fused,
                       tile_nx=o.tile[0], tile_ny=o.tile[1], tile_nz=o.tile[2],
-                      amg_seg_rows=o.amg_seg_rows, gs_refine=o.gs_refine)
+                      amg_seg_rows=o.amg_seg_rows, gs_refine=o.gs_refine,
+                      amg_exact=o.amg_exact)
 
 
 class Fim:
@@ -435,6 +437,13 @@ class Fim:
         _check(lib().fim_amg_level(self.h, int(level), _p(dims, i32p), _p(A, f64p)),
                "fim_amg_level")
         return A, tuple(int(v) for v in dims)
+
+    def fim_amg_coarse_solve(self, b):
+        """The coarsest level's solve of the cycle for b (fim_amg_level order)."""
+        b = _f64(b)
+        x = np.zeros_like(b)
+        _check(lib().fim_amg_coarse_solve(self.h, _p(b, f64p), _p(x, f64p)), "fim_amg_coarse_solve")
+        return x
 
     def fim_amg_levels(self):
         """Number of AMG levels of the CPR stage."""

@@ -100,6 +100,7 @@ class Options:
     tile: tuple = (0, 0, 0)     # block-Jacobi ILU(0) subdomain box (0 = 8 cells per axis)
     amg_seg_rows: int = 0       # entries per colour from which AMG restricts by row segments
     gs_refine: int = 0          # Gram-Schmidt second pass: 1 when cancelled, -1 never, 0 default (never)
+    amg_exact: int = 0          # cells of a coarsest level solved exactly by slabs (<= 0: off)
 
 
 @dataclass

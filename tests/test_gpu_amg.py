@@ -60,13 +60,20 @@ def _interp(dims_f, dims_c):
     return P
 
 
-@pytest.mark.parametrize("cfg", ["c5", "c3"])
-def test_pressure_hierarchy_is_quasi_impes_then_galerkin(cfg):
+def _case(cfg):
     if cfg == "c5":
-        res = rv.config_c5(13, 10, 5)           # two phases, odd x and z
-    else:
-        res = rv.config_c3(9, 7, 5)             # three phases, every dimension odd
-    g = fim.Fim(res, options=rv.Options(precond=rv.PREC_CPR_ILU0, tile=(5, 5, 3)))
+        return rv.config_c5(13, 10, 5)          # two phases, odd x and z
+    if cfg == "c3":
+        return rv.config_c3(9, 7, 5)            # three phases, every dimension odd
+    return rv.config_c2_small(30, 44, 12)       # a hierarchy of several levels
+
+
+@pytest.mark.parametrize("exact", [4096, 0])
+@pytest.mark.parametrize("cfg", ["c5", "c3", "c2"])
+def test_pressure_hierarchy_is_quasi_impes_then_galerkin(cfg, exact):
+    res = _case(cfg)
+    g = fim.Fim(res, options=rv.Options(precond=rv.PREC_CPR_ILU0, tile=(5, 5, 3),
+                                        amg_exact=exact))
     g.set_initial_state()
     dt = float(res.schedule[0])
     assert g.fim_step(dt)[0] == fim.FIM_OK      # a state away from the initial one
@@ -91,7 +98,44 @@ def test_pressure_hierarchy_is_quasi_impes_then_galerkin(cfg):
         # a coarse well row and column carry the sums of the fine couplings
         assert np.array_equal(A[-dims[3]:, -dims[3]:] != 0, gal[-dims[3]:, -dims[3]:] != 0)
         prev, dprev = A, dims
-    assert dprev[0] * dprev[1] * dprev[2] <= 64
+    # the coarsest level: densely inverted (at most 64 cells), or solved by
+    # slabs (at most 4096 cells), which ends the hierarchy earlier
+    assert dprev[0] * dprev[1] * dprev[2] <= (64 if exact <= 0 else exact)
+
+
+@pytest.mark.parametrize("cfg", ["c5", "c3", "c2"])
+def test_coarse_solve_is_exact(cfg):
+    """The coarsest level's solve, by slabs (amg_exact) and by the dense
+    inverse (the default), against LAPACK on the level's dense operator."""
+    res = _case(cfg)
+    out = {}
+    for exact in (4096, 0):
+        g = fim.Fim(res, options=rv.Options(precond=rv.PREC_CPR_ILU0, tile=(5, 5, 3),
+                                            amg_exact=exact))
+        g.set_initial_state()
+        dt = float(res.schedule[0])
+        assert g.fim_step(dt)[0] == fim.FIM_OK
+        g.fim_assemble(dt)
+        nl = g.fim_amg_levels()
+        A, dims = g.fim_amg_level(nl - 1)
+        b = np.random.default_rng(3).standard_normal(A.shape[0])
+        x = g.fim_amg_coarse_solve(b)
+        ref = np.linalg.solve(A, b)
+        err = np.abs(x - ref).max() / np.abs(ref).max()
+        res_norm = np.abs(A @ x - b).max() / np.abs(b).max()
+        print(f"{cfg} amg_exact={exact}: {nl} levels, coarsest {dims}, error {err:.1e}, "
+              f"residual {res_norm:.1e}")
+        assert err <= 1e-9 and res_norm <= 1e-11
+        out[exact] = (nl, dims)
+    # the slab solve takes the place of the levels below it
+    assert out[4096][0] <= out[0][0]
+
+
+def test_amg_exact_is_fixed_at_creation():
+    res = rv.config_c5(8, 6, 3)
+    g = fim.Fim(res)
+    with pytest.raises(fim.FimError, match="amg_exact"):
+        g.fim_set_options(rv.Options(amg_exact=4096))
 
 
 def test_amg_level_rejects_contexts_without_cpr():

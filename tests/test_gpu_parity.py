@@ -701,14 +701,19 @@ def _ensemble_members(options=None):
     return res, members
 
 
-def test_ensemble_members_equal_their_runs_alone():
+@pytest.mark.parametrize("exact", [0, 4096])
+def test_ensemble_members_equal_their_runs_alone(exact):
+    """Bitwise, with the default coarsest solve and with the coarsest level
+    solved by slabs (each member's own slab problem inside the batched
+    cycle)."""
     nsteps = 3
-    res, members = _ensemble_members()
+    opts = rv.Options(amg_exact=exact)
+    res, members = _ensemble_members(opts)
     dt = np.array([r.schedule[:nsteps] for r in res])
     rc, status, reps = fim.fim_ensemble_run(members, dt)
     assert rc == fim.FIM_OK and np.all(status == fim.FIM_OK)
     for k, r in enumerate(res):
-        alone = fim.Fim(r)
+        alone = fim.Fim(r, options=opts)
         alone.set_initial_state()
         for s in range(nsteps):
             rc1, rep1 = alone.fim_step(dt[k, s])
