@@ -172,7 +172,13 @@ typedef struct {
  * every well lies in one slab; that level is solved exactly, by block
  * elimination over the slabs, and the level above it then runs a V-cycle
  * (otherwise the levels go down to at most 64 cells, inverted densely).  It
- * is fixed when the context is created.  profile = k > 0
+ * is fixed when the context is created.  amg_exact_mode (with amg_exact, fixed
+ * at creation): 0 = the level's dense inverse, formed from the slab factors
+ * once per preconditioner setup and applied as a product over the whole
+ * device (the default; it holds (2 half + nwells)^2 doubles, at most 8192
+ * columns, else mode 1 is used); 1 = block substitution over the slabs in
+ * one workgroup at every application (what members of fim_ensemble_run
+ * always use).  profile = k > 0
  * has every k-th Krylov SpMV launch of fim_step (k = 1: every one) stamp
  * its own start and end into a pair of HIP events and reports the summed
  * kernel time of the stamped launches and their count in fim_step_report.  precision FIM_MIXED (with an ILU(0)
@@ -187,7 +193,7 @@ typedef struct {
     int32_t max_newton, max_lin, restart, max_cuts;
     int32_t precond, precision, profile, amg_cycle, amg_sweeps, graphs, forcing, amg_fused;
     int32_t tile_nx, tile_ny, tile_nz, amg_seg_rows;
-    int32_t gs_refine, amg_exact;
+    int32_t gs_refine, amg_exact, amg_exact_mode;
 } fim_options;
 
 #define FIM_MAX_SUB 256

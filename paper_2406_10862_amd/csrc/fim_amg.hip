@@ -640,18 +640,38 @@ __device__ void slab_block(const AmgLevel &L, const AmgExact &E, int b, int m, d
     __syncthreads();
 }
 
-// One workgroup: the Schur complements of the slabs in order, each
-// inverted in place (Gauss-Jordan without pivoting: the pressure operator's
-// Schur complements keep its diagonal dominance), stored to E.binv.
-// Element loops run rows over waves and columns over lanes (no division).
+// a lane's double, read by every lane of the wave (l uniform)
+__device__ inline double readlane_d(double v, int l) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+constexpr int kSlabRows = (kSlabMax + 15) / 16;    // rows of a slab block per wave
+
+// One 1024-thread workgroup: the Schur complements of the slabs in order,
+// each inverted by Gauss-Jordan without pivoting (the pressure operator's
+// Schur complements keep its diagonal dominance; a zero or non-finite pivot
+// sets *E.bad), stored to E.binv.  The block lives in registers: wave w
+// holds rows w + 16 i, lane l columns l and l + 64.  Step k: the wave
+// holding row k scales it (the pivot's own entry becomes 1 / pivot) and
+// passes it on through LDS (two buffers, so one barrier per step); every
+// other row r takes a_rq - a_rk a'_kq, with a_rk read from its lane and
+// column k entering as zero (so it becomes -a_rk / pivot).  The inverse of
+// one slab stays in the registers for the next slab's Schur complement,
+// whose couplings are diagonal (a cell to the same position of the
+// neighbouring slab).
 __device__ void exact_factor_wg(const AmgLevel &L, const AmgExact &E, double *lds) {
     const int tid = threadIdx.x, nt = blockDim.x;
-    const int lane = tid & 63, wave = tid >> 6, nwaves = nt >> 6;
-    const int mm = E.mmax * E.mmax;
-    double *A = lds, *P = lds + mm, *F = lds + 2 * mm;
-    double *am = F + E.mmax, *apv = am + E.mmax;   // couplings to the slab before
+    const int lane = tid & 63, wave = tid >> 6;
+    double *A = lds;                                  // [mmax * mmax], stride m
+    double *U = lds + (size_t)E.mmax * E.mmax;        // [2][mmax] scaled pivot rows
+    double *am = U + 2 * E.mmax, *apv = am + E.mmax;  // couplings to the slab before
     const int dm = 2 * E.axis + 1, dp = 2 * E.axis + 2;
-    int mprev = 0;
+    double a[kSlabRows][2];
+#pragma unroll
+    for (int i = 0; i < kSlabRows; ++i) a[i][0] = a[i][1] = 0.0;
     for (int b = 0; b < E.nslab; ++b) {
         const int m = E.ncs + E.swp[b + 1] - E.swp[b];
         if (b > 0)
@@ -660,65 +680,73 @@ __device__ void exact_factor_wg(const AmgLevel &L, const AmgExact &E, double *ld
                 apv[p] = slab_coef(L, E, b - 1, p, dp);
             }
         slab_block(L, E, b, m, A);                  // (ends with a barrier)
-        if (b > 0) {
-            // A_bb -= A_b,b-1 inv(D_b-1) A_b-1,b: both couplings are diagonal
-            // (a cell to the same position of the neighbouring slab)
-            for (int r = wave; r < E.ncs; r += nwaves)
-                for (int q = lane; q < E.ncs; q += 64)
-                    A[(size_t)r * m + q] -= am[r] * P[(size_t)r * mprev + q] * apv[q];
-            __syncthreads();
-        }
-        // Step kk: the pivot row scaled (its diagonal, the inverted pivot,
-        // written in step kk + 1 or after the last step: the pivot is read
-        // at the start of its own step), the pivot column saved; then every
-        // other row r takes a_rq - f_r a'_kq (a_rk becomes -f_r / piv).  A
-        // thread takes one column (lane, lane + 64) and the rows of its
-        // wave, so the pivot row's entry is loaded once.
-        double ip = 0.0;
-        for (int kk = 0; kk < m; ++kk) {
-            const double piv = A[(size_t)kk * m + kk];
-            if (tid == 0 && kk > 0) A[(size_t)(kk - 1) * m + kk - 1] = ip;
-            ip = 1.0 / piv;
-            if (tid == 0 && !(fabs(piv) > 0.0 && isfinite(piv))) *E.bad = 1;
-            for (int e = tid; e < m; e += nt) {
-                F[e] = e == kk ? 0.0 : A[(size_t)e * m + kk];
-                if (e != kk) A[(size_t)kk * m + e] *= ip;
-            }
-            lds_barrier();
-            // (rows wave + 16 t of the 16 waves, all of a thread's loads
-            // issued before its first product; a slot past the block reads
-            // entry 0 and stores nothing)
-            constexpr int kR = (kSlabMax + 15) / 16;
+        // D_b = A_bb - A_b,b-1 inv(D_b-1) A_b-1,b on the cell rows and columns
+#pragma unroll
+        for (int i = 0; i < kSlabRows; ++i) {
+            const int r = wave + 16 * i;
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const int q = lane + 64 * h;
-                const bool qon = q < m;
-                const int qq = qon ? q : 0;
-                const double akq = A[(size_t)kk * m + qq];
-                double a[kR], f[kR];
-#pragma unroll
-                for (int t = 0; t < kR; ++t) {
-                    const int r = wave + 16 * t, rr = r < m ? r : 0;
-                    a[t] = A[(size_t)rr * m + qq];
-                    f[t] = F[rr];
+                double v = 0.0;
+                if (r < m && q < m) {
+                    v = A[(size_t)r * m + q];
+                    if (b > 0 && r < E.ncs && q < E.ncs) v -= am[r] * a[i][h] * apv[q];
                 }
+                a[i][h] = v;
+            }
+        }
+        // Gauss-Jordan, step k = 16 oi + ow (the row slot oi is a constant
+        // of the unrolled loop, so the registers are indexed statically)
 #pragma unroll
-                for (int t = 0; t < kR; ++t) {
-                    const int r = wave + 16 * t;
-                    if (qon && r < m && r != kk)
-                        A[(size_t)r * m + q] = q == kk ? -f[t] * ip : a[t] - f[t] * akq;
+        for (int oi = 0; oi < kSlabRows; ++oi) {
+            const int h = oi >= 4 ? 1 : 0;          // the slot of column k = 16 oi + ow
+            for (int ow = 0; ow < 16; ++ow) {
+                const int k = 16 * oi + ow;
+                if (k >= m) break;
+                const int lk = k - 64 * h;
+                double *Uk = U + (k & 1) * E.mmax;
+                if (wave == ow) {
+                    const double piv = readlane_d(a[oi][h], lk);
+                    const double ip = 1.0 / piv;
+                    if (lane == 0 && !(fabs(piv) > 0.0 && isfinite(piv))) *E.bad = 1;
+#pragma unroll
+                    for (int hh = 0; hh < 2; ++hh) {
+                        const int q = lane + 64 * hh;
+                        if (q < m) Uk[q] = q == k ? ip : a[oi][hh] * ip;
+                    }
+                }
+                lds_barrier();
+                const double u0 = Uk[lane], u1 = lane + 64 < m ? Uk[lane + 64] : 0.0;
+#pragma unroll
+                for (int i = 0; i < kSlabRows; ++i) {
+                    const int r = wave + 16 * i;
+                    if (r >= m) continue;
+                    if (r == k) {
+                        a[i][0] = u0;
+                        a[i][1] = u1;
+                        continue;
+                    }
+                    const double f = readlane_d(a[i][h], lk);
+                    double v0 = a[i][0], v1 = a[i][1];
+                    if (h == 0 && lane == lk) v0 = 0.0;
+                    if (h == 1 && lane == lk) v1 = 0.0;
+                    a[i][0] = v0 - f * u0;
+                    a[i][1] = v1 - f * u1;
                 }
             }
-            lds_barrier();
         }
-        if (tid == 0) A[(size_t)(m - 1) * m + m - 1] = ip;
-        lds_barrier();
-        double *dst = E.binv + (size_t)b * mm;
-        for (int e = tid; e < m * m; e += nt) dst[e] = A[e];
-        double *t = A;
-        A = P;
-        P = t;
-        mprev = m;
+        double *dst = E.binv + (size_t)b * E.mmax * E.mmax;
+#pragma unroll
+        for (int i = 0; i < kSlabRows; ++i) {
+            const int r = wave + 16 * i;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int q = lane + 64 * h;
+                if (r < m && q < m) dst[(size_t)r * m + q] = a[i][h];
+            }
+        }
+        // (the next slab's coefficients and block overwrite LDS only after
+        // every thread has read this slab's: a barrier ends each step)
         __syncthreads();
     }
 }
@@ -856,6 +884,135 @@ __device__ void exact_solve_wg(const AmgLevel &L, const AmgExact &E, double *z) 
 __global__ __launch_bounds__(1024) void k_amg_exact_solve(AmgLevel L, AmgExact E) {
     extern __shared__ double lds[];
     exact_solve_wg(L, E, lds);
+}
+
+// Storage index (the level's split order; wells after the cells) of slab b,
+// position p.
+__device__ inline int slab_storage(const AmgLevel &L, const AmgExact &E, int b, int p) {
+    if (p >= E.ncs) return 2 * L.half + E.sw[E.swp[b] + p - E.ncs];
+    int i, j, k;
+    slab_cell(E, b, p, i, j, k);
+    return split_of(L, i, j, k);
+}
+
+// The level's inverse X = A^-1 from the slab factors, kInvCols columns per
+// workgroup: the columns of positions p0 .. p0 + 7 of slab s solved by the
+// block substitution (forward from slab s, where the right-hand side starts,
+// so z_s is a column of inv(D_s); backward over every slab), with thread
+// (r, c) forming row r of column c.  Each step's result goes to its rows of
+// X at once (the forward results are read back by the same threads in the
+// backward sweep).  Grid: nslab x ceil(mmax / kInvCols) workgroups of
+// kInvCols * kSlabMax threads.
+constexpr int kInvCols = 8;
+__global__ __launch_bounds__(kInvCols * kSlabMax) void k_amg_exact_inverse(AmgLevel L, AmgExact E) {
+    __shared__ double zx[kSlabMax][kInvCols], t[kSlabMax][kInvCols];
+    const int groups = (E.mmax + kInvCols - 1) / kInvCols;
+    const int s = blockIdx.x / groups, p0 = (blockIdx.x % groups) * kInvCols;
+    const int ms = E.ncs + E.swp[s + 1] - E.swp[s];
+    if (p0 >= ms) return;                                 // (uniform over the block)
+    const int r = threadIdx.x / kInvCols, c = threadIdx.x % kInvCols;
+    const bool con = p0 + c < ms;
+    const size_t col = con ? (size_t)slab_storage(L, E, s, p0 + c) : 0;
+    const int dm = 2 * E.axis + 1, dp = 2 * E.axis + 2;
+    const size_t mm = (size_t)E.mmax * E.mmax;
+    auto slab_m = [&](int b) { return E.ncs + E.swp[b + 1] - E.swp[b]; };
+    // row r of inv(D_b) t (four partial sums, q in order within each)
+    auto product = [&](int b, int m) {
+        const double *B = E.binv + (size_t)b * mm + (size_t)r * m;
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        int q = 0;
+        for (; q + 4 <= m; q += 4) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc[u] += B[q + u] * t[q + u][c];
+        }
+        for (; q < m; ++q) acc[q & 3] += B[q] * t[q][c];
+        return (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    };
+    // forward: z_s = column p0 + c of inv(D_s); z_b = inv(D_b) (-A_b,b-1 z_b-1)
+    for (int b = s; b < E.nslab; ++b) {
+        const int m = slab_m(b);
+        if (b > s) {
+            if (r < m) {
+                double v = 0.0;
+                if (r < E.ncs) v = -slab_coef(L, E, b, r, dm) * zx[r][c];
+                t[r][c] = v;
+            }
+            __syncthreads();
+        }
+        double z = 0.0;
+        if (r < m) {
+            z = b == s ? (con ? E.binv[(size_t)b * mm + (size_t)r * m + p0 + c] : 0.0)
+                       : product(b, m);
+        }
+        __syncthreads();                                   // (t and zx read)
+        if (r < m) {
+            zx[r][c] = z;
+            if (con) E.X[(size_t)slab_storage(L, E, b, r) * E.ldx + col] = z;
+        }
+        __syncthreads();
+    }
+    // backward: x_b = z_b - inv(D_b) A_b,b+1 x_b+1 (z_b = 0 before slab s)
+    for (int b = E.nslab - 2; b >= 0; --b) {
+        const int m = slab_m(b);
+        if (r < m) {
+            double v = 0.0;
+            if (r < E.ncs) v = slab_coef(L, E, b, r, dp) * zx[r][c];
+            t[r][c] = v;
+        }
+        __syncthreads();
+        double x = 0.0;
+        size_t row = 0;
+        if (r < m) {
+            row = (size_t)slab_storage(L, E, b, r) * E.ldx;
+            const double zb = (b >= s && con) ? E.X[row + col] : 0.0;
+            x = zb - product(b, m);
+        }
+        __syncthreads();
+        if (r < m) {
+            zx[r][c] = x;
+            if (con) E.X[row + col] = x;
+        }
+        __syncthreads();
+    }
+}
+
+// x = X b over the whole chip: a wave per row (16-byte loads, four partial
+// sums, a fixed shuffle tree), b staged in LDS by each workgroup (padded
+// entries as zero).  Grid: ceil(nst / kGemvRows) workgroups of 64 kGemvRows.
+constexpr int kGemvRows = 8;
+__global__ __launch_bounds__(64 * kGemvRows) void k_amg_exact_gemv(AmgLevel L, AmgExact E) {
+    extern __shared__ double bs[];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int e = tid; e < E.ldx; e += blockDim.x) {
+        double v = 0.0;
+        if (e < E.nst && (e >= 2 * L.half || pos_of(L, e).i < L.nx)) v = L.b[e];
+        bs[e] = v;
+    }
+    __syncthreads();
+    const int row = blockIdx.x * kGemvRows + wave;
+    if (row >= E.nst) return;
+    const double2 *X = reinterpret_cast<const double2 *>(E.X + (size_t)row * E.ldx);
+    const double2 *B = reinterpret_cast<const double2 *>(bs);
+    const int n2 = E.ldx / 2;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    int f = lane;
+    for (; f + 192 < n2; f += 256) {
+        double2 xv[4], bv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) xv[u] = X[f + 64 * u];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) bv[u] = B[f + 64 * u];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[u] += xv[u].x * bv[u].x + xv[u].y * bv[u].y;
+    }
+    for (int u = 0; f < n2; f += 64, ++u) {
+        const double2 xv = X[f], bv = B[f];
+        acc[u & 3] += xv.x * bv.x + xv.y * bv.y;
+    }
+    double v = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0) L.x[row] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -1559,13 +1716,13 @@ size_t exact_solve_lds(const AmgExact &E) {
            sizeof(double);
 }
 size_t exact_factor_lds(const AmgExact &E) {
-    return ((size_t)2 * E.mmax * E.mmax + 3 * E.mmax + 2) * sizeof(double);
+    return ((size_t)E.mmax * E.mmax + 4 * E.mmax) * sizeof(double);
 }
 
 // the largest LDS of a slab problem the plan admits (nslab * mmax <=
 // kExactSlabDoubles, ncs <= mmax <= kSlabMax), which every context shares
 static size_t exact_factor_lds_max() {
-    return ((size_t)2 * kSlabMax * kSlabMax + 3 * kSlabMax + 2) * sizeof(double);
+    return ((size_t)kSlabMax * kSlabMax + 4 * kSlabMax) * sizeof(double);
 }
 static size_t exact_solve_lds_max() {
     return ((size_t)4 * kExactSlabDoubles + kSlabMax + (kExactSlabDoubles + 2) / 2) * sizeof(double);
@@ -1587,6 +1744,17 @@ void launch_amg_exact_factor(hipStream_t s, const AmgLevel &L, const AmgExact &E
 
 void launch_amg_exact_solve(hipStream_t s, const AmgLevel &L, const AmgExact &E) {
     hipLaunchKernelGGL(k_amg_exact_solve, dim3(1), dim3(1024), exact_solve_lds(E), s, L, E);
+}
+
+void launch_amg_exact_inverse(hipStream_t s, const AmgLevel &L, const AmgExact &E) {
+    const int groups = (E.mmax + kInvCols - 1) / kInvCols;
+    hipLaunchKernelGGL(k_amg_exact_inverse, dim3((unsigned)(E.nslab * groups)),
+                       dim3(kInvCols * kSlabMax), 0, s, L, E);
+}
+
+void launch_amg_exact_gemv(hipStream_t s, const AmgLevel &L, const AmgExact &E) {
+    hipLaunchKernelGGL(k_amg_exact_gemv, dim3((unsigned)((E.nst + kGemvRows - 1) / kGemvRows)),
+                       dim3(64 * kGemvRows), (size_t)E.ldx * sizeof(double), s, L, E);
 }
 
 void launch_amg_sweep(hipStream_t s, const AmgLevel &L, const AmgLevel &C, int color, int mode) {

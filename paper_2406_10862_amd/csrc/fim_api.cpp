@@ -279,6 +279,7 @@ static void check_options(const fim_options *o) {
     REQUIRE(o->gs_refine >= -1 && o->gs_refine <= 1, "gs_refine must be -1, 0 or 1");
     REQUIRE(o->profile >= 0, "profile must be >= 0");
     REQUIRE(o->amg_exact >= -1 && o->amg_exact <= (1 << 20), "amg_exact must be in [-1, 2^20]");
+    REQUIRE(o->amg_exact_mode == 0 || o->amg_exact_mode == 1, "amg_exact_mode must be 0 or 1");
 }
 
 static void build_pattern(fim_ctx *c, std::vector<int> &rp, std::vector<int> &ci,
@@ -492,6 +493,16 @@ static void build_amg(fim_ctx *c, const std::vector<int> &sorted_cells,
         c->ex.bad = c->amg_bad;
         c->ex.binv = c->alloc<double>((size_t)c->ex.nslab * c->ex.mmax * c->ex.mmax);
         HIPCHECK(exact_allow_lds());            // the same value for every context
+        // mode 0: room for the level's dense inverse (rows and columns in
+        // storage order; padded ones stay zero)
+        const AmgLevel &Lc = c->lv.back();
+        c->ex.nst = 2 * Lc.half + Lc.nw;
+        c->ex.ldx = (c->ex.nst + 1) & ~1;
+        c->ex.X = nullptr;
+        if (c->opt.amg_exact_mode == 0 && c->ex.ldx <= kExactGemvCols) {
+            c->ex.X = c->alloc<double>((size_t)c->ex.nst * c->ex.ldx);
+            HIPCHECK(hipMemsetAsync(c->ex.X, 0, (size_t)c->ex.nst * c->ex.ldx * sizeof(double), c->s));
+        }
     } else {
         const AmgLevel &Lc = c->lv.back();
         const size_t n = 2 * (size_t)Lc.half + Lc.nw;
@@ -507,8 +518,17 @@ static void build_amg(fim_ctx *c, const std::vector<int> &sorted_cells,
 // The coarsest level's solver from its current operator: the slab
 // factorisation, or the dense inverse.
 static void coarsest_setup(fim_ctx *c) {
-    if (c->exact_on) launch_amg_exact_factor(c->s, c->lv.back(), c->ex);
-    else launch_amg_coarsest_setup(c->s, c->lv.back(), c->Mden, c->Minv, c->colk, c->amg_bad);
+    if (c->exact_on) {
+        launch_amg_exact_factor(c->s, c->lv.back(), c->ex);
+        if (c->ex.X) launch_amg_exact_inverse(c->s, c->lv.back(), c->ex);
+    } else launch_amg_coarsest_setup(c->s, c->lv.back(), c->Mden, c->Minv, c->colk, c->amg_bad);
+}
+
+// x = A^-1 b on the slab-solved coarsest level: by its dense inverse over
+// the whole device, or by substitution over the slabs in one workgroup.
+static void exact_apply(fim_ctx *c, const AmgLevel &L) {
+    if (c->ex.X) launch_amg_exact_gemv(c->s, L, c->ex);
+    else launch_amg_exact_solve(c->s, L, c->ex);
 }
 
 static void build_subcycle(fim_ctx *c);
@@ -856,7 +876,7 @@ static void amg_cycle(fim_ctx *c, int l, std::vector<int> *rec = nullptr, int ro
     const int rl = l - root;
     if (l == L - 1) {
         if (rec) rec->push_back(amg_op(kOpCoarse, rl));
-        else if (c->exact_on) launch_amg_exact_solve(c->s, c->lv[l], c->ex);
+        else if (c->exact_on) exact_apply(c, c->lv[l]);
         else launch_amg_coarsest_solve(c->s, c->lv[l], c->Minv);
         return;
     }
@@ -3104,6 +3124,9 @@ int fim_set_options(fim_ctx *c, const fim_options *opt) {
         REQUIRE(opt->amg_exact == c->opt.amg_exact,
                 "amg_exact is fixed when the context is created (%d, not %d)", c->opt.amg_exact,
                 opt->amg_exact);
+        REQUIRE(opt->amg_exact_mode == c->opt.amg_exact_mode,
+                "amg_exact_mode is fixed when the context is created (%d, not %d)",
+                c->opt.amg_exact_mode, opt->amg_exact_mode);
         c->sync();
         c->drop_graphs();        // captured steps depend on the options and buffers
         if (opt->restart > c->m) {
@@ -3446,7 +3469,7 @@ int fim_amg_coarse_solve(fim_ctx *c, const double *b, double *x) {
         HIPCHECK(hipMemcpyAsync(db, bs.data(), n * 8, hipMemcpyHostToDevice, c->s));
         L.b = db;
         L.x = dx;
-        if (c->exact_on) launch_amg_exact_solve(c->s, L, c->ex);
+        if (c->exact_on) exact_apply(c, L);
         else launch_amg_coarsest_solve(c->s, L, c->Minv);
         HIPCHECK(hipGetLastError());
         HIPCHECK(hipMemcpyAsync(xs.data(), dx, n * 8, hipMemcpyDeviceToHost, c->s));

@@ -209,6 +209,7 @@ void launch_amg_coarsest_solve(hipStream_t s, const AmgLevel &L, const double *M
 // Gauss-Jordan elimination; solve: forward and backward block substitution.
 constexpr int kSlabMax = 96;           // unknowns of one slab (cells and wells)
 constexpr int kExactCellsDefault = 4096;
+constexpr int kExactGemvCols = 8192;      // columns of a dense inverse product (LDS)
 constexpr int kExactSlabDoubles = 4096;   // slabs x largest block: the solve's LDS vectors
 struct AmgExact {
     int axis;                  // 0 = x, 1 = y, 2 = z
@@ -221,12 +222,18 @@ struct AmgExact {
     const int *wrank;          // [nw] position of a well among its slab's wells
     double *binv;              // [nslab][mmax][mmax] inverted Schur complements
     int *bad;                  // set on a zero or non-finite pivot
+    double *X;                 // the level's inverse [nst][ldx], rows and columns in the
+                               // level's storage order (padded ones zero); null: applied
+                               // by substitution over the slabs in one workgroup
+    int nst, ldx;              // 2 * half + nw; row stride (even)
 };
 size_t exact_solve_lds(const AmgExact &E);     // dynamic LDS of the solve (bytes)
 size_t exact_factor_lds(const AmgExact &E);    // and of the factorisation
 hipError_t exact_allow_lds();
 void launch_amg_exact_factor(hipStream_t s, const AmgLevel &L, const AmgExact &E);
 void launch_amg_exact_solve(hipStream_t s, const AmgLevel &L, const AmgExact &E);
+void launch_amg_exact_inverse(hipStream_t s, const AmgLevel &L, const AmgExact &E);
+void launch_amg_exact_gemv(hipStream_t s, const AmgLevel &L, const AmgExact &E);
 void launch_amg_sweep(hipStream_t s, const AmgLevel &L, const AmgLevel &C, int color, int mode);
 void launch_amg_presmooth(hipStream_t s, const AmgLevel &L);
 // seg_min: levels with at least this many entries per colour restrict by

@@ -62,7 +62,8 @@ class FimOptions(C.Structure):
                 ("profile", C.c_int32), ("amg_cycle", C.c_int32), ("amg_sweeps", C.c_int32),
                 ("graphs", C.c_int32), ("forcing", C.c_int32), ("amg_fused", C.c_int32),
                 ("tile_nx", C.c_int32), ("tile_ny", C.c_int32), ("tile_nz", C.c_int32),
-                ("amg_seg_rows", C.c_int32), ("gs_refine", C.c_int32), ("amg_exact", C.c_int32)]
+                ("amg_seg_rows", C.c_int32), ("gs_refine", C.c_int32), ("amg_exact", C.c_int32),
+                ("amg_exact_mode", C.c_int32)]
 
 
 class FimStepReport(C.Structure):
@@ -236,7 +237,7 @@ def options_struct(o: rv.Options, profile=False) -> FimOptions:
                       forcing=o.forcing, amg_fused=o.amg_fused,
                       tile_nx=o.tile[0], tile_ny=o.tile[1], tile_nz=o.tile[2],
                       amg_seg_rows=o.amg_seg_rows, gs_refine=o.gs_refine,
-                      amg_exact=o.amg_exact)
+                      amg_exact=o.amg_exact, amg_exact_mode=o.amg_exact_mode)
 
 
 class Fim:

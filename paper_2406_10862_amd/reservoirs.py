@@ -101,6 +101,7 @@ class Options:
     amg_seg_rows: int = 0       # entries per colour from which AMG restricts by row segments
     gs_refine: int = 0          # Gram-Schmidt second pass: 1 when cancelled, -1 never, 0 default (never)
     amg_exact: int = 0          # cells of a coarsest level solved exactly by slabs (<= 0: off)
+    amg_exact_mode: int = 0     # 0: its dense inverse applied device-wide; 1: slab substitution
 
 
 @dataclass

@@ -105,13 +105,15 @@ def test_pressure_hierarchy_is_quasi_impes_then_galerkin(cfg, exact):
 
 @pytest.mark.parametrize("cfg", ["c5", "c3", "c2"])
 def test_coarse_solve_is_exact(cfg):
-    """The coarsest level's solve, by slabs (amg_exact) and by the dense
-    inverse (the default), against LAPACK on the level's dense operator."""
+    """The coarsest level's solve against LAPACK on the level's dense
+    operator: a slab-solved level (amg_exact) by its dense inverse from the
+    slab factors applied device-wide (mode 0) and by substitution over the
+    slabs (mode 1), and the default coarsest level by its dense inverse."""
     res = _case(cfg)
     out = {}
-    for exact in (4096, 0):
+    for exact, mode in ((4096, 0), (4096, 1), (0, 0)):
         g = fim.Fim(res, options=rv.Options(precond=rv.PREC_CPR_ILU0, tile=(5, 5, 3),
-                                            amg_exact=exact))
+                                            amg_exact=exact, amg_exact_mode=mode))
         g.set_initial_state()
         dt = float(res.schedule[0])
         assert g.fim_step(dt)[0] == fim.FIM_OK
@@ -123,12 +125,12 @@ def test_coarse_solve_is_exact(cfg):
         ref = np.linalg.solve(A, b)
         err = np.abs(x - ref).max() / np.abs(ref).max()
         res_norm = np.abs(A @ x - b).max() / np.abs(b).max()
-        print(f"{cfg} amg_exact={exact}: {nl} levels, coarsest {dims}, error {err:.1e}, "
-              f"residual {res_norm:.1e}")
+        print(f"{cfg} amg_exact={exact} mode {mode}: {nl} levels, coarsest {dims}, "
+              f"error {err:.1e}, residual {res_norm:.1e}")
         assert err <= 1e-9 and res_norm <= 1e-11
-        out[exact] = (nl, dims)
+        out[exact, mode] = (nl, dims)
     # the slab solve takes the place of the levels below it
-    assert out[4096][0] <= out[0][0]
+    assert out[4096, 0] == out[4096, 1] and out[4096, 0][0] <= out[0, 0][0]
 
 
 def test_amg_exact_is_fixed_at_creation():
@@ -136,6 +138,8 @@ def test_amg_exact_is_fixed_at_creation():
     g = fim.Fim(res)
     with pytest.raises(fim.FimError, match="amg_exact"):
         g.fim_set_options(rv.Options(amg_exact=4096))
+    with pytest.raises(fim.FimError, match="amg_exact_mode"):
+        g.fim_set_options(rv.Options(amg_exact_mode=1))
 
 
 def test_amg_level_rejects_contexts_without_cpr():

@@ -705,9 +705,9 @@ def _ensemble_members(options=None):
 def test_ensemble_members_equal_their_runs_alone(exact):
     """Bitwise, with the default coarsest solve and with the coarsest level
     solved by slabs (each member's own slab problem inside the batched
-    cycle)."""
+    cycle, which substitutes over the slabs as amg_exact_mode 1 does)."""
     nsteps = 3
-    opts = rv.Options(amg_exact=exact)
+    opts = rv.Options(amg_exact=exact, amg_exact_mode=1)
     res, members = _ensemble_members(opts)
     dt = np.array([r.schedule[:nsteps] for r in res])
     rc, status, reps = fim.fim_ensemble_run(members, dt)
