@@ -343,6 +343,15 @@ def summarize_kernels(trace_csv, fetch_csv, write_csv, bench_log, out, title, co
                 if l is not None else (None, "")
         if name == "fim::k_amg_subcycle":
             return None, "AMG levels 3-5 in one workgroup (latency)"
+        if name == "fim::k_amg_exact_gemv":
+            nst = 2 * lv[3]["half"] + 5
+            ldx = (nst + 1) // 2 * 2
+            return nst * ldx * 8 + nst * (4 + 8 + 8), \
+                "AMG coarsest level 3: its dense inverse times the right side"
+        if name == "fim::k_amg_exact_factor":
+            return None, "AMG level 3: slab Schur complements inverted (one workgroup, latency)"
+        if name == "fim::k_amg_exact_inverse":
+            return None, "AMG level 3: dense inverse from the slab factors (latency)"
         return None, ""
 
     tot = sum(sum(v) for v in dur.values())
@@ -662,8 +671,12 @@ def main():
                          "levels of at most -value cells, W between")
     ap.add_argument("--amg-sweeps", type=int, default=0,
                     help="red-black sweep pairs before and after each coarse correction (0 = 1)")
-    ap.add_argument("--amg-exact", type=int, default=0,
-                    help="cells of a coarsest AMG level solved exactly by slabs (0: off)")
+    ap.add_argument("--amg-exact", type=int, default=4096,
+                    help="cells of a coarsest AMG level solved exactly by slabs (<= 0: off; "
+                         "4096: level 3 of the five-spot, 8x28x11 in 28 slabs of 88 cells)")
+    ap.add_argument("--amg-exact-mode", type=int, default=0, choices=[0, 1],
+                    help="0: that level's dense inverse applied device-wide; 1: substitution "
+                         "over the slabs in one workgroup")
     ap.add_argument("--gs-refine", type=int, default=0, choices=[-1, 0, 1],
                     help="Gram-Schmidt second pass: 1 when the first cancelled, -1 never, 0 default (never)")
     ap.add_argument("--precond", default="cpr_ilu0", choices=["bj", "ilu0", "cpr", "cpr_ilu0"])
@@ -728,6 +741,7 @@ def main():
     opts.amg_sweeps = args.amg_sweeps
     opts.gs_refine = args.gs_refine
     opts.amg_exact = args.amg_exact
+    opts.amg_exact_mode = args.amg_exact_mode
     opts.precond = {"bj": rv.PREC_BJ, "ilu0": rv.PREC_ILU0, "cpr": rv.PREC_CPR,
                     "cpr_ilu0": rv.PREC_CPR_ILU0}[args.precond]
     if args.tile is None:
@@ -794,7 +808,8 @@ def main():
     extras = {}
     if args.config == "c2" and args.precision == "fp64" and not args.no_extras:
         mopts = tolerances(args.tol)
-        for k in ("amg_cycle", "amg_sweeps", "precond", "tile"):
+        for k in ("amg_cycle", "amg_sweeps", "precond", "tile", "gs_refine", "amg_exact",
+                  "amg_exact_mode"):
             setattr(mopts, k, getattr(opts, k))
         mopts.precision = rv.MIXED
         g.fim_set_options(mopts, profile=SPMV_STAMP_EVERY)
@@ -871,6 +886,14 @@ def main():
                 opts.amg_cycle, f"W on levels <= {opts.amg_cycle} cells, V above"
                 if opts.amg_cycle > 0 else
                 f"V at the finest level and on levels <= {-opts.amg_cycle} cells, W between"),
+            "amg_coarsest": (
+                "level 3 (8x28x11 cells and 5 wells, 2469 unknowns) solved exactly: its 28 slab "
+                "Schur complements inverted and its dense inverse formed once per Newton "
+                "iteration, applied as one device-wide product; the level above it runs V"
+                if opts.amg_exact_mode == 0 else
+                "level 3 solved exactly by block substitution over its 28 slabs in one workgroup")
+            if opts.amg_exact > 0 and args.config == "c2" else
+            "at most 64 cells, inverted densely once per Newton iteration",
             "gmres_restart": opts.restart,
             "newton_iters": newton, "linear_iters": linear, "cuts": cuts,
             "linear_per_newton": linear / newton if newton else None,

@@ -650,24 +650,31 @@ __device__ inline double readlane_d(double v, int l) {
 
 constexpr int kSlabRows = (kSlabMax + 15) / 16;    // rows of a slab block per wave
 
+// Row of register slot i of a wave: rows in pairs (2p, 2p + 1), pair p held
+// by wave p % 16.
+__device__ inline int slab_row(int wave, int i) { return 32 * (i >> 1) + 2 * wave + (i & 1); }
+
 // One 1024-thread workgroup: the Schur complements of the slabs in order,
 // each inverted by Gauss-Jordan without pivoting (the pressure operator's
 // Schur complements keep its diagonal dominance; a zero or non-finite pivot
-// sets *E.bad), stored to E.binv.  The block lives in registers: wave w
-// holds rows w + 16 i, lane l columns l and l + 64.  Step k: the wave
-// holding row k scales it (the pivot's own entry becomes 1 / pivot) and
-// passes it on through LDS (two buffers, so one barrier per step); every
-// other row r takes a_rq - a_rk a'_kq, with a_rk read from its lane and
-// column k entering as zero (so it becomes -a_rk / pivot).  The inverse of
+// sets *E.bad), stored to E.binv.  The block lives in registers: slot i of
+// wave w holds row slab_row(w, i), lane l columns l and l + 64.  Pivots go
+// in pairs k, k + 1: the wave holding both rows takes the two elimination
+// steps on them (row k scaled, its pivot entry becoming 1 / pivot; row k + 1
+// eliminated with it and scaled; row k then eliminated with row k + 1) and
+// passes them on through LDS (two buffers, so one barrier per pair); every
+// other row r then takes a_r - a_rk u_k - a_r,k+1 u_k+1 with columns k and
+// k + 1 entering as zero, which is the two steps at once.  The inverse of
 // one slab stays in the registers for the next slab's Schur complement,
 // whose couplings are diagonal (a cell to the same position of the
 // neighbouring slab).
 __device__ void exact_factor_wg(const AmgLevel &L, const AmgExact &E, double *lds) {
     const int tid = threadIdx.x, nt = blockDim.x;
-    const int lane = tid & 63, wave = tid >> 6;
+    // (the wave index as a scalar, so the row tests below branch uniformly)
+    const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     double *A = lds;                                  // [mmax * mmax], stride m
-    double *U = lds + (size_t)E.mmax * E.mmax;        // [2][mmax] scaled pivot rows
-    double *am = U + 2 * E.mmax, *apv = am + E.mmax;  // couplings to the slab before
+    double *U = lds + (size_t)E.mmax * E.mmax;        // [2][2][mmax] pivot row pairs
+    double *am = U + 4 * E.mmax, *apv = am + E.mmax;  // couplings to the slab before
     const int dm = 2 * E.axis + 1, dp = 2 * E.axis + 2;
     double a[kSlabRows][2];
 #pragma unroll
@@ -683,7 +690,7 @@ __device__ void exact_factor_wg(const AmgLevel &L, const AmgExact &E, double *ld
         // D_b = A_bb - A_b,b-1 inv(D_b-1) A_b-1,b on the cell rows and columns
 #pragma unroll
         for (int i = 0; i < kSlabRows; ++i) {
-            const int r = wave + 16 * i;
+            const int r = slab_row(wave, i);
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const int q = lane + 64 * h;
@@ -695,50 +702,82 @@ __device__ void exact_factor_wg(const AmgLevel &L, const AmgExact &E, double *ld
                 a[i][h] = v;
             }
         }
-        // Gauss-Jordan, step k = 16 oi + ow (the row slot oi is a constant
-        // of the unrolled loop, so the registers are indexed statically)
+        // pair p = 16 j + ow: rows k = 32 j + 2 ow and k + 1 in slots 2 j and
+        // 2 j + 1 of wave ow (j is a constant of the unrolled loop, so the
+        // registers are indexed statically), their columns in slot h
 #pragma unroll
-        for (int oi = 0; oi < kSlabRows; ++oi) {
-            const int h = oi >= 4 ? 1 : 0;          // the slot of column k = 16 oi + ow
+        for (int j = 0; j < kSlabRows / 2; ++j) {
+            const int h = j == 2 ? 1 : 0;
             for (int ow = 0; ow < 16; ++ow) {
-                const int k = 16 * oi + ow;
+                const int k = 32 * j + 2 * ow;
                 if (k >= m) break;
-                const int lk = k - 64 * h;
-                double *Uk = U + (k & 1) * E.mmax;
+                const bool two = k + 1 < m;
+                const int lk = k - 64 * h;              // lane of column k (k + 1: lk + 1)
+                double *U0 = U + (ow & 1) * 2 * E.mmax, *U1 = U0 + E.mmax;
                 if (wave == ow) {
-                    const double piv = readlane_d(a[oi][h], lk);
+                    const double piv = readlane_d(a[2 * j][h], lk);
                     const double ip = 1.0 / piv;
                     if (lane == 0 && !(fabs(piv) > 0.0 && isfinite(piv))) *E.bad = 1;
+                    double w[2] = {a[2 * j][0] * ip, a[2 * j][1] * ip};   // row k, step k
+                    if (lane == lk) w[h] = ip;
+                    double v[2] = {0.0, 0.0};
+                    if (two) {
+                        double t2[2] = {a[2 * j + 1][0], a[2 * j + 1][1]};   // row k + 1
+                        const double f1 = readlane_d(t2[h], lk);
+                        if (lane == lk) t2[h] = 0.0;
+                        t2[0] -= f1 * w[0];
+                        t2[1] -= f1 * w[1];
+                        const double piv1 = readlane_d(t2[h], lk + 1);
+                        const double ip1 = 1.0 / piv1;
+                        if (lane == 0 && !(fabs(piv1) > 0.0 && isfinite(piv1))) *E.bad = 1;
+                        v[0] = t2[0] * ip1;
+                        v[1] = t2[1] * ip1;
+                        if (lane == lk + 1) v[h] = ip1;
+                        const double g = readlane_d(w[h], lk + 1);        // row k, step k + 1
+                        if (lane == lk + 1) w[h] = 0.0;
+                        w[0] -= g * v[0];
+                        w[1] -= g * v[1];
+                    }
 #pragma unroll
                     for (int hh = 0; hh < 2; ++hh) {
                         const int q = lane + 64 * hh;
-                        if (q < m) Uk[q] = q == k ? ip : a[oi][hh] * ip;
+                        if (q < m) {
+                            U0[q] = w[hh];
+                            U1[q] = v[hh];
+                        }
                     }
                 }
                 lds_barrier();
-                const double u0 = Uk[lane], u1 = lane + 64 < m ? Uk[lane + 64] : 0.0;
+                const double p0 = lane < m ? U0[lane] : 0.0, p1 = lane + 64 < m ? U0[lane + 64] : 0.0;
+                const double q0 = lane < m ? U1[lane] : 0.0, q1 = lane + 64 < m ? U1[lane + 64] : 0.0;
 #pragma unroll
                 for (int i = 0; i < kSlabRows; ++i) {
-                    const int r = wave + 16 * i;
+                    const int r = slab_row(wave, i);
                     if (r >= m) continue;
                     if (r == k) {
-                        a[i][0] = u0;
-                        a[i][1] = u1;
+                        a[i][0] = p0;
+                        a[i][1] = p1;
+                        continue;
+                    }
+                    if (r == k + 1) {
+                        a[i][0] = q0;
+                        a[i][1] = q1;
                         continue;
                     }
                     const double f = readlane_d(a[i][h], lk);
+                    const double f1 = two ? readlane_d(a[i][h], lk + 1) : 0.0;
                     double v0 = a[i][0], v1 = a[i][1];
-                    if (h == 0 && lane == lk) v0 = 0.0;
-                    if (h == 1 && lane == lk) v1 = 0.0;
-                    a[i][0] = v0 - f * u0;
-                    a[i][1] = v1 - f * u1;
+                    if (h == 0 && (lane == lk || lane == lk + 1)) v0 = 0.0;
+                    if (h == 1 && (lane == lk || lane == lk + 1)) v1 = 0.0;
+                    a[i][0] = v0 - f * p0 - f1 * q0;
+                    a[i][1] = v1 - f * p1 - f1 * q1;
                 }
             }
         }
         double *dst = E.binv + (size_t)b * E.mmax * E.mmax;
 #pragma unroll
         for (int i = 0; i < kSlabRows; ++i) {
-            const int r = wave + 16 * i;
+            const int r = slab_row(wave, i);
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const int q = lane + 64 * h;
@@ -746,7 +785,7 @@ __device__ void exact_factor_wg(const AmgLevel &L, const AmgExact &E, double *ld
             }
         }
         // (the next slab's coefficients and block overwrite LDS only after
-        // every thread has read this slab's: a barrier ends each step)
+        // every thread has read this slab's: a barrier ends each pair)
         __syncthreads();
     }
 }
@@ -896,14 +935,19 @@ __device__ inline int slab_storage(const AmgLevel &L, const AmgExact &E, int b, 
 }
 
 // The level's inverse X = A^-1 from the slab factors, kInvCols columns per
-// workgroup: the columns of positions p0 .. p0 + 7 of slab s solved by the
-// block substitution (forward from slab s, where the right-hand side starts,
-// so z_s is a column of inv(D_s); backward over every slab), with thread
-// (r, c) forming row r of column c.  Each step's result goes to its rows of
-// X at once (the forward results are read back by the same threads in the
-// backward sweep).  Grid: nslab x ceil(mmax / kInvCols) workgroups of
-// kInvCols * kSlabMax threads.
-constexpr int kInvCols = 8;
+// workgroup: the columns of positions p0 .. p0 + 9 of slab s (contiguous
+// columns of X) solved by the block substitution (forward from slab s, where
+// the right-hand side starts, so z_s is a column of inv(D_s); backward over
+// every slab).  Thread (r, c) forms row r of column c from row r of inv(D_b)
+// in twelve chunks of 8 entries (immediate offsets; a chunk may run past the
+// row, into the next one or the allocation's padding, where t is zero), two
+// chunks in flight, the first loaded before the step's barrier.  Each step's
+// result goes to its rows of X at once (the forward results are read back by
+// the same threads in the backward sweep); the barriers order LDS only, so
+// those loads and stores stay in flight.  Grid: nslab x ceil(mmax /
+// kInvCols) workgroups of kInvCols * kSlabMax threads (252 for 28 slabs of
+// 90: one round over the CUs).
+constexpr int kInvCols = 10, kInvCh = 8, kInvChunks = kSlabMax / kInvCh;
 __global__ __launch_bounds__(kInvCols * kSlabMax) void k_amg_exact_inverse(AmgLevel L, AmgExact E) {
     __shared__ double zx[kSlabMax][kInvCols], t[kSlabMax][kInvCols];
     const int groups = (E.mmax + kInvCols - 1) / kInvCols;
@@ -912,82 +956,82 @@ __global__ __launch_bounds__(kInvCols * kSlabMax) void k_amg_exact_inverse(AmgLe
     if (p0 >= ms) return;                                 // (uniform over the block)
     const int r = threadIdx.x / kInvCols, c = threadIdx.x % kInvCols;
     const bool con = p0 + c < ms;
-    const size_t col = con ? (size_t)slab_storage(L, E, s, p0 + c) : 0;
+    const size_t col = (size_t)s * E.ncs + E.swp[s] + p0 + c;
     const int dm = 2 * E.axis + 1, dp = 2 * E.axis + 2;
     const size_t mm = (size_t)E.mmax * E.mmax;
     auto slab_m = [&](int b) { return E.ncs + E.swp[b + 1] - E.swp[b]; };
-    // row r of inv(D_b) t (four partial sums, q in order within each)
-    auto product = [&](int b, int m) {
-        const double *B = E.binv + (size_t)b * mm + (size_t)r * m;
-        double acc[4] = {0.0, 0.0, 0.0, 0.0};
-        int q = 0;
-        for (; q + 4 <= m; q += 4) {
+    auto row_of = [&](int b, int m) { return E.binv + (size_t)b * mm + (size_t)(r < m ? r : 0) * m; };
+    auto load_chunk = [&](const double *B, double (&v)[kInvCh]) {
 #pragma unroll
-            for (int u = 0; u < 4; ++u) acc[u] += B[q + u] * t[q + u][c];
+        for (int u = 0; u < kInvCh; ++u) v[u] = B[u];
+    };
+    auto use_chunk = [&](const double (*tq)[kInvCols], const double (&v)[kInvCh], double (&acc)[4]) {
+#pragma unroll
+        for (int u = 0; u < kInvCh; ++u) acc[u & 3] += v[u] * tq[u][c];
+    };
+    double va[kInvCh], vb[kInvCh];
+    auto product = [&](const double *B) {           // (va holds chunk 0)
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+        for (int ch = 0; ch < kInvChunks; ch += 2) {
+            load_chunk(B + kInvCh * (ch + 1), vb);
+            use_chunk(t + kInvCh * ch, va, acc);
+            if (ch + 2 < kInvChunks) load_chunk(B + kInvCh * (ch + 2), va);
+            use_chunk(t + kInvCh * (ch + 1), vb, acc);
         }
-        for (; q < m; ++q) acc[q & 3] += B[q] * t[q][c];
         return (acc[0] + acc[1]) + (acc[2] + acc[3]);
     };
     // forward: z_s = column p0 + c of inv(D_s); z_b = inv(D_b) (-A_b,b-1 z_b-1)
     for (int b = s; b < E.nslab; ++b) {
         const int m = slab_m(b);
-        if (b > s) {
-            if (r < m) {
-                double v = 0.0;
-                if (r < E.ncs) v = -slab_coef(L, E, b, r, dm) * zx[r][c];
-                t[r][c] = v;
-            }
-            __syncthreads();
-        }
+        const double *B = row_of(b, m);
         double z = 0.0;
-        if (r < m) {
-            z = b == s ? (con ? E.binv[(size_t)b * mm + (size_t)r * m + p0 + c] : 0.0)
-                       : product(b, m);
+        if (b == s) {
+            if (r < m && con) z = B[p0 + c];
+        } else {
+            load_chunk(B, va);
+            t[r][c] = r < E.ncs ? -slab_coef(L, E, b, r, dm) * zx[r][c] : 0.0;
+            lds_barrier();
+            z = product(B);
         }
-        __syncthreads();                                   // (t and zx read)
+        lds_barrier();                                     // (t and zx read)
         if (r < m) {
             zx[r][c] = z;
             if (con) E.X[(size_t)slab_storage(L, E, b, r) * E.ldx + col] = z;
         }
-        __syncthreads();
+        lds_barrier();
     }
     // backward: x_b = z_b - inv(D_b) A_b,b+1 x_b+1 (z_b = 0 before slab s)
     for (int b = E.nslab - 2; b >= 0; --b) {
         const int m = slab_m(b);
-        if (r < m) {
-            double v = 0.0;
-            if (r < E.ncs) v = slab_coef(L, E, b, r, dp) * zx[r][c];
-            t[r][c] = v;
-        }
-        __syncthreads();
-        double x = 0.0;
+        const double *B = row_of(b, m);
+        load_chunk(B, va);
         size_t row = 0;
+        double zb = 0.0;
         if (r < m) {
             row = (size_t)slab_storage(L, E, b, r) * E.ldx;
-            const double zb = (b >= s && con) ? E.X[row + col] : 0.0;
-            x = zb - product(b, m);
+            if (b >= s && con) zb = E.X[row + col];
         }
-        __syncthreads();
+        t[r][c] = r < E.ncs ? slab_coef(L, E, b, r, dp) * zx[r][c] : 0.0;
+        lds_barrier();
+        const double x = zb - product(B);
+        lds_barrier();
         if (r < m) {
             zx[r][c] = x;
             if (con) E.X[row + col] = x;
         }
-        __syncthreads();
+        lds_barrier();
     }
 }
 
 // x = X b over the whole chip: a wave per row (16-byte loads, four partial
-// sums, a fixed shuffle tree), b staged in LDS by each workgroup (padded
-// entries as zero).  Grid: ceil(nst / kGemvRows) workgroups of 64 kGemvRows.
+// sums, a fixed shuffle tree), b gathered into slab order in LDS by each
+// workgroup.  Grid: ceil(nst / kGemvRows) workgroups of 64 kGemvRows.
 constexpr int kGemvRows = 8;
 __global__ __launch_bounds__(64 * kGemvRows) void k_amg_exact_gemv(AmgLevel L, AmgExact E) {
     extern __shared__ double bs[];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int e = tid; e < E.ldx; e += blockDim.x) {
-        double v = 0.0;
-        if (e < E.nst && (e >= 2 * L.half || pos_of(L, e).i < L.nx)) v = L.b[e];
-        bs[e] = v;
-    }
+    for (int f = tid; f < E.ldx; f += blockDim.x) bs[f] = f < E.ncol ? L.b[E.cmap[f]] : 0.0;
     __syncthreads();
     const int row = blockIdx.x * kGemvRows + wave;
     if (row >= E.nst) return;
@@ -1716,13 +1760,13 @@ size_t exact_solve_lds(const AmgExact &E) {
            sizeof(double);
 }
 size_t exact_factor_lds(const AmgExact &E) {
-    return ((size_t)E.mmax * E.mmax + 4 * E.mmax) * sizeof(double);
+    return ((size_t)E.mmax * E.mmax + 6 * E.mmax) * sizeof(double);
 }
 
 // the largest LDS of a slab problem the plan admits (nslab * mmax <=
 // kExactSlabDoubles, ncs <= mmax <= kSlabMax), which every context shares
 static size_t exact_factor_lds_max() {
-    return ((size_t)kSlabMax * kSlabMax + 4 * kSlabMax) * sizeof(double);
+    return ((size_t)kSlabMax * kSlabMax + 6 * kSlabMax) * sizeof(double);
 }
 static size_t exact_solve_lds_max() {
     return ((size_t)4 * kExactSlabDoubles + kSlabMax + (kExactSlabDoubles + 2) / 2) * sizeof(double);

@@ -491,17 +491,44 @@ static void build_amg(fim_ctx *c, const std::vector<int> &sorted_cells,
     c->amg_bad = c->alloc<int>(1);
     if (c->exact_on) {
         c->ex.bad = c->amg_bad;
-        c->ex.binv = c->alloc<double>((size_t)c->ex.nslab * c->ex.mmax * c->ex.mmax);
+        // (the padding is read past the last row by the inverse's chunked loads)
+        const size_t nbinv = (size_t)c->ex.nslab * c->ex.mmax * c->ex.mmax;
+        c->ex.binv = c->alloc<double>(nbinv + kSlabMax);
+        HIPCHECK(hipMemsetAsync(c->ex.binv, 0, (nbinv + kSlabMax) * sizeof(double), c->s));
         HIPCHECK(exact_allow_lds());            // the same value for every context
         // mode 0: room for the level's dense inverse (rows and columns in
         // storage order; padded ones stay zero)
         const AmgLevel &Lc = c->lv.back();
-        c->ex.nst = 2 * Lc.half + Lc.nw;
-        c->ex.ldx = (c->ex.nst + 1) & ~1;
-        c->ex.X = nullptr;
-        if (c->opt.amg_exact_mode == 0 && c->ex.ldx <= kExactGemvCols) {
-            c->ex.X = c->alloc<double>((size_t)c->ex.nst * c->ex.ldx);
-            HIPCHECK(hipMemsetAsync(c->ex.X, 0, (size_t)c->ex.nst * c->ex.ldx * sizeof(double), c->s));
+        AmgExact &E = c->ex;
+        E.nst = 2 * Lc.half + Lc.nw;
+        E.ncol = E.nslab * E.ncs + Lc.nw;
+        E.ldx = (E.ncol + 1) & ~1;
+        E.X = nullptr;
+        E.cmap = nullptr;
+        if (c->opt.amg_exact_mode == 0 && E.ldx <= kExactGemvCols) {
+            // column f of slab b, position p (cells by their in-slab position,
+            // then the slab's wells) -> the level's storage index
+            std::vector<int> swp(E.nslab + 1), sw(std::max(Lc.nw, 1)), cmap(E.ncol);
+            HIPCHECK(hipMemcpy(swp.data(), E.swp, swp.size() * sizeof(int), hipMemcpyDeviceToHost));
+            HIPCHECK(hipMemcpy(sw.data(), E.sw, sw.size() * sizeof(int), hipMemcpyDeviceToHost));
+            for (int b = 0; b < E.nslab; ++b) {
+                const int m = E.ncs + swp[b + 1] - swp[b];
+                for (int p = 0; p < m; ++p) {
+                    int st;
+                    if (p >= E.ncs) {
+                        st = 2 * Lc.half + sw[swp[b] + p - E.ncs];
+                    } else {
+                        const int u = p % E.nu, v = p / E.nu;
+                        const int i = E.axis == 0 ? b : u, j = E.axis == 0 ? u : (E.axis == 1 ? b : v),
+                                  k = E.axis == 2 ? b : v;
+                        st = (((i + j + k) & 1) ? Lc.half : 0) + ((i + Lc.nxp * (j + Lc.ny * k)) >> 1);
+                    }
+                    cmap[(size_t)b * E.ncs + swp[b] + p] = st;
+                }
+            }
+            E.cmap = c->upload(cmap.data(), cmap.size());
+            E.X = c->alloc<double>((size_t)E.nst * E.ldx);
+            HIPCHECK(hipMemsetAsync(E.X, 0, (size_t)E.nst * E.ldx * sizeof(double), c->s));
         }
     } else {
         const AmgLevel &Lc = c->lv.back();

@@ -220,12 +220,15 @@ struct AmgExact {
     const int *swp;            // [nslab + 1] slab -> range in sw
     const int *sw;             // wells of each slab, ascending
     const int *wrank;          // [nw] position of a well among its slab's wells
-    double *binv;              // [nslab][mmax][mmax] inverted Schur complements
+    double *binv;              // [nslab][mmax][mmax] inverted Schur complements (and
+                               // kSlabMax doubles of zero padding)
     int *bad;                  // set on a zero or non-finite pivot
-    double *X;                 // the level's inverse [nst][ldx], rows and columns in the
-                               // level's storage order (padded ones zero); null: applied
-                               // by substitution over the slabs in one workgroup
-    int nst, ldx;              // 2 * half + nw; row stride (even)
+    double *X;                 // the level's inverse [nst][ldx]: rows in the level's
+                               // storage order (padded ones zero), columns in slab order
+                               // (slab b's at b * ncs + swp[b]); null: applied by
+                               // substitution over the slabs in one workgroup
+    const int *cmap;           // [ncol] column -> storage index
+    int nst, ncol, ldx;        // 2 * half + nw; nslab * ncs + nw; row stride (even)
 };
 size_t exact_solve_lds(const AmgExact &E);     // dynamic LDS of the solve (bytes)
 size_t exact_factor_lds(const AmgExact &E);    // and of the factorisation

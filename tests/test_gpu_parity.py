@@ -499,12 +499,13 @@ def test_full_size_spmv_and_ilu0_apply_match_oracle():
 
 def test_c2_full_size_step_solves_the_oracle_equations():
     """1,122,000 cells in the launch configuration of the benchmark (CPR
-    with block-Jacobi ILU(0) over 8x16x8 boxes, FP64, GMRES(40), the
-    parity tolerances): the first 10-day step from the initial state.  The
-    oracle's Newton run is out of reach here; its discrete system at the
-    GPU's end state must pass the convergence tests the step claims."""
+    with block-Jacobi ILU(0) over 8x16x8 boxes, the AMG's level 3 solved
+    exactly by its dense inverse, FP64, GMRES(40), the parity tolerances):
+    the first 10-day step from the initial state.  The oracle's Newton run
+    is out of reach here; its discrete system at the GPU's end state must
+    pass the convergence tests the step claims."""
     res = rv.config_c2()
-    opt = rv.Options(max_lin=400, restart=40, max_newton=30, tile=(8, 16, 8))
+    opt = rv.Options(max_lin=400, restart=40, max_newton=30, tile=(8, 16, 8), amg_exact=4096)
     g = fim.Fim(res, options=opt)
     o = fr.OracleModel(res)
     g.fim_set_state(o.P, o.Sw, o.X, o.flag, o.pbhp)

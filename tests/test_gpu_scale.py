@@ -37,10 +37,11 @@ def test_fivespot_264k_first_step_matches_the_oracle_element_by_element():
     ref = np.load(OUT)
     res = workload()
     # the benchmark's options: CPR + block-Jacobi ILU(0) over 8x16x8 boxes,
-    # GMRES(40), graphs, the forcing term; the finest AMG level restricts by
-    # row segments as the 1.1M-cell level does
+    # the first AMG level of at most 4096 cells solved exactly by its dense
+    # inverse, GMRES(40), graphs, the forcing term; the finest AMG level
+    # restricts by row segments as the 1.1M-cell level does
     opt = rv.Options(max_lin=400, restart=40, max_newton=30, tile=(8, 16, 8),
-                     amg_seg_rows=1 << 16)
+                     amg_seg_rows=1 << 16, amg_exact=4096)
     g = fim.Fim(res, options=opt)
     g.set_initial_state()
     newton = linear = 0
