@@ -428,8 +428,10 @@ int fim_amg_level(fim_ctx *ctx, int32_t level, int32_t *dims, double *A);
 /* The coarsest AMG level's solve as the cycle runs it (Sec. 5.1, the
  * pressure stage's coarse problem): x = A_c^-1 b for host arrays in the
  * order of fim_amg_level (cells in natural order, then wells) of the last
- * level, by block elimination over slabs when that level is solved exactly
- * (option amg_exact), else by its dense inverse.  The level's own arrays
+ * level: when that level is solved exactly (option amg_exact), by the
+ * product with its dense inverse formed from the slab factors
+ * (amg_exact_mode 0) or by block substitution over the slabs (mode 1); else
+ * by the dense inverse of the small coarsest level.  The level's own arrays
  * are not touched.  FIM_E_ARG without a CPR preconditioner. */
 int fim_amg_coarse_solve(fim_ctx *ctx, const double *b, double *x);
 
