@@ -654,126 +654,150 @@ constexpr int kSlabRows = (kSlabMax + 15) / 16;    // rows of a slab block per w
 // by wave p % 16.
 __device__ inline int slab_row(int wave, int i) { return 32 * (i >> 1) + 2 * wave + (i & 1); }
 
-// One 1024-thread workgroup: the Schur complements of the slabs in order,
-// each inverted by Gauss-Jordan without pivoting (the pressure operator's
-// Schur complements keep its diagonal dominance; a zero or non-finite pivot
-// sets *E.bad), stored to E.binv.  The block lives in registers: slot i of
-// wave w holds row slab_row(w, i), lane l columns l and l + 64.  Pivots go
-// in pairs k, k + 1: the wave holding both rows takes the two elimination
-// steps on them (row k scaled, its pivot entry becoming 1 / pivot; row k + 1
-// eliminated with it and scaled; row k then eliminated with row k + 1) and
-// passes them on through LDS (two buffers, so one barrier per pair); every
-// other row r then takes a_r - a_rk u_k - a_r,k+1 u_k+1 with columns k and
-// k + 1 entering as zero, which is the two steps at once.  The inverse of
-// one slab stays in the registers for the next slab's Schur complement,
-// whose couplings are diagonal (a cell to the same position of the
-// neighbouring slab).
-__device__ void exact_factor_wg(const AmgLevel &L, const AmgExact &E, double *lds) {
-    const int tid = threadIdx.x, nt = blockDim.x;
-    // (the wave index as a scalar, so the row tests below branch uniformly)
+// Gauss-Jordan inversion without pivoting (the pressure operator's Schur
+// complements keep its diagonal dominance; a zero or non-finite pivot sets
+// *bad) of the m x m block held in registers by a 1024-thread workgroup:
+// slot i of wave w holds row slab_row(w, i), lane l columns l and l + 64.
+// Pivots go in pairs k, k + 1: the wave holding both rows takes the two
+// elimination steps on them (row k scaled, its pivot entry becoming
+// 1 / pivot; row k + 1 eliminated with it and scaled; row k then eliminated
+// with row k + 1) and passes them on through the buffers U ([2][2][ld], two
+// so one barrier per pair); every other row r then takes a_r - a_rk u_k -
+// a_r,k+1 u_k+1 with columns k and k + 1 entering as zero, which is the two
+// steps at once.
+__device__ __forceinline__ void gj_invert(double (&a)[kSlabRows][2], int lane, int wave, int m,
+                                          double *U, int ld, int *bad) {
+    // pair p = 16 j + ow: rows k = 32 j + 2 ow and k + 1 in slots 2 j and
+    // 2 j + 1 of wave ow (j is a constant of the unrolled loop, so the
+    // registers are indexed statically), their columns in slot h
+#pragma unroll
+    for (int j = 0; j < kSlabRows / 2; ++j) {
+        const int h = j == 2 ? 1 : 0;
+        for (int ow = 0; ow < 16; ++ow) {
+            const int k = 32 * j + 2 * ow;
+            if (k >= m) break;
+            const bool two = k + 1 < m;
+            const int lk = k - 64 * h;              // lane of column k (k + 1: lk + 1)
+            double *U0 = U + (ow & 1) * 2 * ld, *U1 = U0 + ld;
+            if (wave == ow) {
+                const double piv = readlane_d(a[2 * j][h], lk);
+                const double ip = 1.0 / piv;
+                if (lane == 0 && !(fabs(piv) > 0.0 && isfinite(piv))) *bad = 1;
+                double w[2] = {a[2 * j][0] * ip, a[2 * j][1] * ip};   // row k, step k
+                if (lane == lk) w[h] = ip;
+                double v[2] = {0.0, 0.0};
+                if (two) {
+                    double t2[2] = {a[2 * j + 1][0], a[2 * j + 1][1]};   // row k + 1
+                    const double f1 = readlane_d(t2[h], lk);
+                    if (lane == lk) t2[h] = 0.0;
+                    t2[0] -= f1 * w[0];
+                    t2[1] -= f1 * w[1];
+                    const double piv1 = readlane_d(t2[h], lk + 1);
+                    const double ip1 = 1.0 / piv1;
+                    if (lane == 0 && !(fabs(piv1) > 0.0 && isfinite(piv1))) *bad = 1;
+                    v[0] = t2[0] * ip1;
+                    v[1] = t2[1] * ip1;
+                    if (lane == lk + 1) v[h] = ip1;
+                    const double g = readlane_d(w[h], lk + 1);        // row k, step k + 1
+                    if (lane == lk + 1) w[h] = 0.0;
+                    w[0] -= g * v[0];
+                    w[1] -= g * v[1];
+                }
+#pragma unroll
+                for (int hh = 0; hh < 2; ++hh) {
+                    const int q = lane + 64 * hh;
+                    if (q < m) {
+                        U0[q] = w[hh];
+                        U1[q] = v[hh];
+                    }
+                }
+            }
+            lds_barrier();
+            const double p0 = lane < m ? U0[lane] : 0.0, p1 = lane + 64 < m ? U0[lane + 64] : 0.0;
+            const double q0 = lane < m ? U1[lane] : 0.0, q1 = lane + 64 < m ? U1[lane + 64] : 0.0;
+#pragma unroll
+            for (int i = 0; i < kSlabRows; ++i) {
+                const int r = slab_row(wave, i);
+                if (r >= m) continue;
+                if (r == k) {
+                    a[i][0] = p0;
+                    a[i][1] = p1;
+                    continue;
+                }
+                if (r == k + 1) {
+                    a[i][0] = q0;
+                    a[i][1] = q1;
+                    continue;
+                }
+                const double f = readlane_d(a[i][h], lk);
+                const double f1 = two ? readlane_d(a[i][h], lk + 1) : 0.0;
+                double v0 = a[i][0], v1 = a[i][1];
+                if (h == 0 && (lane == lk || lane == lk + 1)) v0 = 0.0;
+                if (h == 1 && (lane == lk || lane == lk + 1)) v1 = 0.0;
+                a[i][0] = v0 - f * p0 - f1 * q0;
+                a[i][1] = v1 - f * p1 - f1 * q1;
+            }
+        }
+    }
+}
+
+// Slab b's block minus its couplings through the inverse P (in registers,
+// the layout of gj_invert) of the neighbouring slab b - dir: A_bb -
+// diag(rowc) P diag(colc) on the cell rows and columns (a cell couples to
+// the same position of the neighbouring slab), into the registers a.
+__device__ inline void slab_schur_load(const double *A, int m, int ncs, bool couple,
+                                       const double *rowc, const double *colc,
+                                       double (&a)[kSlabRows][2], int lane, int wave) {
+#pragma unroll
+    for (int i = 0; i < kSlabRows; ++i) {
+        const int r = slab_row(wave, i);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int q = lane + 64 * h;
+            double v = 0.0;
+            if (r < m && q < m) {
+                v = A[(size_t)r * m + q];
+                if (couple && r < ncs && q < ncs) v -= rowc[r] * a[i][h] * colc[q];
+            }
+            a[i][h] = v;
+        }
+    }
+}
+
+// Coupling coefficients of slab b with slab b - dir: rowc[p] of b's cell p
+// towards b - dir, colc[p] of b - dir's cell p towards b.
+__device__ inline void slab_couplings(const AmgLevel &L, const AmgExact &E, int b, int dir,
+                                      double *rowc, double *colc) {
+    const int dm = 2 * E.axis + 1, dp = 2 * E.axis + 2;
+    for (int p = threadIdx.x; p < E.ncs; p += blockDim.x) {
+        rowc[p] = slab_coef(L, E, b, p, dir > 0 ? dm : dp);
+        colc[p] = slab_coef(L, E, b - dir, p, dir > 0 ? dp : dm);
+    }
+}
+
+// One 1024-thread workgroup: the Schur complements of nsteps slabs from b0
+// in direction dir (+1: D_b = A_bb - A_b,b-1 inv(D_b-1) A_b-1,b from the
+// first slab up; -1: E_b = A_bb - A_b,b+1 inv(E_b+1) A_b+1,b from the last
+// down), each inverted by gj_invert and stored to E.binv.  The inverse of
+// one slab stays in the registers for the next slab's Schur complement.
+__device__ void exact_factor_wg(const AmgLevel &L, const AmgExact &E, double *lds, int b0,
+                                int nsteps, int dir) {
+    const int tid = threadIdx.x;
+    // (the wave index as a scalar, so the row tests branch uniformly)
     const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     double *A = lds;                                  // [mmax * mmax], stride m
     double *U = lds + (size_t)E.mmax * E.mmax;        // [2][2][mmax] pivot row pairs
-    double *am = U + 4 * E.mmax, *apv = am + E.mmax;  // couplings to the slab before
-    const int dm = 2 * E.axis + 1, dp = 2 * E.axis + 2;
+    double *rowc = U + 4 * E.mmax, *colc = rowc + E.mmax;
     double a[kSlabRows][2];
 #pragma unroll
     for (int i = 0; i < kSlabRows; ++i) a[i][0] = a[i][1] = 0.0;
-    for (int b = 0; b < E.nslab; ++b) {
+    for (int st = 0; st < nsteps; ++st) {
+        const int b = b0 + dir * st;
         const int m = E.ncs + E.swp[b + 1] - E.swp[b];
-        if (b > 0)
-            for (int p = tid; p < E.ncs; p += nt) {
-                am[p] = slab_coef(L, E, b, p, dm);
-                apv[p] = slab_coef(L, E, b - 1, p, dp);
-            }
+        if (st > 0) slab_couplings(L, E, b, dir, rowc, colc);
         slab_block(L, E, b, m, A);                  // (ends with a barrier)
-        // D_b = A_bb - A_b,b-1 inv(D_b-1) A_b-1,b on the cell rows and columns
-#pragma unroll
-        for (int i = 0; i < kSlabRows; ++i) {
-            const int r = slab_row(wave, i);
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int q = lane + 64 * h;
-                double v = 0.0;
-                if (r < m && q < m) {
-                    v = A[(size_t)r * m + q];
-                    if (b > 0 && r < E.ncs && q < E.ncs) v -= am[r] * a[i][h] * apv[q];
-                }
-                a[i][h] = v;
-            }
-        }
-        // pair p = 16 j + ow: rows k = 32 j + 2 ow and k + 1 in slots 2 j and
-        // 2 j + 1 of wave ow (j is a constant of the unrolled loop, so the
-        // registers are indexed statically), their columns in slot h
-#pragma unroll
-        for (int j = 0; j < kSlabRows / 2; ++j) {
-            const int h = j == 2 ? 1 : 0;
-            for (int ow = 0; ow < 16; ++ow) {
-                const int k = 32 * j + 2 * ow;
-                if (k >= m) break;
-                const bool two = k + 1 < m;
-                const int lk = k - 64 * h;              // lane of column k (k + 1: lk + 1)
-                double *U0 = U + (ow & 1) * 2 * E.mmax, *U1 = U0 + E.mmax;
-                if (wave == ow) {
-                    const double piv = readlane_d(a[2 * j][h], lk);
-                    const double ip = 1.0 / piv;
-                    if (lane == 0 && !(fabs(piv) > 0.0 && isfinite(piv))) *E.bad = 1;
-                    double w[2] = {a[2 * j][0] * ip, a[2 * j][1] * ip};   // row k, step k
-                    if (lane == lk) w[h] = ip;
-                    double v[2] = {0.0, 0.0};
-                    if (two) {
-                        double t2[2] = {a[2 * j + 1][0], a[2 * j + 1][1]};   // row k + 1
-                        const double f1 = readlane_d(t2[h], lk);
-                        if (lane == lk) t2[h] = 0.0;
-                        t2[0] -= f1 * w[0];
-                        t2[1] -= f1 * w[1];
-                        const double piv1 = readlane_d(t2[h], lk + 1);
-                        const double ip1 = 1.0 / piv1;
-                        if (lane == 0 && !(fabs(piv1) > 0.0 && isfinite(piv1))) *E.bad = 1;
-                        v[0] = t2[0] * ip1;
-                        v[1] = t2[1] * ip1;
-                        if (lane == lk + 1) v[h] = ip1;
-                        const double g = readlane_d(w[h], lk + 1);        // row k, step k + 1
-                        if (lane == lk + 1) w[h] = 0.0;
-                        w[0] -= g * v[0];
-                        w[1] -= g * v[1];
-                    }
-#pragma unroll
-                    for (int hh = 0; hh < 2; ++hh) {
-                        const int q = lane + 64 * hh;
-                        if (q < m) {
-                            U0[q] = w[hh];
-                            U1[q] = v[hh];
-                        }
-                    }
-                }
-                lds_barrier();
-                const double p0 = lane < m ? U0[lane] : 0.0, p1 = lane + 64 < m ? U0[lane + 64] : 0.0;
-                const double q0 = lane < m ? U1[lane] : 0.0, q1 = lane + 64 < m ? U1[lane + 64] : 0.0;
-#pragma unroll
-                for (int i = 0; i < kSlabRows; ++i) {
-                    const int r = slab_row(wave, i);
-                    if (r >= m) continue;
-                    if (r == k) {
-                        a[i][0] = p0;
-                        a[i][1] = p1;
-                        continue;
-                    }
-                    if (r == k + 1) {
-                        a[i][0] = q0;
-                        a[i][1] = q1;
-                        continue;
-                    }
-                    const double f = readlane_d(a[i][h], lk);
-                    const double f1 = two ? readlane_d(a[i][h], lk + 1) : 0.0;
-                    double v0 = a[i][0], v1 = a[i][1];
-                    if (h == 0 && (lane == lk || lane == lk + 1)) v0 = 0.0;
-                    if (h == 1 && (lane == lk || lane == lk + 1)) v1 = 0.0;
-                    a[i][0] = v0 - f * p0 - f1 * q0;
-                    a[i][1] = v1 - f * p1 - f1 * q1;
-                }
-            }
-        }
+        slab_schur_load(A, m, E.ncs, st > 0, rowc, colc, a, lane, wave);
+        gj_invert(a, lane, wave, m, U, E.mmax, E.bad);
         double *dst = E.binv + (size_t)b * E.mmax * E.mmax;
 #pragma unroll
         for (int i = 0; i < kSlabRows; ++i) {
@@ -790,9 +814,73 @@ __device__ void exact_factor_wg(const AmgLevel &L, const AmgExact &E, double *ld
     }
 }
 
+// The twist slab t of the two-sided factorisation: T_t = A_tt - A_t,t-1
+// inv(D_t-1) A_t-1,t - A_t,t+1 inv(E_t+1) A_t+1,t (either term absent at an
+// end), inverted by gj_invert into E.binv; the two neighbours' inverses are
+// read from E.binv.
+__device__ void exact_twist_wg(const AmgLevel &L, const AmgExact &E, double *lds) {
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int t = E.twist;
+    double *A = lds, *U = lds + (size_t)E.mmax * E.mmax;
+    double *c0 = U + 4 * E.mmax, *c1 = c0 + E.mmax, *c2 = c1 + E.mmax, *c3 = c2 + E.mmax;
+    const int m = E.ncs + E.swp[t + 1] - E.swp[t];
+    const bool lo = t > 0, hi = t + 1 < E.nslab;
+    if (lo) slab_couplings(L, E, t, 1, c0, c1);
+    if (hi) slab_couplings(L, E, t, -1, c2, c3);
+    slab_block(L, E, t, m, A);                      // (ends with a barrier)
+    const size_t mm = (size_t)E.mmax * E.mmax;
+    const int mlo = lo ? E.ncs + E.swp[t] - E.swp[t - 1] : 0;
+    const int mhi = hi ? E.ncs + E.swp[t + 2] - E.swp[t + 1] : 0;
+    double a[kSlabRows][2];
+#pragma unroll
+    for (int i = 0; i < kSlabRows; ++i) {
+        const int r = slab_row(wave, i);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int q = lane + 64 * h;
+            double v = 0.0;
+            if (r < m && q < m) {
+                v = A[(size_t)r * m + q];
+                if (r < E.ncs && q < E.ncs) {
+                    if (lo) v -= c0[r] * E.binv[(size_t)(t - 1) * mm + (size_t)r * mlo + q] * c1[q];
+                    if (hi) v -= c2[r] * E.binv[(size_t)(t + 1) * mm + (size_t)r * mhi + q] * c3[q];
+                }
+            }
+            a[i][h] = v;
+        }
+    }
+    gj_invert(a, lane, wave, m, U, E.mmax, E.bad);
+    double *dst = E.binv + (size_t)t * mm;
+#pragma unroll
+    for (int i = 0; i < kSlabRows; ++i) {
+        const int r = slab_row(wave, i);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int q = lane + 64 * h;
+            if (r < m && q < m) dst[(size_t)r * m + q] = a[i][h];
+        }
+    }
+}
+
 __global__ __launch_bounds__(1024) void k_amg_exact_factor(AmgLevel L, AmgExact E) {
     extern __shared__ double lds[];
-    exact_factor_wg(L, E, lds);
+    exact_factor_wg(L, E, lds, 0, E.nslab, 1);
+}
+
+// The two sides of the two-sided factorisation at once: workgroup 0 the
+// slabs below the twist from the first up, workgroup 1 those above it from
+// the last down.
+__global__ __launch_bounds__(1024) void k_amg_exact_factor2(AmgLevel L, AmgExact E) {
+    extern __shared__ double lds[];
+    const bool up = blockIdx.x == 0;
+    exact_factor_wg(L, E, lds, up ? 0 : E.nslab - 1, up ? E.twist : E.nslab - 1 - E.twist,
+                    up ? 1 : -1);
+}
+
+__global__ __launch_bounds__(1024) void k_amg_exact_twist(AmgLevel L, AmgExact E) {
+    extern __shared__ double lds[];
+    exact_twist_wg(L, E, lds);
 }
 
 // The exact solve by the whole workgroup: x = A^-1 b of the level, through
@@ -934,22 +1022,23 @@ __device__ inline int slab_storage(const AmgLevel &L, const AmgExact &E, int b, 
     return split_of(L, i, j, k);
 }
 
-// The level's inverse X = A^-1 from the slab factors, kInvCols columns per
-// workgroup: the columns of positions p0 .. p0 + 9 of slab s (contiguous
-// columns of X) solved by the block substitution (forward from slab s, where
-// the right-hand side starts, so z_s is a column of inv(D_s); backward over
-// every slab).  Thread (r, c) forms row r of column c from row r of inv(D_b)
-// in twelve chunks of 8 entries (immediate offsets; a chunk may run past the
-// row, into the next one or the allocation's padding, where t is zero), two
-// chunks in flight, the first loaded before the step's barrier.  Each step's
-// result goes to its rows of X at once (the forward results are read back by
-// the same threads in the backward sweep); the barriers order LDS only, so
-// those loads and stores stay in flight.  Grid: nslab x ceil(mmax /
-// kInvCols) workgroups of kInvCols * kSlabMax threads (252 for 28 slabs of
-// 90: one round over the CUs).
+// The level's inverse X = A^-1 from the two-sided slab factors, kInvCols
+// columns per workgroup: the columns of positions p0 .. p0 + 9 of slab s
+// (contiguous columns of X) solved with those unit right sides: from slab s
+// towards the twist slab (z_s a column of the inverse held for slab s), the
+// twist, then outward on both sides.  Thread (r, c) forms row r of column c
+// from row r of the slab's inverse in twelve chunks of 8 entries (immediate
+// offsets; a chunk may run past the row, into the next one or the
+// allocation's padding, where t is zero), two chunks in flight, the first
+// loaded before the step's barrier.  Each step's result goes to its rows of
+// X at once (the results towards the twist are read back by the same
+// threads on the way out); the barriers order LDS only, so those loads and
+// stores stay in flight.  Grid: nslab x ceil(mmax / kInvCols) workgroups of
+// kInvCols * kSlabMax threads (252 for 28 slabs of 90: one round over the
+// CUs).
 constexpr int kInvCols = 10, kInvCh = 8, kInvChunks = kSlabMax / kInvCh;
 __global__ __launch_bounds__(kInvCols * kSlabMax) void k_amg_exact_inverse(AmgLevel L, AmgExact E) {
-    __shared__ double zx[kSlabMax][kInvCols], t[kSlabMax][kInvCols];
+    __shared__ double zx[kSlabMax][kInvCols], t[kSlabMax][kInvCols], xt[kSlabMax][kInvCols];
     const int groups = (E.mmax + kInvCols - 1) / kInvCols;
     const int s = blockIdx.x / groups, p0 = (blockIdx.x % groups) * kInvCols;
     const int ms = E.ncs + E.swp[s + 1] - E.swp[s];
@@ -981,46 +1070,71 @@ __global__ __launch_bounds__(kInvCols * kSlabMax) void k_amg_exact_inverse(AmgLe
         }
         return (acc[0] + acc[1]) + (acc[2] + acc[3]);
     };
-    // forward: z_s = column p0 + c of inv(D_s); z_b = inv(D_b) (-A_b,b-1 z_b-1)
-    for (int b = s; b < E.nslab; ++b) {
-        const int m = slab_m(b);
-        const double *B = row_of(b, m);
-        double z = 0.0;
-        if (b == s) {
-            if (r < m && con) z = B[p0 + c];
-        } else {
-            load_chunk(B, va);
-            t[r][c] = r < E.ncs ? -slab_coef(L, E, b, r, dm) * zx[r][c] : 0.0;
-            lds_barrier();
-            z = product(B);
-        }
-        lds_barrier();                                     // (t and zx read)
+    // the result of a step: to zx and to its rows of X
+    auto put = [&](int b, int m, double v) {
         if (r < m) {
-            zx[r][c] = z;
-            if (con) E.X[(size_t)slab_storage(L, E, b, r) * E.ldx + col] = z;
+            zx[r][c] = v;
+            if (con) E.X[(size_t)slab_storage(L, E, b, r) * E.ldx + col] = v;
         }
-        lds_barrier();
-    }
-    // backward: x_b = z_b - inv(D_b) A_b,b+1 x_b+1 (z_b = 0 before slab s)
-    for (int b = E.nslab - 2; b >= 0; --b) {
-        const int m = slab_m(b);
+    };
+    // a step b from a neighbour's result in zx: the right side -coef(d) zx
+    // (cell rows; d towards that neighbour), then inv(.) of slab b times it
+    auto step = [&](int b, int m, int d) {
         const double *B = row_of(b, m);
         load_chunk(B, va);
-        size_t row = 0;
-        double zb = 0.0;
-        if (r < m) {
-            row = (size_t)slab_storage(L, E, b, r) * E.ldx;
-            if (b >= s && con) zb = E.X[row + col];
+        t[r][c] = r < E.ncs && r < m ? -slab_coef(L, E, b, r, d) * zx[r][c] : 0.0;
+        lds_barrier();
+        const double v = product(B);
+        lds_barrier();                                     // (t and zx read)
+        return v;
+    };
+    const int t0 = E.twist;
+    // towards the twist: below it z_b = inv(D_b)(e_p [b = s] - A_b,b-1 z_b-1),
+    // above it z_b = inv(E_b)(e_p [b = s] - A_b,b+1 z_b+1)
+    const int dir = s < t0 ? 1 : -1;
+    for (int b = s; b != t0; b += dir) {
+        const int m = slab_m(b);
+        double z = 0.0;
+        if (b == s) {
+            if (r < m && con) z = row_of(b, m)[p0 + c];
+        } else {
+            z = step(b, m, dir > 0 ? dm : dp);
         }
-        t[r][c] = r < E.ncs ? slab_coef(L, E, b, r, dp) * zx[r][c] : 0.0;
+        put(b, m, z);
         lds_barrier();
-        const double x = zb - product(B);
-        lds_barrier();
-        if (r < m) {
-            zx[r][c] = x;
-            if (con) E.X[row + col] = x;
+    }
+    // the twist: x_t = inv(T_t)(e_p [t = s] - the coupling to the last z)
+    {
+        const int m = slab_m(t0);
+        double x = 0.0;
+        if (s == t0) {
+            if (r < m && con) x = row_of(t0, m)[p0 + c];
+        } else {
+            x = step(t0, m, s < t0 ? dm : dp);
         }
+        put(t0, m, x);
+        if (r < m) xt[r][c] = x;
         lds_barrier();
+    }
+    // outward: below the twist x_b = z_b - inv(D_b) A_b,b+1 x_b+1, above it
+    // x_b = z_b - inv(E_b) A_b,b-1 x_b-1, where z_b is stored for the slabs
+    // between s and the twist and zero elsewhere
+    for (int side = 0; side < 2; ++side) {
+        const int od = side == 0 ? -1 : 1;
+        if (side == 1) {
+            zx[r][c] = xt[r][c];
+            lds_barrier();
+        }
+        for (int b = t0 + od; b >= 0 && b < E.nslab; b += od) {
+            const int m = slab_m(b);
+            const bool stored = od < 0 ? (s < t0 && b >= s) : (s > t0 && b <= s);
+            double zb = 0.0;
+            if (r < m && stored && con) zb = E.X[(size_t)slab_storage(L, E, b, r) * E.ldx + col];
+            // step() forms -coef * x of the neighbour: x_b = zb + inv(.) (that)
+            const double v = step(b, m, od < 0 ? dp : dm);
+            put(b, m, zb + v);
+            lds_barrier();
+        }
     }
 }
 
@@ -1760,30 +1874,40 @@ size_t exact_solve_lds(const AmgExact &E) {
            sizeof(double);
 }
 size_t exact_factor_lds(const AmgExact &E) {
-    return ((size_t)E.mmax * E.mmax + 6 * E.mmax) * sizeof(double);
+    return ((size_t)E.mmax * E.mmax + 8 * E.mmax) * sizeof(double);
 }
 
 // the largest LDS of a slab problem the plan admits (nslab * mmax <=
 // kExactSlabDoubles, ncs <= mmax <= kSlabMax), which every context shares
 static size_t exact_factor_lds_max() {
-    return ((size_t)kSlabMax * kSlabMax + 6 * kSlabMax) * sizeof(double);
+    return ((size_t)kSlabMax * kSlabMax + 8 * kSlabMax) * sizeof(double);
 }
 static size_t exact_solve_lds_max() {
     return ((size_t)4 * kExactSlabDoubles + kSlabMax + (kExactSlabDoubles + 2) / 2) * sizeof(double);
 }
 
 hipError_t exact_allow_lds() {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_amg_exact_factor),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)exact_factor_lds_max());
-    if (e != hipSuccess) return e;
+    for (const void *k : {reinterpret_cast<const void *>(&k_amg_exact_factor),
+                          reinterpret_cast<const void *>(&k_amg_exact_factor2),
+                          reinterpret_cast<const void *>(&k_amg_exact_twist)}) {
+        const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 (int)exact_factor_lds_max());
+        if (e != hipSuccess) return e;
+    }
     return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_amg_exact_solve),
                                hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)exact_solve_lds_max());
 }
 
+// One-sided (for the substitution, which reads inv(D_b) of every slab), or
+// with X two-sided: both sides at once, then the twist.
 void launch_amg_exact_factor(hipStream_t s, const AmgLevel &L, const AmgExact &E) {
-    hipLaunchKernelGGL(k_amg_exact_factor, dim3(1), dim3(1024), exact_factor_lds(E), s, L, E);
+    if (!E.X) {
+        hipLaunchKernelGGL(k_amg_exact_factor, dim3(1), dim3(1024), exact_factor_lds(E), s, L, E);
+        return;
+    }
+    hipLaunchKernelGGL(k_amg_exact_factor2, dim3(2), dim3(1024), exact_factor_lds(E), s, L, E);
+    hipLaunchKernelGGL(k_amg_exact_twist, dim3(1), dim3(1024), exact_factor_lds(E), s, L, E);
 }
 
 void launch_amg_exact_solve(hipStream_t s, const AmgLevel &L, const AmgExact &E) {
@@ -1938,7 +2062,7 @@ __global__ __launch_bounds__(1024) void kb_amg_coarsest(const Member *__restrict
     const AmgLevel &L = M.lv[M.nlev - 1];
     extern __shared__ double sm[];
     if (M.exact) {
-        exact_factor_wg(L, M.ex, sm);
+        exact_factor_wg(L, M.ex, sm, 0, M.ex.nslab, 1);
         return;
     }
     const int n = 2 * L.half + L.nw;

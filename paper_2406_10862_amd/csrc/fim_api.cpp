@@ -503,6 +503,7 @@ static void build_amg(fim_ctx *c, const std::vector<int> &sorted_cells,
         E.nst = 2 * Lc.half + Lc.nw;
         E.ncol = E.nslab * E.ncs + Lc.nw;
         E.ldx = (E.ncol + 1) & ~1;
+        E.twist = E.nslab / 2;
         E.X = nullptr;
         E.cmap = nullptr;
         if (c->opt.amg_exact_mode == 0 && E.ldx <= kExactGemvCols) {

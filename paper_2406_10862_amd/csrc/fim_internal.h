@@ -229,6 +229,9 @@ struct AmgExact {
                                // substitution over the slabs in one workgroup
     const int *cmap;           // [ncol] column -> storage index
     int nst, ncol, ldx;        // 2 * half + nw; nslab * ncs + nw; row stride (even)
+    int twist;                 // with X: the factorisation is two-sided, binv holding
+                               // inv(D_b) below slab twist, inv(E_b) above it and the
+                               // twist block's inverse at it
 };
 size_t exact_solve_lds(const AmgExact &E);     // dynamic LDS of the solve (bytes)
 size_t exact_factor_lds(const AmgExact &E);    // and of the factorisation
