@@ -518,7 +518,11 @@ __global__ __launch_bounds__(kBlock) void k_assemble_cells(
     const double *__restrict__ ty, const double *__restrict__ tz, const double *__restrict__ P,
     const double *__restrict__ pbhp, const double *__restrict__ rec,
     const double *__restrict__ aold, double dt) {
-    assemble_cells_body<NB>(blockIdx.x, g, w, sys, depth, tx, ty, tz, P, pbhp, rec, aold, dt);
+    // each XCD takes one contiguous run of cells: the planes above and below a
+    // cell, whose property records its faces read, are then read by blocks
+    // of the same XCD around the same time and stay in that XCD's L2
+    assemble_cells_body<NB>(xcd_block(blockIdx.x, gridDim.x), g, w, sys, depth, tx, ty, tz, P,
+                            pbhp, rec, aold, dt);
 }
 
 // Well rows: one wave per well.  Rate rows sum the injected component over
