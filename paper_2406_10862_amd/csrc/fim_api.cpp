@@ -95,6 +95,8 @@ constexpr double kSatSlack = 1e-6;
 
 struct fim_ctx {
     hipStream_t s = nullptr;          // the context's own stream
+    hipStream_t s2 = nullptr;         // the ILU(0) factorisation beside the AMG setup
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     hipStream_t user_s = nullptr;     // the caller's stream the work is ordered after
     hipEvent_t ev_user = nullptr;
     hipGraphExec_t step_exec[kMaxRestart] = {};   // Arnoldi step j after its SpMV
@@ -247,6 +249,9 @@ struct fim_ctx {
             if (e) (void)hipEventDestroy(e);
         for (auto &e : spmv_ev) (void)hipEventDestroy(e);
         if (ev_user) (void)hipEventDestroy(ev_user);
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+        if (ev_join) (void)hipEventDestroy(ev_join);
+        if (s2) (void)hipStreamDestroy(s2);
         if (s) (void)hipStreamDestroy(s);
     }
 };
@@ -732,7 +737,10 @@ static int create_impl(const fim_grid *grid, const fim_rock *rock, const fim_flu
         // device memory (everything above validated the input without the device)
         HIPCHECK(hipGetDevice(&c->dev));
         HIPCHECK(hipStreamCreateWithFlags(&c->s, hipStreamNonBlocking));
+        HIPCHECK(hipStreamCreateWithFlags(&c->s2, hipStreamNonBlocking));
         HIPCHECK(hipEventCreateWithFlags(&c->ev_user, hipEventDisableTiming));
+        HIPCHECK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+        HIPCHECK(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
         HIPCHECK(hipEventRecord(c->ev_user, c->user_s));
         HIPCHECK(hipStreamWaitEvent(c->s, c->ev_user, 0));
         const int n = c->n;
@@ -1205,27 +1213,50 @@ static void ensure_mixed(fim_ctx *c) {
     }
 }
 
-static void prec_setup(fim_ctx *c) {
+// The second-stage setup (BJ inverses or ILU(0) factors) on a stream, and
+// the AMG hierarchy's extraction and coarsening on the context's stream.
+static void second_stage_setup(fim_ctx *c, hipStream_t ss) {
     if (c->mixed) {
-        launch_to_float(c->s, (long)c->nnzb * c->nb * c->nb, c->val, c->val32);
-        launch_ilu_factor(c->s, c->nb, c->g, c->ilu, c->sys(), c->lu32, c->ilu_bad);
-        if (uses_cpr(c->opt)) {
-            launch_amg_extract(c->s, c->nb, c->lv[0], c->g, c->wells(), c->sys(), c->wq, c->ap32);
-            for (size_t l = 1; l < c->lv.size(); ++l)
-                launch_amg_coarsen(c->s, c->lv[l - 1], c->lv[l], c->cfs_ptr[l], c->cfs_idx[l]);
-            coarsest_setup(c);
-        }
-        c->prec_ready = true;
+        launch_to_float(ss, (long)c->nnzb * c->nb * c->nb, c->val, c->val32);
+        launch_ilu_factor(ss, c->nb, c->g, c->ilu, c->sys(), c->lu32, c->ilu_bad);
+    } else if (!uses_ilu(c->opt)) {
+        launch_bj_setup(ss, c->nb, c->nrows, c->diagpos, c->val, c->dinv, c->bad);
+    } else {
+        launch_ilu_factor(ss, c->nb, c->g, c->ilu, c->sys(), c->lu, c->ilu_bad);
+    }
+}
+static void amg_levels_setup(fim_ctx *c, bool transposed) {
+    if (transposed)
+        launch_cprT_extract(c->s, c->nb, c->lv[0], c->g, c->wells(), c->sys(), c->wq, c->ap);
+    else if (c->mixed)
+        launch_amg_extract(c->s, c->nb, c->lv[0], c->g, c->wells(), c->sys(), c->wq, c->ap32);
+    else
+        launch_amg_extract(c->s, c->nb, c->lv[0], c->g, c->wells(), c->sys(), c->wq, c->ap);
+    for (size_t l = 1; l < c->lv.size(); ++l)
+        launch_amg_coarsen(c->s, c->lv[l - 1], c->lv[l], c->cfs_ptr[l], c->cfs_idx[l]);
+}
+
+// With CPR the second stage is set up on the side stream while the coarsest
+// level's solver is (the slab factorisation ends in single-workgroup
+// kernels that leave most of the device free); the two read the Jacobian
+// and write disjoint arrays.
+static void prec_setup_cpr(fim_ctx *c, bool transposed) {
+    amg_levels_setup(c, transposed);
+    HIPCHECK(hipEventRecord(c->ev_fork, c->s));
+    HIPCHECK(hipStreamWaitEvent(c->s2, c->ev_fork, 0));
+    second_stage_setup(c, c->s2);
+    coarsest_setup(c);
+    HIPCHECK(hipEventRecord(c->ev_join, c->s2));
+    HIPCHECK(hipStreamWaitEvent(c->s, c->ev_join, 0));
+    c->prec_ready = true;
+}
+
+static void prec_setup(fim_ctx *c) {
+    if (uses_cpr(c->opt)) {
+        prec_setup_cpr(c, false);
         return;
     }
-    if (!uses_ilu(c->opt)) launch_bj_setup(c->s, c->nb, c->nrows, c->diagpos, c->val, c->dinv, c->bad);
-    else launch_ilu_factor(c->s, c->nb, c->g, c->ilu, c->sys(), c->lu, c->ilu_bad);
-    if (uses_cpr(c->opt)) {
-        launch_amg_extract(c->s, c->nb, c->lv[0], c->g, c->wells(), c->sys(), c->wq, c->ap);
-        for (size_t l = 1; l < c->lv.size(); ++l)
-            launch_amg_coarsen(c->s, c->lv[l - 1], c->lv[l], c->cfs_ptr[l], c->cfs_idx[l]);
-        coarsest_setup(c);
-    }
+    second_stage_setup(c, c->s);
     c->prec_ready = true;
 }
 
@@ -1762,14 +1793,7 @@ static void ensure_adjoint(fim_ctx *c) {
 // Preconditioner of J^T (held in c->val): ILU(0) of J^T in the boxes, and the
 // transposed CPR first stage (pressure component restricted, A_p^T by the
 // aggregation AMG, prolongation by the quasi-IMPES weights).
-static void adjoint_prec_setup(fim_ctx *c) {
-    launch_ilu_factor(c->s, c->nb, c->g, c->ilu, c->sys(), c->lu, c->ilu_bad);
-    launch_cprT_extract(c->s, c->nb, c->lv[0], c->g, c->wells(), c->sys(), c->wq, c->ap);
-    for (size_t l = 1; l < c->lv.size(); ++l)
-        launch_amg_coarsen(c->s, c->lv[l - 1], c->lv[l], c->cfs_ptr[l], c->cfs_idx[l]);
-    coarsest_setup(c);
-    c->prec_ready = true;
-}
+static void adjoint_prec_setup(fim_ctx *c) { prec_setup_cpr(c, true); }
 
 // Forward: nsteps time steps of fim_step.  Backward, over the accepted
 // sub-steps m = M..1:
