@@ -133,6 +133,32 @@ def test_coarse_solve_is_exact(cfg):
     assert out[4096, 0] == out[4096, 1] and out[4096, 0][0] <= out[0, 0][0]
 
 
+@pytest.mark.parametrize("dims", [(5, 5, 3), (7, 5, 3)])
+def test_coarse_solve_is_exact_with_few_slabs(dims):
+    """The slab-solved coarsest level at its smallest (the hierarchy stops at
+    the first level of at most 64 cells, and the exact level is at least
+    level 1): level 1 of a 5x5x3 five-spot is 3x3x2, three slabs (one on each
+    side of the twist), of 7x5x3 it is 4x3x2, four slabs (two below the
+    twist, one above); both modes against LAPACK."""
+    res = rv.config_c2_small(*dims)
+    for mode in (0, 1):
+        g = fim.Fim(res, options=rv.Options(precond=rv.PREC_CPR_ILU0, amg_exact=4096,
+                                            amg_exact_mode=mode))
+        g.set_initial_state()
+        dt = float(res.schedule[0])
+        assert g.fim_step(dt)[0] == fim.FIM_OK
+        g.fim_assemble(dt)
+        assert g.fim_amg_levels() == 2
+        A, lvl = g.fim_amg_level(1)
+        assert max(lvl[:3]) == (dims[0] + 1) // 2
+        b = np.random.default_rng(5).standard_normal(A.shape[0])
+        x = g.fim_amg_coarse_solve(b)
+        ref = np.linalg.solve(A, b)
+        err = np.abs(x - ref).max() / np.abs(ref).max()
+        print(f"{dims} mode {mode}: coarsest {lvl}, error {err:.1e}")
+        assert err <= 1e-9
+
+
 def test_amg_exact_is_fixed_at_creation():
     res = rv.config_c5(8, 6, 3)
     g = fim.Fim(res)
