@@ -1138,39 +1138,50 @@ __global__ __launch_bounds__(kInvCols * kSlabMax) void k_amg_exact_inverse(AmgLe
     }
 }
 
-// x = X b over the whole chip: a wave per row (16-byte loads, four partial
-// sums, a fixed shuffle tree), b gathered into slab order in LDS by each
-// workgroup.  Grid: ceil(nst / kGemvRows) workgroups of 64 kGemvRows.
-constexpr int kGemvRows = 8;
+// x = X b over the whole chip: a wave per row, its entries in chunks of 8
+// 16-byte loads per lane (the first chunk issued before b is gathered into
+// slab order in LDS by the workgroup, the next one before the current one is
+// used), four partial sums and a fixed shuffle tree.  Grid: ceil(nst /
+// kGemvRows) workgroups of 64 kGemvRows.
+constexpr int kGemvRows = 8, kGemvCh = 8;
 __global__ __launch_bounds__(64 * kGemvRows) void k_amg_exact_gemv(AmgLevel L, AmgExact E) {
     extern __shared__ double bs[];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int row = min((int)blockIdx.x * kGemvRows + wave, E.nst - 1);   // (a spare wave
+    const double2 *X = reinterpret_cast<const double2 *>(E.X + (size_t)row * E.ldx);   // repeats
+    const double2 *B = reinterpret_cast<const double2 *>(bs);              // the last row)
+    const int n2 = E.ldx / 2, nch = (n2 + 64 * kGemvCh - 1) / (64 * kGemvCh);
+    auto load = [&](int ch, double2 (&v)[kGemvCh]) {
+#pragma unroll
+        for (int u = 0; u < kGemvCh; ++u) {
+            const int f = 64 * (kGemvCh * ch + u) + lane;
+            v[u] = f < n2 ? X[f] : make_double2(0.0, 0.0);
+        }
+    };
+    double2 va[kGemvCh], vb[kGemvCh];
+    load(0, va);
     for (int f = tid; f < E.ldx; f += blockDim.x) bs[f] = f < E.ncol ? L.b[E.cmap[f]] : 0.0;
     __syncthreads();
-    const int row = blockIdx.x * kGemvRows + wave;
-    if (row >= E.nst) return;
-    const double2 *X = reinterpret_cast<const double2 *>(E.X + (size_t)row * E.ldx);
-    const double2 *B = reinterpret_cast<const double2 *>(bs);
-    const int n2 = E.ldx / 2;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    int f = lane;
-    for (; f + 192 < n2; f += 256) {
-        double2 xv[4], bv[4];
+    auto use = [&](int ch, const double2 (&v)[kGemvCh]) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) xv[u] = X[f + 64 * u];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) bv[u] = B[f + 64 * u];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) acc[u] += xv[u].x * bv[u].x + xv[u].y * bv[u].y;
-    }
-    for (int u = 0; f < n2; f += 64, ++u) {
-        const double2 xv = X[f], bv = B[f];
-        acc[u & 3] += xv.x * bv.x + xv.y * bv.y;
+        for (int u = 0; u < kGemvCh; ++u) {
+            const int f = 64 * (kGemvCh * ch + u) + lane;
+            const double2 bv = f < n2 ? B[f] : make_double2(0.0, 0.0);
+            acc[u & 3] += v[u].x * bv.x + v[u].y * bv.y;
+        }
+    };
+    for (int ch = 0; ch < nch; ch += 2) {
+        if (ch + 1 < nch) load(ch + 1, vb);
+        use(ch, va);
+        if (ch + 1 >= nch) break;
+        if (ch + 2 < nch) load(ch + 2, va);
+        use(ch + 1, vb);
     }
     double v = (acc[0] + acc[1]) + (acc[2] + acc[3]);
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    if (lane == 0) L.x[row] = v;
+    if (lane == 0 && blockIdx.x * kGemvRows + wave < E.nst) L.x[row] = v;
 }
 
 // ---------------------------------------------------------------------------
