@@ -974,10 +974,12 @@ __device__ void solve_cells_pencils(const Grid &g, const TileBox &tb, const Sys 
         sub_mv<NB>(acc, X[1].v, y + (size_t)(own && li + 1 < tb.txe ? l + 1 : l) * NB);
         sub_mv<NB>(acc, X[2].v, y + (size_t)(own && lj + 1 < tb.tye ? l + tb.txe : l) * NB);
         sub_mv<NB>(acc, X[3].v, y + (size_t)(own && lk + 1 < tb.tze ? l + sxy : l) * NB);
-        // well columns (perforated cells): the wells of this tile
+        // well columns (perforated cells): the wells of this tile (none to
+        // look for in a tile without wells of its own, the common case: the
+        // loads of the loop would stall the step)
         const int qw = rp[own ? l : 0] + (k > 0) + (j > 0) + (i > 0) + 1 + (i + 1 < g.nx) + (j + 1 < g.ny) +
                        (k + 1 < g.nz);
-        const int qe = on ? re[own ? l : 0] : qw;
+        const int qe = on && nwt > 0 ? re[own ? l : 0] : qw;
         for (int q = qw; q < qe; ++q) {
             const int w = sys.colind[q] - g.n;
             if (T.rtile[g.n + w] == blk)
@@ -1100,17 +1102,43 @@ __device__ __forceinline__ void ilu_solve_body(int hb, int nblk, const Grid &g, 
         __syncthreads();
     }
     }
-    for (int l = threadIdx.x; l < ncell + nwt; l += blockDim.x) {
-        int r;
-        if (l < ncell) {
-            const int li = l % tb.txe, lj = (l / tb.txe) % tb.tye, lk = l / sxy;
-            r = (tb.i0 + li) + g.nx * ((tb.j0 + lj) + g.ny * (tb.k0 + lk));
-        } else {
-            r = n + T.tw[w0 + (l - ncell)];
+    // x = y + the first-stage correction, kW rows per thread at a time with
+    // their corrections' loads issued together (a cell's level-0 entry from
+    // its coordinates, as in rhs_cells; a slot past the tile's rows repeats
+    // its last row and stores nothing)
+    constexpr int kW = 4;
+    const int nrow = ncell + nwt;
+    for (int l0 = threadIdx.x; l0 < nrow; l0 += kW * blockDim.x) {
+        int rr[kW], ll[kW];
+        double mu[kW];
+#pragma unroll
+        for (int h = 0; h < kW; ++h) {
+            const int l = min(l0 + h * (int)blockDim.x, nrow - 1);
+            ll[h] = l;
+            int sp;
+            if (l < ncell) {
+                const int li = l % tb.txe, lj = (l / tb.txe) % tb.tye, lk = l / sxy;
+                const int i = tb.i0 + li, j = tb.j0 + lj, k = tb.k0 + lk;
+                rr[h] = i + g.nx * (j + g.ny * k);
+                sp = (((i + j + k) & 1) ? (R.nsplit >> 1) : 0) + ((i + R.nxp * (j + g.ny * k)) >> 1);
+            } else {
+                const int w = T.tw[w0 + (l - ncell)];
+                rr[h] = n + w;
+                sp = R.nsplit + w;
+            }
+            mu[h] = R.ap ? R.px[sp] : 0.0;
         }
 #pragma unroll
-        for (int u = 0; u < NB; ++u)
-            x[(size_t)r * NB + u] = (VT)(y[(size_t)l * NB + u] + rhs_corr<NB>(R, n, r, u));
+        for (int h = 0; h < kW; ++h) {
+            if (l0 + h * (int)blockDim.x >= nrow) continue;
+            const int r = rr[h], l = ll[h];
+#pragma unroll
+            for (int u = 0; u < NB; ++u) {
+                double c = 0.0;
+                if (R.ap) c = (R.pw && r < n) ? R.pw[(size_t)r * NB + u] * mu[h] : (u == 0 ? mu[h] : 0.0);
+                x[(size_t)r * NB + u] = (VT)(y[(size_t)l * NB + u] + c);
+            }
+        }
     }
 }
 
