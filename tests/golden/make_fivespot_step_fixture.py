@@ -11,12 +11,11 @@ natural-order BILU(0)) stalls near 1e-4 on grids this size, so its Newton
 iterations solve through the oracle's linear-solver hook with a library
 primitive instead: GMRES preconditioned by the sparse LU factors (SuperLU)
 of a recent Jacobian, refactored when GMRES fails to converge in 400
-iterations, to the oracle's relative residual of 1e-12 (with --ilu:
-incomplete factors, refactored when 40 restart cycles do not converge).
-The Newton iteration, updates, convergence tests and time-step control are
-the oracle's.  Run from the repository root (hours, about 20 GB of memory):
+iterations, to the oracle's relative residual of 1e-12.  The Newton
+iteration, updates, convergence tests and time-step control are the
+oracle's.  Run from the repository root (about an hour and 15 GB of memory):
 
-    OMP_NUM_THREADS=8 python tests/golden/make_fivespot_step_fixture.py [--ilu]
+    OMP_NUM_THREADS=8 python tests/golden/make_fivespot_step_fixture.py
 
 It writes tests/golden/fivespot_60x220x20_step1.npz (float64 P and Sw per
 cell, the wells' BHP, the accepted sub-step lengths and the oracle's
@@ -53,18 +52,10 @@ class LuGmres:
     `max_restarts` restart cycles factors the current Jacobian and solves
     again."""
 
-    def __init__(self, rtol=1e-12, max_restarts=8, ilu=False):
-        self.rtol, self.max_restarts, self.ilu = rtol, max_restarts, ilu
+    def __init__(self, rtol=1e-12, max_restarts=8):
+        self.rtol, self.max_restarts = rtol, max_restarts
         self.lu = None
         self.fn = LINSOLVE_FN(self._call)
-
-    def _factor(self, A):
-        import scipy.sparse.linalg as sla
-        if self.ilu:
-            # incomplete factors (SuperLU's threshold ILU): cheaper to form,
-            # more GMRES iterations per solve
-            return sla.spilu(A, drop_tol=1e-6, fill_factor=30, permc_spec="COLAMD")
-        return sla.splu(A, permc_spec="COLAMD")
 
     def _matrix(self, nrows, nb, rowptr, colind, val):
         import scipy.sparse as sp
@@ -97,7 +88,7 @@ class LuGmres:
                 xs, it, ok = self._gmres(A, b)
             if not ok:
                 t0 = time.time()
-                self.lu = self._factor(A)
+                self.lu = sla.splu(A, permc_spec="COLAMD")
                 print(f"  factored the Jacobian in {time.time() - t0:.0f} s", flush=True)
                 xs, it, ok = self._gmres(A, b)
             out = np.ctypeslib.as_array(x, shape=(nrows * nb,))
@@ -111,15 +102,9 @@ class LuGmres:
 
 
 def main():
-    import argparse
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--ilu", action="store_true",
-                    help="incomplete LU factors for GMRES (faster on this grid), 40 restarts")
-    ap.add_argument("--out", default=OUT)
-    args = ap.parse_args()
     res = workload()
     o = OracleModel(res)
-    solver = LuGmres(max_restarts=40, ilu=True) if args.ilu else LuGmres()
+    solver = LuGmres()
     opt = o.options(dense_max=0)
     opt.linsolve = C.cast(solver.fn, C.c_void_p)
     t0 = time.time()
@@ -127,12 +112,12 @@ def main():
     wall = time.time() - t0
     if st != 0:
         raise SystemExit(f"the oracle did not converge ({rep.cuts} cuts)")
-    np.savez_compressed(args.out, P=o.P, Sw=o.Sw, pbhp=o.pbhp,
+    np.savez_compressed(OUT, P=o.P, Sw=o.Sw, pbhp=o.pbhp,
                         dt_sub=np.array(rep.dt_sub[: rep.nsub]),
                         newton=np.int64(rep.newton_iters), linear=np.int64(rep.linear_iters),
                         cnv=np.array(rep.cnv[:2]), mb=np.array(rep.mb[:2]))
     print(f"{res.name}: {rep.newton_iters} Newton, {rep.linear_iters} linear iterations, "
-          f"{rep.cuts} cuts, {wall:.0f} s; wrote {args.out}", flush=True)
+          f"{rep.cuts} cuts, {wall:.0f} s; wrote {OUT}", flush=True)
 
 
 if __name__ == "__main__":
