@@ -13,7 +13,8 @@ primitive instead: GMRES preconditioned by the sparse LU factors (SuperLU)
 of a recent Jacobian, refactored when GMRES fails to converge in 400
 iterations, to the oracle's relative residual of 1e-12.  The Newton
 iteration, updates, convergence tests and time-step control are the
-oracle's.  Run from the repository root (about an hour and 15 GB of memory):
+oracle's.  Run from the repository root (several hours: each refactorisation
+takes about 20 minutes; about 20 GB of memory):
 
     OMP_NUM_THREADS=8 python tests/golden/make_fivespot_step_fixture.py
 
