@@ -226,6 +226,50 @@ __device__ inline void multidot_group(int bx, int nbx, long nvec, const T *__res
     }
 }
 
+// The same over element pairs (16-byte loads of doubles), for vectors of
+// even length whose rows start on a pair boundary: x then y of a pair.
+template <class T, int NG>
+__device__ inline void multidot_group2(int bx, int nbx, long nvec, const T *__restrict__ V,
+                                       const T *__restrict__ w, bool self,
+                                       double (&acc)[kDotGroup + 1]) {
+    typedef T T2 __attribute__((ext_vector_type(2)));
+    constexpr int U = NG <= 2 ? 4 : 2;
+    const long S = (long)nbx * blockDim.x, n2 = nvec >> 1;
+    const T2 *w2 = reinterpret_cast<const T2 *>(w);
+    for (long e0 = (long)bx * blockDim.x + threadIdx.x; e0 < n2; e0 += U * S) {
+        T2 we[U], v[U][NG];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const long e = e0 + u * S < n2 ? e0 + u * S : e0;
+            we[u] = w2[e];
+#pragma unroll
+            for (int i = 0; i < NG; ++i)
+                v[u][i] = __builtin_nontemporal_load(reinterpret_cast<const T2 *>(V + (size_t)i * nvec) + e);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool on = e0 + u * S < n2;
+            const double wx = on ? (double)we[u].x : 0.0, wy = on ? (double)we[u].y : 0.0;
+#pragma unroll
+            for (int i = 0; i < NG; ++i) {
+                acc[i] += (double)v[u][i].x * wx;
+                acc[i] += (double)v[u][i].y * wy;
+            }
+            if (self) {
+                acc[kDotGroup] += wx * wx;
+                acc[kDotGroup] += wy * wy;
+            }
+        }
+    }
+}
+
+// pairs of T can be read at V (rows of length nvec) and w
+template <class T>
+__device__ inline bool pair_aligned(long nvec, const T *V, const T *w) {
+    return (nvec & 1) == 0 && (reinterpret_cast<uintptr_t>(V) & (2 * sizeof(T) - 1)) == 0 &&
+           (reinterpret_cast<uintptr_t>(w) & (2 * sizeof(T) - 1)) == 0;
+}
+
 template <class T>
 __device__ __forceinline__ void multidot_part_body(int bx, int nbx, int by, long nvec, int nv,
                                                    const T *__restrict__ V,
@@ -240,7 +284,18 @@ __device__ __forceinline__ void multidot_part_body(int bx, int nbx, int by, long
     for (int i = 0; i <= kDotGroup; ++i) acc[i] = 0.0;
     const bool self = by == 0;                    // the first group also forms <w, w>
     const T *Vg = V + (size_t)g0 * nvec;
-    switch (ng) {
+    if (pair_aligned(nvec, Vg, w)) {
+        switch (ng) {
+        case 1: multidot_group2<T, 1>(bx, nbx, nvec, Vg, w, self, acc); break;
+        case 2: multidot_group2<T, 2>(bx, nbx, nvec, Vg, w, self, acc); break;
+        case 3: multidot_group2<T, 3>(bx, nbx, nvec, Vg, w, self, acc); break;
+        case 4: multidot_group2<T, 4>(bx, nbx, nvec, Vg, w, self, acc); break;
+        case 5: multidot_group2<T, 5>(bx, nbx, nvec, Vg, w, self, acc); break;
+        case 6: multidot_group2<T, 6>(bx, nbx, nvec, Vg, w, self, acc); break;
+        case 7: multidot_group2<T, 7>(bx, nbx, nvec, Vg, w, self, acc); break;
+        default: multidot_group2<T, kDotGroup>(bx, nbx, nvec, Vg, w, self, acc); break;
+        }
+    } else switch (ng) {
     case 1: multidot_group<T, 1>(bx, nbx, nvec, Vg, w, self, acc); break;
     case 2: multidot_group<T, 2>(bx, nbx, nvec, Vg, w, self, acc); break;
     case 3: multidot_group<T, 3>(bx, nbx, nvec, Vg, w, self, acc); break;
@@ -343,14 +398,37 @@ __device__ __forceinline__ void update_norm_body(int bid, int nblk, long nvec, i
     __syncthreads();
     double v[1] = {0.0};
     const bool mx[1] = {false};
-    for (long e = (long)bid * blockDim.x + threadIdx.x; e < nvec; e += (long)nblk * blockDim.x) {
-        double a = (double)w[e];
+    if (pair_aligned(nvec, V, w)) {
+        // element pairs (16-byte loads of doubles), x then y
+        typedef T T2 __attribute__((ext_vector_type(2)));
+        T2 *w2 = reinterpret_cast<T2 *>(w);
+        const long n2 = nvec >> 1;
+        for (long e = (long)bid * blockDim.x + threadIdx.x; e < n2; e += (long)nblk * blockDim.x) {
+            const T2 wv = w2[e];
+            double a0 = (double)wv.x, a1 = (double)wv.y;
 #pragma unroll 8
-        for (int i = 0; i < nv; ++i)
-            a -= c[i] * (double)__builtin_nontemporal_load(V + (size_t)i * nvec + e);
-        const T at = (T)a;                         // the norm of what is stored
-        w[e] = at;
-        v[0] += (double)at * (double)at;
+            for (int i = 0; i < nv; ++i) {
+                const T2 vv = __builtin_nontemporal_load(reinterpret_cast<const T2 *>(V + (size_t)i * nvec) + e);
+                a0 -= c[i] * (double)vv.x;
+                a1 -= c[i] * (double)vv.y;
+            }
+            T2 at;
+            at.x = (T)a0;
+            at.y = (T)a1;
+            w2[e] = at;
+            v[0] += (double)at.x * (double)at.x;
+            v[0] += (double)at.y * (double)at.y;
+        }
+    } else {
+        for (long e = (long)bid * blockDim.x + threadIdx.x; e < nvec; e += (long)nblk * blockDim.x) {
+            double a = (double)w[e];
+#pragma unroll 8
+            for (int i = 0; i < nv; ++i)
+                a -= c[i] * (double)__builtin_nontemporal_load(V + (size_t)i * nvec + e);
+            const T at = (T)a;                     // the norm of what is stored
+            w[e] = at;
+            v[0] += (double)at * (double)at;
+        }
     }
     block_partials<1>(v, mx, partials, bid, nblk);
 }
