@@ -10,11 +10,13 @@ comes from the HIP path.  The oracle's own linear solver (GMRES(50) with
 natural-order BILU(0)) stalls near 1e-4 on grids this size, so its Newton
 iterations solve through the oracle's linear-solver hook with a library
 primitive instead: GMRES preconditioned by the sparse LU factors (SuperLU)
-of a recent Jacobian, refactored when GMRES fails to converge in 400
-iterations, to the oracle's relative residual of 1e-12.  The Newton
-iteration, updates, convergence tests and time-step control are the
-oracle's.  Run from the repository root (several hours: each refactorisation
-takes about 20 minutes; about 20 GB of memory):
+of the Jacobian, to the oracle's relative residual of 1e-12.  The unknowns
+are put in a nested-dissection order of the grid first (recursive
+bisection of the box along its longest axis, each separator plane after
+the two halves it splits, the wells last), which SuperLU factors about four
+times faster than in its own column order.  The Newton iteration, updates,
+convergence tests and time-step control are the oracle's.  Run from the
+repository root (about five minutes per Newton iteration, 10 GB of memory):
 
     OMP_NUM_THREADS=8 python tests/golden/make_fivespot_step_fixture.py
 
@@ -46,16 +48,41 @@ def workload():
     return rv.config_c2_small(*DIMS, nsteps=1)
 
 
-class LuGmres:
-    """J x = rhs by GMRES(50) preconditioned with the SuperLU factors of the
-    last Jacobian that was factored (a factorisation costs as much as a few
-    hundred GMRES iterations here); a solve that fails within
-    `max_restarts` restart cycles factors the current Jacobian and solves
-    again."""
+def nested_dissection(nx, ny, nz, leaf=256):
+    """Cells of an nx x ny x nz grid in nested-dissection order: a box of at
+    most `leaf` cells in natural order, a larger one split at the middle plane
+    of its longest axis, the two halves first and the plane after them."""
+    out = []
 
-    def __init__(self, rtol=1e-12, max_restarts=8):
+    def rec(lo, hi):
+        ext = [h - l for l, h in zip(lo, hi)]
+        if ext[0] * ext[1] * ext[2] <= leaf:
+            for k in range(lo[2], hi[2]):
+                for j in range(lo[1], hi[1]):
+                    out.extend(i + nx * (j + ny * k) for i in range(lo[0], hi[0]))
+            return
+        a = max(range(3), key=lambda d: (ext[d], -d))     # the first longest axis
+        m = (lo[a] + hi[a]) // 2
+        left, right, plane = list(hi), list(lo), (list(lo), list(hi))
+        left[a], right[a] = m, m + 1
+        plane[0][a], plane[1][a] = m, m + 1
+        rec(lo, left)
+        rec(right, hi)
+        rec(*plane)
+
+    rec([0, 0, 0], [nx, ny, nz])
+    return np.array(out, dtype=np.int64)
+
+
+class LuGmres:
+    """J x = rhs by GMRES(50) preconditioned with the SuperLU factors of J in
+    nested-dissection order (the wells last), factored at every call."""
+
+    def __init__(self, dims, rtol=1e-12, max_restarts=8):
         self.rtol, self.max_restarts = rtol, max_restarts
+        self.cells = nested_dissection(*dims)
         self.lu = None
+        self.perm = None
         self.fn = LINSOLVE_FN(self._call)
 
     def _matrix(self, nrows, nb, rowptr, colind, val):
@@ -73,7 +100,13 @@ class LuGmres:
 
         def count(_):
             its[0] += 1
-        M = sla.LinearOperator(A.shape, matvec=self.lu.solve)
+        p = self.perm
+        inv = np.empty_like(p)
+        inv[p] = np.arange(p.size)
+
+        def prec(v):
+            return self.lu.solve(v[p])[inv]
+        M = sla.LinearOperator(A.shape, matvec=prec)
         x, info = sla.gmres(A, b, M=M, rtol=self.rtol, atol=0.0, restart=50,
                             maxiter=self.max_restarts, callback=count, callback_type="pr_norm")
         rel = np.linalg.norm(b - A @ x) / np.linalg.norm(b)
@@ -84,14 +117,15 @@ class LuGmres:
             import scipy.sparse.linalg as sla
             A = self._matrix(nrows, nb, rowptr, colind, val)
             b = np.ctypeslib.as_array(rhs, shape=(nrows * nb,)).copy()
-            ok = False
-            if self.lu is not None:
-                xs, it, ok = self._gmres(A, b)
-            if not ok:
-                t0 = time.time()
-                self.lu = sla.splu(A, permc_spec="COLAMD")
-                print(f"  factored the Jacobian in {time.time() - t0:.0f} s", flush=True)
-                xs, it, ok = self._gmres(A, b)
+            n = self.cells.size
+            self.perm = np.concatenate([(self.cells[:, None] * nb + np.arange(nb)).ravel(),
+                                        np.arange(n * nb, nrows * nb)])
+            t0 = time.time()
+            Ap = A.tocsr()[self.perm][:, self.perm].tocsc()
+            self.lu = sla.splu(Ap, permc_spec="NATURAL", diag_pivot_thresh=0.1,
+                               options=dict(SymmetricMode=True))
+            print(f"  factored the Jacobian in {time.time() - t0:.0f} s", flush=True)
+            xs, it, ok = self._gmres(A, b)
             out = np.ctypeslib.as_array(x, shape=(nrows * nb,))
             out[:] = xs
             iters[0] = it
@@ -105,7 +139,7 @@ class LuGmres:
 def main():
     res = workload()
     o = OracleModel(res)
-    solver = LuGmres()
+    solver = LuGmres(DIMS)
     opt = o.options(dense_max=0)
     opt.linsolve = C.cast(solver.fn, C.c_void_p)
     t0 = time.time()
