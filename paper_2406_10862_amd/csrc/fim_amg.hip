@@ -1027,7 +1027,7 @@ __device__ inline int slab_storage(const AmgLevel &L, const AmgExact &E, int b, 
 // (contiguous columns of X) solved with those unit right sides: from slab s
 // towards the twist slab (z_s a column of the inverse held for slab s), the
 // twist, then outward on both sides.  Thread (r, c) forms row r of column c
-// from row r of the slab's inverse in twelve chunks of 8 entries (immediate
+// from row r of the slab's inverse in eight chunks of 12 entries (immediate
 // offsets; a chunk may run past the row, into the next one or the
 // allocation's padding, where t is zero), two chunks in flight, the first
 // loaded before the step's barrier.  Each step's result goes to its rows of
@@ -1036,7 +1036,7 @@ __device__ inline int slab_storage(const AmgLevel &L, const AmgExact &E, int b, 
 // stores stay in flight.  Grid: nslab x ceil(mmax / kInvCols) workgroups of
 // kInvCols * kSlabMax threads (252 for 28 slabs of 90: one round over the
 // CUs).
-constexpr int kInvCols = 10, kInvCh = 8, kInvChunks = kSlabMax / kInvCh;
+constexpr int kInvCols = 10, kInvCh = 12, kInvChunks = kSlabMax / kInvCh;
 __global__ __launch_bounds__(kInvCols * kSlabMax) void k_amg_exact_inverse(AmgLevel L, AmgExact E) {
     __shared__ double zx[kSlabMax][kInvCols], t[kSlabMax][kInvCols], xt[kSlabMax][kInvCols];
     const int groups = (E.mmax + kInvCols - 1) / kInvCols;
