@@ -432,6 +432,23 @@ def test_mixed_precision_steps_match_oracle(cfg):
     assert all(v <= STATE_TOL for v in worst.values()), worst
 
 
+@pytest.mark.parametrize("precision,mode", [(rv.FP64, 0), (rv.FP64, 1), (rv.MIXED, 0)])
+def test_steps_with_the_exact_coarse_level_match_oracle(precision, mode):
+    """The AMG's first level below the finest (7x9x3 here, nine slabs of 21
+    cells) solved exactly, by its dense inverse (mode 0) or by substitution
+    over the slabs (mode 1), in FP64 and mixed precision: the steps still
+    meet the oracle's to the state tolerance."""
+    res = rv.config_c2_small(13, 17, 5, nsteps=3)
+    g, o, errs = run_parity_steps(res, 3, options=rv.Options(
+        precond=rv.PREC_CPR_ILU0, precision=precision, tile=(5, 6, 3), amg_exact=4096,
+        amg_exact_mode=mode))
+    g.fim_assemble(float(res.schedule[0]))        # (the hierarchy is read at a Jacobian)
+    assert g.fim_amg_levels() == 2
+    worst = {k: max(e[k] for e in errs) for k in errs[0]}
+    print("exact coarse level parity per quantity:", worst)
+    assert all(v <= STATE_TOL for v in worst.values()), worst
+
+
 # three-phase black oil on the 200x200x50 layout (gas injector at the
 # centre, four corner producers), FP64 and mixed precision
 
@@ -793,12 +810,15 @@ def _adjoint_case(cfg):
     return res, res.schedule[:3], qobs
 
 
+@pytest.mark.parametrize("exact", [0, 4096])
 @pytest.mark.parametrize("cfg", ["c5", "c1"])
-def test_adjoint_gradient_matches_oracle(cfg):
+def test_adjoint_gradient_matches_oracle(cfg, exact):
+    """Also with the AMG's first coarse level solved exactly (the transposed
+    CPR stage then factors the transposed level's slabs)."""
     from oracle.adjoint import AdjointOracle
     res, dts, qobs = _adjoint_case(cfg)
     Jo, go = AdjointOracle(res).gradient(dts, qobs)
-    g, o = pair(res, options=rv.Options(tile=(5, 5, 3)))
+    g, o = pair(res, options=rv.Options(tile=(5, 5, 3), amg_exact=exact))
     rc, grad, rep = g.fim_adjoint_gradient(dts, qobs)
     print(f"adjoint {cfg}: J {rep.objective:.6e} (oracle {Jo:.6e}) substeps {rep.substeps} "
           f"adjoint iterations {rep.adjoint_iters} relres {rep.adjoint_relres:.2e} "
