@@ -350,6 +350,11 @@ def summarize_kernels(trace_csv, fetch_csv, write_csv, bench_log, out, title, co
                 "AMG coarsest level 3: its dense inverse times the right side"
         if name == "fim::k_amg_exact_factor":
             return None, "AMG level 3: slab Schur complements inverted (one workgroup, latency)"
+        if name == "fim::k_amg_exact_factor2":
+            return None, ("AMG level 3: slab Schur complements inverted from both ends "
+                          "(two workgroups, latency)")
+        if name == "fim::k_amg_exact_twist":
+            return None, "AMG level 3: the middle slab's two-sided Schur complement (latency)"
         if name == "fim::k_amg_exact_inverse":
             return None, "AMG level 3: dense inverse from the slab factors (latency)"
         return None, ""
