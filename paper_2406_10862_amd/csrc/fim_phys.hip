@@ -449,11 +449,32 @@ __device__ __forceinline__ void assemble_cells_body(
     }
     Side<NB> me, nbr;
     load_side<NB>(rec, n, c, P, depth, me);
-    int q = sys.rowptr[c];
+    const bool ex[6] = {k > 0, j > 0, i > 0, i + 1 < nx, j + 1 < g.ny, k + 1 < g.nz};
+    const int q0 = sys.rowptr[c];
+    const int qd = q0 + ex[0] + ex[1] + ex[2];
+    int q = qd + 1 + ex[3] + ex[4] + ex[5];       // the first well column
     double F[NB], dK[NB][NB], dL[NB][NB], off[NB][NB];
+    // 2x2 blocks: the off-diagonal blocks (-z, -y, -x, +x, +y, +z) are held
+    // and stored with the diagonal one after the last face, so the row's
+    // lines are written in one burst rather than piecemeal while the faces'
+    // loads are in flight (3x3 blocks store each at once: held, they would
+    // take the kernel to one wave per SIMD)
+    constexpr bool kBurst = NB == 2;
+    double OB[kBurst ? 6 : 1][NB][NB];
+    int ql = q0, qu = qd + 1;
+    auto put = [&](int d, int &qp) {
+        if constexpr (kBurst) {
+#pragma unroll
+            for (int e = 0; e < NB; ++e)
+#pragma unroll
+                for (int u = 0; u < NB; ++u) OB[d][e][u] = off[e][u];
+        } else {
+            store_block<NB>(sys.val, qp++, off);
+        }
+    };
 
     // neighbour below in index order: it is the K side of the face
-    auto lower = [&](int cn, double T) {
+    auto lower = [&](int d, int cn, double T) {
         load_side<NB>(rec, n, cn, P, depth, nbr);
         face_flux<NB>(T, nbr, me, F, dK, dL);
 #pragma unroll
@@ -465,10 +486,10 @@ __device__ __forceinline__ void assemble_cells_body(
                 off[e][u] = -dK[e][u];
             }
         }
-        store_block<NB>(sys.val, q++, off);
+        put(d, ql);
     };
     // neighbour above in index order: this cell is the K side
-    auto upper = [&](int cn, double T) {
+    auto upper = [&](int d, int cn, double T) {
         load_side<NB>(rec, n, cn, P, depth, nbr);
         face_flux<NB>(T, me, nbr, F, dK, dL);
 #pragma unroll
@@ -480,15 +501,14 @@ __device__ __forceinline__ void assemble_cells_body(
                 off[e][u] = dL[e][u];
             }
         }
-        store_block<NB>(sys.val, q++, off);
+        put(d, qu);
     };
-    if (k > 0) lower(c - nxy, tz[c - nxy]);
-    if (j > 0) lower(c - nx, ty[c - nx]);
-    if (i > 0) lower(c - 1, tx[c - 1]);
-    const int qd = q++;
-    if (i + 1 < nx) upper(c + 1, tx[c]);
-    if (j + 1 < g.ny) upper(c + nx, ty[c]);
-    if (k + 1 < g.nz) upper(c + nxy, tz[c]);
+    if (ex[0]) lower(0, c - nxy, tz[c - nxy]);
+    if (ex[1]) lower(1, c - nx, ty[c - nx]);
+    if (ex[2]) lower(2, c - 1, tx[c - 1]);
+    if (ex[3]) upper(3, c + 1, tx[c]);
+    if (ex[4]) upper(4, c + nx, ty[c]);
+    if (ex[5]) upper(5, c + nxy, tz[c]);
 
     // perforations of this cell, in ascending well order (well columns)
     for (int pp = w.cps[c]; pp < w.cps[c + 1]; ++pp) {
@@ -507,7 +527,18 @@ __device__ __forceinline__ void assemble_cells_body(
         }
         store_block<NB>(sys.val, q++, off);
     }
-    store_block<NB>(sys.val, qd, D);
+    if constexpr (kBurst) {
+        int qs = q0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+            if (ex[d]) store_block<NB>(sys.val, qs++, OB[d]);
+        store_block<NB>(sys.val, qs++, D);
+#pragma unroll
+        for (int d = 3; d < 6; ++d)
+            if (ex[d]) store_block<NB>(sys.val, qs++, OB[d]);
+    } else {
+        store_block<NB>(sys.val, qd, D);
+    }
 #pragma unroll
     for (int e = 0; e < NB; ++e) sys.R[(size_t)c * NB + e] = R[e];
 }
