@@ -1,6 +1,7 @@
 """The oracle's linear-solver hook, used by the fixture script of the large
 parity case: a step whose Newton iterations solve through the hook (GMRES
-with SuperLU factors, a library primitive) reaches the state the oracle's
+with SuperLU factors in nested-dissection order, a library primitive)
+reaches the state the oracle's
 own solvers reach, and a failing hook fails the step the way a failing
 linear solve does (cuts, then the step-start state restored)."""
 import ctypes as C
@@ -16,7 +17,7 @@ def test_hook_solver_reaches_the_oracle_state():
     res = rv.config_c2_small(12, 20, 6, nsteps=1)
     a, b = OracleModel(res), OracleModel(res)
     st_a, rep_a = a.step(res.schedule[0], a.options())
-    solver = LuGmres()
+    solver = LuGmres((res.nx, res.ny, res.nz))
     opt = b.options(dense_max=0)
     opt.linsolve = C.cast(solver.fn, C.c_void_p)
     st_b, rep_b = b.step(res.schedule[0], opt)
